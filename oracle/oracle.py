@@ -1,0 +1,283 @@
+"""ctypes binding of the binary64 MPPI oracle (test infrastructure only).
+
+Functions take a `workloads.Workload` (inputs in binary32) and widen every
+input to binary64 before calling the C oracle.  Noise is drawn by the oracle's
+own Philox4x32-10 + Box-Muller implementation (the noise definition is written
+out in mppi_oracle.c).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmppi_oracle.so")
+
+MODEL_ID = {"double_integrator": 0, "bicycle": 1, "quadrotor": 2, "bicycle_mlp": 3}
+INTEGRATOR_ID = {"euler": 0, "rk4": 1}
+COST_ID = {"quadratic": 0, "path_circles": 1, "path_costmap": 2, "hover": 3,
+           "track": 4, "goal_circles": 5}
+
+_dp = C.POINTER(C.c_double)
+
+
+class OrcProblem(C.Structure):
+    _fields_ = [
+        ("model", C.c_int32), ("integrator", C.c_int32), ("cost", C.c_int32),
+        ("K", C.c_int32), ("T", C.c_int32), ("n", C.c_int32), ("m", C.c_int32),
+        ("dt", C.c_double), ("lam", C.c_double),
+        ("sigma", C.c_float * 8),
+        ("seed", C.c_uint64), ("instance", C.c_uint32),
+        ("wheelbase", C.c_double), ("mass", C.c_double),
+        ("inertia", C.c_double * 3), ("gravity", C.c_double),
+        ("mlp_hidden", C.c_int32), ("mlp", _dp),
+        ("w", C.c_double * 32),
+        ("ref", _dp), ("ref_len", C.c_int32),
+        ("nseg", C.c_int32), ("knots", _dp), ("coef", _dp),
+        ("ncirc", C.c_int32), ("cx", _dp), ("cy", _dp), ("r2", _dp),
+        ("map_w", C.c_int32), ("map_h", C.c_int32),
+        ("map_x0", C.c_double), ("map_y0", C.c_double), ("map_res", C.c_double),
+        ("map", _dp),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER(OrcProblem)
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+        L.orc_philox4x32.argtypes = [u32p, u32p, C.c_int, u32p]
+        L.orc_philox_many.argtypes = [C.c_int64, u32p, u32p, u32p]
+        L.orc_bm_radius.argtypes = [C.c_uint32]
+        L.orc_bm_radius.restype = C.c_float
+        L.orc_bm_tables.argtypes = [f32p, f32p, f32p]
+        L.orc_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
+                                C.c_int32, f32p, C.c_int64, f32p]
+        L.orc_rollout_costs.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p, f64p, i32p]
+        L.orc_softmin_update.argtypes = [P, f64p, f32p, C.c_int64, f64p, f64p, f64p, f64p]
+        L.orc_softmin_update.restype = C.c_int
+        L.orc_mppi.argtypes = [P, f64p, f64p, C.c_int32, C.c_uint32, f32p, f64p, f64p, f64p]
+        L.orc_mppi.restype = C.c_int
+        L.orc_trajectory.argtypes = [P, f64p, f64p, f64p]
+        L.orc_sequence_cost.argtypes = [P, f64p, f64p]
+        L.orc_sequence_cost.restype = C.c_double
+        L.orc_eval_running_cost.argtypes = [P, f64p, f64p, C.c_int32]
+        L.orc_eval_running_cost.restype = C.c_double
+        L.orc_eval_terminal_cost.argtypes = [P, f64p]
+        L.orc_eval_terminal_cost.restype = C.c_double
+        L.orc_eval_deriv.argtypes = [P, f64p, f64p, f64p]
+        L.orc_step.argtypes = [P, f64p, f64p]
+        L.orc_eval_spline.argtypes = [P, C.c_double, _dp, _dp]
+        L.orc_eval_costmap.argtypes = [P, C.c_double, C.c_double]
+        L.orc_eval_costmap.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Problem:
+    """An OrcProblem plus the binary64 arrays it points into."""
+
+    def __init__(self, wl, **override):
+        self.wl = wl
+        p = OrcProblem()
+        p.model = MODEL_ID[wl.model]
+        p.integrator = INTEGRATOR_ID[wl.integrator]
+        p.cost = COST_ID[wl.cost]
+        p.K, p.T, p.n, p.m = wl.K, wl.T, wl.n, wl.m
+        p.dt = float(np.float32(wl.dt))
+        p.lam = float(override.get("lam", np.float32(wl.lam)))
+        for j in range(wl.m):
+            p.sigma[j] = float(wl.sigma[j])
+        p.seed = wl.seed
+        p.instance = wl.instance
+        p.wheelbase = float(np.float32(wl.wheelbase))
+        p.mass = float(np.float32(wl.mass))
+        for i in range(3):
+            p.inertia[i] = float(np.float32(wl.inertia[i]))
+        p.gravity = float(np.float32(wl.gravity))
+        for i in range(32):
+            p.w[i] = float(wl.w[i])
+        self._keep = []
+
+        def ptr(a):
+            if a is None:
+                return None
+            a = _d(a).ravel()
+            self._keep.append(a)
+            return a.ctypes.data_as(_dp)
+
+        if wl.mlp is not None:
+            p.mlp_hidden = wl.mlp_hidden
+            p.mlp = ptr(wl.mlp)
+        if wl.ref is not None:
+            p.ref = ptr(wl.ref)
+            p.ref_len = int(np.asarray(wl.ref).size)
+        if wl.knots is not None:
+            p.nseg = len(wl.knots) - 1
+            p.knots = ptr(wl.knots)
+            p.coef = ptr(wl.coef)
+        if wl.cx is not None:
+            p.ncirc = len(wl.cx)
+            p.cx, p.cy, p.r2 = ptr(wl.cx), ptr(wl.cy), ptr(wl.r2)
+        if wl.costmap is not None:
+            p.map_h, p.map_w = wl.costmap.shape
+            p.map_x0, p.map_y0 = float(np.float32(wl.map_x0)), float(np.float32(wl.map_y0))
+            p.map_res = float(np.float32(wl.map_res))
+            p.map = ptr(wl.costmap)
+        self.p = p
+
+    @property
+    def ref(self):
+        return C.byref(self.p)
+
+
+# --------------------------------------------------------------------------
+# Noise
+# --------------------------------------------------------------------------
+def philox(ctrs: np.ndarray, key) -> np.ndarray:
+    """Philox4x32-10 blocks for counters ctrs[n][4] under key (k0, k1)."""
+    ctrs = np.ascontiguousarray(ctrs, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctrs)
+    lib().orc_philox_many(len(ctrs), ctrs, np.asarray(key, np.uint32), out)
+    return out
+
+
+def bm_tables():
+    """(r[j1-1] for j1 in 1..2^24, cos[j2], sin[j2] for j2 in 0..2^24-1)."""
+    n = 1 << 24
+    r, c, s = (np.empty(n, np.float32) for _ in range(3))
+    lib().orc_bm_tables(r, c, s)
+    return r, c, s
+
+
+def noise(seed: int, iteration: int, instance: int, K: int, T: int, m: int,
+          sigma) -> np.ndarray:
+    """eps[T][m][K] (binary32) of the noise definition."""
+    eps = np.empty((T, m, K), np.float32)
+    sig = np.zeros(8, np.float32)
+    sig[:m] = sigma
+    lib().orc_noise(seed, iteration, instance, K, T, m, sig, K, eps)
+    return eps
+
+
+def workload_noise(wl, iteration: int = 0) -> np.ndarray:
+    return noise(wl.seed, iteration, wl.instance, wl.K, wl.T, wl.m, wl.sigma)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1
+# --------------------------------------------------------------------------
+def rollout_costs(wl, eps=None, x0=None, u=None, iteration: int = 0, **override):
+    """(S[K], margin[K], crashes[K]) of the rollout stage."""
+    P = Problem(wl, **override)
+    if eps is None:
+        eps = workload_noise(wl, iteration)
+    eps = np.ascontiguousarray(eps, np.float32)
+    x0 = _d(wl.x0 if x0 is None else x0)
+    u = _d(wl.u0 if u is None else u).ravel()
+    S = np.empty(wl.K)
+    margin = np.empty(wl.K)
+    crashes = np.empty(wl.K, np.int32)
+    lib().orc_rollout_costs(P.ref, x0, u, eps, eps.shape[-1], S, margin, crashes)
+    return S, margin, crashes
+
+
+def softmin_update(wl, S, eps, u=None, **override):
+    """(w[K], U[T][m], stats[4], status) of the weighting and update stage."""
+    P = Problem(wl, **override)
+    eps = np.ascontiguousarray(eps, np.float32)
+    u = _d(wl.u0 if u is None else u).ravel()
+    w = np.empty(wl.K)
+    U = np.empty(wl.T * wl.m)
+    stats = np.empty(4)
+    rc = lib().orc_softmin_update(P.ref, _d(S), eps, eps.shape[-1], u, w, U, stats)
+    return w, U.reshape(wl.T, wl.m), stats, rc
+
+
+def mppi(wl, iters=None, iter0: int = 0, u=None, x0=None, **override):
+    """Run `iters` warm-started iterations; returns a dict with the final U and
+    the last iteration's eps, S, w and stats."""
+    P = Problem(wl, **override)
+    iters = wl.iters if iters is None else iters
+    u = _d(wl.u0 if u is None else u).ravel().copy()
+    x0 = _d(wl.x0 if x0 is None else x0)
+    eps = np.empty((wl.T, wl.m, wl.K), np.float32)
+    S = np.empty(wl.K)
+    w = np.empty(wl.K)
+    stats = np.empty(4)
+    rc = lib().orc_mppi(P.ref, x0, u, iters, iter0, eps, S, w, stats)
+    return {"U": u.reshape(wl.T, wl.m), "eps": eps, "S": S, "w": w, "stats": stats,
+            "status": rc}
+
+
+# --------------------------------------------------------------------------
+# Single-point evaluations (model and cost unit tests)
+# --------------------------------------------------------------------------
+def step(wl, x, v):
+    P = Problem(wl)
+    x = _d(x).copy()
+    lib().orc_step(P.ref, x, _d(v))
+    return x
+
+
+def deriv(wl, x, v):
+    P = Problem(wl)
+    d = np.empty(wl.n)
+    lib().orc_eval_deriv(P.ref, _d(x), _d(v), d)
+    return d
+
+
+def trajectory(wl, v_seq, x0=None):
+    P = Problem(wl)
+    xs = np.empty((wl.T + 1, wl.n))
+    lib().orc_trajectory(P.ref, _d(wl.x0 if x0 is None else x0), _d(v_seq).ravel(), xs)
+    return xs
+
+
+def sequence_cost(wl, v_seq, x0=None, **override):
+    P = Problem(wl, **override)
+    return lib().orc_sequence_cost(P.ref, _d(wl.x0 if x0 is None else x0),
+                                   _d(v_seq).ravel())
+
+
+def running_cost(wl, x, v, t=0):
+    P = Problem(wl)
+    return lib().orc_eval_running_cost(P.ref, _d(x), _d(v), t)
+
+
+def terminal_cost(wl, x):
+    P = Problem(wl)
+    return lib().orc_eval_terminal_cost(P.ref, _d(x))
+
+
+def spline(wl, px):
+    P = Problem(wl)
+    y, dy = C.c_double(), C.c_double()
+    lib().orc_eval_spline(P.ref, float(px), C.byref(y), C.byref(dy))
+    return y.value, dy.value
+
+
+def costmap(wl, px, py):
+    P = Problem(wl)
+    return lib().orc_eval_costmap(P.ref, float(px), float(py))
+
+
+__all__ = ["philox", "bm_tables", "noise", "workload_noise", "rollout_costs",
+           "softmin_update", "mppi", "step", "deriv", "trajectory", "sequence_cost",
+           "running_cost", "terminal_cost", "spline", "costmap", "Problem"]
