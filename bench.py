@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of MPPI iterations on one MI355X.
+
+A step is one pass of the whole hot path over one batch: `mppi_iterate(I)`
+of the workload, i.e. I warm-started MPPI iterations, each made of noise
+sampling, fused rollout + cost, and the softmin weighting + control update.
+Default workload: the kinematic bicycle on a spline path with 200 circular
+obstacles, K 8192 samples, horizon 100, 10 iterations per step.
+
+Prints ONE JSON line with the throughput (rollout-steps/s = I*K*T / step time,
+inputs resident in HBM), the roofline position of the dominant kernel measured
+live with HIP events on the library's stream, and the binary64 CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; a wave64 VALU instruction
+# issues over 4 cycles, so non-packed FP32 VALU lane-operations peak at
+# 256 * 4 * 16 * 2.4e9 = 3.93e13 /s (78.6 TFLOP/s counting an FMA as 2).
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_BYTES = 8.0e12
+
+# Algorithmic VALU lane-operations per rollout step of the fused rollout +
+# cost kernel (counted from the arithmetic the method needs; transcendental
+# functions count as one operation each).  The derivation is in the design doc.
+def rollout_ops_per_step(wl) -> int:
+    v_form = wl.m                     # v = u + eps
+    kahan = 4
+    if wl.model == "bicycle":
+        # RK4: 4 stages x (sin, cos, tan, 3 products, 1 scale) + 3 x 5 stage
+        # updates + 3 x 5 accumulations + 5 final updates
+        dyn = 4 * 7 + 15 + 15 + 5
+    elif wl.model == "double_integrator":
+        dyn = 4 if wl.integrator == "euler" else 4 * 4 + 40
+    else:  # quadrotor: derivative ~ 60 ops, 4 stages + 3 x 13 stage updates + 13 x 4 accumulations + normalisation
+        dyn = 4 * 60 + 39 + 52 + 9
+    if wl.cost in ("path_circles", "path_costmap"):
+        nseg = len(wl.knots) - 1
+        cost = 2 + (nseg - 1) * 6 + 9 + 1 + 3 + 6 + 4 + 1  # clamp, select, cubic+slope, atan, errors, squares, controls, add
+        if wl.cost == "path_circles":
+            cost += 5 * len(wl.cx)  # sub, sub, mul, fma, compare per circle
+        else:
+            cost += 20  # bilinear: index math, 4 gathers, 8 lerp ops
+    elif wl.cost == "quadratic":
+        cost = 3 * wl.n + 2 * wl.m
+    elif wl.cost == "hover":
+        cost = 40
+    else:
+        cost = 3 * wl.n + 2 * wl.m
+    return v_form + dyn + cost + kahan
+
+
+def make_workload(name: str):
+    import workloads as W
+    if name == "c2_circles":
+        return W.c2("circles")
+    if name == "c2_costmap":
+        return W.c2("costmap")
+    if name == "c1":
+        return W.c1()
+    if name == "c3":
+        return W.c3()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def source_hash(*rel):
+    h = hashlib.sha256()
+    for r in rel:
+        with open(os.path.join(ROOT, r), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash(*rec.get("sources", [])):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, iters: int):
+    import oracle
+    t0 = time.perf_counter()
+    oracle.mppi(wl, iters=iters)
+    dt = time.perf_counter() - t0
+    return {"value": iters * wl.K * wl.T / dt, "unit": "rollout-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{wl.name}: K {wl.K}, T {wl.T}, {iters} iterations "
+                      f"(binary64 C oracle, single thread, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2_circles")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--cpu-iters", type=int, default=None,
+                    help="oracle iterations for the CPU baseline (default: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2409_07563_amd as M
+
+    wl = make_workload(args.workload)
+    I = wl.iters
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctl = M.Controller(wl, device=dev)
+    stream = ctl.stream
+
+    for _ in range(args.warmup):
+        ctl.iterate(I)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(args.steps):
+        ctl.iterate(I)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = start.elapsed_time(end) / args.steps
+    steps_per_iter = wl.K * wl.T
+    value = I * steps_per_iter / (ms_per_step * 1e-3)
+
+    # per-kernel durations, HIP events on the library's stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_noise = t_roll = t_upd = 0.0
+    for _ in range(args.kernel_reps):
+        ev[0].record(stream)
+        ctl.sample()
+        ev[1].record(stream)
+        ctl.rollout()
+        ev[2].record(stream)
+        ctl.update()
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        t_noise += ev[0].elapsed_time(ev[1])
+        t_roll += ev[1].elapsed_time(ev[2])
+        t_upd += ev[2].elapsed_time(ev[3])
+    n = args.kernel_reps
+    t_noise, t_roll, t_upd = (x / n * 1e-3 for x in (t_noise, t_roll, t_upd))
+
+    ops = rollout_ops_per_step(wl) * steps_per_iter
+    achieved = ops / t_roll
+    traffic = traffic_record("rollout", args.workload)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
+                "kernel": "rollout_kernel", "ops_per_rollout_step": rollout_ops_per_step(wl),
+                "launch_us": t_roll * 1e6}
+    eps_bytes = 4 * wl.T * wl.m * wl.K
+    kernels = {
+        "noise": {"us": t_noise * 1e6, "hbm_GBps": eps_bytes / t_noise / 1e9},
+        "rollout": {"us": t_roll * 1e6},
+        "softmin_update": {"us": t_upd * 1e6, "hbm_GBps": (eps_bytes + 4 * wl.K) / t_upd / 1e9},
+    }
+
+    out = {
+        "metric": "rollout-steps/sec (K*T) per MPPI iter + fwd+bwd/fwd time ratio, 1 MI355X",
+        "value": value, "unit": "rollout-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "K": wl.K, "T": wl.T, "iterations_per_step": I,
+                   "dynamics": wl.model, "integrator": wl.integrator, "cost": wl.cost,
+                   "obstacles": 0 if wl.cx is None else len(wl.cx)},
+        "fwd_bwd_over_fwd": None,
+        "wall_s_timed": wall,
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    ctl.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters or I)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,242 @@
+/*
+ * mppi.h — C ABI of the MI355X MPPI library (libmppi.so).
+ *
+ * One MPPI iteration, as stated in arXiv 2409.07563 (Section II-C, Algorithm 1
+ * and Eq. mppi_update_rule):
+ *   (a1) draw K control-noise sequences eps^k_t ~ N(0, Sigma), t < T;
+ *   (a2) roll every sample out, x <- F(x, u_t + eps^k_t), and accumulate the
+ *        running cost on each post-step state plus the terminal cost -> J^k;
+ *   (a3) baseline rho = min_k J^k;
+ *   (a4) normaliser eta = sum_k exp(-(J^k - rho) / lambda);
+ *   (a5) weights w^k = exp(-(J^k - rho) / lambda) / eta;
+ *   (a6) control update U_t = u_t + sum_k w^k eps^k_t;
+ *   (a7) repeat with u <- U and fresh noise (the outer loop of Algorithm 1).
+ *
+ * Conventions
+ *   - Every pointer prefixed d_ is device memory on the GPU the context was
+ *     created on; every other pointer is host memory.  The caller owns all
+ *     memory.  The library allocates no device memory: the caller passes one
+ *     workspace (size from mppi_workspace_bytes) that must outlive the context.
+ *   - Every call after mppi_create is enqueued on the context's HIP stream and
+ *     returns before the GPU work finishes (stream order is the only ordering).
+ *   - Arrays are binary32, row-major, densely packed unless a stride is given.
+ *   - Errors: invalid arguments return MPPI_EINVAL synchronously with a message
+ *     in mppi_last_error(); a failed HIP call returns MPPI_EDEVICE.  A context
+ *     is not thread-safe; distinct contexts are independent.
+ *   - Non-finite rollout costs count as +inf (weight 0).  If every cost of an
+ *     iteration is non-finite, U is left equal to u and the status word read by
+ *     mppi_get_debug(MPPI_DEBUG_STATS) is MPPI_ENUMERIC.
+ */
+#ifndef MPPI_H
+#define MPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPPI_ABI_VERSION 1u
+#define MPPI_MAX_STATE 16
+#define MPPI_MAX_CONTROL 8
+
+typedef enum mppi_status {
+  MPPI_OK = 0,
+  MPPI_EINVAL = -1,      /* invalid argument (message in mppi_last_error) */
+  MPPI_ENOMEM = -2,      /* workspace too small */
+  MPPI_EDEVICE = -3,     /* a HIP runtime call failed */
+  MPPI_ESTATE = -4,      /* call out of order (e.g. iterate before set_state) */
+  MPPI_EUNSUPPORTED = -5,/* combination not built */
+  MPPI_ENUMERIC = -6     /* every rollout cost was non-finite */
+} mppi_status;
+
+/* Dynamics F (Eq. dynamics, Section II).  State / control dimensions:
+ *   DOUBLE_INTEGRATOR 4/2: (px, py, vx, vy), (ax, ay)
+ *   BICYCLE           5/2: (px, py, yaw, speed, steer), (accel, steer rate);
+ *                          d/dt = (s cos yaw, s sin yaw, s tan(steer)/L, a, r)
+ *   QUADROTOR        13/4: p(3), q = (w,x,y,z) Hamilton, v(3) world, omega(3)
+ *                          body; (thrust, tau_x, tau_y, tau_z);
+ *                          q' = q (x) (0, omega)/2, v' = R(q)(0,0,F)/mass - g e3,
+ *                          omega' = J^-1 (tau - omega x J omega); q is
+ *                          renormalised after each step
+ *   BICYCLE_MLP       5/2: bicycle step + dt * g([x_t; v_t]),
+ *                          g = W3 tanh(W2 tanh(W1 z + b1) + b2) + b3 */
+typedef enum mppi_dynamics {
+  MPPI_DYN_DOUBLE_INTEGRATOR = 0,
+  MPPI_DYN_BICYCLE = 1,
+  MPPI_DYN_QUADROTOR = 2,
+  MPPI_DYN_BICYCLE_MLP = 3
+} mppi_dynamics;
+
+/* Integrator of one step with the control held: forward Euler (the paper's
+ * default, Section II) or classic fourth-order Runge-Kutta. */
+typedef enum mppi_integrator { MPPI_INT_EULER = 0, MPPI_INT_RK4 = 1 } mppi_integrator;
+
+/* Running cost l(x_{t+1}, v_t) and terminal cost phi(x_T); meaning of
+ * mppi_params.w[] per kind:
+ *   QUADRATIC     w[0..n) = Q diag, w[8..8+m) = R diag, w[16..16+n) = Qf diag,
+ *                 ref = goal (n):  l = (x-g)'Q(x-g) + v'Rv,  phi = (x-g)'Qf(x-g)
+ *   PATH_CIRCLES  w = (w_lat, w_head, w_speed, v_ref, r_accel, r_steer, crash,
+ *                 terminal_scale); spline y = s(x) required; circles required:
+ *                 l = w_lat e^2 + w_head (yaw - atan s'(px))^2
+ *                     + w_speed (speed - v_ref)^2 + r_accel a^2 + r_steer r^2
+ *                     + crash * [p inside some circle],
+ *                 e = py - s(px), px clamped to the knot range;
+ *                 phi = terminal_scale * (the first three terms)
+ *   PATH_COSTMAP  as PATH_CIRCLES with the crash term replaced by the bilinear
+ *                 costmap value at p (cell centres, clamp to edge)
+ *   HOVER         w = (w_p, w_v, w_w, w_q, w_u, w_box, box, terminal_scale),
+ *                 ref = (waypoint 3, q_ref 4, u_hover 4):
+ *                 c = w_p|p-pw|^2 + w_v|v|^2 + w_w|omega|^2 + w_q(1-<q,q_ref>^2)
+ *                 l = c + w_u|v_ctrl-u_hover|^2 + w_box sum max(0,|p_i|-box)^2
+ *                 phi = terminal_scale * c
+ *   TRACK         w[0..n) = Q diag, w[8..8+m) = R diag, w[16] = terminal scale,
+ *                 ref = reference states [(T+1)][n]:
+ *                 l_t = (x - ref_{t+1})'Q(x - ref_{t+1}) + v'Rv,
+ *                 phi = w[16] (x - ref_T)'Q(x - ref_T)
+ *   GOAL_CIRCLES  w = (w_goal, r_accel, r_steer, crash, terminal_scale),
+ *                 ref = goal (2): l = w_goal|p-goal|^2 + r_accel a^2
+ *                 + r_steer r^2 + crash*[p inside some circle];
+ *                 phi = terminal_scale * w_goal |p-goal|^2 */
+typedef enum mppi_cost {
+  MPPI_COST_QUADRATIC = 0,
+  MPPI_COST_PATH_CIRCLES = 1,
+  MPPI_COST_PATH_COSTMAP = 2,
+  MPPI_COST_HOVER = 3,
+  MPPI_COST_TRACK = 4,
+  MPPI_COST_GOAL_CIRCLES = 5
+} mppi_cost;
+
+enum {
+  MPPI_F_DEBUG = 1u /* keep per-sample crash counts (MPPI_DEBUG_CRASHES) */
+};
+
+typedef struct mppi_config {
+  uint32_t abi_version;  /* must equal MPPI_ABI_VERSION */
+  uint32_t dynamics;     /* mppi_dynamics */
+  uint32_t integrator;   /* mppi_integrator */
+  uint32_t cost;         /* mppi_cost */
+  int32_t num_samples;   /* K >= 1 */
+  int32_t horizon;       /* T >= 1 */
+  int32_t state_dim;     /* must match the dynamics */
+  int32_t control_dim;   /* must match the dynamics */
+  float dt;              /* > 0 */
+  float lambda;          /* temperature, > 0 */
+  float sigma[MPPI_MAX_CONTROL]; /* noise std per control, >= 0 (diagonal Sigma) */
+  uint64_t seed;         /* Philox key */
+  uint32_t instance;     /* Philox counter word 3 (independent streams) */
+  uint32_t flags;        /* MPPI_F_* */
+} mppi_config;
+
+/* Model and cost constants.  Every array pointer is host memory, read during
+ * mppi_create only (copied into the workspace). */
+typedef struct mppi_params {
+  float wheelbase;        /* BICYCLE*, L > 0 */
+  float mass;             /* QUADROTOR, > 0 */
+  float inertia[3];       /* QUADROTOR, diagonal of J, > 0 */
+  float gravity;          /* QUADROTOR */
+  int32_t mlp_hidden;     /* BICYCLE_MLP: H in [1, 256] */
+  const float* mlp;       /* W1[H][7] b1[H] W2[H][H] b2[H] W3[5][H] b3[5] */
+  float w[32];            /* cost weights, see mppi_cost */
+  const float* ref;       /* goal / waypoint data / reference trajectory */
+  int32_t ref_len;        /* number of floats at ref */
+  int32_t num_segments;   /* spline segments S >= 1 (PATH_*) */
+  const float* knots;     /* S+1 increasing abscissae */
+  const float* coef;      /* [S][4]: y = c0 + c1 d + c2 d^2 + c3 d^3, d = x - knot */
+  int32_t num_circles;    /* circles (PATH_CIRCLES, GOAL_CIRCLES), may be 0 */
+  const float* cx;        /* centres x [N] */
+  const float* cy;        /* centres y [N] */
+  const float* r2;        /* squared radii [N] */
+  int32_t map_w, map_h;   /* costmap cells (PATH_COSTMAP), each >= 2 */
+  float map_x0, map_y0;   /* lower-left corner of cell (0, 0) */
+  float map_res;          /* cell size > 0 */
+  const float* costmap;   /* [map_h][map_w] */
+} mppi_params;
+
+typedef struct mppi_ctx mppi_ctx;
+
+/* Bytes of device workspace a context with this configuration needs
+ * (0 if the configuration is invalid; see mppi_last_error). */
+size_t mppi_workspace_bytes(const mppi_config* cfg, const mppi_params* params);
+
+/* Create a context.  d_workspace: device memory of at least
+ * mppi_workspace_bytes, 256-byte aligned, owned by the caller and used
+ * exclusively by this context until mppi_destroy.  hip_stream: a hipStream_t
+ * (NULL = the null stream).  Copies the parameter arrays to the device and
+ * waits for the copies.  The nominal controls start at zero and the iteration
+ * counter at 0. */
+mppi_status mppi_create(const mppi_config* cfg, const mppi_params* params,
+                        void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                        mppi_ctx** out);
+
+/* x0 <- d_x0[0..n) (enqueued device copy). */
+mppi_status mppi_set_state(mppi_ctx* ctx, const float* d_x0);
+/* u <- d_u[T][m] (enqueued device copy; warm start or restore). */
+mppi_status mppi_set_controls(mppi_ctx* ctx, const float* d_u);
+/* Philox iteration word of the next sampling step (enqueued). */
+mppi_status mppi_set_iteration(mppi_ctx* ctx, uint32_t iteration);
+
+/* Staged iteration (Algorithm 1 split at its natural boundaries):
+ *   mppi_sample  - (a1) eps for the current iteration word
+ *   mppi_rollout - (a2) J^k from x0, u and eps
+ *   mppi_update  - (a3..a6) rho, eta, w and u <- u + sum_k w^k eps^k; then the
+ *                  iteration word advances by one.
+ * mppi_set_costs replaces J (K floats, device) between rollout and update. */
+mppi_status mppi_sample(mppi_ctx* ctx);
+mppi_status mppi_rollout(mppi_ctx* ctx);
+mppi_status mppi_set_costs(mppi_ctx* ctx, const float* d_costs);
+mppi_status mppi_update(mppi_ctx* ctx);
+
+/* (a7) num_iters >= 1 full iterations, warm-started (u <- U between them). */
+mppi_status mppi_iterate(mppi_ctx* ctx, int32_t num_iters);
+
+/* d_U[T][m] <- current nominal controls (enqueued device copy). */
+mppi_status mppi_get_controls(mppi_ctx* ctx, float* d_U);
+
+enum {
+  MPPI_DEBUG_NOISE = 0,   /* float eps[T][m][K] of the last sampling */
+  MPPI_DEBUG_COSTS = 1,   /* float J[K] of the last rollout (or set_costs) */
+  MPPI_DEBUG_WEIGHTS = 2, /* float w[K] of the last update */
+  MPPI_DEBUG_STATS = 3,   /* float[8]: rho, eta, free energy rho - lambda
+                             ln(eta/K), 1/sum w^2, then the int32 status word
+                             (MPPI_OK / MPPI_ENUMERIC) and the int32 iteration
+                             word, then two zero words */
+  MPPI_DEBUG_CRASHES = 4  /* int32 crashed-step count per sample [K]
+                             (needs MPPI_F_DEBUG and a circles cost) */
+};
+/* Enqueue a device copy of an internal buffer to d_dst. */
+mppi_status mppi_get_debug(mppi_ctx* ctx, int32_t what, void* d_dst);
+
+/* Gradient of a loss on the updated controls (not built in this version:
+ * returns MPPI_EUNSUPPORTED). */
+mppi_status mppi_backward(mppi_ctx* ctx, const float* d_dL_dU, float* d_grad);
+
+void mppi_destroy(mppi_ctx* ctx);
+
+/* Message of the last error on this thread; never NULL. */
+const char* mppi_last_error(void);
+
+/* ---- stand-alone noise (the same definition mppi_sample uses) ----------
+ * eps[t][j][k] (row stride ldk >= K floats) of the noise definition:
+ *   normal n = t*m + j of sample k comes from Philox4x32-10 (Salmon et al.,
+ *   SC'11) with counter (n/4, k, iteration, instance) and key (seed lo, seed
+ *   hi); slot n%4 takes the Box-Muller pair (x0,x1) or (x2,x3) and its cosine
+ *   (even) or sine (odd) branch with u1 = ((a>>8)+1) 2^-24, u2 = (b>>8) 2^-24;
+ *   eps = sigma_j * sqrt(-2 ln u1) * {cos,sin}(2 pi u2), where -2 ln u1 and
+ *   sincos use exact range reductions and fixed binary32 polynomials
+ *   (paper_2409_07563_amd/csrc/noise.h spells out every operation), so any
+ *   IEEE-754 host can reproduce eps bit for bit.  sigma: host, m floats. */
+mppi_status mppi_noise(uint64_t seed, uint32_t iteration, uint32_t instance, int32_t K,
+                       int32_t T, int32_t m, const float* sigma, float* d_eps,
+                       int64_t ldk, void* hip_stream);
+
+/* The Box-Muller factors for every possible input (2^24 each, device):
+ * d_r[j1-1] = sqrt(-2 ln(j1 2^-24)), d_c[j2] = cos(2 pi j2 2^-24),
+ * d_s[j2] = sin(2 pi j2 2^-24).  For exhaustive checks of the recipe. */
+mppi_status mppi_noise_tables(float* d_r, float* d_c, float* d_s, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPPI_H */

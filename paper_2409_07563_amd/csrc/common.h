@@ -1,0 +1,92 @@
+// Internal definitions shared by the HIP translation units of libmppi.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mppi.h"
+
+namespace mppi {
+
+constexpr int kWave = 64;
+
+// Model and cost constants as the kernels see them: passed by value as a
+// kernel argument, so every field is wave-uniform (SGPR) and array pointers
+// point into the context's workspace.
+struct DevParams {
+  // integration
+  float dt, half_dt, sixth_dt;
+  // bicycle
+  float inv_wheelbase;
+  // quadrotor
+  float inv_mass, gravity;
+  float inertia[3], inv_inertia[3];
+  // MLP residual
+  int mlp_hidden;
+  const float* mlp;
+  // cost
+  float w[32];
+  const float* ref;
+  int nseg;
+  const float* knots;   // [nseg+1]
+  const float4* coef;   // [nseg] (c0, c1, c2, c3)
+  int ncirc;
+  const float4* circles;  // [ncirc] (cx, cy, r2, 0)
+  int map_w, map_h;
+  float map_x0, map_y0, map_inv_res;
+  const float* costmap;   // [map_h][map_w]
+};
+
+// Per-chunk softmin partials written by the partial-reduction kernel and
+// merged by the merge kernel (see softmin.hip).
+struct SoftminLayout {
+  float* chunk_min;   // [nchunk]
+  float* chunk_sum;   // [nchunk]  sum_k exp(-(J_k - min_c)/lambda)
+  float* chunk_sum2;  // [nchunk]  sum_k exp(-(J_k - min_c)/lambda)^2
+  float* chunk_num;   // [nchunk][TM]  sum_k exp(...) eps[r][k]
+  int nchunk;
+};
+
+// Device-side scalars of a context.
+struct DevState {
+  float stats[4];     // rho, eta, free energy, 1/sum w^2
+  int32_t status;     // MPPI_OK or MPPI_ENUMERIC
+  uint32_t iteration; // Philox iteration word of the next sampling
+  int32_t pad[2];
+};
+
+// ---- host launchers (one translation unit each) ---------------------------
+hipError_t launch_noise(uint64_t seed, const uint32_t* d_iteration, uint32_t iteration,
+                        uint32_t instance, int K, int T, int m, const float* sigma,
+                        float* d_eps, int64_t ldk, hipStream_t stream);
+hipError_t launch_noise_tables(float* d_r, float* d_c, float* d_s, hipStream_t stream);
+
+// Returns hipErrorInvalidValue when the (dynamics, integrator, cost)
+// combination has no kernel.
+hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                          const DevParams& p, const float* d_x0, const float* d_u,
+                          const float* d_eps, int64_t ldk, int K, int T, float* d_S,
+                          int32_t* d_crashes, hipStream_t stream);
+bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
+
+int softmin_chunks(int K);
+hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
+                                 int TM, float lambda, const SoftminLayout& L, float* d_u,
+                                 DevState* d_state, hipStream_t stream);
+hipError_t launch_set_iteration(DevState* d_state, uint32_t iteration, hipStream_t stream);
+hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState* d_state,
+                          float* d_w, hipStream_t stream);
+
+// ---- wave / block reductions ------------------------------------------------
+__device__ inline float wave_min(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+}  // namespace mppi

@@ -1,0 +1,191 @@
+// Running cost l(x_{t+1}, v_t) and terminal cost phi(x_T) of the MPPI rollout
+// (arXiv 2409.07563, Algorithm 1: the cost is charged after each dynamics step
+// on the new state and the sampled control, then phi on the final state).
+// The meaning of DevParams::w per cost kind is documented with mppi_cost in
+// include/mppi.h.
+#pragma once
+
+#include "common.h"
+
+namespace mppi {
+
+// l = sum_i Q_i (x_i - g_i)^2 + sum_j R_j v_j^2;  phi = sum_i Qf_i (x_i - g_i)^2
+struct CostQuadratic {
+  template <int N, int M>
+  __device__ __forceinline__ static float running(const float* x, const float* v, int,
+                                                  const DevParams& p, bool& hit) {
+    float c = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) { const float e = x[i] - p.ref[i]; c += p.w[i] * e * e; }
+#pragma unroll
+    for (int j = 0; j < M; ++j) c += p.w[8 + j] * v[j] * v[j];
+    hit = false;
+    return c;
+  }
+  template <int N>
+  __device__ __forceinline__ static float terminal(const float* x, const DevParams& p) {
+    float c = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) { const float e = x[i] - p.ref[i]; c += p.w[16 + i] * e * e; }
+    return c;
+  }
+};
+
+// Lateral, heading and speed errors of the bicycle against the spline path
+// y = s(x), with px clamped to the knot range and the segment chosen without
+// branches (knots and coefficients are wave-uniform scalar loads).
+__device__ __forceinline__ float path_terms(const float* x, const DevParams& p) {
+  const float px = fminf(fmaxf(x[0], p.knots[0]), p.knots[p.nseg]);
+  float4 c = p.coef[0];
+  float k0 = p.knots[0];
+  for (int s = 1; s < p.nseg; ++s) {
+    const float ks = p.knots[s];
+    const float4 cs = p.coef[s];
+    const bool sel = px >= ks;
+    k0 = sel ? ks : k0;
+    c.x = sel ? cs.x : c.x; c.y = sel ? cs.y : c.y;
+    c.z = sel ? cs.z : c.z; c.w = sel ? cs.w : c.w;
+  }
+  const float d = px - k0;
+  const float y = c.x + d * (c.y + d * (c.z + d * c.w));
+  const float dy = c.y + d * (2.0f * c.z + 3.0f * d * c.w);
+  const float e = x[1] - y;
+  const float eh = x[2] - atanf(dy);
+  const float es = x[3] - p.w[3];
+  return p.w[0] * e * e + p.w[1] * eh * eh + p.w[2] * es * es;
+}
+
+// Point-in-any-circle test (inclusive boundary).
+__device__ __forceinline__ bool in_any_circle(float px, float py, const DevParams& p) {
+  bool hit = false;
+  for (int i = 0; i < p.ncirc; ++i) {
+    const float4 c = p.circles[i];
+    const float dx = px - c.x, dy = py - c.y;
+    hit |= (dx * dx + dy * dy) <= c.z;
+  }
+  return hit;
+}
+
+// Bilinear costmap between cell centres, clamped to the edge cells.
+__device__ __forceinline__ float costmap_value(float px, float py, const DevParams& p) {
+  float gx = (px - p.map_x0) * p.map_inv_res - 0.5f;
+  float gy = (py - p.map_y0) * p.map_inv_res - 0.5f;
+  gx = fminf(fmaxf(gx, 0.0f), static_cast<float>(p.map_w - 1));
+  gy = fminf(fmaxf(gy, 0.0f), static_cast<float>(p.map_h - 1));
+  const int ix = min(static_cast<int>(floorf(gx)), p.map_w - 2);
+  const int iy = min(static_cast<int>(floorf(gy)), p.map_h - 2);
+  const float fx = gx - static_cast<float>(ix), fy = gy - static_cast<float>(iy);
+  const float* row = p.costmap + static_cast<int64_t>(iy) * p.map_w + ix;
+  const float m00 = row[0], m01 = row[1];
+  const float m10 = row[p.map_w], m11 = row[p.map_w + 1];
+  return (1.0f - fx) * (1.0f - fy) * m00 + fx * (1.0f - fy) * m01 + (1.0f - fx) * fy * m10 +
+         fx * fy * m11;
+}
+
+template <bool CIRCLES>
+struct CostPath {
+  template <int N, int M>
+  __device__ __forceinline__ static float running(const float* x, const float* v, int,
+                                                  const DevParams& p, bool& hit) {
+    float c = path_terms(x, p) + p.w[4] * v[0] * v[0] + p.w[5] * v[1] * v[1];
+    if constexpr (CIRCLES) {
+      hit = in_any_circle(x[0], x[1], p);
+      c += hit ? p.w[6] : 0.0f;
+    } else {
+      hit = false;
+      c += costmap_value(x[0], x[1], p);
+    }
+    return c;
+  }
+  template <int N>
+  __device__ __forceinline__ static float terminal(const float* x, const DevParams& p) {
+    return p.w[7] * path_terms(x, p);
+  }
+};
+
+// Quadrotor hover at a waypoint (ref = waypoint 3, q_ref 4, u_hover 4).
+struct CostHover {
+  __device__ __forceinline__ static float state_terms(const float* x, const DevParams& p) {
+    float cp = 0.0f, cv = 0.0f, cw = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float e = x[i] - p.ref[i];
+      cp += e * e;
+      cv += x[7 + i] * x[7 + i];
+      cw += x[10 + i] * x[10 + i];
+    }
+    const float dq = x[3] * p.ref[3] + x[4] * p.ref[4] + x[5] * p.ref[5] + x[6] * p.ref[6];
+    return p.w[0] * cp + p.w[1] * cv + p.w[2] * cw + p.w[3] * (1.0f - dq * dq);
+  }
+  template <int N, int M>
+  __device__ __forceinline__ static float running(const float* x, const float* v, int,
+                                                  const DevParams& p, bool& hit) {
+    float c = state_terms(x, p);
+    float cu = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { const float e = v[j] - p.ref[7 + j]; cu += e * e; }
+    float cb = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { const float o = fmaxf(fabsf(x[i]) - p.w[6], 0.0f); cb += o * o; }
+    hit = false;
+    return c + p.w[4] * cu + p.w[5] * cb;
+  }
+  template <int N>
+  __device__ __forceinline__ static float terminal(const float* x, const DevParams& p) {
+    return p.w[7] * state_terms(x, p);
+  }
+};
+
+// Time-indexed tracking: l_t = (x - ref_{t+1})' Q (x - ref_{t+1}) + v' R v.
+struct CostTrack {
+  template <int N, int M>
+  __device__ __forceinline__ static float running(const float* x, const float* v, int t,
+                                                  const DevParams& p, bool& hit) {
+    const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
+    float c = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) { const float e = x[i] - r[i]; c += p.w[i] * e * e; }
+#pragma unroll
+    for (int j = 0; j < M; ++j) c += p.w[8 + j] * v[j] * v[j];
+    hit = false;
+    return c;
+  }
+  // the terminal reference row is read by the kernel through t = T - 1
+  template <int N>
+  __device__ __forceinline__ static float terminal_at(const float* x, int T, const DevParams& p) {
+    const float* r = p.ref + static_cast<int64_t>(T) * N;
+    float c = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) { const float e = x[i] - r[i]; c += p.w[i] * e * e; }
+    return p.w[16] * c;
+  }
+};
+
+// Goal distance with circular obstacles (bicycle).
+struct CostGoalCircles {
+  template <int N, int M>
+  __device__ __forceinline__ static float running(const float* x, const float* v, int,
+                                                  const DevParams& p, bool& hit) {
+    const float dx = x[0] - p.ref[0], dy = x[1] - p.ref[1];
+    float c = p.w[0] * (dx * dx + dy * dy) + p.w[1] * v[0] * v[0] + p.w[2] * v[1] * v[1];
+    hit = in_any_circle(x[0], x[1], p);
+    return c + (hit ? p.w[3] : 0.0f);
+  }
+  template <int N>
+  __device__ __forceinline__ static float terminal(const float* x, const DevParams& p) {
+    const float dx = x[0] - p.ref[0], dy = x[1] - p.ref[1];
+    return p.w[4] * p.w[0] * (dx * dx + dy * dy);
+  }
+};
+
+// Uniform access to the terminal cost (TRACK needs the horizon).
+template <class Cost, int N>
+__device__ __forceinline__ float terminal_cost(const float* x, int T, const DevParams& p) {
+  if constexpr (__is_same(Cost, CostTrack)) {
+    return CostTrack::terminal_at<N>(x, T, p);
+  } else {
+    return Cost::template terminal<N>(x, p);
+  }
+}
+
+}  // namespace mppi

@@ -1,0 +1,109 @@
+// Gaussian control noise for step (a1) of the MPPI iteration: eps ~ N(0, Sigma)
+// (arXiv 2409.07563, Algorithm 1; the paper does not name its generator).
+//
+// Counter-based so that any sample/time entry can be produced independently
+// and reproduced bit for bit on a CPU:
+//   * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+//     easy as 1, 2, 3", SC'11): 10 rounds of the 4x32 round function with the
+//     multipliers 0xD2511F53 / 0xCD9E8D57 and the key bumped by the Weyl
+//     constants 0x9E3779B9 / 0xBB67AE85 between rounds.
+//   * Box-Muller (1958) on 24-bit uniforms.  Every operation below is a single
+//     IEEE-754 binary32 operation with round-to-nearest-even; contraction is
+//     disabled in this file's functions so the compiler cannot fuse or
+//     re-associate them.  Range reductions are exact:
+//       -2 ln u1, u1 = j1 2^-24, j1 in [1, 2^24]:  j1 = 2^e f with
+//         f in [sqrt(1/2), sqrt(2)) read from the float bits of j1, x = f - 1,
+//         ln u1 = (e-24) ln2_hi + ((e-24) ln2_lo + x P(x)), P of degree 9
+//         (Chebyshev interpolant of log1p(x)/x on [sqrt(1/2)-1, sqrt(2)-1]);
+//         the radius is the correctly rounded sqrt.
+//       sincos(2 pi u2), u2 = j2 2^-24: quadrant q = (j2 + 2^21) >> 22, the
+//         remainder f = (j2 - q 2^22) 2^-24 in [-1/8, 1/8) is exact, and
+//         sin / cos of 2 pi f are the order-9 / order-10 Taylor polynomials in
+//         f (binary32 coefficients), evaluated in f^2 by Horner with fma.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mppi {
+namespace noise {
+
+struct Words { uint32_t x0, x1, x2, x3; };
+
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;  // the bump after the last round is never used
+    k1 += 0xBB67AE85u;
+  }
+  return Words{c0, c1, c2, c3};
+}
+
+// Horner coefficients (binary32).  kLog: log1p(x)/x, constant term first.
+__constant__ static const float kLog[10] = {
+    0x1.000000p+0f, -0x1.fffff8p-2f, 0x1.55555ep-2f, -0x1.000424p-2f, 0x1.999e86p-3f,
+    -0x1.5423b0p-3f, 0x1.22cf10p-3f, -0x1.0fb036p-3f, 0x1.064786p-3f, -0x1.31335ap-4f};
+// sin(2 pi f) / f and cos(2 pi f) as polynomials in f^2, constant term first.
+__constant__ static const float kSin[5] = {0x1.921fb6p+2f, -0x1.4abbcep+5f, 0x1.466bc6p+6f,
+                                           -0x1.32d2ccp+6f, 0x1.507834p+5f};
+__constant__ static const float kCos[6] = {0x1.000000p+0f, -0x1.3bd3ccp+4f, 0x1.03c1f0p+6f,
+                                           -0x1.55d3c8p+6f, 0x1.e1f506p+5f, -0x1.a6d1f2p+4f};
+
+// sqrt(-2 ln(j1 * 2^-24)), j1 in [1, 2^24]
+__device__ __forceinline__ float radius(uint32_t j1) {
+#pragma clang fp contract(off)
+  const uint32_t b = __float_as_uint(static_cast<float>(j1));  // exact conversion
+  const uint32_t mant = b & 0x7FFFFFu;
+  const bool high = mant > 0x3504F3u;                          // f > RN(sqrt 2)
+  // f in [sqrt(1/2), sqrt(2)): the mantissa with exponent 0, or -1 when high
+  const float f = __uint_as_float(mant | (high ? 0x3F000000u : 0x3F800000u));
+  const int e = static_cast<int>(b >> 23) - 127 + (high ? 1 : 0);
+  const float x = f - 1.0f;
+  float p = kLog[9];
+#pragma unroll
+  for (int i = 8; i >= 0; --i) p = __builtin_fmaf(p, x, kLog[i]);
+  const float ke = static_cast<float>(e - 24);
+  const float lnu = __builtin_fmaf(ke, 0x1.62e400p-1f, __builtin_fmaf(ke, 0x1.7f7d1cp-20f, x * p));
+  return __builtin_sqrtf(-2.0f * lnu);
+}
+
+// (cos, sin)(2 pi j2 2^-24), j2 in [0, 2^24)
+__device__ __forceinline__ void angle(uint32_t j2, float& c_out, float& s_out) {
+#pragma clang fp contract(off)
+  const uint32_t q = (j2 + (1u << 21)) >> 22;
+  const int32_t rem = static_cast<int32_t>(j2) - static_cast<int32_t>(q << 22);
+  const float f = static_cast<float>(rem) * 0x1p-24f;
+  const float y = f * f;
+  float ps = kSin[4];
+#pragma unroll
+  for (int i = 3; i >= 0; --i) ps = __builtin_fmaf(ps, y, kSin[i]);
+  const float s = f * ps;
+  float c = kCos[5];
+#pragma unroll
+  for (int i = 4; i >= 0; --i) c = __builtin_fmaf(c, y, kCos[i]);
+  // rotate by q * pi/2: (c, s) -> (-s, c) per quadrant
+  const uint32_t qq = q & 3u;
+  const float cs = (qq & 1u) ? s : c;
+  const float sn = (qq & 1u) ? c : s;
+  c_out = ((qq + 1u) & 2u) ? -cs : cs;  // negated in quadrants 1 and 2
+  s_out = (qq & 2u) ? -sn : sn;         // negated in quadrants 2 and 3
+}
+
+// The two standard normals of one Box-Muller pair of Philox words.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
+#pragma clang fp contract(off)
+  const float r = radius((a >> 8) + 1u);
+  float c, s;
+  angle(b >> 8, c, s);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+}  // namespace noise
+}  // namespace mppi

@@ -1,0 +1,50 @@
+"""Shared parity helpers: run a workload through the GPU library and through
+the oracle on the same seeded noise, and the tolerances of the comparison.
+
+Tolerances (the target is 1e-4 relative in binary32):
+  * noise: bit-exact (same counter-based definition on both sides);
+  * rollout costs J: |J_gpu - J_or| <= 1e-4 max(|J_or|, 1) for every sample
+    whose crash decisions are not within binary32 reach of flipping (their
+    smallest relative margin |d^2 - r^2| / r^2 is >= AMBIGUOUS_MARGIN);
+  * controls: |U_gpu - U_or| <= 1e-4 max(|U_or|_inf, |sigma|_inf) plus the
+    change that the allowed cost deviation can cause through the softmin:
+    sum_k |dU/dJ_k| 1e-4 max(|J_k|, 1), dU_t/dJ_k = -(w_k/lambda)(eps_k,t -
+    sum_i w_i eps_i,t) (all computed from the oracle's own values).
+"""
+import numpy as np
+
+REL = 1e-4
+AMBIGUOUS_MARGIN = 1e-3
+
+
+def cost_tol(S_or):
+    return REL * np.maximum(np.abs(S_or), 1.0)
+
+
+def controls_tol(wl, S_or, w_or, eps, lam=None):
+    lam = float(np.float32(wl.lam if lam is None else lam))
+    E = eps.astype(np.float64)                        # [T][m][K]
+    mean = np.tensordot(E, w_or, axes=([2], [0]))     # sum_i w_i eps_i  [T][m]
+    dU = (w_or / lam) * np.abs(E - mean[:, :, None])  # |dU_t / dJ_k|     [T][m][K]
+    prop = np.tensordot(dU, cost_tol(S_or), axes=([2], [0]))
+    scale = max(np.abs(wl.u0).max(), np.abs(wl.sigma).max())
+    return REL * scale + prop
+
+
+def assert_costs_close(S_gpu, S_or, margin=None, name=""):
+    S_gpu = np.asarray(S_gpu, np.float64)
+    ok = np.abs(S_gpu - S_or) <= cost_tol(S_or)
+    if margin is not None:
+        ok |= margin < AMBIGUOUS_MARGIN
+    bad = np.flatnonzero(~ok)
+    assert bad.size == 0, (
+        f"{name}: {bad.size} costs off; first {bad[:5]}: gpu {S_gpu[bad[:5]]} "
+        f"oracle {S_or[bad[:5]]} rel {(np.abs(S_gpu - S_or) / np.maximum(np.abs(S_or), 1))[bad[:5]]}")
+
+
+def assert_controls_close(U_gpu, U_or, tol, name=""):
+    U_gpu = np.asarray(U_gpu, np.float64)
+    err = np.abs(U_gpu - U_or)
+    bad = err > tol
+    assert not bad.any(), (f"{name}: {bad.sum()} controls off, max err {err.max():.3g}, "
+                           f"worst ratio {(err / tol).max():.3g}")

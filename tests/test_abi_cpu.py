@@ -1,0 +1,92 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/mppi.h declares, and rejects invalid configurations synchronously
+(mppi_workspace_bytes validates without touching the device)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2409_07563_amd import _abi
+    _abi.lib()
+    return _abi
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "mppi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mppi_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(abi):
+    names = header_functions()
+    assert len(names) >= 17, names
+    L = abi.lib()
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in abi.EXPORTS, f"{n} missing from the binding"
+    assert sorted(abi.EXPORTS) == names  # and the binding declares nothing else
+
+
+def test_struct_sizes_match_the_header(abi):
+    # sizes of the C structs as laid out by the host compiler
+    assert C.sizeof(abi.Config) == 88
+    assert C.sizeof(abi.Params) == 264
+
+
+def _bytes(abi, wl, **cfg_override):
+    from paper_2409_07563_amd.controller import Controller
+    cfg = abi.Config()
+    cfg.abi_version = abi.ABI_VERSION
+    cfg.dynamics = abi.DYNAMICS[wl.model]
+    cfg.integrator = abi.INTEGRATORS[wl.integrator]
+    cfg.cost = abi.COSTS[wl.cost]
+    cfg.num_samples, cfg.horizon = wl.K, wl.T
+    cfg.state_dim, cfg.control_dim = wl.n, wl.m
+    cfg.dt, cfg.lam = wl.dt, wl.lam
+    for j in range(wl.m):
+        cfg.sigma[j] = float(wl.sigma[j])
+    for k, v in cfg_override.items():
+        setattr(cfg, k, v)
+    params, keep = Controller._params(wl)
+    n = abi.lib().mppi_workspace_bytes(C.byref(cfg), C.byref(params))
+    return n, abi.lib().mppi_last_error().decode()
+
+
+def test_workspace_size_for_valid_configs(abi):
+    for wl in (W.c1(), W.c2("circles", K=8192), W.c2("costmap"), W.c3(K=4096, T=50)):
+        n, msg = _bytes(abi, wl)
+        eps_bytes = 4 * wl.T * wl.m * ((wl.K + 63) // 64 * 64)
+        assert n >= eps_bytes, (wl.name, n, msg)
+        assert n < 4 * eps_bytes + (8 << 20)
+
+
+@pytest.mark.parametrize("override,needle", [
+    ({"abi_version": 99}, "abi_version"), ({"num_samples": 0}, "num_samples"),
+    ({"horizon": 0}, "horizon"), ({"lam": 0.0}, "lambda"), ({"lam": float("nan")}, "lambda"),
+    ({"dt": -1.0}, "dt"), ({"state_dim": 3}, "dims"), ({"dynamics": 9}, "dynamics"),
+    ({"cost": 3}, "not defined"), ({"num_samples": (1 << 20) + 1}, "num_samples")])
+def test_invalid_configs_rejected(abi, override, needle):
+    n, msg = _bytes(abi, W.c2("circles", K=256, T=10), **override)
+    assert n == 0 and needle in msg, msg
+
+
+def test_invalid_params_rejected(abi):
+    wl = W.c2("circles", K=256, T=10)
+    wl.knots = wl.knots[::-1].copy()
+    n, msg = _bytes(abi, wl)
+    assert n == 0 and "knots" in msg
+    wl = W.c3(K=64, T=4)
+    wl.mass = 0.0
+    n, msg = _bytes(abi, wl)
+    assert n == 0 and "mass" in msg
+    n, msg = _bytes(abi, W.c1(K=64, T=4).replace(ref=None))
+    assert n == 0 and "ref" in msg
