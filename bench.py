@@ -48,7 +48,11 @@ def rollout_ops_per_step(wl) -> int:
         nseg = len(wl.knots) - 1
         cost = 2 + (nseg - 1) * 6 + 9 + 1 + 3 + 6 + 4 + 1  # clamp, select, cubic+slope, atan, errors, squares, controls, add
         if wl.cost == "path_circles":
-            cost += 5 * len(wl.cx)  # sub, sub, mul, fma, compare per circle
+            # crash test through the uniform obstacle grid: cell index (2 x
+            # sub, mul, clamp x2, convert) + cell index + 2 list bounds, and
+            # one candidate test (2 sub, mul, fma, compare) -- the useful work
+            # of a point query, whatever the occupancy of its cell
+            cost += 14 + 5
         else:
             cost += 20  # bilinear: index math, 4 gathers, 8 lerp ops
     elif wl.cost == "quadratic":

@@ -109,7 +109,10 @@ typedef enum mppi_cost {
 } mppi_cost;
 
 enum {
-  MPPI_F_DEBUG = 1u /* keep per-sample crash counts (MPPI_DEBUG_CRASHES) */
+  MPPI_F_DEBUG = 1u,         /* keep per-sample crash counts (MPPI_DEBUG_CRASHES) */
+  MPPI_F_ACCURATE_TRIG = 2u  /* bicycle: library sin/cos/tan instead of the hardware
+                                transcendental units (the paper's own choice of
+                                intrinsics for trigonometry, Sec. III-B) */
 };
 
 typedef struct mppi_config {

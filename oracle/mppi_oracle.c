@@ -406,10 +406,19 @@ static int circles_hit(const orc_problem* P, double px, double py,
 /* Bilinear interpolation of the costmap between cell centres, clamped to the
  * edge cells.  Cell (ix, iy) has its centre at
  * (x0 + (ix + 1/2) res, y0 + (iy + 1/2) res). */
+static double costmap_eval_grad(const orc_problem* P, double px, double py, double* slope);
 static double costmap_eval(const orc_problem* P, double px, double py) {
+  double slope;
+  return costmap_eval_grad(P, px, py, &slope);
+}
+
+/* Value and |dM/dx| + |dM/dy| of the bilinear costmap (0 along clamped
+ * directions). */
+static double costmap_eval_grad(const orc_problem* P, double px, double py, double* slope) {
   const int W = P->map_w, H = P->map_h;
   double gx = (px - P->map_x0) / P->map_res - 0.5;
   double gy = (py - P->map_y0) / P->map_res - 0.5;
+  const int clamp_x = gx < 0.0 || gx > W - 1, clamp_y = gy < 0.0 || gy > H - 1;
   if (gx < 0.0) gx = 0.0;
   if (gx > W - 1) gx = W - 1;
   if (gy < 0.0) gy = 0.0;
@@ -421,6 +430,9 @@ static double costmap_eval(const orc_problem* P, double px, double py) {
   const double* m = P->map;
   const double m00 = m[iy * W + ix], m01 = m[iy * W + ix + 1];
   const double m10 = m[(iy + 1) * W + ix], m11 = m[(iy + 1) * W + ix + 1];
+  const double dmx = ((1.0 - fy) * (m01 - m00) + fy * (m11 - m10)) / P->map_res;
+  const double dmy = ((1.0 - fx) * (m10 - m00) + fx * (m11 - m01)) / P->map_res;
+  *slope = (clamp_x ? 0.0 : fabs(dmx)) + (clamp_y ? 0.0 : fabs(dmy));
   return (1.0 - fx) * (1.0 - fy) * m00 + fx * (1.0 - fy) * m01 +
          (1.0 - fx) * fy * m10 + fx * fy * m11;
 }
@@ -464,7 +476,7 @@ static double quad_state_terms(const orc_problem* P, const double* x) {
  */
 static double running_cost(const orc_problem* P, const double* x,
                            const double* v, int t, double* margin,
-                           int* crashed) {
+                           int* crashed, double* slope) {
   const int n = P->n, m = P->m;
   double c = 0.0;
   switch (P->cost) {
@@ -478,7 +490,9 @@ static double running_cost(const orc_problem* P, const double* x,
       if (P->cost == ORC_COST_PATH_CIRCLES) {
         if (circles_hit(P, x[0], x[1], margin)) { c += P->w[6]; ++*crashed; }
       } else {
-        c += costmap_eval(P, x[0], x[1]);
+        double sl;
+        c += costmap_eval_grad(P, x[0], x[1], &sl);
+        *slope += sl;
       }
       break;
     case ORC_COST_HOVER: {
@@ -544,28 +558,30 @@ static double terminal_cost(const orc_problem* P, const double* x) {
 /* Rollout costs J^k for every sample (the inner loops of Algorithm 1):
  * x <- x0; for t: v = u_t + eps_t; x <- F(x, v); J += l(x, v); then J += phi(x).
  * eps is [T][m][ldk].  margin[k] / crashes[k] (optional) receive the smallest
- * crash-decision margin and the number of crashed steps.  Optional xs receives
- * the state trajectory [K][T+1][n]. */
+ * crash-decision margin and the number of crashed steps; slope[k] (optional)
+ * the sum over steps of the costmap's |dM/dx| + |dM/dy| at the visited
+ * positions (how strongly the cost reacts to a position error). */
 void orc_rollout_costs(const orc_problem* P, const double* x0, const double* u,
                        const float* eps, int64_t ldk, double* S, double* margin,
-                       int32_t* crashes) {
+                       int32_t* crashes, double* slope) {
   const int n = P->n, m = P->m;
   for (int32_t k = 0; k < P->K; ++k) {
     double x[16], v[8];
     for (int i = 0; i < n; ++i) x[i] = x0[i];
-    double J = 0.0, mg = INFINITY;
+    double J = 0.0, mg = INFINITY, sl = 0.0;
     int cr = 0;
     for (int32_t t = 0; t < P->T; ++t) {
       for (int j = 0; j < m; ++j)
         v[j] = u[t * m + j] + (double)eps[((int64_t)t * m + j) * ldk + k];
       orc_step(P, x, v);
-      J += running_cost(P, x, v, t, &mg, &cr);
+      J += running_cost(P, x, v, t, &mg, &cr, &sl);
     }
     J += terminal_cost(P, x);
     if (!isfinite(J)) J = INFINITY;
     S[k] = J;
     if (margin) margin[k] = mg;
     if (crashes) crashes[k] = cr;
+    if (slope) slope[k] = sl;
   }
 }
 
@@ -626,7 +642,7 @@ int orc_mppi(const orc_problem* P, const double* x0, double* u, int32_t iters,
   int rc = 0;
   for (int32_t i = 0; i < iters; ++i) {
     orc_noise(P->seed, iter0 + (uint32_t)i, P->instance, K, T, m, P->sigma, K, eps);
-    orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL);
+    orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL, NULL);
     rc = orc_softmin_update(P, S, eps, K, u, w, U, stats_out);
     for (int32_t q = 0; q < T * m; ++q) u[q] = U[q];
   }
@@ -653,13 +669,13 @@ void orc_trajectory(const orc_problem* P, const double* x0, const double* v_seq,
 double orc_sequence_cost(const orc_problem* P, const double* x0,
                          const double* v_seq) {
   const int n = P->n, m = P->m;
-  double x[16], mg = INFINITY;
+  double x[16], mg = INFINITY, sl = 0.0;
   int cr = 0;
   for (int i = 0; i < n; ++i) x[i] = x0[i];
   double J = 0.0;
   for (int32_t t = 0; t < P->T; ++t) {
     orc_step(P, x, v_seq + t * m);
-    J += running_cost(P, x, v_seq + t * m, t, &mg, &cr);
+    J += running_cost(P, x, v_seq + t * m, t, &mg, &cr, &sl);
   }
   return J + terminal_cost(P, x);
 }
@@ -667,9 +683,9 @@ double orc_sequence_cost(const orc_problem* P, const double* x0,
 /* Single-point evaluations used by unit tests of the model and cost pieces. */
 double orc_eval_running_cost(const orc_problem* P, const double* x,
                              const double* v, int32_t t) {
-  double mg = INFINITY;
+  double mg = INFINITY, sl = 0.0;
   int cr = 0;
-  return running_cost(P, x, v, t, &mg, &cr);
+  return running_cost(P, x, v, t, &mg, &cr, &sl);
 }
 double orc_eval_terminal_cost(const orc_problem* P, const double* x) {
   return terminal_cost(P, x);

@@ -65,7 +65,7 @@ def lib():
         L.orc_bm_tables.argtypes = [f32p, f32p, f32p]
         L.orc_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
                                 C.c_int32, f32p, C.c_int64, f32p]
-        L.orc_rollout_costs.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p, f64p, i32p]
+        L.orc_rollout_costs.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p, f64p, i32p, f64p]
         L.orc_softmin_update.argtypes = [P, f64p, f32p, C.c_int64, f64p, f64p, f64p, f64p]
         L.orc_softmin_update.restype = C.c_int
         L.orc_mppi.argtypes = [P, f64p, f64p, C.c_int32, C.c_uint32, f32p, f64p, f64p, f64p]
@@ -183,8 +183,10 @@ def workload_noise(wl, iteration: int = 0) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Algorithm 1
 # --------------------------------------------------------------------------
-def rollout_costs(wl, eps=None, x0=None, u=None, iteration: int = 0, **override):
-    """(S[K], margin[K], crashes[K]) of the rollout stage."""
+def rollout_costs(wl, eps=None, x0=None, u=None, iteration: int = 0, slope=False,
+                  **override):
+    """(S[K], margin[K], crashes[K]) of the rollout stage, plus the costmap
+    slope exposure slope[K] when slope=True."""
     P = Problem(wl, **override)
     if eps is None:
         eps = workload_noise(wl, iteration)
@@ -194,7 +196,10 @@ def rollout_costs(wl, eps=None, x0=None, u=None, iteration: int = 0, **override)
     S = np.empty(wl.K)
     margin = np.empty(wl.K)
     crashes = np.empty(wl.K, np.int32)
-    lib().orc_rollout_costs(P.ref, x0, u, eps, eps.shape[-1], S, margin, crashes)
+    sl = np.empty(wl.K)
+    lib().orc_rollout_costs(P.ref, x0, u, eps, eps.shape[-1], S, margin, crashes, sl)
+    if slope:
+        return S, margin, crashes, sl
     return S, margin, crashes
 
 

@@ -31,11 +31,20 @@ struct DevParams {
   const float* knots;   // [nseg+1]
   const float4* coef;   // [nseg] (c0, c1, c2, c3)
   int ncirc;
-  const float4* circles;  // [ncirc] (cx, cy, r2, 0)
+  // Uniform grid over the circles, staged into LDS by the rollout kernel:
+  // grid[0 .. grid_off4) holds ncell+1 uint32 list offsets, then grid_nent
+  // float4 entries (cx, cy, r2, 0), each circle listed in every cell its
+  // (slightly inflated) bounding box touches.
+  const float4* grid;
+  int grid_nx, grid_ny, grid_off4, grid_words4;
+  float grid_x0, grid_y0, grid_inv_cell;
   int map_w, map_h;
-  float map_x0, map_y0, map_inv_res;
+  float map_x0, map_y0, map_res, map_inv_res;
   const float* costmap;   // [map_h][map_w]
 };
+
+// Largest circle grid the rollout kernel stages into LDS.
+constexpr int kMaxGridBytes = 64 * 1024;
 
 // Per-chunk softmin partials written by the partial-reduction kernel and
 // merged by the merge kernel (see softmin.hip).
@@ -64,9 +73,9 @@ hipError_t launch_noise_tables(float* d_r, float* d_c, float* d_s, hipStream_t s
 // Returns hipErrorInvalidValue when the (dynamics, integrator, cost)
 // combination has no kernel.
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
-                          const DevParams& p, const float* d_x0, const float* d_u,
-                          const float* d_eps, int64_t ldk, int K, int T, float* d_S,
-                          int32_t* d_crashes, hipStream_t stream);
+                          bool accurate_trig, const DevParams& p, const float* d_x0,
+                          const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
+                          float* d_S, int32_t* d_crashes, hipStream_t stream);
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
 
 int softmin_chunks(int K);

@@ -11,9 +11,10 @@ namespace mppi {
 
 // l = sum_i Q_i (x_i - g_i)^2 + sum_j R_j v_j^2;  phi = sum_i Qf_i (x_i - g_i)^2
 struct CostQuadratic {
+  static constexpr bool kGrid = false;
   template <int N, int M>
-  __device__ __forceinline__ static float running(const float* x, const float* v, int,
-                                                  const DevParams& p, bool& hit) {
+  __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int,
+                                                  const DevParams& p, const float4* lds, bool& hit) {
     float c = 0.0f;
 #pragma unroll
     for (int i = 0; i < N; ++i) { const float e = x[i] - p.ref[i]; c += p.w[i] * e * e; }
@@ -55,26 +56,49 @@ __device__ __forceinline__ float path_terms(const float* x, const DevParams& p) 
   return p.w[0] * e * e + p.w[1] * eh * eh + p.w[2] * es * es;
 }
 
-// Point-in-any-circle test (inclusive boundary).
-__device__ __forceinline__ bool in_any_circle(float px, float py, const DevParams& p) {
+// Point-in-any-circle test (inclusive boundary) through the uniform grid
+// staged in LDS: only the circles listed in the point's cell are tested.  A
+// circle is listed in every cell its bounding box, inflated by far more than
+// the binary32 error of the cell computation, touches, so every circle that
+// contains the point is in the list (points off the grid clamp to an edge
+// cell, whose circles cannot contain them).
+__device__ __forceinline__ bool in_any_circle(float px, float py, const DevParams& p,
+                                              const float4* lds) {
+  const float gx = fminf(fmaxf((px - p.grid_x0) * p.grid_inv_cell, 0.0f),
+                         static_cast<float>(p.grid_nx - 1));
+  const float gy = fminf(fmaxf((py - p.grid_y0) * p.grid_inv_cell, 0.0f),
+                         static_cast<float>(p.grid_ny - 1));
+  const int cell = static_cast<int>(gy) * p.grid_nx + static_cast<int>(gx);
+  const uint32_t* off = reinterpret_cast<const uint32_t*>(lds);
+  const float4* ent = lds + p.grid_off4;
+  const uint32_t b = off[cell], e = off[cell + 1];
   bool hit = false;
-  for (int i = 0; i < p.ncirc; ++i) {
-    const float4 c = p.circles[i];
+  for (uint32_t j = b; j < e; ++j) {
+    const float4 c = ent[j];
     const float dx = px - c.x, dy = py - c.y;
     hit |= (dx * dx + dy * dy) <= c.z;
   }
   return hit;
 }
 
-// Bilinear costmap between cell centres, clamped to the edge cells.
-__device__ __forceinline__ float costmap_value(float px, float py, const DevParams& p) {
-  float gx = (px - p.map_x0) * p.map_inv_res - 0.5f;
-  float gy = (py - p.map_y0) * p.map_inv_res - 0.5f;
-  gx = fminf(fmaxf(gx, 0.0f), static_cast<float>(p.map_w - 1));
-  gy = fminf(fmaxf(gy, 0.0f), static_cast<float>(p.map_h - 1));
-  const int ix = min(static_cast<int>(floorf(gx)), p.map_w - 2);
-  const int iy = min(static_cast<int>(floorf(gy)), p.map_h - 2);
-  const float fx = gx - static_cast<float>(ix), fy = gy - static_cast<float>(iy);
+// Bilinear costmap between cell centres, clamped to the edge cells.  The
+// cell comes from the rounded cell coordinate; the interpolation fractions are
+// measured from that cell's centre (exact in binary32 for the usual
+// power-of-two-friendly resolutions) and include the position's compensation
+// term, so they do not inherit the rounding of a coordinate near 256 cells.
+__device__ __forceinline__ float costmap_value(float px, float py, float cpx, float cpy,
+                                               const DevParams& p) {
+  const float gx = fminf(fmaxf((px - p.map_x0) * p.map_inv_res - 0.5f, 0.0f),
+                         static_cast<float>(p.map_w - 1));
+  const float gy = fminf(fmaxf((py - p.map_y0) * p.map_inv_res - 0.5f, 0.0f),
+                         static_cast<float>(p.map_h - 1));
+  const int ix = min(static_cast<int>(gx), p.map_w - 2);
+  const int iy = min(static_cast<int>(gy), p.map_h - 2);
+  const float res = p.map_res;
+  const float cx = p.map_x0 + (static_cast<float>(ix) + 0.5f) * res;
+  const float cy = p.map_y0 + (static_cast<float>(iy) + 0.5f) * res;
+  const float fx = fminf(fmaxf(((px - cx) - cpx) * p.map_inv_res, 0.0f), 1.0f);
+  const float fy = fminf(fmaxf(((py - cy) - cpy) * p.map_inv_res, 0.0f), 1.0f);
   const float* row = p.costmap + static_cast<int64_t>(iy) * p.map_w + ix;
   const float m00 = row[0], m01 = row[1];
   const float m10 = row[p.map_w], m11 = row[p.map_w + 1];
@@ -84,16 +108,17 @@ __device__ __forceinline__ float costmap_value(float px, float py, const DevPara
 
 template <bool CIRCLES>
 struct CostPath {
+  static constexpr bool kGrid = CIRCLES;
   template <int N, int M>
-  __device__ __forceinline__ static float running(const float* x, const float* v, int,
-                                                  const DevParams& p, bool& hit) {
+  __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int,
+                                                  const DevParams& p, const float4* lds, bool& hit) {
     float c = path_terms(x, p) + p.w[4] * v[0] * v[0] + p.w[5] * v[1] * v[1];
     if constexpr (CIRCLES) {
-      hit = in_any_circle(x[0], x[1], p);
+      hit = in_any_circle(x[0], x[1], p, lds);
       c += hit ? p.w[6] : 0.0f;
     } else {
       hit = false;
-      c += costmap_value(x[0], x[1], p);
+      c += costmap_value(x[0], x[1], comp[0], comp[1], p);
     }
     return c;
   }
@@ -105,6 +130,7 @@ struct CostPath {
 
 // Quadrotor hover at a waypoint (ref = waypoint 3, q_ref 4, u_hover 4).
 struct CostHover {
+  static constexpr bool kGrid = false;
   __device__ __forceinline__ static float state_terms(const float* x, const DevParams& p) {
     float cp = 0.0f, cv = 0.0f, cw = 0.0f;
 #pragma unroll
@@ -118,8 +144,8 @@ struct CostHover {
     return p.w[0] * cp + p.w[1] * cv + p.w[2] * cw + p.w[3] * (1.0f - dq * dq);
   }
   template <int N, int M>
-  __device__ __forceinline__ static float running(const float* x, const float* v, int,
-                                                  const DevParams& p, bool& hit) {
+  __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int,
+                                                  const DevParams& p, const float4* lds, bool& hit) {
     float c = state_terms(x, p);
     float cu = 0.0f;
 #pragma unroll
@@ -138,9 +164,10 @@ struct CostHover {
 
 // Time-indexed tracking: l_t = (x - ref_{t+1})' Q (x - ref_{t+1}) + v' R v.
 struct CostTrack {
+  static constexpr bool kGrid = false;
   template <int N, int M>
-  __device__ __forceinline__ static float running(const float* x, const float* v, int t,
-                                                  const DevParams& p, bool& hit) {
+  __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int t,
+                                                  const DevParams& p, const float4* lds, bool& hit) {
     const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
     float c = 0.0f;
 #pragma unroll
@@ -163,12 +190,13 @@ struct CostTrack {
 
 // Goal distance with circular obstacles (bicycle).
 struct CostGoalCircles {
+  static constexpr bool kGrid = true;
   template <int N, int M>
-  __device__ __forceinline__ static float running(const float* x, const float* v, int,
-                                                  const DevParams& p, bool& hit) {
+  __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int,
+                                                  const DevParams& p, const float4* lds, bool& hit) {
     const float dx = x[0] - p.ref[0], dy = x[1] - p.ref[1];
     float c = p.w[0] * (dx * dx + dy * dy) + p.w[1] * v[0] * v[0] + p.w[2] * v[1] * v[1];
-    hit = in_any_circle(x[0], x[1], p);
+    hit = in_any_circle(x[0], x[1], p, lds);
     return c + (hit ? p.w[3] : 0.0f);
   }
   template <int N>

@@ -120,8 +120,8 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
         return fail(MPPI_EINVAL, "spline knots must increase (knot %d)", s + 1);
   }
   if (uses_circles(c->cost)) {
-    if (p->num_circles < 0 || p->num_circles > (1 << 16))
-      return fail(MPPI_EINVAL, "num_circles %d outside [0, 65536]", p->num_circles);
+    if (p->num_circles < 0 || p->num_circles > 2048)
+      return fail(MPPI_EINVAL, "num_circles %d outside [0, 2048]", p->num_circles);
     if (p->num_circles > 0 && (!p->cx || !p->cy || !p->r2))
       return fail(MPPI_EINVAL, "circle arrays must not be NULL");
   }
@@ -158,14 +158,90 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m) {
   const int S = uses_spline(c->cost) ? p->num_segments : 0;
   L.knots = take(sizeof(float) * (S + 1));
   L.coef = take(sizeof(float4) * (S > 0 ? S : 1));
-  const int N = uses_circles(c->cost) ? p->num_circles : 0;
-  L.circles = take(sizeof(float4) * (N > 0 ? N : 1));
+  L.circles = take(uses_circles(c->cost) ? kMaxGridBytes : sizeof(float4));
   const size_t cells =
       c->cost == MPPI_COST_PATH_COSTMAP ? (size_t)p->map_w * (size_t)p->map_h : 1;
   L.costmap = take(sizeof(float) * cells);
   L.mlp = take(sizeof(float));
   L.total = off;
   return L;
+}
+
+
+// Uniform grid over the circles for the rollout's crash test.  Each circle is
+// listed in every cell that its bounding box, inflated by delta = 1e-3 cells,
+// touches; the kernel computes a point's cell in binary32 with an error far
+// below delta, so the list of the computed cell holds every circle that
+// contains the point.  The cell size starts near two circle radii (about one
+// listed circle per cell) and grows until the grid fits kMaxGridBytes of LDS.
+struct Grid {
+  std::vector<float4> words;  // offsets (uint32, padded to float4) then entries
+  int nx = 1, ny = 1, off4 = 1;
+  float x0 = 0.0f, y0 = 0.0f, inv_cell = 1.0f;
+};
+
+bool build_grid(const float* cx, const float* cy, const float* r2, int N, Grid* g) {
+  g->words.assign(1, float4{0, 0, 0, 0});  // one empty cell: offsets {0, 0}
+  g->nx = g->ny = 1;
+  g->off4 = 1;
+  if (N == 0) return true;
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300, rmax = 0.0;
+  std::vector<double> r(N);
+  for (int i = 0; i < N; ++i) {
+    r[i] = sqrt(fmax(static_cast<double>(r2[i]), 0.0));
+    rmax = fmax(rmax, r[i]);
+    xmin = fmin(xmin, cx[i] - r[i]); xmax = fmax(xmax, cx[i] + r[i]);
+    ymin = fmin(ymin, cy[i] - r[i]); ymax = fmax(ymax, cy[i] + r[i]);
+  }
+  const double span = fmax(xmax - xmin, ymax - ymin);
+  double cell = fmax(2.0 * rmax, sqrt((xmax - xmin) * (ymax - ymin) / (4.0 * N)));
+  cell = fmax(cell, 1e-3 * (1.0 + fabs(xmin) + fabs(xmax) + fabs(ymin) + fabs(ymax)));
+  cell = fmax(cell, span / 256.0);
+  for (int attempt = 0; attempt < 64; ++attempt, cell *= 1.5) {
+    const float inv = static_cast<float>(1.0 / cell);
+    const double c = 1.0 / static_cast<double>(inv);  // the cell size the kernel sees
+    const float fx0 = static_cast<float>(xmin - 0.5 * c), fy0 = static_cast<float>(ymin - 0.5 * c);
+    const int nx = static_cast<int>(floor((xmax - fx0) / c)) + 2;
+    const int ny = static_cast<int>(floor((ymax - fy0) / c)) + 2;
+    if (nx > 256 || ny > 256) continue;
+    const int ncell = nx * ny;
+    const double delta = 1e-3 * c;
+    auto span_of = [&](double lo, double hi, double o, int n, int* a, int* b) {
+      *a = static_cast<int>(floor((lo - delta - o) / c));
+      *b = static_cast<int>(floor((hi + delta - o) / c));
+      *a = *a < 0 ? 0 : (*a > n - 1 ? n - 1 : *a);
+      *b = *b < 0 ? 0 : (*b > n - 1 ? n - 1 : *b);
+    };
+    std::vector<uint32_t> count(ncell + 1, 0);
+    for (int i = 0; i < N; ++i) {
+      int ax, bx, ay, by;
+      span_of(cx[i] - r[i], cx[i] + r[i], fx0, nx, &ax, &bx);
+      span_of(cy[i] - r[i], cy[i] + r[i], fy0, ny, &ay, &by);
+      for (int iy = ay; iy <= by; ++iy)
+        for (int ix = ax; ix <= bx; ++ix) ++count[iy * nx + ix + 1];
+    }
+    for (int q = 0; q < ncell; ++q) count[q + 1] += count[q];
+    const uint32_t nent = count[ncell];
+    const int off4 = (ncell + 1 + 3) / 4;
+    if (16.0 * (off4 + static_cast<double>(nent)) > kMaxGridBytes) continue;
+    std::vector<float4> words(off4 + nent, float4{0, 0, 0, 0});
+    uint32_t* off = reinterpret_cast<uint32_t*>(words.data());
+    for (int q = 0; q <= ncell; ++q) off[q] = count[q];
+    std::vector<uint32_t> fill(count.begin(), count.end() - 1);
+    for (int i = 0; i < N; ++i) {
+      int ax, bx, ay, by;
+      span_of(cx[i] - r[i], cx[i] + r[i], fx0, nx, &ax, &bx);
+      span_of(cy[i] - r[i], cy[i] + r[i], fy0, ny, &ay, &by);
+      for (int iy = ay; iy <= by; ++iy)
+        for (int ix = ax; ix <= bx; ++ix)
+          words[off4 + fill[iy * nx + ix]++] = float4{cx[i], cy[i], r2[i], 0.0f};
+    }
+    g->words.swap(words);
+    g->nx = nx; g->ny = ny; g->off4 = off4;
+    g->x0 = fx0; g->y0 = fy0; g->inv_cell = inv;
+    return true;
+  }
+  return false;
 }
 
 }  // namespace
@@ -233,8 +309,11 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
       coef[s] = float4{p->coef[4 * s], p->coef[4 * s + 1], p->coef[4 * s + 2], p->coef[4 * s + 3]};
   }
   const int N = uses_circles(cfg->cost) ? p->num_circles : 0;
-  std::vector<float4> circles(N > 0 ? N : 1, float4{0, 0, 0, 0});
-  for (int i = 0; i < N; ++i) circles[i] = float4{p->cx[i], p->cy[i], p->r2[i], 0.0f};
+  Grid grid;
+  if (!build_grid(p->cx, p->cy, p->r2, N, &grid)) {
+    delete c;
+    return fail(MPPI_EUNSUPPORTED, "circle grid does not fit %d bytes of LDS", kMaxGridBytes);
+  }
 
   auto fail_free = [&](mppi_status s) { delete c; return s; };
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
@@ -249,7 +328,7 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
   if (e == hipSuccess) e = up(L.ref, ref.data(), sizeof(float) * ref.size());
   if (e == hipSuccess) e = up(L.knots, knots.data(), sizeof(float) * knots.size());
   if (e == hipSuccess) e = up(L.coef, coef.data(), sizeof(float4) * coef.size());
-  if (e == hipSuccess) e = up(L.circles, circles.data(), sizeof(float4) * circles.size());
+  if (e == hipSuccess) e = up(L.circles, grid.words.data(), sizeof(float4) * grid.words.size());
   if (e == hipSuccess && cfg->cost == MPPI_COST_PATH_COSTMAP)
     e = up(L.costmap, p->costmap, sizeof(float) * (size_t)p->map_w * p->map_h);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -273,12 +352,20 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
   d.knots = c->at<float>(L.knots);
   d.coef = c->at<float4>(L.coef);
   d.ncirc = N;
-  d.circles = c->at<float4>(L.circles);
+  d.grid = c->at<float4>(L.circles);
+  d.grid_nx = grid.nx;
+  d.grid_ny = grid.ny;
+  d.grid_off4 = grid.off4;
+  d.grid_words4 = static_cast<int>(grid.words.size());
+  d.grid_x0 = grid.x0;
+  d.grid_y0 = grid.y0;
+  d.grid_inv_cell = grid.inv_cell;
   if (cfg->cost == MPPI_COST_PATH_COSTMAP) {
     d.map_w = p->map_w;
     d.map_h = p->map_h;
     d.map_x0 = p->map_x0;
     d.map_y0 = p->map_y0;
+    d.map_res = p->map_res;
     d.map_inv_res = static_cast<float>(1.0 / static_cast<double>(p->map_res));
     d.costmap = c->at<float>(L.costmap);
   }
@@ -325,7 +412,8 @@ mppi_status mppi_rollout(mppi_ctx* c) {
   int32_t* crashes = (c->cfg.flags & MPPI_F_DEBUG) && uses_circles(c->cfg.cost)
                          ? c->at<int32_t>(c->L.crashes)
                          : nullptr;
-  hipError_t e = launch_rollout(c->cfg.dynamics, c->cfg.integrator, c->cfg.cost, c->dp,
+  hipError_t e = launch_rollout(c->cfg.dynamics, c->cfg.integrator, c->cfg.cost,
+                                (c->cfg.flags & MPPI_F_ACCURATE_TRIG) != 0, c->dp,
                                 c->at<float>(c->L.x0), c->at<float>(c->L.u),
                                 c->at<float>(c->L.eps), c->L.ldk, c->K, c->T,
                                 c->at<float>(c->L.S), crashes, c->stream);

@@ -2,33 +2,40 @@
 // registers for the whole horizon; per step it reads its noise (coalesced:
 // lanes are consecutive samples of one [T*m][ldk] row), forms v = u_t + eps,
 // advances the dynamics and adds the running cost with compensated (Kahan)
-// summation; the terminal cost closes the sum.  u_t and every cost constant
-// are wave-uniform and arrive through scalar loads.  The noise of step t+1 is
-// requested before step t is computed so that its HBM latency overlaps the
-// arithmetic.
+// summation; the terminal cost closes the sum.  u_t, the spline and every
+// cost weight are wave-uniform and arrive through scalar loads; the obstacle
+// grid (circle costs) is staged once per workgroup into LDS.  The noise of
+// step t+1 is requested before step t is computed so that its memory latency
+// overlaps the arithmetic.
 #include "common.h"
 #include "costs.h"
 #include "dynamics.h"
 
 namespace mppi {
 
+constexpr int kRolloutBlock = 64;
+
 template <class Model, int INTEG, class Cost, bool COUNT>
-__global__ __launch_bounds__(64) void rollout_kernel(DevParams p, const float* __restrict__ x0,
-                                                     const float* __restrict__ u,
-                                                     const float* __restrict__ eps, int64_t ldk,
-                                                     int K, int T, float* __restrict__ S,
-                                                     int32_t* __restrict__ crashes) {
+__global__ __launch_bounds__(kRolloutBlock) void rollout_kernel(
+    DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
+    const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
+    int32_t* __restrict__ crashes) {
   constexpr int N = Model::N, M = Model::M;
+  extern __shared__ float4 lds[];
+  if constexpr (Cost::kGrid) {
+    for (int i = threadIdx.x; i < p.grid_words4; i += blockDim.x) lds[i] = p.grid[i];
+    __syncthreads();
+  }
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  float x[N];
+  if (k >= K) return;  // no barrier follows
+  float x[N], comp[N > 0 ? N : 1];
 #pragma unroll
-  for (int i = 0; i < N; ++i) x[i] = x0[i];
+  for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
   const float* e = eps + k;
   float nxt[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) nxt[j] = e[j * ldk];
-  float sum = 0.0f, comp = 0.0f;
+  float sum = 0.0f, sum_c = 0.0f;
   int ncrash = 0;
   for (int t = 0; t < T; ++t) {
     float v[M];
@@ -39,19 +46,16 @@ __global__ __launch_bounds__(64) void rollout_kernel(DevParams p, const float* _
 #pragma unroll
       for (int j = 0; j < M; ++j) nxt[j] = en[j * ldk];
     }
-    step<Model, INTEG>(x, v, p);
+    step<Model, INTEG>(x, v, comp, p);
     bool hit;
-    const float l = Cost::template running<N, M>(x, v, t, p, hit);
+    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, hit);
     if constexpr (COUNT) ncrash += hit ? 1 : 0;
-    const float y = l - comp;
+    const float y = l - sum_c;
     const float s = sum + y;
-    comp = (s - sum) - y;
+    sum_c = (s - sum) - y;
     sum = s;
   }
-  {
-    const float y = terminal_cost<Cost, N>(x, T, p) - comp;
-    sum = sum + y;
-  }
+  sum = sum + (terminal_cost<Cost, N>(x, T, p) - sum_c);
   S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
   if constexpr (COUNT) crashes[k] = ncrash;
 }
@@ -63,60 +67,68 @@ using RolloutFn = void (*)(DevParams, const float*, const float*, const float*, 
 
 template <class Model, int INTEG, class Cost>
 RolloutFn pick(bool count) {
-  return count ? rollout_kernel<Model, INTEG, Cost, true> : rollout_kernel<Model, INTEG, Cost, false>;
+  if (count) return rollout_kernel<Model, INTEG, Cost, true>;
+  return rollout_kernel<Model, INTEG, Cost, false>;
+}
+
+// costs defined for every model, and those that need the bicycle's layout
+// (px, py, yaw, speed, ...) or the quadrotor's
+template <class Model, int INTEG>
+RolloutFn pick_generic(uint32_t cost, bool count) {
+  if (cost == MPPI_COST_QUADRATIC) return pick<Model, INTEG, CostQuadratic>(count);
+  if (cost == MPPI_COST_TRACK) return pick<Model, INTEG, CostTrack>(count);
+  return nullptr;
 }
 
 template <class Model, int INTEG>
-RolloutFn pick_cost(uint32_t cost, bool count, bool wheeled, bool quad) {
+RolloutFn pick_wheeled(uint32_t cost, bool count) {
   switch (cost) {
-    case MPPI_COST_QUADRATIC: return pick<Model, INTEG, CostQuadratic>(count);
-    case MPPI_COST_TRACK: return pick<Model, INTEG, CostTrack>(count);
-    case MPPI_COST_PATH_CIRCLES:
-      return wheeled ? pick<Model, INTEG, CostPath<true>>(count) : nullptr;
-    case MPPI_COST_PATH_COSTMAP:
-      return wheeled ? pick<Model, INTEG, CostPath<false>>(count) : nullptr;
-    case MPPI_COST_GOAL_CIRCLES:
-      return wheeled ? pick<Model, INTEG, CostGoalCircles>(count) : nullptr;
-    case MPPI_COST_HOVER: return quad ? pick<Model, INTEG, CostHover>(count) : nullptr;
+    case MPPI_COST_PATH_CIRCLES: return pick<Model, INTEG, CostPath<true>>(count);
+    case MPPI_COST_PATH_COSTMAP: return pick<Model, INTEG, CostPath<false>>(count);
+    case MPPI_COST_GOAL_CIRCLES: return pick<Model, INTEG, CostGoalCircles>(count);
+    default: return pick_generic<Model, INTEG>(cost, count);
+  }
+}
+
+template <int INTEG>
+RolloutFn pick_model(uint32_t dynamics, uint32_t cost, bool accurate, bool count) {
+  switch (dynamics) {
+    case MPPI_DYN_DOUBLE_INTEGRATOR: return pick_generic<DoubleIntegrator, INTEG>(cost, count);
+    case MPPI_DYN_BICYCLE:
+      return accurate ? pick_wheeled<Bicycle<false>, INTEG>(cost, count)
+                      : pick_wheeled<Bicycle<true>, INTEG>(cost, count);
+    case MPPI_DYN_QUADROTOR:
+      if (cost == MPPI_COST_HOVER) return pick<Quadrotor, INTEG, CostHover>(count);
+      return pick_generic<Quadrotor, INTEG>(cost, count);
     default: return nullptr;
   }
 }
 
-template <class Model>
-RolloutFn pick_integrator(uint32_t integ, uint32_t cost, bool count, bool wheeled, bool quad) {
-  if (integ == MPPI_INT_EULER) return pick_cost<Model, kEuler>(cost, count, wheeled, quad);
-  if (integ == MPPI_INT_RK4) return pick_cost<Model, kRK4>(cost, count, wheeled, quad);
+RolloutFn select(uint32_t dynamics, uint32_t integ, uint32_t cost, bool accurate, bool count) {
+  if (integ == MPPI_INT_EULER) return pick_model<kEuler>(dynamics, cost, accurate, count);
+  if (integ == MPPI_INT_RK4) return pick_model<kRK4>(dynamics, cost, accurate, count);
   return nullptr;
 }
 
-RolloutFn select(uint32_t dynamics, uint32_t integ, uint32_t cost, bool count) {
-  switch (dynamics) {
-    case MPPI_DYN_DOUBLE_INTEGRATOR:
-      return pick_integrator<DoubleIntegrator>(integ, cost, count, false, false);
-    case MPPI_DYN_BICYCLE:
-      return pick_integrator<Bicycle>(integ, cost, count, true, false);
-    case MPPI_DYN_QUADROTOR:
-      return pick_integrator<Quadrotor>(integ, cost, count, false, true);
-    default:
-      return nullptr;
-  }
+bool uses_grid(uint32_t cost) {
+  return cost == MPPI_COST_PATH_CIRCLES || cost == MPPI_COST_GOAL_CIRCLES;
 }
 
 }  // namespace
 
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost) {
-  return select(dynamics, integrator, cost, false) != nullptr;
+  return select(dynamics, integrator, cost, false, false) != nullptr;
 }
 
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
-                          const DevParams& p, const float* d_x0, const float* d_u,
-                          const float* d_eps, int64_t ldk, int K, int T, float* d_S,
-                          int32_t* d_crashes, hipStream_t stream) {
-  RolloutFn fn = select(dynamics, integrator, cost, d_crashes != nullptr);
+                          bool accurate_trig, const DevParams& p, const float* d_x0,
+                          const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
+                          float* d_S, int32_t* d_crashes, hipStream_t stream) {
+  RolloutFn fn = select(dynamics, integrator, cost, accurate_trig, d_crashes != nullptr);
   if (!fn) return hipErrorInvalidValue;
-  constexpr int kBlock = 64;
-  hipLaunchKernelGGL(fn, dim3((K + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, p, d_x0, d_u,
-                     d_eps, ldk, K, T, d_S, d_crashes);
+  const size_t lds = uses_grid(cost) ? sizeof(float4) * static_cast<size_t>(p.grid_words4) : 0;
+  hipLaunchKernelGGL(fn, dim3((K + kRolloutBlock - 1) / kRolloutBlock), dim3(kRolloutBlock), lds,
+                     stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S, d_crashes);
   return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ def test_noise_bitexact(mppi, oracle_lib, seed, it, inst, K, T, m):
 # workloads at oracle-friendly sizes (several tiles and a ragged tail)
 # ---------------------------------------------------------------------------
 def _cases():
-    c4 = W.c4(n_instances=2)[1].replace(K=700, T=60)
+    c4 = W.c4(n_instances=2)[1].replace(K=700, T=60, u0=np.zeros((60, 2), np.float32))
     return {
         "c1": W.c1(K=1024, T=100),
         "c1_ragged": W.c1(K=1000, T=37),
@@ -83,13 +83,14 @@ def _cases():
 CASES = _cases()
 
 
-def _run_one_iteration(mppi, wl, debug=True):
-    ctl = mppi.Controller(wl, debug=debug and wl.cost in ("path_circles", "goal_circles"))
+def _run_one_iteration(mppi, wl, debug=True, accurate_trig=False):
+    ctl = mppi.Controller(wl, debug=debug and wl.cost in ("path_circles", "goal_circles"),
+                          accurate_trig=accurate_trig)
     ctl.sample()
     ctl.rollout()
     S = _np(ctl.costs())
     eps = _np(ctl.noise())
-    crashes = _np(ctl.crashes()) if ctl.cfg.flags else None
+    crashes = _np(ctl.crashes()) if ctl.cfg.flags & 1 else None
     ctl.update()
     U = _np(ctl.controls())
     stats = ctl.stats()
@@ -98,14 +99,19 @@ def _run_one_iteration(mppi, wl, debug=True):
     return dict(S=S, eps=eps, U=U, stats=stats, w=w, crashes=crashes)
 
 
+TRIG = [False, True]
+
+
+@pytest.mark.parametrize("accurate", TRIG, ids=["hw_trig", "lib_trig"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_rollout_costs_parity(mppi, oracle_lib, name):
+def test_rollout_costs_parity(mppi, oracle_lib, name, accurate):
     wl = CASES[name]
-    g = _run_one_iteration(mppi, wl)
+    g = _run_one_iteration(mppi, wl, accurate_trig=accurate)
     eps_or = oracle_lib.workload_noise(wl)
     assert np.array_equal(g["eps"].view(np.uint32), eps_or.view(np.uint32))
-    S_or, margin, crashes = oracle_lib.rollout_costs(wl, eps=eps_or)
-    parity.assert_costs_close(g["S"], S_or, margin, name)
+    S_or, margin, crashes, slope = oracle_lib.rollout_costs(wl, eps=eps_or, slope=True)
+    parity.assert_costs_close(g["S"], S_or, margin, name,
+                              slope=slope if wl.cost == "path_costmap" else None)
     if g["crashes"] is not None:
         sure = margin >= parity.AMBIGUOUS_MARGIN
         assert np.array_equal(g["crashes"][sure], crashes[sure])
@@ -139,10 +145,11 @@ def test_update_parity_on_oracle_costs(mppi, oracle_lib, name):
     assert np.allclose(w, w_or, rtol=1e-4, atol=1e-7)
 
 
+@pytest.mark.parametrize("accurate", TRIG, ids=["hw_trig", "lib_trig"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_iteration_end_to_end(mppi, oracle_lib, name):
+def test_iteration_end_to_end(mppi, oracle_lib, name, accurate):
     wl = CASES[name]
-    g = _run_one_iteration(mppi, wl)
+    g = _run_one_iteration(mppi, wl, accurate_trig=accurate)
     o = oracle_lib.mppi(wl, iters=1)
     tol = parity.controls_tol(wl, o["S"], o["w"], o["eps"])
     parity.assert_controls_close(g["U"], o["U"], tol, name)
@@ -151,9 +158,8 @@ def test_iteration_end_to_end(mppi, oracle_lib, name):
 
 def test_c2_full_size_ten_iterations(mppi, oracle_lib):
     """The benchmark workload (K 8192, T 100, 10 warm-started iterations):
-    every iteration checked from the oracle's own warm start, then the
-    10-iteration result of one mppi_iterate(10) call against the per-iteration
-    chain it is made of."""
+    every iteration checked from the oracle's own warm start (the GPU is
+    handed the oracle's u and iteration word)."""
     wl = W.c2("circles")
     ctl = mppi.Controller(wl)
     u = wl.u0.astype(np.float64)
