@@ -28,16 +28,19 @@ struct DevParams {
   float w[32];
   const float* ref;
   int nseg;
-  const float* knots;   // [nseg+1]
-  const float4* coef;   // [nseg] (c0, c1, c2, c3)
   int ncirc;
-  // Uniform grid over the circles, staged into LDS by the rollout kernel:
-  // grid[0 .. grid_off4) holds ncell+1 uint32 list offsets, then grid_nent
-  // float4 entries (cx, cy, r2, 0), each circle listed in every cell its
-  // (slightly inflated) bounding box touches.
-  const float4* grid;
-  int grid_nx, grid_ny, grid_off4, grid_words4;
+  // Read-only cost data that the rollout kernel stages into LDS (one float4
+  // array, `stage_words4` long):
+  //   circle grid at float4 offset 0: ncell+1 uint32 list offsets padded to
+  //   grid_off4 float4s, then the entries (cx, cy, r2, 0), each circle listed
+  //   in every cell its (slightly inflated) bounding box touches;
+  //   spline at float4 offset spline_coef4: nseg coefficient rows (c0..c3),
+  //   then the nseg+1 knots from float4 offset spline_knot4.
+  const float4* stage;
+  int stage_words4;
+  int grid_nx, grid_ny, grid_off4;
   float grid_x0, grid_y0, grid_inv_cell;
+  int spline_coef4, spline_knot4;
   int map_w, map_h;
   float map_x0, map_y0, map_res, map_inv_res;
   const float* costmap;   // [map_h][map_w]
@@ -77,6 +80,9 @@ hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           float* d_S, int32_t* d_crashes, hipStream_t stream);
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
+// LDS bytes the rollout kernel stages (cost data + the nominal controls).
+size_t rollout_lds_bytes(uint32_t dynamics, uint32_t cost, int stage_words4, int T);
+constexpr size_t kMaxRolloutLds = 160 * 1024;
 
 int softmin_chunks(int K);
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,

@@ -10,11 +10,20 @@
 namespace mppi {
 
 // l = sum_i Q_i (x_i - g_i)^2 + sum_j R_j v_j^2;  phi = sum_i Qf_i (x_i - g_i)^2
+// Every cost has a per-lane State (carried in registers across the horizon)
+// and reads staged data from `lds`; kStage says whether the kernel must stage
+// the read-only cost data.
+struct NoState {};
+
 struct CostQuadratic {
-  static constexpr bool kGrid = false;
+  static constexpr bool kStage = false;
+  using State = NoState;
+  __device__ __forceinline__ static void init(State&, const float*, const DevParams&,
+                                              const float4*) {}
   template <int N, int M>
   __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int,
-                                                  const DevParams& p, const float4* lds, bool& hit) {
+                                                  const DevParams& p, const float4* lds, State&,
+                                                  bool& hit) {
     float c = 0.0f;
 #pragma unroll
     for (int i = 0; i < N; ++i) { const float e = x[i] - p.ref[i]; c += p.w[i] * e * e; }
@@ -32,21 +41,45 @@ struct CostQuadratic {
   }
 };
 
-// Lateral, heading and speed errors of the bicycle against the spline path
-// y = s(x), with px clamped to the knot range and the segment chosen without
-// branches (knots and coefficients are wave-uniform scalar loads).
-__device__ __forceinline__ float path_terms(const float* x, const DevParams& p) {
-  const float px = fminf(fmaxf(x[0], p.knots[0]), p.knots[p.nseg]);
-  float4 c = p.coef[0];
-  float k0 = p.knots[0];
-  for (int s = 1; s < p.nseg; ++s) {
-    const float ks = p.knots[s];
-    const float4 cs = p.coef[s];
-    const bool sel = px >= ks;
-    k0 = sel ? ks : k0;
-    c.x = sel ? cs.x : c.x; c.y = sel ? cs.y : c.y;
-    c.z = sel ? cs.z : c.z; c.w = sel ? cs.w : c.w;
+// The spline segment of a lane's current position, cached in registers: a
+// trajectory moves a few centimetres per step, so the segment rarely changes
+// and re-selecting it costs two compares; a change reloads the segment's
+// knots and coefficients from LDS.  Segment s covers [knot_s, knot_{s+1})
+// (the last one also its right end), matching a search over all segments.
+struct SplineCursor {
+  int seg;
+  float lo, hi;  // knots of seg and seg+1
+  float4 c;
+};
+
+__device__ __forceinline__ void spline_load(SplineCursor& sc, int seg, const DevParams& p,
+                                            const float4* lds) {
+  const float* knots = reinterpret_cast<const float*>(lds + p.spline_knot4);
+  sc.seg = seg;
+  sc.lo = knots[seg];
+  sc.hi = knots[seg + 1];
+  sc.c = lds[p.spline_coef4 + seg];
+}
+
+// Moves the cursor to the segment of px (already clamped to the knot range).
+__device__ __forceinline__ void spline_seek(SplineCursor& sc, float px, const DevParams& p,
+                                            const float4* lds) {
+  const float* knots = reinterpret_cast<const float*>(lds + p.spline_knot4);
+  int seg = sc.seg;
+  if (px >= sc.hi || px < sc.lo) {
+    while (seg + 1 < p.nseg && px >= knots[seg + 1]) ++seg;
+    while (seg > 0 && px < knots[seg]) --seg;
+    spline_load(sc, seg, p, lds);
   }
+}
+
+__device__ __forceinline__ float path_terms(const float* x, SplineCursor& sc,
+                                            const DevParams& p, const float4* lds) {
+  const float* knots = reinterpret_cast<const float*>(lds + p.spline_knot4);
+  const float px = fminf(fmaxf(x[0], knots[0]), knots[p.nseg]);
+  spline_seek(sc, px, p, lds);
+  const float4 c = sc.c;
+  const float k0 = sc.lo;
   const float d = px - k0;
   const float y = c.x + d * (c.y + d * (c.z + d * c.w));
   const float dy = c.y + d * (2.0f * c.z + 3.0f * d * c.w);
@@ -70,7 +103,7 @@ __device__ __forceinline__ bool in_any_circle(float px, float py, const DevParam
                          static_cast<float>(p.grid_ny - 1));
   const int cell = static_cast<int>(gy) * p.grid_nx + static_cast<int>(gx);
   const uint32_t* off = reinterpret_cast<const uint32_t*>(lds);
-  const float4* ent = lds + p.grid_off4;
+  const float4* ent = lds + p.grid_off4;  // grid at the start of the stage
   const uint32_t b = off[cell], e = off[cell + 1];
   bool hit = false;
   for (uint32_t j = b; j < e; ++j) {
@@ -108,11 +141,17 @@ __device__ __forceinline__ float costmap_value(float px, float py, float cpx, fl
 
 template <bool CIRCLES>
 struct CostPath {
-  static constexpr bool kGrid = CIRCLES;
+  static constexpr bool kStage = true;
+  using State = SplineCursor;
+  __device__ __forceinline__ static void init(State& st, const float*, const DevParams& p,
+                                              const float4* lds) {
+    spline_load(st, 0, p, lds);
+  }
   template <int N, int M>
   __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int,
-                                                  const DevParams& p, const float4* lds, bool& hit) {
-    float c = path_terms(x, p) + p.w[4] * v[0] * v[0] + p.w[5] * v[1] * v[1];
+                                                  const DevParams& p, const float4* lds, State& st,
+                                                  bool& hit) {
+    float c = path_terms(x, st, p, lds) + p.w[4] * v[0] * v[0] + p.w[5] * v[1] * v[1];
     if constexpr (CIRCLES) {
       hit = in_any_circle(x[0], x[1], p, lds);
       c += hit ? p.w[6] : 0.0f;
@@ -123,14 +162,18 @@ struct CostPath {
     return c;
   }
   template <int N>
-  __device__ __forceinline__ static float terminal(const float* x, const DevParams& p) {
-    return p.w[7] * path_terms(x, p);
+  __device__ __forceinline__ static float terminal(const float* x, const DevParams& p,
+                                                   const float4* lds, State& st) {
+    return p.w[7] * path_terms(x, st, p, lds);
   }
 };
 
 // Quadrotor hover at a waypoint (ref = waypoint 3, q_ref 4, u_hover 4).
 struct CostHover {
-  static constexpr bool kGrid = false;
+  static constexpr bool kStage = false;
+  using State = NoState;
+  __device__ __forceinline__ static void init(State&, const float*, const DevParams&,
+                                              const float4*) {}
   __device__ __forceinline__ static float state_terms(const float* x, const DevParams& p) {
     float cp = 0.0f, cv = 0.0f, cw = 0.0f;
 #pragma unroll
@@ -145,7 +188,8 @@ struct CostHover {
   }
   template <int N, int M>
   __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int,
-                                                  const DevParams& p, const float4* lds, bool& hit) {
+                                                  const DevParams& p, const float4* lds, State&,
+                                                  bool& hit) {
     float c = state_terms(x, p);
     float cu = 0.0f;
 #pragma unroll
@@ -164,10 +208,14 @@ struct CostHover {
 
 // Time-indexed tracking: l_t = (x - ref_{t+1})' Q (x - ref_{t+1}) + v' R v.
 struct CostTrack {
-  static constexpr bool kGrid = false;
+  static constexpr bool kStage = false;
+  using State = NoState;
+  __device__ __forceinline__ static void init(State&, const float*, const DevParams&,
+                                              const float4*) {}
   template <int N, int M>
   __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int t,
-                                                  const DevParams& p, const float4* lds, bool& hit) {
+                                                  const DevParams& p, const float4* lds, State&,
+                                                  bool& hit) {
     const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
     float c = 0.0f;
 #pragma unroll
@@ -190,10 +238,14 @@ struct CostTrack {
 
 // Goal distance with circular obstacles (bicycle).
 struct CostGoalCircles {
-  static constexpr bool kGrid = true;
+  static constexpr bool kStage = true;
+  using State = NoState;
+  __device__ __forceinline__ static void init(State&, const float*, const DevParams&,
+                                              const float4*) {}
   template <int N, int M>
   __device__ __forceinline__ static float running(const float* x, const float* comp, const float* v, int,
-                                                  const DevParams& p, const float4* lds, bool& hit) {
+                                                  const DevParams& p, const float4* lds, State&,
+                                                  bool& hit) {
     const float dx = x[0] - p.ref[0], dy = x[1] - p.ref[1];
     float c = p.w[0] * (dx * dx + dy * dy) + p.w[1] * v[0] * v[0] + p.w[2] * v[1] * v[1];
     hit = in_any_circle(x[0], x[1], p, lds);
@@ -206,11 +258,15 @@ struct CostGoalCircles {
   }
 };
 
-// Uniform access to the terminal cost (TRACK needs the horizon).
+// Uniform access to the terminal cost (TRACK needs the horizon, the path cost
+// its staged spline and cursor).
 template <class Cost, int N>
-__device__ __forceinline__ float terminal_cost(const float* x, int T, const DevParams& p) {
+__device__ __forceinline__ float terminal_cost(const float* x, int T, const DevParams& p,
+                                               const float4* lds, typename Cost::State& st) {
   if constexpr (__is_same(Cost, CostTrack)) {
     return CostTrack::terminal_at<N>(x, T, p);
+  } else if constexpr (__is_same(Cost, CostPath<true>) || __is_same(Cost, CostPath<false>)) {
+    return Cost::template terminal<N>(x, p, lds, st);
   } else {
     return Cost::template terminal<N>(x, p);
   }

@@ -37,7 +37,7 @@ struct Bicycle {
     if constexpr (FAST) {
       sn = __sinf(x[2]);
       cs = __cosf(x[2]);
-      tn = __fdividef(__sinf(x[4]), __cosf(x[4]));
+      tn = __sinf(x[4]) * __builtin_amdgcn_rcpf(__cosf(x[4]));
     } else {
       sincosf(x[2], &sn, &cs);
       tn = tanf(x[4]);

@@ -58,7 +58,7 @@ struct Layout {
   int nchunk;
   size_t state, x0, u, eps, S, crashes, weights;
   size_t chunk_min, chunk_sum, chunk_sum2, chunk_num;
-  size_t ref, knots, coef, circles, costmap, mlp;
+  size_t ref, stage, costmap, mlp;
   size_t total;
 };
 
@@ -156,9 +156,8 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m) {
   L.chunk_num = take(sizeof(float) * (size_t)L.nchunk * TM);
   L.ref = take(sizeof(float) * (size_t)(p->ref ? p->ref_len : 1));
   const int S = uses_spline(c->cost) ? p->num_segments : 0;
-  L.knots = take(sizeof(float) * (S + 1));
-  L.coef = take(sizeof(float4) * (S > 0 ? S : 1));
-  L.circles = take(uses_circles(c->cost) ? kMaxGridBytes : sizeof(float4));
+  L.stage = take((uses_circles(c->cost) ? kMaxGridBytes : sizeof(float4)) +
+                 sizeof(float4) * (S + (S + 1 + 3) / 4));
   const size_t cells =
       c->cost == MPPI_COST_PATH_COSTMAP ? (size_t)p->map_w * (size_t)p->map_h : 1;
   L.costmap = take(sizeof(float) * cells);
@@ -300,19 +299,30 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
   // host staging of the parameter arrays in their device formats
   std::vector<float> ref(p->ref ? p->ref_len : 1, 0.0f);
   if (p->ref) memcpy(ref.data(), p->ref, sizeof(float) * p->ref_len);
+  // the staged cost block: circle grid, then spline coefficient rows, then knots
   const int S = uses_spline(cfg->cost) ? p->num_segments : 0;
-  std::vector<float> knots(S + 1, 0.0f);
-  std::vector<float4> coef(S > 0 ? S : 1, float4{0, 0, 0, 0});
-  if (S > 0) {
-    memcpy(knots.data(), p->knots, sizeof(float) * (S + 1));
-    for (int s = 0; s < S; ++s)
-      coef[s] = float4{p->coef[4 * s], p->coef[4 * s + 1], p->coef[4 * s + 2], p->coef[4 * s + 3]};
-  }
   const int N = uses_circles(cfg->cost) ? p->num_circles : 0;
   Grid grid;
   if (!build_grid(p->cx, p->cy, p->r2, N, &grid)) {
     delete c;
     return fail(MPPI_EUNSUPPORTED, "circle grid does not fit %d bytes of LDS", kMaxGridBytes);
+  }
+  std::vector<float4> stage(grid.words);
+  const int spline_coef4 = static_cast<int>(stage.size());
+  for (int s = 0; s < S; ++s)
+    stage.push_back(float4{p->coef[4 * s], p->coef[4 * s + 1], p->coef[4 * s + 2], p->coef[4 * s + 3]});
+  const int spline_knot4 = static_cast<int>(stage.size());
+  if (S > 0) {
+    std::vector<float> kn(((S + 1 + 3) / 4) * 4, 0.0f);
+    memcpy(kn.data(), p->knots, sizeof(float) * (S + 1));
+    for (size_t q = 0; q < kn.size(); q += 4)
+      stage.push_back(float4{kn[q], kn[q + 1], kn[q + 2], kn[q + 3]});
+  }
+  if (rollout_lds_bytes(cfg->dynamics, cfg->cost, static_cast<int>(stage.size()), c->T) >
+      kMaxRolloutLds) {
+    delete c;
+    return fail(MPPI_EUNSUPPORTED, "cost data plus T*m controls exceed %zu bytes of LDS",
+                kMaxRolloutLds);
   }
 
   auto fail_free = [&](mppi_status s) { delete c; return s; };
@@ -326,9 +336,7 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
   std::vector<float> zeros_u(c->TM, 0.0f);
   if (e == hipSuccess) e = up(L.u, zeros_u.data(), sizeof(float) * c->TM);
   if (e == hipSuccess) e = up(L.ref, ref.data(), sizeof(float) * ref.size());
-  if (e == hipSuccess) e = up(L.knots, knots.data(), sizeof(float) * knots.size());
-  if (e == hipSuccess) e = up(L.coef, coef.data(), sizeof(float4) * coef.size());
-  if (e == hipSuccess) e = up(L.circles, grid.words.data(), sizeof(float4) * grid.words.size());
+  if (e == hipSuccess) e = up(L.stage, stage.data(), sizeof(float4) * stage.size());
   if (e == hipSuccess && cfg->cost == MPPI_COST_PATH_COSTMAP)
     e = up(L.costmap, p->costmap, sizeof(float) * (size_t)p->map_w * p->map_h);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -349,14 +357,14 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
   memcpy(d.w, p->w, sizeof d.w);
   d.ref = c->at<float>(L.ref);
   d.nseg = S;
-  d.knots = c->at<float>(L.knots);
-  d.coef = c->at<float4>(L.coef);
   d.ncirc = N;
-  d.grid = c->at<float4>(L.circles);
+  d.stage = c->at<float4>(L.stage);
+  d.stage_words4 = static_cast<int>(stage.size());
+  d.spline_coef4 = spline_coef4;
+  d.spline_knot4 = spline_knot4;
   d.grid_nx = grid.nx;
   d.grid_ny = grid.ny;
   d.grid_off4 = grid.off4;
-  d.grid_words4 = static_cast<int>(grid.words.size());
   d.grid_x0 = grid.x0;
   d.grid_y0 = grid.y0;
   d.grid_inv_cell = grid.inv_cell;

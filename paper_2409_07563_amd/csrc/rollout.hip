@@ -3,10 +3,10 @@
 // lanes are consecutive samples of one [T*m][ldk] row), forms v = u_t + eps,
 // advances the dynamics and adds the running cost with compensated (Kahan)
 // summation; the terminal cost closes the sum.  u_t, the spline and every
-// cost weight are wave-uniform and arrive through scalar loads; the obstacle
-// grid (circle costs) is staged once per workgroup into LDS.  The noise of
-// step t+1 is requested before step t is computed so that its memory latency
-// overlaps the arithmetic.
+// cost weight are wave-uniform; u (all T steps), the obstacle grid and the
+// spline are staged once per workgroup into LDS, so no step waits on a scalar
+// or global load of them.  The noise of step t+1 is requested before step t
+// is computed so that its memory latency overlaps the arithmetic.
 #include "common.h"
 #include "costs.h"
 #include "dynamics.h"
@@ -22,10 +22,13 @@ __global__ __launch_bounds__(kRolloutBlock) void rollout_kernel(
     int32_t* __restrict__ crashes) {
   constexpr int N = Model::N, M = Model::M;
   extern __shared__ float4 lds[];
-  if constexpr (Cost::kGrid) {
-    for (int i = threadIdx.x; i < p.grid_words4; i += blockDim.x) lds[i] = p.grid[i];
-    __syncthreads();
-  }
+  constexpr bool kStage = Cost::kStage;
+  const int u_off4 = kStage ? p.stage_words4 : 0;
+  float* lds_u = reinterpret_cast<float*>(lds + u_off4);
+  if constexpr (kStage)
+    for (int i = threadIdx.x; i < p.stage_words4; i += blockDim.x) lds[i] = p.stage[i];
+  for (int i = threadIdx.x; i < T * M; i += blockDim.x) lds_u[i] = u[i];
+  __syncthreads();
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;  // no barrier follows
   float x[N], comp[N > 0 ? N : 1];
@@ -35,12 +38,14 @@ __global__ __launch_bounds__(kRolloutBlock) void rollout_kernel(
   float nxt[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) nxt[j] = e[j * ldk];
+  typename Cost::State cs;
+  Cost::init(cs, x, p, lds);
   float sum = 0.0f, sum_c = 0.0f;
   int ncrash = 0;
   for (int t = 0; t < T; ++t) {
     float v[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = u[t * M + j] + nxt[j];
+    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + nxt[j];
     if (t + 1 < T) {
       const float* en = e + static_cast<int64_t>(t + 1) * M * ldk;
 #pragma unroll
@@ -48,14 +53,14 @@ __global__ __launch_bounds__(kRolloutBlock) void rollout_kernel(
     }
     step<Model, INTEG>(x, v, comp, p);
     bool hit;
-    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, hit);
+    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
     if constexpr (COUNT) ncrash += hit ? 1 : 0;
     const float y = l - sum_c;
     const float s = sum + y;
     sum_c = (s - sum) - y;
     sum = s;
   }
-  sum = sum + (terminal_cost<Cost, N>(x, T, p) - sum_c);
+  sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
   S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
   if constexpr (COUNT) crashes[k] = ncrash;
 }
@@ -110,11 +115,19 @@ RolloutFn select(uint32_t dynamics, uint32_t integ, uint32_t cost, bool accurate
   return nullptr;
 }
 
-bool uses_grid(uint32_t cost) {
-  return cost == MPPI_COST_PATH_CIRCLES || cost == MPPI_COST_GOAL_CIRCLES;
+bool uses_stage(uint32_t cost) {
+  return cost == MPPI_COST_PATH_CIRCLES || cost == MPPI_COST_PATH_COSTMAP ||
+         cost == MPPI_COST_GOAL_CIRCLES;
 }
 
+int Model_m(uint32_t dynamics) { return dynamics == MPPI_DYN_QUADROTOR ? 4 : 2; }
+
 }  // namespace
+
+size_t rollout_lds_bytes(uint32_t dynamics, uint32_t cost, int stage_words4, int T) {
+  return (uses_stage(cost) ? sizeof(float4) * static_cast<size_t>(stage_words4) : 0) +
+         sizeof(float) * static_cast<size_t>(T) * Model_m(dynamics);
+}
 
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost) {
   return select(dynamics, integrator, cost, false, false) != nullptr;
@@ -126,7 +139,14 @@ hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                           float* d_S, int32_t* d_crashes, hipStream_t stream) {
   RolloutFn fn = select(dynamics, integrator, cost, accurate_trig, d_crashes != nullptr);
   if (!fn) return hipErrorInvalidValue;
-  const size_t lds = uses_grid(cost) ? sizeof(float4) * static_cast<size_t>(p.grid_words4) : 0;
+  const size_t lds = (uses_stage(cost) ? sizeof(float4) * static_cast<size_t>(p.stage_words4) : 0) +
+                     sizeof(float) * static_cast<size_t>(T) * Model_m(dynamics);
+  if (lds > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(fn, dim3((K + kRolloutBlock - 1) / kRolloutBlock), dim3(kRolloutBlock), lds,
                      stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S, d_crashes);
   return hipGetLastError();
