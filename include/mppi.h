@@ -110,9 +110,13 @@ typedef enum mppi_cost {
 
 enum {
   MPPI_F_DEBUG = 1u,         /* keep per-sample crash counts (MPPI_DEBUG_CRASHES) */
-  MPPI_F_ACCURATE_TRIG = 2u  /* bicycle: library sin/cos/tan instead of the hardware
+  MPPI_F_ACCURATE_TRIG = 2u, /* bicycle: library sin/cos/tan instead of the hardware
                                 transcendental units (the paper's own choice of
                                 intrinsics for trigonometry, Sec. III-B) */
+  MPPI_F_ROLLOUT_LANE = 4u,  /* force one lane per sample in the rollout */
+  MPPI_F_ROLLOUT_QUAD = 8u   /* force four lanes per sample (bicycle + RK4 only);
+                                by default the library picks four lanes per sample
+                                for the bicycle with RK4 when K <= 32768 */
 };
 
 typedef struct mppi_config {

@@ -26,6 +26,8 @@ COSTS = {"quadratic": 0, "path_circles": 1, "path_costmap": 2, "hover": 3, "trac
          "goal_circles": 5}
 F_DEBUG = 1
 F_ACCURATE_TRIG = 2
+F_ROLLOUT_LANE = 4
+F_ROLLOUT_QUAD = 8
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
 
 _fp = C.POINTER(C.c_float)

@@ -28,7 +28,8 @@ class Controller:
     """
 
     def __init__(self, problem, device: str | torch.device = "cuda", debug: bool = False,
-                 accurate_trig: bool = False, stream: torch.cuda.Stream | None = None):
+                 accurate_trig: bool = False, rollout: str = "auto",
+                 stream: torch.cuda.Stream | None = None):
         self.device = torch.device(device)
         self.problem = problem
         n, m = int(np.asarray(problem.x0).size), int(np.asarray(problem.sigma).size)
@@ -46,7 +47,8 @@ class Controller:
             cfg.sigma[j] = float(problem.sigma[j])
         cfg.seed = int(problem.seed)
         cfg.instance = int(getattr(problem, "instance", 0))
-        cfg.flags = (_abi.F_DEBUG if debug else 0) | (_abi.F_ACCURATE_TRIG if accurate_trig else 0)
+        cfg.flags = ((_abi.F_DEBUG if debug else 0) | (_abi.F_ACCURATE_TRIG if accurate_trig else 0)
+                     | {"auto": 0, "lane": _abi.F_ROLLOUT_LANE, "quad": _abi.F_ROLLOUT_QUAD}[rollout])
         self.cfg = cfg
         self.params, self._keep = self._params(problem)
         L = lib()

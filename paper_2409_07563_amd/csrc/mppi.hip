@@ -252,6 +252,7 @@ struct mppi_ctx {
   char* ws;
   hipStream_t stream;
   DevParams dp;
+  bool quad = false;  // four lanes per sample in the rollout
   bool have_state = false;
   bool have_noise = false;
   bool have_costs = false;
@@ -342,6 +343,12 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail_free(hip_fail(e, "parameter upload"));
 
+  // rollout variant: four lanes per sample while one lane per sample would
+  // leave most SIMDs idle
+  c->quad = rollout_quad_available(cfg->dynamics, cfg->integrator) &&
+            !(cfg->flags & MPPI_F_ROLLOUT_LANE) &&
+            ((cfg->flags & MPPI_F_ROLLOUT_QUAD) || c->K <= 32768);
+
   DevParams& d = c->dp;
   memset(&d, 0, sizeof d);
   d.dt = cfg->dt;
@@ -421,7 +428,7 @@ mppi_status mppi_rollout(mppi_ctx* c) {
                          ? c->at<int32_t>(c->L.crashes)
                          : nullptr;
   hipError_t e = launch_rollout(c->cfg.dynamics, c->cfg.integrator, c->cfg.cost,
-                                (c->cfg.flags & MPPI_F_ACCURATE_TRIG) != 0, c->dp,
+                                (c->cfg.flags & MPPI_F_ACCURATE_TRIG) != 0, c->quad, c->dp,
                                 c->at<float>(c->L.x0), c->at<float>(c->L.u),
                                 c->at<float>(c->L.eps), c->L.ldk, c->K, c->T,
                                 c->at<float>(c->L.S), crashes, c->stream);

@@ -65,6 +65,141 @@ __global__ __launch_bounds__(kRolloutBlock) void rollout_kernel(
   if constexpr (COUNT) crashes[k] = ncrash;
 }
 
+
+// ---------------------------------------------------------------------------
+// Bicycle + RK4 with four lanes per sample (a DPP quad), the MI355X form of the
+// paper's intra-sample thread axis (Sec. III-C).  Lane j of a quad evaluates
+// RK4 stage j: for the kinematic bicycle the stage yaw rates
+// k_psi = s_j tan(steer_j) / L depend only on speed and steer, which are linear
+// in time over a step, so all four tan / sin / cos evaluations run at once and
+// one in-quad shift delivers k_psi of the previous stage for
+// yaw_j = yaw + c_j dt k_psi(j-1).  Three quad sums assemble the RK4 increment;
+// every lane ends with bitwise the same state (binary32 addition commutes).
+// The running cost is evaluated every fourth step by all four lanes at once,
+// each on the step it latched (t = j mod 4), so the cost code is amortised
+// four ways; each lane keeps a compensated partial sum, summed per quad at the
+// end.
+// ---------------------------------------------------------------------------
+// quad_perm selectors: [1,0,3,2], [2,3,0,1] and the shift [0,0,1,2]
+constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E, kQuadShift = 0x90;
+template <int CTRL>
+__device__ __forceinline__ float quad_dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_sum(float v) {
+  const float a = v + quad_dpp<kQuadSwap1>(v);
+  return a + quad_dpp<kQuadSwap2>(a);
+}
+
+template <class Cost, bool FAST, bool COUNT>
+__global__ __launch_bounds__(kRolloutBlock) void rollout_bicycle_quad_kernel(
+    DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
+    const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
+    int32_t* __restrict__ crashes) {
+  using Model = Bicycle<FAST>;
+  constexpr int N = 5, M = 2;
+  extern __shared__ float4 lds[];
+  const int u_off4 = Cost::kStage ? p.stage_words4 : 0;
+  float* lds_u = reinterpret_cast<float*>(lds + u_off4);
+  if constexpr (Cost::kStage)
+    for (int i = threadIdx.x; i < p.stage_words4; i += blockDim.x) lds[i] = p.stage[i];
+  for (int i = threadIdx.x; i < T * M; i += blockDim.x) lds_u[i] = u[i];
+  __syncthreads();
+  const int j = threadIdx.x & 3;
+  const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  if (k >= K) return;  // whole quads leave together; no barrier follows
+  // stage coefficient c_j dt (0, dt/2, dt/2, dt) and RK4 weight (1, 2, 2, 1)
+  const float cdt = j == 0 ? 0.0f : (j == 3 ? p.dt : p.half_dt);
+  const float wj = (j == 1 || j == 2) ? 2.0f : 1.0f;
+  float x[N], comp[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
+  const float* e = eps + k;
+  float nxt[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) nxt[q] = e[q * ldk];
+  // the step this lane evaluates the running cost of
+  float lx[N], lc[N], lv[M];
+  int lt = -1;
+  typename Cost::State cs;
+  Cost::init(cs, x, p, lds);
+  float sum = 0.0f, sum_c = 0.0f;
+  int ncrash = 0;
+  for (int t = 0; t < T; ++t) {
+    float v[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) v[q] = lds_u[t * M + q] + nxt[q];
+    if (t + 1 < T) {
+      const float* en = e + static_cast<int64_t>(t + 1) * M * ldk;
+#pragma unroll
+      for (int q = 0; q < M; ++q) nxt[q] = en[q * ldk];
+    }
+    // stage j of RK4
+    const float sj = x[3] + cdt * v[0];
+    const float dj = x[4] + cdt * v[1];
+    float tn;
+    if constexpr (FAST) {
+      tn = __sinf(dj) * __builtin_amdgcn_rcpf(__cosf(dj));
+    } else {
+      tn = tanf(dj);
+    }
+    const float kpsi = sj * tn * p.inv_wheelbase;
+    const float kprev = quad_dpp<kQuadShift>(kpsi);
+    const float yj = j == 0 ? x[2] : x[2] + cdt * kprev;
+    float sn, co;
+    if constexpr (FAST) {
+      sn = __sinf(yj);
+      co = __cosf(yj);
+    } else {
+      sincosf(yj, &sn, &co);
+    }
+    const float gx = quad_sum(wj * (sj * co));
+    const float gy = quad_sum(wj * (sj * sn));
+    const float gp = quad_sum(wj * kpsi);
+    const float x0s[N] = {x[0], x[1], x[2], x[3], x[4]};
+    const float inc[N] = {p.sixth_dt * gx, p.sixth_dt * gy, p.sixth_dt * gp,
+                          p.sixth_dt * (((v[0] + 2.0f * v[0]) + 2.0f * v[0]) + v[0]),
+                          p.sixth_dt * (((v[1] + 2.0f * v[1]) + 2.0f * v[1]) + v[1])};
+    advance<Model>(x, x0s, inc, comp);
+    // latch this step for lane t mod 4, evaluate a full group every 4 steps
+    if ((t & 3) == j) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) { lx[i] = x[i]; lc[i] = comp[i]; }
+#pragma unroll
+      for (int q = 0; q < M; ++q) lv[q] = v[q];
+      lt = t;
+    }
+    if ((t & 3) == 3 || t + 1 == T) {
+      if (lt >= 0) {
+        bool hit;
+        const float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
+        if constexpr (COUNT) ncrash += hit ? 1 : 0;
+        const float y = l - sum_c;
+        const float s = sum + y;
+        sum_c = (s - sum) - y;
+        sum = s;
+        lt = -1;
+      }
+    }
+  }
+  // terminal cost once per sample (lane 0), then the quad's partial sums
+  const float phi = terminal_cost<Cost, N>(x, T, p, lds, cs);
+  if (j == 0) {
+    const float y = phi - sum_c;
+    const float s = sum + y;
+    sum_c = (s - sum) - y;
+    sum = s;
+  }
+  const float total = quad_sum(sum - sum_c);
+  if (j == 0) S[k] = __builtin_isfinite(total) ? total : __builtin_inff();
+  if constexpr (COUNT) {
+    int c = ncrash;
+    c += __builtin_amdgcn_update_dpp(0, c, kQuadSwap1, 0xF, 0xF, false);
+    c += __builtin_amdgcn_update_dpp(0, c, kQuadSwap2, 0xF, 0xF, false);
+    if (j == 0) crashes[k] = c;
+  }
+}
+
 namespace {
 
 using RolloutFn = void (*)(DevParams, const float*, const float*, const float*, int64_t, int,
@@ -109,6 +244,24 @@ RolloutFn pick_model(uint32_t dynamics, uint32_t cost, bool accurate, bool count
   }
 }
 
+template <class Cost, bool FAST>
+RolloutFn pick_quad(bool count) {
+  if (count) return rollout_bicycle_quad_kernel<Cost, FAST, true>;
+  return rollout_bicycle_quad_kernel<Cost, FAST, false>;
+}
+
+template <bool FAST>
+RolloutFn pick_quad_cost(uint32_t cost, bool count) {
+  switch (cost) {
+    case MPPI_COST_PATH_CIRCLES: return pick_quad<CostPath<true>, FAST>(count);
+    case MPPI_COST_PATH_COSTMAP: return pick_quad<CostPath<false>, FAST>(count);
+    case MPPI_COST_GOAL_CIRCLES: return pick_quad<CostGoalCircles, FAST>(count);
+    case MPPI_COST_QUADRATIC: return pick_quad<CostQuadratic, FAST>(count);
+    case MPPI_COST_TRACK: return pick_quad<CostTrack, FAST>(count);
+    default: return nullptr;
+  }
+}
+
 RolloutFn select(uint32_t dynamics, uint32_t integ, uint32_t cost, bool accurate, bool count) {
   if (integ == MPPI_INT_EULER) return pick_model<kEuler>(dynamics, cost, accurate, count);
   if (integ == MPPI_INT_RK4) return pick_model<kRK4>(dynamics, cost, accurate, count);
@@ -133,12 +286,21 @@ bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost) {
   return select(dynamics, integrator, cost, false, false) != nullptr;
 }
 
+bool rollout_quad_available(uint32_t dynamics, uint32_t integrator) {
+  return dynamics == MPPI_DYN_BICYCLE && integrator == MPPI_INT_RK4;
+}
+
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
-                          bool accurate_trig, const DevParams& p, const float* d_x0,
+                          bool accurate_trig, bool quad, const DevParams& p, const float* d_x0,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           float* d_S, int32_t* d_crashes, hipStream_t stream) {
-  RolloutFn fn = select(dynamics, integrator, cost, accurate_trig, d_crashes != nullptr);
+  const bool count = d_crashes != nullptr;
+  const bool use_quad = quad && rollout_quad_available(dynamics, integrator);
+  RolloutFn fn = use_quad ? (accurate_trig ? pick_quad_cost<false>(cost, count)
+                                           : pick_quad_cost<true>(cost, count))
+                          : select(dynamics, integrator, cost, accurate_trig, count);
   if (!fn) return hipErrorInvalidValue;
+  const int lanes_per_sample = use_quad ? 4 : 1;
   const size_t lds = (uses_stage(cost) ? sizeof(float4) * static_cast<size_t>(p.stage_words4) : 0) +
                      sizeof(float) * static_cast<size_t>(T) * Model_m(dynamics);
   if (lds > 48 * 1024) {
@@ -147,8 +309,10 @@ hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, dim3((K + kRolloutBlock - 1) / kRolloutBlock), dim3(kRolloutBlock), lds,
-                     stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S, d_crashes);
+  const int64_t lanes = static_cast<int64_t>(K) * lanes_per_sample;
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((lanes + kRolloutBlock - 1) / kRolloutBlock)),
+                     dim3(kRolloutBlock), lds, stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S,
+                     d_crashes);
   return hipGetLastError();
 }
 

@@ -83,9 +83,9 @@ def _cases():
 CASES = _cases()
 
 
-def _run_one_iteration(mppi, wl, debug=True, accurate_trig=False):
+def _run_one_iteration(mppi, wl, debug=True, accurate_trig=False, rollout="auto"):
     ctl = mppi.Controller(wl, debug=debug and wl.cost in ("path_circles", "goal_circles"),
-                          accurate_trig=accurate_trig)
+                          accurate_trig=accurate_trig, rollout=rollout)
     ctl.sample()
     ctl.rollout()
     S = _np(ctl.costs())
@@ -116,6 +116,38 @@ def test_rollout_costs_parity(mppi, oracle_lib, name, accurate):
         sure = margin >= parity.AMBIGUOUS_MARGIN
         assert np.array_equal(g["crashes"][sure], crashes[sure])
         assert crashes.sum() > 0 or name.startswith("c4")
+
+
+BICYCLE_CASES = [n for n, w in CASES.items() if w.model == "bicycle"]
+
+
+@pytest.mark.parametrize("rollout", ["lane", "quad"])
+@pytest.mark.parametrize("name", BICYCLE_CASES)
+def test_rollout_variants_parity(mppi, oracle_lib, name, rollout):
+    """Both rollout kernels of the bicycle (one lane per sample, and four
+    lanes per sample) against the oracle, costs and crash counts."""
+    wl = CASES[name]
+    g = _run_one_iteration(mppi, wl, rollout=rollout)
+    eps_or = oracle_lib.workload_noise(wl)
+    S_or, margin, crashes, slope = oracle_lib.rollout_costs(wl, eps=eps_or, slope=True)
+    parity.assert_costs_close(g["S"], S_or, margin, f"{name}/{rollout}",
+                              slope=slope if wl.cost == "path_costmap" else None)
+    if g["crashes"] is not None:
+        sure = margin >= parity.AMBIGUOUS_MARGIN
+        assert np.array_equal(g["crashes"][sure], crashes[sure])
+    o = oracle_lib.mppi(wl, iters=1)
+    parity.assert_controls_close(g["U"], o["U"], parity.controls_tol(wl, o["S"], o["w"], o["eps"]),
+                                 f"{name}/{rollout}")
+
+
+@pytest.mark.parametrize("K,T", [(1, 1), (3, 5), (17, 6), (64, 7), (65, 4)])
+def test_quad_rollout_ragged_shapes(mppi, oracle_lib, K, T):
+    """Four lanes per sample: partial quads of the last wave, horizons that
+    are not a multiple of the four-step cost groups."""
+    wl = W.c2("circles", K=K, T=T, iters=1)
+    g = _run_one_iteration(mppi, wl, rollout="quad")
+    S_or, margin, crashes = oracle_lib.rollout_costs(wl, eps=oracle_lib.workload_noise(wl))
+    parity.assert_costs_close(g["S"], S_or, margin, f"quad K{K} T{T}")
 
 
 @pytest.mark.parametrize("name", ["c1", "c2_circles", "c3", "c1_ragged"])
