@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=None,
                     help="oracle iterations for the CPU baseline (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="first run 3 device-to-device copies of this many MiB (a known "
+                         "traffic reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -131,6 +134,14 @@ def main():
     I = wl.iters
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy_mb:
+        n = args.calibrate_copy_mb << 18  # float32 elements
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctl = M.Controller(wl, device=dev)
     stream = ctl.stream
 
