@@ -55,6 +55,10 @@ def rollout_ops_per_step(wl) -> int:
             cost += 14 + 5
         else:
             cost += 20  # bilinear: index math, 4 gathers, 8 lerp ops
+    elif wl.cost == "goal_circles":
+        # goal distance (2 sub, mul, fma, scale), controls (2 mul, 2 fma),
+        # grid crash query as for the path cost (14 + 5), crash add
+        cost = 5 + 4 + 19 + 1
     elif wl.cost == "quadratic":
         cost = 3 * wl.n + 2 * wl.m
     elif wl.cost == "hover":
@@ -74,6 +78,8 @@ def make_workload(name: str):
         return W.c1()
     if name == "c3":
         return W.c3()
+    if name == "c4":
+        return W.c4()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -95,6 +101,29 @@ def traffic_record(kernel: str, workload: str):
     if rec.get("source_hash") != source_hash(*rec.get("sources", [])):
         return None
     return rec.get("bytes_per_launch")
+
+
+def phase_times(ctl, reps: int):
+    """Average durations (s) of the sampling, rollout and update launches:
+    HIP events recorded on the library's stream around direct C-ABI calls."""
+    import torch
+    import paper_2409_07563_amd as M
+    L, ctx, stream = M.lib(), ctl.ctx, ctl.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    acc = [0.0, 0.0, 0.0]
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        ev[0].record(stream)
+        M._abi.check(L.mppi_sample(ctx))
+        ev[1].record(stream)
+        M._abi.check(L.mppi_rollout(ctx))
+        ev[2].record(stream)
+        M._abi.check(L.mppi_update(ctx))
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        for i in range(3):
+            acc[i] += ev[i].elapsed_time(ev[i + 1])
+    return tuple(a / reps * 1e-3 for a in acc)
 
 
 def cpu_baseline(wl, iters: int):
@@ -131,6 +160,8 @@ def main():
     import paper_2409_07563_amd as M
 
     wl = make_workload(args.workload)
+    if isinstance(wl, list):
+        return bench_batch(args, wl)
     I = wl.iters
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -161,23 +192,7 @@ def main():
     steps_per_iter = wl.K * wl.T
     value = I * steps_per_iter / (ms_per_step * 1e-3)
 
-    # per-kernel durations, HIP events on the library's stream
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    t_noise = t_roll = t_upd = 0.0
-    for _ in range(args.kernel_reps):
-        ev[0].record(stream)
-        ctl.sample()
-        ev[1].record(stream)
-        ctl.rollout()
-        ev[2].record(stream)
-        ctl.update()
-        ev[3].record(stream)
-        torch.cuda.synchronize()
-        t_noise += ev[0].elapsed_time(ev[1])
-        t_roll += ev[1].elapsed_time(ev[2])
-        t_upd += ev[2].elapsed_time(ev[3])
-    n = args.kernel_reps
-    t_noise, t_roll, t_upd = (x / n * 1e-3 for x in (t_noise, t_roll, t_upd))
+    t_noise, t_roll, t_upd = phase_times(ctl, args.kernel_reps)
 
     ops = rollout_ops_per_step(wl) * steps_per_iter
     achieved = ops / t_roll
@@ -190,7 +205,7 @@ def main():
     kernels = {
         "noise": {"us": t_noise * 1e6, "hbm_GBps": eps_bytes / t_noise / 1e9},
         "rollout": {"us": t_roll * 1e6},
-        "softmin_update": {"us": t_upd * 1e6, "hbm_GBps": (eps_bytes + 4 * wl.K) / t_upd / 1e9},
+        "softmin_update": {"us": t_upd * 1e6, "hbm_GBps": (eps_bytes + 8 * wl.K) / t_upd / 1e9},
     }
 
     out = {
@@ -209,6 +224,69 @@ def main():
     ctl.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters or I)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, insts):
+    """Many independent instances: one batched context (one launch per phase,
+    the per-iteration sequence replayed from a hipGraph) against the same
+    instances run one context after another on one stream."""
+    import torch
+    import paper_2409_07563_amd as M
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    total = sum(w.K * w.T for w in insts)
+    ctl = M.Controller(insts, device=dev)
+    stream = ctl.stream
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ms = timed(lambda: ctl.iterate(1), args.steps, args.warmup)
+    tn, tr, tu = phase_times(ctl, max(1, args.kernel_reps // 5))
+    ctl.close()
+
+    # the same instances as single contexts, one after another on one stream
+    singles = [M.Controller(w, device=dev, stream=stream) for w in insts]
+    def loop():
+        for c in singles:
+            c.iterate(1)
+    ms_loop = timed(loop, max(1, args.steps // 4), 1)
+    for c in singles:
+        c.close()
+
+    ops = sum(rollout_ops_per_step(w) * w.K * w.T for w in insts)
+    achieved = ops / tr
+    eps_bytes = sum(4 * w.T * w.m * w.K for w in insts)
+    out = {
+        "metric": "rollout-steps/sec (K*T) per MPPI iter + fwd+bwd/fwd time ratio, 1 MI355X",
+        "value": total / (ms * 1e-3), "unit": "rollout-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4_batched_bicycle", "instances": len(insts),
+                   "sum_K_T": total, "K_range": [min(w.K for w in insts), max(w.K for w in insts)],
+                   "T_range": [min(w.T for w in insts), max(w.T for w in insts)],
+                   "iterations_per_step": 1, "cost": insts[0].cost},
+        "looped_single_contexts": {"ms_per_step": ms_loop, "value": total / (ms_loop * 1e-3),
+                                   "speedup_of_batch": ms_loop / ms},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": traffic_record("rollout", args.workload),
+                     "kernel": "batch_rollout_kernel", "launch_us": tr * 1e6},
+        "kernels": {"noise": {"us": tn * 1e6, "hbm_GBps": eps_bytes / tn / 1e9},
+                    "rollout": {"us": tr * 1e6},
+                    "softmin_update": {"us": tu * 1e6, "hbm_GBps": eps_bytes / tu / 1e9}},
+    }
     print(json.dumps(out), flush=True)
 
 

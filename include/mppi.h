@@ -177,11 +177,38 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* params,
                         void* d_workspace, size_t workspace_bytes, void* hip_stream,
                         mppi_ctx** out);
 
-/* x0 <- d_x0[0..n) (enqueued device copy). */
+/* ---- batches (spec extension: many independent instances) ----------
+ * A batch context holds n independent MPPI instances that share dynamics,
+ * integrator, cost kind and flags but each have their own K, T, dt, lambda,
+ * sigma, seed / instance word and parameter arrays (their own obstacles,
+ * goal, weights).  Every phase of an iteration runs all instances in one
+ * launch over a work list (instance, block of samples) ordered by horizon,
+ * longest first.  All calls below accept batch contexts; wherever a call
+ * takes or returns a per-instance array, a batch context uses the
+ * concatenation of the instances' arrays in instance order ("packed"), at
+ * the offsets mppi_offsets reports.  A context from mppi_create is a batch of
+ * one. */
+size_t mppi_batch_workspace_bytes(const mppi_config* cfgs, const mppi_params* params, int32_t n);
+mppi_status mppi_create_batch(const mppi_config* cfgs, const mppi_params* params, int32_t n,
+                              void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                              mppi_ctx** out);
+int32_t mppi_num_instances(const mppi_ctx* ctx);
+enum {
+  MPPI_PACKED_STATE = 0,    /* state_dim floats per instance */
+  MPPI_PACKED_CONTROLS = 1, /* T*m floats per instance */
+  MPPI_PACKED_SAMPLES = 2,  /* K values per instance (costs, weights, crash counts) */
+  MPPI_PACKED_NOISE = 3     /* T*m*K floats per instance */
+};
+/* host_offsets[0..n]: element offsets of each instance in a packed array of
+ * the given kind (host_offsets[n] = total length). */
+mppi_status mppi_offsets(const mppi_ctx* ctx, int32_t what, int64_t* host_offsets);
+
+/* x0 <- d_x0[0..n) (enqueued device copy; packed for a batch). */
 mppi_status mppi_set_state(mppi_ctx* ctx, const float* d_x0);
-/* u <- d_u[T][m] (enqueued device copy; warm start or restore). */
+/* u <- d_u[T][m] (enqueued device copy; warm start or restore; packed). */
 mppi_status mppi_set_controls(mppi_ctx* ctx, const float* d_u);
-/* Philox iteration word of the next sampling step (enqueued). */
+/* Philox iteration word of the next sampling step (enqueued; every instance
+ * of a batch). */
 mppi_status mppi_set_iteration(mppi_ctx* ctx, uint32_t iteration);
 
 /* Staged iteration (Algorithm 1 split at its natural boundaries):
@@ -195,7 +222,10 @@ mppi_status mppi_rollout(mppi_ctx* ctx);
 mppi_status mppi_set_costs(mppi_ctx* ctx, const float* d_costs);
 mppi_status mppi_update(mppi_ctx* ctx);
 
-/* (a7) num_iters >= 1 full iterations, warm-started (u <- U between them). */
+/* (a7) num_iters >= 1 full iterations, warm-started (u <- U between them).
+ * The launch sequence for a given num_iters is captured into a hipGraph on
+ * first use and replayed afterwards (the context's stream must not be under
+ * capture by the caller at that first call). */
 mppi_status mppi_iterate(mppi_ctx* ctx, int32_t num_iters);
 
 /* d_U[T][m] <- current nominal controls (enqueued device copy). */
@@ -205,10 +235,10 @@ enum {
   MPPI_DEBUG_NOISE = 0,   /* float eps[T][m][K] of the last sampling */
   MPPI_DEBUG_COSTS = 1,   /* float J[K] of the last rollout (or set_costs) */
   MPPI_DEBUG_WEIGHTS = 2, /* float w[K] of the last update */
-  MPPI_DEBUG_STATS = 3,   /* float[8]: rho, eta, free energy rho - lambda
-                             ln(eta/K), 1/sum w^2, then the int32 status word
-                             (MPPI_OK / MPPI_ENUMERIC) and the int32 iteration
-                             word, then two zero words */
+  MPPI_DEBUG_STATS = 3,   /* float[8] per instance: rho, eta, free energy
+                             rho - lambda ln(eta/K), 1/sum w^2, then the int32
+                             status word (MPPI_OK / MPPI_ENUMERIC) and the int32
+                             iteration word, then two zero words */
   MPPI_DEBUG_CRASHES = 4  /* int32 crashed-step count per sample [K]
                              (needs MPPI_F_DEBUG and a circles cost) */
 };

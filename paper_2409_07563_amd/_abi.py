@@ -29,6 +29,7 @@ F_ACCURATE_TRIG = 2
 F_ROLLOUT_LANE = 4
 F_ROLLOUT_QUAD = 8
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
+PACKED_STATE, PACKED_CONTROLS, PACKED_SAMPLES, PACKED_NOISE = 0, 1, 2, 3
 
 _fp = C.POINTER(C.c_float)
 
@@ -72,6 +73,11 @@ EXPORTS = {
     "mppi_noise": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
                              C.c_int32, _fp, C.c_void_p, C.c_int64, C.c_void_p]),
     "mppi_noise_tables": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mppi_batch_workspace_bytes": (C.c_size_t, [C.POINTER(Config), C.POINTER(Params), C.c_int32]),
+    "mppi_create_batch": (C.c_int, [C.POINTER(Config), C.POINTER(Params), C.c_int32, C.c_void_p,
+                                    C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mppi_num_instances": (C.c_int32, [C.c_void_p]),
+    "mppi_offsets": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
 }
 
 _lib = None

@@ -49,15 +49,7 @@ struct DevParams {
 // Largest circle grid the rollout kernel stages into LDS.
 constexpr int kMaxGridBytes = 64 * 1024;
 
-// Per-chunk softmin partials written by the partial-reduction kernel and
-// merged by the merge kernel (see softmin.hip).
-struct SoftminLayout {
-  float* chunk_min;   // [nchunk]
-  float* chunk_sum;   // [nchunk]  sum_k exp(-(J_k - min_c)/lambda)
-  float* chunk_sum2;  // [nchunk]  sum_k exp(-(J_k - min_c)/lambda)^2
-  float* chunk_num;   // [nchunk][TM]  sum_k exp(...) eps[r][k]
-  int nchunk;
-};
+struct Sigma8 { float v[MPPI_MAX_CONTROL]; };
 
 // Device-side scalars of a context.
 struct DevState {
@@ -65,6 +57,37 @@ struct DevState {
   int32_t status;     // MPPI_OK or MPPI_ENUMERIC
   uint32_t iteration; // Philox iteration word of the next sampling
   int32_t pad[2];
+};
+
+// One instance of a batch, as the batched kernels read it (device memory).
+struct BatchInst {
+  DevParams p;
+  const float* x0;
+  float* u;
+  float* eps;
+  float* S;
+  int32_t* crashes;  // null unless crash counting
+  int64_t ldk;
+  int K, T, TM;
+  float lambda, inv_lambda;
+  uint32_t key0, key1, instance;
+  Sigma8 sigma;
+  float* e;  // unnormalised weights exp(-(J_k - rho)/lambda) [ldk]
+  DevState* st;
+};
+
+// Work lists of the batched kernels (host-built, device-resident):
+//   sample tiles (instance, block of kBatchTile samples), longest horizon first;
+//   row tiles (instance, block of gemv_rows_per_block() rows of the update).
+constexpr int kBatchTile = 256;
+struct BatchPlan {
+  const BatchInst* insts;
+  const int2* sample_tiles;
+  int n_sample_tiles;
+  const int2* row_tiles;
+  int n_row_tiles;
+  int n_inst;
+  size_t rollout_lds;
 };
 
 // ---- host launchers (one translation unit each) ---------------------------
@@ -86,13 +109,20 @@ bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
 size_t rollout_lds_bytes(uint32_t dynamics, uint32_t cost, int stage_words4, int T);
 constexpr size_t kMaxRolloutLds = 160 * 1024;
 
-int softmin_chunks(int K);
+int gemv_rows_per_block();
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
-                                 int TM, float lambda, const SoftminLayout& L, float* d_u,
+                                 int TM, float lambda, float* d_e, float* d_u,
                                  DevState* d_state, hipStream_t stream);
 hipError_t launch_set_iteration(DevState* d_state, uint32_t iteration, hipStream_t stream);
 hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState* d_state,
                           float* d_w, hipStream_t stream);
+
+hipError_t launch_batch_noise(const BatchPlan& b, hipStream_t stream);
+hipError_t launch_batch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                                bool accurate_trig, bool count, const BatchPlan& b,
+                                hipStream_t stream);
+hipError_t launch_batch_update(const BatchPlan& b, hipStream_t stream);
+hipError_t launch_batch_set_iteration(const BatchPlan& b, uint32_t iteration, hipStream_t stream);
 
 // ---- wave / block reductions ------------------------------------------------
 __device__ inline float wave_min(float v) {

@@ -1,12 +1,15 @@
 // Host side of the C ABI declared in include/mppi.h: argument validation,
-// workspace carving, parameter upload and the launch sequence of one MPPI
-// iteration (arXiv 2409.07563, Algorithm 1).  No device allocation happens
-// here; all device memory is the caller's workspace.
+// workspace carving, parameter upload, the circle grid, batch work lists and
+// the launch sequence of MPPI iterations (arXiv 2409.07563, Algorithm 1),
+// captured once per iteration count in a hipGraph.  No device allocation
+// happens here; all device memory is the caller's workspace.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -52,12 +55,10 @@ int model_dims(uint32_t dyn, int* n, int* m) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Workspace layout (byte offsets from the workspace base), all 256-aligned.
+// Per-instance workspace slice (byte offsets from the slice base, 256-aligned).
 struct Layout {
   int64_t ldk;  // noise row stride (K rounded up to a wave)
-  int nchunk;
-  size_t state, x0, u, eps, S, crashes, weights;
-  size_t chunk_min, chunk_sum, chunk_sum2, chunk_num;
+  size_t eps, e;
   size_t ref, stage, costmap, mlp;
   size_t total;
 };
@@ -137,23 +138,14 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
 }
 
 Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m) {
+  (void)n;
   Layout L{};
   const int K = c->num_samples, T = c->horizon, TM = T * m;
   L.ldk = (K + kWave - 1) / kWave * kWave;
-  L.nchunk = softmin_chunks(K);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-  L.state = take(sizeof(DevState));
-  L.x0 = take(sizeof(float) * MPPI_MAX_STATE);
-  L.u = take(sizeof(float) * TM);
   L.eps = take(sizeof(float) * (size_t)TM * L.ldk);
-  L.S = take(sizeof(float) * L.ldk);
-  L.crashes = take(sizeof(int32_t) * L.ldk);
-  L.weights = take(sizeof(float) * L.ldk);
-  L.chunk_min = take(sizeof(float) * L.nchunk);
-  L.chunk_sum = take(sizeof(float) * L.nchunk);
-  L.chunk_sum2 = take(sizeof(float) * L.nchunk);
-  L.chunk_num = take(sizeof(float) * (size_t)L.nchunk * TM);
+  L.e = take(sizeof(float) * L.ldk);
   L.ref = take(sizeof(float) * (size_t)(p->ref ? p->ref_len : 1));
   const int S = uses_spline(c->cost) ? p->num_segments : 0;
   L.stage = take((uses_circles(c->cost) ? kMaxGridBytes : sizeof(float4)) +
@@ -165,7 +157,6 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m) {
   L.total = off;
   return L;
 }
-
 
 // Uniform grid over the circles for the rollout's crash test.  Each circle is
 // listed in every cell that its bounding box, inflated by delta = 1e-3 cells,
@@ -243,72 +234,120 @@ bool build_grid(const float* cx, const float* cy, const float* r2, int N, Grid* 
   return false;
 }
 
-}  // namespace
 
-struct mppi_ctx {
+// One MPPI problem instance inside a context: its configuration, its slice
+// of the workspace and the device-side constants its kernels take.
+struct Instance {
   mppi_config cfg;
   int n, m, K, T, TM;
   Layout L;
-  char* ws;
-  hipStream_t stream;
+  char* base;  // the instance's workspace slice
   DevParams dp;
-  bool quad = false;  // four lanes per sample in the rollout
+  bool quad;   // four lanes per sample in the single-instance rollout
+  // views into the context's packed regions
+  DevState* st;
+  float* x0;
+  float* u;
+  float* S;
+  int32_t* crashes;
+  int64_t off_x0, off_u, off_S;
+
+  template <class X>
+  X* at(size_t off) const { return reinterpret_cast<X*>(base + off); }
+  float* eps() const { return at<float>(L.eps); }
+  float* e() const { return at<float>(L.e); }
+};
+
+// Context-level layout: packed per-instance regions first (so the packed host
+// views of set_state / set_controls / get_controls / costs are single copies),
+// then the batch tables, then the instance slices.
+struct CtxLayout {
+  size_t states, x0, u, S, crashes, insts, sample_tiles, row_tiles;
+  std::vector<size_t> slice;
+  size_t total;
+  int n_sample_tiles, n_row_tiles;
+};
+
+CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, int n_inst,
+                          bool batch) {
+  CtxLayout C{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  int64_t nx = 0, nu = 0, nS = 0;
+  C.n_sample_tiles = C.n_row_tiles = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    int n, m;
+    model_dims(cfgs[i].dynamics, &n, &m);
+    nx += n;
+    nu += (int64_t)cfgs[i].horizon * m;
+    nS += cfgs[i].num_samples;
+    const int TM = cfgs[i].horizon * m;
+    C.n_sample_tiles += (cfgs[i].num_samples + kBatchTile - 1) / kBatchTile;
+    C.n_row_tiles += (TM + gemv_rows_per_block() - 1) / gemv_rows_per_block();
+  }
+  C.states = take(sizeof(DevState) * n_inst);
+  C.x0 = take(sizeof(float) * (nx + MPPI_MAX_STATE));
+  C.u = take(sizeof(float) * nu);
+  C.S = take(sizeof(float) * (nS + kWave));
+  C.crashes = take(sizeof(int32_t) * (nS + kWave));
+  if (batch) {
+    C.insts = take(sizeof(BatchInst) * n_inst);
+    C.sample_tiles = take(sizeof(int2) * C.n_sample_tiles);
+    C.row_tiles = take(sizeof(int2) * C.n_row_tiles);
+  }
+  C.slice.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    int n, m;
+    model_dims(cfgs[i].dynamics, &n, &m);
+    C.slice[i] = take(make_layout(&cfgs[i], &params[i], n, m).total);
+  }
+  C.total = off;
+  return C;
+}
+
+}  // namespace
+
+struct mppi_ctx {
+  std::vector<Instance> inst;
+  bool batch = false;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  CtxLayout C;
+  BatchPlan plan{};
+  int64_t n_x0 = 0, n_u = 0, n_S = 0;
   bool have_state = false;
   bool have_noise = false;
   bool have_costs = false;
+  std::map<int, hipGraphExec_t> graphs;  // mppi_iterate(I) launch sequences
 
-  template <class X>
-  X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
-  DevState* state() const { return at<DevState>(L.state); }
-  SoftminLayout softmin() const {
-    return SoftminLayout{at<float>(L.chunk_min), at<float>(L.chunk_sum), at<float>(L.chunk_sum2),
-                         at<float>(L.chunk_num), L.nchunk};
+  ~mppi_ctx() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
   }
+  const Instance& one() const { return inst[0]; }
 };
 
-extern "C" {
+namespace {
 
-const char* mppi_last_error(void) { return g_last_error.c_str(); }
-
-size_t mppi_workspace_bytes(const mppi_config* cfg, const mppi_params* params) {
-  int n, m;
-  if (validate(cfg, params, &n, &m) != MPPI_OK) return 0;
-  return make_layout(cfg, params, n, m).total;
-}
-
-mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_workspace,
-                        size_t workspace_bytes, void* hip_stream, mppi_ctx** out) {
-  if (!out) return fail(MPPI_EINVAL, "out must not be NULL");
-  *out = nullptr;
+// Uploads one instance's parameter arrays into its slice and fills its
+// device constants.  Enqueued on `stream`; the caller synchronises.
+mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* slice,
+                           hipStream_t stream, Instance* I, std::vector<std::vector<float4>>* keep) {
   int n, m;
   mppi_status st = validate(cfg, p, &n, &m);
   if (st != MPPI_OK) return st;
-  const Layout L = make_layout(cfg, p, n, m);
-  if (!d_workspace) return fail(MPPI_EINVAL, "workspace must not be NULL");
-  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
-    return fail(MPPI_EINVAL, "workspace must be %zu-byte aligned", kAlign);
-  if (workspace_bytes < L.total)
-    return fail(MPPI_ENOMEM, "workspace of %zu bytes, need %zu", workspace_bytes, L.total);
+  I->cfg = *cfg;
+  I->n = n; I->m = m; I->K = cfg->num_samples; I->T = cfg->horizon; I->TM = I->T * m;
+  I->L = make_layout(cfg, p, n, m);
+  I->base = slice;
 
-  mppi_ctx* c = new mppi_ctx();
-  c->cfg = *cfg;
-  c->n = n; c->m = m; c->K = cfg->num_samples; c->T = cfg->horizon; c->TM = c->T * m;
-  c->L = L;
-  c->ws = static_cast<char*>(d_workspace);
-  c->stream = static_cast<hipStream_t>(hip_stream);
-
-  // host staging of the parameter arrays in their device formats
-  std::vector<float> ref(p->ref ? p->ref_len : 1, 0.0f);
-  if (p->ref) memcpy(ref.data(), p->ref, sizeof(float) * p->ref_len);
   // the staged cost block: circle grid, then spline coefficient rows, then knots
   const int S = uses_spline(cfg->cost) ? p->num_segments : 0;
   const int N = uses_circles(cfg->cost) ? p->num_circles : 0;
   Grid grid;
-  if (!build_grid(p->cx, p->cy, p->r2, N, &grid)) {
-    delete c;
+  if (!build_grid(p->cx, p->cy, p->r2, N, &grid))
     return fail(MPPI_EUNSUPPORTED, "circle grid does not fit %d bytes of LDS", kMaxGridBytes);
-  }
-  std::vector<float4> stage(grid.words);
+  keep->emplace_back(grid.words);
+  std::vector<float4>& stage = keep->back();
   const int spline_coef4 = static_cast<int>(stage.size());
   for (int s = 0; s < S; ++s)
     stage.push_back(float4{p->coef[4 * s], p->coef[4 * s + 1], p->coef[4 * s + 2], p->coef[4 * s + 3]});
@@ -319,37 +358,32 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
     for (size_t q = 0; q < kn.size(); q += 4)
       stage.push_back(float4{kn[q], kn[q + 1], kn[q + 2], kn[q + 3]});
   }
-  if (rollout_lds_bytes(cfg->dynamics, cfg->cost, static_cast<int>(stage.size()), c->T) >
-      kMaxRolloutLds) {
-    delete c;
+  if (rollout_lds_bytes(cfg->dynamics, cfg->cost, static_cast<int>(stage.size()), I->T) >
+      kMaxRolloutLds)
     return fail(MPPI_EUNSUPPORTED, "cost data plus T*m controls exceed %zu bytes of LDS",
                 kMaxRolloutLds);
-  }
+  keep->emplace_back();
+  std::vector<float4>& ref4 = keep->back();
+  const int ref_len = p->ref ? p->ref_len : 1;
+  ref4.resize((ref_len + 3) / 4, float4{0, 0, 0, 0});
+  if (p->ref) memcpy(ref4.data(), p->ref, sizeof(float) * p->ref_len);
 
-  auto fail_free = [&](mppi_status s) { delete c; return s; };
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
-    return hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+    return hipMemcpyAsync(slice + off, src, bytes, hipMemcpyHostToDevice, stream);
   };
-  hipError_t e = hipSuccess;
-  DevState st0{};
-  st0.status = MPPI_OK;
-  if (e == hipSuccess) e = up(L.state, &st0, sizeof st0);
-  std::vector<float> zeros_u(c->TM, 0.0f);
-  if (e == hipSuccess) e = up(L.u, zeros_u.data(), sizeof(float) * c->TM);
-  if (e == hipSuccess) e = up(L.ref, ref.data(), sizeof(float) * ref.size());
-  if (e == hipSuccess) e = up(L.stage, stage.data(), sizeof(float4) * stage.size());
+  hipError_t e = up(I->L.ref, ref4.data(), sizeof(float) * ref_len);
+  if (e == hipSuccess) e = up(I->L.stage, stage.data(), sizeof(float4) * stage.size());
   if (e == hipSuccess && cfg->cost == MPPI_COST_PATH_COSTMAP)
-    e = up(L.costmap, p->costmap, sizeof(float) * (size_t)p->map_w * p->map_h);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return fail_free(hip_fail(e, "parameter upload"));
+    e = up(I->L.costmap, p->costmap, sizeof(float) * (size_t)p->map_w * p->map_h);
+  if (e != hipSuccess) return hip_fail(e, "parameter upload");
 
   // rollout variant: four lanes per sample while one lane per sample would
   // leave most SIMDs idle
-  c->quad = rollout_quad_available(cfg->dynamics, cfg->integrator) &&
+  I->quad = rollout_quad_available(cfg->dynamics, cfg->integrator) &&
             !(cfg->flags & MPPI_F_ROLLOUT_LANE) &&
-            ((cfg->flags & MPPI_F_ROLLOUT_QUAD) || c->K <= 32768);
+            ((cfg->flags & MPPI_F_ROLLOUT_QUAD) || I->K <= 32768);
 
-  DevParams& d = c->dp;
+  DevParams& d = I->dp;
   memset(&d, 0, sizeof d);
   d.dt = cfg->dt;
   d.half_dt = 0.5f * cfg->dt;
@@ -362,10 +396,10 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
     d.inv_inertia[i] = p->inertia[i] > 0.0f ? static_cast<float>(1.0 / p->inertia[i]) : 0.0f;
   }
   memcpy(d.w, p->w, sizeof d.w);
-  d.ref = c->at<float>(L.ref);
+  d.ref = I->at<float>(I->L.ref);
   d.nseg = S;
   d.ncirc = N;
-  d.stage = c->at<float4>(L.stage);
+  d.stage = I->at<float4>(I->L.stage);
   d.stage_words4 = static_cast<int>(stage.size());
   d.spline_coef4 = spline_coef4;
   d.spline_knot4 = spline_knot4;
@@ -382,40 +416,235 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_wo
     d.map_y0 = p->map_y0;
     d.map_res = p->map_res;
     d.map_inv_res = static_cast<float>(1.0 / static_cast<double>(p->map_res));
-    d.costmap = c->at<float>(L.costmap);
+    d.costmap = I->at<float>(I->L.costmap);
   }
+  return MPPI_OK;
+}
+
+mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n_inst, bool batch,
+                       void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                       mppi_ctx** out) {
+  if (!out) return fail(MPPI_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (!cfgs || !params || n_inst < 1 || n_inst > 65536)
+    return fail(MPPI_EINVAL, "need 1..65536 configurations and parameter sets");
+  for (int i = 0; i < n_inst; ++i) {
+    int n, m;
+    mppi_status s = validate(&cfgs[i], &params[i], &n, &m);
+    if (s != MPPI_OK) return s;
+    if (batch && (cfgs[i].dynamics != cfgs[0].dynamics || cfgs[i].integrator != cfgs[0].integrator ||
+                  cfgs[i].cost != cfgs[0].cost || cfgs[i].flags != cfgs[0].flags))
+      return fail(MPPI_EINVAL, "batch instance %d differs from instance 0 in dynamics, "
+                  "integrator, cost or flags", i);
+  }
+  const CtxLayout C = make_ctx_layout(cfgs, params, n_inst, batch);
+  if (!d_workspace) return fail(MPPI_EINVAL, "workspace must not be NULL");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+    return fail(MPPI_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  if (workspace_bytes < C.total)
+    return fail(MPPI_ENOMEM, "workspace of %zu bytes, need %zu", workspace_bytes, C.total);
+
+  mppi_ctx* c = new mppi_ctx();
+  c->batch = batch;
+  c->ws = static_cast<char*>(d_workspace);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->C = C;
+  c->inst.resize(n_inst);
+  std::vector<std::vector<float4>> keep;
+  keep.reserve(2 * n_inst);
+  std::vector<DevState> states(n_inst);
+  int64_t ox = 0, ou = 0, oS = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    Instance& I = c->inst[i];
+    mppi_status s = setup_instance(&cfgs[i], &params[i], c->ws + C.slice[i], c->stream, &I, &keep);
+    if (s != MPPI_OK) { (void)hipStreamSynchronize(c->stream); delete c; return s; }
+    I.st = reinterpret_cast<DevState*>(c->ws + C.states) + i;
+    I.x0 = reinterpret_cast<float*>(c->ws + C.x0) + ox;
+    I.u = reinterpret_cast<float*>(c->ws + C.u) + ou;
+    I.S = reinterpret_cast<float*>(c->ws + C.S) + oS;
+    I.crashes = reinterpret_cast<int32_t*>(c->ws + C.crashes) + oS;
+    I.off_x0 = ox; I.off_u = ou; I.off_S = oS;
+    ox += I.n; ou += I.TM; oS += I.K;
+    states[i] = DevState{};
+    states[i].status = MPPI_OK;
+  }
+  c->n_x0 = ox; c->n_u = ou; c->n_S = oS;
+  hipError_t e = hipMemcpyAsync(c->ws + C.states, states.data(), sizeof(DevState) * n_inst,
+                                hipMemcpyHostToDevice, c->stream);
+  std::vector<float> zeros(ou, 0.0f);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + C.u, zeros.data(), sizeof(float) * ou, hipMemcpyHostToDevice, c->stream);
+
+  // batch tables
+  std::vector<BatchInst> bi;
+  std::vector<int2> st_tiles, row_tiles;
+  if (batch && e == hipSuccess) {
+    size_t lds = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      const Instance& I = c->inst[i];
+      BatchInst b{};
+      b.p = I.dp;
+      b.x0 = I.x0; b.u = I.u; b.eps = I.eps(); b.S = I.S;
+      b.crashes = (cfgs[i].flags & MPPI_F_DEBUG) && uses_circles(cfgs[i].cost) ? I.crashes : nullptr;
+      b.ldk = I.L.ldk; b.K = I.K; b.T = I.T; b.TM = I.TM;
+      b.lambda = cfgs[i].lambda;
+      b.inv_lambda = static_cast<float>(1.0 / static_cast<double>(cfgs[i].lambda));
+      b.key0 = static_cast<uint32_t>(cfgs[i].seed);
+      b.key1 = static_cast<uint32_t>(cfgs[i].seed >> 32);
+      b.instance = cfgs[i].instance;
+      for (int j = 0; j < I.m; ++j) b.sigma.v[j] = cfgs[i].sigma[j];
+      b.e = I.e();
+      b.st = I.st;
+      bi.push_back(b);
+      lds = std::max(lds, rollout_lds_bytes(cfgs[i].dynamics, cfgs[i].cost, I.dp.stage_words4, I.T));
+    }
+    // sample tiles, longest horizon first (stable: instance order within a horizon)
+    std::vector<int> order(n_inst);
+    for (int i = 0; i < n_inst; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b2) { return c->inst[a].T > c->inst[b2].T; });
+    for (int i : order)
+      for (int t = 0; t * kBatchTile < c->inst[i].K; ++t) st_tiles.push_back(int2{i, t});
+    const int rpb = gemv_rows_per_block();
+    for (int i = 0; i < n_inst; ++i)
+      for (int rb = 0; rb * rpb < c->inst[i].TM; ++rb) row_tiles.push_back(int2{i, rb});
+    e = hipMemcpyAsync(c->ws + C.insts, bi.data(), sizeof(BatchInst) * n_inst,
+                       hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->ws + C.sample_tiles, st_tiles.data(), sizeof(int2) * st_tiles.size(),
+                         hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->ws + C.row_tiles, row_tiles.data(), sizeof(int2) * row_tiles.size(),
+                         hipMemcpyHostToDevice, c->stream);
+    BatchPlan& P = c->plan;
+    P.insts = reinterpret_cast<const BatchInst*>(c->ws + C.insts);
+    P.sample_tiles = reinterpret_cast<const int2*>(c->ws + C.sample_tiles);
+    P.n_sample_tiles = static_cast<int>(st_tiles.size());
+    P.row_tiles = reinterpret_cast<const int2*>(c->ws + C.row_tiles);
+    P.n_row_tiles = static_cast<int>(row_tiles.size());
+    P.n_inst = n_inst;
+    P.rollout_lds = lds;
+  }
+  const hipError_t e2 = hipStreamSynchronize(c->stream);  // host staging buffers die here
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) { delete c; return hip_fail(e, "context upload"); }
   *out = c;
   g_last_error.clear();
   return MPPI_OK;
 }
 
+// ---- the phases of one iteration on a context -------------------------------
+hipError_t phase_sample(mppi_ctx* c) {
+  if (c->batch) return launch_batch_noise(c->plan, c->stream);
+  const Instance& I = c->one();
+  return launch_noise(I.cfg.seed, &I.st->iteration, 0u, I.cfg.instance, I.K, I.T, I.m,
+                      I.cfg.sigma, I.eps(), I.L.ldk, c->stream);
+}
+
+hipError_t phase_rollout(mppi_ctx* c) {
+  const Instance& I = c->one();
+  const bool count = (I.cfg.flags & MPPI_F_DEBUG) && uses_circles(I.cfg.cost);
+  const bool accurate = (I.cfg.flags & MPPI_F_ACCURATE_TRIG) != 0;
+  if (c->batch)
+    return launch_batch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, count,
+                                c->plan, c->stream);
+  return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.quad, I.dp, I.x0,
+                        I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
+                        c->stream);
+}
+
+hipError_t phase_update(mppi_ctx* c) {
+  if (c->batch) return launch_batch_update(c->plan, c->stream);
+  const Instance& I = c->one();
+  return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, I.e(), I.u, I.st,
+                               c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mppi_last_error(void) { return g_last_error.c_str(); }
+
+size_t mppi_workspace_bytes(const mppi_config* cfg, const mppi_params* params) {
+  int n, m;
+  if (validate(cfg, params, &n, &m) != MPPI_OK) return 0;
+  return make_ctx_layout(cfg, params, 1, false).total;
+}
+
+size_t mppi_batch_workspace_bytes(const mppi_config* cfgs, const mppi_params* params, int32_t n) {
+  if (!cfgs || !params || n < 1 || n > 65536) {
+    fail(MPPI_EINVAL, "need 1..65536 configurations and parameter sets");
+    return 0;
+  }
+  for (int i = 0; i < n; ++i) {
+    int ns, ms;
+    if (validate(&cfgs[i], &params[i], &ns, &ms) != MPPI_OK) return 0;
+  }
+  return make_ctx_layout(cfgs, params, n, true).total;
+}
+
+mppi_status mppi_create(const mppi_config* cfg, const mppi_params* p, void* d_workspace,
+                        size_t workspace_bytes, void* hip_stream, mppi_ctx** out) {
+  return create_ctx(cfg, p, 1, false, d_workspace, workspace_bytes, hip_stream, out);
+}
+
+mppi_status mppi_create_batch(const mppi_config* cfgs, const mppi_params* params, int32_t n,
+                              void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                              mppi_ctx** out) {
+  return create_ctx(cfgs, params, n, true, d_workspace, workspace_bytes, hip_stream, out);
+}
+
 void mppi_destroy(mppi_ctx* ctx) { delete ctx; }
+
+int32_t mppi_num_instances(const mppi_ctx* c) { return c ? static_cast<int32_t>(c->inst.size()) : 0; }
+
+mppi_status mppi_offsets(const mppi_ctx* c, int32_t what, int64_t* host_offsets) {
+  if (!c || !host_offsets) return fail(MPPI_EINVAL, "ctx and host_offsets must not be NULL");
+  int64_t acc = 0;
+  for (size_t i = 0; i < c->inst.size(); ++i) {
+    const Instance& I = c->inst[i];
+    host_offsets[i] = acc;
+    switch (what) {
+      case MPPI_PACKED_STATE: acc += I.n; break;
+      case MPPI_PACKED_CONTROLS: acc += I.TM; break;
+      case MPPI_PACKED_SAMPLES: acc += I.K; break;
+      case MPPI_PACKED_NOISE: acc += static_cast<int64_t>(I.TM) * I.K; break;
+      default: return fail(MPPI_EINVAL, "unknown packed array %d", what);
+    }
+  }
+  host_offsets[c->inst.size()] = acc;
+  return MPPI_OK;
+}
 
 mppi_status mppi_set_state(mppi_ctx* c, const float* d_x0) {
   if (!c || !d_x0) return fail(MPPI_EINVAL, "ctx and d_x0 must not be NULL");
-  HIP_TRY(hipMemcpyAsync(c->at<float>(c->L.x0), d_x0, sizeof(float) * c->n,
-                         hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->C.x0, d_x0, sizeof(float) * c->n_x0, hipMemcpyDeviceToDevice,
+                         c->stream));
   c->have_state = true;
   return MPPI_OK;
 }
 
 mppi_status mppi_set_controls(mppi_ctx* c, const float* d_u) {
   if (!c || !d_u) return fail(MPPI_EINVAL, "ctx and d_u must not be NULL");
-  HIP_TRY(hipMemcpyAsync(c->at<float>(c->L.u), d_u, sizeof(float) * c->TM,
-                         hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->C.u, d_u, sizeof(float) * c->n_u, hipMemcpyDeviceToDevice,
+                         c->stream));
   return MPPI_OK;
 }
 
 mppi_status mppi_set_iteration(mppi_ctx* c, uint32_t iteration) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
-  HIP_TRY(launch_set_iteration(c->state(), iteration, c->stream));
+  if (c->batch) {
+    HIP_TRY(launch_batch_set_iteration(c->plan, iteration, c->stream));
+  } else {
+    HIP_TRY(launch_set_iteration(c->one().st, iteration, c->stream));
+  }
   return MPPI_OK;
 }
 
 mppi_status mppi_sample(mppi_ctx* c) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
-  HIP_TRY(launch_noise(c->cfg.seed, &c->state()->iteration, 0u, c->cfg.instance, c->K, c->T, c->m,
-                       c->cfg.sigma, c->at<float>(c->L.eps), c->L.ldk, c->stream));
+  HIP_TRY(phase_sample(c));
   c->have_noise = true;
   return MPPI_OK;
 }
@@ -424,14 +653,7 @@ mppi_status mppi_rollout(mppi_ctx* c) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
   if (!c->have_state) return fail(MPPI_ESTATE, "mppi_set_state must come before a rollout");
   if (!c->have_noise) return fail(MPPI_ESTATE, "mppi_sample must come before a rollout");
-  int32_t* crashes = (c->cfg.flags & MPPI_F_DEBUG) && uses_circles(c->cfg.cost)
-                         ? c->at<int32_t>(c->L.crashes)
-                         : nullptr;
-  hipError_t e = launch_rollout(c->cfg.dynamics, c->cfg.integrator, c->cfg.cost,
-                                (c->cfg.flags & MPPI_F_ACCURATE_TRIG) != 0, c->quad, c->dp,
-                                c->at<float>(c->L.x0), c->at<float>(c->L.u),
-                                c->at<float>(c->L.eps), c->L.ldk, c->K, c->T,
-                                c->at<float>(c->L.S), crashes, c->stream);
+  hipError_t e = phase_rollout(c);
   if (e != hipSuccess) return hip_fail(e, "rollout launch");
   c->have_costs = true;
   return MPPI_OK;
@@ -439,8 +661,8 @@ mppi_status mppi_rollout(mppi_ctx* c) {
 
 mppi_status mppi_set_costs(mppi_ctx* c, const float* d_costs) {
   if (!c || !d_costs) return fail(MPPI_EINVAL, "ctx and d_costs must not be NULL");
-  HIP_TRY(hipMemcpyAsync(c->at<float>(c->L.S), d_costs, sizeof(float) * c->K,
-                         hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->C.S, d_costs, sizeof(float) * c->n_S, hipMemcpyDeviceToDevice,
+                         c->stream));
   c->have_costs = true;
   return MPPI_OK;
 }
@@ -449,9 +671,7 @@ mppi_status mppi_update(mppi_ctx* c) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
   if (!c->have_noise || !c->have_costs)
     return fail(MPPI_ESTATE, "mppi_update needs noise and costs of the current iteration");
-  hipError_t e = launch_softmin_update(c->at<float>(c->L.S), c->at<float>(c->L.eps), c->L.ldk, c->K,
-                                       c->TM, c->cfg.lambda, c->softmin(), c->at<float>(c->L.u),
-                                       c->state(), c->stream);
+  hipError_t e = phase_update(c);
   if (e != hipSuccess) return hip_fail(e, "update launch");
   return MPPI_OK;
 }
@@ -460,48 +680,82 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
   if (num_iters < 1) return fail(MPPI_EINVAL, "num_iters must be >= 1");
   if (!c->have_state) return fail(MPPI_ESTATE, "mppi_set_state must come before mppi_iterate");
-  for (int i = 0; i < num_iters; ++i) {
-    mppi_status s;
-    if ((s = mppi_sample(c)) != MPPI_OK) return s;
-    if ((s = mppi_rollout(c)) != MPPI_OK) return s;
-    if ((s = mppi_update(c)) != MPPI_OK) return s;
+  // the launch sequence of num_iters iterations, captured once and replayed
+  // (the null stream cannot be captured: launch directly there)
+  if (c->stream == nullptr) {
+    for (int i = 0; i < num_iters; ++i) {
+      hipError_t e = phase_sample(c);
+      if (e == hipSuccess) e = phase_rollout(c);
+      if (e == hipSuccess) e = phase_update(c);
+      if (e != hipSuccess) return hip_fail(e, "iteration launch");
+    }
+    c->have_noise = c->have_costs = true;
+    return MPPI_OK;
   }
+  auto it = c->graphs.find(num_iters);
+  if (it == c->graphs.end()) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < num_iters && e == hipSuccess; ++i) {
+      e = phase_sample(c);
+      if (e == hipSuccess) e = phase_rollout(c);
+      if (e == hipSuccess) e = phase_update(c);
+    }
+    const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(e != hipSuccess ? e : ec, "iteration capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiation");
+    it = c->graphs.emplace(num_iters, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, c->stream));
+  c->have_noise = c->have_costs = true;
   return MPPI_OK;
 }
 
 mppi_status mppi_get_controls(mppi_ctx* c, float* d_U) {
   if (!c || !d_U) return fail(MPPI_EINVAL, "ctx and d_U must not be NULL");
-  HIP_TRY(hipMemcpyAsync(d_U, c->at<float>(c->L.u), sizeof(float) * c->TM,
-                         hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(d_U, c->ws + c->C.u, sizeof(float) * c->n_u, hipMemcpyDeviceToDevice,
+                         c->stream));
   return MPPI_OK;
 }
 
 mppi_status mppi_get_debug(mppi_ctx* c, int32_t what, void* d_dst) {
   if (!c || !d_dst) return fail(MPPI_EINVAL, "ctx and d_dst must not be NULL");
   switch (what) {
-    case MPPI_DEBUG_NOISE:
-      HIP_TRY(hipMemcpy2DAsync(d_dst, sizeof(float) * c->K, c->at<float>(c->L.eps),
-                               sizeof(float) * c->L.ldk, sizeof(float) * c->K, c->TM,
-                               hipMemcpyDeviceToDevice, c->stream));
-      return MPPI_OK;
-    case MPPI_DEBUG_COSTS:
-      HIP_TRY(hipMemcpyAsync(d_dst, c->at<float>(c->L.S), sizeof(float) * c->K,
-                             hipMemcpyDeviceToDevice, c->stream));
-      return MPPI_OK;
-    case MPPI_DEBUG_WEIGHTS: {
-      hipError_t e = launch_weights(c->at<float>(c->L.S), c->K, c->cfg.lambda, c->state(),
-                                    static_cast<float*>(d_dst), c->stream);
-      if (e != hipSuccess) return hip_fail(e, "weights launch");
+    case MPPI_DEBUG_NOISE: {
+      char* dst = static_cast<char*>(d_dst);
+      for (const Instance& I : c->inst) {
+        HIP_TRY(hipMemcpy2DAsync(dst, sizeof(float) * I.K, I.eps(), sizeof(float) * I.L.ldk,
+                                 sizeof(float) * I.K, I.TM, hipMemcpyDeviceToDevice, c->stream));
+        dst += sizeof(float) * static_cast<size_t>(I.TM) * I.K;
+      }
       return MPPI_OK;
     }
+    case MPPI_DEBUG_COSTS:
+      HIP_TRY(hipMemcpyAsync(d_dst, c->ws + c->C.S, sizeof(float) * c->n_S,
+                             hipMemcpyDeviceToDevice, c->stream));
+      return MPPI_OK;
+    case MPPI_DEBUG_WEIGHTS:
+      for (const Instance& I : c->inst) {
+        hipError_t e = launch_weights(I.S, I.K, I.cfg.lambda, I.st,
+                                      static_cast<float*>(d_dst) + I.off_S, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "weights launch");
+      }
+      return MPPI_OK;
     case MPPI_DEBUG_STATS:
-      HIP_TRY(hipMemcpyAsync(d_dst, c->state(), sizeof(DevState), hipMemcpyDeviceToDevice,
-                             c->stream));
+      HIP_TRY(hipMemcpyAsync(d_dst, c->ws + c->C.states, sizeof(DevState) * c->inst.size(),
+                             hipMemcpyDeviceToDevice, c->stream));
       return MPPI_OK;
     case MPPI_DEBUG_CRASHES:
-      if (!(c->cfg.flags & MPPI_F_DEBUG) || !uses_circles(c->cfg.cost))
+      if (!(c->one().cfg.flags & MPPI_F_DEBUG) || !uses_circles(c->one().cfg.cost))
         return fail(MPPI_ESTATE, "crash counts need MPPI_F_DEBUG and a circles cost");
-      HIP_TRY(hipMemcpyAsync(d_dst, c->at<int32_t>(c->L.crashes), sizeof(int32_t) * c->K,
+      HIP_TRY(hipMemcpyAsync(d_dst, c->ws + c->C.crashes, sizeof(int32_t) * c->n_S,
                              hipMemcpyDeviceToDevice, c->stream));
       return MPPI_OK;
     default:

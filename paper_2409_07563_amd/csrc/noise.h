@@ -105,5 +105,26 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
   z1 = r * s;
 }
 
+// Philox call c of sample k: the four normals n = 4c .. 4c+3 (n = t*m + j),
+// scaled by sigma_j and stored at eps[n * ldk + k] (n < TM).
+__device__ __forceinline__ void emit_call(uint32_t key0, uint32_t key1, uint32_t iteration,
+                                          uint32_t instance, int k, int c, int TM, int m,
+                                          const float* sigma, float* __restrict__ eps,
+                                          int64_t ldk) {
+  const Words w = philox4x32_10(static_cast<uint32_t>(c), static_cast<uint32_t>(k), iteration,
+                                instance, key0, key1);
+  float z[4];
+  box_muller(w.x0, w.x1, z[0], z[1]);
+  box_muller(w.x2, w.x3, z[2], z[3]);
+  const int n0 = 4 * c;
+  int j = n0 % m;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int n = n0 + s;
+    if (n < TM) eps[static_cast<int64_t>(n) * ldk + k] = sigma[j] * z[s];
+    j = (j + 1 == m) ? 0 : j + 1;
+  }
+}
+
 }  // namespace noise
 }  // namespace mppi

@@ -11,8 +11,6 @@
 
 namespace mppi {
 
-struct Sigma8 { float v[MPPI_MAX_CONTROL]; };
-
 __global__ __launch_bounds__(256) void noise_kernel(uint32_t key0, uint32_t key1,
                                                     const uint32_t* __restrict__ d_iteration,
                                                     uint32_t iteration, uint32_t instance,
@@ -22,20 +20,7 @@ __global__ __launch_bounds__(256) void noise_kernel(uint32_t key0, uint32_t key1
   const int c = blockIdx.y;
   if (k >= K) return;
   const uint32_t it = d_iteration ? *d_iteration : iteration;
-  const noise::Words w = noise::philox4x32_10(static_cast<uint32_t>(c), static_cast<uint32_t>(k),
-                                              it, instance, key0, key1);
-  float z[4];
-  noise::box_muller(w.x0, w.x1, z[0], z[1]);
-  noise::box_muller(w.x2, w.x3, z[2], z[3]);
-  const int n0 = 4 * c;
-  // j = n mod m for the four consecutive normals (m <= 8)
-  int j = n0 % m;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int n = n0 + s;
-    if (n < TM) eps[static_cast<int64_t>(n) * ldk + k] = sigma.v[j] * z[s];
-    j = (j + 1 == m) ? 0 : j + 1;
-  }
+  noise::emit_call(key0, key1, it, instance, k, c, TM, m, sigma.v, eps, ldk);
 }
 
 hipError_t launch_noise(uint64_t seed, const uint32_t* d_iteration, uint32_t iteration,

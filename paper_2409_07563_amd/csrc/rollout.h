@@ -1,0 +1,76 @@
+// Device bodies of the fused rollout + cost (step a2), shared by the
+// single-instance kernels (rollout.hip) and the batched kernels (batch.hip).
+//
+// One lane per sample keeps the state in registers for the whole horizon;
+// per step it reads its noise (coalesced: lanes are consecutive samples of one
+// [T*m][ldk] row), forms v = u_t + eps, advances the dynamics and adds the
+// running cost with compensated (Kahan) summation; the terminal cost closes
+// the sum.  u (all T steps) and the read-only cost data (obstacle grid,
+// spline) are staged once per workgroup into LDS by stage_rollout_lds.
+#pragma once
+
+#include "common.h"
+#include "costs.h"
+#include "dynamics.h"
+
+namespace mppi {
+
+// LDS layout: [cost stage (float4 words, if the cost stages any)][u: T*M floats]
+template <class Cost>
+__device__ __forceinline__ float* stage_rollout_lds(const DevParams& p, const float* __restrict__ u,
+                                                    int TM, float4* lds) {
+  const int u_off4 = Cost::kStage ? p.stage_words4 : 0;
+  float* lds_u = reinterpret_cast<float*>(lds + u_off4);
+  if constexpr (Cost::kStage)
+    for (int i = threadIdx.x; i < p.stage_words4; i += blockDim.x) lds[i] = p.stage[i];
+  for (int i = threadIdx.x; i < TM; i += blockDim.x) lds_u[i] = u[i];
+  __syncthreads();
+  return lds_u;
+}
+
+struct RolloutResult {
+  float cost;
+  int crashes;
+};
+
+// One lane per sample: e points at eps[0][0][k] of this lane's sample.
+template <class Model, int INTEG, class Cost, bool COUNT>
+__device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
+                                                      const float* __restrict__ x0,
+                                                      const float* lds_u,
+                                                      const float* __restrict__ e, int64_t ldk,
+                                                      int T, const float4* lds) {
+  constexpr int N = Model::N, M = Model::M;
+  float x[N], comp[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
+  float nxt[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) nxt[j] = e[j * ldk];
+  typename Cost::State cs;
+  Cost::init(cs, x, p, lds);
+  float sum = 0.0f, sum_c = 0.0f;
+  int ncrash = 0;
+  for (int t = 0; t < T; ++t) {
+    float v[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + nxt[j];
+    if (t + 1 < T) {
+      const float* en = e + static_cast<int64_t>(t + 1) * M * ldk;
+#pragma unroll
+      for (int j = 0; j < M; ++j) nxt[j] = en[j * ldk];
+    }
+    step<Model, INTEG>(x, v, comp, p);
+    bool hit;
+    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    if constexpr (COUNT) ncrash += hit ? 1 : 0;
+    const float y = l - sum_c;
+    const float s = sum + y;
+    sum_c = (s - sum) - y;
+    sum = s;
+  }
+  sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
+  return RolloutResult{__builtin_isfinite(sum) ? sum : __builtin_inff(), ncrash};
+}
+
+}  // namespace mppi

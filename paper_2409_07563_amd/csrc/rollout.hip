@@ -1,15 +1,10 @@
-// Step (a2): fused rollout + cost.  One lane per sample keeps the state in
-// registers for the whole horizon; per step it reads its noise (coalesced:
-// lanes are consecutive samples of one [T*m][ldk] row), forms v = u_t + eps,
-// advances the dynamics and adds the running cost with compensated (Kahan)
-// summation; the terminal cost closes the sum.  u_t, the spline and every
-// cost weight are wave-uniform; u (all T steps), the obstacle grid and the
-// spline are staged once per workgroup into LDS, so no step waits on a scalar
-// or global load of them.  The noise of step t+1 is requested before step t
-// is computed so that its memory latency overlaps the arithmetic.
-#include "common.h"
-#include "costs.h"
-#include "dynamics.h"
+// Step (a2) for one instance: the fused rollout + cost kernels (one lane per
+// sample, or four lanes per sample for the bicycle with RK4) and the choice
+// between them.  The per-lane body lives in rollout.h.  u, the obstacle grid
+// and the spline are staged once per workgroup into LDS, so no step waits on
+// a scalar or global load of them; the noise of step t+1 is requested before
+// step t is computed so that its memory latency overlaps the arithmetic.
+#include "rollout.h"
 
 namespace mppi {
 
@@ -20,51 +15,14 @@ __global__ __launch_bounds__(kRolloutBlock) void rollout_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
     int32_t* __restrict__ crashes) {
-  constexpr int N = Model::N, M = Model::M;
   extern __shared__ float4 lds[];
-  constexpr bool kStage = Cost::kStage;
-  const int u_off4 = kStage ? p.stage_words4 : 0;
-  float* lds_u = reinterpret_cast<float*>(lds + u_off4);
-  if constexpr (kStage)
-    for (int i = threadIdx.x; i < p.stage_words4; i += blockDim.x) lds[i] = p.stage[i];
-  for (int i = threadIdx.x; i < T * M; i += blockDim.x) lds_u[i] = u[i];
-  __syncthreads();
+  const float* lds_u = stage_rollout_lds<Cost>(p, u, T * Model::M, lds);
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;  // no barrier follows
-  float x[N], comp[N > 0 ? N : 1];
-#pragma unroll
-  for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
-  const float* e = eps + k;
-  float nxt[M];
-#pragma unroll
-  for (int j = 0; j < M; ++j) nxt[j] = e[j * ldk];
-  typename Cost::State cs;
-  Cost::init(cs, x, p, lds);
-  float sum = 0.0f, sum_c = 0.0f;
-  int ncrash = 0;
-  for (int t = 0; t < T; ++t) {
-    float v[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + nxt[j];
-    if (t + 1 < T) {
-      const float* en = e + static_cast<int64_t>(t + 1) * M * ldk;
-#pragma unroll
-      for (int j = 0; j < M; ++j) nxt[j] = en[j * ldk];
-    }
-    step<Model, INTEG>(x, v, comp, p);
-    bool hit;
-    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
-    if constexpr (COUNT) ncrash += hit ? 1 : 0;
-    const float y = l - sum_c;
-    const float s = sum + y;
-    sum_c = (s - sum) - y;
-    sum = s;
-  }
-  sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
-  S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
-  if constexpr (COUNT) crashes[k] = ncrash;
+  const RolloutResult r = rollout_lane<Model, INTEG, Cost, COUNT>(p, x0, lds_u, eps + k, ldk, T, lds);
+  S[k] = r.cost;
+  if constexpr (COUNT) crashes[k] = r.crashes;
 }
-
 
 // ---------------------------------------------------------------------------
 // Bicycle + RK4 with four lanes per sample (a DPP quad), the MI355X form of the
@@ -99,12 +57,7 @@ __global__ __launch_bounds__(kRolloutBlock) void rollout_bicycle_quad_kernel(
   using Model = Bicycle<FAST>;
   constexpr int N = 5, M = 2;
   extern __shared__ float4 lds[];
-  const int u_off4 = Cost::kStage ? p.stage_words4 : 0;
-  float* lds_u = reinterpret_cast<float*>(lds + u_off4);
-  if constexpr (Cost::kStage)
-    for (int i = threadIdx.x; i < p.stage_words4; i += blockDim.x) lds[i] = p.stage[i];
-  for (int i = threadIdx.x; i < T * M; i += blockDim.x) lds_u[i] = u[i];
-  __syncthreads();
+  const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
   const int j = threadIdx.x & 3;
   const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
   if (k >= K) return;  // whole quads leave together; no barrier follows

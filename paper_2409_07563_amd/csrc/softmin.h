@@ -1,0 +1,129 @@
+// Device bodies of steps (a3)-(a6): baseline, normaliser, weights and control
+// update (arXiv 2409.07563, Algorithm 1 and Eq. mppi_update_rule), shared by
+// the single-instance kernels (softmin.hip) and the batched kernels
+// (batch.hip).  Two phases, both with a fixed reduction order (bitwise
+// reproducible):
+//  * weights: one workgroup per instance finds rho = min_k J_k, writes
+//    e_k = exp(-(J_k - rho)/lambda) (0 for a non-finite J_k), reduces
+//    eta = sum e_k and sum e_k^2, and records the statistics;
+//  * weighted noise: U[r] = u[r] + (sum_k e_k eps[r][k]) / eta, a matrix-vector
+//    product over the [T*m][ldk] noise.  A workgroup of four waves owns a row:
+//    its lanes stream the row with 16-byte loads along k (four in flight per
+//    lane), accumulate privately, reduce once per wave and combine the four
+//    wave sums in a fixed order, so eps is read exactly once at HBM speed.
+#pragma once
+
+#include "common.h"
+
+namespace mppi {
+
+constexpr int kWeightsBlock = 1024;
+constexpr int kGemvBlock = 256;  // one row per workgroup
+
+template <int NW>
+__device__ __forceinline__ float block_min(float v, float* lds) {
+  v = wave_min(v);
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  float r = lds[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) r = fminf(r, lds[i]);
+  return r;
+}
+
+template <int NW>
+__device__ __forceinline__ float block_sum(float v, float* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  float r = lds[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) r += lds[i];
+  return r;
+}
+
+// One workgroup of kWeightsBlock threads per instance.  Also advances the
+// instance's iteration word (read by the next sampling step).
+__device__ __forceinline__ void weights_body(const float* __restrict__ S, int K, float lambda,
+                                             float inv_lambda, float* __restrict__ e,
+                                             DevState* __restrict__ st) {
+  constexpr int NW = kWeightsBlock / kWave;
+  __shared__ float lds[NW];
+  float m = __builtin_inff();
+  for (int k = threadIdx.x; k < K; k += kWeightsBlock) m = fminf(m, S[k]);
+  const float rho = block_min<NW>(m, lds);
+  const bool finite = rho < __builtin_inff();
+  float se = 0.0f, se2 = 0.0f;
+  for (int k = threadIdx.x; k < K; k += kWeightsBlock) {
+    const float s = S[k];
+    // non-finite J_k (NaN was turned into +inf by the rollout) gets weight 0
+    const float ek = (finite && s < __builtin_inff()) ? expf((rho - s) * inv_lambda) : 0.0f;
+    e[k] = ek;
+    se += ek;
+    se2 += ek * ek;
+  }
+  const float eta = block_sum<NW>(se, lds);
+  const float sum_e2 = block_sum<NW>(se2, lds);
+  if (threadIdx.x == 0) {
+    st->stats[0] = rho;
+    st->stats[1] = finite ? eta : 0.0f;
+    st->stats[2] = finite ? rho - lambda * logf(eta / static_cast<float>(K)) : __builtin_inff();
+    st->stats[3] = finite ? (eta * eta) / sum_e2 : 0.0f;
+    st->status = finite ? MPPI_OK : MPPI_ENUMERIC;
+    st->iteration = st->iteration + 1u;
+  }
+}
+
+// Row r of the update, one workgroup of kGemvBlock threads:
+// u[r] += (sum_k e_k eps[r][k]) / eta.  The row starts 16-byte aligned (ldk is
+// a multiple of 64); the last K mod 4 entries go through a scalar tail so the
+// unwritten padding of a row is never read.  When every cost was non-finite
+// (eta = 0) u is left unchanged.
+__device__ __forceinline__ void gemv_row(const float* __restrict__ eps, int64_t ldk, int K,
+                                         const float* __restrict__ e, const DevState* st,
+                                         float* __restrict__ u, int r) {
+  constexpr int NW = kGemvBlock / kWave;
+  __shared__ float part[NW];
+  const int tid = threadIdx.x;
+  const float* row = eps + static_cast<int64_t>(r) * ldk;
+  const int K4 = K & ~3;
+  constexpr int kStride = 4 * kGemvBlock;  // floats per sweep of the workgroup
+  float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f;
+  int k = 4 * tid;
+  for (; k + 3 * kStride < K4; k += 4 * kStride) {
+    const float4 x0 = *reinterpret_cast<const float4*>(row + k);
+    const float4 x1 = *reinterpret_cast<const float4*>(row + k + kStride);
+    const float4 x2 = *reinterpret_cast<const float4*>(row + k + 2 * kStride);
+    const float4 x3 = *reinterpret_cast<const float4*>(row + k + 3 * kStride);
+    const float4 w0 = *reinterpret_cast<const float4*>(e + k);
+    const float4 w1 = *reinterpret_cast<const float4*>(e + k + kStride);
+    const float4 w2 = *reinterpret_cast<const float4*>(e + k + 2 * kStride);
+    const float4 w3 = *reinterpret_cast<const float4*>(e + k + 3 * kStride);
+    acc0 += w0.x * x0.x + w0.y * x0.y + w0.z * x0.z + w0.w * x0.w;
+    acc1 += w1.x * x1.x + w1.y * x1.y + w1.z * x1.z + w1.w * x1.w;
+    acc2 += w2.x * x2.x + w2.y * x2.y + w2.z * x2.z + w2.w * x2.w;
+    acc3 += w3.x * x3.x + w3.y * x3.y + w3.z * x3.z + w3.w * x3.w;
+  }
+  for (; k < K4; k += kStride) {
+    const float4 x = *reinterpret_cast<const float4*>(row + k);
+    const float4 w = *reinterpret_cast<const float4*>(e + k);
+    acc0 += w.x * x.x + w.y * x.y + w.z * x.z + w.w * x.w;
+  }
+  if (K4 + tid < K) acc0 += e[K4 + tid] * row[K4 + tid];
+  const float acc = wave_sum((acc0 + acc1) + (acc2 + acc3));
+  if (tid % kWave == 0) part[tid / kWave] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    float tot = part[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) tot += part[i];
+    const float eta = st->stats[1];
+    if (eta > 0.0f) u[r] = u[r] + tot / eta;
+  }
+}
+
+}  // namespace mppi

@@ -43,20 +43,12 @@ def test_struct_sizes_match_the_header(abi):
 
 
 def _bytes(abi, wl, **cfg_override):
-    from paper_2409_07563_amd.controller import Controller
-    cfg = abi.Config()
-    cfg.abi_version = abi.ABI_VERSION
-    cfg.dynamics = abi.DYNAMICS[wl.model]
-    cfg.integrator = abi.INTEGRATORS[wl.integrator]
-    cfg.cost = abi.COSTS[wl.cost]
-    cfg.num_samples, cfg.horizon = wl.K, wl.T
-    cfg.state_dim, cfg.control_dim = wl.n, wl.m
-    cfg.dt, cfg.lam = wl.dt, wl.lam
-    for j in range(wl.m):
-        cfg.sigma[j] = float(wl.sigma[j])
+    from paper_2409_07563_amd import controller
+    cfg = controller._config(wl, False, False, "auto")
     for k, v in cfg_override.items():
         setattr(cfg, k, v)
-    params, keep = Controller._params(wl)
+    keep = []
+    params = controller._params(wl, keep)
     n = abi.lib().mppi_workspace_bytes(C.byref(cfg), C.byref(params))
     return n, abi.lib().mppi_last_error().decode()
 
@@ -77,6 +69,18 @@ def test_workspace_size_for_valid_configs(abi):
 def test_invalid_configs_rejected(abi, override, needle):
     n, msg = _bytes(abi, W.c2("circles", K=256, T=10), **override)
     assert n == 0 and needle in msg, msg
+
+
+def test_batch_workspace_and_mismatch(abi):
+    from paper_2409_07563_amd import controller
+    insts = W.c4(n_instances=5)
+    keep = []
+    cfgs = (abi.Config * 5)(*[controller._config(w, False, False, "auto") for w in insts])
+    params = (abi.Params * 5)(*[controller._params(w, keep) for w in insts])
+    n = abi.lib().mppi_batch_workspace_bytes(cfgs, params, 5)
+    singles = sum(_bytes(abi, w)[0] for w in insts)
+    assert n > 0 and n >= 0.9 * singles
+    assert abi.lib().mppi_batch_workspace_bytes(cfgs, params, 0) == 0
 
 
 def test_invalid_params_rejected(abi):

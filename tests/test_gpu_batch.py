@@ -1,0 +1,109 @@
+"""Batched MPPI (many independent instances in one launch per phase) against
+the oracle and against single-instance contexts, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", file=sys.stderr, flush=True)
+    yield
+
+
+@pytest.fixture(scope="module")
+def mppi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2409_07563_amd as M
+    M.lib()
+    return M
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def small_batch(n=12, kmax=700):
+    """Heterogeneous instances of the c4 recipe, K capped so that the oracle
+    is quick; K, T, lambda, obstacles and goals all differ."""
+    out = []
+    for wl in W.c4(n_instances=n):
+        K = min(wl.K, kmax) - (wl.instance % 3) * 17   # ragged sizes
+        out.append(wl.replace(K=K))
+    return out
+
+
+def test_batch_against_oracle(mppi, oracle_lib):
+    insts = small_batch()
+    ctl = mppi.Controller(insts, debug=True)
+    ctl.sample()
+    ctl.rollout()
+    S = ctl.split(_np(ctl.costs()), 2)
+    eps = ctl.split(_np(ctl.noise()), 3)
+    crashes = ctl.split(_np(ctl.crashes()), 2)
+    ctl.update()
+    U = ctl.split(_np(ctl.controls()), 1)
+    stats = ctl.stats()
+    ctl.close()
+    for i, wl in enumerate(insts):
+        e_or = oracle_lib.workload_noise(wl)
+        assert np.array_equal(eps[i].view(np.uint32), e_or.ravel().view(np.uint32)), i
+        S_or, margin, cr_or = oracle_lib.rollout_costs(wl, eps=e_or)
+        parity.assert_costs_close(S[i], S_or, margin, f"instance {i}")
+        sure = margin >= parity.AMBIGUOUS_MARGIN
+        assert np.array_equal(crashes[i][sure], cr_or[sure])
+        o = oracle_lib.mppi(wl, iters=1)
+        parity.assert_controls_close(U[i].reshape(wl.T, 2), o["U"],
+                                     parity.controls_tol(wl, o["S"], o["w"], o["eps"]),
+                                     f"instance {i}")
+        assert stats[i]["status"] == 0 and stats[i]["iteration"] == 1
+
+
+def test_batch_equals_single_contexts_bitwise(mppi):
+    """The batch runs the same lane body and the same reduction order as a
+    single-instance context with one lane per sample: results are identical."""
+    insts = small_batch(n=6)
+    ctl = mppi.Controller(insts)
+    ctl.iterate(3)
+    U = ctl.split(_np(ctl.controls()), 1)
+    S = ctl.split(_np(ctl.costs()), 2)
+    ctl.close()
+    for i, wl in enumerate(insts):
+        one = mppi.Controller(wl, rollout="lane")
+        one.iterate(3)
+        u1 = _np(one.controls()).ravel()
+        s1 = _np(one.costs())
+        one.close()
+        assert np.array_equal(U[i].view(np.uint32), u1.view(np.uint32)), i
+        assert np.array_equal(S[i].view(np.uint32), s1.view(np.uint32)), i
+
+
+def test_batch_full_size_sampled(mppi, oracle_lib):
+    """All 256 instances of the c4 recipe in one context: every status OK, and
+    a sample of instances / samples recomputed by the oracle."""
+    insts = W.c4()
+    ctl = mppi.Controller(insts)
+    ctl.sample()
+    ctl.rollout()
+    S = ctl.split(_np(ctl.costs()), 2)
+    ctl.update()
+    stats = ctl.stats()
+    ctl.close()
+    assert all(s["status"] == 0 for s in stats)
+    rng = np.random.default_rng(4)
+    for i in rng.choice(len(insts), 6, replace=False):
+        wl = insts[i]
+        idx = rng.choice(wl.K, 48, replace=False)
+        eps = oracle_lib.workload_noise(wl)[:, :, idx]
+        S_or, margin, _ = oracle_lib.rollout_costs(wl.replace(K=len(idx)), eps=eps)
+        parity.assert_costs_close(S[i][idx], S_or, margin, f"instance {i}")
