@@ -715,3 +715,225 @@ void orc_philox_many(int64_t n, const uint32_t* ctr, const uint32_t key[2],
                      uint32_t* out) {
   for (int64_t i = 0; i < n; ++i) orc_philox4x32(ctr + 4 * i, key, 10, out + 4 * i);
 }
+
+/* ------------------------------------------------------------------------ */
+/* 7. Gradient of a loss on the updated controls (differentiable MPPI)       */
+/* ------------------------------------------------------------------------ */
+/*
+ * For one iteration U = u + sum_k w_k eps_k with w = softmin(J / lambda) and
+ * u independent of theta, a loss L(U) with G = dL/dU has
+ *   dL/dJ_k = -(w_k / lambda) (g_k - sum_i w_i g_i),  g_k = <G, eps_k>
+ * (the baseline rho cancels), and dL/dtheta = sum_k (dL/dJ_k) dJ_k/dtheta.
+ * dJ_k/dtheta comes from the discrete adjoint of the rollout: the costate
+ * mu_t = dJ/dx_t is swept backwards through every RK4 stage and the MLP
+ * residual of the actual discrete map (not a continuous adjoint ODE).
+ * Parameter layout of grad: [MLP blob (W1 b1 W2 b2 W3 b3) | Q diag (n) |
+ * wheelbase]; supported for the bicycle models with the TRACK cost.
+ */
+
+/* Jacobian-transpose product of the bicycle derivative at (x, v):
+ * dx += (df/dx)^T c, and dL += (df/dwheelbase)^T c. */
+static void bicycle_deriv_vjp(const orc_problem* P, const double* x, const double* c,
+                              double* dx, double* dL) {
+  const double psi = x[2], s = x[3], d = x[4], Lw = P->wheelbase;
+  const double cp = cos(psi), sp = sin(psi), td = tan(d), sec2 = 1.0 + td * td;
+  dx[2] += -s * sp * c[0] + s * cp * c[1];
+  dx[3] += cp * c[0] + sp * c[1] + td / Lw * c[2];
+  dx[4] += s * sec2 / Lw * c[2];
+  *dL += -s * td / (Lw * Lw) * c[2];
+}
+
+/* MLP residual forward with the activations kept for its backward. */
+static void mlp_forward_keep(const orc_problem* P, const double* z, double* h1, double* h2,
+                             double* g) {
+  const int H = P->mlp_hidden;
+  const double* W1 = P->mlp;
+  const double* b1 = W1 + H * 7;
+  const double* W2 = b1 + H;
+  const double* b2 = W2 + H * H;
+  const double* W3 = b2 + H;
+  const double* b3 = W3 + 5 * H;
+  for (int i = 0; i < H; ++i) {
+    double a = b1[i];
+    for (int j = 0; j < 7; ++j) a += W1[i * 7 + j] * z[j];
+    h1[i] = tanh(a);
+  }
+  for (int i = 0; i < H; ++i) {
+    double a = b2[i];
+    for (int j = 0; j < H; ++j) a += W2[i * H + j] * h1[j];
+    h2[i] = tanh(a);
+  }
+  for (int i = 0; i < 5; ++i) {
+    double a = b3[i];
+    for (int j = 0; j < H; ++j) a += W3[i * H + j] * h2[j];
+    g[i] = a;
+  }
+}
+
+/* Backward of g(z): dz += (dg/dz)^T cg, dmlp += (dg/dtheta)^T cg. */
+static void mlp_vjp(const orc_problem* P, const double* z, const double* cg, double* dz,
+                    double* dmlp) {
+  const int H = P->mlp_hidden;
+  double h1[256], h2[256], g[5], da2[256], da1[256];
+  mlp_forward_keep(P, z, h1, h2, g);
+  const double* W1 = P->mlp;
+  const double* W2 = W1 + H * 7 + H;
+  const double* W3 = W2 + H * H + H;
+  double* dW1 = dmlp;
+  double* db1 = dW1 + H * 7;
+  double* dW2 = db1 + H;
+  double* db2 = dW2 + H * H;
+  double* dW3 = db2 + H;
+  double* db3 = dW3 + 5 * H;
+  for (int i = 0; i < 5; ++i) {
+    db3[i] += cg[i];
+    for (int j = 0; j < H; ++j) dW3[i * H + j] += cg[i] * h2[j];
+  }
+  for (int j = 0; j < H; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < 5; ++i) s += W3[i * H + j] * cg[i];
+    da2[j] = s * (1.0 - h2[j] * h2[j]);
+  }
+  for (int i = 0; i < H; ++i) {
+    db2[i] += da2[i];
+    for (int j = 0; j < H; ++j) dW2[i * H + j] += da2[i] * h1[j];
+  }
+  for (int j = 0; j < H; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < H; ++i) s += W2[i * H + j] * da2[i];
+    da1[j] = s * (1.0 - h1[j] * h1[j]);
+  }
+  for (int i = 0; i < H; ++i) {
+    db1[i] += da1[i];
+    for (int j = 0; j < 7; ++j) dW1[i * 7 + j] += da1[i] * z[j];
+  }
+  for (int j = 0; j < 7; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < H; ++i) s += W1[i * 7 + j] * da1[i];
+    dz[j] += s;
+  }
+}
+
+/* Backward of one step x1 = F(x0, v): given mu1 = dJ/dx1, returns
+ * mu0 = (dF/dx0)^T mu1 and accumulates (dF/dtheta)^T mu1 into grad. */
+static void step_vjp(const orc_problem* P, const double* x0, const double* v, const double* mu1,
+                     double* mu0, double* grad_mlp, double* grad_L) {
+  const int n = 5;
+  const double h = P->dt;
+  double k1[5], k2[5], k3[5], x2[5], x3[5], x4[5];
+  deriv(P, x0, v, k1);
+  for (int i = 0; i < n; ++i) x2[i] = x0[i] + 0.5 * h * k1[i];
+  deriv(P, x2, v, k2);
+  for (int i = 0; i < n; ++i) x3[i] = x0[i] + 0.5 * h * k2[i];
+  deriv(P, x3, v, k3);
+  for (int i = 0; i < n; ++i) x4[i] = x0[i] + h * k3[i];
+  double ck1[5], ck2[5], ck3[5], ck4[5], cx[5];
+  for (int i = 0; i < n; ++i) {
+    mu0[i] = mu1[i];
+    ck1[i] = h / 6.0 * mu1[i];
+    ck2[i] = h / 3.0 * mu1[i];
+    ck3[i] = h / 3.0 * mu1[i];
+    ck4[i] = h / 6.0 * mu1[i];
+  }
+  /* k4 = f(x4), x4 = x0 + h k3 */
+  for (int i = 0; i < n; ++i) cx[i] = 0.0;
+  bicycle_deriv_vjp(P, x4, ck4, cx, grad_L);
+  for (int i = 0; i < n; ++i) { mu0[i] += cx[i]; ck3[i] += h * cx[i]; }
+  /* k3 = f(x3), x3 = x0 + h/2 k2 */
+  for (int i = 0; i < n; ++i) cx[i] = 0.0;
+  bicycle_deriv_vjp(P, x3, ck3, cx, grad_L);
+  for (int i = 0; i < n; ++i) { mu0[i] += cx[i]; ck2[i] += 0.5 * h * cx[i]; }
+  /* k2 = f(x2), x2 = x0 + h/2 k1 */
+  for (int i = 0; i < n; ++i) cx[i] = 0.0;
+  bicycle_deriv_vjp(P, x2, ck2, cx, grad_L);
+  for (int i = 0; i < n; ++i) { mu0[i] += cx[i]; ck1[i] += 0.5 * h * cx[i]; }
+  /* k1 = f(x0) */
+  for (int i = 0; i < n; ++i) cx[i] = 0.0;
+  bicycle_deriv_vjp(P, x0, ck1, cx, grad_L);
+  for (int i = 0; i < n; ++i) mu0[i] += cx[i];
+  /* residual dt * g([x0; v]) */
+  if (P->model == ORC_BICYCLE_MLP) {
+    double z[7] = {x0[0], x0[1], x0[2], x0[3], x0[4], v[0], v[1]};
+    double cg[5], dz[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < 5; ++i) cg[i] = h * mu1[i];
+    mlp_vjp(P, z, cg, dz, grad_mlp);
+    for (int i = 0; i < 5; ++i) mu0[i] += dz[i];
+  }
+}
+
+/* grad <- dL/dtheta for L with dL/dU = G (layout above); also returns the
+ * forward's U, S and w.  Returns 0, -1 if unsupported, -6 if all J are
+ * non-finite. */
+int orc_backward(const orc_problem* P, const double* x0, const double* u, const float* eps,
+                 const double* G, double* grad, double* U_out, double* S_out, double* w_out) {
+  if ((P->model != ORC_BICYCLE && P->model != ORC_BICYCLE_MLP) || P->cost != ORC_COST_TRACK ||
+      P->integrator != ORC_RK4)
+    return -1;
+  const int32_t K = P->K, T = P->T, m = P->m, n = P->n;
+  const int H = P->mlp_hidden;
+  const int nmlp = P->model == ORC_BICYCLE_MLP ? 7 * H + H + H * H + H + 5 * H + 5 : 0;
+  const int ngrad = nmlp + n + 1;
+  double* S = (double*)malloc(sizeof(double) * K);
+  double* w = (double*)malloc(sizeof(double) * K);
+  double* U = (double*)malloc(sizeof(double) * T * m);
+  double stats[4];
+  orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL, NULL);
+  int rc = orc_softmin_update(P, S, eps, K, u, w, U, stats);
+  for (int i = 0; i < ngrad; ++i) grad[i] = 0.0;
+  if (rc == 0) {
+    double* g = (double*)malloc(sizeof(double) * K);
+    double gbar = 0.0;
+    for (int32_t k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int32_t r = 0; r < T * m; ++r) acc += G[r] * (double)eps[(int64_t)r * K + k];
+      g[k] = acc;
+      gbar += w[k] * acc;
+    }
+    double* xs = (double*)malloc(sizeof(double) * (T + 1) * n);
+    double* vs = (double*)malloc(sizeof(double) * T * m);
+    double* gmlp = grad;
+    double* gQ = grad + nmlp;
+    double* gL = grad + nmlp + n;
+    for (int32_t k = 0; k < K; ++k) {
+      const double a = -(w[k] / P->lambda) * (g[k] - gbar);
+      if (a == 0.0) continue;
+      for (int i = 0; i < n; ++i) xs[i] = x0[i];
+      for (int32_t t = 0; t < T; ++t) {
+        for (int j = 0; j < m; ++j) vs[t * m + j] = u[t * m + j] + (double)eps[((int64_t)t * m + j) * K + k];
+        for (int i = 0; i < n; ++i) xs[(t + 1) * n + i] = xs[t * n + i];
+        orc_step(P, xs + (t + 1) * n, vs + t * m);
+      }
+      /* terminal and running costs: phi = w16 sum Q_i e_i^2 at x_T, l_t at x_{t+1} */
+      double mu[5], mu0[5];
+      const double* xT = xs + T * n;
+      const double* rT = P->ref + (int64_t)T * n;
+      for (int i = 0; i < n; ++i) {
+        const double e = xT[i] - rT[i];
+        mu[i] = a * 2.0 * P->w[16] * P->w[i] * e;
+        gQ[i] += a * P->w[16] * e * e;
+      }
+      for (int32_t t = T - 1; t >= 0; --t) {
+        /* running cost l_t on x_{t+1} */
+        const double* x1 = xs + (t + 1) * n;
+        const double* r1 = P->ref + (int64_t)(t + 1) * n;
+        for (int i = 0; i < n; ++i) {
+          const double e = x1[i] - r1[i];
+          mu[i] += a * 2.0 * P->w[i] * e;
+          gQ[i] += a * e * e;
+        }
+        step_vjp(P, xs + t * n, vs + t * m, mu, mu0, gmlp, gL);
+        for (int i = 0; i < n; ++i) mu[i] = mu0[i];
+      }
+    }
+    free(xs);
+    free(vs);
+    free(g);
+  }
+  if (U_out) for (int i = 0; i < T * m; ++i) U_out[i] = U[i];
+  if (S_out) for (int k = 0; k < K; ++k) S_out[k] = S[k];
+  if (w_out) for (int k = 0; k < K; ++k) w_out[k] = w[k];
+  free(S);
+  free(w);
+  free(U);
+  return rc;
+}

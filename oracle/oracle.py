@@ -70,6 +70,8 @@ def lib():
         L.orc_softmin_update.restype = C.c_int
         L.orc_mppi.argtypes = [P, f64p, f64p, C.c_int32, C.c_uint32, f32p, f64p, f64p, f64p]
         L.orc_mppi.restype = C.c_int
+        L.orc_backward.argtypes = [P, f64p, f64p, f32p, f64p, f64p, f64p, f64p, f64p]
+        L.orc_backward.restype = C.c_int
         L.orc_trajectory.argtypes = [P, f64p, f64p, f64p]
         L.orc_sequence_cost.argtypes = [P, f64p, f64p]
         L.orc_sequence_cost.restype = C.c_double
@@ -93,8 +95,9 @@ def _d(a):
 class Problem:
     """An OrcProblem plus the binary64 arrays it points into."""
 
-    def __init__(self, wl, **override):
+    def __init__(self, wl, keep_f64: bool = False, **override):
         self.wl = wl
+        r32 = (lambda v: float(v)) if keep_f64 else (lambda v: float(np.float32(v)))
         p = OrcProblem()
         p.model = MODEL_ID[wl.model]
         p.integrator = INTEGRATOR_ID[wl.integrator]
@@ -106,7 +109,7 @@ class Problem:
             p.sigma[j] = float(wl.sigma[j])
         p.seed = wl.seed
         p.instance = wl.instance
-        p.wheelbase = float(np.float32(wl.wheelbase))
+        p.wheelbase = r32(wl.wheelbase)
         p.mass = float(np.float32(wl.mass))
         for i in range(3):
             p.inertia[i] = float(np.float32(wl.inertia[i]))
@@ -229,6 +232,64 @@ def mppi(wl, iters=None, iter0: int = 0, u=None, x0=None, **override):
     rc = lib().orc_mppi(P.ref, x0, u, iters, iter0, eps, S, w, stats)
     return {"U": u.reshape(wl.T, wl.m), "eps": eps, "S": S, "w": w, "stats": stats,
             "status": rc}
+
+
+def n_grad(wl) -> int:
+    """Length of the gradient vector: [MLP blob | Q diag (n) | wheelbase]."""
+    H = wl.mlp_hidden if wl.model == "bicycle_mlp" else 0
+    nmlp = 7 * H + H + H * H + H + 5 * H + 5 if H else 0
+    return nmlp + wl.n + 1
+
+
+def backward(wl, dL_dU, u=None, x0=None, eps=None, iteration: int = 0):
+    """dL/dtheta (layout [MLP blob | Q diag | wheelbase]) of a loss on the
+    controls of one iteration, given dL/dU; plus U, S, w of that iteration."""
+    P = Problem(wl)
+    if eps is None:
+        eps = workload_noise(wl, iteration)
+    eps = np.ascontiguousarray(eps, np.float32)
+    u = _d(wl.u0 if u is None else u).ravel()
+    x0 = _d(wl.x0 if x0 is None else x0)
+    grad = np.zeros(n_grad(wl))
+    U = np.empty(wl.T * wl.m)
+    S = np.empty(wl.K)
+    w = np.empty(wl.K)
+    rc = lib().orc_backward(P.ref, x0, u, eps, _d(dL_dU).ravel(), grad, U, S, w)
+    if rc == -1:
+        raise ValueError("backward needs a bicycle model with RK4 and the track cost")
+    return {"grad": grad, "U": U.reshape(wl.T, wl.m), "S": S, "w": w, "status": rc}
+
+
+def with_theta(wl, theta):
+    """The workload with its parameters set from a vector in the gradient layout."""
+    theta = np.asarray(theta, np.float64)
+    H = wl.mlp_hidden if wl.model == "bicycle_mlp" else 0
+    nmlp = 7 * H + H + H * H + H + 5 * H + 5 if H else 0
+    w = wl.w.astype(np.float64).copy()
+    w[:wl.n] = theta[nmlp:nmlp + wl.n]
+    return wl.replace(mlp=theta[:nmlp].copy() if H else wl.mlp, w=w,
+                      wheelbase=float(theta[nmlp + wl.n]))
+
+
+def theta_of(wl):
+    parts = [np.asarray(wl.mlp, np.float64)] if wl.model == "bicycle_mlp" else []
+    parts += [wl.w[:wl.n].astype(np.float64), [float(np.float32(wl.wheelbase))]]
+    return np.concatenate(parts)
+
+
+def loss_and_controls(wl, u_ref, theta=None, iteration: int = 0):
+    """(L, U) with L = |U - u_ref|^2 for one iteration at parameters theta
+    (binary64 throughout: theta is not rounded to binary32)."""
+    w2 = wl if theta is None else with_theta(wl, theta)
+    P = Problem(w2, keep_f64=True)
+    u = _d(w2.u0).ravel().copy()
+    eps = np.empty((w2.T, w2.m, w2.K), np.float32)
+    S = np.empty(w2.K)
+    w = np.empty(w2.K)
+    stats = np.empty(4)
+    lib().orc_mppi(P.ref, _d(w2.x0), u, 1, iteration, eps, S, w, stats)
+    U = u.reshape(w2.T, w2.m)
+    return float(np.sum((U - u_ref) ** 2)), U
 
 
 # --------------------------------------------------------------------------

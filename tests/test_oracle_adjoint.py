@@ -1,0 +1,93 @@
+"""Pins for the oracle's gradient of a loss on the updated controls.
+
+The adjoint (a reverse sweep through the softmin Jacobian, the RK4 stages and
+the MLP residual) is checked against central finite differences of the
+oracle's own forward iteration, which runs through entirely separate code
+(the rollout, the update and the loss are re-evaluated at perturbed
+parameters).  Central differences with step h have truncation error O(h^2);
+a first-layer weight that multiplies a position of tens of metres sits where
+the loss is strongly curved, so the difference quotients at h and h/2 are
+combined by Richardson extrapolation (error O(h^4)).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+
+def _central(wl, uref, theta, i, h):
+    tp = theta.copy()
+    tp[i] += h
+    tm = theta.copy()
+    tm[i] -= h
+    return (O.loss_and_controls(wl, uref, tp)[0] - O.loss_and_controls(wl, uref, tm)[0]) / (2 * h)
+
+
+def _fd(wl, uref, theta, i, h):
+    return (4.0 * _central(wl, uref, theta, i, h / 2) - _central(wl, uref, theta, i, h)) / 3.0
+
+
+def _check(wl, uref, idx, rtol=2e-5):
+    L0, U0 = O.loss_and_controls(wl, uref)
+    r = O.backward(wl, 2.0 * (U0 - uref))
+    assert r["status"] == 0
+    np.testing.assert_allclose(r["U"], U0, rtol=0, atol=1e-12)
+    theta = O.theta_of(wl)
+    scale = np.max(np.abs(r["grad"]))
+    for i in idx:
+        h = 1e-3 * max(1.0, abs(theta[i]))
+        fd = _fd(wl, uref, theta, i, h)
+        assert abs(r["grad"][i] - fd) <= rtol * max(abs(fd), 1e-3 * scale), (i, r["grad"][i], fd)
+    return r
+
+
+def test_adjoint_vs_fd_bicycle_mlp():
+    wl = W.c5(K=64, T=20, hidden=16)
+    uref = W.c5_uref(T=20)
+    n = O.n_grad(wl)
+    rng = np.random.default_rng(1)
+    H = 16
+    nmlp = 7 * H + H + H * H + H + 5 * H + 5
+    # a few entries of every parameter block, every Q entry and the wheelbase
+    blocks = [(0, 7 * H), (7 * H, 8 * H), (8 * H, 8 * H + H * H), (8 * H + H * H, 9 * H + H * H),
+              (9 * H + H * H, 14 * H + H * H), (14 * H + H * H, nmlp)]
+    idx = [int(rng.integers(a, b)) for a, b in blocks for _ in range(3)]
+    idx += list(range(nmlp, n))
+    _check(wl, uref, idx)
+
+
+def test_adjoint_vs_fd_plain_bicycle():
+    wl = W.c5(K=48, T=15, hidden=16).replace(model="bicycle", mlp=None, mlp_hidden=0)
+    uref = W.c5_uref(T=15)
+    r = _check(wl, uref, range(O.n_grad(wl)))
+    assert O.n_grad(wl) == 6
+    assert np.all(np.isfinite(r["grad"]))
+
+
+def test_adjoint_linear_in_loss_gradient():
+    wl = W.c5(K=32, T=10, hidden=8)
+    rng = np.random.default_rng(2)
+    G1, G2 = rng.normal(size=(2, 10, 2))
+    g1 = O.backward(wl, G1)["grad"]
+    g2 = O.backward(wl, G2)["grad"]
+    g12 = O.backward(wl, 0.5 * G1 - 2.0 * G2)["grad"]
+    np.testing.assert_allclose(g12, 0.5 * g1 - 2.0 * g2, rtol=1e-10, atol=1e-12 * np.abs(g1).max())
+
+
+def test_adjoint_zero_when_loss_ignores_controls():
+    wl = W.c5(K=16, T=8, hidden=8)
+    r = O.backward(wl, np.zeros((8, 2)))
+    assert np.all(r["grad"] == 0.0)
+
+
+def test_adjoint_single_sample_has_no_gradient():
+    # with K = 1 the weight is 1 whatever the cost: U = u + eps_0
+    wl = W.c5(K=1, T=8, hidden=8)
+    r = O.backward(wl, np.ones((8, 2)))
+    assert np.all(r["grad"] == 0.0)
+
+
+def test_adjoint_rejects_other_models():
+    with pytest.raises(ValueError):
+        O.backward(W.c1(K=8, T=4), np.zeros((4, 2)))
