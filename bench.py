@@ -29,6 +29,13 @@ sys.path.insert(0, ROOT)
 # 256 * 4 * 16 * 2.4e9 = 3.93e13 /s (78.6 TFLOP/s counting an FMA as 2).
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12
+# Dense FP32 matrix-core peak of MI355X (v_mfma_f32_16x16x4_f32), FLOP/s.
+MFMA_FP32_PEAK = 157.3e12
+
+
+def mlp_macs(hidden: int) -> int:
+    """Multiply-adds of one evaluation of the 7 -> H -> H -> 5 residual MLP."""
+    return 7 * hidden + hidden * hidden + 5 * hidden
 
 # Algorithmic VALU lane-operations per rollout step of the fused rollout +
 # cost kernel (counted from the arithmetic the method needs; transcendental
@@ -80,6 +87,8 @@ def make_workload(name: str):
         return W.c3()
     if name == "c4":
         return W.c4()
+    if name == "c5":
+        return W.c5()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -162,6 +171,8 @@ def main():
     wl = make_workload(args.workload)
     if isinstance(wl, list):
         return bench_batch(args, wl)
+    if wl.model == "bicycle_mlp":
+        return bench_grad(args, wl)
     I = wl.iters
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -224,6 +235,91 @@ def main():
     ctl.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters or I)
+    print(json.dumps(out), flush=True)
+
+
+def bench_grad(args, wl):
+    """Differentiable MPPI (MLP residual dynamics): the plain forward iteration,
+    and one forward iteration in gradient mode (checkpointing rollout) plus the
+    adjoint backward of L = |U - u_ref|^2, on the same GPU."""
+    import numpy as np
+    import torch
+    import paper_2409_07563_amd as M
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    uref = torch.as_tensor(W.c5_uref(T=wl.T), device=dev)
+
+    def timed(stream, fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps * 1e-3
+
+    def measure(w):
+        plain = M.Controller(w, device=dev)
+        t_fwd = timed(plain.stream, lambda: plain.iterate(1), args.steps, args.warmup)
+        t_noise, t_roll, t_upd = phase_times(plain, args.kernel_reps)
+        plain.close()
+        grad = M.Controller(w, device=dev, requires_grad=True)
+        grad.iterate(1)
+        G = (2.0 * (grad.controls() - uref)).contiguous()
+        L = M.lib()
+
+        def fwd_bwd():
+            M._abi.check(L.mppi_iterate(grad.ctx, 1))
+            M._abi.check(L.mppi_backward(grad.ctx, G.data_ptr(), out.data_ptr()))
+        out = torch.empty(grad.theta_len(), device=dev)
+        grad._enter()
+        t_fb = timed(grad.stream, fwd_bwd, args.steps, args.warmup)
+        t_fg = timed(grad.stream, lambda: M._abi.check(L.mppi_iterate(grad.ctx, 1)),
+                     args.steps, args.warmup)
+        swept = int((grad.weights() > 0).sum())
+        grad.close()
+        return t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept
+
+    t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept = measure(wl)
+    dense = wl.replace(lam=500.0)
+    d_fwd, _, _, _, d_fb, d_fg, d_swept = measure(dense)
+
+    steps = wl.K * wl.T
+    flops = 2.0 * mlp_macs(wl.mlp_hidden) * steps
+    achieved = flops / t_roll
+    eps_bytes = 4 * wl.T * wl.m * wl.K
+    out = {
+        "metric": "rollout-steps/sec (K*T) per MPPI iter + fwd+bwd/fwd time ratio, 1 MI355X",
+        "value": steps / t_fwd, "unit": "rollout-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_fwd * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "K": wl.K, "T": wl.T, "iterations_per_step": 1,
+                   "dynamics": wl.model, "hidden": wl.mlp_hidden, "integrator": wl.integrator,
+                   "cost": wl.cost, "lambda": wl.lam, "checkpoint_every": 10},
+        "fwd_bwd_over_fwd": (t_fb) / t_fwd,
+        "grad": {"fwd_plain_ms": t_fwd * 1e3, "fwd_checkpointing_ms": t_fg * 1e3,
+                 "fwd_plus_bwd_ms": t_fb * 1e3, "bwd_ms": (t_fb - t_fg) * 1e3,
+                 "samples_swept": swept,
+                 "lambda_500": {"fwd_bwd_over_fwd": d_fb / d_fwd, "fwd_plus_bwd_ms": d_fb * 1e3,
+                                "bwd_ms": (d_fb - d_fg) * 1e3, "samples_swept": d_swept}},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12,
+                     "peak": MFMA_FP32_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / MFMA_FP32_PEAK,
+                     "traffic": traffic_record("rollout_tile", args.workload),
+                     "kernel": "rollout_tile_kernel", "flops_per_rollout_step":
+                         2 * mlp_macs(wl.mlp_hidden), "launch_us": t_roll * 1e6},
+        "kernels": {"noise": {"us": t_noise * 1e6, "hbm_GBps": eps_bytes / t_noise / 1e9},
+                    "rollout": {"us": t_roll * 1e6},
+                    "softmin_update": {"us": t_upd * 1e6,
+                                       "hbm_GBps": (eps_bytes + 8 * wl.K) / t_upd / 1e9}},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, 1)
     print(json.dumps(out), flush=True)
 
 

@@ -61,7 +61,10 @@ typedef enum mppi_status {
  *                          omega' = J^-1 (tau - omega x J omega); q is
  *                          renormalised after each step
  *   BICYCLE_MLP       5/2: bicycle step + dt * g([x_t; v_t]),
- *                          g = W3 tanh(W2 tanh(W1 z + b1) + b2) + b3 */
+ *                          g = W3 tanh(W2 tanh(W1 z + b1) + b2) + b3,
+ *                          H = 16, 32 or 64 hidden units; costs QUADRATIC and
+ *                          TRACK; the MLP runs on the matrix cores in
+ *                          binary32 */
 typedef enum mppi_dynamics {
   MPPI_DYN_DOUBLE_INTEGRATOR = 0,
   MPPI_DYN_BICYCLE = 1,
@@ -114,9 +117,14 @@ enum {
                                 transcendental units (the paper's own choice of
                                 intrinsics for trigonometry, Sec. III-B) */
   MPPI_F_ROLLOUT_LANE = 4u,  /* force one lane per sample in the rollout */
-  MPPI_F_ROLLOUT_QUAD = 8u   /* force four lanes per sample (bicycle + RK4 only);
+  MPPI_F_ROLLOUT_QUAD = 8u,  /* force four lanes per sample (bicycle + RK4 only);
                                 by default the library picks four lanes per sample
                                 for the bicycle with RK4 when K <= 32768 */
+  MPPI_F_REQUIRES_GRAD = 16u /* keep what mppi_backward needs: the rollout stores
+                                state checkpoints every params.checkpoint_every
+                                steps and a copy of the controls it used (BICYCLE
+                                or BICYCLE_MLP with RK4 and the TRACK cost; not
+                                for batch contexts) */
 };
 
 typedef struct mppi_config {
@@ -159,6 +167,8 @@ typedef struct mppi_params {
   float map_x0, map_y0;   /* lower-left corner of cell (0, 0) */
   float map_res;          /* cell size > 0 */
   const float* costmap;   /* [map_h][map_w] */
+  int32_t checkpoint_every; /* MPPI_F_REQUIRES_GRAD: steps between state
+                               checkpoints, 1..64 (0 = 10) */
 } mppi_params;
 
 typedef struct mppi_ctx mppi_ctx;
@@ -245,8 +255,33 @@ enum {
 /* Enqueue a device copy of an internal buffer to d_dst. */
 mppi_status mppi_get_debug(mppi_ctx* ctx, int32_t what, void* d_dst);
 
-/* Gradient of a loss on the updated controls (not built in this version:
- * returns MPPI_EUNSUPPORTED). */
+/* ---- differentiation (spec extension) --------------------------------
+ * The parameter vector theta, "gradient layout", n_theta floats:
+ *   [W1 (H*7) | b1 (H) | W2 (H*H) | b2 (H) | W3 (5*H) | b3 (5)]  (BICYCLE_MLP only)
+ *   [Q diag = w[0..n) of the TRACK cost (n) | wheelbase (1)].
+ * mppi_theta_len: n_theta of a context (0 and an error message if the
+ * context cannot differentiate). */
+int32_t mppi_theta_len(const mppi_ctx* ctx);
+
+/* Replace theta (host memory, n_theta floats in the gradient layout): the MLP
+ * weights, the Q diagonal and the wheelbase.  Waits for the upload; iteration
+ * graphs captured before are rebuilt on their next use.  Needs
+ * MPPI_F_REQUIRES_GRAD.  Errors: EINVAL (NULL, non-finite values, wheelbase
+ * <= 0), ESTATE (context without MPPI_F_REQUIRES_GRAD). */
+mppi_status mppi_set_theta(mppi_ctx* ctx, const float* host_theta);
+
+/* Gradient of a loss L on the controls U produced by the last update,
+ * U = u + sum_k w_k eps_k (Algorithm 1; the nominal u of that iteration is
+ * held fixed): d_grad[n_theta] <- dL/dtheta (device, gradient layout) given
+ * d_dL_dU[T][m] = dL/dU (device).  Differentiates through the softmin weights
+ * (w_k depends on theta only through the costs J_k; the baseline rho drops
+ * out) and through every rollout: the costate is swept backwards over the
+ * discrete step (the four RK4 stages and the MLP residual) from state
+ * checkpoints.  Samples of weight exactly zero contribute nothing and are
+ * skipped.  Binary32 throughout except the normaliser eta (binary64).
+ * Enqueued on the context's stream; the result is bitwise reproducible.
+ * Errors: EINVAL (NULL), ESTATE (no MPPI_F_REQUIRES_GRAD, or no update since
+ * the last mppi_sample / mppi_set_costs), EDEVICE. */
 mppi_status mppi_backward(mppi_ctx* ctx, const float* d_dL_dU, float* d_grad);
 
 void mppi_destroy(mppi_ctx* ctx);

@@ -862,10 +862,15 @@ static void step_vjp(const orc_problem* P, const double* x0, const double* v, co
 }
 
 /* grad <- dL/dtheta for L with dL/dU = G (layout above); also returns the
- * forward's U, S and w.  Returns 0, -1 if unsupported, -6 if all J are
- * non-finite. */
+ * forward's U, S and w.  S_in (optional): costs to form the weights from in
+ * place of the rollout's own (the sweeps still differentiate the rollouts).
+ * grad_abs (optional): sum over samples of rel_k |a_k dJ_k/dtheta| (rel_k = 1
+ * when rel is NULL), the scale of the rounding error of the sum when sample
+ * k's terms carry relative error rel_k.  Returns 0, -1 if unsupported, -6 if
+ * all J are non-finite. */
 int orc_backward(const orc_problem* P, const double* x0, const double* u, const float* eps,
-                 const double* G, double* grad, double* U_out, double* S_out, double* w_out) {
+                 const double* G, const double* S_in, const double* rel, double* grad,
+                 double* grad_abs, double* U_out, double* S_out, double* w_out) {
   if ((P->model != ORC_BICYCLE && P->model != ORC_BICYCLE_MLP) || P->cost != ORC_COST_TRACK ||
       P->integrator != ORC_RK4)
     return -1;
@@ -877,26 +882,42 @@ int orc_backward(const orc_problem* P, const double* x0, const double* u, const 
   double* w = (double*)malloc(sizeof(double) * K);
   double* U = (double*)malloc(sizeof(double) * T * m);
   double stats[4];
-  orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL, NULL);
+  if (S_in)
+    for (int32_t k = 0; k < K; ++k) S[k] = S_in[k];
+  else
+    orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL, NULL);
   int rc = orc_softmin_update(P, S, eps, K, u, w, U, stats);
-  for (int i = 0; i < ngrad; ++i) grad[i] = 0.0;
+  double* dk = (double*)malloc(sizeof(double) * ngrad); /* dJ_k/dtheta of one sample */
+  for (int i = 0; i < ngrad; ++i) {
+    grad[i] = 0.0;
+    if (grad_abs) grad_abs[i] = 0.0;
+  }
   if (rc == 0) {
+    /* g_k = <G, eps_k>; dL/dJ_k = -(w_k/lambda) (g_k - sum_i w_i g_i), written
+     * as -(w_k/lambda) sum_i w_i (g_k - g_i) (the weights sum to one) so that
+     * no cancellation occurs when one sample holds almost all the weight */
     double* g = (double*)malloc(sizeof(double) * K);
-    double gbar = 0.0;
+    double* ak = (double*)malloc(sizeof(double) * K);
     for (int32_t k = 0; k < K; ++k) {
       double acc = 0.0;
       for (int32_t r = 0; r < T * m; ++r) acc += G[r] * (double)eps[(int64_t)r * K + k];
       g[k] = acc;
-      gbar += w[k] * acc;
+    }
+    for (int32_t k = 0; k < K; ++k) {
+      double d = 0.0;
+      if (w[k] != 0.0)
+        for (int32_t i = 0; i < K; ++i) d += w[i] * (g[k] - g[i]);
+      ak[k] = -(w[k] / P->lambda) * d;
     }
     double* xs = (double*)malloc(sizeof(double) * (T + 1) * n);
     double* vs = (double*)malloc(sizeof(double) * T * m);
-    double* gmlp = grad;
-    double* gQ = grad + nmlp;
-    double* gL = grad + nmlp + n;
+    double* gmlp = dk;
+    double* gQ = dk + nmlp;
+    double* gL = dk + nmlp + n;
     for (int32_t k = 0; k < K; ++k) {
-      const double a = -(w[k] / P->lambda) * (g[k] - gbar);
+      const double a = ak[k];
       if (a == 0.0) continue;
+      for (int i = 0; i < ngrad; ++i) dk[i] = 0.0;
       for (int i = 0; i < n; ++i) xs[i] = x0[i];
       for (int32_t t = 0; t < T; ++t) {
         for (int j = 0; j < m; ++j) vs[t * m + j] = u[t * m + j] + (double)eps[((int64_t)t * m + j) * K + k];
@@ -904,13 +925,14 @@ int orc_backward(const orc_problem* P, const double* x0, const double* u, const 
         orc_step(P, xs + (t + 1) * n, vs + t * m);
       }
       /* terminal and running costs: phi = w16 sum Q_i e_i^2 at x_T, l_t at x_{t+1} */
+      /* dJ_k/dtheta with mu_t = dJ_k/dx_t (a_k is applied afterwards) */
       double mu[5], mu0[5];
       const double* xT = xs + T * n;
       const double* rT = P->ref + (int64_t)T * n;
       for (int i = 0; i < n; ++i) {
         const double e = xT[i] - rT[i];
-        mu[i] = a * 2.0 * P->w[16] * P->w[i] * e;
-        gQ[i] += a * P->w[16] * e * e;
+        mu[i] = 2.0 * P->w[16] * P->w[i] * e;
+        gQ[i] += P->w[16] * e * e;
       }
       for (int32_t t = T - 1; t >= 0; --t) {
         /* running cost l_t on x_{t+1} */
@@ -918,22 +940,73 @@ int orc_backward(const orc_problem* P, const double* x0, const double* u, const 
         const double* r1 = P->ref + (int64_t)(t + 1) * n;
         for (int i = 0; i < n; ++i) {
           const double e = x1[i] - r1[i];
-          mu[i] += a * 2.0 * P->w[i] * e;
-          gQ[i] += a * e * e;
+          mu[i] += 2.0 * P->w[i] * e;
+          gQ[i] += e * e;
         }
         step_vjp(P, xs + t * n, vs + t * m, mu, mu0, gmlp, gL);
         for (int i = 0; i < n; ++i) mu[i] = mu0[i];
+      }
+      for (int i = 0; i < ngrad; ++i) {
+        grad[i] += a * dk[i];
+        if (grad_abs) grad_abs[i] += fabs(a * dk[i]) * (rel ? rel[k] : 1.0);
       }
     }
     free(xs);
     free(vs);
     free(g);
+    free(ak);
   }
   if (U_out) for (int i = 0; i < T * m; ++i) U_out[i] = U[i];
   if (S_out) for (int k = 0; k < K; ++k) S_out[k] = S[k];
   if (w_out) for (int k = 0; k < K; ++k) w_out[k] = w[k];
+  free(dk);
   free(S);
   free(w);
   free(U);
   return rc;
+}
+
+/* Sensitivity of each sample's cost to the rounding of its trajectory:
+ * cond[k] = sum_{t=1..T} sum_i |dJ_k/dx_{t,i}| |x_{t,i}|, the first-order
+ * change of J_k when every state component at every step is perturbed by one
+ * unit in the last place relative to its size.  A binary32 rollout commits a
+ * few such roundings per component and step, so its cost can differ from the
+ * binary64 one by a small multiple of 2^-24 cond[k] whatever the kernel does.
+ * Same models, integrator and cost as orc_backward; returns -1 otherwise. */
+int orc_cost_condition(const orc_problem* P, const double* x0, const double* u, const float* eps,
+                       int64_t ldk, double* cond) {
+  if ((P->model != ORC_BICYCLE && P->model != ORC_BICYCLE_MLP) || P->cost != ORC_COST_TRACK ||
+      P->integrator != ORC_RK4)
+    return -1;
+  const int32_t K = P->K, T = P->T, m = P->m, n = P->n;
+  const int H = P->mlp_hidden;
+  const int nmlp = P->model == ORC_BICYCLE_MLP ? 7 * H + H + H * H + H + 5 * H + 5 : 0;
+  double* scratch = (double*)malloc(sizeof(double) * (nmlp + 1));
+  double* xs = (double*)malloc(sizeof(double) * (T + 1) * n);
+  double* vs = (double*)malloc(sizeof(double) * T * m);
+  for (int32_t k = 0; k < K; ++k) {
+    for (int i = 0; i < n; ++i) xs[i] = x0[i];
+    for (int32_t t = 0; t < T; ++t) {
+      for (int j = 0; j < m; ++j) vs[t * m + j] = u[t * m + j] + (double)eps[((int64_t)t * m + j) * ldk + k];
+      for (int i = 0; i < n; ++i) xs[(t + 1) * n + i] = xs[t * n + i];
+      orc_step(P, xs + (t + 1) * n, vs + t * m);
+    }
+    double mu[5], mu0[5], c = 0.0;
+    const double* xT = xs + T * n;
+    const double* rT = P->ref + (int64_t)T * n;
+    for (int i = 0; i < n; ++i) mu[i] = 2.0 * P->w[16] * P->w[i] * (xT[i] - rT[i]);
+    for (int32_t t = T - 1; t >= 0; --t) {
+      const double* x1 = xs + (t + 1) * n;
+      const double* r1 = P->ref + (int64_t)(t + 1) * n;
+      for (int i = 0; i < n; ++i) mu[i] += 2.0 * P->w[i] * (x1[i] - r1[i]);
+      for (int i = 0; i < n; ++i) c += fabs(mu[i]) * fabs(x1[i]);
+      step_vjp(P, xs + t * n, vs + t * m, mu, mu0, scratch, scratch + nmlp);
+      for (int i = 0; i < n; ++i) mu[i] = mu0[i];
+    }
+    cond[k] = c;
+  }
+  free(scratch);
+  free(xs);
+  free(vs);
+  return 0;
 }

@@ -46,6 +46,15 @@ class OrcProblem(C.Structure):
 _lib = None
 
 
+class _opt_f64p:
+    """A C-contiguous float64 array argument that may be None (NULL)."""
+    _t = np.ctypeslib.ndpointer(np.float64, flags="C")
+
+    @classmethod
+    def from_param(cls, obj):
+        return None if obj is None else cls._t.from_param(obj)
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -70,8 +79,11 @@ def lib():
         L.orc_softmin_update.restype = C.c_int
         L.orc_mppi.argtypes = [P, f64p, f64p, C.c_int32, C.c_uint32, f32p, f64p, f64p, f64p]
         L.orc_mppi.restype = C.c_int
-        L.orc_backward.argtypes = [P, f64p, f64p, f32p, f64p, f64p, f64p, f64p, f64p]
+        L.orc_backward.argtypes = [P, f64p, f64p, f32p, f64p, _opt_f64p, _opt_f64p, f64p,
+                                   _opt_f64p, f64p, f64p, f64p]
         L.orc_backward.restype = C.c_int
+        L.orc_cost_condition.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p]
+        L.orc_cost_condition.restype = C.c_int
         L.orc_trajectory.argtypes = [P, f64p, f64p, f64p]
         L.orc_sequence_cost.argtypes = [P, f64p, f64p]
         L.orc_sequence_cost.restype = C.c_double
@@ -241,9 +253,12 @@ def n_grad(wl) -> int:
     return nmlp + wl.n + 1
 
 
-def backward(wl, dL_dU, u=None, x0=None, eps=None, iteration: int = 0):
+def backward(wl, dL_dU, u=None, x0=None, eps=None, iteration: int = 0, S=None, rel=None):
     """dL/dtheta (layout [MLP blob | Q diag | wheelbase]) of a loss on the
-    controls of one iteration, given dL/dU; plus U, S, w of that iteration."""
+    controls of one iteration, given dL/dU; plus U, S, w of that iteration and
+    grad_abs = sum_k rel_k |a_k dJ_k/dtheta| (rel_k = 1 by default).  S
+    (optional): costs that form the weights in place of the oracle's own
+    rollout costs."""
     P = Problem(wl)
     if eps is None:
         eps = workload_noise(wl, iteration)
@@ -251,13 +266,33 @@ def backward(wl, dL_dU, u=None, x0=None, eps=None, iteration: int = 0):
     u = _d(wl.u0 if u is None else u).ravel()
     x0 = _d(wl.x0 if x0 is None else x0)
     grad = np.zeros(n_grad(wl))
+    grad_abs = np.zeros(n_grad(wl))
     U = np.empty(wl.T * wl.m)
-    S = np.empty(wl.K)
+    S_out = np.empty(wl.K)
     w = np.empty(wl.K)
-    rc = lib().orc_backward(P.ref, x0, u, eps, _d(dL_dU).ravel(), grad, U, S, w)
+    S_in = None if S is None else _d(S).ravel()
+    rel_in = None if rel is None else _d(rel).ravel()
+    rc = lib().orc_backward(P.ref, x0, u, eps, _d(dL_dU).ravel(), S_in, rel_in, grad, grad_abs, U,
+                            S_out, w)
     if rc == -1:
         raise ValueError("backward needs a bicycle model with RK4 and the track cost")
-    return {"grad": grad, "U": U.reshape(wl.T, wl.m), "S": S, "w": w, "status": rc}
+    return {"grad": grad, "grad_abs": grad_abs, "U": U.reshape(wl.T, wl.m), "S": S_out, "w": w,
+            "status": rc}
+
+
+def cost_condition(wl, eps=None, x0=None, u=None, iteration: int = 0):
+    """cond[K]: first-order sensitivity of each J_k to a relative perturbation
+    of every state component at every step (sum_t,i |dJ_k/dx_t,i| |x_t,i|)."""
+    P = Problem(wl)
+    if eps is None:
+        eps = workload_noise(wl, iteration)
+    eps = np.ascontiguousarray(eps, np.float32)
+    cond = np.empty(wl.K)
+    rc = lib().orc_cost_condition(P.ref, _d(wl.x0 if x0 is None else x0),
+                                  _d(wl.u0 if u is None else u).ravel(), eps, eps.shape[-1], cond)
+    if rc == -1:
+        raise ValueError("cost_condition needs a bicycle model with RK4 and the track cost")
+    return cond
 
 
 def with_theta(wl, theta):
@@ -346,4 +381,6 @@ def costmap(wl, px, py):
 
 __all__ = ["philox", "bm_tables", "noise", "workload_noise", "rollout_costs",
            "softmin_update", "mppi", "step", "deriv", "trajectory", "sequence_cost",
-           "running_cost", "terminal_cost", "spline", "costmap", "Problem"]
+           "running_cost", "terminal_cost", "spline", "costmap", "Problem", "n_grad",
+           "backward", "with_theta", "theta_of", "loss_and_controls",
+           "cost_condition"]

@@ -28,6 +28,7 @@ F_DEBUG = 1
 F_ACCURATE_TRIG = 2
 F_ROLLOUT_LANE = 4
 F_ROLLOUT_QUAD = 8
+F_REQUIRES_GRAD = 16
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
 PACKED_STATE, PACKED_CONTROLS, PACKED_SAMPLES, PACKED_NOISE = 0, 1, 2, 3
 
@@ -50,7 +51,8 @@ class Params(C.Structure):
                 ("num_segments", C.c_int32), ("knots", _fp), ("coef", _fp),
                 ("num_circles", C.c_int32), ("cx", _fp), ("cy", _fp), ("r2", _fp),
                 ("map_w", C.c_int32), ("map_h", C.c_int32), ("map_x0", C.c_float),
-                ("map_y0", C.c_float), ("map_res", C.c_float), ("costmap", _fp)]
+                ("map_y0", C.c_float), ("map_res", C.c_float), ("costmap", _fp),
+                ("checkpoint_every", C.c_int32)]
 
 
 EXPORTS = {
@@ -68,6 +70,8 @@ EXPORTS = {
     "mppi_get_controls": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mppi_get_debug": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "mppi_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mppi_theta_len": (C.c_int32, [C.c_void_p]),
+    "mppi_set_theta": (C.c_int, [C.c_void_p, _fp]),
     "mppi_destroy": (None, [C.c_void_p]),
     "mppi_last_error": (C.c_char_p, []),
     "mppi_noise": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,

@@ -27,7 +27,8 @@ def _fptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
-def _config(pb, debug: bool, accurate_trig: bool, rollout: str) -> _abi.Config:
+def _config(pb, debug: bool, accurate_trig: bool, rollout: str,
+            requires_grad: bool = False) -> _abi.Config:
     n, m = int(np.asarray(pb.x0).size), int(np.asarray(pb.sigma).size)
     cfg = _abi.Config()
     cfg.abi_version = _abi.ABI_VERSION
@@ -43,12 +44,14 @@ def _config(pb, debug: bool, accurate_trig: bool, rollout: str) -> _abi.Config:
     cfg.seed = int(pb.seed)
     cfg.instance = int(getattr(pb, "instance", 0))
     cfg.flags = ((_abi.F_DEBUG if debug else 0) | (_abi.F_ACCURATE_TRIG if accurate_trig else 0)
-                 | {"auto": 0, "lane": _abi.F_ROLLOUT_LANE, "quad": _abi.F_ROLLOUT_QUAD}[rollout])
+                 | {"auto": 0, "lane": _abi.F_ROLLOUT_LANE, "quad": _abi.F_ROLLOUT_QUAD}[rollout]
+                 | (_abi.F_REQUIRES_GRAD if requires_grad else 0))
     return cfg
 
 
-def _params(pb, keep: list) -> _abi.Params:
+def _params(pb, keep: list, checkpoint_every: int = 0) -> _abi.Params:
     p = _abi.Params()
+    p.checkpoint_every = int(checkpoint_every)
 
     def arr(a):
         a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
@@ -90,11 +93,15 @@ class Controller:
     `problem` is a workload description (model, integrator, cost, K, T, dt,
     lam, sigma, seed, instance, x0, u0, w and the model / cost arrays) or a
     sequence of them (a batch sharing model, integrator and cost kind).
+
+    requires_grad: keep what `backward` needs (state checkpoints every
+    `checkpoint_every` steps and the controls of the rollout).
     """
 
     def __init__(self, problem, device: str | torch.device = "cuda", debug: bool = False,
                  accurate_trig: bool = False, rollout: str = "auto",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, requires_grad: bool = False,
+                 checkpoint_every: int = 10):
         self.device = torch.device(device)
         self.batch = isinstance(problem, (list, tuple))
         probs: Sequence = list(problem) if self.batch else [problem]
@@ -104,8 +111,10 @@ class Controller:
         self.n, self.m = int(np.asarray(pb.x0).size), int(np.asarray(pb.sigma).size)
         self.K, self.T = int(pb.K), int(pb.T)
         self._keep: list = []
-        cfgs = (_abi.Config * self.n_inst)(*[_config(q, debug, accurate_trig, rollout) for q in probs])
-        params = (_abi.Params * self.n_inst)(*[_params(q, self._keep) for q in probs])
+        cfgs = (_abi.Config * self.n_inst)(
+            *[_config(q, debug, accurate_trig, rollout, requires_grad) for q in probs])
+        params = (_abi.Params * self.n_inst)(
+            *[_params(q, self._keep, checkpoint_every if requires_grad else 0) for q in probs])
         self.cfg, self._cfgs, self._params = cfgs[0], cfgs, params
         L = lib()
         if self.batch:
@@ -211,6 +220,39 @@ class Controller:
         U = self._empty(n)
         check(lib().mppi_get_controls(self.ctx, U.data_ptr()))
         return self._leave(U if self.batch else U.reshape(self.T, self.m))
+
+    # -- differentiation ----------------------------------------------------
+    def theta_len(self) -> int:
+        n = lib().mppi_theta_len(self.ctx)
+        if n == 0:
+            raise _abi.MPPIError(_abi.MPPI_ESTATE, lib().mppi_last_error().decode())
+        return int(n)
+
+    def theta(self) -> torch.Tensor:
+        """theta of the problem as created: [MLP blob | Q diag | wheelbase] (CPU)."""
+        pb = self.problems[0]
+        parts = [np.asarray(pb.mlp, np.float32).ravel()] if pb.model == "bicycle_mlp" else []
+        parts += [np.asarray(pb.w, np.float32)[:self.n], np.float32([pb.wheelbase])]
+        return torch.from_numpy(np.concatenate(parts))
+
+    def set_theta(self, theta) -> None:
+        """Replace the MLP weights, the Q diagonal and the wheelbase (waits for
+        the upload)."""
+        t = theta.detach().to("cpu", torch.float32) if torch.is_tensor(theta) else \
+            torch.as_tensor(np.asarray(theta, np.float32))
+        a = np.ascontiguousarray(t.numpy().ravel(), np.float32)
+        if a.size != self.theta_len():
+            raise ValueError(f"theta has {a.size} entries, the context needs {self.theta_len()}")
+        self._enter()
+        check(lib().mppi_set_theta(self.ctx, _fptr(a)))
+
+    def backward(self, dL_dU) -> torch.Tensor:
+        """dL/dtheta of a loss on the controls of the last update."""
+        g = self._dev(dL_dU, self.T * self.m)
+        out = self._empty(self.theta_len())
+        check(lib().mppi_backward(self.ctx, g.data_ptr(), out.data_ptr()))
+        self._g = g
+        return self._leave(out)
 
     # -- inspection ---------------------------------------------------------
     def noise(self) -> torch.Tensor:

@@ -1,0 +1,527 @@
+// Step (a9): gradient of a loss L(U) on the controls of one MPPI iteration
+// with respect to the dynamics parameters (MLP weights, wheelbase) and the
+// diagonal state weights Q of the tracking cost.
+//
+// With U = u + sum_k w_k eps_k, w = softmin(J / lambda) and u independent of
+// the parameters theta (Algorithm 1, Eq. for the update), G = dL/dU gives
+//   dL/dJ_k = a_k = -(w_k / lambda) (g_k - sum_i w_i g_i),  g_k = <G, eps_k>,
+//   dL/dtheta = sum_k a_k dJ_k/dtheta,
+// and dJ_k/dtheta comes from a reverse sweep of the costate mu_t = dJ_k/dx_t
+// through the discrete step (the four RK4 stages and the MLP residual) and
+// the tracking cost.  Kernels, in stream order:
+//   project:  g_k for blocks of 64 samples, with per-block sums of e_k
+//             (binary64: the normaliser eta), the count of samples of nonzero
+//             weight and the first sample of weight e_k = 1 (a minimiser);
+//   scan:     eta, the block offsets, and the weighted mean of g taken
+//             relative to the minimiser's g_ref: d = sum_i w_i (g_i - g_ref);
+//   compact:  the list (k, a_k) of samples with nonzero weight, in k order,
+//             a_k = -(w_k / lambda) ((g_k - g_ref) - d).  The shift keeps
+//             g_k - sum_i w_i g_i accurate when one sample holds almost all
+//             the weight (there the plain difference cancels completely);
+//   sweep:    per tile of 16 listed samples, segment by segment from the
+//             last: the states are rebuilt from the forward's checkpoints,
+//             then the costate runs backwards through them.  The MLP and its
+//             transposes run on the matrix cores (mlp.h); the weight
+//             gradients are outer products summed over the tile's samples
+//             (MFMA with the samples as the contraction index, operands
+//             transposed through LDS) and over time in registers.  Each tile
+//             writes its partial gradient;
+//   reduce:   the partial gradients of the tiles, summed in tile order.
+// Every sum has a fixed order, so the gradient is bitwise reproducible.
+// Samples of zero weight contribute exactly zero and are skipped.
+#include "dynamics.h"
+#include "mlp.h"
+
+namespace mppi {
+
+constexpr int kTileS = 16;           // samples per sweep tile (one wave)
+constexpr int kProjectBlock = 256;   // 64 samples x 4 row groups
+constexpr int kProjectSamples = 64;
+
+struct BwdBlock {
+  double sum_e;
+  int count;
+  int kmin;  // first sample of the block with e_k = 1, or INT_MAX
+};
+struct BwdMeta {
+  double eta;
+  float gref, dbar;
+  int count;
+};
+constexpr int kScanBlock = 1024;
+struct BwdItem {
+  int k;
+  float a;
+};
+
+__global__ __launch_bounds__(kProjectBlock) void adjoint_project_kernel(
+    const float* __restrict__ G, const float* __restrict__ eps, int64_t ldk, int K, int TM,
+    const float* __restrict__ e, float* __restrict__ gk, BwdBlock* __restrict__ part) {
+  __shared__ float red[kProjectBlock];
+  const int s = threadIdx.x % kProjectSamples, rg = threadIdx.x / kProjectSamples;
+  const int k = blockIdx.x * kProjectSamples + s;
+  float acc = 0.0f;
+  if (k < K)
+    for (int r = rg; r < TM; r += 4) acc += G[r] * eps[static_cast<int64_t>(r) * ldk + k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (rg == 0) {
+    const float g = (red[s] + red[s + 64]) + (red[s + 128] + red[s + 192]);
+    const float ek = k < K ? e[k] : 0.0f;
+    if (k < K) gk[k] = g;
+    // per-block sums over the 64 samples (one wave, fixed shuffle tree)
+    int cnt = ek > 0.0f ? 1 : 0;
+    int kmin = ek == 1.0f ? k : 0x7FFFFFFF;
+    double de = static_cast<double>(ek);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      cnt += __shfl_xor(cnt, o, kWave);
+      kmin = min(kmin, __shfl_xor(kmin, o, kWave));
+      de += __shfl_xor(de, o, kWave);
+    }
+    if (s == 0) part[blockIdx.x] = BwdBlock{de, cnt, kmin};
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void adjoint_scan_kernel(
+    const BwdBlock* __restrict__ part, int nb, const float* __restrict__ e,
+    const float* __restrict__ gk, int K, int* __restrict__ offs, BwdMeta* __restrict__ meta) {
+  __shared__ double s_eta;
+  __shared__ float s_gref;
+  __shared__ float red[kScanBlock / kWave];
+  if (threadIdx.x == 0) {
+    double eta = 0.0;
+    int count = 0, kmin = 0x7FFFFFFF;
+    for (int b = 0; b < nb; ++b) {
+      const BwdBlock q = part[b];
+      offs[b] = count;
+      count += q.count;
+      eta += q.sum_e;
+      kmin = min(kmin, q.kmin);
+    }
+    const bool ok = eta > 0.0 && kmin < K;
+    s_eta = ok ? eta : 0.0;
+    s_gref = ok ? gk[kmin] : 0.0f;
+    meta->eta = s_eta;
+    meta->gref = s_gref;
+    meta->count = ok ? count : 0;
+  }
+  __syncthreads();
+  // d = sum_i e_i (g_i - g_ref) / eta, fixed partition and tree
+  const float gref = s_gref;
+  float acc = 0.0f;
+  for (int k = threadIdx.x; k < K; k += kScanBlock) {
+    const float ek = e[k];
+    if (ek > 0.0f) acc += ek * (gk[k] - gref);
+  }
+  acc = wave_sum(acc);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float tot = red[0];
+    for (int i = 1; i < kScanBlock / kWave; ++i) tot += red[i];
+    meta->dbar = s_eta > 0.0 ? static_cast<float>(static_cast<double>(tot) / s_eta) : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(kProjectSamples) void adjoint_compact_kernel(
+    const float* __restrict__ e, const float* __restrict__ gk, int K, float inv_lambda,
+    const int* __restrict__ offs, const BwdMeta* __restrict__ meta, BwdItem* __restrict__ list) {
+  const int lane = threadIdx.x;
+  const int k = blockIdx.x * kProjectSamples + lane;
+  const float ek = k < K ? e[k] : 0.0f;
+  const bool nz = ek > 0.0f && meta->eta > 0.0;
+  const uint64_t mask = __ballot(nz);
+  if (!nz) return;
+  const int rank = __popcll(mask & ((uint64_t{1} << lane) - 1u));
+  const float w = static_cast<float>(static_cast<double>(ek) / meta->eta);
+  const float a = -(w * inv_lambda) * ((gk[k] - meta->gref) - meta->dbar);
+  list[offs[blockIdx.x] + rank] = BwdItem{k, a};
+}
+
+// dx += (df/dx)^T c and dL += (df/d wheelbase)^T c for the bicycle derivative
+// f = (s cos psi, s sin psi, s tan(delta) / L, a, delta_rate) at x.
+template <bool FAST>
+__device__ __forceinline__ void bicycle_vjp(const float* x, const float* c, float inv_l,
+                                            float* dx, float& dl) {
+  float sn, cs, sd, cd;
+  if constexpr (FAST) {
+    sn = __sinf(x[2]);
+    cs = __cosf(x[2]);
+    sd = __sinf(x[4]);
+    cd = __cosf(x[4]);
+  } else {
+    sincosf(x[2], &sn, &cs);
+    sincosf(x[4], &sd, &cd);
+  }
+  const float rc = FAST ? __builtin_amdgcn_rcpf(cd) : 1.0f / cd;
+  const float tn = FAST ? sd * rc : tanf(x[4]);
+  const float s = x[3];
+  dx[2] += s * (cs * c[1] - sn * c[0]);
+  dx[3] += cs * c[0] + sn * c[1] + tn * inv_l * c[2];
+  dx[4] += s * (1.0f + tn * tn) * inv_l * c[2];
+  dl -= s * tn * inv_l * inv_l * c[2];
+}
+
+template <int MT>
+struct SweepLds {
+  static constexpr int P = 64 * MT + 16;  // transposition row stride (16 mod 32: no bank conflicts)
+  static constexpr int kFwd = MT ? mlp::Pack<MT>::kFwdRows * kWave : 0;
+  static constexpr int kBwd = MT ? mlp::Pack<MT>::kBwdRows * kWave : 0;
+  static constexpr int kTb = MT ? kTileS * P : 0;
+  static size_t bytes(int c) {
+    return sizeof(float) * (kFwd + kBwd + kTb + kTileS * ((c + 1) * 5 + c * 2));
+  }
+};
+
+// Sum over the 16 lanes of a lane group (fixed xor tree).
+__device__ __forceinline__ float group_sum(float v) {
+  v += __shfl_xor(v, 8, kWave);
+  v += __shfl_xor(v, 4, kWave);
+  v += __shfl_xor(v, 2, kWave);
+  v += __shfl_xor(v, 1, kWave);
+  return v;
+}
+
+template <int MT, bool FAST>
+__global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
+    DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
+    const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
+    const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp) {
+  using Model = Bicycle<FAST>;
+  using L = SweepLds<MT>;
+  using f4 = mlp::f4;
+  constexpr int N = 5, M = 2, H = 16 * MT;
+  const int base = blockIdx.x * kTileS;
+  if (base >= meta->count) return;  // wave-uniform
+  extern __shared__ float4 lds4[];
+  float* lds = reinterpret_cast<float*>(lds4);
+  const int lane = threadIdx.x, n = lane % kTileS, g = lane / kTileS;
+  if constexpr (MT > 0) {
+    const float4* src_f = reinterpret_cast<const float4*>(p.mlp);
+    const float4* src_b = reinterpret_cast<const float4*>(p.mlp_bwd);
+    for (int i = lane; i < L::kFwd / 4; i += kWave) lds4[i] = src_f[i];
+    for (int i = lane; i < L::kBwd / 4; i += kWave) lds4[L::kFwd / 4 + i] = src_b[i];
+  }
+  const mlp::PackView<MT ? MT : 1> WF{lds + lane};
+  const mlp::PackView<MT ? MT : 1> WB{lds + L::kFwd + lane};
+  float* tb = lds + L::kFwd + L::kBwd;
+  float* xs = tb + L::kTb + n * ((c + 1) * N);                     // [c+1][5] of sample n
+  float* vs = tb + L::kTb + kTileS * (c + 1) * N + n * (c * M);    // [c][2] of sample n
+  __syncthreads();
+
+  const int idx = base + n;
+  const bool valid = idx < meta->count;
+  const BwdItem item = list[valid ? idx : base];
+  const int k = item.k;
+  const float a = valid ? item.a : 0.0f;  // padding lanes rebuild a listed sample, weight 0
+  const float* e = eps + k;
+
+  // accumulators: weight gradients (D layout), biases, Q, wheelbase
+  f4 dW1[MT ? MT : 1], dW2[MT ? MT : 1][MT ? MT : 1], dW3[MT ? MT : 1];
+  f4 db1[MT ? MT : 1], db2[MT ? MT : 1];
+  float db3[N], gQ[N], gL = 0.0f, mu[N];
+  const f4 zero4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int t = 0; t < (MT ? MT : 1); ++t) {
+    dW1[t] = dW3[t] = db1[t] = db2[t] = zero4;
+#pragma unroll
+    for (int q = 0; q < (MT ? MT : 1); ++q) dW2[t][q] = zero4;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) { db3[i] = 0.0f; gQ[i] = 0.0f; mu[i] = 0.0f; }
+
+  const int nseg = (T + c - 1) / c;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int t0 = seg * c, len = min(c, T - t0);
+    // rebuild x_{t0} .. x_{t0+len} from the checkpoint
+    float x[N], comp[N];
+    const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + k;
+#pragma unroll
+    for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
+    comp[0] = ck[5 * ldk];
+    comp[1] = ck[6 * ldk];
+    for (int j = 0; j < len; ++j) {
+      const int t = t0 + j;
+      float v[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) v[q] = u[t * M + q] + e[static_cast<int64_t>(t * M + q) * ldk];
+      if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) xs[j * N + i] = x[i];
+#pragma unroll
+        for (int q = 0; q < M; ++q) vs[j * M + q] = v[q];
+      }
+      if constexpr (MT > 0) {
+        float res[N];
+        mlp::residual<MT>(WF, x, v, g, n, res);
+        step<Model, kRK4>(x, v, comp, p, res);
+      } else {
+        step<Model, kRK4>(x, v, comp, p);
+      }
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) xs[len * N + i] = x[i];
+    }
+    __syncthreads();
+    if (seg == nseg - 1) {  // terminal cost w16 sum_i Q_i (x_T - r_T)^2
+      const float* r = p.ref + static_cast<int64_t>(T) * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const float d = xs[len * N + i] - r[i];
+        mu[i] = a * 2.0f * p.w[16] * p.w[i] * d;
+        gQ[i] += a * p.w[16] * d * d;
+      }
+    }
+    for (int j = len - 1; j >= 0; --j) {
+      const int t = t0 + j;
+      // running cost at x_{t+1}
+      const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const float d = xs[(j + 1) * N + i] - r[i];
+        mu[i] += a * 2.0f * p.w[i] * d;
+        gQ[i] += a * d * d;
+      }
+      float xt[N], v[M];
+#pragma unroll
+      for (int i = 0; i < N; ++i) xt[i] = xs[j * N + i];
+#pragma unroll
+      for (int q = 0; q < M; ++q) v[q] = vs[j * M + q];
+      // RK4 stages of the step from x_t, then their transposes in reverse
+      float k1[N], xa[N], k2[N], xb[N], k3[N], xc[N];
+      Model::deriv(xt, v, k1, p);
+#pragma unroll
+      for (int i = 0; i < N; ++i) xa[i] = xt[i] + p.half_dt * k1[i];
+      Model::deriv(xa, v, k2, p);
+#pragma unroll
+      for (int i = 0; i < N; ++i) xb[i] = xt[i] + p.half_dt * k2[i];
+      Model::deriv(xb, v, k3, p);
+#pragma unroll
+      for (int i = 0; i < N; ++i) xc[i] = xt[i] + p.dt * k3[i];
+      float mu0[N], cst[N], cx[N];
+      const float third_dt = 2.0f * p.sixth_dt;
+#pragma unroll
+      for (int i = 0; i < N; ++i) { mu0[i] = mu[i]; cst[i] = p.sixth_dt * mu[i]; cx[i] = 0.0f; }
+      bicycle_vjp<FAST>(xc, cst, p.inv_wheelbase, cx, gL);  // k4 = f(xc), xc = x + dt k3
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        mu0[i] += cx[i];
+        cst[i] = third_dt * mu[i] + p.dt * cx[i];
+        cx[i] = 0.0f;
+      }
+      bicycle_vjp<FAST>(xb, cst, p.inv_wheelbase, cx, gL);  // k3 = f(xb), xb = x + dt/2 k2
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        mu0[i] += cx[i];
+        cst[i] = third_dt * mu[i] + p.half_dt * cx[i];
+        cx[i] = 0.0f;
+      }
+      bicycle_vjp<FAST>(xa, cst, p.inv_wheelbase, cx, gL);  // k2 = f(xa), xa = x + dt/2 k1
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        mu0[i] += cx[i];
+        cst[i] = p.sixth_dt * mu[i] + p.half_dt * cx[i];
+        cx[i] = 0.0f;
+      }
+      bicycle_vjp<FAST>(xt, cst, p.inv_wheelbase, cx, gL);  // k1 = f(x)
+#pragma unroll
+      for (int i = 0; i < N; ++i) mu0[i] += cx[i];
+
+      if constexpr (MT > 0) {
+        // residual dt g(z): c = dt mu_{t+1}
+        f4 h1[MT], h2[MT], da1[MT], da2[MT], dz;
+        mlp::hidden<MT>(WF, xt, v, g, h1, h2);
+        float cg[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) cg[i] = p.dt * mu[i];
+        mlp::backward<MT>(WB, cg, g, h1, h2, da1, da2, dz);
+        float dzs[N];
+        mlp::broadcast5(dz, n, dzs);
+#pragma unroll
+        for (int i = 0; i < N; ++i) mu0[i] += dzs[i];
+#pragma unroll
+        for (int t2 = 0; t2 < MT; ++t2) { db1[t2] += da1[t2]; db2[t2] += da2[t2]; }
+#pragma unroll
+        for (int i = 0; i < N; ++i) db3[i] += cg[i];
+        // weight gradients: transpose the tile's activations through LDS so
+        // the samples become the MFMA contraction index
+        float* row = tb + n * L::P;
+#pragma unroll
+        for (int t2 = 0; t2 < MT; ++t2) {
+          *reinterpret_cast<f4*>(row + 16 * t2 + 4 * g) = h1[t2];
+          *reinterpret_cast<f4*>(row + H + 16 * t2 + 4 * g) = h2[t2];
+          *reinterpret_cast<f4*>(row + 2 * H + 16 * t2 + 4 * g) = da1[t2];
+          *reinterpret_cast<f4*>(row + 3 * H + 16 * t2 + 4 * g) = da2[t2];
+        }
+        // rows 4H .. 4H+7: z = (x, v, 0); rows 4H+8 .. 4H+15: c (5) and zeros
+        const f4 zc = g == 0 ? f4{xt[0], xt[1], xt[2], xt[3]}
+                    : g == 1 ? f4{xt[4], v[0], v[1], 0.0f}
+                    : g == 2 ? f4{cg[0], cg[1], cg[2], cg[3]}
+                             : f4{cg[4], 0.0f, 0.0f, 0.0f};
+        *reinterpret_cast<f4*>(row + 4 * H + 4 * g) = zc;
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float* tq = tb + (4 * s + g) * L::P;
+          float ah[MT], ad2[MT], ad1[MT], bh2[MT];
+#pragma unroll
+          for (int t2 = 0; t2 < MT; ++t2) {
+            ah[t2] = tq[16 * t2 + n];
+            bh2[t2] = tq[H + 16 * t2 + n];
+            ad1[t2] = tq[2 * H + 16 * t2 + n];
+            ad2[t2] = tq[3 * H + 16 * t2 + n];
+          }
+          const float bz = tq[4 * H + n];
+          const float ac = n < 8 ? tq[4 * H + 8 + n] : 0.0f;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int nt = 0; nt < MT; ++nt) dW2[mt][nt] = mlp::mfma(ad2[mt], ah[nt], dW2[mt][nt]);
+            dW1[mt] = mlp::mfma(ad1[mt], bz, dW1[mt]);
+            dW3[mt] = mlp::mfma(ac, bh2[mt], dW3[mt]);
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) mu[i] = mu0[i];
+    }
+    __syncthreads();  // xs / vs are rewritten by the next segment
+  }
+
+  // this tile's partial gradient: [W1 | b1 | W2 | b2 | W3 | b3 | Q | wheelbase]
+  float* out = partial + static_cast<int64_t>(blockIdx.x) * ngp;
+  const int offQ = MT ? 14 * H + H * H + 5 : 0;
+  if constexpr (MT > 0) {
+    const int oB1 = 7 * H, oW2 = 8 * H, oB2 = 8 * H + H * H, oW3 = 9 * H + H * H,
+              oB3 = 14 * H + H * H;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * mt + 4 * g + i;
+        if (n < 7) out[r * 7 + n] = dW1[mt][i];
+#pragma unroll
+        for (int nt = 0; nt < MT; ++nt) out[oW2 + r * H + 16 * nt + n] = dW2[mt][nt][i];
+        const int o = 4 * g + i;
+        if (o < 5) out[oW3 + o * H + 16 * mt + n] = dW3[mt][i];
+        const float s1 = group_sum(db1[mt][i]);
+        const float s2 = group_sum(db2[mt][i]);
+        if (n == 0) { out[oB1 + r] = s1; out[oB2 + r] = s2; }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const float s3 = group_sum(db3[i]);
+      if (lane == 0) out[oB3 + i] = s3;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const float sq = group_sum(gQ[i]);
+    if (lane == 0) out[offQ + i] = sq;
+  }
+  const float sl = group_sum(gL);
+  if (lane == 0) out[offQ + N] = sl;
+}
+
+__global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float* __restrict__ partial,
+                                                             int64_t ngp, int ngrad,
+                                                             const BwdMeta* __restrict__ meta,
+                                                             float* __restrict__ grad) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= ngrad) return;
+  const int tiles = (meta->count + kTileS - 1) / kTileS;
+  float s = 0.0f;
+  for (int w = 0; w < tiles; ++w) s += partial[static_cast<int64_t>(w) * ngp + j];
+  grad[j] = s;
+}
+
+// ---- host side ----------------------------------------------------------------
+int adjoint_grad_len(uint32_t dynamics, int hidden) {
+  const int H = dynamics == MPPI_DYN_BICYCLE_MLP ? hidden : 0;
+  return (H ? 14 * H + H * H + 5 : 0) + 6;
+}
+
+AdjointScratch adjoint_scratch_layout(int K, int ngrad) {
+  AdjointScratch s{};
+  const int nb = (K + kProjectSamples - 1) / kProjectSamples;
+  const int tiles = (K + kTileS - 1) / kTileS;
+  s.ngp = (ngrad + 63) / 64 * 64;
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off = (off + b + 255) / 256 * 256; return o; };
+  s.gk = take(sizeof(float) * K);
+  s.part = take(sizeof(BwdBlock) * nb);
+  s.offs = take(sizeof(int) * nb);
+  s.meta = take(sizeof(BwdMeta));
+  s.list = take(sizeof(BwdItem) * K);
+  s.partial = take(sizeof(float) * static_cast<size_t>(tiles) * s.ngp);
+  s.total = off;
+  return s;
+}
+
+size_t adjoint_lds_bytes(int hidden, int ckpt_every) {
+  switch (hidden) {
+    case 0: return SweepLds<0>::bytes(ckpt_every);
+    case 16: return SweepLds<1>::bytes(ckpt_every);
+    case 32: return SweepLds<2>::bytes(ckpt_every);
+    case 64: return SweepLds<4>::bytes(ckpt_every);
+    default: return 0;
+  }
+}
+
+namespace {
+using SweepFn = void (*)(DevParams, const float*, const float*, int64_t, int, const float*, int,
+                         const BwdItem*, const BwdMeta*, float*, int64_t);
+template <int MT>
+SweepFn pick_sweep(bool accurate) {
+  return accurate ? adjoint_sweep_kernel<MT, false> : adjoint_sweep_kernel<MT, true>;
+}
+}  // namespace
+
+hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
+                          const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
+                          const float* d_e, float lambda, const float* d_ckpt, int ckpt_every,
+                          char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
+                          hipStream_t stream) {
+  SweepFn fn = nullptr;
+  switch (hidden) {
+    case 0: fn = pick_sweep<0>(accurate_trig); break;
+    case 16: fn = pick_sweep<1>(accurate_trig); break;
+    case 32: fn = pick_sweep<2>(accurate_trig); break;
+    case 64: fn = pick_sweep<4>(accurate_trig); break;
+    default: return hipErrorInvalidValue;
+  }
+  const size_t lds = adjoint_lds_bytes(hidden, ckpt_every);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  float* gk = reinterpret_cast<float*>(d_scratch + s.gk);
+  BwdBlock* part = reinterpret_cast<BwdBlock*>(d_scratch + s.part);
+  int* offs = reinterpret_cast<int*>(d_scratch + s.offs);
+  BwdMeta* meta = reinterpret_cast<BwdMeta*>(d_scratch + s.meta);
+  BwdItem* list = reinterpret_cast<BwdItem*>(d_scratch + s.list);
+  float* partial = reinterpret_cast<float*>(d_scratch + s.partial);
+  const int nb = (K + kProjectSamples - 1) / kProjectSamples;
+  const int TM = T * 2;
+  hipLaunchKernelGGL(adjoint_project_kernel, dim3(nb), dim3(kProjectBlock), 0, stream, d_G, d_eps,
+                     ldk, K, TM, d_e, gk, part);
+  hipLaunchKernelGGL(adjoint_scan_kernel, dim3(1), dim3(kScanBlock), 0, stream, part, nb, d_e, gk,
+                     K, offs, meta);
+  hipLaunchKernelGGL(adjoint_compact_kernel, dim3(nb), dim3(kProjectSamples), 0, stream, d_e, gk,
+                     K, static_cast<float>(1.0 / static_cast<double>(lambda)), offs, meta, list);
+  const int tiles = (K + kTileS - 1) / kTileS;
+  hipLaunchKernelGGL(fn, dim3(tiles), dim3(kWave), lds, stream, p, d_u, d_eps, ldk, T, d_ckpt,
+                     ckpt_every, list, meta, partial, s.ngp);
+  hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((ngrad + 255) / 256), dim3(256), 0, stream,
+                     partial, s.ngp, ngrad, meta, d_grad);
+  return hipGetLastError();
+}
+
+}  // namespace mppi

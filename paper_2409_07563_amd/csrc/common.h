@@ -21,9 +21,10 @@ struct DevParams {
   // quadrotor
   float inv_mass, gravity;
   float inertia[3], inv_inertia[3];
-  // MLP residual
+  // MLP residual: operand packs of the MFMA tiles (mlp.h)
   int mlp_hidden;
-  const float* mlp;
+  const float* mlp;      // forward pack
+  const float* mlp_bwd;  // transposed-weight pack of the adjoint
   // cost
   float w[32];
   const float* ref;
@@ -116,6 +117,27 @@ hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t l
 hipError_t launch_set_iteration(DevState* d_state, uint32_t iteration, hipStream_t stream);
 hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState* d_state,
                           float* d_w, hipStream_t stream);
+
+// MLP residual dynamics and the checkpointing forward (rollout_tiles.hip)
+bool rollout_tiles_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int hidden);
+hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                                bool accurate_trig, const DevParams& p, const float* d_x0,
+                                const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
+                                float* d_S, float* d_ckpt, int ckpt_every, hipStream_t stream);
+
+// The adjoint (adjoint.hip).  Scratch: byte offsets inside one device region.
+struct AdjointScratch {
+  size_t gk, part, offs, meta, list, partial, total;
+  int64_t ngp;  // floats per partial-gradient row
+};
+int adjoint_grad_len(uint32_t dynamics, int hidden);
+AdjointScratch adjoint_scratch_layout(int K, int ngrad);
+size_t adjoint_lds_bytes(int hidden, int ckpt_every);
+hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
+                          const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
+                          const float* d_e, float lambda, const float* d_ckpt, int ckpt_every,
+                          char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
+                          hipStream_t stream);
 
 hipError_t launch_batch_noise(const BatchPlan& b, hipStream_t stream);
 hipError_t launch_batch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,

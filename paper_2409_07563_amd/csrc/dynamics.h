@@ -100,8 +100,11 @@ __device__ __forceinline__ void advance(float* x, const float* x0, const float* 
   }
 }
 
+// One step.  res (optional): a residual r added as dt * r to the increment
+// (the MLP residual dynamics evaluate it on the pre-step state).
 template <class Model, int INTEG>
-__device__ __forceinline__ void step(float* x, const float* v, float* comp, const DevParams& p) {
+__device__ __forceinline__ void step(float* x, const float* v, float* comp, const DevParams& p,
+                                     const float* res = nullptr) {
   constexpr int N = Model::N;
   float x0[N], inc[N];
 #pragma unroll
@@ -125,6 +128,10 @@ __device__ __forceinline__ void step(float* x, const float* v, float* comp, cons
     Model::deriv(xs, v, k, p);
 #pragma unroll
     for (int i = 0; i < N; ++i) inc[i] = p.sixth_dt * (acc[i] + k[i]);
+  }
+  if (res) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) inc[i] += p.dt * res[i];
   }
   advance<Model>(x, x0, inc, comp);
   Model::post_step(x, p);

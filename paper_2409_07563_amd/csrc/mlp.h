@@ -1,0 +1,222 @@
+// The MLP residual g(z) = W3 tanh(W2 tanh(W1 z + b1) + b2) + b3 of the
+// learned dynamics, z = (x, v) in R^7, H hidden units (H = 16 MT), evaluated
+// for 16 samples at a time on the matrix cores with
+// v_mfma_f32_16x16x4_f32 (binary32 operands and accumulation).
+//
+// Lane layout of a wave (64 lanes): n = lane % 16 is the sample of the tile,
+// g = lane / 16 the lane's group.  For D[16][16] += A[16][4] B[4][16] a lane
+// holds A[n][g], B[g][n] and D[4g + i][n] (i = 0..3).  Activations therefore
+// live in the D layout: lane (g, n) holds hidden rows 16t + 4g + i of sample
+// n in register (t, i).  The next layer consumes them without any data
+// movement by contracting over a permuted hidden index: its K-step (t, i)
+// takes row 16t + 4g + i in lane group g, and the weight operand is packed to
+// match (A[m][g] = W[16 mt + m][16 t + 4 g + i]).
+//
+// Operand packs (host-built at context creation, one row of 64 lane values
+// per MFMA operand, read as pack[row * 64 + lane]):
+//   forward:  W1 (M-tile t, K-step j: inputs 4j + g, input 7 is padding),
+//             W2 (t, K-step (tt, i)), W3 (K-step (tt, i), outputs 0..4 of 16),
+//             then the biases in the D layout: b1 (t, i), b2 (t, i), b3 (i).
+//   adjoint:  W3^T (t, K-step j: outputs 4j + g), W2^T (t, (tt, i)),
+//             W1^T (K-step (tt, i), inputs 0..6 of 16).
+#pragma once
+
+#include "common.h"
+
+namespace mppi {
+namespace mlp {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int MT>
+struct Pack {
+  // forward rows
+  static constexpr int kW1 = 0;
+  static constexpr int kW2 = kW1 + 2 * MT;
+  static constexpr int kW3 = kW2 + 4 * MT * MT;
+  static constexpr int kB1 = kW3 + 4 * MT;
+  static constexpr int kB2 = kB1 + 4 * MT;
+  static constexpr int kB3 = kB2 + 4 * MT;
+  static constexpr int kFwdRows = kB3 + 4;
+  // adjoint rows
+  static constexpr int kW3t = 0;
+  static constexpr int kW2t = kW3t + 2 * MT;
+  static constexpr int kW1t = kW2t + 4 * MT * MT;
+  static constexpr int kBwdRows = kW1t + 4 * MT;
+};
+
+// The forward operands of one lane, register resident.
+template <int MT>
+struct Weights {
+  float w1_[MT][2];
+  float w2_[MT][MT][4];
+  float w3_[MT][4];
+  f4 b1_[MT], b2_[MT], b3_;
+
+  __device__ __forceinline__ void load(const float* __restrict__ pack, int lane) {
+    using P = Pack<MT>;
+    auto at = [&](int row) { return pack[row * kWave + lane]; };
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      w1_[t][0] = at(P::kW1 + 2 * t);
+      w1_[t][1] = at(P::kW1 + 2 * t + 1);
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w2_[t][tt][i] = at(P::kW2 + (t * MT + tt) * 4 + i);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        w3_[t][i] = at(P::kW3 + 4 * t + i);
+        b1_[t][i] = at(P::kB1 + 4 * t + i);
+        b2_[t][i] = at(P::kB2 + 4 * t + i);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b3_[i] = at(P::kB3 + i);
+  }
+  __device__ __forceinline__ float w1(int t, int j) const { return w1_[t][j]; }
+  __device__ __forceinline__ float w2(int t, int tt, int i) const { return w2_[t][tt][i]; }
+  __device__ __forceinline__ float w3(int tt, int i) const { return w3_[tt][i]; }
+  __device__ __forceinline__ f4 b1(int t) const { return b1_[t]; }
+  __device__ __forceinline__ f4 b2(int t) const { return b2_[t]; }
+  __device__ __forceinline__ f4 b3() const { return b3_; }
+};
+
+// The same operands read from a pack in memory (LDS) at each use.
+template <int MT>
+struct PackView {
+  const float* pk;  // points at pack[0 * 64 + lane]
+  using P = Pack<MT>;
+  __device__ __forceinline__ float at(int row) const { return pk[row * kWave]; }
+  __device__ __forceinline__ f4 at4(int row) const {
+    return f4{at(row), at(row + 1), at(row + 2), at(row + 3)};
+  }
+  __device__ __forceinline__ float w1(int t, int j) const { return at(P::kW1 + 2 * t + j); }
+  __device__ __forceinline__ float w2(int t, int tt, int i) const {
+    return at(P::kW2 + (t * MT + tt) * 4 + i);
+  }
+  __device__ __forceinline__ float w3(int tt, int i) const { return at(P::kW3 + 4 * tt + i); }
+  __device__ __forceinline__ f4 b1(int t) const { return at4(P::kB1 + 4 * t); }
+  __device__ __forceinline__ f4 b2(int t) const { return at4(P::kB2 + 4 * t); }
+  __device__ __forceinline__ f4 b3() const { return at4(P::kB3); }
+  // adjoint pack (a separate array: pk points at its lane)
+  __device__ __forceinline__ float w3t(int t, int j) const { return at(P::kW3t + 2 * t + j); }
+  __device__ __forceinline__ float w2t(int t, int tt, int i) const {
+    return at(P::kW2t + (t * MT + tt) * 4 + i);
+  }
+  __device__ __forceinline__ float w1t(int tt, int i) const { return at(P::kW1t + 4 * tt + i); }
+};
+
+__device__ __forceinline__ f4 tanh4(f4 a) {
+  return f4{tanhf(a[0]), tanhf(a[1]), tanhf(a[2]), tanhf(a[3])};
+}
+
+// The B operand of an input-side K-step: component 4j + g of (x0..x4, v0, v1, 0).
+__device__ __forceinline__ float input_operand(const float* x, const float* v, int g, int j) {
+  if (j == 0) return g == 0 ? x[0] : g == 1 ? x[1] : g == 2 ? x[2] : x[3];
+  return g == 0 ? x[4] : g == 1 ? v[0] : g == 2 ? v[1] : 0.0f;
+}
+
+// Hidden activations h1 = tanh(W1 z + b1), h2 = tanh(W2 h1 + b2) of the
+// wave's 16 samples, in the D layout.
+template <int MT, class WS>
+__device__ __forceinline__ void hidden(const WS& W, const float* x, const float* v, int g,
+                                       f4 (&h1)[MT], f4 (&h2)[MT]) {
+  const float z0 = input_operand(x, v, g, 0), z1 = input_operand(x, v, g, 1);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) h1[t] = tanh4(mfma(W.w1(t, 1), z1, mfma(W.w1(t, 0), z0, W.b1(t))));
+  f4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = W.b2(t);
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int t = 0; t < MT; ++t) acc[t] = mfma(W.w2(t, tt, i), h1[tt][i], acc[t]);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) h2[t] = tanh4(acc[t]);
+}
+
+// Output rows 4g + i of W3 h2 + b3 (rows >= 5 are padding), one accumulator
+// per K-tile, combined in a fixed order.
+template <int MT, class WS>
+__device__ __forceinline__ f4 output(const WS& W, const f4 (&h2)[MT]) {
+  f4 acc[MT];
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt) {
+    acc[tt] = tt == 0 ? W.b3() : f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[tt] = mfma(W.w3(tt, i), h2[tt][i], acc[tt]);
+  }
+  f4 r = acc[0];
+#pragma unroll
+  for (int tt = 1; tt < MT; ++tt) r += acc[tt];
+  return r;
+}
+
+// The five output rows of the lane's own sample n, gathered from the lanes
+// that hold them (rows 0..3: group 0, row 4: group 1).
+__device__ __forceinline__ void broadcast5(f4 d, int n, float* out) {
+  out[0] = __shfl(d[0], n, kWave);
+  out[1] = __shfl(d[1], n, kWave);
+  out[2] = __shfl(d[2], n, kWave);
+  out[3] = __shfl(d[3], n, kWave);
+  out[4] = __shfl(d[0], 16 + n, kWave);
+}
+
+// g(x, v) for the lane's sample (every group gets all five components).
+template <int MT, class WS>
+__device__ __forceinline__ void residual(const WS& W, const float* x, const float* v, int g,
+                                         int n, float* res) {
+  f4 h1[MT], h2[MT];
+  hidden<MT>(W, x, v, g, h1, h2);
+  broadcast5(output<MT>(W, h2), n, res);
+}
+
+// Reverse mode through g for the tile: given c = dL/dg (five components per
+// lane, for the lane's sample) and the activations of the forward,
+//   da2 = (W3^T c) * (1 - h2^2),  da1 = (W2^T da2) * (1 - h1^2),
+//   dz  = W1^T da1  (rows 4g + i of 16; rows 0..6 are z's components),
+// all in the D layout.
+template <int MT>
+__device__ __forceinline__ void backward(const PackView<MT>& B, const float* c, int g,
+                                         const f4 (&h1)[MT], const f4 (&h2)[MT], f4 (&da1)[MT],
+                                         f4 (&da2)[MT], f4& dz) {
+  const f4 one{1.0f, 1.0f, 1.0f, 1.0f};
+  const float c0 = g == 0 ? c[0] : g == 1 ? c[1] : g == 2 ? c[2] : c[3];
+  const float c1 = g == 0 ? c[4] : 0.0f;
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const f4 a = mfma(B.w3t(t, 1), c1, mfma(B.w3t(t, 0), c0, f4{0.0f, 0.0f, 0.0f, 0.0f}));
+    da2[t] = a * (one - h2[t] * h2[t]);
+  }
+  f4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int t = 0; t < MT; ++t) acc[t] = mfma(B.w2t(t, tt, i), da2[tt][i], acc[t]);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) da1[t] = acc[t] * (one - h1[t] * h1[t]);
+  f4 zacc[MT];
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt) {
+    zacc[tt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) zacc[tt] = mfma(B.w1t(tt, i), da1[tt][i], zacc[tt]);
+  }
+  dz = zacc[0];
+#pragma unroll
+  for (int tt = 1; tt < MT; ++tt) dz += zacc[tt];
+}
+
+}  // namespace mlp
+}  // namespace mppi

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "common.h"
+#include "mlp.h"
 
 using namespace mppi;
 
@@ -59,9 +60,71 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   int64_t ldk;  // noise row stride (K rounded up to a wave)
   size_t eps, e;
-  size_t ref, stage, costmap, mlp;
+  size_t ref, stage, costmap, mlp, mlp_bwd;
+  // MPPI_F_REQUIRES_GRAD: checkpoints [nseg][7][ldk], the rollout's controls,
+  // the adjoint's scratch
+  size_t ckpt, u_roll, adj;
+  AdjointScratch adj_layout;
   size_t total;
 };
+
+int mlp_hidden_of(const mppi_config* c, const mppi_params* p) {
+  return c->dynamics == MPPI_DYN_BICYCLE_MLP ? p->mlp_hidden : 0;
+}
+int pack_rows(int hidden, bool bwd) {
+  switch (hidden) {
+    case 16: return bwd ? mlp::Pack<1>::kBwdRows : mlp::Pack<1>::kFwdRows;
+    case 32: return bwd ? mlp::Pack<2>::kBwdRows : mlp::Pack<2>::kFwdRows;
+    case 64: return bwd ? mlp::Pack<4>::kBwdRows : mlp::Pack<4>::kFwdRows;
+    default: return 0;
+  }
+}
+bool wants_grad(const mppi_config* c) { return (c->flags & MPPI_F_REQUIRES_GRAD) != 0; }
+int ckpt_every_of(const mppi_params* p) { return p->checkpoint_every ? p->checkpoint_every : 10; }
+
+// The MFMA operand packs of the MLP (lane layout in mlp.h) from the weight
+// blob W1[H][7] b1[H] W2[H][H] b2[H] W3[5][H] b3[5].
+void build_mlp_packs(const float* blob, int H, std::vector<float4>* fwd, std::vector<float4>* bwd) {
+  const int MT = H / 16;
+  const float* W1 = blob;
+  const float* b1 = W1 + 7 * H;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + 5 * H;
+  const int fr = pack_rows(H, false), br = pack_rows(H, true);
+  std::vector<float> f(static_cast<size_t>(fr) * kWave, 0.0f), b(static_cast<size_t>(br) * kWave, 0.0f);
+  for (int l = 0; l < kWave; ++l) {
+    const int n = l % 16, g = l / 16;
+    int r = 0;
+    auto F = [&](float v) { f[static_cast<size_t>(r++) * kWave + l] = v; };
+    for (int t = 0; t < MT; ++t)
+      for (int j = 0; j < 2; ++j) F(4 * j + g < 7 ? W1[(16 * t + n) * 7 + 4 * j + g] : 0.0f);
+    for (int t = 0; t < MT; ++t)
+      for (int tt = 0; tt < MT; ++tt)
+        for (int i = 0; i < 4; ++i) F(W2[(16 * t + n) * H + 16 * tt + 4 * g + i]);
+    for (int tt = 0; tt < MT; ++tt)
+      for (int i = 0; i < 4; ++i) F(n < 5 ? W3[n * H + 16 * tt + 4 * g + i] : 0.0f);
+    for (int t = 0; t < MT; ++t)
+      for (int i = 0; i < 4; ++i) F(b1[16 * t + 4 * g + i]);
+    for (int t = 0; t < MT; ++t)
+      for (int i = 0; i < 4; ++i) F(b2[16 * t + 4 * g + i]);
+    for (int i = 0; i < 4; ++i) F(4 * g + i < 5 ? b3[4 * g + i] : 0.0f);
+    r = 0;
+    auto B = [&](float v) { b[static_cast<size_t>(r++) * kWave + l] = v; };
+    for (int t = 0; t < MT; ++t)
+      for (int j = 0; j < 2; ++j) B(4 * j + g < 5 ? W3[(4 * j + g) * H + 16 * t + n] : 0.0f);
+    for (int t = 0; t < MT; ++t)
+      for (int tt = 0; tt < MT; ++tt)
+        for (int i = 0; i < 4; ++i) B(W2[(16 * tt + 4 * g + i) * H + 16 * t + n]);
+    for (int tt = 0; tt < MT; ++tt)
+      for (int i = 0; i < 4; ++i) B(n < 7 ? W1[(16 * tt + 4 * g + i) * 7 + n] : 0.0f);
+  }
+  fwd->assign(reinterpret_cast<const float4*>(f.data()),
+              reinterpret_cast<const float4*>(f.data()) + f.size() / 4);
+  bwd->assign(reinterpret_cast<const float4*>(b.data()),
+              reinterpret_cast<const float4*>(b.data()) + b.size() / 4);
+}
 
 bool uses_circles(uint32_t cost) {
   return cost == MPPI_COST_PATH_CIRCLES || cost == MPPI_COST_GOAL_CIRCLES;
@@ -91,12 +154,27 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
   for (int j = 0; j < m; ++j)
     if (!(c->sigma[j] >= 0.0f) || !isfinite(c->sigma[j]))
       return fail(MPPI_EINVAL, "sigma[%d] must be finite and >= 0", j);
-  if (c->dynamics == MPPI_DYN_BICYCLE_MLP)
-    return fail(MPPI_EUNSUPPORTED, "MLP residual dynamics are not built in this version");
-  if (!rollout_supported(c->dynamics, c->integrator, c->cost))
+  if (c->dynamics == MPPI_DYN_BICYCLE_MLP) {
+    if (!p->mlp) return fail(MPPI_EINVAL, "MLP dynamics need the weight blob");
+    if (p->mlp_hidden != 16 && p->mlp_hidden != 32 && p->mlp_hidden != 64)
+      return fail(MPPI_EUNSUPPORTED, "MLP hidden width %d: built for 16, 32 and 64",
+                  p->mlp_hidden);
+    if (!rollout_tiles_supported(c->dynamics, c->integrator, c->cost, p->mlp_hidden))
+      return fail(MPPI_EUNSUPPORTED, "cost %u is not built for MLP dynamics", c->cost);
+  } else if (!rollout_supported(c->dynamics, c->integrator, c->cost)) {
     return fail(MPPI_EUNSUPPORTED, "cost %u is not defined for dynamics %u", c->cost, c->dynamics);
-  if ((c->dynamics == MPPI_DYN_BICYCLE) && !(p->wheelbase > 0.0f))
+  }
+  if ((c->dynamics == MPPI_DYN_BICYCLE || c->dynamics == MPPI_DYN_BICYCLE_MLP) &&
+      !(p->wheelbase > 0.0f))
     return fail(MPPI_EINVAL, "wheelbase must be > 0");
+  if (wants_grad(c)) {
+    if (!((c->dynamics == MPPI_DYN_BICYCLE || c->dynamics == MPPI_DYN_BICYCLE_MLP) &&
+          c->integrator == MPPI_INT_RK4 && c->cost == MPPI_COST_TRACK))
+      return fail(MPPI_EUNSUPPORTED, "MPPI_F_REQUIRES_GRAD needs the bicycle (with or without "
+                  "the MLP residual), RK4 and the TRACK cost");
+    if (p->checkpoint_every < 0 || p->checkpoint_every > 64)
+      return fail(MPPI_EINVAL, "checkpoint_every %d outside [0, 64]", p->checkpoint_every);
+  }
   if (c->dynamics == MPPI_DYN_QUADROTOR) {
     if (!(p->mass > 0.0f)) return fail(MPPI_EINVAL, "mass must be > 0");
     for (int i = 0; i < 3; ++i)
@@ -153,7 +231,17 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m) {
   const size_t cells =
       c->cost == MPPI_COST_PATH_COSTMAP ? (size_t)p->map_w * (size_t)p->map_h : 1;
   L.costmap = take(sizeof(float) * cells);
-  L.mlp = take(sizeof(float));
+  const int H = mlp_hidden_of(c, p);
+  L.mlp = take(sizeof(float) * kWave * (H ? pack_rows(H, false) : 1));
+  L.mlp_bwd = take(sizeof(float) * kWave * (H ? pack_rows(H, true) : 1));
+  if (wants_grad(c)) {
+    const int ce = ckpt_every_of(p);
+    const int nseg = (T + ce - 1) / ce;
+    L.ckpt = take(sizeof(float) * 7 * static_cast<size_t>(nseg) * L.ldk);
+    L.u_roll = take(sizeof(float) * TM);
+    L.adj_layout = adjoint_scratch_layout(K, adjoint_grad_len(c->dynamics, H));
+    L.adj = take(L.adj_layout.total);
+  }
   L.total = off;
   return L;
 }
@@ -244,6 +332,8 @@ struct Instance {
   char* base;  // the instance's workspace slice
   DevParams dp;
   bool quad;   // four lanes per sample in the single-instance rollout
+  bool grad;   // MPPI_F_REQUIRES_GRAD
+  int hidden, ckpt_every, n_theta;
   // views into the context's packed regions
   DevState* st;
   float* x0;
@@ -318,6 +408,8 @@ struct mppi_ctx {
   bool have_state = false;
   bool have_noise = false;
   bool have_costs = false;
+  bool rollout_fresh = false;  // the costs are this iteration's rollout
+  bool grad_ready = false;     // an update followed a fresh rollout
   std::map<int, hipGraphExec_t> graphs;  // mppi_iterate(I) launch sequences
 
   ~mppi_ctx() {
@@ -375,6 +467,19 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* s
   if (e == hipSuccess) e = up(I->L.stage, stage.data(), sizeof(float4) * stage.size());
   if (e == hipSuccess && cfg->cost == MPPI_COST_PATH_COSTMAP)
     e = up(I->L.costmap, p->costmap, sizeof(float) * (size_t)p->map_w * p->map_h);
+  I->hidden = mlp_hidden_of(cfg, p);
+  I->grad = wants_grad(cfg);
+  I->ckpt_every = ckpt_every_of(p);
+  I->n_theta = adjoint_grad_len(cfg->dynamics, I->hidden);
+  if (e == hipSuccess && I->hidden) {
+    keep->emplace_back();
+    std::vector<float4>& fwd = keep->back();
+    keep->emplace_back();
+    std::vector<float4>& bwd = keep->back();
+    build_mlp_packs(p->mlp, I->hidden, &fwd, &bwd);
+    e = up(I->L.mlp, fwd.data(), sizeof(float4) * fwd.size());
+    if (e == hipSuccess) e = up(I->L.mlp_bwd, bwd.data(), sizeof(float4) * bwd.size());
+  }
   if (e != hipSuccess) return hip_fail(e, "parameter upload");
 
   // rollout variant: four lanes per sample while one lane per sample would
@@ -397,6 +502,9 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* s
   }
   memcpy(d.w, p->w, sizeof d.w);
   d.ref = I->at<float>(I->L.ref);
+  d.mlp_hidden = I->hidden;
+  d.mlp = I->hidden ? I->at<float>(I->L.mlp) : nullptr;
+  d.mlp_bwd = I->hidden ? I->at<float>(I->L.mlp_bwd) : nullptr;
   d.nseg = S;
   d.ncirc = N;
   d.stage = I->at<float4>(I->L.stage);
@@ -432,6 +540,9 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
     int n, m;
     mppi_status s = validate(&cfgs[i], &params[i], &n, &m);
     if (s != MPPI_OK) return s;
+    if (batch && (cfgs[i].dynamics == MPPI_DYN_BICYCLE_MLP || wants_grad(&cfgs[i])))
+      return fail(MPPI_EUNSUPPORTED, "batch contexts run neither MLP dynamics nor "
+                  "MPPI_F_REQUIRES_GRAD");
     if (batch && (cfgs[i].dynamics != cfgs[0].dynamics || cfgs[i].integrator != cfgs[0].integrator ||
                   cfgs[i].cost != cfgs[0].cost || cfgs[i].flags != cfgs[0].flags))
       return fail(MPPI_EINVAL, "batch instance %d differs from instance 0 in dynamics, "
@@ -451,7 +562,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   c->C = C;
   c->inst.resize(n_inst);
   std::vector<std::vector<float4>> keep;
-  keep.reserve(2 * n_inst);
+  keep.reserve(4 * n_inst);
   std::vector<DevState> states(n_inst);
   int64_t ox = 0, ou = 0, oS = 0;
   for (int i = 0; i < n_inst; ++i) {
@@ -548,6 +659,17 @@ hipError_t phase_rollout(mppi_ctx* c) {
   if (c->batch)
     return launch_batch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, count,
                                 c->plan, c->stream);
+  if (I.hidden || I.grad) {
+    float* ckpt = I.grad ? I.at<float>(I.L.ckpt) : nullptr;
+    if (I.grad) {
+      hipError_t e = hipMemcpyAsync(I.at<float>(I.L.u_roll), I.u, sizeof(float) * I.TM,
+                                    hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    return launch_rollout_tiles(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp, I.x0,
+                                I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,
+                                c->stream);
+  }
   return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.quad, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
                         c->stream);
@@ -646,6 +768,7 @@ mppi_status mppi_sample(mppi_ctx* c) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
   HIP_TRY(phase_sample(c));
   c->have_noise = true;
+  c->rollout_fresh = c->grad_ready = false;
   return MPPI_OK;
 }
 
@@ -656,6 +779,7 @@ mppi_status mppi_rollout(mppi_ctx* c) {
   hipError_t e = phase_rollout(c);
   if (e != hipSuccess) return hip_fail(e, "rollout launch");
   c->have_costs = true;
+  c->rollout_fresh = true;
   return MPPI_OK;
 }
 
@@ -664,6 +788,7 @@ mppi_status mppi_set_costs(mppi_ctx* c, const float* d_costs) {
   HIP_TRY(hipMemcpyAsync(c->ws + c->C.S, d_costs, sizeof(float) * c->n_S, hipMemcpyDeviceToDevice,
                          c->stream));
   c->have_costs = true;
+  c->rollout_fresh = c->grad_ready = false;
   return MPPI_OK;
 }
 
@@ -673,6 +798,7 @@ mppi_status mppi_update(mppi_ctx* c) {
     return fail(MPPI_ESTATE, "mppi_update needs noise and costs of the current iteration");
   hipError_t e = phase_update(c);
   if (e != hipSuccess) return hip_fail(e, "update launch");
+  c->grad_ready = c->rollout_fresh;
   return MPPI_OK;
 }
 
@@ -689,7 +815,7 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
       if (e == hipSuccess) e = phase_update(c);
       if (e != hipSuccess) return hip_fail(e, "iteration launch");
     }
-    c->have_noise = c->have_costs = true;
+    c->have_noise = c->have_costs = c->rollout_fresh = c->grad_ready = true;
     return MPPI_OK;
   }
   auto it = c->graphs.find(num_iters);
@@ -714,7 +840,7 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
     it = c->graphs.emplace(num_iters, exec).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, c->stream));
-  c->have_noise = c->have_costs = true;
+  c->have_noise = c->have_costs = c->rollout_fresh = c->grad_ready = true;
   return MPPI_OK;
 }
 
@@ -763,11 +889,56 @@ mppi_status mppi_get_debug(mppi_ctx* c, int32_t what, void* d_dst) {
   }
 }
 
+int32_t mppi_theta_len(const mppi_ctx* c) {
+  if (!c) { fail(MPPI_EINVAL, "ctx must not be NULL"); return 0; }
+  if (c->batch || !c->one().grad) {
+    fail(MPPI_ESTATE, "the context was created without MPPI_F_REQUIRES_GRAD");
+    return 0;
+  }
+  return c->one().n_theta;
+}
+
+mppi_status mppi_set_theta(mppi_ctx* c, const float* host_theta) {
+  if (!c || !host_theta) return fail(MPPI_EINVAL, "ctx and host_theta must not be NULL");
+  if (c->batch || !c->one().grad)
+    return fail(MPPI_ESTATE, "the context was created without MPPI_F_REQUIRES_GRAD");
+  Instance& I = c->inst[0];
+  for (int i = 0; i < I.n_theta; ++i)
+    if (!isfinite(host_theta[i])) return fail(MPPI_EINVAL, "theta[%d] is not finite", i);
+  const int nmlp = I.n_theta - I.n - 1;
+  const float wheelbase = host_theta[nmlp + I.n];
+  if (!(wheelbase > 0.0f)) return fail(MPPI_EINVAL, "wheelbase must be > 0");
+  if (I.hidden) {
+    std::vector<float4> fwd, bwd;
+    build_mlp_packs(host_theta, I.hidden, &fwd, &bwd);
+    HIP_TRY(hipMemcpyAsync(I.at<char>(I.L.mlp), fwd.data(), sizeof(float4) * fwd.size(),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(I.at<char>(I.L.mlp_bwd), bwd.data(), sizeof(float4) * bwd.size(),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  for (int i = 0; i < I.n; ++i) I.dp.w[i] = host_theta[nmlp + i];
+  I.dp.inv_wheelbase = static_cast<float>(1.0 / wheelbase);
+  // the kernels take the constants by value: recapture graphs on next use
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  c->graphs.clear();
+  return MPPI_OK;
+}
+
 mppi_status mppi_backward(mppi_ctx* c, const float* d_dL_dU, float* d_grad) {
-  (void)d_dL_dU;
-  (void)d_grad;
-  if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
-  return fail(MPPI_EUNSUPPORTED, "mppi_backward is not built in this version");
+  if (!c || !d_dL_dU || !d_grad) return fail(MPPI_EINVAL, "ctx, d_dL_dU and d_grad must not be NULL");
+  if (c->batch || !c->one().grad)
+    return fail(MPPI_ESTATE, "the context was created without MPPI_F_REQUIRES_GRAD");
+  if (!c->grad_ready)
+    return fail(MPPI_ESTATE, "mppi_backward needs an update that followed this iteration's "
+                "rollout (none since the last mppi_sample or mppi_set_costs)");
+  const Instance& I = c->one();
+  hipError_t e = launch_adjoint(I.dp, (I.cfg.flags & MPPI_F_ACCURATE_TRIG) != 0, I.hidden, d_dL_dU,
+                                I.at<float>(I.L.u_roll), I.eps(), I.L.ldk, I.K, I.T, I.e(),
+                                I.cfg.lambda, I.at<float>(I.L.ckpt), I.ckpt_every,
+                                I.at<char>(I.L.adj), I.L.adj_layout, I.n_theta, d_grad, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  return MPPI_OK;
 }
 
 mppi_status mppi_noise(uint64_t seed, uint32_t iteration, uint32_t instance, int32_t K, int32_t T,

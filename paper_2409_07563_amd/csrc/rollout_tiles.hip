@@ -1,0 +1,134 @@
+// Step (a2) for the bicycle with an MLP residual (x_{t+1} = RK4 / Euler step
+// + dt g([x_t; v_t])), and the checkpointing forward of the adjoint.
+//
+// A wave owns a tile of 16 samples.  The MLP runs on the matrix cores over
+// the tile (mlp.h); every lane group g = lane / 16 carries a full copy of its
+// sample's state, so the bicycle step and the cost run lane-locally, and the
+// MLP input and output need only register selects and four-lane gathers.
+// The nominal controls are staged in LDS.
+//
+// Checkpoints (optional): the state and the compensation terms of the
+// positions at t = 0, c, 2c, ... are stored as ckpt[s][7][ldk], so the
+// adjoint can rebuild each segment bit for bit.
+#include "mlp.h"
+#include "rollout.h"
+
+namespace mppi {
+
+constexpr int kTile = 16;
+constexpr int kCkptWords = 7;
+
+template <int MT, int INTEG, class Cost, bool FAST>
+__global__ __launch_bounds__(kWave) void rollout_tile_kernel(
+    DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
+    const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
+    float* __restrict__ ckpt, int ckpt_every) {
+  using Model = Bicycle<FAST>;
+  constexpr int N = Model::N, M = Model::M;
+  extern __shared__ float4 lds[];
+  const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
+  const int lane = threadIdx.x, n = lane % kTile, g = lane / kTile;
+  const int k = blockIdx.x * kTile + n;
+  const bool live = k < K;
+  // lanes past K recompute sample K-1 (they take part in the MFMAs) and store nothing
+  const float* e = eps + (live ? k : K - 1);
+  mlp::Weights<MT ? MT : 1> W;
+  if constexpr (MT > 0) W.load(p.mlp, lane);
+  float x[N], comp[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
+  typename Cost::State cs;
+  Cost::init(cs, x, p, lds);
+  float sum = 0.0f, sum_c = 0.0f;
+  int next_ckpt = 0;
+  float* ck = ckpt ? ckpt + k : nullptr;
+  for (int t = 0; t < T; ++t) {
+    float v[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + e[static_cast<int64_t>(t * M + j) * ldk];
+    if (ck && t == next_ckpt) {
+      if (g == 0 && live) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) ck[i * ldk] = x[i];
+        ck[5 * ldk] = comp[0];
+        ck[6 * ldk] = comp[1];
+      }
+      ck += kCkptWords * ldk;
+      next_ckpt += ckpt_every;
+    }
+    if constexpr (MT > 0) {
+      float res[N];
+      mlp::residual<MT>(W, x, v, g, n, res);
+      step<Model, INTEG>(x, v, comp, p, res);
+    } else {
+      step<Model, INTEG>(x, v, comp, p);
+    }
+    bool hit;
+    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    const float y = l - sum_c;
+    const float s = sum + y;
+    sum_c = (s - sum) - y;
+    sum = s;
+  }
+  sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
+  if (g == 0 && live) S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
+}
+
+namespace {
+
+using TileFn = void (*)(DevParams, const float*, const float*, const float*, int64_t, int, int,
+                        float*, float*, int);
+
+template <int MT, int INTEG, bool FAST>
+TileFn pick_cost(uint32_t cost) {
+  if (cost == MPPI_COST_TRACK) return rollout_tile_kernel<MT, INTEG, CostTrack, FAST>;
+  if (cost == MPPI_COST_QUADRATIC) return rollout_tile_kernel<MT, INTEG, CostQuadratic, FAST>;
+  return nullptr;
+}
+
+template <int MT>
+TileFn pick_tile(uint32_t integrator, uint32_t cost, bool accurate) {
+  if (integrator == MPPI_INT_RK4)
+    return accurate ? pick_cost<MT, kRK4, false>(cost) : pick_cost<MT, kRK4, true>(cost);
+  if (integrator == MPPI_INT_EULER)
+    return accurate ? pick_cost<MT, kEuler, false>(cost) : pick_cost<MT, kEuler, true>(cost);
+  return nullptr;
+}
+
+TileFn select_tile(uint32_t dynamics, uint32_t integrator, uint32_t cost, bool accurate,
+                   int hidden) {
+  if (dynamics == MPPI_DYN_BICYCLE) return pick_tile<0>(integrator, cost, accurate);
+  if (dynamics != MPPI_DYN_BICYCLE_MLP) return nullptr;
+  switch (hidden) {
+    case 16: return pick_tile<1>(integrator, cost, accurate);
+    case 32: return pick_tile<2>(integrator, cost, accurate);
+    case 64: return pick_tile<4>(integrator, cost, accurate);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+bool rollout_tiles_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int hidden) {
+  return select_tile(dynamics, integrator, cost, false, hidden) != nullptr;
+}
+
+hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                                bool accurate_trig, const DevParams& p, const float* d_x0,
+                                const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
+                                float* d_S, float* d_ckpt, int ckpt_every, hipStream_t stream) {
+  TileFn fn = select_tile(dynamics, integrator, cost, accurate_trig, p.mlp_hidden);
+  if (!fn || (d_ckpt && ckpt_every < 1)) return hipErrorInvalidValue;
+  const size_t lds = sizeof(float) * static_cast<size_t>(T) * 2;
+  if (lds > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((K + kTile - 1) / kTile)), dim3(kWave), lds,
+                     stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S, d_ckpt, ckpt_every);
+  return hipGetLastError();
+}
+
+}  // namespace mppi

@@ -39,16 +39,16 @@ def test_every_declared_function_is_exported(abi):
 def test_struct_sizes_match_the_header(abi):
     # sizes of the C structs as laid out by the host compiler
     assert C.sizeof(abi.Config) == 88
-    assert C.sizeof(abi.Params) == 264
+    assert C.sizeof(abi.Params) == 272
 
 
-def _bytes(abi, wl, **cfg_override):
+def _bytes(abi, wl, grad=False, ckpt=0, **cfg_override):
     from paper_2409_07563_amd import controller
-    cfg = controller._config(wl, False, False, "auto")
+    cfg = controller._config(wl, False, False, "auto", grad)
     for k, v in cfg_override.items():
         setattr(cfg, k, v)
     keep = []
-    params = controller._params(wl, keep)
+    params = controller._params(wl, keep, ckpt)
     n = abi.lib().mppi_workspace_bytes(C.byref(cfg), C.byref(params))
     return n, abi.lib().mppi_last_error().decode()
 
@@ -94,3 +94,26 @@ def test_invalid_params_rejected(abi):
     assert n == 0 and "mass" in msg
     n, msg = _bytes(abi, W.c1(K=64, T=4).replace(ref=None))
     assert n == 0 and "ref" in msg
+
+
+def test_mlp_and_grad_configs(abi):
+    wl = W.c5(K=8192, T=100)
+    n, msg = _bytes(abi, wl)
+    assert n > 0, msg
+    ng, msg = _bytes(abi, wl, grad=True)
+    # checkpoints (T / c = 10 segments x 7 x K floats) and one partial gradient
+    # per 16 samples
+    assert ng > n + 4 * 7 * 10 * 8192 + 4 * (8192 // 16) * 5003, msg
+    assert _bytes(abi, wl.replace(model="bicycle", mlp=None, mlp_hidden=0), grad=True)[0] > 0
+    for bad, needle in ((wl.replace(mlp_hidden=48), "hidden"),
+                        (wl.replace(mlp=None), "weight blob"),
+                        (wl.replace(cost="path_circles"), "not built"),
+                        (wl.replace(wheelbase=0.0), "wheelbase")):
+        n, msg = _bytes(abi, bad)
+        assert n == 0 and needle in msg, msg
+    n, msg = _bytes(abi, wl, grad=True, ckpt=65)
+    assert n == 0 and "checkpoint" in msg
+    n, msg = _bytes(abi, W.c1(K=64, T=4), grad=True)
+    assert n == 0 and "REQUIRES_GRAD" in msg
+    n, msg = _bytes(abi, wl, grad=True, integrator=0)
+    assert n == 0 and "REQUIRES_GRAD" in msg

@@ -1,0 +1,319 @@
+"""GPU parity of the MLP residual dynamics (matrix-core forward) and of the
+adjoint (mppi_backward / the autograd Function) against the binary64 oracle.
+
+Gradient tolerance: the gradient is a sum over samples of a_k dJ_k/dtheta
+whose terms cancel (sum_k a_k = 0).  Each binary32 term carries a relative
+error of order 1e-5 (the costate sweep over the horizon), so the comparison
+bound is 1e-4 * sum_k |a_k dJ_k/dtheta| per parameter (the oracle returns
+that scale as grad_abs).  Over the full horizon (T = 100) part of the samples
+follow chaotic trajectories (see tests/parity.py): there each sample's share
+of the bound is scaled by its own conditioning, rel_k = max(1e-4, COND_ULPS
+2^-24 cond_k / max(|J_k|, 1)), since a binary32 sweep cannot pin such a
+sample's dJ_k/dtheta any closer.  The oracle forms its weights from the GPU's costs
+(the adjoint is checked in isolation, as the update is): the weights are
+exponentially sensitive to the costs, and the costs themselves are checked
+separately (to 1e-4 relative, widened by each trajectory's conditioning,
+see tests/parity.py).  At the configuration's temperature (lambda = 0.5) one
+sample holds essentially all the weight and the gradient is tiny; the
+tempered cases (lambda = 50) exercise a spread of weights.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", file=sys.stderr, flush=True)
+    yield
+
+
+@pytest.fixture(scope="module")
+def mppi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2409_07563_amd as M
+    M.lib()
+    return M
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _c5(K, T, H=64, **kw):
+    return W.c5(K=K, T=T, hidden=H, **kw)
+
+
+# ---------------------------------------------------------------------------
+# forward: MLP residual dynamics on the matrix cores
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("H,K,T,accurate", [(64, 1000, 60, False), (64, 1000, 60, True),
+                                            (16, 777, 40, False), (32, 300, 25, False),
+                                            (64, 37, 13, False), (64, 1, 5, False)])
+def test_mlp_rollout_costs(mppi, oracle_lib, H, K, T, accurate):
+    wl = _c5(K, T, H)
+    c = mppi.Controller(wl, accurate_trig=accurate)
+    c.sample()
+    c.rollout()
+    S = _np(c.costs()).astype(np.float64)
+    eps = _np(c.noise())
+    assert np.array_equal(eps.view(np.uint32), oracle_lib.workload_noise(wl).view(np.uint32))
+    S_or = oracle_lib.rollout_costs(wl, eps)[0]
+    cond = oracle_lib.cost_condition(wl, eps)
+    parity.assert_costs_close(S, S_or, name=f"mlp H={H}", cond=cond)
+    # well-conditioned horizon: the plain 1e-4 bound holds for every sample
+    if T <= 60:
+        parity.assert_costs_close(S, S_or, name=f"mlp H={H} (plain bound)")
+    c.close()
+
+
+def test_mlp_iterations_end_to_end(mppi, oracle_lib):
+    wl = _c5(2048, 100)
+    c = mppi.Controller(wl)
+    u = wl.u0.astype(np.float64)
+    for it in range(3):
+        c.sample()
+        c.rollout()
+        c.update()
+        eps = _np(c.noise())
+        S = _np(c.costs()).astype(np.float64)
+        U = _np(c.controls())
+        S_or, _, _ = oracle_lib.rollout_costs(wl, eps, u=u)
+        cond = oracle_lib.cost_condition(wl, eps, u=u)
+        parity.assert_costs_close(S, S_or, name=f"iteration {it}", cond=cond)
+        w_or, U_or, _, _ = oracle_lib.softmin_update(wl, S_or, eps, u=u)
+        tol = parity.controls_tol(wl, S_or, w_or, eps, cond=cond)
+        parity.assert_controls_close(U, U_or, tol, name=f"iteration {it}")
+        u = U.astype(np.float64)  # continue from the GPU's controls
+    c.close()
+
+
+def test_grad_mode_keeps_the_forward(mppi, oracle_lib):
+    # the checkpointing forward computes the same costs as the plain one
+    wl = _c5(500, 30)
+    a = mppi.Controller(wl)
+    b = mppi.Controller(wl, requires_grad=True, checkpoint_every=7)
+    for c in (a, b):
+        c.sample()
+        c.rollout()
+    assert np.array_equal(_np(a.costs()), _np(b.costs()))
+    # plain bicycle with checkpoints (tile kernel) against the oracle
+    wb = wl.replace(model="bicycle", mlp=None, mlp_hidden=0)
+    c = mppi.Controller(wb, requires_grad=True)
+    c.sample()
+    c.rollout()
+    parity.assert_costs_close(_np(c.costs()).astype(np.float64),
+                              oracle_lib.rollout_costs(wb, _np(c.noise()))[0], name="bicycle")
+    for c in (a, b, c):
+        c.close()
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+def _grad_case(mppi, wl, uref, checkpoint_every=10, accurate=False):
+    c = mppi.Controller(wl, requires_grad=True, checkpoint_every=checkpoint_every,
+                        accurate_trig=accurate)
+    c.sample()
+    c.rollout()
+    c.update()
+    U = _np(c.controls()).astype(np.float64)
+    G = (2.0 * (U - uref)).astype(np.float32)
+    g = _np(c.backward(G)).astype(np.float64)
+    return c, U, G, g
+
+
+def _assert_grad_close(g, ref, name="", rel=None):
+    scale = ref["grad_abs"] if rel is not None else 1e-4 * ref["grad_abs"]
+    tol = scale + 1e-3 * scale.max()
+    err = np.abs(g - ref["grad"])
+    bad = np.flatnonzero(err > tol)
+    assert bad.size == 0, (f"{name}: {bad.size} of {g.size} entries off, first {bad[:5]}: "
+                           f"gpu {g[bad[:5]]} oracle {ref['grad'][bad[:5]]} "
+                           f"worst ratio {(err / tol).max():.3g}")
+
+
+@pytest.mark.parametrize("H,K,T,ce,lam", [
+    (64, 1024, 40, 10, 0.5), (64, 1024, 40, 10, 50.0), (16, 700, 33, 10, 50.0),
+    (32, 256, 20, 7, 5.0), (64, 100, 23, 1, 50.0), (64, 333, 50, 64, 0.5),
+    (64, 333, 50, 64, 50.0), (0, 1000, 50, 10, 0.5), (0, 1000, 50, 10, 50.0)])
+def test_backward_vs_oracle(mppi, oracle_lib, H, K, T, ce, lam):
+    wl = _c5(K, T, H if H else 16).replace(lam=lam)
+    if H == 0:
+        wl = wl.replace(model="bicycle", mlp=None, mlp_hidden=0)
+    uref = W.c5_uref(T=T)
+    c, U, G, g = _grad_case(mppi, wl, uref, checkpoint_every=ce)
+    S = _np(c.costs()).astype(np.float64)
+    eps = _np(c.noise())
+    assert g.shape == (oracle_lib.n_grad(wl),)
+    ref = oracle_lib.backward(wl, G.astype(np.float64), eps=eps, S=S)
+    _assert_grad_close(g, ref, name=f"H={H} K={K} T={T} c={ce} lambda={lam}")
+    c.close()
+
+
+def test_backward_accurate_trig(mppi, oracle_lib):
+    wl = _c5(512, 40, 16)
+    uref = W.c5_uref(T=40)
+    c, U, G, g = _grad_case(mppi, wl, uref, accurate=True)
+    ref = oracle_lib.backward(wl, G.astype(np.float64), eps=_np(c.noise()),
+                              S=_np(c.costs()).astype(np.float64))
+    _assert_grad_close(g, ref, name="accurate trig")
+    c.close()
+
+
+@pytest.mark.parametrize("lam", [0.5, 500.0])
+def test_backward_full_size(mppi, oracle_lib, lam):
+    # the configuration the benchmark times: K = 8192, T = 100, H = 64
+    wl = W.c5().replace(lam=lam)
+    uref = W.c5_uref()
+    c, U, G, g = _grad_case(mppi, wl, uref)
+    eps = _np(c.noise())
+    S = _np(c.costs()).astype(np.float64)
+    S_or = oracle_lib.rollout_costs(wl, eps)[0]
+    cond = oracle_lib.cost_condition(wl, eps)
+    parity.assert_costs_close(S, S_or, name="c5 full size costs", cond=cond)
+    rel = np.maximum(1e-4, parity.COND_ULPS * 2.0 ** -24 * cond / np.maximum(np.abs(S_or), 1.0))
+    ref = oracle_lib.backward(wl, G.astype(np.float64), eps=eps, S=S, rel=rel)
+    _assert_grad_close(g, ref, name=f"c5 full size lambda={lam}", rel=rel)
+    c.close()
+
+
+def test_backward_deterministic_and_repeatable(mppi):
+    wl = _c5(1000, 30)
+    uref = W.c5_uref(T=30)
+    c, U, G, g = _grad_case(mppi, wl, uref)
+    g2 = _np(c.backward(G))
+    assert np.array_equal(g.astype(np.float32).view(np.uint32), g2.view(np.uint32))
+    c.close()
+
+
+def test_autograd_function(mppi, oracle_lib):
+    import torch
+    wl = _c5(512, 30)
+    uref = torch.as_tensor(W.c5_uref(T=30), device="cuda")
+    c = mppi.Controller(wl, requires_grad=True)
+    theta = c.theta().cuda().requires_grad_(True)
+    U = mppi.mppi_step(theta, c)
+    loss = ((U - uref) ** 2).sum()
+    loss.backward()
+    # the same iteration through the staged API: same U, same gradient
+    ref = mppi.Controller(wl, requires_grad=True)
+    ref.sample()
+    ref.rollout()
+    ref.update()
+    U2 = ref.controls()
+    assert torch.equal(U.detach(), U2)
+    g2 = ref.backward(2.0 * (U2 - uref))
+    assert torch.equal(theta.grad, g2)
+    # a second forward draws the next iteration's noise; a stale backward is refused
+    U3 = mppi.mppi_step(theta, c)
+    with pytest.raises(RuntimeError):
+        torch.autograd.grad(((U - uref) ** 2).sum(), theta)
+    assert not torch.equal(U3, U.detach())
+    c.close()
+    ref.close()
+
+
+def test_set_theta_changes_the_model(mppi, oracle_lib):
+    wl = _c5(400, 30, 16)
+    c = mppi.Controller(wl, requires_grad=True)
+    th = oracle_lib.theta_of(wl)
+    rng = np.random.default_rng(5)
+    th2 = th + 0.05 * rng.normal(size=th.size) * np.abs(th).clip(0.1)
+    th2[-1] = 2.2  # wheelbase
+    th2 = th2.astype(np.float32)
+    c.set_theta(th2)
+    c.sample()
+    c.rollout()
+    S = _np(c.costs()).astype(np.float64)
+    wl2 = oracle_lib.with_theta(wl, th2.astype(np.float64))
+    parity.assert_costs_close(S, oracle_lib.rollout_costs(wl2, _np(c.noise()))[0],
+                              name="after set_theta")
+    # iterate() re-captures its graph with the new constants
+    c.set_theta(th.astype(np.float32))
+    c.set_iteration(0)
+    c.iterate(1)
+    S_it = _np(c.costs()).astype(np.float64)
+    parity.assert_costs_close(S_it, oracle_lib.rollout_costs(wl, _np(c.noise()))[0],
+                              name="iterate after set_theta")
+    c.close()
+
+
+def test_gradient_against_gpu_finite_differences(mppi):
+    # central differences of the binary32 forward for the wheelbase and the Q
+    # diagonal, at a temperature where the weights are spread (at lambda = 0.5
+    # a step of 1e-3 in Q moves the costs by ~lambda and hands the weight to
+    # another sample: U is then piecewise constant at the scale of h); looser
+    # (1e-2 of the largest) because each quotient divides binary32 rounding
+    # of L by 2h
+    wl = _c5(2048, 40, 16).replace(lam=50.0)
+    uref = W.c5_uref(T=40)
+    c = mppi.Controller(wl, requires_grad=True)
+    th = c.theta().numpy().astype(np.float64)
+
+    def loss(theta):
+        c.set_theta(theta.astype(np.float32))
+        c.set_controls(wl.u0)  # every evaluation from the same nominal controls
+        c.set_iteration(0)
+        c.sample()
+        c.rollout()
+        c.update()
+        U = _np(c.controls()).astype(np.float64)
+        return float(((U - uref) ** 2).sum()), U
+
+    L0, U0 = loss(th)
+    g = _np(c.backward((2.0 * (U0 - uref)).astype(np.float32))).astype(np.float64)
+    idx = list(range(th.size - 6, th.size))
+    fd = []
+    for i in idx:
+        h = 1e-3 * max(1.0, abs(th[i]))
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd.append((loss(tp)[0] - loss(tm)[0]) / (2 * h))
+    fd = np.array(fd)
+    assert np.all(np.abs(g[idx] - fd) <= 1e-2 * np.abs(fd).max() + 1e-3 * np.abs(fd)), (g[idx], fd)
+    c.close()
+
+
+def test_backward_state_errors(mppi):
+    from paper_2409_07563_amd import MPPIError
+    import torch
+    wl = _c5(64, 10, 16)
+    c = mppi.Controller(wl)
+    with pytest.raises(MPPIError, match="REQUIRES_GRAD"):
+        c.theta_len()
+    c.close()
+    c = mppi.Controller(wl, requires_grad=True)
+    G = torch.zeros(10, 2, device="cuda")
+    with pytest.raises(MPPIError, match="update"):
+        c.backward(G)
+    c.sample()
+    c.rollout()
+    c.update()
+    c.backward(G)
+    c.sample()
+    with pytest.raises(MPPIError, match="update"):
+        c.backward(G)
+    c.rollout()
+    c.set_costs(c.costs())
+    c.update()
+    with pytest.raises(MPPIError, match="update"):
+        c.backward(G)
+    with pytest.raises(ValueError):
+        c.set_theta(np.zeros(3, np.float32))
+    bad = c.theta().numpy().copy()
+    bad[-1] = -1.0
+    with pytest.raises(MPPIError, match="wheelbase"):
+        c.set_theta(bad)
+    c.close()
