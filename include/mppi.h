@@ -213,6 +213,36 @@ enum {
  * the given kind (host_offsets[n] = total length). */
 mppi_status mppi_offsets(const mppi_ctx* ctx, int32_t what, int64_t* host_offsets);
 
+/* ---- launch shapes and the autotuner (spec extension) ------------------
+ * How the kernels of a context are launched; none of it changes results
+ * except lanes_per_sample, which selects a different (equally accurate)
+ * rollout kernel.  The paper picks between its kernels by timing them
+ * (Sec. III-C); mppi_autotune does the same over this table. */
+typedef struct mppi_tuning {
+  int32_t lanes_per_sample; /* rollout: 1, or 4 (the bicycle with RK4, single instance);
+                               16 for MLP dynamics and gradient mode (fixed) */
+  int32_t rollout_block;    /* threads per rollout workgroup: 64, 128 or 256
+                               (64, fixed, for MLP dynamics and gradient mode) */
+  int32_t batch_tile;       /* samples per work tile of a batch context: 64, 128 or 256 */
+  int32_t noise_calls;      /* Philox calls per thread of the single-instance noise
+                               kernel: 1, 2 or 4 */
+} mppi_tuning;
+
+/* The context's current launch shapes. */
+mppi_status mppi_get_tuning(const mppi_ctx* ctx, mppi_tuning* out);
+/* Apply launch shapes (EINVAL for a value outside its set; EUNSUPPORTED for
+ * lanes_per_sample 4 where no such kernel exists).  Rebuilds a batch's work
+ * list (waits for the upload); captured iteration graphs are rebuilt on their
+ * next use. */
+mppi_status mppi_set_tuning(mppi_ctx* ctx, const mppi_tuning* t);
+/* Time every candidate launch shape of the sampling and rollout phases on this
+ * context (reps launches each, HIP events on the context's stream, after one
+ * warm-up launch) and apply the fastest.  Needs mppi_set_state; overwrites the
+ * noise and cost buffers (not u or the iteration word).  host_report
+ * (optional, report_len bytes): one line per candidate, "phase shape time_us".
+ * Synchronises the context's stream. */
+mppi_status mppi_autotune(mppi_ctx* ctx, int32_t reps, char* host_report, size_t report_len);
+
 /* x0 <- d_x0[0..n) (enqueued device copy; packed for a batch). */
 mppi_status mppi_set_state(mppi_ctx* ctx, const float* d_x0);
 /* u <- d_u[T][m] (enqueued device copy; warm start or restore; packed). */

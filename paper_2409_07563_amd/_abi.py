@@ -55,6 +55,14 @@ class Params(C.Structure):
                 ("checkpoint_every", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("lanes_per_sample", C.c_int32), ("rollout_block", C.c_int32),
+                ("batch_tile", C.c_int32), ("noise_calls", C.c_int32)]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 EXPORTS = {
     "mppi_workspace_bytes": (C.c_size_t, [C.POINTER(Config), C.POINTER(Params)]),
     "mppi_create": (C.c_int, [C.POINTER(Config), C.POINTER(Params), C.c_void_p, C.c_size_t,
@@ -71,6 +79,9 @@ EXPORTS = {
     "mppi_get_debug": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "mppi_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mppi_theta_len": (C.c_int32, [C.c_void_p]),
+    "mppi_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
+    "mppi_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
+    "mppi_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.c_size_t]),
     "mppi_set_theta": (C.c_int, [C.c_void_p, _fp]),
     "mppi_destroy": (None, [C.c_void_p]),
     "mppi_last_error": (C.c_char_p, []),

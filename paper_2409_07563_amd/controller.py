@@ -221,6 +221,45 @@ class Controller:
         check(lib().mppi_get_controls(self.ctx, U.data_ptr()))
         return self._leave(U if self.batch else U.reshape(self.T, self.m))
 
+    # -- launch shapes ------------------------------------------------------
+    def tuning(self) -> dict:
+        t = _abi.Tuning()
+        check(lib().mppi_get_tuning(self.ctx, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **shape) -> None:
+        """Change launch shapes (lanes_per_sample, rollout_block, batch_tile,
+        noise_calls); the others keep their values."""
+        t = _abi.Tuning()
+        check(lib().mppi_get_tuning(self.ctx, C.byref(t)))
+        for k, v in shape.items():
+            if k not in t.as_dict():
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        self._enter()
+        check(lib().mppi_set_tuning(self.ctx, C.byref(t)))
+
+    def autotune(self, reps: int = 10, cache: str | None = None) -> dict:
+        """Time the candidate launch shapes on this context and apply the
+        fastest.  With a cache file, a stored choice for the same key (device
+        architecture, dynamics, integrator, cost, K bucket, horizon, batch
+        size) is applied without timing, and a new choice is stored."""
+        from . import autotune as _at
+        key = _at.key(self)
+        if cache is not None:
+            hit = _at.load(cache).get(key)
+            if hit is not None:
+                self.set_tuning(**hit["tuning"])
+                return {"key": key, "tuning": self.tuning(), "cached": True}
+        buf = C.create_string_buffer(8192)
+        self._enter()
+        check(lib().mppi_autotune(self.ctx, int(reps), buf, len(buf)))
+        result = {"key": key, "tuning": self.tuning(), "cached": False,
+                  "timings": _at.parse_report(buf.value.decode())}
+        if cache is not None:
+            _at.store(cache, key, result)
+        return result
+
     # -- differentiation ----------------------------------------------------
     def theta_len(self) -> int:
         n = lib().mppi_theta_len(self.ctx)

@@ -331,12 +331,12 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
 
       if constexpr (MT > 0) {
         // residual dt g(z): c = dt mu_{t+1}
-        f4 h1[MT], h2[MT], da1[MT], da2[MT], dz;
-        mlp::hidden<MT>(WF, xt, v, g, h1, h2);
+        f4 h1[MT], h2[MT], d1[MT], d2[MT], da1[MT], da2[MT], dz;
+        mlp::hidden_d<MT>(WF, xt, v, g, h1, h2, d1, d2);
         float cg[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) cg[i] = p.dt * mu[i];
-        mlp::backward<MT>(WB, cg, g, h1, h2, da1, da2, dz);
+        mlp::backward<MT>(WB, cg, g, d1, d2, da1, da2, dz);
         float dzs[N];
         mlp::broadcast5(dz, n, dzs);
 #pragma unroll
@@ -427,16 +427,36 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   if (lane == 0) out[offQ + N] = sl;
 }
 
-__global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float* __restrict__ partial,
-                                                             int64_t ngp, int ngrad,
-                                                             const BwdMeta* __restrict__ meta,
-                                                             float* __restrict__ grad) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= ngrad) return;
+// grad[j] = sum over the swept tiles of partial[tile][j]: 64 columns per
+// workgroup, the tiles split over 16 lanes per column (tile = p mod 16), the
+// 16 partial sums combined in a fixed order.
+constexpr int kReduceCols = 64, kReduceParts = 16;
+__global__ __launch_bounds__(kReduceCols * kReduceParts) void adjoint_reduce_kernel(
+    const float* __restrict__ partial, int64_t ngp, int ngrad, const BwdMeta* __restrict__ meta,
+    float* __restrict__ grad) {
+  __shared__ float red[kReduceParts][kReduceCols];
+  const int c = threadIdx.x % kReduceCols, part = threadIdx.x / kReduceCols;
+  const int j = blockIdx.x * kReduceCols + c;
   const int tiles = (meta->count + kTileS - 1) / kTileS;
   float s = 0.0f;
-  for (int w = 0; w < tiles; ++w) s += partial[static_cast<int64_t>(w) * ngp + j];
-  grad[j] = s;
+  if (j < ngrad) {
+    int w = part;
+    float s1 = 0.0f;
+    for (; w + kReduceParts < tiles; w += 2 * kReduceParts) {
+      s += partial[static_cast<int64_t>(w) * ngp + j];
+      s1 += partial[static_cast<int64_t>(w + kReduceParts) * ngp + j];
+    }
+    if (w < tiles) s += partial[static_cast<int64_t>(w) * ngp + j];
+    s += s1;
+  }
+  red[part][c] = s;
+  __syncthreads();
+  if (part == 0 && j < ngrad) {
+    float t = red[0][c];
+#pragma unroll
+    for (int q = 1; q < kReduceParts; ++q) t += red[q][c];
+    grad[j] = t;
+  }
 }
 
 // ---- host side ----------------------------------------------------------------
@@ -519,8 +539,9 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   const int tiles = (K + kTileS - 1) / kTileS;
   hipLaunchKernelGGL(fn, dim3(tiles), dim3(kWave), lds, stream, p, d_u, d_eps, ldk, T, d_ckpt,
                      ckpt_every, list, meta, partial, s.ngp);
-  hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((ngrad + 255) / 256), dim3(256), 0, stream,
-                     partial, s.ngp, ngrad, meta, d_grad);
+  hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((ngrad + kReduceCols - 1) / kReduceCols),
+                     dim3(kReduceCols * kReduceParts), 0, stream, partial, s.ngp, ngrad, meta,
+                     d_grad);
   return hipGetLastError();
 }
 

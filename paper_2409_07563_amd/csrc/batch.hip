@@ -14,13 +14,13 @@
 
 namespace mppi {
 
-// (a1) every normal of a tile's kBatchTile samples; one thread per sample loops
+// (a1) every normal of a tile's samples; one thread per sample loops
 // over the Philox calls of its sample, each call storing four coalesced rows.
-__global__ __launch_bounds__(kBatchTile) void batch_noise_kernel(
+__global__ __launch_bounds__(kBatchMaxTile) void batch_noise_kernel(
     const BatchInst* __restrict__ insts, const int2* __restrict__ tiles) {
   const int2 tl = tiles[blockIdx.x];
   const BatchInst& b = insts[tl.x];
-  const int k = tl.y * kBatchTile + threadIdx.x;
+  const int k = tl.y * static_cast<int>(blockDim.x) + threadIdx.x;
   if (k >= b.K) return;
   const uint32_t it = b.st->iteration;
   const int ncall = (b.TM + 3) / 4;
@@ -29,17 +29,17 @@ __global__ __launch_bounds__(kBatchTile) void batch_noise_kernel(
     noise::emit_call(b.key0, b.key1, it, b.instance, k, c, b.TM, m, b.sigma.v, b.eps, b.ldk);
 }
 
-// (a2) one lane per sample over a tile of kBatchTile samples of one instance;
+// (a2) one lane per sample over a tile of samples of one instance;
 // the instance's cost data and controls are staged in LDS per workgroup.
 template <class Model, int INTEG, class Cost, bool COUNT>
-__global__ __launch_bounds__(kBatchTile) void batch_rollout_kernel(
+__global__ __launch_bounds__(kBatchMaxTile) void batch_rollout_kernel(
     const BatchInst* __restrict__ insts, const int2* __restrict__ tiles) {
   extern __shared__ float4 lds[];
   const int2 tl = tiles[blockIdx.x];
   const BatchInst& b = insts[tl.x];
   const DevParams& p = b.p;
   const float* lds_u = stage_rollout_lds<Cost>(p, b.u, b.TM, lds);
-  const int k = tl.y * kBatchTile + threadIdx.x;
+  const int k = tl.y * static_cast<int>(blockDim.x) + threadIdx.x;
   if (k >= b.K) return;  // no barrier follows
   const RolloutResult r =
       rollout_lane<Model, INTEG, Cost, COUNT>(p, b.x0, lds_u, b.eps + k, b.ldk, b.T, lds);
@@ -111,7 +111,7 @@ BatchFn pick_model(uint32_t dynamics, uint32_t cost, bool accurate, bool count) 
 }  // namespace
 
 hipError_t launch_batch_noise(const BatchPlan& b, hipStream_t stream) {
-  hipLaunchKernelGGL(batch_noise_kernel, dim3(b.n_sample_tiles), dim3(kBatchTile), 0, stream,
+  hipLaunchKernelGGL(batch_noise_kernel, dim3(b.n_sample_tiles), dim3(b.tile), 0, stream,
                      b.insts, b.sample_tiles);
   return hipGetLastError();
 }
@@ -128,7 +128,7 @@ hipError_t launch_batch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t
                                        static_cast<int>(b.rollout_lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, dim3(b.n_sample_tiles), dim3(kBatchTile), b.rollout_lds, stream, b.insts,
+  hipLaunchKernelGGL(fn, dim3(b.n_sample_tiles), dim3(b.tile), b.rollout_lds, stream, b.insts,
                      b.sample_tiles);
   return hipGetLastError();
 }

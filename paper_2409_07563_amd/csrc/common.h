@@ -78,13 +78,16 @@ struct BatchInst {
 };
 
 // Work lists of the batched kernels (host-built, device-resident):
-//   sample tiles (instance, block of kBatchTile samples), longest horizon first;
+//   sample tiles (instance, block of `tile` samples), longest horizon first;
 //   row tiles (instance, block of gemv_rows_per_block() rows of the update).
-constexpr int kBatchTile = 256;
+// The tile size is a launch parameter (64, 128 or 256 samples, one thread
+// each; the autotuner picks it); kBatchMinTile sizes the tile table.
+constexpr int kBatchMaxTile = 256, kBatchMinTile = 64;
 struct BatchPlan {
   const BatchInst* insts;
   const int2* sample_tiles;
   int n_sample_tiles;
+  int tile;
   const int2* row_tiles;
   int n_row_tiles;
   int n_inst;
@@ -92,19 +95,21 @@ struct BatchPlan {
 };
 
 // ---- host launchers (one translation unit each) ---------------------------
+// calls: Philox calls per thread (1, 2 or 4; the values do not depend on it)
 hipError_t launch_noise(uint64_t seed, const uint32_t* d_iteration, uint32_t iteration,
                         uint32_t instance, int K, int T, int m, const float* sigma,
-                        float* d_eps, int64_t ldk, hipStream_t stream);
+                        float* d_eps, int64_t ldk, hipStream_t stream, int calls = 1);
 hipError_t launch_noise_tables(float* d_r, float* d_c, float* d_s, hipStream_t stream);
 
 // Returns hipErrorInvalidValue when the (dynamics, integrator, cost)
 // combination has no kernel.
 // quad: use the four-lanes-per-sample kernel where one exists (bicycle, RK4).
 bool rollout_quad_available(uint32_t dynamics, uint32_t integrator);
+// block: threads per workgroup, 64, 128 or 256
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                           bool accurate_trig, bool quad, const DevParams& p, const float* d_x0,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
-                          float* d_S, int32_t* d_crashes, hipStream_t stream);
+                          float* d_S, int32_t* d_crashes, hipStream_t stream, int block = 64);
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
 // LDS bytes the rollout kernel stages (cost data + the nominal controls).
 size_t rollout_lds_bytes(uint32_t dynamics, uint32_t cost, int stage_words4, int T);

@@ -111,8 +111,40 @@ struct PackView {
   __device__ __forceinline__ float w1t(int tt, int i) const { return at(P::kW1t + 4 * tt + i); }
 };
 
+// The activation from one hardware exp2 and one reciprocal (v_exp_f32,
+// v_rcp_f32, about 1 ulp each): with e = e^{-2|a|} = 2^{-2|a| log2 e} in
+// (0, 1] and r = 1 / (1 + e),
+//   tanh(a) = sign(a) (1 - e) r   (absolute error below 3e-7), and
+//   tanh'(a) = 1 - tanh^2(a) = 4 e r^2,
+// the latter accurate to a few ulps even where the unit saturates (1 - h^2
+// formed from a rounded h would cancel there).  No overflow for any a.
+// About 7 instructions against the ~17 of the library tanhf.
+__device__ __forceinline__ void act_hw(float a, float& h, float& e, float& r) {
+  e = __builtin_amdgcn_exp2f(-2.88539008177792681f * __builtin_fabsf(a));
+  r = __builtin_amdgcn_rcpf(1.0f + e);
+  h = __builtin_copysignf((1.0f - e) * r, a);
+}
+
 __device__ __forceinline__ f4 tanh4(f4 a) {
-  return f4{tanhf(a[0]), tanhf(a[1]), tanhf(a[2]), tanhf(a[3])};
+  f4 h;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float hi, e, r;
+    act_hw(a[i], hi, e, r);
+    h[i] = hi;
+  }
+  return h;
+}
+
+// tanh and its derivative
+__device__ __forceinline__ void tanh4_d(f4 a, f4& h, f4& d) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float hi, e, r;
+    act_hw(a[i], hi, e, r);
+    h[i] = hi;
+    d[i] = 4.0f * e * r * r;
+  }
 }
 
 // The B operand of an input-side K-step: component 4j + g of (x0..x4, v0, v1, 0).
@@ -122,13 +154,17 @@ __device__ __forceinline__ float input_operand(const float* x, const float* v, i
 }
 
 // Hidden activations h1 = tanh(W1 z + b1), h2 = tanh(W2 h1 + b2) of the
-// wave's 16 samples, in the D layout.
-template <int MT, class WS>
-__device__ __forceinline__ void hidden(const WS& W, const float* x, const float* v, int g,
-                                       f4 (&h1)[MT], f4 (&h2)[MT]) {
+// wave's 16 samples, in the D layout; with DERIV also tanh' of both layers.
+template <int MT, bool DERIV, class WS>
+__device__ __forceinline__ void hidden_impl(const WS& W, const float* x, const float* v, int g,
+                                            f4 (&h1)[MT], f4 (&h2)[MT], f4* d1, f4* d2) {
   const float z0 = input_operand(x, v, g, 0), z1 = input_operand(x, v, g, 1);
 #pragma unroll
-  for (int t = 0; t < MT; ++t) h1[t] = tanh4(mfma(W.w1(t, 1), z1, mfma(W.w1(t, 0), z0, W.b1(t))));
+  for (int t = 0; t < MT; ++t) {
+    const f4 a = mfma(W.w1(t, 1), z1, mfma(W.w1(t, 0), z0, W.b1(t)));
+    if constexpr (DERIV) tanh4_d(a, h1[t], d1[t]);
+    else h1[t] = tanh4(a);
+  }
   f4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = W.b2(t);
@@ -139,7 +175,23 @@ __device__ __forceinline__ void hidden(const WS& W, const float* x, const float*
 #pragma unroll
       for (int t = 0; t < MT; ++t) acc[t] = mfma(W.w2(t, tt, i), h1[tt][i], acc[t]);
 #pragma unroll
-  for (int t = 0; t < MT; ++t) h2[t] = tanh4(acc[t]);
+  for (int t = 0; t < MT; ++t) {
+    if constexpr (DERIV) tanh4_d(acc[t], h2[t], d2[t]);
+    else h2[t] = tanh4(acc[t]);
+  }
+}
+
+template <int MT, class WS>
+__device__ __forceinline__ void hidden(const WS& W, const float* x, const float* v, int g,
+                                       f4 (&h1)[MT], f4 (&h2)[MT]) {
+  hidden_impl<MT, false>(W, x, v, g, h1, h2, nullptr, nullptr);
+}
+
+template <int MT, class WS>
+__device__ __forceinline__ void hidden_d(const WS& W, const float* x, const float* v, int g,
+                                         f4 (&h1)[MT], f4 (&h2)[MT], f4 (&d1)[MT],
+                                         f4 (&d2)[MT]) {
+  hidden_impl<MT, true>(W, x, v, g, h1, h2, d1, d2);
 }
 
 // Output rows 4g + i of W3 h2 + b3 (rows >= 5 are padding), one accumulator
@@ -179,21 +231,21 @@ __device__ __forceinline__ void residual(const WS& W, const float* x, const floa
 }
 
 // Reverse mode through g for the tile: given c = dL/dg (five components per
-// lane, for the lane's sample) and the activations of the forward,
-//   da2 = (W3^T c) * (1 - h2^2),  da1 = (W2^T da2) * (1 - h1^2),
+// lane, for the lane's sample) and the activation derivatives of the forward
+// (d1, d2 = tanh' of the two hidden layers),
+//   da2 = (W3^T c) * d2,  da1 = (W2^T da2) * d1,
 //   dz  = W1^T da1  (rows 4g + i of 16; rows 0..6 are z's components),
 // all in the D layout.
 template <int MT>
 __device__ __forceinline__ void backward(const PackView<MT>& B, const float* c, int g,
-                                         const f4 (&h1)[MT], const f4 (&h2)[MT], f4 (&da1)[MT],
+                                         const f4 (&d1)[MT], const f4 (&d2)[MT], f4 (&da1)[MT],
                                          f4 (&da2)[MT], f4& dz) {
-  const f4 one{1.0f, 1.0f, 1.0f, 1.0f};
   const float c0 = g == 0 ? c[0] : g == 1 ? c[1] : g == 2 ? c[2] : c[3];
   const float c1 = g == 0 ? c[4] : 0.0f;
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
     const f4 a = mfma(B.w3t(t, 1), c1, mfma(B.w3t(t, 0), c0, f4{0.0f, 0.0f, 0.0f, 0.0f}));
-    da2[t] = a * (one - h2[t] * h2[t]);
+    da2[t] = a * d2[t];
   }
   f4 acc[MT];
 #pragma unroll
@@ -205,7 +257,7 @@ __device__ __forceinline__ void backward(const PackView<MT>& B, const float* c, 
 #pragma unroll
       for (int t = 0; t < MT; ++t) acc[t] = mfma(B.w2t(t, tt, i), da2[tt][i], acc[t]);
 #pragma unroll
-  for (int t = 0; t < MT; ++t) da1[t] = acc[t] * (one - h1[t] * h1[t]);
+  for (int t = 0; t < MT; ++t) da1[t] = acc[t] * d1[t];
   f4 zacc[MT];
 #pragma unroll
   for (int tt = 0; tt < MT; ++tt) {

@@ -372,7 +372,7 @@ CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, in
     nu += (int64_t)cfgs[i].horizon * m;
     nS += cfgs[i].num_samples;
     const int TM = cfgs[i].horizon * m;
-    C.n_sample_tiles += (cfgs[i].num_samples + kBatchTile - 1) / kBatchTile;
+    C.n_sample_tiles += (cfgs[i].num_samples + kBatchMinTile - 1) / kBatchMinTile;
     C.n_row_tiles += (TM + gemv_rows_per_block() - 1) / gemv_rows_per_block();
   }
   C.states = take(sizeof(DevState) * n_inst);
@@ -411,9 +411,12 @@ struct mppi_ctx {
   bool rollout_fresh = false;  // the costs are this iteration's rollout
   bool grad_ready = false;     // an update followed a fresh rollout
   std::map<int, hipGraphExec_t> graphs;  // mppi_iterate(I) launch sequences
+  mppi_tuning tune{};                     // launch shapes (lanes: instance 0's choice)
 
-  ~mppi_ctx() {
+  ~mppi_ctx() { drop_graphs(); }
+  void drop_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
   }
   const Instance& one() const { return inst[0]; }
 };
@@ -529,6 +532,26 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* s
   return MPPI_OK;
 }
 
+// The sample tiles of a batch, `tile` samples each, longest horizon first
+// (stable: instance order within a horizon).  Uploads and waits.
+hipError_t upload_sample_tiles(mppi_ctx* c, int tile) {
+  const int n_inst = static_cast<int>(c->inst.size());
+  std::vector<int> order(n_inst);
+  for (int i = 0; i < n_inst; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return c->inst[a].T > c->inst[b].T; });
+  std::vector<int2> tiles;
+  for (int i : order)
+    for (int t = 0; t * tile < c->inst[i].K; ++t) tiles.push_back(int2{i, t});
+  hipError_t e = hipMemcpyAsync(c->ws + c->C.sample_tiles, tiles.data(), sizeof(int2) * tiles.size(),
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  c->plan.n_sample_tiles = static_cast<int>(tiles.size());
+  c->plan.tile = tile;
+  return hipSuccess;
+}
+
 mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n_inst, bool batch,
                        void* d_workspace, size_t workspace_bytes, void* hip_stream,
                        mppi_ctx** out) {
@@ -588,7 +611,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
 
   // batch tables
   std::vector<BatchInst> bi;
-  std::vector<int2> st_tiles, row_tiles;
+  std::vector<int2> row_tiles;
   if (batch && e == hipSuccess) {
     size_t lds = 0;
     for (int i = 0; i < n_inst; ++i) {
@@ -609,28 +632,17 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
       bi.push_back(b);
       lds = std::max(lds, rollout_lds_bytes(cfgs[i].dynamics, cfgs[i].cost, I.dp.stage_words4, I.T));
     }
-    // sample tiles, longest horizon first (stable: instance order within a horizon)
-    std::vector<int> order(n_inst);
-    for (int i = 0; i < n_inst; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b2) { return c->inst[a].T > c->inst[b2].T; });
-    for (int i : order)
-      for (int t = 0; t * kBatchTile < c->inst[i].K; ++t) st_tiles.push_back(int2{i, t});
     const int rpb = gemv_rows_per_block();
     for (int i = 0; i < n_inst; ++i)
       for (int rb = 0; rb * rpb < c->inst[i].TM; ++rb) row_tiles.push_back(int2{i, rb});
     e = hipMemcpyAsync(c->ws + C.insts, bi.data(), sizeof(BatchInst) * n_inst,
                        hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(c->ws + C.sample_tiles, st_tiles.data(), sizeof(int2) * st_tiles.size(),
-                         hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess)
       e = hipMemcpyAsync(c->ws + C.row_tiles, row_tiles.data(), sizeof(int2) * row_tiles.size(),
                          hipMemcpyHostToDevice, c->stream);
     BatchPlan& P = c->plan;
     P.insts = reinterpret_cast<const BatchInst*>(c->ws + C.insts);
     P.sample_tiles = reinterpret_cast<const int2*>(c->ws + C.sample_tiles);
-    P.n_sample_tiles = static_cast<int>(st_tiles.size());
     P.row_tiles = reinterpret_cast<const int2*>(c->ws + C.row_tiles);
     P.n_row_tiles = static_cast<int>(row_tiles.size());
     P.n_inst = n_inst;
@@ -638,6 +650,15 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   }
   const hipError_t e2 = hipStreamSynchronize(c->stream);  // host staging buffers die here
   if (e == hipSuccess) e = e2;
+  // default launch shapes: four lanes per sample where one lane per sample
+  // would leave most SIMDs idle
+  const Instance& I0 = c->inst[0];
+  const bool tiles = I0.hidden || I0.grad;
+  c->tune.lanes_per_sample = tiles ? 16 : (!batch && I0.quad ? 4 : 1);
+  c->tune.rollout_block = 64;
+  c->tune.batch_tile = kBatchMaxTile;
+  c->tune.noise_calls = 1;
+  if (e == hipSuccess && batch) e = upload_sample_tiles(c, c->tune.batch_tile);
   if (e != hipSuccess) { delete c; return hip_fail(e, "context upload"); }
   *out = c;
   g_last_error.clear();
@@ -649,7 +670,7 @@ hipError_t phase_sample(mppi_ctx* c) {
   if (c->batch) return launch_batch_noise(c->plan, c->stream);
   const Instance& I = c->one();
   return launch_noise(I.cfg.seed, &I.st->iteration, 0u, I.cfg.instance, I.K, I.T, I.m,
-                      I.cfg.sigma, I.eps(), I.L.ldk, c->stream);
+                      I.cfg.sigma, I.eps(), I.L.ldk, c->stream, c->tune.noise_calls);
 }
 
 hipError_t phase_rollout(mppi_ctx* c) {
@@ -672,7 +693,7 @@ hipError_t phase_rollout(mppi_ctx* c) {
   }
   return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.quad, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
-                        c->stream);
+                        c->stream, c->tune.rollout_block);
 }
 
 hipError_t phase_update(mppi_ctx* c) {
@@ -737,6 +758,139 @@ mppi_status mppi_offsets(const mppi_ctx* c, int32_t what, int64_t* host_offsets)
   }
   host_offsets[c->inst.size()] = acc;
   return MPPI_OK;
+}
+
+mppi_status mppi_get_tuning(const mppi_ctx* c, mppi_tuning* out) {
+  if (!c || !out) return fail(MPPI_EINVAL, "ctx and out must not be NULL");
+  *out = c->tune;
+  return MPPI_OK;
+}
+
+mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
+  if (!c || !t) return fail(MPPI_EINVAL, "ctx and t must not be NULL");
+  auto shape = [](int v) { return v == 64 || v == 128 || v == 256; };
+  if (!shape(t->rollout_block) || !shape(t->batch_tile))
+    return fail(MPPI_EINVAL, "rollout_block and batch_tile must be 64, 128 or 256");
+  if (t->noise_calls != 1 && t->noise_calls != 2 && t->noise_calls != 4)
+    return fail(MPPI_EINVAL, "noise_calls must be 1, 2 or 4");
+  Instance& I = c->inst[0];
+  if (I.hidden || I.grad) {
+    if (t->lanes_per_sample != 16 || t->rollout_block != 64)
+      return fail(MPPI_EUNSUPPORTED, "MLP dynamics and gradient mode use 16 lanes per sample "
+                  "and 64-thread workgroups");
+  } else if (t->lanes_per_sample == 4) {
+    if (c->batch || !rollout_quad_available(I.cfg.dynamics, I.cfg.integrator))
+      return fail(MPPI_EUNSUPPORTED, "four lanes per sample exist for a single bicycle "
+                  "instance with RK4 only");
+  } else if (t->lanes_per_sample != 1) {
+    return fail(MPPI_EINVAL, "lanes_per_sample must be 1 or 4");
+  }
+  if (c->batch && t->batch_tile != c->plan.tile) HIP_TRY(upload_sample_tiles(c, t->batch_tile));
+  if (!(I.hidden || I.grad)) I.quad = t->lanes_per_sample == 4;
+  c->tune = *t;
+  c->drop_graphs();
+  return MPPI_OK;
+}
+
+mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report_len) {
+  if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
+  if (!c->have_state) return fail(MPPI_ESTATE, "mppi_set_state must come before mppi_autotune");
+  if (reps < 1) reps = 1;
+  std::string text;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  hipError_t e = hipEventCreate(&b);
+  auto done = [&](mppi_status st) {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (report && report_len) {
+      snprintf(report, report_len, "%s", text.c_str());
+    }
+    return st;
+  };
+  if (e != hipSuccess) return done(hip_fail(e, "hipEventCreate"));
+  // seconds per launch of fn, after one warm-up launch
+  auto time_it = [&](auto fn, double* us) -> hipError_t {
+    hipError_t err = fn();
+    if (err == hipSuccess) err = hipEventRecord(a, c->stream);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = fn();
+    if (err == hipSuccess) err = hipEventRecord(b, c->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, a, b);
+    *us = 1e3 * ms / reps;
+    return err;
+  };
+  auto line = [&](const char* phase, const mppi_tuning& t, double us) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s lanes=%d block=%d tile=%d calls=%d %.2f\n", phase,
+             t.lanes_per_sample, t.rollout_block, t.batch_tile, t.noise_calls, us);
+    text += buf;
+  };
+  mppi_tuning best = c->tune;
+  const Instance& I = c->one();
+  const bool tiles = I.hidden || I.grad;
+  double us, best_us = 1e300;
+  if (c->batch) {
+    // the tile size shapes both the noise and the rollout launch
+    for (int tile : {64, 128, 256}) {
+      mppi_tuning t = c->tune;
+      t.batch_tile = tile;
+      mppi_status st = mppi_set_tuning(c, &t);
+      if (st != MPPI_OK) return done(st);
+      e = time_it([&] {
+        hipError_t err = phase_sample(c);
+        return err == hipSuccess ? phase_rollout(c) : err;
+      }, &us);
+      if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
+      line("sample+rollout", t, us);
+      if (us < best_us) { best_us = us; best = t; }
+    }
+  } else {
+    for (int calls : {1, 2, 4}) {
+      mppi_tuning t = c->tune;
+      t.noise_calls = calls;
+      mppi_status st = mppi_set_tuning(c, &t);
+      if (st != MPPI_OK) return done(st);
+      e = time_it([&] { return phase_sample(c); }, &us);
+      if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
+      line("sample", t, us);
+      if (us < best_us) { best_us = us; best.noise_calls = calls; }
+    }
+    if (!tiles) {
+      best_us = 1e300;
+      const bool quad_ok = rollout_quad_available(I.cfg.dynamics, I.cfg.integrator);
+      for (int lanes : {1, 4}) {
+        if (lanes == 4 && !quad_ok) continue;
+        for (int block : {64, 128, 256}) {
+          mppi_tuning t = c->tune;
+          t.lanes_per_sample = lanes;
+          t.rollout_block = block;
+          mppi_status st = mppi_set_tuning(c, &t);
+          if (st != MPPI_OK) return done(st);
+          e = time_it([&] { return phase_rollout(c); }, &us);
+          if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
+          line("rollout", t, us);
+          if (us < best_us) {
+            best_us = us;
+            best.lanes_per_sample = lanes;
+            best.rollout_block = block;
+          }
+        }
+      }
+    }
+  }
+  mppi_status st = mppi_set_tuning(c, &best);
+  if (st != MPPI_OK) return done(st);
+  // the noise and cost buffers now hold this iteration's sampling and rollout
+  e = phase_sample(c);
+  if (e == hipSuccess) e = phase_rollout(c);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
+  c->have_noise = c->have_costs = c->rollout_fresh = true;
+  c->grad_ready = false;
+  line("chosen", best, 0.0);
+  return done(MPPI_OK);
 }
 
 mppi_status mppi_set_state(mppi_ctx* c, const float* d_x0) {
@@ -920,8 +1074,7 @@ mppi_status mppi_set_theta(mppi_ctx* c, const float* host_theta) {
   for (int i = 0; i < I.n; ++i) I.dp.w[i] = host_theta[nmlp + i];
   I.dp.inv_wheelbase = static_cast<float>(1.0 / wheelbase);
   // the kernels take the constants by value: recapture graphs on next use
-  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
-  c->graphs.clear();
+  c->drop_graphs();
   return MPPI_OK;
 }
 

@@ -8,10 +8,12 @@
 
 namespace mppi {
 
-constexpr int kRolloutBlock = 64;
+// Workgroup size: a launch parameter (64, 128 or 256 threads; the autotuner
+// picks it), so the kernels are compiled for the largest.
+constexpr int kRolloutMaxBlock = 256;
 
 template <class Model, int INTEG, class Cost, bool COUNT>
-__global__ __launch_bounds__(kRolloutBlock) void rollout_kernel(
+__global__ __launch_bounds__(kRolloutMaxBlock) void rollout_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
     int32_t* __restrict__ crashes) {
@@ -50,7 +52,7 @@ __device__ __forceinline__ float quad_sum(float v) {
 }
 
 template <class Cost, bool FAST, bool COUNT>
-__global__ __launch_bounds__(kRolloutBlock) void rollout_bicycle_quad_kernel(
+__global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_quad_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
     int32_t* __restrict__ crashes) {
@@ -246,7 +248,8 @@ bool rollout_quad_available(uint32_t dynamics, uint32_t integrator) {
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                           bool accurate_trig, bool quad, const DevParams& p, const float* d_x0,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
-                          float* d_S, int32_t* d_crashes, hipStream_t stream) {
+                          float* d_S, int32_t* d_crashes, hipStream_t stream, int block) {
+  if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
   const bool count = d_crashes != nullptr;
   const bool use_quad = quad && rollout_quad_available(dynamics, integrator);
   RolloutFn fn = use_quad ? (accurate_trig ? pick_quad_cost<false>(cost, count)
@@ -263,8 +266,8 @@ hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
     if (e != hipSuccess) return e;
   }
   const int64_t lanes = static_cast<int64_t>(K) * lanes_per_sample;
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((lanes + kRolloutBlock - 1) / kRolloutBlock)),
-                     dim3(kRolloutBlock), lds, stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S,
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((lanes + block - 1) / block)),
+                     dim3(block), lds, stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S,
                      d_crashes);
   return hipGetLastError();
 }
