@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=None,
                     help="oracle iterations for the CPU baseline (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of timing the candidates")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run 3 device-to-device copies of this many MiB (a known "
                          "traffic reference for hardware byte counters)")
@@ -168,12 +170,6 @@ def main():
     import torch
     import paper_2409_07563_amd as M
 
-    wl = make_workload(args.workload)
-    if isinstance(wl, list):
-        return bench_batch(args, wl)
-    if wl.model == "bicycle_mlp":
-        return bench_grad(args, wl)
-    I = wl.iters
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy_mb:
@@ -184,8 +180,15 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    wl = make_workload(args.workload)
+    if isinstance(wl, list):
+        return bench_batch(args, wl)
+    if wl.model == "bicycle_mlp":
+        return bench_grad(args, wl)
+    I = wl.iters
     ctl = M.Controller(wl, device=dev)
     stream = ctl.stream
+    tuned = ctl.autotune(reps=10) if not args.no_autotune else None
 
     for _ in range(args.warmup):
         ctl.iterate(I)
@@ -229,6 +232,7 @@ def main():
                    "obstacles": 0 if wl.cx is None else len(wl.cx)},
         "fwd_bwd_over_fwd": None,
         "wall_s_timed": wall,
+        "tuning": ctl.tuning(),
         "roofline": roofline,
         "kernels": kernels,
     }
@@ -265,6 +269,8 @@ def bench_grad(args, wl):
 
     def measure(w):
         plain = M.Controller(w, device=dev)
+        if not args.no_autotune:
+            plain.autotune(reps=3)
         t_fwd = timed(plain.stream, lambda: plain.iterate(1), args.steps, args.warmup)
         t_noise, t_roll, t_upd = phase_times(plain, args.kernel_reps)
         plain.close()
@@ -335,6 +341,9 @@ def bench_batch(args, insts):
     total = sum(w.K * w.T for w in insts)
     ctl = M.Controller(insts, device=dev)
     stream = ctl.stream
+    if not args.no_autotune:
+        ctl.autotune(reps=3)
+    tuning = ctl.tuning()
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -353,6 +362,7 @@ def bench_batch(args, insts):
     ctl.close()
 
     # the same instances as single contexts, one after another on one stream
+    # (each with the default launch shapes of its size)
     singles = [M.Controller(w, device=dev, stream=stream) for w in insts]
     def loop():
         for c in singles:
@@ -373,6 +383,7 @@ def bench_batch(args, insts):
                    "sum_K_T": total, "K_range": [min(w.K for w in insts), max(w.K for w in insts)],
                    "T_range": [min(w.T for w in insts), max(w.T for w in insts)],
                    "iterations_per_step": 1, "cost": insts[0].cost},
+        "tuning": tuning,
         "looped_single_contexts": {"ms_per_step": ms_loop, "value": total / (ms_loop * 1e-3),
                                    "speedup_of_batch": ms_loop / ms},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,

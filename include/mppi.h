@@ -219,8 +219,10 @@ mppi_status mppi_offsets(const mppi_ctx* ctx, int32_t what, int64_t* host_offset
  * rollout kernel.  The paper picks between its kernels by timing them
  * (Sec. III-C); mppi_autotune does the same over this table. */
 typedef struct mppi_tuning {
-  int32_t lanes_per_sample; /* rollout: 1, or 4 (the bicycle with RK4, single instance);
-                               16 for MLP dynamics and gradient mode (fixed) */
+  int32_t lanes_per_sample; /* rollout: 1, or 4, 8 or 16 (the bicycle with RK4, single
+                               instance: RK4 stages across a quad, the running cost
+                               shared by the lanes); 16 for MLP dynamics and
+                               gradient mode (fixed) */
   int32_t rollout_block;    /* threads per rollout workgroup: 64, 128 or 256
                                (64, fixed, for MLP dynamics and gradient mode) */
   int32_t batch_tile;       /* samples per work tile of a batch context: 64, 128 or 256 */
@@ -231,7 +233,7 @@ typedef struct mppi_tuning {
 /* The context's current launch shapes. */
 mppi_status mppi_get_tuning(const mppi_ctx* ctx, mppi_tuning* out);
 /* Apply launch shapes (EINVAL for a value outside its set; EUNSUPPORTED for
- * lanes_per_sample 4 where no such kernel exists).  Rebuilds a batch's work
+ * lanes_per_sample 4, 8 or 16 where no such kernel exists).  Rebuilds a batch's work
  * list (waits for the upload); captured iteration graphs are rebuilt on their
  * next use. */
 mppi_status mppi_set_tuning(mppi_ctx* ctx, const mppi_tuning* t);

@@ -103,11 +103,12 @@ hipError_t launch_noise_tables(float* d_r, float* d_c, float* d_s, hipStream_t s
 
 // Returns hipErrorInvalidValue when the (dynamics, integrator, cost)
 // combination has no kernel.
-// quad: use the four-lanes-per-sample kernel where one exists (bicycle, RK4).
+// lanes: 1 lane per sample, or 4, 8 or 16 where the grouped kernel exists
+// (bicycle, RK4: rollout_quad_available).
 bool rollout_quad_available(uint32_t dynamics, uint32_t integrator);
 // block: threads per workgroup, 64, 128 or 256
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
-                          bool accurate_trig, bool quad, const DevParams& p, const float* d_x0,
+                          bool accurate_trig, int lanes, const DevParams& p, const float* d_x0,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           float* d_S, int32_t* d_crashes, hipStream_t stream, int block = 64);
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);

@@ -331,7 +331,7 @@ struct Instance {
   Layout L;
   char* base;  // the instance's workspace slice
   DevParams dp;
-  bool quad;   // four lanes per sample in the single-instance rollout
+  int lanes;   // lanes per sample of the single-instance rollout (1, 4, 8, 16)
   bool grad;   // MPPI_F_REQUIRES_GRAD
   int hidden, ckpt_every, n_theta;
   // views into the context's packed regions
@@ -487,9 +487,10 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* s
 
   // rollout variant: four lanes per sample while one lane per sample would
   // leave most SIMDs idle
-  I->quad = rollout_quad_available(cfg->dynamics, cfg->integrator) &&
-            !(cfg->flags & MPPI_F_ROLLOUT_LANE) &&
-            ((cfg->flags & MPPI_F_ROLLOUT_QUAD) || I->K <= 32768);
+  I->lanes = rollout_quad_available(cfg->dynamics, cfg->integrator) &&
+                     !(cfg->flags & MPPI_F_ROLLOUT_LANE) &&
+                     ((cfg->flags & MPPI_F_ROLLOUT_QUAD) || I->K <= 32768)
+                 ? 4 : 1;
 
   DevParams& d = I->dp;
   memset(&d, 0, sizeof d);
@@ -654,7 +655,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   // would leave most SIMDs idle
   const Instance& I0 = c->inst[0];
   const bool tiles = I0.hidden || I0.grad;
-  c->tune.lanes_per_sample = tiles ? 16 : (!batch && I0.quad ? 4 : 1);
+  c->tune.lanes_per_sample = tiles ? 16 : (batch ? 1 : I0.lanes);
   c->tune.rollout_block = 64;
   c->tune.batch_tile = kBatchMaxTile;
   c->tune.noise_calls = 1;
@@ -691,7 +692,7 @@ hipError_t phase_rollout(mppi_ctx* c) {
                                 I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,
                                 c->stream);
   }
-  return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.quad, I.dp, I.x0,
+  return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.lanes, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
                         c->stream, c->tune.rollout_block);
 }
@@ -778,15 +779,16 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
     if (t->lanes_per_sample != 16 || t->rollout_block != 64)
       return fail(MPPI_EUNSUPPORTED, "MLP dynamics and gradient mode use 16 lanes per sample "
                   "and 64-thread workgroups");
-  } else if (t->lanes_per_sample == 4) {
+  } else if (t->lanes_per_sample == 4 || t->lanes_per_sample == 8 ||
+             t->lanes_per_sample == 16) {
     if (c->batch || !rollout_quad_available(I.cfg.dynamics, I.cfg.integrator))
-      return fail(MPPI_EUNSUPPORTED, "four lanes per sample exist for a single bicycle "
+      return fail(MPPI_EUNSUPPORTED, "4, 8 or 16 lanes per sample exist for a single bicycle "
                   "instance with RK4 only");
   } else if (t->lanes_per_sample != 1) {
-    return fail(MPPI_EINVAL, "lanes_per_sample must be 1 or 4");
+    return fail(MPPI_EINVAL, "lanes_per_sample must be 1, 4, 8 or 16");
   }
   if (c->batch && t->batch_tile != c->plan.tile) HIP_TRY(upload_sample_tiles(c, t->batch_tile));
-  if (!(I.hidden || I.grad)) I.quad = t->lanes_per_sample == 4;
+  if (!(I.hidden || I.grad)) I.lanes = t->lanes_per_sample;
   c->tune = *t;
   c->drop_graphs();
   return MPPI_OK;
@@ -860,8 +862,8 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     if (!tiles) {
       best_us = 1e300;
       const bool quad_ok = rollout_quad_available(I.cfg.dynamics, I.cfg.integrator);
-      for (int lanes : {1, 4}) {
-        if (lanes == 4 && !quad_ok) continue;
+      for (int lanes : {1, 4, 8, 16}) {
+        if (lanes > 1 && !quad_ok) continue;
         for (int block : {64, 128, 256}) {
           mppi_tuning t = c->tune;
           t.lanes_per_sample = lanes;

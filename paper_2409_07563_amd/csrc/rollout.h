@@ -2,8 +2,9 @@
 // single-instance kernels (rollout.hip) and the batched kernels (batch.hip).
 //
 // One lane per sample keeps the state in registers for the whole horizon;
-// per step it reads its noise (coalesced: lanes are consecutive samples of one
-// [T*m][ldk] row), forms v = u_t + eps, advances the dynamics and adds the
+// per step it takes its noise (coalesced: lanes are consecutive samples of one
+// [T*m][ldk] row; requested a few steps ahead), forms v = u_t + eps, advances
+// the dynamics and adds the
 // running cost with compensated (Kahan) summation; the terminal cost closes
 // the sum.  u (all T steps) and the read-only cost data (obstacle grid,
 // spline) are staged once per workgroup into LDS by stage_rollout_lds.
@@ -28,6 +29,42 @@ __device__ __forceinline__ float* stage_rollout_lds(const DevParams& p, const fl
   return lds_u;
 }
 
+// The noise of the next D steps of one sample, requested D steps before its
+// use so that the L2 / HBM latency of a load (about a microsecond) overlaps
+// several steps of arithmetic rather than one.  e points at eps[0][0][k];
+// steps at or past T are never read.
+template <int M, int D = 4>
+struct NoiseAhead {
+  float q[D][M];
+  const float* e;
+  int64_t ldk;
+  int T;
+  __device__ __forceinline__ void init(const float* e_, int64_t ldk_, int T_) {
+    e = e_;
+    ldk = ldk_;
+    T = T_;
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        q[d][j] = d < T ? e[static_cast<int64_t>(d * M + j) * ldk] : 0.0f;
+  }
+  // the noise of step t (the front of the ring), then the request of step t + D
+  __device__ __forceinline__ void pop(int t, float* out) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) out[j] = q[0][j];
+#pragma unroll
+    for (int d = 0; d + 1 < D; ++d)
+#pragma unroll
+      for (int j = 0; j < M; ++j) q[d][j] = q[d + 1][j];
+    if (t + D < T) {
+      const float* en = e + static_cast<int64_t>(t + D) * M * ldk;
+#pragma unroll
+      for (int j = 0; j < M; ++j) q[D - 1][j] = en[j * ldk];
+    }
+  }
+};
+
 struct RolloutResult {
   float cost;
   int crashes;
@@ -44,22 +81,17 @@ __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
   float x[N], comp[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
-  float nxt[M];
-#pragma unroll
-  for (int j = 0; j < M; ++j) nxt[j] = e[j * ldk];
+  NoiseAhead<M> ahead;
+  ahead.init(e, ldk, T);
   typename Cost::State cs;
   Cost::init(cs, x, p, lds);
   float sum = 0.0f, sum_c = 0.0f;
   int ncrash = 0;
   for (int t = 0; t < T; ++t) {
     float v[M];
+    ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + nxt[j];
-    if (t + 1 < T) {
-      const float* en = e + static_cast<int64_t>(t + 1) * M * ldk;
-#pragma unroll
-      for (int j = 0; j < M; ++j) nxt[j] = en[j * ldk];
-    }
+    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + v[j];
     step<Model, INTEG>(x, v, comp, p);
     bool hit;
     const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);

@@ -1,9 +1,9 @@
 // Step (a2) for one instance: the fused rollout + cost kernels (one lane per
-// sample, or four lanes per sample for the bicycle with RK4) and the choice
-// between them.  The per-lane body lives in rollout.h.  u, the obstacle grid
+// sample, or 4 / 8 / 16 lanes per sample for the bicycle with RK4) and the
+// choice between them.  The per-lane body lives in rollout.h.  u, the obstacle grid
 // and the spline are staged once per workgroup into LDS, so no step waits on
-// a scalar or global load of them; the noise of step t+1 is requested before
-// step t is computed so that its memory latency overlaps the arithmetic.
+// a scalar or global load of them; the noise is requested a few steps ahead
+// of its use (NoiseAhead) so that its memory latency overlaps the arithmetic.
 #include "rollout.h"
 
 namespace mppi {
@@ -27,18 +27,25 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Bicycle + RK4 with four lanes per sample (a DPP quad), the MI355X form of the
-// paper's intra-sample thread axis (Sec. III-C).  Lane j of a quad evaluates
-// RK4 stage j: for the kinematic bicycle the stage yaw rates
-// k_psi = s_j tan(steer_j) / L depend only on speed and steer, which are linear
-// in time over a step, so all four tan / sin / cos evaluations run at once and
-// one in-quad shift delivers k_psi of the previous stage for
-// yaw_j = yaw + c_j dt k_psi(j-1).  Three quad sums assemble the RK4 increment;
-// every lane ends with bitwise the same state (binary32 addition commutes).
-// The running cost is evaluated every fourth step by all four lanes at once,
-// each on the step it latched (t = j mod 4), so the cost code is amortised
-// four ways; each lane keeps a compensated partial sum, summed per quad at the
-// end.
+// Bicycle + RK4 with L = 4, 8 or 16 lanes per sample, the MI355X form of the
+// paper's intra-sample thread axis (Sec. III-C).  Within each DPP quad, lane
+// j = lane mod 4 evaluates RK4 stage j: for the kinematic bicycle the stage
+// yaw rates k_psi = s_j tan(steer_j) / L depend only on speed and steer,
+// which are linear in time over a step, so all four tan / sin / cos
+// evaluations run at once and one in-quad shift delivers k_psi of the
+// previous stage for yaw_j = yaw + c_j dt k_psi(j-1).  Three quad sums
+// assemble the RK4 increment; every lane ends with bitwise the same state
+// (binary32 addition commutes).  With L > 4 the quads of a sample repeat the
+// same dynamics and exist to share the running cost: lane s = lane mod L
+// latches the steps t = s (mod L), and every L steps all L lanes evaluate
+// their latched step at once, so the cost (the LDS-latency-bound spline and
+// obstacle lookups) is amortised L ways and the sample count K fills L times
+// as many waves.  Each lane keeps a compensated partial sum, summed over the
+// L lanes in a fixed butterfly order at the end.
+//
+// The step loop is unrolled by four: the noise of step t + 4 is requested
+// into the register slot that step t has just used, and u of step t + 1 is
+// read from LDS during step t, so neither load stalls the step that needs it.
 // ---------------------------------------------------------------------------
 // quad_perm selectors: [1,0,3,2], [2,3,0,1] and the shift [0,0,1,2]
 constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E, kQuadShift = 0x90;
@@ -50,19 +57,38 @@ __device__ __forceinline__ float quad_sum(float v) {
   const float a = v + quad_dpp<kQuadSwap1>(v);
   return a + quad_dpp<kQuadSwap2>(a);
 }
+// sum over the L lanes of a sample (every lane gets the same value)
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+  v = quad_sum(v);
+  if constexpr (L >= 8) v += __shfl_xor(v, 4, kWave);
+  if constexpr (L >= 16) v += __shfl_xor(v, 8, kWave);
+  return v;
+}
+template <int L>
+__device__ __forceinline__ int group_sum_int(int c) {
+  c += __builtin_amdgcn_update_dpp(0, c, kQuadSwap1, 0xF, 0xF, false);
+  c += __builtin_amdgcn_update_dpp(0, c, kQuadSwap2, 0xF, 0xF, false);
+  if constexpr (L >= 8) c += __shfl_xor(c, 4, kWave);
+  if constexpr (L >= 16) c += __shfl_xor(c, 8, kWave);
+  return c;
+}
 
-template <class Cost, bool FAST, bool COUNT>
-__global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_quad_kernel(
+template <class Cost, bool FAST, bool COUNT, int L>
+__global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
     int32_t* __restrict__ crashes) {
+  static_assert(L == 4 || L == 8 || L == 16, "lanes per sample");
   using Model = Bicycle<FAST>;
   constexpr int N = 5, M = 2;
   extern __shared__ float4 lds[];
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
-  const int j = threadIdx.x & 3;
-  const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-  if (k >= K) return;  // whole quads leave together; no barrier follows
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = gl & 3;           // RK4 stage
+  const int slot = gl & (L - 1);  // latches the steps t = slot (mod L)
+  const int k = gl / L;
+  if (k >= K) return;  // whole groups leave together; no barrier follows
   // stage coefficient c_j dt (0, dt/2, dt/2, dt) and RK4 weight (1, 2, 2, 1)
   const float cdt = j == 0 ? 0.0f : (j == 3 ? p.dt : p.half_dt);
   const float wj = (j == 1 || j == 2) ? 2.0f : 1.0f;
@@ -70,9 +96,14 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_quad_kernel(
 #pragma unroll
   for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
   const float* e = eps + k;
-  float nxt[M];
+  float q[4][M];  // noise of the next four steps, slot t mod 4
 #pragma unroll
-  for (int q = 0; q < M; ++q) nxt[q] = e[q * ldk];
+  for (int d = 0; d < 4; ++d)
+#pragma unroll
+    for (int c = 0; c < M; ++c) q[d][c] = d < T ? e[static_cast<int64_t>(d * M + c) * ldk] : 0.0f;
+  float un[M];  // u of the coming step
+#pragma unroll
+  for (int c = 0; c < M; ++c) un[c] = lds_u[c];
   // the step this lane evaluates the running cost of
   float lx[N], lc[N], lv[M];
   int lt = -1;
@@ -80,78 +111,86 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_quad_kernel(
   Cost::init(cs, x, p, lds);
   float sum = 0.0f, sum_c = 0.0f;
   int ncrash = 0;
-  for (int t = 0; t < T; ++t) {
-    float v[M];
+  for (int t0 = 0; t0 < T; t0 += 4) {
 #pragma unroll
-    for (int q = 0; q < M; ++q) v[q] = lds_u[t * M + q] + nxt[q];
-    if (t + 1 < T) {
-      const float* en = e + static_cast<int64_t>(t + 1) * M * ldk;
+    for (int d = 0; d < 4; ++d) {
+      const int t = t0 + d;
+      if (t < T) {
+        float v[M];
 #pragma unroll
-      for (int q = 0; q < M; ++q) nxt[q] = en[q * ldk];
-    }
-    // stage j of RK4
-    const float sj = x[3] + cdt * v[0];
-    const float dj = x[4] + cdt * v[1];
-    float tn;
-    if constexpr (FAST) {
-      tn = __sinf(dj) * __builtin_amdgcn_rcpf(__cosf(dj));
-    } else {
-      tn = tanf(dj);
-    }
-    const float kpsi = sj * tn * p.inv_wheelbase;
-    const float kprev = quad_dpp<kQuadShift>(kpsi);
-    const float yj = j == 0 ? x[2] : x[2] + cdt * kprev;
-    float sn, co;
-    if constexpr (FAST) {
-      sn = __sinf(yj);
-      co = __cosf(yj);
-    } else {
-      sincosf(yj, &sn, &co);
-    }
-    const float gx = quad_sum(wj * (sj * co));
-    const float gy = quad_sum(wj * (sj * sn));
-    const float gp = quad_sum(wj * kpsi);
-    const float x0s[N] = {x[0], x[1], x[2], x[3], x[4]};
-    const float inc[N] = {p.sixth_dt * gx, p.sixth_dt * gy, p.sixth_dt * gp,
-                          p.sixth_dt * (((v[0] + 2.0f * v[0]) + 2.0f * v[0]) + v[0]),
-                          p.sixth_dt * (((v[1] + 2.0f * v[1]) + 2.0f * v[1]) + v[1])};
-    advance<Model>(x, x0s, inc, comp);
-    // latch this step for lane t mod 4, evaluate a full group every 4 steps
-    if ((t & 3) == j) {
+        for (int c = 0; c < M; ++c) v[c] = un[c] + q[d][c];
+        if (t + 4 < T) {
+          const float* en = e + static_cast<int64_t>(t + 4) * M * ldk;
 #pragma unroll
-      for (int i = 0; i < N; ++i) { lx[i] = x[i]; lc[i] = comp[i]; }
+          for (int c = 0; c < M; ++c) q[d][c] = en[c * ldk];
+        }
+        if (t + 1 < T) {
 #pragma unroll
-      for (int q = 0; q < M; ++q) lv[q] = v[q];
-      lt = t;
-    }
-    if ((t & 3) == 3 || t + 1 == T) {
-      if (lt >= 0) {
-        bool hit;
-        const float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
-        if constexpr (COUNT) ncrash += hit ? 1 : 0;
-        const float y = l - sum_c;
-        const float s = sum + y;
-        sum_c = (s - sum) - y;
-        sum = s;
-        lt = -1;
+          for (int c = 0; c < M; ++c) un[c] = lds_u[(t + 1) * M + c];
+        }
+        // stage j of RK4
+        const float sj = x[3] + cdt * v[0];
+        const float dj = x[4] + cdt * v[1];
+        float tn;
+        if constexpr (FAST) {
+          tn = __sinf(dj) * __builtin_amdgcn_rcpf(__cosf(dj));
+        } else {
+          tn = tanf(dj);
+        }
+        const float kpsi = sj * tn * p.inv_wheelbase;
+        const float kprev = quad_dpp<kQuadShift>(kpsi);
+        const float yj = j == 0 ? x[2] : x[2] + cdt * kprev;
+        float sn, co;
+        if constexpr (FAST) {
+          sn = __sinf(yj);
+          co = __cosf(yj);
+        } else {
+          sincosf(yj, &sn, &co);
+        }
+        const float gx = quad_sum(wj * (sj * co));
+        const float gy = quad_sum(wj * (sj * sn));
+        const float gp = quad_sum(wj * kpsi);
+        const float x0s[N] = {x[0], x[1], x[2], x[3], x[4]};
+        const float inc[N] = {p.sixth_dt * gx, p.sixth_dt * gy, p.sixth_dt * gp,
+                              p.sixth_dt * (((v[0] + 2.0f * v[0]) + 2.0f * v[0]) + v[0]),
+                              p.sixth_dt * (((v[1] + 2.0f * v[1]) + 2.0f * v[1]) + v[1])};
+        advance<Model>(x, x0s, inc, comp);
+        // latch this step for lane t mod L, evaluate a full group every L steps
+        if ((t & (L - 1)) == slot) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) { lx[i] = x[i]; lc[i] = comp[i]; }
+#pragma unroll
+          for (int c = 0; c < M; ++c) lv[c] = v[c];
+          lt = t;
+        }
+        if ((t & (L - 1)) == L - 1 || t + 1 == T) {
+          if (lt >= 0) {
+            bool hit;
+            const float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
+            if constexpr (COUNT) ncrash += hit ? 1 : 0;
+            const float y = l - sum_c;
+            const float s = sum + y;
+            sum_c = (s - sum) - y;
+            sum = s;
+            lt = -1;
+          }
+        }
       }
     }
   }
-  // terminal cost once per sample (lane 0), then the quad's partial sums
+  // terminal cost once per sample (slot 0), then the group's partial sums
   const float phi = terminal_cost<Cost, N>(x, T, p, lds, cs);
-  if (j == 0) {
+  if (slot == 0) {
     const float y = phi - sum_c;
     const float s = sum + y;
     sum_c = (s - sum) - y;
     sum = s;
   }
-  const float total = quad_sum(sum - sum_c);
-  if (j == 0) S[k] = __builtin_isfinite(total) ? total : __builtin_inff();
+  const float total = group_sum<L>(sum - sum_c);
+  if (slot == 0) S[k] = __builtin_isfinite(total) ? total : __builtin_inff();
   if constexpr (COUNT) {
-    int c = ncrash;
-    c += __builtin_amdgcn_update_dpp(0, c, kQuadSwap1, 0xF, 0xF, false);
-    c += __builtin_amdgcn_update_dpp(0, c, kQuadSwap2, 0xF, 0xF, false);
-    if (j == 0) crashes[k] = c;
+    const int c = group_sum_int<L>(ncrash);
+    if (slot == 0) crashes[k] = c;
   }
 }
 
@@ -199,20 +238,30 @@ RolloutFn pick_model(uint32_t dynamics, uint32_t cost, bool accurate, bool count
   }
 }
 
+template <class Cost, bool FAST, int L>
+RolloutFn pick_group(bool count) {
+  if (count) return rollout_bicycle_group_kernel<Cost, FAST, true, L>;
+  return rollout_bicycle_group_kernel<Cost, FAST, false, L>;
+}
+
 template <class Cost, bool FAST>
-RolloutFn pick_quad(bool count) {
-  if (count) return rollout_bicycle_quad_kernel<Cost, FAST, true>;
-  return rollout_bicycle_quad_kernel<Cost, FAST, false>;
+RolloutFn pick_group_lanes(int lanes, bool count) {
+  switch (lanes) {
+    case 4: return pick_group<Cost, FAST, 4>(count);
+    case 8: return pick_group<Cost, FAST, 8>(count);
+    case 16: return pick_group<Cost, FAST, 16>(count);
+    default: return nullptr;
+  }
 }
 
 template <bool FAST>
-RolloutFn pick_quad_cost(uint32_t cost, bool count) {
+RolloutFn pick_group_cost(uint32_t cost, int lanes, bool count) {
   switch (cost) {
-    case MPPI_COST_PATH_CIRCLES: return pick_quad<CostPath<true>, FAST>(count);
-    case MPPI_COST_PATH_COSTMAP: return pick_quad<CostPath<false>, FAST>(count);
-    case MPPI_COST_GOAL_CIRCLES: return pick_quad<CostGoalCircles, FAST>(count);
-    case MPPI_COST_QUADRATIC: return pick_quad<CostQuadratic, FAST>(count);
-    case MPPI_COST_TRACK: return pick_quad<CostTrack, FAST>(count);
+    case MPPI_COST_PATH_CIRCLES: return pick_group_lanes<CostPath<true>, FAST>(lanes, count);
+    case MPPI_COST_PATH_COSTMAP: return pick_group_lanes<CostPath<false>, FAST>(lanes, count);
+    case MPPI_COST_GOAL_CIRCLES: return pick_group_lanes<CostGoalCircles, FAST>(lanes, count);
+    case MPPI_COST_QUADRATIC: return pick_group_lanes<CostQuadratic, FAST>(lanes, count);
+    case MPPI_COST_TRACK: return pick_group_lanes<CostTrack, FAST>(lanes, count);
     default: return nullptr;
   }
 }
@@ -246,17 +295,18 @@ bool rollout_quad_available(uint32_t dynamics, uint32_t integrator) {
 }
 
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
-                          bool accurate_trig, bool quad, const DevParams& p, const float* d_x0,
+                          bool accurate_trig, int lanes, const DevParams& p, const float* d_x0,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           float* d_S, int32_t* d_crashes, hipStream_t stream, int block) {
   if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
   const bool count = d_crashes != nullptr;
-  const bool use_quad = quad && rollout_quad_available(dynamics, integrator);
-  RolloutFn fn = use_quad ? (accurate_trig ? pick_quad_cost<false>(cost, count)
-                                           : pick_quad_cost<true>(cost, count))
-                          : select(dynamics, integrator, cost, accurate_trig, count);
+  const bool group = lanes > 1;
+  if (group && !rollout_quad_available(dynamics, integrator)) return hipErrorInvalidValue;
+  RolloutFn fn = group ? (accurate_trig ? pick_group_cost<false>(cost, lanes, count)
+                                        : pick_group_cost<true>(cost, lanes, count))
+                       : select(dynamics, integrator, cost, accurate_trig, count);
   if (!fn) return hipErrorInvalidValue;
-  const int lanes_per_sample = use_quad ? 4 : 1;
+  const int lanes_per_sample = group ? lanes : 1;
   const size_t lds = (uses_stage(cost) ? sizeof(float4) * static_cast<size_t>(p.stage_words4) : 0) +
                      sizeof(float) * static_cast<size_t>(T) * Model_m(dynamics);
   if (lds > 48 * 1024) {
@@ -265,8 +315,8 @@ hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  const int64_t lanes = static_cast<int64_t>(K) * lanes_per_sample;
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((lanes + block - 1) / block)),
+  const int64_t threads = static_cast<int64_t>(K) * lanes_per_sample;
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((threads + block - 1) / block)),
                      dim3(block), lds, stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S,
                      d_crashes);
   return hipGetLastError();

@@ -31,7 +31,8 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
   const int k = blockIdx.x * kTile + n;
   const bool live = k < K;
   // lanes past K recompute sample K-1 (they take part in the MFMAs) and store nothing
-  const float* e = eps + (live ? k : K - 1);
+  NoiseAhead<M> ahead;
+  ahead.init(eps + (live ? k : K - 1), ldk, T);
   mlp::Weights<MT ? MT : 1> W;
   if constexpr (MT > 0) W.load(p.mlp, lane);
   float x[N], comp[N];
@@ -44,8 +45,9 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
   float* ck = ckpt ? ckpt + k : nullptr;
   for (int t = 0; t < T; ++t) {
     float v[M];
+    ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + e[static_cast<int64_t>(t * M + j) * ldk];
+    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + v[j];
     if (ck && t == next_ckpt) {
       if (g == 0 && live) {
 #pragma unroll

@@ -55,7 +55,7 @@ def test_rollout_shapes(mppi, oracle_lib):
     eps = _np(c.noise())
     S_or, margin, _ = oracle_lib.rollout_costs(wl, eps)
     by_lanes = {}
-    for lanes in (1, 4):
+    for lanes in (1, 4, 8, 16):
         for block in (64, 128, 256):
             c.set_tuning(lanes_per_sample=lanes, rollout_block=block)
             c.rollout()
@@ -125,11 +125,11 @@ def test_invalid_shapes_rejected(mppi):
     from paper_2409_07563_amd import MPPIError
     c = mppi.Controller(W.c1(K=256, T=10))
     for bad in ({"rollout_block": 96}, {"batch_tile": 32}, {"noise_calls": 3},
-                {"lanes_per_sample": 2}):
+                {"lanes_per_sample": 2}, {"lanes_per_sample": 32}):
         with pytest.raises(MPPIError):
             c.set_tuning(**bad)
-    with pytest.raises(MPPIError, match="four lanes"):
-        c.set_tuning(lanes_per_sample=4)  # no four-lane kernel for the double integrator
+    with pytest.raises(MPPIError, match="lanes per sample exist"):
+        c.set_tuning(lanes_per_sample=8)  # no grouped kernel for the double integrator
     c.close()
     c = mppi.Controller(W.c5(K=64, T=10, hidden=16))
     with pytest.raises(MPPIError, match="16 lanes"):

@@ -83,9 +83,11 @@ def _cases():
 CASES = _cases()
 
 
-def _run_one_iteration(mppi, wl, debug=True, accurate_trig=False, rollout="auto"):
+def _run_one_iteration(mppi, wl, debug=True, accurate_trig=False, rollout="auto", lanes=None):
     ctl = mppi.Controller(wl, debug=debug and wl.cost in ("path_circles", "goal_circles"),
                           accurate_trig=accurate_trig, rollout=rollout)
+    if lanes is not None:
+        ctl.set_tuning(lanes_per_sample=lanes)
     ctl.sample()
     ctl.rollout()
     S = _np(ctl.costs())
@@ -121,13 +123,14 @@ def test_rollout_costs_parity(mppi, oracle_lib, name, accurate):
 BICYCLE_CASES = [n for n, w in CASES.items() if w.model == "bicycle"]
 
 
-@pytest.mark.parametrize("rollout", ["lane", "quad"])
+@pytest.mark.parametrize("lanes", [1, 4, 8, 16])
 @pytest.mark.parametrize("name", BICYCLE_CASES)
-def test_rollout_variants_parity(mppi, oracle_lib, name, rollout):
-    """Both rollout kernels of the bicycle (one lane per sample, and four
-    lanes per sample) against the oracle, costs and crash counts."""
+def test_rollout_variants_parity(mppi, oracle_lib, name, lanes):
+    """Every rollout kernel of the bicycle (one lane per sample, and 4, 8 or
+    16 lanes per sample) against the oracle, costs and crash counts."""
     wl = CASES[name]
-    g = _run_one_iteration(mppi, wl, rollout=rollout)
+    rollout = f"lanes{lanes}"
+    g = _run_one_iteration(mppi, wl, lanes=lanes)
     eps_or = oracle_lib.workload_noise(wl)
     S_or, margin, crashes, slope = oracle_lib.rollout_costs(wl, eps=eps_or, slope=True)
     parity.assert_costs_close(g["S"], S_or, margin, f"{name}/{rollout}",
@@ -140,14 +143,18 @@ def test_rollout_variants_parity(mppi, oracle_lib, name, rollout):
                                  f"{name}/{rollout}")
 
 
-@pytest.mark.parametrize("K,T", [(1, 1), (3, 5), (17, 6), (64, 7), (65, 4)])
-def test_quad_rollout_ragged_shapes(mppi, oracle_lib, K, T):
-    """Four lanes per sample: partial quads of the last wave, horizons that
-    are not a multiple of the four-step cost groups."""
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+@pytest.mark.parametrize("K,T", [(1, 1), (3, 5), (17, 6), (64, 7), (65, 4), (33, 23)])
+def test_grouped_rollout_ragged_shapes(mppi, oracle_lib, K, T, lanes):
+    """Several lanes per sample: partial groups in the last wave, horizons
+    that are not a multiple of the unrolled four steps or of the L-step cost
+    groups."""
     wl = W.c2("circles", K=K, T=T, iters=1)
-    g = _run_one_iteration(mppi, wl, rollout="quad")
+    g = _run_one_iteration(mppi, wl, lanes=lanes)
     S_or, margin, crashes = oracle_lib.rollout_costs(wl, eps=oracle_lib.workload_noise(wl))
-    parity.assert_costs_close(g["S"], S_or, margin, f"quad K{K} T{T}")
+    parity.assert_costs_close(g["S"], S_or, margin, f"lanes {lanes} K{K} T{T}")
+    sure = margin >= parity.AMBIGUOUS_MARGIN
+    assert np.array_equal(g["crashes"][sure], crashes[sure])
 
 
 @pytest.mark.parametrize("name", ["c1", "c2_circles", "c3", "c1_ragged"])
