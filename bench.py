@@ -188,7 +188,7 @@ def main():
     I = wl.iters
     ctl = M.Controller(wl, device=dev)
     stream = ctl.stream
-    tuned = ctl.autotune(reps=10) if not args.no_autotune else None
+    tuned = ctl.autotune(reps=30) if not args.no_autotune else None
 
     for _ in range(args.warmup):
         ctl.iterate(I)

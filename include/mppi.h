@@ -223,8 +223,10 @@ typedef struct mppi_tuning {
                                instance: RK4 stages across a quad, the running cost
                                shared by the lanes); 16 for MLP dynamics and
                                gradient mode (fixed) */
-  int32_t rollout_block;    /* threads per rollout workgroup: 64, 128 or 256
-                               (64, fixed, for MLP dynamics and gradient mode) */
+  int32_t rollout_block;    /* threads per rollout workgroup: 64, 128 or 256; for MLP
+                               dynamics and gradient mode 64 (one wave per 16-sample
+                               tile) or 4 H (the tile's MLP split over H/16 waves,
+                               H = 32, 64; the default there) */
   int32_t batch_tile;       /* samples per work tile of a batch context: 64, 128 or 256 */
   int32_t noise_calls;      /* Philox calls per thread of the single-instance noise
                                kernel: 1, 2 or 4 */

@@ -19,8 +19,10 @@
 //             g_k - sum_i w_i g_i accurate when one sample holds almost all
 //             the weight (there the plain difference cancels completely);
 //   sweep:    per tile of 16 listed samples, segment by segment from the
-//             last: the states are rebuilt from the forward's checkpoints,
-//             then the costate runs backwards through them.  The MLP and its
+//             last: the states are rebuilt from the forward's checkpoints
+//             (keeping the MLP pre-activations of each step in a per-tile
+//             scratch that stays in L2), then the costate runs backwards
+//             through them.  The MLP and its
 //             transposes run on the matrix cores (mlp.h); the weight
 //             gradients are outer products summed over the tile's samples
 //             (MFMA with the samples as the contraction index, operands
@@ -163,6 +165,54 @@ __device__ __forceinline__ void bicycle_vjp(const float* x, const float* c, floa
   dl -= s * tn * inv_l * inv_l * c[2];
 }
 
+// mu0 = (dF/dx)^T mu for the RK4 bicycle step from x (control v held), and
+// gL += (dF/d wheelbase)^T mu: the four stages are rebuilt, then transposed
+// in reverse.
+template <bool FAST>
+__device__ __forceinline__ void rk4_vjp(const DevParams& p, const float* xt, const float* v,
+                                        const float* mu, float* mu0, float& gL) {
+  using Model = Bicycle<FAST>;
+  constexpr int N = 5;
+  float k1[N], xa[N], k2[N], xb[N], k3[N], xc[N];
+  Model::deriv(xt, v, k1, p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) xa[i] = xt[i] + p.half_dt * k1[i];
+  Model::deriv(xa, v, k2, p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) xb[i] = xt[i] + p.half_dt * k2[i];
+  Model::deriv(xb, v, k3, p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) xc[i] = xt[i] + p.dt * k3[i];
+  float cst[N], cx[N];
+  const float third_dt = 2.0f * p.sixth_dt;
+#pragma unroll
+  for (int i = 0; i < N; ++i) { mu0[i] = mu[i]; cst[i] = p.sixth_dt * mu[i]; cx[i] = 0.0f; }
+  bicycle_vjp<FAST>(xc, cst, p.inv_wheelbase, cx, gL);  // k4 = f(xc), xc = x + dt k3
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    mu0[i] += cx[i];
+    cst[i] = third_dt * mu[i] + p.dt * cx[i];
+    cx[i] = 0.0f;
+  }
+  bicycle_vjp<FAST>(xb, cst, p.inv_wheelbase, cx, gL);  // k3 = f(xb), xb = x + dt/2 k2
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    mu0[i] += cx[i];
+    cst[i] = third_dt * mu[i] + p.half_dt * cx[i];
+    cx[i] = 0.0f;
+  }
+  bicycle_vjp<FAST>(xa, cst, p.inv_wheelbase, cx, gL);  // k2 = f(xa), xa = x + dt/2 k1
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    mu0[i] += cx[i];
+    cst[i] = p.sixth_dt * mu[i] + p.half_dt * cx[i];
+    cx[i] = 0.0f;
+  }
+  bicycle_vjp<FAST>(xt, cst, p.inv_wheelbase, cx, gL);  // k1 = f(x)
+#pragma unroll
+  for (int i = 0; i < N; ++i) mu0[i] += cx[i];
+}
+
 template <int MT>
 struct SweepLds {
   static constexpr int P = 64 * MT + 16;  // transposition row stride (16 mod 32: no bank conflicts)
@@ -187,7 +237,8 @@ template <int MT, bool FAST>
 __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
-    const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp) {
+    const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp,
+    mlp::f4* __restrict__ pre) {
   using Model = Bicycle<FAST>;
   using L = SweepLds<MT>;
   using f4 = mlp::f4;
@@ -210,6 +261,8 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   float* vs = tb + L::kTb + kTileS * (c + 1) * N + n * (c * M);    // [c][2] of sample n
   __syncthreads();
 
+  // this tile's pre-activation scratch: [c steps][2 layers][MT][64 lanes] f4
+  mlp::f4* my_pre = pre + static_cast<int64_t>(blockIdx.x) * c * 2 * (MT ? MT : 1) * kWave + lane;
   const int idx = base + n;
   const bool valid = idx < meta->count;
   const BwdItem item = list[valid ? idx : base];
@@ -254,7 +307,14 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
       }
       if constexpr (MT > 0) {
         float res[N];
-        mlp::residual<MT>(WF, x, v, g, n, res);
+        f4 a1[MT], a2[MT];
+        mlp::residual_keep<MT>(WF, x, v, g, n, res, a1, a2);
+        f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
+#pragma unroll
+        for (int t2 = 0; t2 < MT; ++t2) {
+          ps[t2 * kWave] = a1[t2];
+          ps[(MT + t2) * kWave] = a2[t2];
+        }
         step<Model, kRK4>(x, v, comp, p, res);
       } else {
         step<Model, kRK4>(x, v, comp, p);
@@ -289,50 +349,20 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
       for (int i = 0; i < N; ++i) xt[i] = xs[j * N + i];
 #pragma unroll
       for (int q = 0; q < M; ++q) v[q] = vs[j * M + q];
-      // RK4 stages of the step from x_t, then their transposes in reverse
-      float k1[N], xa[N], k2[N], xb[N], k3[N], xc[N];
-      Model::deriv(xt, v, k1, p);
-#pragma unroll
-      for (int i = 0; i < N; ++i) xa[i] = xt[i] + p.half_dt * k1[i];
-      Model::deriv(xa, v, k2, p);
-#pragma unroll
-      for (int i = 0; i < N; ++i) xb[i] = xt[i] + p.half_dt * k2[i];
-      Model::deriv(xb, v, k3, p);
-#pragma unroll
-      for (int i = 0; i < N; ++i) xc[i] = xt[i] + p.dt * k3[i];
-      float mu0[N], cst[N], cx[N];
-      const float third_dt = 2.0f * p.sixth_dt;
-#pragma unroll
-      for (int i = 0; i < N; ++i) { mu0[i] = mu[i]; cst[i] = p.sixth_dt * mu[i]; cx[i] = 0.0f; }
-      bicycle_vjp<FAST>(xc, cst, p.inv_wheelbase, cx, gL);  // k4 = f(xc), xc = x + dt k3
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        mu0[i] += cx[i];
-        cst[i] = third_dt * mu[i] + p.dt * cx[i];
-        cx[i] = 0.0f;
-      }
-      bicycle_vjp<FAST>(xb, cst, p.inv_wheelbase, cx, gL);  // k3 = f(xb), xb = x + dt/2 k2
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        mu0[i] += cx[i];
-        cst[i] = third_dt * mu[i] + p.half_dt * cx[i];
-        cx[i] = 0.0f;
-      }
-      bicycle_vjp<FAST>(xa, cst, p.inv_wheelbase, cx, gL);  // k2 = f(xa), xa = x + dt/2 k1
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        mu0[i] += cx[i];
-        cst[i] = p.sixth_dt * mu[i] + p.half_dt * cx[i];
-        cx[i] = 0.0f;
-      }
-      bicycle_vjp<FAST>(xt, cst, p.inv_wheelbase, cx, gL);  // k1 = f(x)
-#pragma unroll
-      for (int i = 0; i < N; ++i) mu0[i] += cx[i];
+      float mu0[N];
+      rk4_vjp<FAST>(p, xt, v, mu, mu0, gL);
 
       if constexpr (MT > 0) {
         // residual dt g(z): c = dt mu_{t+1}
         f4 h1[MT], h2[MT], d1[MT], d2[MT], da1[MT], da2[MT], dz;
-        mlp::hidden_d<MT>(WF, xt, v, g, h1, h2, d1, d2);
+        {
+          const f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
+#pragma unroll
+          for (int t2 = 0; t2 < MT; ++t2) {
+            mlp::tanh4_d(ps[t2 * kWave], h1[t2], d1[t2]);
+            mlp::tanh4_d(ps[(MT + t2) * kWave], h2[t2], d2[t2]);
+          }
+        }
         float cg[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) cg[i] = p.dt * mu[i];
@@ -427,6 +457,279 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   if (lane == 0) out[offQ + N] = sl;
 }
 
+// The sweep with the tile's MLP split over MT waves of one workgroup (H =
+// 16 MT): wave w owns hidden M-tile w in every product, with its operand
+// slices in registers (the weight packs need no LDS):
+//   forward rebuild: h1 tile w, then h2 tile w over all of h1 (h1 tiles
+//     exchanged through LDS), output partial over K-tile w (exchanged);
+//   reverse: da2 tile w = (W3^T c)[w] d2[w]; da1 tile w = (W2^T da2)[w] d1[w]
+//     over all da2 tiles (exchanged); dz partial over K-tile w (exchanged);
+//     dW2 row block w, dW1 row block w and dW3 column block w as outer
+//     products over the tile's samples (the activations of all waves meet in
+//     the shared transposition buffer).
+// Every accumulation runs in the order of the one-wave sweep, so the
+// gradient is bitwise the same; the bicycle step and its transpose are
+// repeated by every wave.
+template <int MT, bool FAST>
+struct SplitLds {
+  static constexpr int P = 64 * MT + 16;
+  static size_t bytes(int c) {
+    return sizeof(float) * (kTileS * P + kTileS * ((c + 1) * 5 + c * 2)) +
+           sizeof(mlp::f4) * 2 * 2 * MT * kWave;
+  }
+};
+
+template <int MT, bool FAST>
+__global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
+    DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
+    const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
+    const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp,
+    mlp::f4* __restrict__ pre) {
+  using Model = Bicycle<FAST>;
+  using f4 = mlp::f4;
+  using PK = mlp::Pack<MT>;
+  constexpr int N = 5, M = 2, H = 16 * MT, PS = SplitLds<MT, FAST>::P;
+  const int base = blockIdx.x * kTileS;
+  if (base >= meta->count) return;  // workgroup-uniform
+  extern __shared__ float4 lds4[];
+  float* tb = reinterpret_cast<float*>(lds4);                         // [16][PS]
+  float* st_x = tb + kTileS * PS;                                     // states
+  f4* xa = reinterpret_cast<f4*>(st_x + kTileS * ((c + 1) * N + c * M));  // [2][MT][64]
+  f4* xb = xa + 2 * MT * kWave;                                       // [2][MT][64]
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int n = lane % kTileS, g = lane / kTileS;
+  float* xs = st_x + n * ((c + 1) * N);
+  float* vs = st_x + kTileS * (c + 1) * N + n * (c * M);
+  auto xch = [&](f4* buf, int par, int q) -> f4& { return buf[(par * MT + q) * kWave + lane]; };
+
+  // this wave's operand slices
+  const float* pf = p.mlp + lane;
+  const float* pb = p.mlp_bwd + lane;
+  float fw1[2], fw2[MT][4], fw3[4], bw3t[2], bw2t[MT][4], bw1t[4];
+  f4 fb1, fb2, fb3;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    fw1[j] = pf[(PK::kW1 + 2 * w + j) * kWave];
+    bw3t[j] = pb[(PK::kW3t + 2 * w + j) * kWave];
+  }
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fw2[tt][i] = pf[(PK::kW2 + (w * MT + tt) * 4 + i) * kWave];
+      bw2t[tt][i] = pb[(PK::kW2t + (w * MT + tt) * 4 + i) * kWave];
+    }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    fw3[i] = pf[(PK::kW3 + 4 * w + i) * kWave];
+    bw1t[i] = pb[(PK::kW1t + 4 * w + i) * kWave];
+    fb1[i] = pf[(PK::kB1 + 4 * w + i) * kWave];
+    fb2[i] = pf[(PK::kB2 + 4 * w + i) * kWave];
+    fb3[i] = w == 0 ? pf[(PK::kB3 + i) * kWave] : 0.0f;
+  }
+
+  // this tile's pre-activation scratch: [c steps][2 layers][MT][64 lanes] f4
+  f4* my_pre = pre + static_cast<int64_t>(blockIdx.x) * c * 2 * MT * kWave + lane;
+  const int idx = base + n;
+  const bool valid = idx < meta->count;
+  const BwdItem item = list[valid ? idx : base];
+  const int k = item.k;
+  const float a = valid ? item.a : 0.0f;
+  const float* e = eps + k;
+
+  const f4 zero4{0.0f, 0.0f, 0.0f, 0.0f};
+  f4 dW1 = zero4, dW3 = zero4, db1 = zero4, db2 = zero4, dW2[MT];
+#pragma unroll
+  for (int q = 0; q < MT; ++q) dW2[q] = zero4;
+  float db3[N], gQ[N], gL = 0.0f, mu[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) { db3[i] = 0.0f; gQ[i] = 0.0f; mu[i] = 0.0f; }
+  int par = 0;
+
+  const int nseg = (T + c - 1) / c;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int t0 = seg * c, len = min(c, T - t0);
+    float x[N], comp[N];
+    const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + k;
+#pragma unroll
+    for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
+    comp[0] = ck[5 * ldk];
+    comp[1] = ck[6 * ldk];
+    for (int j = 0; j < len; ++j) {
+      const int t = t0 + j;
+      float v[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) v[q] = u[t * M + q] + e[static_cast<int64_t>(t * M + q) * ldk];
+      if (w == 0 && g == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) xs[j * N + i] = x[i];
+#pragma unroll
+        for (int q = 0; q < M; ++q) vs[j * M + q] = v[q];
+      }
+      // MLP forward, split (as the split forward kernel)
+      const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
+      const f4 a1w = mlp::mfma(fw1[1], z1, mlp::mfma(fw1[0], z0, fb1));
+      const f4 h1w = mlp::tanh4(a1w);
+      xch(xa, par, w) = h1w;
+      __syncthreads();
+      f4 acc = fb2;
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt) {
+        const f4 h = tt == w ? h1w : xch(xa, par, tt);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc = mlp::mfma(fw2[tt][i], h[i], acc);
+      }
+      const f4 h2w = mlp::tanh4(acc);
+      f4 part = fb3;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[i], h2w[i], part);
+      xch(xb, par, w) = part;
+      f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
+      ps[w * kWave] = a1w;
+      ps[(MT + w) * kWave] = acc;
+      __syncthreads();
+      f4 out = xch(xb, par, 0);
+#pragma unroll
+      for (int tt = 1; tt < MT; ++tt) out += xch(xb, par, tt);
+      par ^= 1;
+      float res[N];
+      mlp::broadcast5(out, n, res);
+      step<Model, kRK4>(x, v, comp, p, res);
+    }
+    if (w == 0 && g == 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) xs[len * N + i] = x[i];
+    }
+    __syncthreads();
+    if (seg == nseg - 1) {
+      const float* r = p.ref + static_cast<int64_t>(T) * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const float d = xs[len * N + i] - r[i];
+        mu[i] = a * 2.0f * p.w[16] * p.w[i] * d;
+        gQ[i] += a * p.w[16] * d * d;
+      }
+    }
+    for (int j = len - 1; j >= 0; --j) {
+      const int t = t0 + j;
+      const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const float d = xs[(j + 1) * N + i] - r[i];
+        mu[i] += a * 2.0f * p.w[i] * d;
+        gQ[i] += a * d * d;
+      }
+      float xt[N], v[M];
+#pragma unroll
+      for (int i = 0; i < N; ++i) xt[i] = xs[j * N + i];
+#pragma unroll
+      for (int q = 0; q < M; ++q) v[q] = vs[j * M + q];
+      float mu0[N];
+      rk4_vjp<FAST>(p, xt, v, mu, mu0, gL);
+      // the MLP residual dt g(z): c = dt mu_{t+1}
+      f4 h1w, d1w, h2w, d2w;
+      {
+        const f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
+        mlp::tanh4_d(ps[w * kWave], h1w, d1w);
+        mlp::tanh4_d(ps[(MT + w) * kWave], h2w, d2w);
+      }
+      float cg[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) cg[i] = p.dt * mu[i];
+      const float c0 = g == 0 ? cg[0] : g == 1 ? cg[1] : g == 2 ? cg[2] : cg[3];
+      const float c1 = g == 0 ? cg[4] : 0.0f;
+      const f4 da2w = mlp::mfma(bw3t[1], c1, mlp::mfma(bw3t[0], c0, zero4)) * d2w;
+      xch(xa, par, w) = da2w;
+      __syncthreads();
+      f4 acc = zero4;
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt) {
+        const f4 d = tt == w ? da2w : xch(xa, par, tt);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc = mlp::mfma(bw2t[tt][i], d[i], acc);
+      }
+      const f4 da1w = acc * d1w;
+      f4 zp = zero4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) zp = mlp::mfma(bw1t[i], da1w[i], zp);
+      xch(xb, par, w) = zp;
+      // the transposition buffer: this wave's rows, and z / c from wave 0
+      float* row = tb + n * PS;
+      *reinterpret_cast<f4*>(row + 16 * w + 4 * g) = h1w;
+      *reinterpret_cast<f4*>(row + H + 16 * w + 4 * g) = h2w;
+      *reinterpret_cast<f4*>(row + 2 * H + 16 * w + 4 * g) = da1w;
+      *reinterpret_cast<f4*>(row + 3 * H + 16 * w + 4 * g) = da2w;
+      if (w == 0) {
+        const f4 zc = g == 0 ? f4{xt[0], xt[1], xt[2], xt[3]}
+                    : g == 1 ? f4{xt[4], v[0], v[1], 0.0f}
+                    : g == 2 ? f4{cg[0], cg[1], cg[2], cg[3]}
+                             : f4{cg[4], 0.0f, 0.0f, 0.0f};
+        *reinterpret_cast<f4*>(row + 4 * H + 4 * g) = zc;
+      }
+      __syncthreads();
+      f4 dz = xch(xb, par, 0);
+#pragma unroll
+      for (int tt = 1; tt < MT; ++tt) dz += xch(xb, par, tt);
+      par ^= 1;
+      float dzs[N];
+      mlp::broadcast5(dz, n, dzs);
+#pragma unroll
+      for (int i = 0; i < N; ++i) mu0[i] += dzs[i];
+      db1 += da1w;
+      db2 += da2w;
+      if (w == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) db3[i] += cg[i];
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const float* tq = tb + (4 * s4 + g) * PS;
+        const float ad2 = tq[3 * H + 16 * w + n];
+        const float ad1 = tq[2 * H + 16 * w + n];
+        const float bh2 = tq[H + 16 * w + n];
+        const float bz = tq[4 * H + n];
+        const float ac = n < 8 ? tq[4 * H + 8 + n] : 0.0f;
+#pragma unroll
+        for (int nt = 0; nt < MT; ++nt) dW2[nt] = mlp::mfma(ad2, tq[16 * nt + n], dW2[nt]);
+        dW1 = mlp::mfma(ad1, bz, dW1);
+        dW3 = mlp::mfma(ac, bh2, dW3);
+      }
+      __syncthreads();  // the transposition buffer is rewritten by the next step
+#pragma unroll
+      for (int i = 0; i < N; ++i) mu[i] = mu0[i];
+    }
+    __syncthreads();  // xs / vs are rewritten by the next segment
+  }
+
+  // this tile's partial gradient: [W1 | b1 | W2 | b2 | W3 | b3 | Q | wheelbase]
+  float* out = partial + static_cast<int64_t>(blockIdx.x) * ngp;
+  const int oB1 = 7 * H, oW2 = 8 * H, oB2 = 8 * H + H * H, oW3 = 9 * H + H * H,
+            oB3 = 14 * H + H * H, offQ = 14 * H + H * H + 5;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * w + 4 * g + i;
+    if (n < 7) out[r * 7 + n] = dW1[i];
+#pragma unroll
+    for (int nt = 0; nt < MT; ++nt) out[oW2 + r * H + 16 * nt + n] = dW2[nt][i];
+    const int o = 4 * g + i;
+    if (o < 5) out[oW3 + o * H + 16 * w + n] = dW3[i];
+    const float s1 = group_sum(db1[i]);
+    const float s2 = group_sum(db2[i]);
+    if (n == 0) { out[oB1 + r] = s1; out[oB2 + r] = s2; }
+  }
+  if (w == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const float s3 = group_sum(db3[i]);
+      if (lane == 0) out[oB3 + i] = s3;
+      const float sq = group_sum(gQ[i]);
+      if (lane == 0) out[offQ + i] = sq;
+    }
+    const float sl = group_sum(gL);
+    if (lane == 0) out[offQ + N] = sl;
+  }
+}
+
 // grad[j] = sum over the swept tiles of partial[tile][j]: 64 columns per
 // workgroup, the tiles split over 16 lanes per column (tile = p mod 16), the
 // 16 partial sums combined in a fixed order.
@@ -465,7 +768,7 @@ int adjoint_grad_len(uint32_t dynamics, int hidden) {
   return (H ? 14 * H + H * H + 5 : 0) + 6;
 }
 
-AdjointScratch adjoint_scratch_layout(int K, int ngrad) {
+AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_every) {
   AdjointScratch s{};
   const int nb = (K + kProjectSamples - 1) / kProjectSamples;
   const int tiles = (K + kTileS - 1) / kTileS;
@@ -478,6 +781,9 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad) {
   s.meta = take(sizeof(BwdMeta));
   s.list = take(sizeof(BwdItem) * K);
   s.partial = take(sizeof(float) * static_cast<size_t>(tiles) * s.ngp);
+  // pre-activations of one segment per tile: c steps x 2 layers x H/16 x 64 lanes x 4
+  s.pre = take(sizeof(float) * 4 * static_cast<size_t>(tiles) * ckpt_every * 2 *
+               (hidden > 0 ? hidden / 16 : 0) * kWave);
   s.total = off;
   return s;
 }
@@ -494,10 +800,14 @@ size_t adjoint_lds_bytes(int hidden, int ckpt_every) {
 
 namespace {
 using SweepFn = void (*)(DevParams, const float*, const float*, int64_t, int, const float*, int,
-                         const BwdItem*, const BwdMeta*, float*, int64_t);
+                         const BwdItem*, const BwdMeta*, float*, int64_t, mlp::f4*);
 template <int MT>
 SweepFn pick_sweep(bool accurate) {
   return accurate ? adjoint_sweep_kernel<MT, false> : adjoint_sweep_kernel<MT, true>;
+}
+template <int MT>
+SweepFn pick_split_sweep(bool accurate) {
+  return accurate ? adjoint_sweep_split_kernel<MT, false> : adjoint_sweep_split_kernel<MT, true>;
 }
 }  // namespace
 
@@ -505,16 +815,25 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, const float* d_ckpt, int ckpt_every,
                           char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
-                          hipStream_t stream) {
+                          hipStream_t stream, bool split) {
   SweepFn fn = nullptr;
-  switch (hidden) {
-    case 0: fn = pick_sweep<0>(accurate_trig); break;
-    case 16: fn = pick_sweep<1>(accurate_trig); break;
-    case 32: fn = pick_sweep<2>(accurate_trig); break;
-    case 64: fn = pick_sweep<4>(accurate_trig); break;
-    default: return hipErrorInvalidValue;
+  const int waves = split && hidden >= 32 ? hidden / 16 : 1;
+  size_t lds = adjoint_lds_bytes(hidden, ckpt_every);
+  if (waves == 4) {
+    fn = pick_split_sweep<4>(accurate_trig);
+    lds = SplitLds<4, true>::bytes(ckpt_every);
+  } else if (waves == 2) {
+    fn = pick_split_sweep<2>(accurate_trig);
+    lds = SplitLds<2, true>::bytes(ckpt_every);
+  } else {
+    switch (hidden) {
+      case 0: fn = pick_sweep<0>(accurate_trig); break;
+      case 16: fn = pick_sweep<1>(accurate_trig); break;
+      case 32: fn = pick_sweep<2>(accurate_trig); break;
+      case 64: fn = pick_sweep<4>(accurate_trig); break;
+      default: return hipErrorInvalidValue;
+    }
   }
-  const size_t lds = adjoint_lds_bytes(hidden, ckpt_every);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 48 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -528,6 +847,7 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   BwdMeta* meta = reinterpret_cast<BwdMeta*>(d_scratch + s.meta);
   BwdItem* list = reinterpret_cast<BwdItem*>(d_scratch + s.list);
   float* partial = reinterpret_cast<float*>(d_scratch + s.partial);
+  mlp::f4* pre = reinterpret_cast<mlp::f4*>(d_scratch + s.pre);
   const int nb = (K + kProjectSamples - 1) / kProjectSamples;
   const int TM = T * 2;
   hipLaunchKernelGGL(adjoint_project_kernel, dim3(nb), dim3(kProjectBlock), 0, stream, d_G, d_eps,
@@ -537,8 +857,8 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   hipLaunchKernelGGL(adjoint_compact_kernel, dim3(nb), dim3(kProjectSamples), 0, stream, d_e, gk,
                      K, static_cast<float>(1.0 / static_cast<double>(lambda)), offs, meta, list);
   const int tiles = (K + kTileS - 1) / kTileS;
-  hipLaunchKernelGGL(fn, dim3(tiles), dim3(kWave), lds, stream, p, d_u, d_eps, ldk, T, d_ckpt,
-                     ckpt_every, list, meta, partial, s.ngp);
+  hipLaunchKernelGGL(fn, dim3(tiles), dim3(kWave * waves), lds, stream, p, d_u, d_eps, ldk, T,
+                     d_ckpt, ckpt_every, list, meta, partial, s.ngp, pre);
   hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((ngrad + kReduceCols - 1) / kReduceCols),
                      dim3(kReduceCols * kReduceParts), 0, stream, partial, s.ngp, ngrad, meta,
                      d_grad);

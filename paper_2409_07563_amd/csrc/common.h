@@ -95,6 +95,8 @@ struct BatchPlan {
 };
 
 // ---- host launchers (one translation unit each) ---------------------------
+// The iteration word is *d_iteration + iteration when d_iteration is given
+// (read on the device at run time), else iteration.
 // calls: Philox calls per thread (1, 2 or 4; the values do not depend on it)
 hipError_t launch_noise(uint64_t seed, const uint32_t* d_iteration, uint32_t iteration,
                         uint32_t instance, int K, int T, int m, const float* sigma,
@@ -126,24 +128,26 @@ hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState*
 
 // MLP residual dynamics and the checkpointing forward (rollout_tiles.hip)
 bool rollout_tiles_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int hidden);
+// split: the MLP of a 16-sample tile spread over H/16 waves (H = 32, 64)
 hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                                 bool accurate_trig, const DevParams& p, const float* d_x0,
                                 const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
-                                float* d_S, float* d_ckpt, int ckpt_every, hipStream_t stream);
+                                float* d_S, float* d_ckpt, int ckpt_every, hipStream_t stream,
+                                bool split = true);
 
 // The adjoint (adjoint.hip).  Scratch: byte offsets inside one device region.
 struct AdjointScratch {
-  size_t gk, part, offs, meta, list, partial, total;
+  size_t gk, part, offs, meta, list, partial, pre, total;
   int64_t ngp;  // floats per partial-gradient row
 };
 int adjoint_grad_len(uint32_t dynamics, int hidden);
-AdjointScratch adjoint_scratch_layout(int K, int ngrad);
+AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_every);
 size_t adjoint_lds_bytes(int hidden, int ckpt_every);
 hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, const float* d_ckpt, int ckpt_every,
                           char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
-                          hipStream_t stream);
+                          hipStream_t stream, bool split = true);
 
 hipError_t launch_batch_noise(const BatchPlan& b, hipStream_t stream);
 hipError_t launch_batch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,

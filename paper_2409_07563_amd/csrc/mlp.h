@@ -154,14 +154,17 @@ __device__ __forceinline__ float input_operand(const float* x, const float* v, i
 }
 
 // Hidden activations h1 = tanh(W1 z + b1), h2 = tanh(W2 h1 + b2) of the
-// wave's 16 samples, in the D layout; with DERIV also tanh' of both layers.
+// wave's 16 samples, in the D layout; with DERIV also tanh' of both layers;
+// with pre1 / pre2 also the pre-activations.
 template <int MT, bool DERIV, class WS>
 __device__ __forceinline__ void hidden_impl(const WS& W, const float* x, const float* v, int g,
-                                            f4 (&h1)[MT], f4 (&h2)[MT], f4* d1, f4* d2) {
+                                            f4 (&h1)[MT], f4 (&h2)[MT], f4* d1, f4* d2,
+                                            f4* pre1 = nullptr, f4* pre2 = nullptr) {
   const float z0 = input_operand(x, v, g, 0), z1 = input_operand(x, v, g, 1);
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
     const f4 a = mfma(W.w1(t, 1), z1, mfma(W.w1(t, 0), z0, W.b1(t)));
+    if (pre1) pre1[t] = a;
     if constexpr (DERIV) tanh4_d(a, h1[t], d1[t]);
     else h1[t] = tanh4(a);
   }
@@ -176,6 +179,7 @@ __device__ __forceinline__ void hidden_impl(const WS& W, const float* x, const f
       for (int t = 0; t < MT; ++t) acc[t] = mfma(W.w2(t, tt, i), h1[tt][i], acc[t]);
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
+    if (pre2) pre2[t] = acc[t];
     if constexpr (DERIV) tanh4_d(acc[t], h2[t], d2[t]);
     else h2[t] = tanh4(acc[t]);
   }
@@ -227,6 +231,15 @@ __device__ __forceinline__ void residual(const WS& W, const float* x, const floa
                                          int n, float* res) {
   f4 h1[MT], h2[MT];
   hidden<MT>(W, x, v, g, h1, h2);
+  broadcast5(output<MT>(W, h2), n, res);
+}
+
+// The same, also handing back the pre-activations of both hidden layers.
+template <int MT, class WS>
+__device__ __forceinline__ void residual_keep(const WS& W, const float* x, const float* v, int g,
+                                              int n, float* res, f4 (&pre1)[MT], f4 (&pre2)[MT]) {
+  f4 h1[MT], h2[MT];
+  hidden_impl<MT, false>(W, x, v, g, h1, h2, nullptr, nullptr, pre1, pre2);
   broadcast5(output<MT>(W, h2), n, res);
 }
 

@@ -239,7 +239,7 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m) {
     const int nseg = (T + ce - 1) / ce;
     L.ckpt = take(sizeof(float) * 7 * static_cast<size_t>(nseg) * L.ldk);
     L.u_roll = take(sizeof(float) * TM);
-    L.adj_layout = adjoint_scratch_layout(K, adjoint_grad_len(c->dynamics, H));
+    L.adj_layout = adjoint_scratch_layout(K, adjoint_grad_len(c->dynamics, H), H, ce);
     L.adj = take(L.adj_layout.total);
   }
   L.total = off;
@@ -412,7 +412,6 @@ struct mppi_ctx {
   bool grad_ready = false;     // an update followed a fresh rollout
   std::map<int, hipGraphExec_t> graphs;  // mppi_iterate(I) launch sequences
   mppi_tuning tune{};                     // launch shapes (lanes: instance 0's choice)
-
   ~mppi_ctx() { drop_graphs(); }
   void drop_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -656,7 +655,8 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   const Instance& I0 = c->inst[0];
   const bool tiles = I0.hidden || I0.grad;
   c->tune.lanes_per_sample = tiles ? 16 : (batch ? 1 : I0.lanes);
-  c->tune.rollout_block = 64;
+  // MLP dynamics: the tile's MLP split over H/16 waves where that form exists
+  c->tune.rollout_block = I0.hidden >= 32 ? 4 * I0.hidden : 64;
   c->tune.batch_tile = kBatchMaxTile;
   c->tune.noise_calls = 1;
   if (e == hipSuccess && batch) e = upload_sample_tiles(c, c->tune.batch_tile);
@@ -690,7 +690,7 @@ hipError_t phase_rollout(mppi_ctx* c) {
     }
     return launch_rollout_tiles(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp, I.x0,
                                 I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,
-                                c->stream);
+                                c->stream, c->tune.rollout_block > kWave);
   }
   return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.lanes, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
@@ -776,9 +776,11 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
     return fail(MPPI_EINVAL, "noise_calls must be 1, 2 or 4");
   Instance& I = c->inst[0];
   if (I.hidden || I.grad) {
-    if (t->lanes_per_sample != 16 || t->rollout_block != 64)
+    const bool split_ok = I.hidden >= 32 && t->rollout_block == 4 * I.hidden;
+    if (t->lanes_per_sample != 16 || !(t->rollout_block == 64 || split_ok))
       return fail(MPPI_EUNSUPPORTED, "MLP dynamics and gradient mode use 16 lanes per sample "
-                  "and 64-thread workgroups");
+                  "and 64-thread workgroups (or 4 H threads, the MLP split over H/16 waves, "
+                  "for H = 32, 64)");
   } else if (t->lanes_per_sample == 4 || t->lanes_per_sample == 8 ||
              t->lanes_per_sample == 16) {
     if (c->batch || !rollout_quad_available(I.cfg.dynamics, I.cfg.integrator))
@@ -829,60 +831,95 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
              t.lanes_per_sample, t.rollout_block, t.batch_tile, t.noise_calls, us);
     text += buf;
   };
+  // Each group of candidates shapes one phase; the candidates of a group are
+  // timed round-robin in kRounds rounds and each keeps its best round, so a
+  // drift of the clock or of the caches does not decide the choice.
+  constexpr int kRounds = 3;
   mppi_tuning best = c->tune;
   const Instance& I = c->one();
   const bool tiles = I.hidden || I.grad;
-  double us, best_us = 1e300;
+  struct Cand {
+    mppi_tuning t;
+    double us;
+  };
+  auto search = [&](const char* phase, std::vector<mppi_tuning> cands, auto fn,
+                    mppi_tuning* chosen) -> mppi_status {
+    std::vector<Cand> cs;
+    for (const mppi_tuning& t : cands) cs.push_back(Cand{t, 1e300});
+    for (int r = 0; r < kRounds; ++r)
+      for (Cand& cd : cs) {
+        mppi_status st = mppi_set_tuning(c, &cd.t);
+        if (st != MPPI_OK) return st;
+        double us = 0.0;
+        hipError_t err = time_it(fn, &us);
+        if (err != hipSuccess) return hip_fail(err, "autotune launch");
+        cd.us = std::min(cd.us, us);
+      }
+    const Cand* b = &cs[0];
+    for (const Cand& cd : cs) {
+      line(phase, cd.t, cd.us);
+      if (cd.us < b->us) b = &cd;
+    }
+    *chosen = b->t;
+    return MPPI_OK;
+  };
+  auto sample_rollout = [&] {
+    hipError_t err = phase_sample(c);
+    return err == hipSuccess ? phase_rollout(c) : err;
+  };
+  mppi_status st;
   if (c->batch) {
     // the tile size shapes both the noise and the rollout launch
+    std::vector<mppi_tuning> cands;
     for (int tile : {64, 128, 256}) {
       mppi_tuning t = c->tune;
       t.batch_tile = tile;
-      mppi_status st = mppi_set_tuning(c, &t);
-      if (st != MPPI_OK) return done(st);
-      e = time_it([&] {
-        hipError_t err = phase_sample(c);
-        return err == hipSuccess ? phase_rollout(c) : err;
-      }, &us);
-      if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
-      line("sample+rollout", t, us);
-      if (us < best_us) { best_us = us; best = t; }
+      cands.push_back(t);
     }
+    st = search("sample+rollout", cands, sample_rollout, &best);
+    if (st != MPPI_OK) return done(st);
   } else {
+    std::vector<mppi_tuning> cands;
     for (int calls : {1, 2, 4}) {
       mppi_tuning t = c->tune;
       t.noise_calls = calls;
-      mppi_status st = mppi_set_tuning(c, &t);
-      if (st != MPPI_OK) return done(st);
-      e = time_it([&] { return phase_sample(c); }, &us);
-      if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
-      line("sample", t, us);
-      if (us < best_us) { best_us = us; best.noise_calls = calls; }
+      cands.push_back(t);
     }
-    if (!tiles) {
-      best_us = 1e300;
+    mppi_tuning pick;
+    st = search("sample", cands, [&] { return phase_sample(c); }, &pick);
+    if (st != MPPI_OK) return done(st);
+    best.noise_calls = pick.noise_calls;
+    st = mppi_set_tuning(c, &best);
+    if (st != MPPI_OK) return done(st);
+    cands.clear();
+    if (tiles && I.hidden >= 32) {
+      for (int block : {64, 4 * I.hidden}) {
+        mppi_tuning t = best;
+        t.rollout_block = block;
+        cands.push_back(t);
+      }
+    } else if (!tiles) {
       const bool quad_ok = rollout_quad_available(I.cfg.dynamics, I.cfg.integrator);
       for (int lanes : {1, 4, 8, 16}) {
         if (lanes > 1 && !quad_ok) continue;
         for (int block : {64, 128, 256}) {
-          mppi_tuning t = c->tune;
+          mppi_tuning t = best;
           t.lanes_per_sample = lanes;
           t.rollout_block = block;
-          mppi_status st = mppi_set_tuning(c, &t);
-          if (st != MPPI_OK) return done(st);
-          e = time_it([&] { return phase_rollout(c); }, &us);
-          if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
-          line("rollout", t, us);
-          if (us < best_us) {
-            best_us = us;
-            best.lanes_per_sample = lanes;
-            best.rollout_block = block;
-          }
+          cands.push_back(t);
         }
       }
     }
+    if (!cands.empty()) {
+      e = phase_sample(c);  // the rollouts read this iteration's noise
+      if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
+      st = search("rollout", cands, [&] { return phase_rollout(c); }, &pick);
+      if (st != MPPI_OK) return done(st);
+      best.lanes_per_sample = pick.lanes_per_sample;
+      best.rollout_block = pick.rollout_block;
+    }
   }
-  mppi_status st = mppi_set_tuning(c, &best);
+  st = mppi_set_tuning(c, &best);
   if (st != MPPI_OK) return done(st);
   // the noise and cost buffers now hold this iteration's sampling and rollout
   e = phase_sample(c);
@@ -1091,7 +1128,8 @@ mppi_status mppi_backward(mppi_ctx* c, const float* d_dL_dU, float* d_grad) {
   hipError_t e = launch_adjoint(I.dp, (I.cfg.flags & MPPI_F_ACCURATE_TRIG) != 0, I.hidden, d_dL_dU,
                                 I.at<float>(I.L.u_roll), I.eps(), I.L.ldk, I.K, I.T, I.e(),
                                 I.cfg.lambda, I.at<float>(I.L.ckpt), I.ckpt_every,
-                                I.at<char>(I.L.adj), I.L.adj_layout, I.n_theta, d_grad, c->stream);
+                                I.at<char>(I.L.adj), I.L.adj_layout, I.n_theta, d_grad, c->stream,
+                                c->tune.rollout_block > kWave);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return MPPI_OK;
 }

@@ -20,7 +20,7 @@ __global__ __launch_bounds__(256) void noise_kernel(uint32_t key0, uint32_t key1
                                                     int calls) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  const uint32_t it = d_iteration ? *d_iteration : iteration;
+  const uint32_t it = d_iteration ? *d_iteration + iteration : iteration;
   const int ncall = (TM + 3) / 4;
   const int c0 = blockIdx.y * calls;
   for (int c = c0; c < c0 + calls && c < ncall; ++c)

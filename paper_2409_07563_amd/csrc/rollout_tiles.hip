@@ -76,6 +76,114 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
   if (g == 0 && live) S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
 }
 
+// The same rollout with the MLP split over MT waves of one workgroup (H =
+// 16 MT hidden units): wave w owns M-tile w of both hidden layers and K-tile w
+// of the output layer.  Per step the waves exchange their h1 tiles and their
+// partial outputs through LDS (double-buffered by step parity, two barriers).
+// Every per-element accumulation runs in the same order as in the one-wave
+// kernel (layer 2: K-steps (tt, i) in order; output: K-tile partials summed
+// 0, 1, ..., MT-1), so the results are bitwise the same; the waves of a tile
+// repeat its bicycle step and cost.  MT times as many waves keep more SIMDs
+// busy, and each wave's matrix-core work overlaps another wave's VALU work.
+template <int MT, int INTEG, class Cost, bool FAST>
+__global__ __launch_bounds__(kWave * MT) void rollout_tile_split_kernel(
+    DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
+    const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
+    float* __restrict__ ckpt, int ckpt_every) {
+  using Model = Bicycle<FAST>;
+  using f4 = mlp::f4;
+  using P = mlp::Pack<MT>;
+  constexpr int N = Model::N, M = Model::M;
+  __shared__ f4 xh[2][MT][kWave];  // h1 tiles
+  __shared__ f4 xg[2][MT][kWave];  // output partials
+  extern __shared__ float4 lds[];
+  const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int n = lane % kTile, g = lane / kTile;
+  const int k = blockIdx.x * kTile + n;
+  const bool live = k < K;
+  NoiseAhead<M> ahead;
+  ahead.init(eps + (live ? k : K - 1), ldk, T);
+  // this wave's operands
+  const float* pk = p.mlp + lane;
+  auto at = [&](int row) { return pk[row * kWave]; };
+  float w1[2], w2[MT][4], w3[4];
+  f4 b1, b2, b3;
+  w1[0] = at(P::kW1 + 2 * w);
+  w1[1] = at(P::kW1 + 2 * w + 1);
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w2[tt][i] = at(P::kW2 + (w * MT + tt) * 4 + i);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    w3[i] = at(P::kW3 + 4 * w + i);
+    b1[i] = at(P::kB1 + 4 * w + i);
+    b2[i] = at(P::kB2 + 4 * w + i);
+    b3[i] = w == 0 ? at(P::kB3 + i) : 0.0f;
+  }
+  float x[N], comp[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
+  typename Cost::State cs;
+  Cost::init(cs, x, p, lds);
+  float sum = 0.0f, sum_c = 0.0f;
+  int next_ckpt = 0;
+  float* ck = ckpt ? ckpt + k : nullptr;
+  for (int t = 0; t < T; ++t) {
+    const int par = t & 1;
+    float v[M];
+    ahead.pop(t, v);
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + v[j];
+    if (ck && t == next_ckpt) {
+      if (w == 0 && g == 0 && live) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) ck[i * ldk] = x[i];
+        ck[5 * ldk] = comp[0];
+        ck[6 * ldk] = comp[1];
+      }
+      ck += kCkptWords * ldk;
+      next_ckpt += ckpt_every;
+    }
+    // layer 1, tile w
+    const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
+    const f4 h1w = mlp::tanh4(mlp::mfma(w1[1], z1, mlp::mfma(w1[0], z0, b1)));
+    xh[par][w][lane] = h1w;
+    __syncthreads();
+    f4 h1[MT];
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt) h1[tt] = tt == w ? h1w : xh[par][tt][lane];
+    // layer 2, tile w, over all of h1
+    f4 acc = b2;
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc = mlp::mfma(w2[tt][i], h1[tt][i], acc);
+    const f4 h2w = mlp::tanh4(acc);
+    // output, K-tile w
+    f4 part = b3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part = mlp::mfma(w3[i], h2w[i], part);
+    xg[par][w][lane] = part;
+    __syncthreads();
+    f4 out = xg[par][0][lane];
+#pragma unroll
+    for (int tt = 1; tt < MT; ++tt) out += xg[par][tt][lane];
+    float res[N];
+    mlp::broadcast5(out, n, res);
+    step<Model, INTEG>(x, v, comp, p, res);
+    bool hit;
+    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    const float y = l - sum_c;
+    const float s = sum + y;
+    sum_c = (s - sum) - y;
+    sum = s;
+  }
+  sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
+  if (w == 0 && g == 0 && live) S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
+}
+
 namespace {
 
 using TileFn = void (*)(DevParams, const float*, const float*, const float*, int64_t, int, int,
@@ -94,6 +202,23 @@ TileFn pick_tile(uint32_t integrator, uint32_t cost, bool accurate) {
     return accurate ? pick_cost<MT, kRK4, false>(cost) : pick_cost<MT, kRK4, true>(cost);
   if (integrator == MPPI_INT_EULER)
     return accurate ? pick_cost<MT, kEuler, false>(cost) : pick_cost<MT, kEuler, true>(cost);
+  return nullptr;
+}
+
+template <int MT, int INTEG, bool FAST>
+TileFn pick_split_cost(uint32_t cost) {
+  if (cost == MPPI_COST_TRACK) return rollout_tile_split_kernel<MT, INTEG, CostTrack, FAST>;
+  if (cost == MPPI_COST_QUADRATIC) return rollout_tile_split_kernel<MT, INTEG, CostQuadratic, FAST>;
+  return nullptr;
+}
+
+template <int MT>
+TileFn pick_split(uint32_t integrator, uint32_t cost, bool accurate) {
+  if (integrator == MPPI_INT_RK4)
+    return accurate ? pick_split_cost<MT, kRK4, false>(cost) : pick_split_cost<MT, kRK4, true>(cost);
+  if (integrator == MPPI_INT_EULER)
+    return accurate ? pick_split_cost<MT, kEuler, false>(cost)
+                    : pick_split_cost<MT, kEuler, true>(cost);
   return nullptr;
 }
 
@@ -118,8 +243,15 @@ bool rollout_tiles_supported(uint32_t dynamics, uint32_t integrator, uint32_t co
 hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                                 bool accurate_trig, const DevParams& p, const float* d_x0,
                                 const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
-                                float* d_S, float* d_ckpt, int ckpt_every, hipStream_t stream) {
-  TileFn fn = select_tile(dynamics, integrator, cost, accurate_trig, p.mlp_hidden);
+                                float* d_S, float* d_ckpt, int ckpt_every, hipStream_t stream,
+                                bool split) {
+  // the split form exists for H = 32 and 64 (two and four waves per tile)
+  const int waves = split && dynamics == MPPI_DYN_BICYCLE_MLP && p.mlp_hidden >= 32
+                        ? p.mlp_hidden / 16 : 1;
+  TileFn fn = nullptr;
+  if (waves == 4) fn = pick_split<4>(integrator, cost, accurate_trig);
+  else if (waves == 2) fn = pick_split<2>(integrator, cost, accurate_trig);
+  else fn = select_tile(dynamics, integrator, cost, accurate_trig, p.mlp_hidden);
   if (!fn || (d_ckpt && ckpt_every < 1)) return hipErrorInvalidValue;
   const size_t lds = sizeof(float) * static_cast<size_t>(T) * 2;
   if (lds > 48 * 1024) {
@@ -128,8 +260,8 @@ hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((K + kTile - 1) / kTile)), dim3(kWave), lds,
-                     stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S, d_ckpt, ckpt_every);
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((K + kTile - 1) / kTile)), dim3(kWave * waves),
+                     lds, stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S, d_ckpt, ckpt_every);
   return hipGetLastError();
 }
 

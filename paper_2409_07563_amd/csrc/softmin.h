@@ -46,28 +46,67 @@ __device__ __forceinline__ float block_sum(float v, float* lds) {
   return r;
 }
 
+// Sum of two values over the workgroup in one pass (fixed order).
+template <int NW>
+__device__ __forceinline__ void block_sum2(float& a, float& b, float2* lds) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) lds[wv] = float2{a, b};
+  __syncthreads();
+  float2 r = lds[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) { r.x += lds[i].x; r.y += lds[i].y; }
+  a = r.x;
+  b = r.y;
+}
+
 // One workgroup of kWeightsBlock threads per instance.  Also advances the
-// instance's iteration word (read by the next sampling step).
+// instance's iteration word (read by the next sampling step).  Up to
+// kWeightsCache costs per thread (K <= 16384) stay in registers between the
+// min pass and the exponential pass.
+constexpr int kWeightsCache = 16;
 __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K, float lambda,
                                              float inv_lambda, float* __restrict__ e,
                                              DevState* __restrict__ st) {
   constexpr int NW = kWeightsBlock / kWave;
   __shared__ float lds[NW];
+  __shared__ float2 lds2[NW];
+  const bool cached = K <= kWeightsCache * kWeightsBlock;
+  float sv[kWeightsCache];
   float m = __builtin_inff();
-  for (int k = threadIdx.x; k < K; k += kWeightsBlock) m = fminf(m, S[k]);
+  if (cached) {
+#pragma unroll
+    for (int q = 0; q < kWeightsCache; ++q) {
+      const int k = threadIdx.x + q * kWeightsBlock;
+      sv[q] = k < K ? S[k] : __builtin_inff();
+      m = fminf(m, sv[q]);
+    }
+  } else {
+    for (int k = threadIdx.x; k < K; k += kWeightsBlock) m = fminf(m, S[k]);
+  }
   const float rho = block_min<NW>(m, lds);
   const bool finite = rho < __builtin_inff();
   float se = 0.0f, se2 = 0.0f;
-  for (int k = threadIdx.x; k < K; k += kWeightsBlock) {
-    const float s = S[k];
+  auto one = [&](int k, float s) {
     // non-finite J_k (NaN was turned into +inf by the rollout) gets weight 0
     const float ek = (finite && s < __builtin_inff()) ? expf((rho - s) * inv_lambda) : 0.0f;
     e[k] = ek;
     se += ek;
     se2 += ek * ek;
+  };
+  if (cached) {
+#pragma unroll
+    for (int q = 0; q < kWeightsCache; ++q) {
+      const int k = threadIdx.x + q * kWeightsBlock;
+      if (k < K) one(k, sv[q]);
+    }
+  } else {
+    for (int k = threadIdx.x; k < K; k += kWeightsBlock) one(k, S[k]);
   }
-  const float eta = block_sum<NW>(se, lds);
-  const float sum_e2 = block_sum<NW>(se2, lds);
+  block_sum2<NW>(se, se2, lds2);
+  const float eta = se, sum_e2 = se2;
   if (threadIdx.x == 0) {
     st->stats[0] = rho;
     st->stats[1] = finite ? eta : 0.0f;

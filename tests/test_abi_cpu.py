@@ -78,8 +78,9 @@ def test_batch_workspace_and_mismatch(abi):
     cfgs = (abi.Config * 5)(*[controller._config(w, False, False, "auto") for w in insts])
     params = (abi.Params * 5)(*[controller._params(w, keep) for w in insts])
     n = abi.lib().mppi_batch_workspace_bytes(cfgs, params, 5)
+    eps = sum(4 * w.T * w.m * ((w.K + 63) // 64 * 64) for w in insts)
     singles = sum(_bytes(abi, w)[0] for w in insts)
-    assert n > 0 and n >= 0.9 * singles
+    assert n > 0 and eps <= n and n >= 0.9 * singles
     assert abi.lib().mppi_batch_workspace_bytes(cfgs, params, 0) == 0
 
 

@@ -119,6 +119,29 @@ def test_autotune_batch_and_mlp(mppi):
     r = c.autotune(reps=2)
     assert r["tuning"]["lanes_per_sample"] == 16
     c.close()
+    c = mppi.Controller(W.c5(K=512, T=20, hidden=64))
+    r = c.autotune(reps=2)
+    assert r["tuning"]["rollout_block"] in (64, 256)
+    c.close()
+
+
+@pytest.mark.parametrize("H", [32, 64])
+def test_split_mlp_tile_is_bitwise_the_single_wave_tile(mppi, H):
+    """The MLP of a tile split over H/16 waves accumulates in the same order as
+    the one-wave form: the costs are bitwise equal, with and without
+    checkpoints."""
+    wl = W.c5(K=777, T=30, hidden=H)
+    out = []
+    for block in (64, 4 * H):
+        for grad in (False, True):
+            c = mppi.Controller(wl, requires_grad=grad)
+            c.set_tuning(rollout_block=block)
+            c.sample()
+            c.rollout()
+            out.append(_np(c.costs()))
+            c.close()
+    for o in out[1:]:
+        assert np.array_equal(o.view(np.uint32), out[0].view(np.uint32))
 
 
 def test_invalid_shapes_rejected(mppi):
@@ -134,4 +157,6 @@ def test_invalid_shapes_rejected(mppi):
     c = mppi.Controller(W.c5(K=64, T=10, hidden=16))
     with pytest.raises(MPPIError, match="16 lanes"):
         c.set_tuning(lanes_per_sample=1)
+    with pytest.raises(MPPIError, match="16 lanes"):
+        c.set_tuning(rollout_block=256)  # no split form for H = 16
     c.close()
