@@ -270,11 +270,13 @@ def bench_grad(args, wl):
     def measure(w):
         plain = M.Controller(w, device=dev)
         if not args.no_autotune:
-            plain.autotune(reps=3)
+            plain.autotune(reps=10)
+        tuning = plain.tuning()
         t_fwd = timed(plain.stream, lambda: plain.iterate(1), args.steps, args.warmup)
         t_noise, t_roll, t_upd = phase_times(plain, args.kernel_reps)
         plain.close()
         grad = M.Controller(w, device=dev, requires_grad=True)
+        grad.set_tuning(**tuning)  # the same launch shapes as the plain forward
         grad.iterate(1)
         G = (2.0 * (grad.controls() - uref)).contiguous()
         L = M.lib()
@@ -289,11 +291,11 @@ def bench_grad(args, wl):
                      args.steps, args.warmup)
         swept = int((grad.weights() > 0).sum())
         grad.close()
-        return t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept
+        return t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept, tuning
 
-    t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept = measure(wl)
+    t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept, tuning = measure(wl)
     dense = wl.replace(lam=500.0)
-    d_fwd, _, _, _, d_fb, d_fg, d_swept = measure(dense)
+    d_fwd, _, _, _, d_fb, d_fg, d_swept, _ = measure(dense)
 
     steps = wl.K * wl.T
     flops = 2.0 * mlp_macs(wl.mlp_hidden) * steps
@@ -308,6 +310,7 @@ def bench_grad(args, wl):
                    "dynamics": wl.model, "hidden": wl.mlp_hidden, "integrator": wl.integrator,
                    "cost": wl.cost, "lambda": wl.lam, "checkpoint_every": 10},
         "fwd_bwd_over_fwd": (t_fb) / t_fwd,
+        "tuning": tuning,
         "grad": {"fwd_plain_ms": t_fwd * 1e3, "fwd_checkpointing_ms": t_fg * 1e3,
                  "fwd_plus_bwd_ms": t_fb * 1e3, "bwd_ms": (t_fb - t_fg) * 1e3,
                  "samples_swept": swept,

@@ -225,8 +225,9 @@ typedef struct mppi_tuning {
                                gradient mode (fixed) */
   int32_t rollout_block;    /* threads per rollout workgroup: 64, 128 or 256; for MLP
                                dynamics and gradient mode 64 (one wave per 16-sample
-                               tile) or 4 H (the tile's MLP split over H/16 waves,
-                               H = 32, 64; the default there) */
+                               tile), or 128 / 256 (the tile's MLP split over 2
+                               waves, H = 32 and 64, or 4 waves, H = 64; the
+                               largest is the default) */
   int32_t batch_tile;       /* samples per work tile of a batch context: 64, 128 or 256 */
   int32_t noise_calls;      /* Philox calls per thread of the single-instance noise
                                kernel: 1, 2 or 4 */

@@ -457,20 +457,22 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   if (lane == 0) out[offQ + N] = sl;
 }
 
-// The sweep with the tile's MLP split over MT waves of one workgroup (H =
-// 16 MT): wave w owns hidden M-tile w in every product, with its operand
-// slices in registers (the weight packs need no LDS):
-//   forward rebuild: h1 tile w, then h2 tile w over all of h1 (h1 tiles
-//     exchanged through LDS), output partial over K-tile w (exchanged);
-//   reverse: da2 tile w = (W3^T c)[w] d2[w]; da1 tile w = (W2^T da2)[w] d1[w]
-//     over all da2 tiles (exchanged); dz partial over K-tile w (exchanged);
-//     dW2 row block w, dW1 row block w and dW3 column block w as outer
-//     products over the tile's samples (the activations of all waves meet in
-//     the shared transposition buffer).
+// The sweep with the tile's MLP split over SW waves of one workgroup (SW = 2
+// or 4, H = 16 MT): wave w owns the TW = MT / SW hidden M-tiles q0 = w TW, ...
+// in every product, with its operand slices in registers (the weight packs
+// need no LDS):
+//   forward rebuild: h1 of the own tiles, then h2 of the own tiles over all of
+//     h1 (h1 tiles exchanged through LDS), output partials of the own K-tiles
+//     (exchanged);
+//   reverse: da2 of the own tiles = (W3^T c) d2; da1 of the own tiles =
+//     (W2^T da2) d1 over all da2 tiles (exchanged); dz partials of the own
+//     K-tiles (exchanged); dW2 / dW1 rows and dW3 columns of the own tiles as
+//     outer products over the tile's samples (the activations of all waves
+//     meet in the shared transposition buffer).
 // Every accumulation runs in the order of the one-wave sweep, so the
 // gradient is bitwise the same; the bicycle step and its transpose are
 // repeated by every wave.
-template <int MT, bool FAST>
+template <int MT, int SW>
 struct SplitLds {
   static constexpr int P = 64 * MT + 16;
   static size_t bytes(int c) {
@@ -479,25 +481,28 @@ struct SplitLds {
   }
 };
 
-template <int MT, bool FAST>
-__global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
+template <int MT, int SW, bool FAST>
+__global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
     const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp,
     mlp::f4* __restrict__ pre) {
+  static_assert(MT % SW == 0, "tiles per wave");
+  constexpr int TW = MT / SW;
   using Model = Bicycle<FAST>;
   using f4 = mlp::f4;
   using PK = mlp::Pack<MT>;
-  constexpr int N = 5, M = 2, H = 16 * MT, PS = SplitLds<MT, FAST>::P;
+  constexpr int N = 5, M = 2, H = 16 * MT, PS = SplitLds<MT, SW>::P;
   const int base = blockIdx.x * kTileS;
   if (base >= meta->count) return;  // workgroup-uniform
   extern __shared__ float4 lds4[];
-  float* tb = reinterpret_cast<float*>(lds4);                         // [16][PS]
-  float* st_x = tb + kTileS * PS;                                     // states
+  float* tb = reinterpret_cast<float*>(lds4);                             // [16][PS]
+  float* st_x = tb + kTileS * PS;                                         // states
   f4* xa = reinterpret_cast<f4*>(st_x + kTileS * ((c + 1) * N + c * M));  // [2][MT][64]
-  f4* xb = xa + 2 * MT * kWave;                                       // [2][MT][64]
+  f4* xb = xa + 2 * MT * kWave;                                           // [2][MT][64]
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int n = lane % kTileS, g = lane / kTileS;
+  const int q0 = w * TW;
   float* xs = st_x + n * ((c + 1) * N);
   float* vs = st_x + kTileS * (c + 1) * N + n * (c * M);
   auto xch = [&](f4* buf, int par, int q) -> f4& { return buf[(par * MT + q) * kWave + lane]; };
@@ -505,27 +510,31 @@ __global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
   // this wave's operand slices
   const float* pf = p.mlp + lane;
   const float* pb = p.mlp_bwd + lane;
-  float fw1[2], fw2[MT][4], fw3[4], bw3t[2], bw2t[MT][4], bw1t[4];
-  f4 fb1, fb2, fb3;
+  float fw1[TW][2], fw2[TW][MT][4], fw3[TW][4], bw3t[TW][2], bw2t[TW][MT][4], bw1t[TW][4];
+  f4 fb1[TW], fb2[TW], fb3[TW];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    fw1[j] = pf[(PK::kW1 + 2 * w + j) * kWave];
-    bw3t[j] = pb[(PK::kW3t + 2 * w + j) * kWave];
-  }
+  for (int q = 0; q < TW; ++q) {
+    const int t = q0 + q;
 #pragma unroll
-  for (int tt = 0; tt < MT; ++tt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      fw2[tt][i] = pf[(PK::kW2 + (w * MT + tt) * 4 + i) * kWave];
-      bw2t[tt][i] = pb[(PK::kW2t + (w * MT + tt) * 4 + i) * kWave];
+    for (int j = 0; j < 2; ++j) {
+      fw1[q][j] = pf[(PK::kW1 + 2 * t + j) * kWave];
+      bw3t[q][j] = pb[(PK::kW3t + 2 * t + j) * kWave];
     }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    fw3[i] = pf[(PK::kW3 + 4 * w + i) * kWave];
-    bw1t[i] = pb[(PK::kW1t + 4 * w + i) * kWave];
-    fb1[i] = pf[(PK::kB1 + 4 * w + i) * kWave];
-    fb2[i] = pf[(PK::kB2 + 4 * w + i) * kWave];
-    fb3[i] = w == 0 ? pf[(PK::kB3 + i) * kWave] : 0.0f;
+    for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        fw2[q][tt][i] = pf[(PK::kW2 + (t * MT + tt) * 4 + i) * kWave];
+        bw2t[q][tt][i] = pb[(PK::kW2t + (t * MT + tt) * 4 + i) * kWave];
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fw3[q][i] = pf[(PK::kW3 + 4 * t + i) * kWave];
+      bw1t[q][i] = pb[(PK::kW1t + 4 * t + i) * kWave];
+      fb1[q][i] = pf[(PK::kB1 + 4 * t + i) * kWave];
+      fb2[q][i] = pf[(PK::kB2 + 4 * t + i) * kWave];
+      fb3[q][i] = t == 0 ? pf[(PK::kB3 + i) * kWave] : 0.0f;
+    }
   }
 
   // this tile's pre-activation scratch: [c steps][2 layers][MT][64 lanes] f4
@@ -538,9 +547,13 @@ __global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
   const float* e = eps + k;
 
   const f4 zero4{0.0f, 0.0f, 0.0f, 0.0f};
-  f4 dW1 = zero4, dW3 = zero4, db1 = zero4, db2 = zero4, dW2[MT];
+  f4 dW1[TW], dW3[TW], db1[TW], db2[TW], dW2[TW][MT];
 #pragma unroll
-  for (int q = 0; q < MT; ++q) dW2[q] = zero4;
+  for (int q = 0; q < TW; ++q) {
+    dW1[q] = dW3[q] = db1[q] = db2[q] = zero4;
+#pragma unroll
+    for (int nt = 0; nt < MT; ++nt) dW2[q][nt] = zero4;
+  }
   float db3[N], gQ[N], gL = 0.0f, mu[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { db3[i] = 0.0f; gQ[i] = 0.0f; mu[i] = 0.0f; }
@@ -567,26 +580,35 @@ __global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
         for (int q = 0; q < M; ++q) vs[j * M + q] = v[q];
       }
       // MLP forward, split (as the split forward kernel)
+      f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
       const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
-      const f4 a1w = mlp::mfma(fw1[1], z1, mlp::mfma(fw1[0], z0, fb1));
-      const f4 h1w = mlp::tanh4(a1w);
-      xch(xa, par, w) = h1w;
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        const f4 a1 = mlp::mfma(fw1[q][1], z1, mlp::mfma(fw1[q][0], z0, fb1[q]));
+        ps[(q0 + q) * kWave] = a1;
+        xch(xa, par, q0 + q) = mlp::tanh4(a1);
+      }
       __syncthreads();
-      f4 acc = fb2;
+      f4 acc[TW];
+#pragma unroll
+      for (int q = 0; q < TW; ++q) acc[q] = fb2[q];
 #pragma unroll
       for (int tt = 0; tt < MT; ++tt) {
-        const f4 h = tt == w ? h1w : xch(xa, par, tt);
+        const f4 h = xch(xa, par, tt);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc = mlp::mfma(fw2[tt][i], h[i], acc);
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(fw2[q][tt][i], h[i], acc[q]);
       }
-      const f4 h2w = mlp::tanh4(acc);
-      f4 part = fb3;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[i], h2w[i], part);
-      xch(xb, par, w) = part;
-      f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
-      ps[w * kWave] = a1w;
-      ps[(MT + w) * kWave] = acc;
+      for (int q = 0; q < TW; ++q) {
+        ps[(MT + q0 + q) * kWave] = acc[q];
+        const f4 h2 = mlp::tanh4(acc[q]);
+        f4 part = fb3[q];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[q][i], h2[i], part);
+        xch(xb, par, q0 + q) = part;
+      }
       __syncthreads();
       f4 out = xch(xb, par, 0);
 #pragma unroll
@@ -627,39 +649,55 @@ __global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
       float mu0[N];
       rk4_vjp<FAST>(p, xt, v, mu, mu0, gL);
       // the MLP residual dt g(z): c = dt mu_{t+1}
-      f4 h1w, d1w, h2w, d2w;
+      f4 h1[TW], d1[TW], h2[TW], d2[TW];
       {
         const f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
-        mlp::tanh4_d(ps[w * kWave], h1w, d1w);
-        mlp::tanh4_d(ps[(MT + w) * kWave], h2w, d2w);
+#pragma unroll
+        for (int q = 0; q < TW; ++q) {
+          mlp::tanh4_d(ps[(q0 + q) * kWave], h1[q], d1[q]);
+          mlp::tanh4_d(ps[(MT + q0 + q) * kWave], h2[q], d2[q]);
+        }
       }
       float cg[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) cg[i] = p.dt * mu[i];
       const float c0 = g == 0 ? cg[0] : g == 1 ? cg[1] : g == 2 ? cg[2] : cg[3];
       const float c1 = g == 0 ? cg[4] : 0.0f;
-      const f4 da2w = mlp::mfma(bw3t[1], c1, mlp::mfma(bw3t[0], c0, zero4)) * d2w;
-      xch(xa, par, w) = da2w;
+      f4 da2[TW];
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        da2[q] = mlp::mfma(bw3t[q][1], c1, mlp::mfma(bw3t[q][0], c0, zero4)) * d2[q];
+        xch(xa, par, q0 + q) = da2[q];
+      }
       __syncthreads();
-      f4 acc = zero4;
+      f4 acc[TW];
+#pragma unroll
+      for (int q = 0; q < TW; ++q) acc[q] = zero4;
 #pragma unroll
       for (int tt = 0; tt < MT; ++tt) {
-        const f4 d = tt == w ? da2w : xch(xa, par, tt);
+        const f4 d = xch(xa, par, tt);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc = mlp::mfma(bw2t[tt][i], d[i], acc);
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(bw2t[q][tt][i], d[i], acc[q]);
       }
-      const f4 da1w = acc * d1w;
-      f4 zp = zero4;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) zp = mlp::mfma(bw1t[i], da1w[i], zp);
-      xch(xb, par, w) = zp;
-      // the transposition buffer: this wave's rows, and z / c from wave 0
       float* row = tb + n * PS;
-      *reinterpret_cast<f4*>(row + 16 * w + 4 * g) = h1w;
-      *reinterpret_cast<f4*>(row + H + 16 * w + 4 * g) = h2w;
-      *reinterpret_cast<f4*>(row + 2 * H + 16 * w + 4 * g) = da1w;
-      *reinterpret_cast<f4*>(row + 3 * H + 16 * w + 4 * g) = da2w;
-      if (w == 0) {
+      f4 da1[TW];
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        da1[q] = acc[q] * d1[q];
+        f4 zp = zero4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) zp = mlp::mfma(bw1t[q][i], da1[q][i], zp);
+        xch(xb, par, q0 + q) = zp;
+        // the transposition buffer: the own rows
+        const int qt = q0 + q;
+        *reinterpret_cast<f4*>(row + 16 * qt + 4 * g) = h1[q];
+        *reinterpret_cast<f4*>(row + H + 16 * qt + 4 * g) = h2[q];
+        *reinterpret_cast<f4*>(row + 2 * H + 16 * qt + 4 * g) = da1[q];
+        *reinterpret_cast<f4*>(row + 3 * H + 16 * qt + 4 * g) = da2[q];
+      }
+      if (w == 0) {  // z and c
         const f4 zc = g == 0 ? f4{xt[0], xt[1], xt[2], xt[3]}
                     : g == 1 ? f4{xt[4], v[0], v[1], 0.0f}
                     : g == 2 ? f4{cg[0], cg[1], cg[2], cg[3]}
@@ -675,8 +713,11 @@ __global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
       mlp::broadcast5(dz, n, dzs);
 #pragma unroll
       for (int i = 0; i < N; ++i) mu0[i] += dzs[i];
-      db1 += da1w;
-      db2 += da2w;
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        db1[q] += da1[q];
+        db2[q] += da2[q];
+      }
       if (w == 0) {
 #pragma unroll
         for (int i = 0; i < N; ++i) db3[i] += cg[i];
@@ -684,15 +725,22 @@ __global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const float* tq = tb + (4 * s4 + g) * PS;
-        const float ad2 = tq[3 * H + 16 * w + n];
-        const float ad1 = tq[2 * H + 16 * w + n];
-        const float bh2 = tq[H + 16 * w + n];
         const float bz = tq[4 * H + n];
         const float ac = n < 8 ? tq[4 * H + 8 + n] : 0.0f;
+        float bh1[MT];
 #pragma unroll
-        for (int nt = 0; nt < MT; ++nt) dW2[nt] = mlp::mfma(ad2, tq[16 * nt + n], dW2[nt]);
-        dW1 = mlp::mfma(ad1, bz, dW1);
-        dW3 = mlp::mfma(ac, bh2, dW3);
+        for (int nt = 0; nt < MT; ++nt) bh1[nt] = tq[16 * nt + n];
+#pragma unroll
+        for (int q = 0; q < TW; ++q) {
+          const int qt = q0 + q;
+          const float ad2 = tq[3 * H + 16 * qt + n];
+          const float ad1 = tq[2 * H + 16 * qt + n];
+          const float bh2 = tq[H + 16 * qt + n];
+#pragma unroll
+          for (int nt = 0; nt < MT; ++nt) dW2[q][nt] = mlp::mfma(ad2, bh1[nt], dW2[q][nt]);
+          dW1[q] = mlp::mfma(ad1, bz, dW1[q]);
+          dW3[q] = mlp::mfma(ac, bh2, dW3[q]);
+        }
       }
       __syncthreads();  // the transposition buffer is rewritten by the next step
 #pragma unroll
@@ -706,16 +754,20 @@ __global__ __launch_bounds__(kWave * MT) void adjoint_sweep_split_kernel(
   const int oB1 = 7 * H, oW2 = 8 * H, oB2 = 8 * H + H * H, oW3 = 9 * H + H * H,
             oB3 = 14 * H + H * H, offQ = 14 * H + H * H + 5;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = 16 * w + 4 * g + i;
-    if (n < 7) out[r * 7 + n] = dW1[i];
+  for (int q = 0; q < TW; ++q) {
+    const int qt = q0 + q;
 #pragma unroll
-    for (int nt = 0; nt < MT; ++nt) out[oW2 + r * H + 16 * nt + n] = dW2[nt][i];
-    const int o = 4 * g + i;
-    if (o < 5) out[oW3 + o * H + 16 * w + n] = dW3[i];
-    const float s1 = group_sum(db1[i]);
-    const float s2 = group_sum(db2[i]);
-    if (n == 0) { out[oB1 + r] = s1; out[oB2 + r] = s2; }
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * qt + 4 * g + i;
+      if (n < 7) out[r * 7 + n] = dW1[q][i];
+#pragma unroll
+      for (int nt = 0; nt < MT; ++nt) out[oW2 + r * H + 16 * nt + n] = dW2[q][nt][i];
+      const int o = 4 * g + i;
+      if (o < 5) out[oW3 + o * H + 16 * qt + n] = dW3[q][i];
+      const float s1 = group_sum(db1[q][i]);
+      const float s2 = group_sum(db2[q][i]);
+      if (n == 0) { out[oB1 + r] = s1; out[oB2 + r] = s2; }
+    }
   }
   if (w == 0) {
 #pragma unroll
@@ -805,9 +857,10 @@ template <int MT>
 SweepFn pick_sweep(bool accurate) {
   return accurate ? adjoint_sweep_kernel<MT, false> : adjoint_sweep_kernel<MT, true>;
 }
-template <int MT>
+template <int MT, int SW>
 SweepFn pick_split_sweep(bool accurate) {
-  return accurate ? adjoint_sweep_split_kernel<MT, false> : adjoint_sweep_split_kernel<MT, true>;
+  return accurate ? adjoint_sweep_split_kernel<MT, SW, false>
+                  : adjoint_sweep_split_kernel<MT, SW, true>;
 }
 }  // namespace
 
@@ -815,16 +868,22 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, const float* d_ckpt, int ckpt_every,
                           char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
-                          hipStream_t stream, bool split) {
+                          hipStream_t stream, int waves) {
   SweepFn fn = nullptr;
-  const int waves = split && hidden >= 32 ? hidden / 16 : 1;
   size_t lds = adjoint_lds_bytes(hidden, ckpt_every);
-  if (waves == 4) {
-    fn = pick_split_sweep<4>(accurate_trig);
-    lds = SplitLds<4, true>::bytes(ckpt_every);
-  } else if (waves == 2) {
-    fn = pick_split_sweep<2>(accurate_trig);
-    lds = SplitLds<2, true>::bytes(ckpt_every);
+  if (waves > 1) {
+    if (hidden == 64 && waves == 4) {
+      fn = pick_split_sweep<4, 4>(accurate_trig);
+      lds = SplitLds<4, 4>::bytes(ckpt_every);
+    } else if (hidden == 64 && waves == 2) {
+      fn = pick_split_sweep<4, 2>(accurate_trig);
+      lds = SplitLds<4, 2>::bytes(ckpt_every);
+    } else if (hidden == 32 && waves == 2) {
+      fn = pick_split_sweep<2, 2>(accurate_trig);
+      lds = SplitLds<2, 2>::bytes(ckpt_every);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else {
     switch (hidden) {
       case 0: fn = pick_sweep<0>(accurate_trig); break;

@@ -128,12 +128,13 @@ hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState*
 
 // MLP residual dynamics and the checkpointing forward (rollout_tiles.hip)
 bool rollout_tiles_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int hidden);
-// split: the MLP of a 16-sample tile spread over H/16 waves (H = 32, 64)
+// waves: waves per 16-sample tile: 1, or the MLP split over 2 (H = 32, 64)
+// or 4 (H = 64) waves; hipErrorInvalidValue for other combinations
 hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                                 bool accurate_trig, const DevParams& p, const float* d_x0,
                                 const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                                 float* d_S, float* d_ckpt, int ckpt_every, hipStream_t stream,
-                                bool split = true);
+                                int waves = 1);
 
 // The adjoint (adjoint.hip).  Scratch: byte offsets inside one device region.
 struct AdjointScratch {
@@ -147,7 +148,7 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, const float* d_ckpt, int ckpt_every,
                           char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
-                          hipStream_t stream, bool split = true);
+                          hipStream_t stream, int waves = 1);
 
 hipError_t launch_batch_noise(const BatchPlan& b, hipStream_t stream);
 hipError_t launch_batch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,

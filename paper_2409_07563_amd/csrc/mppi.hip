@@ -690,7 +690,7 @@ hipError_t phase_rollout(mppi_ctx* c) {
     }
     return launch_rollout_tiles(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp, I.x0,
                                 I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,
-                                c->stream, c->tune.rollout_block > kWave);
+                                c->stream, c->tune.rollout_block / kWave);
   }
   return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.lanes, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
@@ -776,11 +776,14 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
     return fail(MPPI_EINVAL, "noise_calls must be 1, 2 or 4");
   Instance& I = c->inst[0];
   if (I.hidden || I.grad) {
-    const bool split_ok = I.hidden >= 32 && t->rollout_block == 4 * I.hidden;
+    // waves per 16-sample tile: 1, or the MLP split over 2 (H = 32, 64) or 4 (H = 64)
+    const int waves = t->rollout_block / kWave;
+    const bool split_ok = (I.hidden == 64 && (waves == 2 || waves == 4)) ||
+                          (I.hidden == 32 && waves == 2);
     if (t->lanes_per_sample != 16 || !(t->rollout_block == 64 || split_ok))
       return fail(MPPI_EUNSUPPORTED, "MLP dynamics and gradient mode use 16 lanes per sample "
-                  "and 64-thread workgroups (or 4 H threads, the MLP split over H/16 waves, "
-                  "for H = 32, 64)");
+                  "and 64-thread workgroups, or 128 / 256 threads with the MLP split over "
+                  "2 (H = 32, 64) or 4 (H = 64) waves");
   } else if (t->lanes_per_sample == 4 || t->lanes_per_sample == 8 ||
              t->lanes_per_sample == 16) {
     if (c->batch || !rollout_quad_available(I.cfg.dynamics, I.cfg.integrator))
@@ -893,7 +896,8 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     if (st != MPPI_OK) return done(st);
     cands.clear();
     if (tiles && I.hidden >= 32) {
-      for (int block : {64, 4 * I.hidden}) {
+      for (int block : {64, 128, 256}) {
+        if (block == 256 && I.hidden != 64) continue;
         mppi_tuning t = best;
         t.rollout_block = block;
         cands.push_back(t);
@@ -1129,7 +1133,7 @@ mppi_status mppi_backward(mppi_ctx* c, const float* d_dL_dU, float* d_grad) {
                                 I.at<float>(I.L.u_roll), I.eps(), I.L.ldk, I.K, I.T, I.e(),
                                 I.cfg.lambda, I.at<float>(I.L.ckpt), I.ckpt_every,
                                 I.at<char>(I.L.adj), I.L.adj_layout, I.n_theta, d_grad, c->stream,
-                                c->tune.rollout_block > kWave);
+                                c->tune.rollout_block / kWave);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return MPPI_OK;
 }

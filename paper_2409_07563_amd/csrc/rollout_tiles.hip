@@ -76,26 +76,29 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
   if (g == 0 && live) S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
 }
 
-// The same rollout with the MLP split over MT waves of one workgroup (H =
-// 16 MT hidden units): wave w owns M-tile w of both hidden layers and K-tile w
-// of the output layer.  Per step the waves exchange their h1 tiles and their
-// partial outputs through LDS (double-buffered by step parity, two barriers).
-// Every per-element accumulation runs in the same order as in the one-wave
-// kernel (layer 2: K-steps (tt, i) in order; output: K-tile partials summed
-// 0, 1, ..., MT-1), so the results are bitwise the same; the waves of a tile
-// repeat its bicycle step and cost.  MT times as many waves keep more SIMDs
-// busy, and each wave's matrix-core work overlaps another wave's VALU work.
-template <int MT, int INTEG, class Cost, bool FAST>
-__global__ __launch_bounds__(kWave * MT) void rollout_tile_split_kernel(
+// The same rollout with the MLP split over SW waves of one workgroup (SW = 2
+// or 4, H = 16 MT hidden units): wave w owns the MT / SW M-tiles q = w MT/SW
+// ... of both hidden layers and the same K-tiles of the output layer.  Per
+// step the waves exchange their h1 tiles and their per-K-tile output partials
+// through LDS (double-buffered by step parity, two barriers).  Every
+// per-element accumulation runs in the same order as in the one-wave kernel
+// (layer 2: K-steps (tt, i) in order; output: the K-tile partials summed 0,
+// 1, ..., MT-1), so the results are bitwise the same; the waves of a tile
+// repeat its bicycle step and cost.  More waves keep more SIMDs busy, and a
+// wave's matrix-core work overlaps another wave's VALU work.
+template <int MT, int SW, int INTEG, class Cost, bool FAST>
+__global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
     float* __restrict__ ckpt, int ckpt_every) {
+  static_assert(MT % SW == 0, "tiles per wave");
+  constexpr int TW = MT / SW;  // M-tiles per wave
   using Model = Bicycle<FAST>;
   using f4 = mlp::f4;
   using P = mlp::Pack<MT>;
   constexpr int N = Model::N, M = Model::M;
   __shared__ f4 xh[2][MT][kWave];  // h1 tiles
-  __shared__ f4 xg[2][MT][kWave];  // output partials
+  __shared__ f4 xg[2][MT][kWave];  // output partials per K-tile
   extern __shared__ float4 lds[];
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -104,23 +107,28 @@ __global__ __launch_bounds__(kWave * MT) void rollout_tile_split_kernel(
   const bool live = k < K;
   NoiseAhead<M> ahead;
   ahead.init(eps + (live ? k : K - 1), ldk, T);
-  // this wave's operands
+  // this wave's operands (tiles q0 .. q0 + TW - 1)
+  const int q0 = w * TW;
   const float* pk = p.mlp + lane;
   auto at = [&](int row) { return pk[row * kWave]; };
-  float w1[2], w2[MT][4], w3[4];
-  f4 b1, b2, b3;
-  w1[0] = at(P::kW1 + 2 * w);
-  w1[1] = at(P::kW1 + 2 * w + 1);
+  float w1[TW][2], w2[TW][MT][4], w3[TW][4];
+  f4 b1[TW], b2[TW], b3[TW];
 #pragma unroll
-  for (int tt = 0; tt < MT; ++tt)
+  for (int q = 0; q < TW; ++q) {
+    const int t = q0 + q;
+    w1[q][0] = at(P::kW1 + 2 * t);
+    w1[q][1] = at(P::kW1 + 2 * t + 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) w2[tt][i] = at(P::kW2 + (w * MT + tt) * 4 + i);
+    for (int tt = 0; tt < MT; ++tt)
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    w3[i] = at(P::kW3 + 4 * w + i);
-    b1[i] = at(P::kB1 + 4 * w + i);
-    b2[i] = at(P::kB2 + 4 * w + i);
-    b3[i] = w == 0 ? at(P::kB3 + i) : 0.0f;
+      for (int i = 0; i < 4; ++i) w2[q][tt][i] = at(P::kW2 + (t * MT + tt) * 4 + i);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      w3[q][i] = at(P::kW3 + 4 * t + i);
+      b1[q][i] = at(P::kB1 + 4 * t + i);
+      b2[q][i] = at(P::kB2 + 4 * t + i);
+      b3[q][i] = t == 0 ? at(P::kB3 + i) : 0.0f;
+    }
   }
   float x[N], comp[N];
 #pragma unroll
@@ -146,26 +154,34 @@ __global__ __launch_bounds__(kWave * MT) void rollout_tile_split_kernel(
       ck += kCkptWords * ldk;
       next_ckpt += ckpt_every;
     }
-    // layer 1, tile w
+    // layer 1, own tiles
     const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
-    const f4 h1w = mlp::tanh4(mlp::mfma(w1[1], z1, mlp::mfma(w1[0], z0, b1)));
-    xh[par][w][lane] = h1w;
-    __syncthreads();
-    f4 h1[MT];
 #pragma unroll
-    for (int tt = 0; tt < MT; ++tt) h1[tt] = tt == w ? h1w : xh[par][tt][lane];
-    // layer 2, tile w, over all of h1
-    f4 acc = b2;
+    for (int q = 0; q < TW; ++q)
+      xh[par][q0 + q][lane] = mlp::tanh4(mlp::mfma(w1[q][1], z1, mlp::mfma(w1[q][0], z0, b1[q])));
+    __syncthreads();
+    f4 h1[MT];  // every tile, the own ones included, read back from LDS
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt) h1[tt] = xh[par][tt][lane];
+    // layer 2, own tiles, over all of h1
+    f4 acc[TW];
+#pragma unroll
+    for (int q = 0; q < TW; ++q) acc[q] = b2[q];
 #pragma unroll
     for (int tt = 0; tt < MT; ++tt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc = mlp::mfma(w2[tt][i], h1[tt][i], acc);
-    const f4 h2w = mlp::tanh4(acc);
-    // output, K-tile w
-    f4 part = b3;
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) part = mlp::mfma(w3[i], h2w[i], part);
-    xg[par][w][lane] = part;
+        for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(w2[q][tt][i], h1[tt][i], acc[q]);
+    // output partials of the own K-tiles
+#pragma unroll
+    for (int q = 0; q < TW; ++q) {
+      const f4 h2 = mlp::tanh4(acc[q]);
+      f4 part = b3[q];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part = mlp::mfma(w3[q][i], h2[i], part);
+      xg[par][q0 + q][lane] = part;
+    }
     __syncthreads();
     f4 out = xg[par][0][lane];
 #pragma unroll
@@ -205,20 +221,22 @@ TileFn pick_tile(uint32_t integrator, uint32_t cost, bool accurate) {
   return nullptr;
 }
 
-template <int MT, int INTEG, bool FAST>
+template <int MT, int SW, int INTEG, bool FAST>
 TileFn pick_split_cost(uint32_t cost) {
-  if (cost == MPPI_COST_TRACK) return rollout_tile_split_kernel<MT, INTEG, CostTrack, FAST>;
-  if (cost == MPPI_COST_QUADRATIC) return rollout_tile_split_kernel<MT, INTEG, CostQuadratic, FAST>;
+  if (cost == MPPI_COST_TRACK) return rollout_tile_split_kernel<MT, SW, INTEG, CostTrack, FAST>;
+  if (cost == MPPI_COST_QUADRATIC)
+    return rollout_tile_split_kernel<MT, SW, INTEG, CostQuadratic, FAST>;
   return nullptr;
 }
 
-template <int MT>
+template <int MT, int SW>
 TileFn pick_split(uint32_t integrator, uint32_t cost, bool accurate) {
   if (integrator == MPPI_INT_RK4)
-    return accurate ? pick_split_cost<MT, kRK4, false>(cost) : pick_split_cost<MT, kRK4, true>(cost);
+    return accurate ? pick_split_cost<MT, SW, kRK4, false>(cost)
+                    : pick_split_cost<MT, SW, kRK4, true>(cost);
   if (integrator == MPPI_INT_EULER)
-    return accurate ? pick_split_cost<MT, kEuler, false>(cost)
-                    : pick_split_cost<MT, kEuler, true>(cost);
+    return accurate ? pick_split_cost<MT, SW, kEuler, false>(cost)
+                    : pick_split_cost<MT, SW, kEuler, true>(cost);
   return nullptr;
 }
 
@@ -244,14 +262,14 @@ hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t
                                 bool accurate_trig, const DevParams& p, const float* d_x0,
                                 const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                                 float* d_S, float* d_ckpt, int ckpt_every, hipStream_t stream,
-                                bool split) {
-  // the split form exists for H = 32 and 64 (two and four waves per tile)
-  const int waves = split && dynamics == MPPI_DYN_BICYCLE_MLP && p.mlp_hidden >= 32
-                        ? p.mlp_hidden / 16 : 1;
+                                int waves) {
+  // the split forms: H = 32 over 2 waves; H = 64 over 2 or 4 waves
+  const bool mlp = dynamics == MPPI_DYN_BICYCLE_MLP;
   TileFn fn = nullptr;
-  if (waves == 4) fn = pick_split<4>(integrator, cost, accurate_trig);
-  else if (waves == 2) fn = pick_split<2>(integrator, cost, accurate_trig);
-  else fn = select_tile(dynamics, integrator, cost, accurate_trig, p.mlp_hidden);
+  if (waves == 1) fn = select_tile(dynamics, integrator, cost, accurate_trig, p.mlp_hidden);
+  else if (mlp && p.mlp_hidden == 64 && waves == 4) fn = pick_split<4, 4>(integrator, cost, accurate_trig);
+  else if (mlp && p.mlp_hidden == 64 && waves == 2) fn = pick_split<4, 2>(integrator, cost, accurate_trig);
+  else if (mlp && p.mlp_hidden == 32 && waves == 2) fn = pick_split<2, 2>(integrator, cost, accurate_trig);
   if (!fn || (d_ckpt && ckpt_every < 1)) return hipErrorInvalidValue;
   const size_t lds = sizeof(float) * static_cast<size_t>(T) * 2;
   if (lds > 48 * 1024) {

@@ -63,47 +63,50 @@ __device__ __forceinline__ void block_sum2(float& a, float& b, float2* lds) {
 }
 
 // One workgroup of kWeightsBlock threads per instance.  Also advances the
-// instance's iteration word (read by the next sampling step).  Up to
-// kWeightsCache costs per thread (K <= 16384) stay in registers between the
-// min pass and the exponential pass.
-constexpr int kWeightsCache = 16;
+// instance's iteration word (read by the next sampling step).  The costs are
+// taken in chunks of kWeightsChunk per thread, every load of a chunk issued
+// before the first is used, so a pass costs a few memory latencies rather than
+// one per element; when K fits one chunk (K <= 32768) the costs stay in
+// registers between the min pass and the exponential pass.
+constexpr int kWeightsChunk = 32;
 __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K, float lambda,
                                              float inv_lambda, float* __restrict__ e,
                                              DevState* __restrict__ st) {
   constexpr int NW = kWeightsBlock / kWave;
+  constexpr int kSpan = kWeightsChunk * kWeightsBlock;  // costs per chunk
   __shared__ float lds[NW];
   __shared__ float2 lds2[NW];
-  const bool cached = K <= kWeightsCache * kWeightsBlock;
-  float sv[kWeightsCache];
-  float m = __builtin_inff();
-  if (cached) {
+  float sv[kWeightsChunk];
+  auto load_chunk = [&](int c0) {
 #pragma unroll
-    for (int q = 0; q < kWeightsCache; ++q) {
-      const int k = threadIdx.x + q * kWeightsBlock;
+    for (int q = 0; q < kWeightsChunk; ++q) {
+      const int k = c0 + threadIdx.x + q * kWeightsBlock;
       sv[q] = k < K ? S[k] : __builtin_inff();
-      m = fminf(m, sv[q]);
     }
-  } else {
-    for (int k = threadIdx.x; k < K; k += kWeightsBlock) m = fminf(m, S[k]);
+  };
+  float m = __builtin_inff();
+  for (int c0 = 0; c0 < K; c0 += kSpan) {
+    load_chunk(c0);
+#pragma unroll
+    for (int q = 0; q < kWeightsChunk; ++q) m = fminf(m, sv[q]);
   }
   const float rho = block_min<NW>(m, lds);
   const bool finite = rho < __builtin_inff();
   float se = 0.0f, se2 = 0.0f;
-  auto one = [&](int k, float s) {
-    // non-finite J_k (NaN was turned into +inf by the rollout) gets weight 0
-    const float ek = (finite && s < __builtin_inff()) ? expf((rho - s) * inv_lambda) : 0.0f;
-    e[k] = ek;
-    se += ek;
-    se2 += ek * ek;
-  };
-  if (cached) {
+  for (int c0 = 0; c0 < K; c0 += kSpan) {
+    if (K > kSpan) load_chunk(c0);  // one chunk: still in registers
 #pragma unroll
-    for (int q = 0; q < kWeightsCache; ++q) {
-      const int k = threadIdx.x + q * kWeightsBlock;
-      if (k < K) one(k, sv[q]);
+    for (int q = 0; q < kWeightsChunk; ++q) {
+      const int k = c0 + threadIdx.x + q * kWeightsBlock;
+      if (k < K) {
+        // non-finite J_k (NaN was turned into +inf by the rollout) gets weight 0
+        const float s = sv[q];
+        const float ek = (finite && s < __builtin_inff()) ? expf((rho - s) * inv_lambda) : 0.0f;
+        e[k] = ek;
+        se += ek;
+        se2 += ek * ek;
+      }
     }
-  } else {
-    for (int k = threadIdx.x; k < K; k += kWeightsBlock) one(k, S[k]);
   }
   block_sum2<NW>(se, se2, lds2);
   const float eta = se, sum_e2 = se2;

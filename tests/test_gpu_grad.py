@@ -321,16 +321,17 @@ def test_backward_state_errors(mppi):
 
 @pytest.mark.parametrize("H", [32, 64])
 def test_split_sweep_is_bitwise_the_single_wave_sweep(mppi, H):
-    """The adjoint with the tile's MLP split over H/16 waves accumulates in the
-    order of the one-wave sweep: the gradients are bitwise equal."""
+    """The adjoint with the tile's MLP split over 2 or 4 waves accumulates in
+    the order of the one-wave sweep: the gradients are bitwise equal."""
     import torch
     wl = _c5(600, 25, H).replace(lam=50.0)
     uref = torch.as_tensor(W.c5_uref(T=25), device="cuda")
     grads = []
-    for block in (64, 4 * H):
+    for block in ((64, 128) if H == 32 else (64, 128, 256)):
         c = mppi.Controller(wl, requires_grad=True, checkpoint_every=7)
         c.set_tuning(rollout_block=block)
         c.iterate(1)
         grads.append(c.backward(2.0 * (c.controls() - uref)))
         c.close()
-    assert torch.equal(grads[0], grads[1])
+    for gr in grads[1:]:
+        assert torch.equal(grads[0], gr)
