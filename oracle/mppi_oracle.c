@@ -236,6 +236,10 @@ typedef struct {
   int32_t map_w, map_h; /* costmap [map_h][map_w], cell centres on a grid */
   double map_x0, map_y0, map_res;
   const double* map;
+  /* importance-sampling term in the weights (1) or not (0), and the step
+   * size of the update (1: the plain MPPI update) */
+  int32_t is_beta;
+  double gamma;
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -561,6 +565,22 @@ static double terminal_cost(const orc_problem* P, const double* x) {
  * crash-decision margin and the number of crashed steps; slope[k] (optional)
  * the sum over steps of the costmap's |dM/dx| + |dM/dy| at the visited
  * positions (how strongly the cost reacts to a position error). */
+/* The importance-sampling term of one step (section "MPPI-Generic's MPPI
+ * Implementation" and Eq. information_theoretic_weighting): the sampling distribution N(u_t, Sigma)
+ * against the base distribution N(0, Sigma) gives ln p/s = -(v - u/2)' Sigma^-1
+ * u, and the weights use J - lambda beta ln p/s, i.e. J plus
+ * lambda (v - u/2)' Sigma^-1 u (Sigma diagonal). */
+static double is_term(const orc_problem* P, const double* u_t, const double* v) {
+  double s = 0.0;
+  for (int j = 0; j < P->m; ++j) {
+    const double sg = (double)P->sigma[j];
+    s += (v[j] - 0.5 * u_t[j]) * u_t[j] / (sg * sg);
+  }
+  return P->lambda * s;
+}
+
+/* S[k]: the cost J of sample k's rollout (Algorithm 1), plus the
+ * importance-sampling term when P->is_beta is set. */
 void orc_rollout_costs(const orc_problem* P, const double* x0, const double* u,
                        const float* eps, int64_t ldk, double* S, double* margin,
                        int32_t* crashes, double* slope) {
@@ -575,6 +595,7 @@ void orc_rollout_costs(const orc_problem* P, const double* x0, const double* u,
         v[j] = u[t * m + j] + (double)eps[((int64_t)t * m + j) * ldk + k];
       orc_step(P, x, v);
       J += running_cost(P, x, v, t, &mg, &cr, &sl);
+      if (P->is_beta) J += is_term(P, u + t * m, v);
     }
     J += terminal_cost(P, x);
     if (!isfinite(J)) J = INFINITY;
@@ -587,7 +608,10 @@ void orc_rollout_costs(const orc_problem* P, const double* x0, const double* u,
 
 /* Baseline, normaliser, weights and control update (the last two loops of
  * Algorithm 1):  rho = min J;  eta = sum exp(-(J - rho)/lambda);
- * w = exp(-(J - rho)/lambda)/eta;  U_t = u_t + sum_k w_k eps_{k,t}.
+ * w = exp(-(J - rho)/lambda)/eta;  U_t = u_t + gamma sum_k w_k eps_{k,t}
+ * (gamma = 1: Algorithm 1; otherwise the step size of the dynamic
+ * mirror-descent form U = (1 - gamma) u + gamma sum_k w_k v_k, section
+ * "Comparisons to sampling-efficient algorithms").
  * stats = (rho, eta, free-energy estimate rho - lambda ln(eta/K),
  * effective sample size 1/sum w^2).  Returns 0, or -6 when every J is
  * non-finite (then w = 0 and U = u). */
@@ -617,7 +641,7 @@ int orc_softmin_update(const orc_problem* P, const double* S, const float* eps,
       double acc = 0.0;
       const float* row = eps + ((int64_t)t * m + j) * ldk;
       for (int32_t k = 0; k < K; ++k) acc += w[k] * (double)row[k];
-      U[t * m + j] = u[t * m + j] + acc;
+      U[t * m + j] = u[t * m + j] + P->gamma * acc;
     }
   if (stats) {
     stats[0] = rho;

@@ -40,6 +40,7 @@ class OrcProblem(C.Structure):
         ("map_w", C.c_int32), ("map_h", C.c_int32),
         ("map_x0", C.c_double), ("map_y0", C.c_double), ("map_res", C.c_double),
         ("map", _dp),
+        ("is_beta", C.c_int32), ("gamma", C.c_double),
     ]
 
 
@@ -126,6 +127,8 @@ class Problem:
         for i in range(3):
             p.inertia[i] = float(np.float32(wl.inertia[i]))
         p.gravity = float(np.float32(wl.gravity))
+        p.is_beta = int(getattr(wl, "is_beta", 0))
+        p.gamma = float(np.float32(getattr(wl, "gamma", 1.0)))
         for i in range(32):
             p.w[i] = float(wl.w[i])
         self._keep = []

@@ -55,6 +55,8 @@ class Workload:
     w: np.ndarray
     iters: int = 1
     instance: int = 0
+    is_beta: int = 0      # importance-sampling term in the weights (0 or 1)
+    gamma: float = 1.0    # step size of the update (1: plain MPPI)
     wheelbase: float = 0.0
     mass: float = 0.0
     inertia: tuple = (0.0, 0.0, 0.0)
