@@ -931,7 +931,7 @@ int orc_backward(const orc_problem* P, const double* x0, const double* u, const 
       double d = 0.0;
       if (w[k] != 0.0)
         for (int32_t i = 0; i < K; ++i) d += w[i] * (g[k] - g[i]);
-      ak[k] = -(w[k] / P->lambda) * d;
+      ak[k] = -(P->gamma * w[k] / P->lambda) * d; /* U - u = gamma sum w eps */
     }
     double* xs = (double*)malloc(sizeof(double) * (T + 1) * n);
     double* vs = (double*)malloc(sizeof(double) * T * m);

@@ -65,6 +65,20 @@ def test_adjoint_vs_fd_plain_bicycle():
     assert np.all(np.isfinite(r["grad"]))
 
 
+@pytest.mark.parametrize("gamma", [0.6, 1.0])
+def test_adjoint_vs_fd_with_importance_sampling_and_step_size(gamma):
+    """The importance-sampling term does not depend on theta but reweights the
+    samples; the step size scales U - u and with it the gradient."""
+    wl = W.c5(K=48, T=15, hidden=8)
+    wl.u0 = np.random.default_rng(9).normal(0, 0.3, (wl.T, wl.m)).astype(np.float32)
+    wl = wl.replace(is_beta=1, gamma=gamma)
+    uref = W.c5_uref(T=15)
+    rng = np.random.default_rng(4)
+    n = O.n_grad(wl)
+    idx = sorted(set(int(i) for i in rng.integers(0, n - 6, 8))) + list(range(n - 6, n))
+    _check(wl, uref, idx)
+
+
 def test_adjoint_linear_in_loss_gradient():
     wl = W.c5(K=32, T=10, hidden=8)
     rng = np.random.default_rng(2)
