@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MPPI_ABI_VERSION 1u
+#define MPPI_ABI_VERSION 2u
 #define MPPI_MAX_STATE 16
 #define MPPI_MAX_CONTROL 8
 
@@ -120,11 +120,25 @@ enum {
   MPPI_F_ROLLOUT_QUAD = 8u,  /* force four lanes per sample (bicycle + RK4 only);
                                 by default the library picks four lanes per sample
                                 for the bicycle with RK4 when K <= 32768 */
-  MPPI_F_REQUIRES_GRAD = 16u /* keep what mppi_backward needs: the rollout stores
+  MPPI_F_REQUIRES_GRAD = 16u, /* keep what mppi_backward needs: the rollout stores
                                 state checkpoints every params.checkpoint_every
                                 steps and a copy of the controls it used (BICYCLE
                                 or BICYCLE_MLP with RK4 and the TRACK cost; not
                                 for batch contexts) */
+  MPPI_F_IMPORTANCE_SAMPLING = 32u,
+                             /* beta = 1 of the importance-sampling weight (section
+                                "MPPI-Generic's MPPI Implementation", Eq.
+                                information_theoretic_weighting): every step adds
+                                lambda (v_t - u_t/2)' Sigma^-1 u_t to the sample's
+                                cost, which is the cost the weights are formed from
+                                and mppi_get_debug(MPPI_DEBUG_COSTS) returns; needs
+                                every sigma > 0.  Without it beta = 0 (Algorithm 1) */
+  MPPI_F_STEP_SIZE = 64u     /* use config.step_size as the step size gamma >= 0 of
+                                the dynamic mirror-descent update (section
+                                "Comparisons to sampling-efficient algorithms"):
+                                U = (1 - gamma) u + gamma sum_k w_k v_k, computed as
+                                u + gamma sum_k w_k eps_k; mppi_backward scales its
+                                gradient to match.  Without it gamma = 1 */
 };
 
 typedef struct mppi_config {
@@ -142,6 +156,7 @@ typedef struct mppi_config {
   uint64_t seed;         /* Philox key */
   uint32_t instance;     /* Philox counter word 3 (independent streams) */
   uint32_t flags;        /* MPPI_F_* */
+  float step_size;       /* gamma, read only with MPPI_F_STEP_SIZE: finite, >= 0 */
 } mppi_config;
 
 /* Model and cost constants.  Every array pointer is host memory, read during

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmppi.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_CONTROL = 8
 
 MPPI_OK, MPPI_EINVAL, MPPI_ENOMEM, MPPI_EDEVICE, MPPI_ESTATE, MPPI_EUNSUPPORTED, \
@@ -29,6 +29,8 @@ F_ACCURATE_TRIG = 2
 F_ROLLOUT_LANE = 4
 F_ROLLOUT_QUAD = 8
 F_REQUIRES_GRAD = 16
+F_IMPORTANCE_SAMPLING = 32
+F_STEP_SIZE = 64
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
 PACKED_STATE, PACKED_CONTROLS, PACKED_SAMPLES, PACKED_NOISE = 0, 1, 2, 3
 
@@ -41,7 +43,8 @@ class Config(C.Structure):
                 ("num_samples", C.c_int32), ("horizon", C.c_int32),
                 ("state_dim", C.c_int32), ("control_dim", C.c_int32),
                 ("dt", C.c_float), ("lam", C.c_float), ("sigma", C.c_float * MAX_CONTROL),
-                ("seed", C.c_uint64), ("instance", C.c_uint32), ("flags", C.c_uint32)]
+                ("seed", C.c_uint64), ("instance", C.c_uint32), ("flags", C.c_uint32),
+                ("step_size", C.c_float)]
 
 
 class Params(C.Structure):

@@ -45,7 +45,12 @@ def _config(pb, debug: bool, accurate_trig: bool, rollout: str,
     cfg.instance = int(getattr(pb, "instance", 0))
     cfg.flags = ((_abi.F_DEBUG if debug else 0) | (_abi.F_ACCURATE_TRIG if accurate_trig else 0)
                  | {"auto": 0, "lane": _abi.F_ROLLOUT_LANE, "quad": _abi.F_ROLLOUT_QUAD}[rollout]
-                 | (_abi.F_REQUIRES_GRAD if requires_grad else 0))
+                 | (_abi.F_REQUIRES_GRAD if requires_grad else 0)
+                 | (_abi.F_IMPORTANCE_SAMPLING if getattr(pb, "is_beta", 0) else 0)
+                 | _abi.F_STEP_SIZE)
+    # always explicit (gamma = 1 is Algorithm 1): the instances of a batch
+    # share their flags but not their step sizes
+    cfg.step_size = float(np.float32(getattr(pb, "gamma", 1.0)))
     return cfg
 
 

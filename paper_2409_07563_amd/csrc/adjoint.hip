@@ -2,9 +2,10 @@
 // with respect to the dynamics parameters (MLP weights, wheelbase) and the
 // diagonal state weights Q of the tracking cost.
 //
-// With U = u + sum_k w_k eps_k, w = softmin(J / lambda) and u independent of
-// the parameters theta (Algorithm 1, Eq. for the update), G = dL/dU gives
-//   dL/dJ_k = a_k = -(w_k / lambda) (g_k - sum_i w_i g_i),  g_k = <G, eps_k>,
+// With U = u + gamma sum_k w_k eps_k (gamma = 1 in Algorithm 1, else the
+// step size of the mirror-descent form), w = softmin(J / lambda) and u
+// independent of the parameters theta, G = dL/dU gives
+//   dL/dJ_k = a_k = -(gamma w_k / lambda) (g_k - sum_i w_i g_i),  g_k = <G, eps_k>,
 //   dL/dtheta = sum_k a_k dJ_k/dtheta,
 // and dJ_k/dtheta comes from a reverse sweep of the costate mu_t = dJ_k/dx_t
 // through the discrete step (the four RK4 stages and the MLP residual) and
@@ -15,7 +16,7 @@
 //   scan:     eta, the block offsets, and the weighted mean of g taken
 //             relative to the minimiser's g_ref: d = sum_i w_i (g_i - g_ref);
 //   compact:  the list (k, a_k) of samples with nonzero weight, in k order,
-//             a_k = -(w_k / lambda) ((g_k - g_ref) - d).  The shift keeps
+//             a_k = -(gamma w_k / lambda) ((g_k - g_ref) - d).  The shift keeps
 //             g_k - sum_i w_i g_i accurate when one sample holds almost all
 //             the weight (there the plain difference cancels completely);
 //   sweep:    per tile of 16 listed samples, segment by segment from the
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kScanBlock) void adjoint_scan_kernel(
 }
 
 __global__ __launch_bounds__(kProjectSamples) void adjoint_compact_kernel(
-    const float* __restrict__ e, const float* __restrict__ gk, int K, float inv_lambda,
+    const float* __restrict__ e, const float* __restrict__ gk, int K, float scale,
     const int* __restrict__ offs, const BwdMeta* __restrict__ meta, BwdItem* __restrict__ list) {
   const int lane = threadIdx.x;
   const int k = blockIdx.x * kProjectSamples + lane;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(kProjectSamples) void adjoint_compact_kernel(
   if (!nz) return;
   const int rank = __popcll(mask & ((uint64_t{1} << lane) - 1u));
   const float w = static_cast<float>(static_cast<double>(ek) / meta->eta);
-  const float a = -(w * inv_lambda) * ((gk[k] - meta->gref) - meta->dbar);
+  const float a = -(w * scale) * ((gk[k] - meta->gref) - meta->dbar);  // scale = gamma/lambda
   list[offs[blockIdx.x] + rank] = BwdItem{k, a};
 }
 
@@ -866,8 +867,8 @@ SweepFn pick_split_sweep(bool accurate) {
 
 hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
-                          const float* d_e, float lambda, const float* d_ckpt, int ckpt_every,
-                          char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
+                          const float* d_e, float lambda, float step, const float* d_ckpt,
+                          int ckpt_every, char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
                           hipStream_t stream, int waves) {
   SweepFn fn = nullptr;
   size_t lds = adjoint_lds_bytes(hidden, ckpt_every);
@@ -914,7 +915,8 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   hipLaunchKernelGGL(adjoint_scan_kernel, dim3(1), dim3(kScanBlock), 0, stream, part, nb, d_e, gk,
                      K, offs, meta);
   hipLaunchKernelGGL(adjoint_compact_kernel, dim3(nb), dim3(kProjectSamples), 0, stream, d_e, gk,
-                     K, static_cast<float>(1.0 / static_cast<double>(lambda)), offs, meta, list);
+                     K, static_cast<float>(static_cast<double>(step) / static_cast<double>(lambda)),
+                     offs, meta, list);
   const int tiles = (K + kTileS - 1) / kTileS;
   hipLaunchKernelGGL(fn, dim3(tiles), dim3(kWave * waves), lds, stream, p, d_u, d_eps, ldk, T,
                      d_ckpt, ckpt_every, list, meta, partial, s.ngp, pre);

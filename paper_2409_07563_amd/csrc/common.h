@@ -45,6 +45,10 @@ struct DevParams {
   int map_w, map_h;
   float map_x0, map_y0, map_res, map_inv_res;
   const float* costmap;   // [map_h][map_w]
+  // importance-sampling term of a step: sum_j is_coef[j] (v_j - u_j/2) u_j with
+  // is_coef[j] = lambda / sigma_j^2 (added to the running cost when importance)
+  int importance;
+  float is_coef[MPPI_MAX_CONTROL];
 };
 
 // Largest circle grid the rollout kernel stages into LDS.
@@ -71,6 +75,7 @@ struct BatchInst {
   int64_t ldk;
   int K, T, TM;
   float lambda, inv_lambda;
+  float step;  // step size gamma of the update
   uint32_t key0, key1, instance;
   Sigma8 sigma;
   float* e;  // unnormalised weights exp(-(J_k - rho)/lambda) [ldk]
@@ -119,8 +124,9 @@ size_t rollout_lds_bytes(uint32_t dynamics, uint32_t cost, int stage_words4, int
 constexpr size_t kMaxRolloutLds = 160 * 1024;
 
 int gemv_rows_per_block();
+// step: the step size gamma of u += gamma sum_k w_k eps_k (1 for Algorithm 1)
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
-                                 int TM, float lambda, float* d_e, float* d_u,
+                                 int TM, float lambda, float step, float* d_e, float* d_u,
                                  DevState* d_state, hipStream_t stream);
 hipError_t launch_set_iteration(DevState* d_state, uint32_t iteration, hipStream_t stream);
 hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState* d_state,
@@ -146,7 +152,8 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_eve
 size_t adjoint_lds_bytes(int hidden, int ckpt_every);
 hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
-                          const float* d_e, float lambda, const float* d_ckpt, int ckpt_every,
+                          const float* d_e, float lambda, float step, const float* d_ckpt,
+                          int ckpt_every,
                           char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
                           hipStream_t stream, int waves = 1);
 

@@ -80,6 +80,10 @@ int pack_rows(int hidden, bool bwd) {
   }
 }
 bool wants_grad(const mppi_config* c) { return (c->flags & MPPI_F_REQUIRES_GRAD) != 0; }
+// The step size gamma of the update (1: Algorithm 1).
+float step_size(const mppi_config& c) {
+  return (c.flags & MPPI_F_STEP_SIZE) ? c.step_size : 1.0f;
+}
 int ckpt_every_of(const mppi_params* p) { return p->checkpoint_every ? p->checkpoint_every : 10; }
 
 // The MFMA operand packs of the MLP (lane layout in mlp.h) from the weight
@@ -154,6 +158,12 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
   for (int j = 0; j < m; ++j)
     if (!(c->sigma[j] >= 0.0f) || !isfinite(c->sigma[j]))
       return fail(MPPI_EINVAL, "sigma[%d] must be finite and >= 0", j);
+  if (c->flags & MPPI_F_IMPORTANCE_SAMPLING)
+    for (int j = 0; j < m; ++j)
+      if (!(c->sigma[j] > 0.0f))
+        return fail(MPPI_EINVAL, "MPPI_F_IMPORTANCE_SAMPLING needs sigma[%d] > 0", j);
+  if ((c->flags & MPPI_F_STEP_SIZE) && (!(c->step_size >= 0.0f) || !isfinite(c->step_size)))
+    return fail(MPPI_EINVAL, "step_size must be finite and >= 0");
   if (c->dynamics == MPPI_DYN_BICYCLE_MLP) {
     if (!p->mlp) return fail(MPPI_EINVAL, "MLP dynamics need the weight blob");
     if (p->mlp_hidden != 16 && p->mlp_hidden != 32 && p->mlp_hidden != 64)
@@ -508,6 +518,11 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* s
   d.mlp_hidden = I->hidden;
   d.mlp = I->hidden ? I->at<float>(I->L.mlp) : nullptr;
   d.mlp_bwd = I->hidden ? I->at<float>(I->L.mlp_bwd) : nullptr;
+  d.importance = (cfg->flags & MPPI_F_IMPORTANCE_SAMPLING) ? 1 : 0;
+  for (int j = 0; j < m && d.importance; ++j) {
+    const double sg = cfg->sigma[j];
+    d.is_coef[j] = static_cast<float>(static_cast<double>(cfg->lambda) / (sg * sg));
+  }
   d.nseg = S;
   d.ncirc = N;
   d.stage = I->at<float4>(I->L.stage);
@@ -623,6 +638,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
       b.ldk = I.L.ldk; b.K = I.K; b.T = I.T; b.TM = I.TM;
       b.lambda = cfgs[i].lambda;
       b.inv_lambda = static_cast<float>(1.0 / static_cast<double>(cfgs[i].lambda));
+      b.step = step_size(cfgs[i]);
       b.key0 = static_cast<uint32_t>(cfgs[i].seed);
       b.key1 = static_cast<uint32_t>(cfgs[i].seed >> 32);
       b.instance = cfgs[i].instance;
@@ -700,7 +716,8 @@ hipError_t phase_rollout(mppi_ctx* c) {
 hipError_t phase_update(mppi_ctx* c) {
   if (c->batch) return launch_batch_update(c->plan, c->stream);
   const Instance& I = c->one();
-  return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, I.e(), I.u, I.st,
+  return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, step_size(I.cfg),
+                               I.e(), I.u, I.st,
                                c->stream);
 }
 
@@ -1131,7 +1148,8 @@ mppi_status mppi_backward(mppi_ctx* c, const float* d_dL_dU, float* d_grad) {
   const Instance& I = c->one();
   hipError_t e = launch_adjoint(I.dp, (I.cfg.flags & MPPI_F_ACCURATE_TRIG) != 0, I.hidden, d_dL_dU,
                                 I.at<float>(I.L.u_roll), I.eps(), I.L.ldk, I.K, I.T, I.e(),
-                                I.cfg.lambda, I.at<float>(I.L.ckpt), I.ckpt_every,
+                                I.cfg.lambda, step_size(I.cfg), I.at<float>(I.L.ckpt),
+                                I.ckpt_every,
                                 I.at<char>(I.L.adj), I.L.adj_layout, I.n_theta, d_grad, c->stream,
                                 c->tune.rollout_block / kWave);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");

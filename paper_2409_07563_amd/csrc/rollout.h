@@ -65,6 +65,17 @@ struct NoiseAhead {
   }
 };
 
+// The importance-sampling term of one step (section "MPPI-Generic's MPPI
+// Implementation", Eq. information_theoretic_weighting, beta = 1):
+// lambda (v - u/2)' Sigma^-1 u with p.is_coef[j] = lambda / sigma_j^2.
+template <int M>
+__device__ __forceinline__ float is_term(const DevParams& p, const float* v, const float* u) {
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < M; ++j) s += (p.is_coef[j] * u[j]) * (v[j] - 0.5f * u[j]);
+  return s;
+}
+
 struct RolloutResult {
   float cost;
   int crashes;
@@ -94,7 +105,8 @@ __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
     for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + v[j];
     step<Model, INTEG>(x, v, comp, p);
     bool hit;
-    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
     if constexpr (COUNT) ncrash += hit ? 1 : 0;
     const float y = l - sum_c;
     const float s = sum + y;

@@ -166,7 +166,8 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
         if ((t & (L - 1)) == L - 1 || t + 1 == T) {
           if (lt >= 0) {
             bool hit;
-            const float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
+            float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
+            if (p.importance) l += is_term<M>(p, lv, lds_u + lt * M);
             if constexpr (COUNT) ncrash += hit ? 1 : 0;
             const float y = l - sum_c;
             const float s = sum + y;

@@ -66,7 +66,8 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
       step<Model, INTEG>(x, v, comp, p);
     }
     bool hit;
-    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
     const float y = l - sum_c;
     const float s = sum + y;
     sum_c = (s - sum) - y;
@@ -190,7 +191,8 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     mlp::broadcast5(out, n, res);
     step<Model, INTEG>(x, v, comp, p, res);
     bool hit;
-    const float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+    if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
     const float y = l - sum_c;
     const float s = sum + y;
     sum_c = (s - sum) - y;

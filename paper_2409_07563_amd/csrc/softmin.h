@@ -8,9 +8,9 @@
 //    eta = sum e_k and sum e_k^2, and records the statistics;
 //  * weighted noise: U[r] = u[r] + (sum_k e_k eps[r][k]) / eta, a matrix-vector
 //    product over the [T*m][ldk] noise.  A workgroup of four waves owns a row:
-//    its lanes stream the row with 16-byte loads along k (four in flight per
+//    its lanes stream the row with 16-byte loads along k (eight in flight per
 //    lane), accumulate privately, reduce once per wave and combine the four
-//    wave sums in a fixed order, so eps is read exactly once at HBM speed.
+//    wave sums in a fixed order, so eps is read exactly once.
 #pragma once
 
 #include "common.h"
@@ -121,50 +121,53 @@ __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K,
 }
 
 // Row r of the update, one workgroup of kGemvBlock threads:
-// u[r] += (sum_k e_k eps[r][k]) / eta.  The row starts 16-byte aligned (ldk is
+// u[r] += step * ((sum_k e_k eps[r][k]) / eta), step the step size gamma.  The row starts 16-byte aligned (ldk is
 // a multiple of 64); the last K mod 4 entries go through a scalar tail so the
-// unwritten padding of a row is never read.  When every cost was non-finite
-// (eta = 0) u is left unchanged.
+// unwritten padding of a row is never read.  Eight 16-byte loads of the row
+// (and eight of e) are in flight per lane, so a row of up to 8192 samples is
+// one memory round trip.  When every cost was non-finite (eta = 0) u is left
+// unchanged.
 __device__ __forceinline__ void gemv_row(const float* __restrict__ eps, int64_t ldk, int K,
                                          const float* __restrict__ e, const DevState* st,
-                                         float* __restrict__ u, int r) {
+                                         float* __restrict__ u, float step, int r) {
   constexpr int NW = kGemvBlock / kWave;
+  constexpr int kIn = 8;                     // loads in flight per lane and array
+  constexpr int kStride = 4 * kGemvBlock;    // floats per sweep of the workgroup
   __shared__ float part[NW];
   const int tid = threadIdx.x;
   const float* row = eps + static_cast<int64_t>(r) * ldk;
   const int K4 = K & ~3;
-  constexpr int kStride = 4 * kGemvBlock;  // floats per sweep of the workgroup
-  float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f;
+  float acc[kIn];
+#pragma unroll
+  for (int q = 0; q < kIn; ++q) acc[q] = 0.0f;
   int k = 4 * tid;
-  for (; k + 3 * kStride < K4; k += 4 * kStride) {
-    const float4 x0 = *reinterpret_cast<const float4*>(row + k);
-    const float4 x1 = *reinterpret_cast<const float4*>(row + k + kStride);
-    const float4 x2 = *reinterpret_cast<const float4*>(row + k + 2 * kStride);
-    const float4 x3 = *reinterpret_cast<const float4*>(row + k + 3 * kStride);
-    const float4 w0 = *reinterpret_cast<const float4*>(e + k);
-    const float4 w1 = *reinterpret_cast<const float4*>(e + k + kStride);
-    const float4 w2 = *reinterpret_cast<const float4*>(e + k + 2 * kStride);
-    const float4 w3 = *reinterpret_cast<const float4*>(e + k + 3 * kStride);
-    acc0 += w0.x * x0.x + w0.y * x0.y + w0.z * x0.z + w0.w * x0.w;
-    acc1 += w1.x * x1.x + w1.y * x1.y + w1.z * x1.z + w1.w * x1.w;
-    acc2 += w2.x * x2.x + w2.y * x2.y + w2.z * x2.z + w2.w * x2.w;
-    acc3 += w3.x * x3.x + w3.y * x3.y + w3.z * x3.z + w3.w * x3.w;
+  for (; k + (kIn - 1) * kStride < K4; k += kIn * kStride) {
+    float4 x[kIn], w[kIn];
+#pragma unroll
+    for (int q = 0; q < kIn; ++q) {
+      x[q] = *reinterpret_cast<const float4*>(row + k + q * kStride);
+      w[q] = *reinterpret_cast<const float4*>(e + k + q * kStride);
+    }
+#pragma unroll
+    for (int q = 0; q < kIn; ++q)
+      acc[q] += w[q].x * x[q].x + w[q].y * x[q].y + w[q].z * x[q].z + w[q].w * x[q].w;
   }
   for (; k < K4; k += kStride) {
     const float4 x = *reinterpret_cast<const float4*>(row + k);
     const float4 w = *reinterpret_cast<const float4*>(e + k);
-    acc0 += w.x * x.x + w.y * x.y + w.z * x.z + w.w * x.w;
+    acc[0] += w.x * x.x + w.y * x.y + w.z * x.z + w.w * x.w;
   }
-  if (K4 + tid < K) acc0 += e[K4 + tid] * row[K4 + tid];
-  const float acc = wave_sum((acc0 + acc1) + (acc2 + acc3));
-  if (tid % kWave == 0) part[tid / kWave] = acc;
+  if (K4 + tid < K) acc[0] += e[K4 + tid] * row[K4 + tid];
+  const float a = wave_sum(((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                           ((acc[4] + acc[5]) + (acc[6] + acc[7])));
+  if (tid % kWave == 0) part[tid / kWave] = a;
   __syncthreads();
   if (tid == 0) {
     float tot = part[0];
 #pragma unroll
     for (int i = 1; i < NW; ++i) tot += part[i];
     const float eta = st->stats[1];
-    if (eta > 0.0f) u[r] = u[r] + tot / eta;
+    if (eta > 0.0f) u[r] = u[r] + step * (tot / eta);
   }
 }
 

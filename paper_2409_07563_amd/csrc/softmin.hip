@@ -14,12 +14,12 @@ __global__ __launch_bounds__(kWeightsBlock) void weights_kernel_one(
 
 __global__ __launch_bounds__(kGemvBlock) void gemv_kernel_one(
     const float* __restrict__ eps, int64_t ldk, int K, const float* __restrict__ e,
-    const DevState* __restrict__ st, float* __restrict__ u) {
-  gemv_row(eps, ldk, K, e, st, u, blockIdx.x);
+    const DevState* __restrict__ st, float* __restrict__ u, float step) {
+  gemv_row(eps, ldk, K, e, st, u, step, blockIdx.x);
 }
 
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
-                                 int TM, float lambda, float* d_e, float* d_u,
+                                 int TM, float lambda, float step, float* d_e, float* d_u,
                                  DevState* d_state, hipStream_t stream) {
   const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
   hipLaunchKernelGGL(weights_kernel_one, dim3(1), dim3(kWeightsBlock), 0, stream, d_S, K, lambda,
@@ -27,7 +27,7 @@ hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t l
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(gemv_kernel_one, dim3(TM), dim3(kGemvBlock), 0, stream, d_eps, ldk, K, d_e,
-                     d_state, d_u);
+                     d_state, d_u, step);
   return hipGetLastError();
 }
 

@@ -20,8 +20,9 @@ Tolerances (the target is 1e-4 relative in binary32):
     (RK4 stages, the MLP's sums), COND_ULPS = 32 covers that with margin;
   * controls: |U_gpu - U_or| <= 1e-4 max(|U_or|_inf, |sigma|_inf) plus the
     change that the allowed cost deviation can cause through the softmin:
-    sum_k |dU/dJ_k| 1e-4 max(|J_k|, 1), dU_t/dJ_k = -(w_k/lambda)(eps_k,t -
-    sum_i w_i eps_i,t) (all computed from the oracle's own values).
+    sum_k |dU/dJ_k| 1e-4 max(|J_k|, 1), dU_t/dJ_k = -(gamma w_k/lambda)(eps_k,t -
+    sum_i w_i eps_i,t), gamma the step size (all computed from the oracle's own
+    values).
 """
 import numpy as np
 
@@ -42,7 +43,8 @@ def controls_tol(wl, S_or, w_or, eps, lam=None, cond=None):
     lam = float(np.float32(wl.lam if lam is None else lam))
     E = eps.astype(np.float64)                        # [T][m][K]
     mean = np.tensordot(E, w_or, axes=([2], [0]))     # sum_i w_i eps_i  [T][m]
-    dU = (w_or / lam) * np.abs(E - mean[:, :, None])  # |dU_t / dJ_k|     [T][m][K]
+    gamma = abs(float(np.float32(getattr(wl, "gamma", 1.0))))  # U - u = gamma sum w eps
+    dU = (gamma * w_or / lam) * np.abs(E - mean[:, :, None])  # |dU_t / dJ_k|  [T][m][K]
     prop = np.tensordot(dU, cost_tol(S_or, cond), axes=([2], [0]))
     scale = max(np.abs(wl.u0).max(), np.abs(wl.sigma).max())
     return REL * scale + prop
