@@ -240,6 +240,9 @@ typedef struct {
    * size of the update (1: the plain MPPI update) */
   int32_t is_beta;
   double gamma;
+  /* cosines chained ahead of every running cost, scaled by zero (the cost
+   * complexity experiment of the Results section); 0 = none */
+  int32_t cost_cosines;
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -482,6 +485,13 @@ static double running_cost(const orc_problem* P, const double* x,
                            const double* v, int t, double* margin,
                            int* crashed, double* slope) {
   const int n = P->n, m = P->m;
+  /* the inflation: cost_cosines nested cosines of 1, times zero */
+  double infl = 0.0;
+  if (P->cost_cosines > 0) {
+    double z = 1.0;
+    for (int32_t i = 0; i < P->cost_cosines; ++i) z = cos(z);
+    infl = 0.0 * z;
+  }
   double c = 0.0;
   switch (P->cost) {
     case ORC_COST_QUADRATIC:
@@ -522,7 +532,7 @@ static double running_cost(const orc_problem* P, const double* x,
       break;
     }
   }
-  return c;
+  return c + infl;
 }
 
 /* Terminal cost phi(x_T). */

@@ -40,7 +40,7 @@ class OrcProblem(C.Structure):
         ("map_w", C.c_int32), ("map_h", C.c_int32),
         ("map_x0", C.c_double), ("map_y0", C.c_double), ("map_res", C.c_double),
         ("map", _dp),
-        ("is_beta", C.c_int32), ("gamma", C.c_double),
+        ("is_beta", C.c_int32), ("gamma", C.c_double), ("cost_cosines", C.c_int32),
     ]
 
 
@@ -129,6 +129,7 @@ class Problem:
         p.gravity = float(np.float32(wl.gravity))
         p.is_beta = int(getattr(wl, "is_beta", 0))
         p.gamma = float(np.float32(getattr(wl, "gamma", 1.0)))
+        p.cost_cosines = int(getattr(wl, "cost_cosines", 0))
         for i in range(32):
             p.w[i] = float(wl.w[i])
         self._keep = []

@@ -1,4 +1,4 @@
-"""Pins of the oracle's two update options: the importance-sampling term
+"""Pins of the oracle's update options: the importance-sampling term
 (section "MPPI-Generic's MPPI Implementation", Eqs. info_theory_weighting and
 information_theoretic_weighting, beta in {0, 1}) and the step size gamma of
 the dynamic mirror-descent update (section "Comparisons to sampling-efficient
@@ -7,7 +7,9 @@ algorithms").
 The importance-sampling weight is p(V)/s(V|theta) with p the zero-mean and s
 the u-mean Gaussian of covariance diag(sigma^2); the tests evaluate it from
 the Gaussian densities themselves (scipy's log-pdf, mpmath's pdf), not from
-the closed form the oracle uses.
+the closed form the oracle uses.  The cost inflation of the cost-complexity
+experiment (Results section: nested cosines scaled by zero) must leave every
+cost unchanged.
 """
 import numpy as np
 import pytest
@@ -137,3 +139,13 @@ def test_step_size_scales_the_correction(oracle_lib):
         wg, Ug, _, _ = oracle_lib.softmin_update(wl.replace(gamma=g), S, eps)
         assert np.array_equal(wg, w1)
         assert np.allclose(Ug - u, g * (U1 - u), rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("make", [lambda: W.c2("circles", K=64, T=30, iters=1),
+                                  lambda: W.c3(K=32, T=20), lambda: W.c1(K=50, T=10)])
+def test_cost_inflation_adds_exactly_zero(oracle_lib, make):
+    wl = make()
+    eps = oracle_lib.workload_noise(wl)
+    S0, m0, c0 = oracle_lib.rollout_costs(wl, eps=eps)
+    S1, m1, c1 = oracle_lib.rollout_costs(wl.replace(cost_cosines=40), eps=eps)
+    assert np.array_equal(S0, S1) and np.array_equal(c0, c1)

@@ -57,6 +57,7 @@ class Workload:
     instance: int = 0
     is_beta: int = 0      # importance-sampling term in the weights (0 or 1)
     gamma: float = 1.0    # step size of the update (1: plain MPPI)
+    cost_cosines: int = 0 # cosines chained ahead of each running cost, times 0
     wheelbase: float = 0.0
     mass: float = 0.0
     inertia: tuple = (0.0, 0.0, 0.0)
