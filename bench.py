@@ -72,7 +72,8 @@ def rollout_ops_per_step(wl) -> int:
         cost = 40
     else:
         cost = 3 * wl.n + 2 * wl.m
-    return v_form + dyn + cost + kahan
+    # the cost-complexity load: one operation per nested cosine
+    return v_form + dyn + cost + kahan + int(getattr(wl, "cost_cosines", 0))
 
 
 def make_workload(name: str):
@@ -135,6 +136,18 @@ def phase_times(ctl, reps: int):
     return tuple(a / reps * 1e-3 for a in acc)
 
 
+def rollout_forms(tuned):
+    """Fastest autotuned rollout launch (us) of the fused and of the split form."""
+    if not tuned or "timings" not in tuned:
+        return None
+    best = {}
+    for r in tuned["timings"]:
+        if r["phase"] == "rollout":
+            name = "split" if r.get("form") == 1 else "fused"
+            best[name] = min(best.get(name, float("inf")), r["us"])
+    return best or None
+
+
 def cpu_baseline(wl, iters: int):
     import oracle
     t0 = time.perf_counter()
@@ -158,6 +171,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing the candidates")
+    ap.add_argument("--cost-cosines", type=int, default=0,
+                    help="nested cosines ahead of every running cost (the cost-complexity "
+                         "load of the paper's Results section)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run 3 device-to-device copies of this many MiB (a known "
                          "traffic reference for hardware byte counters)")
@@ -181,6 +197,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
     wl = make_workload(args.workload)
+    if args.cost_cosines:
+        wl = ([w.replace(cost_cosines=args.cost_cosines) for w in wl] if isinstance(wl, list)
+              else wl.replace(cost_cosines=args.cost_cosines))
     if isinstance(wl, list):
         return bench_batch(args, wl)
     if wl.model == "bicycle_mlp":
@@ -211,10 +230,12 @@ def main():
     ops = rollout_ops_per_step(wl) * steps_per_iter
     achieved = ops / t_roll
     traffic = traffic_record("rollout", args.workload)
+    split = ctl.tuning()["rollout_form"] == 1
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
-                "kernel": "rollout_kernel", "ops_per_rollout_step": rollout_ops_per_step(wl),
-                "launch_us": t_roll * 1e6}
+                "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS,
+                "traffic": None if split else traffic,
+                "kernel": "split_dynamics + split_cost" if split else "rollout_kernel",
+                "ops_per_rollout_step": rollout_ops_per_step(wl), "launch_us": t_roll * 1e6}
     eps_bytes = 4 * wl.T * wl.m * wl.K
     kernels = {
         "noise": {"us": t_noise * 1e6, "hbm_GBps": eps_bytes / t_noise / 1e9},
@@ -229,10 +250,12 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "K": wl.K, "T": wl.T, "iterations_per_step": I,
                    "dynamics": wl.model, "integrator": wl.integrator, "cost": wl.cost,
-                   "obstacles": 0 if wl.cx is None else len(wl.cx)},
+                   "obstacles": 0 if wl.cx is None else len(wl.cx),
+                   "cost_cosines": wl.cost_cosines},
         "fwd_bwd_over_fwd": None,
         "wall_s_timed": wall,
         "tuning": ctl.tuning(),
+        "rollout_forms_us": rollout_forms(tuned),
         "roofline": roofline,
         "kernels": kernels,
     }

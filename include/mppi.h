@@ -184,6 +184,10 @@ typedef struct mppi_params {
   const float* costmap;   /* [map_h][map_w] */
   int32_t checkpoint_every; /* MPPI_F_REQUIRES_GRAD: steps between state
                                checkpoints, 1..64 (0 = 10) */
+  int32_t cost_cosines;   /* 0..65536 nested cosines evaluated ahead of every running
+                             cost and scaled by zero: the synthetic cost-complexity
+                             load of the paper's Results section.  It changes no
+                             result, only the cost's computation time */
 } mppi_params;
 
 typedef struct mppi_ctx mppi_ctx;
@@ -230,9 +234,20 @@ mppi_status mppi_offsets(const mppi_ctx* ctx, int32_t what, int64_t* host_offset
 
 /* ---- launch shapes and the autotuner (spec extension) ------------------
  * How the kernels of a context are launched; none of it changes results
- * except lanes_per_sample, which selects a different (equally accurate)
- * rollout kernel.  The paper picks between its kernels by timing them
- * (Sec. III-C); mppi_autotune does the same over this table. */
+ * except lanes_per_sample and rollout_form, which select a different (equally
+ * accurate) rollout kernel.  The paper picks between its kernels by timing
+ * them (section "Choosing between the Split and Combined Kernels");
+ * mppi_autotune does the same over this table.
+ *
+ * The split form (section "Split Kernel Description") runs step (a2) as two
+ * kernels: the dynamics kernel integrates every sample over the horizon and
+ * writes its states x_1..x_T to a trajectory buffer in the workspace; the
+ * cost kernel then evaluates the running costs of all T steps in parallel
+ * (cost_waves waves per 64 samples, wave g taking the steps t = g,
+ * g + cost_waves, ...) and sums them per sample in a fixed order.  It exists
+ * for single contexts with DOUBLE_INTEGRATOR, BICYCLE or QUADROTOR dynamics
+ * (not for MLP dynamics, gradient mode or batches). */
+enum { MPPI_ROLLOUT_FUSED = 0, MPPI_ROLLOUT_SPLIT = 1 };
 typedef struct mppi_tuning {
   int32_t lanes_per_sample; /* rollout: 1, or 4, 8 or 16 (the bicycle with RK4, single
                                instance: RK4 stages across a quad, the running cost
@@ -246,12 +261,21 @@ typedef struct mppi_tuning {
   int32_t batch_tile;       /* samples per work tile of a batch context: 64, 128 or 256 */
   int32_t noise_calls;      /* Philox calls per thread of the single-instance noise
                                kernel: 1, 2 or 4 */
+  int32_t rollout_form;     /* MPPI_ROLLOUT_FUSED (default) or MPPI_ROLLOUT_SPLIT; in
+                               the split form lanes_per_sample (1, or 4 for the
+                               bicycle with RK4) and rollout_block shape the
+                               dynamics kernel */
+  int32_t cost_waves;       /* split form: waves that share the steps of 64 samples in
+                               the cost kernel, a power of two from 1 to 128 (up to
+                               16 in one workgroup; beyond, chunks of 16 waves whose
+                               partial sums a small kernel adds; default 8) */
 } mppi_tuning;
 
 /* The context's current launch shapes. */
 mppi_status mppi_get_tuning(const mppi_ctx* ctx, mppi_tuning* out);
 /* Apply launch shapes (EINVAL for a value outside its set; EUNSUPPORTED for
- * lanes_per_sample 4, 8 or 16 where no such kernel exists).  Rebuilds a batch's work
+ * lanes_per_sample 4, 8 or 16 where no such kernel exists, or the split form
+ * where it does not exist).  Rebuilds a batch's work
  * list (waits for the upload); captured iteration graphs are rebuilt on their
  * next use. */
 mppi_status mppi_set_tuning(mppi_ctx* ctx, const mppi_tuning* t);

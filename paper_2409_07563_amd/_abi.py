@@ -31,6 +31,7 @@ F_ROLLOUT_QUAD = 8
 F_REQUIRES_GRAD = 16
 F_IMPORTANCE_SAMPLING = 32
 F_STEP_SIZE = 64
+ROLLOUT_FUSED, ROLLOUT_SPLIT = 0, 1
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
 PACKED_STATE, PACKED_CONTROLS, PACKED_SAMPLES, PACKED_NOISE = 0, 1, 2, 3
 
@@ -55,12 +56,13 @@ class Params(C.Structure):
                 ("num_circles", C.c_int32), ("cx", _fp), ("cy", _fp), ("r2", _fp),
                 ("map_w", C.c_int32), ("map_h", C.c_int32), ("map_x0", C.c_float),
                 ("map_y0", C.c_float), ("map_res", C.c_float), ("costmap", _fp),
-                ("checkpoint_every", C.c_int32)]
+                ("checkpoint_every", C.c_int32), ("cost_cosines", C.c_int32)]
 
 
 class Tuning(C.Structure):
     _fields_ = [("lanes_per_sample", C.c_int32), ("rollout_block", C.c_int32),
-                ("batch_tile", C.c_int32), ("noise_calls", C.c_int32)]
+                ("batch_tile", C.c_int32), ("noise_calls", C.c_int32),
+                ("rollout_form", C.c_int32), ("cost_waves", C.c_int32)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}

@@ -2,7 +2,8 @@
 
 A choice is keyed by what decides it: the device architecture, the dynamics,
 integrator and cost, the number of samples rounded up to a power of two, the
-horizon, the MLP width and the number of batch instances.  The cache is a
+horizon, the MLP width, the number of batch instances and the cost's
+synthetic load (nested cosines).  The cache is a
 JSON object {key: {"tuning": {...}, "timings": [...]}} written atomically.
 """
 from __future__ import annotations
@@ -32,7 +33,8 @@ def key(ctl, arch_name: str | None = None) -> str:
     Ts = [int(q.T) for q in ctl.problems]
     return "|".join([arch_name or arch(ctl.device), pb.model, pb.integrator, pb.cost,
                      f"K{k_bucket(max(Ks))}", f"T{max(Ts)}", f"H{hidden}",
-                     f"n{ctl.n_inst}", f"sumKT{k_bucket(sum(k * t for k, t in zip(Ks, Ts)))}"])
+                     f"n{ctl.n_inst}", f"sumKT{k_bucket(sum(k * t for k, t in zip(Ks, Ts)))}",
+                     f"cos{int(getattr(pb, 'cost_cosines', 0))}"])
 
 
 def parse_report(text: str) -> list:

@@ -57,6 +57,7 @@ def _config(pb, debug: bool, accurate_trig: bool, rollout: str,
 def _params(pb, keep: list, checkpoint_every: int = 0) -> _abi.Params:
     p = _abi.Params()
     p.checkpoint_every = int(checkpoint_every)
+    p.cost_cosines = int(getattr(pb, "cost_cosines", 0))
 
     def arr(a):
         a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
@@ -234,7 +235,7 @@ class Controller:
 
     def set_tuning(self, **shape) -> None:
         """Change launch shapes (lanes_per_sample, rollout_block, batch_tile,
-        noise_calls); the others keep their values."""
+        noise_calls, rollout_form, cost_waves); the others keep their values."""
         t = _abi.Tuning()
         check(lib().mppi_get_tuning(self.ctx, C.byref(t)))
         for k, v in shape.items():

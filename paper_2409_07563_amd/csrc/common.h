@@ -49,6 +49,8 @@ struct DevParams {
   // is_coef[j] = lambda / sigma_j^2 (added to the running cost when importance)
   int importance;
   float is_coef[MPPI_MAX_CONTROL];
+  // nested cosines ahead of each running cost (a pure compute load)
+  int cosines;
 };
 
 // Largest circle grid the rollout kernel stages into LDS.
@@ -119,6 +121,24 @@ hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           float* d_S, int32_t* d_crashes, hipStream_t stream, int block = 64);
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
+
+// The split form of (a2) (split.hip): a dynamics kernel writes the states
+// x_1..x_T of every sample to d_traj ([T][traj_words][ldk], the state then,
+// for the costmap cost, the compensation of the position), a cost kernel
+// evaluates all steps in parallel.  lanes: 1, or 4 (bicycle, RK4); block:
+// dynamics threads per workgroup (64, 128, 256); waves: cost waves per 64
+// samples, a power of two up to kSplitMaxWaves * kSplitMaxChunks (up to 16 in
+// one workgroup, more as chunks of 16 whose partial sums go to d_part:
+// kSplitMaxChunks * ldk floats, then as many ints).
+constexpr int kSplitMaxWaves = 16, kSplitMaxChunks = 8;
+bool rollout_split_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
+int split_traj_words(uint32_t dynamics, uint32_t cost);
+hipError_t launch_rollout_split(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                                bool accurate_trig, int lanes, const DevParams& p,
+                                const float* d_x0, const float* d_u, const float* d_eps,
+                                int64_t ldk, int K, int T, float* d_traj, float* d_part,
+                                float* d_S, int32_t* d_crashes, hipStream_t stream, int block,
+                                int waves);
 // LDS bytes the rollout kernel stages (cost data + the nominal controls).
 size_t rollout_lds_bytes(uint32_t dynamics, uint32_t cost, int stage_words4, int T);
 constexpr size_t kMaxRolloutLds = 160 * 1024;

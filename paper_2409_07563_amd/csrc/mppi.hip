@@ -65,6 +65,10 @@ struct Layout {
   // the adjoint's scratch
   size_t ckpt, u_roll, adj;
   AdjointScratch adj_layout;
+  // split rollout form: the trajectory buffer [T][traj_words][ldk] and the
+  // cost chunks' partial sums and counts
+  size_t traj, split_part;
+  int traj_words;  // 0: no split form for this instance
   size_t total;
 };
 
@@ -185,6 +189,8 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
     if (p->checkpoint_every < 0 || p->checkpoint_every > 64)
       return fail(MPPI_EINVAL, "checkpoint_every %d outside [0, 64]", p->checkpoint_every);
   }
+  if (p->cost_cosines < 0 || p->cost_cosines > 65536)
+    return fail(MPPI_EINVAL, "cost_cosines %d outside [0, 65536]", p->cost_cosines);
   if (c->dynamics == MPPI_DYN_QUADROTOR) {
     if (!(p->mass > 0.0f)) return fail(MPPI_EINVAL, "mass must be > 0");
     for (int i = 0; i < 3; ++i)
@@ -225,7 +231,16 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
   return MPPI_OK;
 }
 
-Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m) {
+// The split rollout form exists for single, non-MLP, non-gradient contexts
+// whose cost kernel fits the LDS.
+bool split_form_for(const mppi_config* c, const mppi_params* p, bool batch) {
+  if (batch || wants_grad(c) || mlp_hidden_of(c, p) ||
+      !rollout_split_supported(c->dynamics, c->integrator, c->cost))
+    return false;
+  return true;
+}
+
+Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, bool batch) {
   (void)n;
   Layout L{};
   const int K = c->num_samples, T = c->horizon, TM = T * m;
@@ -251,6 +266,11 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m) {
     L.u_roll = take(sizeof(float) * TM);
     L.adj_layout = adjoint_scratch_layout(K, adjoint_grad_len(c->dynamics, H), H, ce);
     L.adj = take(L.adj_layout.total);
+  }
+  if (split_form_for(c, p, batch)) {
+    L.traj_words = split_traj_words(c->dynamics, c->cost);
+    L.traj = take(sizeof(float) * static_cast<size_t>(T) * L.traj_words * L.ldk);
+    L.split_part = take(2 * sizeof(float) * kSplitMaxChunks * static_cast<size_t>(L.ldk));
   }
   L.total = off;
   return L;
@@ -342,6 +362,7 @@ struct Instance {
   char* base;  // the instance's workspace slice
   DevParams dp;
   int lanes;   // lanes per sample of the single-instance rollout (1, 4, 8, 16)
+  bool split;  // the split rollout form is available
   bool grad;   // MPPI_F_REQUIRES_GRAD
   int hidden, ckpt_every, n_theta;
   // views into the context's packed regions
@@ -399,7 +420,7 @@ CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, in
   for (int i = 0; i < n_inst; ++i) {
     int n, m;
     model_dims(cfgs[i].dynamics, &n, &m);
-    C.slice[i] = take(make_layout(&cfgs[i], &params[i], n, m).total);
+    C.slice[i] = take(make_layout(&cfgs[i], &params[i], n, m, batch).total);
   }
   C.total = off;
   return C;
@@ -434,14 +455,14 @@ namespace {
 
 // Uploads one instance's parameter arrays into its slice and fills its
 // device constants.  Enqueued on `stream`; the caller synchronises.
-mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* slice,
+mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool batch, char* slice,
                            hipStream_t stream, Instance* I, std::vector<std::vector<float4>>* keep) {
   int n, m;
   mppi_status st = validate(cfg, p, &n, &m);
   if (st != MPPI_OK) return st;
   I->cfg = *cfg;
   I->n = n; I->m = m; I->K = cfg->num_samples; I->T = cfg->horizon; I->TM = I->T * m;
-  I->L = make_layout(cfg, p, n, m);
+  I->L = make_layout(cfg, p, n, m, batch);
   I->base = slice;
 
   // the staged cost block: circle grid, then spline coefficient rows, then knots
@@ -462,10 +483,13 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* s
     for (size_t q = 0; q < kn.size(); q += 4)
       stage.push_back(float4{kn[q], kn[q + 1], kn[q + 2], kn[q + 3]});
   }
-  if (rollout_lds_bytes(cfg->dynamics, cfg->cost, static_cast<int>(stage.size()), I->T) >
-      kMaxRolloutLds)
+  const size_t lds_need =
+      rollout_lds_bytes(cfg->dynamics, cfg->cost, static_cast<int>(stage.size()), I->T);
+  if (lds_need > kMaxRolloutLds)
     return fail(MPPI_EUNSUPPORTED, "cost data plus T*m controls exceed %zu bytes of LDS",
                 kMaxRolloutLds);
+  // the split form's cost kernel also holds 16 x 64 partial sums and counts
+  I->split = I->L.traj_words > 0 && lds_need + 2 * 16 * 64 * 4 <= kMaxRolloutLds;
   keep->emplace_back();
   std::vector<float4>& ref4 = keep->back();
   const int ref_len = p->ref ? p->ref_len : 1;
@@ -518,6 +542,7 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, char* s
   d.mlp_hidden = I->hidden;
   d.mlp = I->hidden ? I->at<float>(I->L.mlp) : nullptr;
   d.mlp_bwd = I->hidden ? I->at<float>(I->L.mlp_bwd) : nullptr;
+  d.cosines = p->cost_cosines;
   d.importance = (cfg->flags & MPPI_F_IMPORTANCE_SAMPLING) ? 1 : 0;
   for (int j = 0; j < m && d.importance; ++j) {
     const double sg = cfg->sigma[j];
@@ -605,7 +630,8 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   int64_t ox = 0, ou = 0, oS = 0;
   for (int i = 0; i < n_inst; ++i) {
     Instance& I = c->inst[i];
-    mppi_status s = setup_instance(&cfgs[i], &params[i], c->ws + C.slice[i], c->stream, &I, &keep);
+    mppi_status s =
+        setup_instance(&cfgs[i], &params[i], batch, c->ws + C.slice[i], c->stream, &I, &keep);
     if (s != MPPI_OK) { (void)hipStreamSynchronize(c->stream); delete c; return s; }
     I.st = reinterpret_cast<DevState*>(c->ws + C.states) + i;
     I.x0 = reinterpret_cast<float*>(c->ws + C.x0) + ox;
@@ -675,6 +701,8 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   c->tune.rollout_block = I0.hidden >= 32 ? 4 * I0.hidden : 64;
   c->tune.batch_tile = kBatchMaxTile;
   c->tune.noise_calls = 1;
+  c->tune.rollout_form = MPPI_ROLLOUT_FUSED;
+  c->tune.cost_waves = 8;
   if (e == hipSuccess && batch) e = upload_sample_tiles(c, c->tune.batch_tile);
   if (e != hipSuccess) { delete c; return hip_fail(e, "context upload"); }
   *out = c;
@@ -708,6 +736,12 @@ hipError_t phase_rollout(mppi_ctx* c) {
                                 I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,
                                 c->stream, c->tune.rollout_block / kWave);
   }
+  if (c->tune.rollout_form == MPPI_ROLLOUT_SPLIT)
+    return launch_rollout_split(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.lanes,
+                                I.dp, I.x0, I.u, I.eps(), I.L.ldk, I.K, I.T, I.at<float>(I.L.traj),
+                                I.at<float>(I.L.split_part), I.S, count ? I.crashes : nullptr,
+                                c->stream,
+                                c->tune.rollout_block, c->tune.cost_waves);
   return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.lanes, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
                         c->stream, c->tune.rollout_block);
@@ -791,7 +825,22 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
     return fail(MPPI_EINVAL, "rollout_block and batch_tile must be 64, 128 or 256");
   if (t->noise_calls != 1 && t->noise_calls != 2 && t->noise_calls != 4)
     return fail(MPPI_EINVAL, "noise_calls must be 1, 2 or 4");
+  const int cw = t->cost_waves;
+  if (cw < 1 || cw > kSplitMaxWaves * kSplitMaxChunks || (cw & (cw - 1)))
+    return fail(MPPI_EINVAL, "cost_waves must be a power of two from 1 to %d",
+                kSplitMaxWaves * kSplitMaxChunks);
+  if (t->rollout_form != MPPI_ROLLOUT_FUSED && t->rollout_form != MPPI_ROLLOUT_SPLIT)
+    return fail(MPPI_EINVAL, "rollout_form must be MPPI_ROLLOUT_FUSED or MPPI_ROLLOUT_SPLIT");
   Instance& I = c->inst[0];
+  if (t->rollout_form == MPPI_ROLLOUT_SPLIT) {
+    if (c->batch || !I.split)
+      return fail(MPPI_EUNSUPPORTED, "the split rollout form exists for single contexts with "
+                  "double-integrator, bicycle or quadrotor dynamics (no gradient mode)");
+    if (t->lanes_per_sample != 1 &&
+        !(t->lanes_per_sample == 4 && rollout_quad_available(I.cfg.dynamics, I.cfg.integrator)))
+      return fail(MPPI_EUNSUPPORTED, "split form: lanes_per_sample 1, or 4 for the bicycle "
+                  "with RK4");
+  }
   if (I.hidden || I.grad) {
     // waves per 16-sample tile: 1, or the MLP split over 2 (H = 32, 64) or 4 (H = 64)
     const int waves = t->rollout_block / kWave;
@@ -847,8 +896,9 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
   };
   auto line = [&](const char* phase, const mppi_tuning& t, double us) {
     char buf[160];
-    snprintf(buf, sizeof buf, "%s lanes=%d block=%d tile=%d calls=%d %.2f\n", phase,
-             t.lanes_per_sample, t.rollout_block, t.batch_tile, t.noise_calls, us);
+    snprintf(buf, sizeof buf, "%s lanes=%d block=%d tile=%d calls=%d form=%d waves=%d %.2f\n",
+             phase, t.lanes_per_sample, t.rollout_block, t.batch_tile, t.noise_calls,
+             t.rollout_form, t.cost_waves, us);
     text += buf;
   };
   // Each group of candidates shapes one phase; the candidates of a group are
@@ -925,11 +975,27 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
         if (lanes > 1 && !quad_ok) continue;
         for (int block : {64, 128, 256}) {
           mppi_tuning t = best;
+          t.rollout_form = MPPI_ROLLOUT_FUSED;
           t.lanes_per_sample = lanes;
           t.rollout_block = block;
           cands.push_back(t);
         }
       }
+      // the split form (section "Choosing between the Split and Combined
+      // Kernels": both are timed, the faster is kept)
+      if (I.split)
+        for (int lanes : {1, 4}) {
+          if (lanes > 1 && !quad_ok) continue;
+          for (int block : {64, 128, 256})
+            for (int waves : {2, 4, 8, 16, 32, 64, 128}) {
+              mppi_tuning t = best;
+              t.rollout_form = MPPI_ROLLOUT_SPLIT;
+              t.lanes_per_sample = lanes;
+              t.rollout_block = block;
+              t.cost_waves = waves;
+              cands.push_back(t);
+            }
+        }
     }
     if (!cands.empty()) {
       e = phase_sample(c);  // the rollouts read this iteration's noise
@@ -938,6 +1004,8 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
       if (st != MPPI_OK) return done(st);
       best.lanes_per_sample = pick.lanes_per_sample;
       best.rollout_block = pick.rollout_block;
+      best.rollout_form = pick.rollout_form;
+      best.cost_waves = pick.cost_waves;
     }
   }
   st = mppi_set_tuning(c, &best);

@@ -76,6 +76,15 @@ __device__ __forceinline__ float is_term(const DevParams& p, const float* v, con
   return s;
 }
 
+// The cost-complexity load of the paper's Results section: p.cosines nested
+// cosines of 1, scaled by zero, so it adds exactly +0 to a cost (the chain
+// stays positive) and costs only time.
+__device__ __forceinline__ float inflation(const DevParams& p) {
+  float z = 1.0f;
+  for (int i = 0; i < p.cosines; ++i) z = cosf(z);
+  return 0.0f * z;
+}
+
 struct RolloutResult {
   float cost;
   int crashes;
@@ -107,6 +116,7 @@ __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
     bool hit;
     float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
     if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
+    if (p.cosines) l += inflation(p);
     if constexpr (COUNT) ncrash += hit ? 1 : 0;
     const float y = l - sum_c;
     const float s = sum + y;

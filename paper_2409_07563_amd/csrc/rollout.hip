@@ -4,6 +4,7 @@
 // and the spline are staged once per workgroup into LDS, so no step waits on
 // a scalar or global load of them; the noise is requested a few steps ahead
 // of its use (NoiseAhead) so that its memory latency overlaps the arithmetic.
+#include "quad.h"
 #include "rollout.h"
 
 namespace mppi {
@@ -29,13 +30,8 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_kernel(
 // ---------------------------------------------------------------------------
 // Bicycle + RK4 with L = 4, 8 or 16 lanes per sample, the MI355X form of the
 // paper's intra-sample thread axis (Sec. III-C).  Within each DPP quad, lane
-// j = lane mod 4 evaluates RK4 stage j: for the kinematic bicycle the stage
-// yaw rates k_psi = s_j tan(steer_j) / L depend only on speed and steer,
-// which are linear in time over a step, so all four tan / sin / cos
-// evaluations run at once and one in-quad shift delivers k_psi of the
-// previous stage for yaw_j = yaw + c_j dt k_psi(j-1).  Three quad sums
-// assemble the RK4 increment; every lane ends with bitwise the same state
-// (binary32 addition commutes).  With L > 4 the quads of a sample repeat the
+// j = lane mod 4 evaluates RK4 stage j (bicycle_quad_step, quad.h); every
+// lane ends with bitwise the same state.  With L > 4 the quads of a sample repeat the
 // same dynamics and exist to share the running cost: lane s = lane mod L
 // latches the steps t = s (mod L), and every L steps all L lanes evaluate
 // their latched step at once, so the cost (the LDS-latency-bound spline and
@@ -47,16 +43,6 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_kernel(
 // into the register slot that step t has just used, and u of step t + 1 is
 // read from LDS during step t, so neither load stalls the step that needs it.
 // ---------------------------------------------------------------------------
-// quad_perm selectors: [1,0,3,2], [2,3,0,1] and the shift [0,0,1,2]
-constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E, kQuadShift = 0x90;
-template <int CTRL>
-__device__ __forceinline__ float quad_dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float quad_sum(float v) {
-  const float a = v + quad_dpp<kQuadSwap1>(v);
-  return a + quad_dpp<kQuadSwap2>(a);
-}
 // sum over the L lanes of a sample (every lane gets the same value)
 template <int L>
 __device__ __forceinline__ float group_sum(float v) {
@@ -80,7 +66,6 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
     int32_t* __restrict__ crashes) {
   static_assert(L == 4 || L == 8 || L == 16, "lanes per sample");
-  using Model = Bicycle<FAST>;
   constexpr int N = 5, M = 2;
   extern __shared__ float4 lds[];
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
@@ -128,33 +113,7 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
 #pragma unroll
           for (int c = 0; c < M; ++c) un[c] = lds_u[(t + 1) * M + c];
         }
-        // stage j of RK4
-        const float sj = x[3] + cdt * v[0];
-        const float dj = x[4] + cdt * v[1];
-        float tn;
-        if constexpr (FAST) {
-          tn = __sinf(dj) * __builtin_amdgcn_rcpf(__cosf(dj));
-        } else {
-          tn = tanf(dj);
-        }
-        const float kpsi = sj * tn * p.inv_wheelbase;
-        const float kprev = quad_dpp<kQuadShift>(kpsi);
-        const float yj = j == 0 ? x[2] : x[2] + cdt * kprev;
-        float sn, co;
-        if constexpr (FAST) {
-          sn = __sinf(yj);
-          co = __cosf(yj);
-        } else {
-          sincosf(yj, &sn, &co);
-        }
-        const float gx = quad_sum(wj * (sj * co));
-        const float gy = quad_sum(wj * (sj * sn));
-        const float gp = quad_sum(wj * kpsi);
-        const float x0s[N] = {x[0], x[1], x[2], x[3], x[4]};
-        const float inc[N] = {p.sixth_dt * gx, p.sixth_dt * gy, p.sixth_dt * gp,
-                              p.sixth_dt * (((v[0] + 2.0f * v[0]) + 2.0f * v[0]) + v[0]),
-                              p.sixth_dt * (((v[1] + 2.0f * v[1]) + 2.0f * v[1]) + v[1])};
-        advance<Model>(x, x0s, inc, comp);
+        bicycle_quad_step<FAST>(x, comp, v, j, cdt, wj, p);
         // latch this step for lane t mod L, evaluate a full group every L steps
         if ((t & (L - 1)) == slot) {
 #pragma unroll
@@ -168,6 +127,7 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
             bool hit;
             float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
             if (p.importance) l += is_term<M>(p, lv, lds_u + lt * M);
+            if (p.cosines) l += inflation(p);
             if constexpr (COUNT) ncrash += hit ? 1 : 0;
             const float y = l - sum_c;
             const float s = sum + y;

@@ -68,6 +68,7 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
     bool hit;
     float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
     if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
+    if (p.cosines) l += inflation(p);
     const float y = l - sum_c;
     const float s = sum + y;
     sum_c = (s - sum) - y;
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     bool hit;
     float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
     if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
+    if (p.cosines) l += inflation(p);
     const float y = l - sum_c;
     const float s = sum + y;
     sum_c = (s - sum) - y;

@@ -40,6 +40,7 @@ def test_struct_sizes_match_the_header(abi):
     # sizes of the C structs as laid out by the host compiler
     assert C.sizeof(abi.Config) == 96
     assert C.sizeof(abi.Params) == 272
+    assert C.sizeof(abi.Tuning) == 24
 
 
 def _bytes(abi, wl, grad=False, ckpt=0, **cfg_override):
@@ -79,8 +80,11 @@ def test_batch_workspace_and_mismatch(abi):
     params = (abi.Params * 5)(*[controller._params(w, keep) for w in insts])
     n = abi.lib().mppi_batch_workspace_bytes(cfgs, params, 5)
     eps = sum(4 * w.T * w.m * ((w.K + 63) // 64 * 64) for w in insts)
+    # a single context also reserves the split rollout form's trajectory
+    # buffer ([T][5][ldk] for the bicycle), which a batch does not have
+    traj = sum(4 * w.T * 5 * ((w.K + 63) // 64 * 64) for w in insts)
     singles = sum(_bytes(abi, w)[0] for w in insts)
-    assert n > 0 and eps <= n and n >= 0.9 * singles
+    assert n > 0 and eps <= n and n >= 0.9 * (singles - traj) and n < singles
     assert abi.lib().mppi_batch_workspace_bytes(cfgs, params, 0) == 0
 
 
