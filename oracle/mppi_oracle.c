@@ -687,6 +687,25 @@ int orc_mppi(const orc_problem* P, const double* x0, double* u, int32_t iters,
   return rc;
 }
 
+/* The MPC warm start between calls (section "Beginner", the plant's
+ * optimisation stride): the nominal sequence moves `steps` steps forward,
+ * u[t] <- u[t + steps]; the steps past the horizon take the last control
+ * (fill 0) or zero (fill 1).  u is [T][m], updated in place. */
+void orc_shift(const orc_problem* P, double* u, int32_t steps, int32_t fill) {
+  const int32_t T = P->T, m = P->m;
+  double* old = (double*)malloc(sizeof(double) * (size_t)T * m);
+  for (int32_t q = 0; q < T * m; ++q) old[q] = u[q];
+  for (int32_t t = 0; t < T; ++t)
+    for (int j = 0; j < m; ++j) {
+      const int64_t src = (int64_t)t + steps;
+      double val;
+      if (src < T) val = old[src * m + j];
+      else val = fill == 0 ? old[(int64_t)(T - 1) * m + j] : 0.0;
+      u[(int64_t)t * m + j] = val;
+    }
+  free(old);
+}
+
 /* Deterministic rollout of one control sequence; xs receives [T+1][n]. */
 void orc_trajectory(const orc_problem* P, const double* x0, const double* v_seq,
                     double* xs) {

@@ -85,6 +85,7 @@ def lib():
         L.orc_backward.restype = C.c_int
         L.orc_cost_condition.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p]
         L.orc_cost_condition.restype = C.c_int
+        L.orc_shift.argtypes = [P, f64p, C.c_int32, C.c_int32]
         L.orc_trajectory.argtypes = [P, f64p, f64p, f64p]
         L.orc_sequence_cost.argtypes = [P, f64p, f64p]
         L.orc_sequence_cost.restype = C.c_double
@@ -250,6 +251,15 @@ def mppi(wl, iters=None, iter0: int = 0, u=None, x0=None, **override):
             "status": rc}
 
 
+def shift(wl, u, steps: int, fill: str = "hold"):
+    """The MPC warm start: u[t] <- u[t + steps], the tail held at the last
+    control (fill "hold") or zero ("zero").  Returns a new [T][m] array."""
+    P = Problem(wl)
+    out = _d(u).ravel().copy()
+    lib().orc_shift(P.ref, out, int(steps), {"hold": 0, "zero": 1}[fill])
+    return out.reshape(wl.T, wl.m)
+
+
 def n_grad(wl) -> int:
     """Length of the gradient vector: [MLP blob | Q diag (n) | wheelbase]."""
     H = wl.mlp_hidden if wl.model == "bicycle_mlp" else 0
@@ -387,4 +397,4 @@ __all__ = ["philox", "bm_tables", "noise", "workload_noise", "rollout_costs",
            "softmin_update", "mppi", "step", "deriv", "trajectory", "sequence_cost",
            "running_cost", "terminal_cost", "spline", "costmap", "Problem", "n_grad",
            "backward", "with_theta", "theta_of", "loss_and_controls",
-           "cost_condition"]
+           "cost_condition", "shift"]

@@ -149,3 +149,24 @@ def test_cost_inflation_adds_exactly_zero(oracle_lib, make):
     S0, m0, c0 = oracle_lib.rollout_costs(wl, eps=eps)
     S1, m1, c1 = oracle_lib.rollout_costs(wl.replace(cost_cosines=40), eps=eps)
     assert np.array_equal(S0, S1) and np.array_equal(c0, c1)
+
+
+def test_shift_worked_example(oracle_lib):
+    """The warm start of an MPC step (section "Beginner": the nominal
+    sequence moves forward by the optimisation stride), worked by hand."""
+    wl = W.c1(K=4, T=3)
+    u = np.array([[1.0, 2.0], [3.0, 4.0], [5.0, 6.0]])
+    assert np.array_equal(oracle_lib.shift(wl, u, 1), [[3, 4], [5, 6], [5, 6]])
+    assert np.array_equal(oracle_lib.shift(wl, u, 1, "zero"), [[3, 4], [5, 6], [0, 0]])
+    assert np.array_equal(oracle_lib.shift(wl, u, 2), [[5, 6], [5, 6], [5, 6]])
+    assert np.array_equal(oracle_lib.shift(wl, u, 0), u)
+    assert np.array_equal(oracle_lib.shift(wl, u, 7, "zero"), np.zeros((3, 2)))
+
+
+def test_shift_composes(oracle_lib):
+    wl = W.c2("circles", K=8, T=37, iters=1)
+    u = np.random.default_rng(2).normal(size=(37, 2))
+    for fill in ("hold", "zero"):
+        for a, b in ((1, 1), (3, 5), (20, 20), (0, 9)):
+            two = oracle_lib.shift(wl, oracle_lib.shift(wl, u, a, fill), b, fill)
+            assert np.array_equal(two, oracle_lib.shift(wl, u, a + b, fill))
