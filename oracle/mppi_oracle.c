@@ -787,13 +787,15 @@ void orc_philox_many(int64_t n, const uint32_t* ctr, const uint32_t key[2],
 /* Jacobian-transpose product of the bicycle derivative at (x, v):
  * dx += (df/dx)^T c, and dL += (df/dwheelbase)^T c. */
 static void bicycle_deriv_vjp(const orc_problem* P, const double* x, const double* c,
-                              double* dx, double* dL) {
+                              double* dx, double* dL, double* dv) {
   const double psi = x[2], s = x[3], d = x[4], Lw = P->wheelbase;
   const double cp = cos(psi), sp = sin(psi), td = tan(d), sec2 = 1.0 + td * td;
   dx[2] += -s * sp * c[0] + s * cp * c[1];
   dx[3] += cp * c[0] + sp * c[1] + td / Lw * c[2];
   dx[4] += s * sec2 / Lw * c[2];
   *dL += -s * td / (Lw * Lw) * c[2];
+  /* speed' = accel = v0, steer' = steer rate = v1 */
+  if (dv) { dv[0] += c[3]; dv[1] += c[4]; }
 }
 
 /* MLP residual forward with the activations kept for its backward. */
@@ -868,9 +870,10 @@ static void mlp_vjp(const orc_problem* P, const double* z, const double* cg, dou
 }
 
 /* Backward of one step x1 = F(x0, v): given mu1 = dJ/dx1, returns
- * mu0 = (dF/dx0)^T mu1 and accumulates (dF/dtheta)^T mu1 into grad. */
+ * mu0 = (dF/dx0)^T mu1 and accumulates (dF/dtheta)^T mu1 into grad and, when
+ * dv is given, (dF/dv)^T mu1 into dv. */
 static void step_vjp(const orc_problem* P, const double* x0, const double* v, const double* mu1,
-                     double* mu0, double* grad_mlp, double* grad_L) {
+                     double* mu0, double* grad_mlp, double* grad_L, double* dv) {
   const int n = 5;
   const double h = P->dt;
   double k1[5], k2[5], k3[5], x2[5], x3[5], x4[5];
@@ -890,19 +893,19 @@ static void step_vjp(const orc_problem* P, const double* x0, const double* v, co
   }
   /* k4 = f(x4), x4 = x0 + h k3 */
   for (int i = 0; i < n; ++i) cx[i] = 0.0;
-  bicycle_deriv_vjp(P, x4, ck4, cx, grad_L);
+  bicycle_deriv_vjp(P, x4, ck4, cx, grad_L, dv);
   for (int i = 0; i < n; ++i) { mu0[i] += cx[i]; ck3[i] += h * cx[i]; }
   /* k3 = f(x3), x3 = x0 + h/2 k2 */
   for (int i = 0; i < n; ++i) cx[i] = 0.0;
-  bicycle_deriv_vjp(P, x3, ck3, cx, grad_L);
+  bicycle_deriv_vjp(P, x3, ck3, cx, grad_L, dv);
   for (int i = 0; i < n; ++i) { mu0[i] += cx[i]; ck2[i] += 0.5 * h * cx[i]; }
   /* k2 = f(x2), x2 = x0 + h/2 k1 */
   for (int i = 0; i < n; ++i) cx[i] = 0.0;
-  bicycle_deriv_vjp(P, x2, ck2, cx, grad_L);
+  bicycle_deriv_vjp(P, x2, ck2, cx, grad_L, dv);
   for (int i = 0; i < n; ++i) { mu0[i] += cx[i]; ck1[i] += 0.5 * h * cx[i]; }
   /* k1 = f(x0) */
   for (int i = 0; i < n; ++i) cx[i] = 0.0;
-  bicycle_deriv_vjp(P, x0, ck1, cx, grad_L);
+  bicycle_deriv_vjp(P, x0, ck1, cx, grad_L, dv);
   for (int i = 0; i < n; ++i) mu0[i] += cx[i];
   /* residual dt * g([x0; v]) */
   if (P->model == ORC_BICYCLE_MLP) {
@@ -911,27 +914,30 @@ static void step_vjp(const orc_problem* P, const double* x0, const double* v, co
     for (int i = 0; i < 5; ++i) cg[i] = h * mu1[i];
     mlp_vjp(P, z, cg, dz, grad_mlp);
     for (int i = 0; i < 5; ++i) mu0[i] += dz[i];
+    if (dv) { dv[0] += dz[5]; dv[1] += dz[6]; }
   }
 }
 
-/* grad <- dL/dtheta for L with dL/dU = G (layout above); also returns the
- * forward's U, S and w.  S_in (optional): costs to form the weights from in
- * place of the rollout's own (the sweeps still differentiate the rollouts).
- * grad_abs (optional): sum over samples of rel_k |a_k dJ_k/dtheta| (rel_k = 1
- * when rel is NULL), the scale of the rounding error of the sum when sample
- * k's terms carry relative error rel_k.  Returns 0, -1 if unsupported, -6 if
- * all J are non-finite. */
-int orc_backward(const orc_problem* P, const double* x0, const double* u, const float* eps,
-                 const double* G, const double* S_in, const double* rel, double* grad,
-                 double* grad_abs, double* U_out, double* S_out, double* w_out) {
-  if ((P->model != ORC_BICYCLE && P->model != ORC_BICYCLE_MLP) || P->cost != ORC_COST_TRACK ||
-      P->integrator != ORC_RK4)
-    return -1;
+static int backward_supported(const orc_problem* P) {
+  return (P->model == ORC_BICYCLE || P->model == ORC_BICYCLE_MLP) && P->cost == ORC_COST_TRACK &&
+         P->integrator == ORC_RK4;
+}
+
+/* One iteration's reverse pass (accumulating): grad += dL/dtheta at fixed u,
+ * du += sum_k a_k dJ_k/du (the dependence of the costs on the nominal
+ * sequence u, through v = u + eps and, with the importance-sampling term,
+ * directly), with a_k = dL/dJ_k; grad_abs / du_abs += the matching sums of
+ * |terms| (rel_k-scaled for grad_abs).  The arguments are those of
+ * orc_backward. */
+static int backward_one(const orc_problem* P, const double* x0, const double* u, const float* eps,
+                        const double* G, const double* S_in, const double* rel, double* grad,
+                        double* grad_abs, double* du, double* du_abs, double* U_out,
+                        double* S_out, double* w_out) {
   const int32_t K = P->K, T = P->T, m = P->m, n = P->n;
   const int H = P->mlp_hidden;
   const int nmlp = P->model == ORC_BICYCLE_MLP ? 7 * H + H + H * H + H + 5 * H + 5 : 0;
   const int ngrad = nmlp + n + 1;
-  double* S = (double*)malloc(sizeof(double) * K);
+  double* S = (double*)calloc((size_t)K, sizeof(double));
   double* w = (double*)malloc(sizeof(double) * K);
   double* U = (double*)malloc(sizeof(double) * T * m);
   double stats[4];
@@ -941,10 +947,7 @@ int orc_backward(const orc_problem* P, const double* x0, const double* u, const 
     orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL, NULL);
   int rc = orc_softmin_update(P, S, eps, K, u, w, U, stats);
   double* dk = (double*)malloc(sizeof(double) * ngrad); /* dJ_k/dtheta of one sample */
-  for (int i = 0; i < ngrad; ++i) {
-    grad[i] = 0.0;
-    if (grad_abs) grad_abs[i] = 0.0;
-  }
+  double* dku = (double*)malloc(sizeof(double) * T * m); /* dJ_k/du of one sample */
   if (rc == 0) {
     /* g_k = <G, eps_k>; dL/dJ_k = -(w_k/lambda) (g_k - sum_i w_i g_i), written
      * as -(w_k/lambda) sum_i w_i (g_k - g_i) (the weights sum to one) so that
@@ -971,6 +974,7 @@ int orc_backward(const orc_problem* P, const double* x0, const double* u, const 
       const double a = ak[k];
       if (a == 0.0) continue;
       for (int i = 0; i < ngrad; ++i) dk[i] = 0.0;
+      for (int i = 0; i < T * m; ++i) dku[i] = 0.0;
       for (int i = 0; i < n; ++i) xs[i] = x0[i];
       for (int32_t t = 0; t < T; ++t) {
         for (int j = 0; j < m; ++j) vs[t * m + j] = u[t * m + j] + (double)eps[((int64_t)t * m + j) * K + k];
@@ -996,12 +1000,24 @@ int orc_backward(const orc_problem* P, const double* x0, const double* u, const 
           mu[i] += 2.0 * P->w[i] * e;
           gQ[i] += e * e;
         }
-        step_vjp(P, xs + t * n, vs + t * m, mu, mu0, gmlp, gL);
+        /* dJ/dv_t: the control term of l_t, then the step */
+        double* dv = dku + t * m;
+        for (int j = 0; j < m; ++j) dv[j] = 2.0 * P->w[8 + j] * vs[t * m + j];
+        step_vjp(P, xs + t * n, vs + t * m, mu, mu0, gmlp, gL, dv);
+        /* the importance-sampling term lambda (v - u/2)' Sigma^-1 u with
+         * v = u + eps: its derivative in u is lambda Sigma^-1 v */
+        if (P->is_beta)
+          for (int j = 0; j < m; ++j)
+            dv[j] += P->lambda * vs[t * m + j] / ((double)P->sigma[j] * (double)P->sigma[j]);
         for (int i = 0; i < n; ++i) mu[i] = mu0[i];
       }
       for (int i = 0; i < ngrad; ++i) {
         grad[i] += a * dk[i];
         if (grad_abs) grad_abs[i] += fabs(a * dk[i]) * (rel ? rel[k] : 1.0);
+      }
+      for (int i = 0; i < T * m; ++i) {
+        if (du) du[i] += a * dku[i];
+        if (du_abs) du_abs[i] += fabs(a * dku[i]);
       }
     }
     free(xs);
@@ -1013,9 +1029,95 @@ int orc_backward(const orc_problem* P, const double* x0, const double* u, const 
   if (S_out) for (int k = 0; k < K; ++k) S_out[k] = S[k];
   if (w_out) for (int k = 0; k < K; ++k) w_out[k] = w[k];
   free(dk);
+  free(dku);
   free(S);
   free(w);
   free(U);
+  return rc;
+}
+
+/* grad <- dL/dtheta for L with dL/dU = G (layout above), for one iteration
+ * from u (which does not depend on theta); also returns the forward's U, S
+ * and w.  S_in (optional): costs to form the weights from in place of the
+ * rollout's own (the sweeps still differentiate the rollouts).  grad_abs
+ * (optional): sum over samples of rel_k |a_k dJ_k/dtheta| (rel_k = 1 when rel
+ * is NULL), the scale of the rounding error of the sum when sample k's terms
+ * carry relative error rel_k.  du (optional): sum_k a_k dJ_k/du, the part of
+ * dL/du that passes through the costs (dL/du = G + du), with du_abs the sum
+ * of |terms|.  Returns 0, -1 if unsupported, -6 if all J are non-finite. */
+int orc_backward(const orc_problem* P, const double* x0, const double* u, const float* eps,
+                 const double* G, const double* S_in, const double* rel, double* grad,
+                 double* grad_abs, double* U_out, double* S_out, double* w_out, double* du,
+                 double* du_abs) {
+  if (!backward_supported(P)) return -1;
+  const int ngrad = (P->model == ORC_BICYCLE_MLP ? 14 * P->mlp_hidden +
+                     P->mlp_hidden * P->mlp_hidden + 5 : 0) + P->n + 1;
+  for (int i = 0; i < ngrad; ++i) {
+    grad[i] = 0.0;
+    if (grad_abs) grad_abs[i] = 0.0;
+  }
+  for (int i = 0; i < P->T * P->m; ++i) {
+    if (du) du[i] = 0.0;
+    if (du_abs) du_abs[i] = 0.0;
+  }
+  return backward_one(P, x0, u, eps, G, S_in, rel, grad, grad_abs, du, du_abs, U_out, S_out,
+                      w_out);
+}
+
+/* The gradient through `iters` warm-started iterations (Algorithm 1's outer
+ * loop, iteration words iter0, iter0 + 1, ...) from the nominal sequence u0:
+ * with u_{i+1} = u_i + gamma sum_k w_k(u_i, theta) eps_k and a loss on u_I
+ * given by G = dL/du_I, the reverse pass runs the iterations backwards,
+ *   grad += sum_k a_k dJ_k/dtheta,   G <- G + sum_k a_k dJ_k/du_i,
+ * with a_k the softmin Jacobian of iteration i applied to the current G.
+ * Outputs: grad (dL/dtheta), grad_abs (sum of |terms| over all iterations,
+ * optional), du0 (dL/du0, optional), U_out (u_I, optional).  Returns 0, -1 if
+ * unsupported, or the first nonzero status of an iteration. */
+int orc_backward_iters(const orc_problem* P, const double* x0, const double* u0, int32_t iters,
+                       uint32_t iter0, const double* G, double* grad, double* grad_abs,
+                       double* du0, double* U_out) {
+  if (!backward_supported(P) || iters < 1) return -1;
+  const int32_t K = P->K, T = P->T, m = P->m, TM = T * m;
+  const int ngrad = (P->model == ORC_BICYCLE_MLP ? 14 * P->mlp_hidden +
+                     P->mlp_hidden * P->mlp_hidden + 5 : 0) + P->n + 1;
+  double* tape = (double*)malloc(sizeof(double) * (size_t)(iters + 1) * TM);
+  float* eps = (float*)malloc(sizeof(float) * (size_t)TM * K);
+  double* S = (double*)malloc(sizeof(double) * K);
+  double* w = (double*)malloc(sizeof(double) * K);
+  double stats[4];
+  int rc = 0;
+  for (int i = 0; i < TM; ++i) tape[i] = u0[i];
+  for (int32_t it = 0; it < iters; ++it) {
+    const double* u = tape + (size_t)it * TM;
+    double* U = tape + (size_t)(it + 1) * TM;
+    orc_noise(P->seed, iter0 + (uint32_t)it, P->instance, K, T, m, P->sigma, K, eps);
+    orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL, NULL);
+    const int r = orc_softmin_update(P, S, eps, K, u, w, U, stats);
+    if (r && !rc) rc = r;
+  }
+  for (int i = 0; i < ngrad; ++i) {
+    grad[i] = 0.0;
+    if (grad_abs) grad_abs[i] = 0.0;
+  }
+  double* Gc = (double*)malloc(sizeof(double) * TM);
+  double* du = (double*)malloc(sizeof(double) * TM);
+  for (int i = 0; i < TM; ++i) Gc[i] = G[i];
+  for (int32_t it = iters - 1; it >= 0; --it) {
+    orc_noise(P->seed, iter0 + (uint32_t)it, P->instance, K, T, m, P->sigma, K, eps);
+    for (int i = 0; i < TM; ++i) du[i] = 0.0;
+    const int r = backward_one(P, x0, tape + (size_t)it * TM, eps, Gc, NULL, NULL, grad, grad_abs,
+                               du, NULL, NULL, NULL, NULL);
+    if (r && !rc) rc = r;
+    for (int i = 0; i < TM; ++i) Gc[i] += du[i];
+  }
+  if (du0) for (int i = 0; i < TM; ++i) du0[i] = Gc[i];
+  if (U_out) for (int i = 0; i < TM; ++i) U_out[i] = tape[(size_t)iters * TM + i];
+  free(Gc);
+  free(du);
+  free(tape);
+  free(eps);
+  free(S);
+  free(w);
   return rc;
 }
 
@@ -1053,7 +1155,7 @@ int orc_cost_condition(const orc_problem* P, const double* x0, const double* u, 
       const double* r1 = P->ref + (int64_t)(t + 1) * n;
       for (int i = 0; i < n; ++i) mu[i] += 2.0 * P->w[i] * (x1[i] - r1[i]);
       for (int i = 0; i < n; ++i) c += fabs(mu[i]) * fabs(x1[i]);
-      step_vjp(P, xs + t * n, vs + t * m, mu, mu0, scratch, scratch + nmlp);
+      step_vjp(P, xs + t * n, vs + t * m, mu, mu0, scratch, scratch + nmlp, NULL);
       for (int i = 0; i < n; ++i) mu[i] = mu0[i];
     }
     cond[k] = c;

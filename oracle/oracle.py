@@ -81,8 +81,11 @@ def lib():
         L.orc_mppi.argtypes = [P, f64p, f64p, C.c_int32, C.c_uint32, f32p, f64p, f64p, f64p]
         L.orc_mppi.restype = C.c_int
         L.orc_backward.argtypes = [P, f64p, f64p, f32p, f64p, _opt_f64p, _opt_f64p, f64p,
-                                   _opt_f64p, f64p, f64p, f64p]
+                                   _opt_f64p, f64p, f64p, f64p, _opt_f64p, _opt_f64p]
         L.orc_backward.restype = C.c_int
+        L.orc_backward_iters.argtypes = [P, f64p, f64p, C.c_int32, C.c_uint32, f64p, f64p,
+                                         _opt_f64p, _opt_f64p, _opt_f64p]
+        L.orc_backward_iters.restype = C.c_int
         L.orc_cost_condition.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p]
         L.orc_cost_condition.restype = C.c_int
         L.orc_shift.argtypes = [P, f64p, C.c_int32, C.c_int32]
@@ -286,12 +289,33 @@ def backward(wl, dL_dU, u=None, x0=None, eps=None, iteration: int = 0, S=None, r
     w = np.empty(wl.K)
     S_in = None if S is None else _d(S).ravel()
     rel_in = None if rel is None else _d(rel).ravel()
+    du = np.empty(wl.T * wl.m)
+    du_abs = np.empty(wl.T * wl.m)
     rc = lib().orc_backward(P.ref, x0, u, eps, _d(dL_dU).ravel(), S_in, rel_in, grad, grad_abs, U,
-                            S_out, w)
+                            S_out, w, du, du_abs)
     if rc == -1:
         raise ValueError("backward needs a bicycle model with RK4 and the track cost")
     return {"grad": grad, "grad_abs": grad_abs, "U": U.reshape(wl.T, wl.m), "S": S_out, "w": w,
-            "status": rc}
+            "du": du.reshape(wl.T, wl.m), "du_abs": du_abs.reshape(wl.T, wl.m), "status": rc}
+
+
+def backward_iters(wl, dL_dU, iters: int, u=None, x0=None, iter0: int = 0):
+    """Gradient through `iters` warm-started iterations from u (default
+    wl.u0): {"grad": dL/dtheta, "grad_abs", "du0": dL/du0, "U": u_iters,
+    "status"} for a loss with dL/du_iters = dL_dU."""
+    P = Problem(wl)
+    u = _d(wl.u0 if u is None else u).ravel()
+    x0 = _d(wl.x0 if x0 is None else x0)
+    grad = np.zeros(n_grad(wl))
+    grad_abs = np.zeros(n_grad(wl))
+    du0 = np.empty(wl.T * wl.m)
+    U = np.empty(wl.T * wl.m)
+    rc = lib().orc_backward_iters(P.ref, x0, u, int(iters), int(iter0), _d(dL_dU).ravel(), grad,
+                                  grad_abs, du0, U)
+    if rc == -1:
+        raise ValueError("backward needs a bicycle model with RK4 and the track cost")
+    return {"grad": grad, "grad_abs": grad_abs, "du0": du0.reshape(wl.T, wl.m),
+            "U": U.reshape(wl.T, wl.m), "status": rc}
 
 
 def cost_condition(wl, eps=None, x0=None, u=None, iteration: int = 0):
@@ -326,17 +350,18 @@ def theta_of(wl):
     return np.concatenate(parts)
 
 
-def loss_and_controls(wl, u_ref, theta=None, iteration: int = 0):
-    """(L, U) with L = |U - u_ref|^2 for one iteration at parameters theta
-    (binary64 throughout: theta is not rounded to binary32)."""
+def loss_and_controls(wl, u_ref, theta=None, iteration: int = 0, iters: int = 1, u0=None):
+    """(L, U) with L = |U - u_ref|^2 after `iters` warm-started iterations
+    from u0 (default wl.u0) at parameters theta (binary64 throughout: theta
+    and u0 are not rounded to binary32)."""
     w2 = wl if theta is None else with_theta(wl, theta)
     P = Problem(w2, keep_f64=True)
-    u = _d(w2.u0).ravel().copy()
+    u = _d(w2.u0 if u0 is None else u0).ravel().copy()
     eps = np.empty((w2.T, w2.m, w2.K), np.float32)
     S = np.empty(w2.K)
     w = np.empty(w2.K)
     stats = np.empty(4)
-    lib().orc_mppi(P.ref, _d(w2.x0), u, 1, iteration, eps, S, w, stats)
+    lib().orc_mppi(P.ref, _d(w2.x0), u, int(iters), iteration, eps, S, w, stats)
     U = u.reshape(w2.T, w2.m)
     return float(np.sum((U - u_ref) ** 2)), U
 
@@ -397,4 +422,4 @@ __all__ = ["philox", "bm_tables", "noise", "workload_noise", "rollout_costs",
            "softmin_update", "mppi", "step", "deriv", "trajectory", "sequence_cost",
            "running_cost", "terminal_cost", "spline", "costmap", "Problem", "n_grad",
            "backward", "with_theta", "theta_of", "loss_and_controls",
-           "cost_condition", "shift"]
+           "cost_condition", "shift", "backward_iters"]

@@ -105,3 +105,92 @@ def test_adjoint_single_sample_has_no_gradient():
 def test_adjoint_rejects_other_models():
     with pytest.raises(ValueError):
         O.backward(W.c1(K=8, T=4), np.zeros((4, 2)))
+
+
+# ---------------------------------------------------------------------------
+# the dependence on the nominal sequence, and several warm-started iterations
+# ---------------------------------------------------------------------------
+def _central_u(wl, uref, u0, idx, h, iters):
+    up = u0.copy()
+    up.flat[idx] += h
+    um = u0.copy()
+    um.flat[idx] -= h
+    Lp = O.loss_and_controls(wl, uref, iters=iters, u0=up)[0]
+    Lm = O.loss_and_controls(wl, uref, iters=iters, u0=um)[0]
+    return (Lp - Lm) / (2 * h)
+
+
+def _fd_u(wl, uref, u0, idx, h, iters):
+    return (4.0 * _central_u(wl, uref, u0, idx, h / 2, iters)
+            - _central_u(wl, uref, u0, idx, h, iters)) / 3.0
+
+
+def _fd_theta(wl, uref, theta, i, h, iters):
+    def c(hh):
+        tp = theta.copy()
+        tp[i] += hh
+        tm = theta.copy()
+        tm[i] -= hh
+        return (O.loss_and_controls(wl, uref, tp, iters=iters)[0]
+                - O.loss_and_controls(wl, uref, tm, iters=iters)[0]) / (2 * hh)
+    return (4.0 * c(h / 2) - c(h)) / 3.0
+
+
+@pytest.mark.parametrize("model,is_beta", [("bicycle_mlp", 0), ("bicycle", 1)])
+def test_control_gradient_vs_fd(model, is_beta):
+    """dL/du = G + sum_k a_k dJ_k/du for one iteration (the costs depend on u
+    through v = u + eps, and directly through the importance-sampling term)."""
+    wl = W.c5(K=40, T=12, hidden=8)
+    if model == "bicycle":
+        wl = wl.replace(model="bicycle", mlp=None, mlp_hidden=0)
+    u0 = np.random.default_rng(3).normal(0, 0.3, (wl.T, wl.m))
+    wl = wl.replace(u0=u0.astype(np.float32), is_beta=is_beta, gamma=0.8)
+    u0 = wl.u0.astype(np.float64)
+    uref = W.c5_uref(T=wl.T)
+    L0, U0 = O.loss_and_controls(wl, uref, u0=u0)
+    G = 2.0 * (U0 - uref)
+    r = O.backward(wl, G)
+    dLdu = G + r["du"]
+    scale = np.abs(dLdu).max()
+    for idx in range(0, wl.T * wl.m, 3):
+        fd = _fd_u(wl, uref, u0, idx, 1e-3, 1)
+        assert abs(dLdu.flat[idx] - fd) <= 2e-5 * max(abs(fd), 1e-3 * scale), (idx, dLdu.flat[idx], fd)
+
+
+@pytest.mark.parametrize("iters,is_beta,gamma", [(2, 0, 1.0), (3, 1, 0.7)])
+def test_multi_iteration_gradient_vs_fd(iters, is_beta, gamma):
+    """Through several warm-started iterations both theta and u0 matter at
+    every iteration; each is checked against Richardson-extrapolated central
+    differences of the oracle's own I-iteration forward."""
+    wl = W.c5(K=48, T=12, hidden=8).replace(lam=20.0)
+    u0 = np.random.default_rng(5).normal(0, 0.2, (wl.T, wl.m)).astype(np.float32)
+    wl = wl.replace(u0=u0, is_beta=is_beta, gamma=gamma)
+    uref = W.c5_uref(T=wl.T)
+    L0, U0 = O.loss_and_controls(wl, uref, iters=iters)
+    r = O.backward_iters(wl, 2.0 * (U0 - uref), iters)
+    assert r["status"] == 0
+    np.testing.assert_allclose(r["U"], U0, rtol=0, atol=1e-12)
+    theta = O.theta_of(wl)
+    n = O.n_grad(wl)
+    rng = np.random.default_rng(6)
+    idx = sorted(set(int(i) for i in rng.integers(0, n - 6, 6))) + list(range(n - 6, n))
+    scale = np.abs(r["grad"]).max()
+    for i in idx:
+        h = 1e-3 * max(1.0, abs(theta[i]))
+        fd = _fd_theta(wl, uref, theta, i, h, iters)
+        assert abs(r["grad"][i] - fd) <= 2e-5 * max(abs(fd), 1e-3 * scale), (i, r["grad"][i], fd)
+    su = np.abs(r["du0"]).max()
+    for j in range(1, wl.T * wl.m, 5):
+        fd = _fd_u(wl, uref, wl.u0.astype(np.float64), j, 1e-3, iters)
+        assert abs(r["du0"].flat[j] - fd) <= 2e-5 * max(abs(fd), 1e-3 * su), (j, r["du0"].flat[j], fd)
+
+
+def test_one_iteration_of_the_chain_is_the_single_backward():
+    wl = W.c5(K=32, T=10, hidden=8)
+    uref = W.c5_uref(T=10)
+    L0, U0 = O.loss_and_controls(wl, uref)
+    G = 2.0 * (U0 - uref)
+    a = O.backward(wl, G)
+    b = O.backward_iters(wl, G, 1)
+    assert np.array_equal(a["grad"], b["grad"])
+    assert np.array_equal(G + a["du"], b["du0"])
