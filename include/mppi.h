@@ -184,6 +184,8 @@ typedef struct mppi_params {
   const float* costmap;   /* [map_h][map_w] */
   int32_t checkpoint_every; /* MPPI_F_REQUIRES_GRAD: steps between state
                                checkpoints, 1..64 (0 = 10) */
+  int32_t tape_len;       /* MPPI_F_REQUIRES_GRAD: updates mppi_backward_iters can
+                             differentiate through, 1..1024 (0 = 16) */
   int32_t cost_cosines;   /* 0..65536 nested cosines evaluated ahead of every running
                              cost and scaled by zero: the synthetic cost-complexity
                              load of the paper's Results section.  It changes no
@@ -294,6 +296,14 @@ mppi_status mppi_set_controls(mppi_ctx* ctx, const float* d_u);
 /* Philox iteration word of the next sampling step (enqueued; every instance
  * of a batch). */
 mppi_status mppi_set_iteration(mppi_ctx* ctx, uint32_t iteration);
+/* MPC warm start between control calls (section "Beginner": a new MPC
+ * iteration samples around the previous sequence moved forward by the
+ * optimisation stride): u[t] <- u[t + steps] for t + steps < T, the steps past
+ * the horizon take u[T-1] (fill = MPPI_SHIFT_HOLD) or 0 (MPPI_SHIFT_ZERO).
+ * steps >= 0 (steps >= T leaves no old entry).  Enqueued kernel (may be
+ * captured in a graph); every instance of a batch.  Errors: EINVAL. */
+enum { MPPI_SHIFT_HOLD = 0, MPPI_SHIFT_ZERO = 1 };
+mppi_status mppi_shift(mppi_ctx* ctx, int32_t steps, int32_t fill);
 
 /* Staged iteration (Algorithm 1 split at its natural boundaries):
  *   mppi_sample  - (a1) eps for the current iteration word
@@ -357,6 +367,28 @@ mppi_status mppi_set_theta(mppi_ctx* ctx, const float* host_theta);
  * Errors: EINVAL (NULL), ESTATE (no MPPI_F_REQUIRES_GRAD, or no update since
  * the last mppi_sample / mppi_set_costs), EDEVICE. */
 mppi_status mppi_backward(mppi_ctx* ctx, const float* d_dL_dU, float* d_grad);
+
+/* Gradient through every update since the tape started (the warm-started
+ * iterations of Algorithm 1's outer loop): with u_{i+1} = u_i + gamma
+ * sum_k w_k(u_i, theta) eps_k for i = 0..n-1 and d_dL_dU = dL/du_n (device,
+ * [T][m]), d_grad[n_theta] <- dL/dtheta (device) and, if d_dL_du0 is given,
+ * d_dL_du0[T][m] <- dL/du_0 (device).  In gradient mode each update records
+ * its u and Philox iteration word on the tape (params.tape_len slots); the
+ * tape starts over at mppi_create, mppi_set_state, mppi_set_controls,
+ * mppi_set_theta and mppi_shift.  The reverse pass runs the updates
+ * backwards: it rebuilds update i (its noise from the recorded word, the
+ * checkpointing rollout from the recorded u_i, the weights), adds the
+ * gradient of that iteration at fixed u_i, and carries dL/du_i = dL/du_{i+1} +
+ * sum_k a_k dJ_k/du_i (the costs depend on u_i through v = u_i + eps and,
+ * with MPPI_F_IMPORTANCE_SAMPLING, directly) to the next one.  With one
+ * update it gives mppi_backward's gradient.  Synchronises the context's stream
+ * once (to read the tape's length); afterwards the noise, cost and weight
+ * buffers hold the first taped update's values (mppi_backward then needs a new
+ * iteration).  Errors: EINVAL (NULL), ESTATE (no MPPI_F_REQUIRES_GRAD; no
+ * update since the tape started; more than tape_len updates; an update whose
+ * costs came from mppi_set_costs), EDEVICE. */
+mppi_status mppi_backward_iters(mppi_ctx* ctx, const float* d_dL_dU, float* d_grad,
+                                float* d_dL_du0);
 
 void mppi_destroy(mppi_ctx* ctx);
 

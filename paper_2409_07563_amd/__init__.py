@@ -8,6 +8,6 @@ HIP kernels for gfx950 behind the C ABI of include/mppi.h.
 """
 from ._abi import MPPIError, lib  # noqa: F401
 from .controller import Controller, noise, noise_tables  # noqa: F401
-from .autograd import MPPIStep, mppi_step  # noqa: F401
+from .autograd import MPPISteps, MPPIStep, mppi_step, mppi_steps  # noqa: F401
 
 __all__ = ["Controller", "MPPIError", "lib", "noise", "noise_tables"]

@@ -32,6 +32,7 @@ F_REQUIRES_GRAD = 16
 F_IMPORTANCE_SAMPLING = 32
 F_STEP_SIZE = 64
 ROLLOUT_FUSED, ROLLOUT_SPLIT = 0, 1
+SHIFT_HOLD, SHIFT_ZERO = 0, 1
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
 PACKED_STATE, PACKED_CONTROLS, PACKED_SAMPLES, PACKED_NOISE = 0, 1, 2, 3
 
@@ -56,7 +57,8 @@ class Params(C.Structure):
                 ("num_circles", C.c_int32), ("cx", _fp), ("cy", _fp), ("r2", _fp),
                 ("map_w", C.c_int32), ("map_h", C.c_int32), ("map_x0", C.c_float),
                 ("map_y0", C.c_float), ("map_res", C.c_float), ("costmap", _fp),
-                ("checkpoint_every", C.c_int32), ("cost_cosines", C.c_int32)]
+                ("checkpoint_every", C.c_int32), ("tape_len", C.c_int32),
+                ("cost_cosines", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -75,6 +77,7 @@ EXPORTS = {
     "mppi_set_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mppi_set_controls": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mppi_set_iteration": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "mppi_shift": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "mppi_sample": (C.c_int, [C.c_void_p]),
     "mppi_rollout": (C.c_int, [C.c_void_p]),
     "mppi_set_costs": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -83,6 +86,7 @@ EXPORTS = {
     "mppi_get_controls": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mppi_get_debug": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "mppi_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mppi_backward_iters": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mppi_theta_len": (C.c_int32, [C.c_void_p]),
     "mppi_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
     "mppi_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmppi.so")
 SOURCES = ["mppi.hip", "noise.hip", "rollout.hip", "rollout_tiles.hip", "softmin.hip", "batch.hip",
-           "adjoint.hip", "split.hip"]
+           "adjoint.hip", "split.hip", "controls.hip"]
 ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU

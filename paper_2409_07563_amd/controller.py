@@ -54,9 +54,10 @@ def _config(pb, debug: bool, accurate_trig: bool, rollout: str,
     return cfg
 
 
-def _params(pb, keep: list, checkpoint_every: int = 0) -> _abi.Params:
+def _params(pb, keep: list, checkpoint_every: int = 0, tape_len: int = 0) -> _abi.Params:
     p = _abi.Params()
     p.checkpoint_every = int(checkpoint_every)
+    p.tape_len = int(tape_len)
     p.cost_cosines = int(getattr(pb, "cost_cosines", 0))
 
     def arr(a):
@@ -101,13 +102,14 @@ class Controller:
     sequence of them (a batch sharing model, integrator and cost kind).
 
     requires_grad: keep what `backward` needs (state checkpoints every
-    `checkpoint_every` steps and the controls of the rollout).
+    `checkpoint_every` steps and the controls of the rollout) and a tape of
+    `tape_len` updates for `backward_iters`.
     """
 
     def __init__(self, problem, device: str | torch.device = "cuda", debug: bool = False,
                  accurate_trig: bool = False, rollout: str = "auto",
                  stream: torch.cuda.Stream | None = None, requires_grad: bool = False,
-                 checkpoint_every: int = 10):
+                 checkpoint_every: int = 10, tape_len: int = 16):
         self.device = torch.device(device)
         self.batch = isinstance(problem, (list, tuple))
         probs: Sequence = list(problem) if self.batch else [problem]
@@ -120,7 +122,8 @@ class Controller:
         cfgs = (_abi.Config * self.n_inst)(
             *[_config(q, debug, accurate_trig, rollout, requires_grad) for q in probs])
         params = (_abi.Params * self.n_inst)(
-            *[_params(q, self._keep, checkpoint_every if requires_grad else 0) for q in probs])
+            *[_params(q, self._keep, checkpoint_every if requires_grad else 0,
+                      tape_len if requires_grad else 0) for q in probs])
         self.cfg, self._cfgs, self._params = cfgs[0], cfgs, params
         L = lib()
         if self.batch:
@@ -197,6 +200,13 @@ class Controller:
     def set_iteration(self, iteration: int) -> None:
         self._enter()
         check(lib().mppi_set_iteration(self.ctx, int(iteration)))
+
+    def shift(self, steps: int, fill: str = "hold") -> None:
+        """MPC warm start: u[t] <- u[t + steps]; the tail holds the last
+        control ("hold") or becomes zero ("zero")."""
+        self._enter()
+        check(lib().mppi_shift(self.ctx, int(steps),
+                               {"hold": _abi.SHIFT_HOLD, "zero": _abi.SHIFT_ZERO}[fill]))
 
     # -- the iteration ------------------------------------------------------
     def sample(self) -> None:
@@ -298,6 +308,16 @@ class Controller:
         check(lib().mppi_backward(self.ctx, g.data_ptr(), out.data_ptr()))
         self._g = g
         return self._leave(out)
+
+    def backward_iters(self, dL_dU):
+        """(dL/dtheta, dL/du0) through every update since the tape started
+        (the last set_state / set_controls / set_theta / shift)."""
+        g = self._dev(dL_dU, self.T * self.m)
+        out = self._empty(self.theta_len())
+        du0 = self._empty(self.T * self.m)
+        check(lib().mppi_backward_iters(self.ctx, g.data_ptr(), out.data_ptr(), du0.data_ptr()))
+        self._g = g
+        return self._leave(out), self._leave(du0).reshape(self.T, self.m)
 
     # -- inspection ---------------------------------------------------------
     def noise(self) -> torch.Tensor:

@@ -142,11 +142,14 @@ __global__ __launch_bounds__(kProjectSamples) void adjoint_compact_kernel(
   list[offs[blockIdx.x] + rank] = BwdItem{k, a};
 }
 
-// dx += (df/dx)^T c and dL += (df/d wheelbase)^T c for the bicycle derivative
-// f = (s cos psi, s sin psi, s tan(delta) / L, a, delta_rate) at x.
+// dx += (df/dx)^T c, dL += (df/d wheelbase)^T c and dv += (df/dv)^T c for
+// the bicycle derivative f = (s cos psi, s sin psi, s tan(delta) / L, a,
+// delta_rate) at x with control v = (a, delta_rate).
 template <bool FAST>
 __device__ __forceinline__ void bicycle_vjp(const float* x, const float* c, float inv_l,
-                                            float* dx, float& dl) {
+                                            float* dx, float& dl, float* dv) {
+  dv[0] += c[3];
+  dv[1] += c[4];
   float sn, cs, sd, cd;
   if constexpr (FAST) {
     sn = __sinf(x[2]);
@@ -166,12 +169,12 @@ __device__ __forceinline__ void bicycle_vjp(const float* x, const float* c, floa
   dl -= s * tn * inv_l * inv_l * c[2];
 }
 
-// mu0 = (dF/dx)^T mu for the RK4 bicycle step from x (control v held), and
-// gL += (dF/d wheelbase)^T mu: the four stages are rebuilt, then transposed
-// in reverse.
+// mu0 = (dF/dx)^T mu for the RK4 bicycle step from x (control v held),
+// gL += (dF/d wheelbase)^T mu and dv += (dF/dv)^T mu: the four stages are
+// rebuilt, then transposed in reverse.
 template <bool FAST>
 __device__ __forceinline__ void rk4_vjp(const DevParams& p, const float* xt, const float* v,
-                                        const float* mu, float* mu0, float& gL) {
+                                        const float* mu, float* mu0, float& gL, float* dv) {
   using Model = Bicycle<FAST>;
   constexpr int N = 5;
   float k1[N], xa[N], k2[N], xb[N], k3[N], xc[N];
@@ -188,28 +191,28 @@ __device__ __forceinline__ void rk4_vjp(const DevParams& p, const float* xt, con
   const float third_dt = 2.0f * p.sixth_dt;
 #pragma unroll
   for (int i = 0; i < N; ++i) { mu0[i] = mu[i]; cst[i] = p.sixth_dt * mu[i]; cx[i] = 0.0f; }
-  bicycle_vjp<FAST>(xc, cst, p.inv_wheelbase, cx, gL);  // k4 = f(xc), xc = x + dt k3
+  bicycle_vjp<FAST>(xc, cst, p.inv_wheelbase, cx, gL, dv);  // k4 = f(xc), xc = x + dt k3
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     mu0[i] += cx[i];
     cst[i] = third_dt * mu[i] + p.dt * cx[i];
     cx[i] = 0.0f;
   }
-  bicycle_vjp<FAST>(xb, cst, p.inv_wheelbase, cx, gL);  // k3 = f(xb), xb = x + dt/2 k2
+  bicycle_vjp<FAST>(xb, cst, p.inv_wheelbase, cx, gL, dv);  // k3 = f(xb), xb = x + dt/2 k2
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     mu0[i] += cx[i];
     cst[i] = third_dt * mu[i] + p.half_dt * cx[i];
     cx[i] = 0.0f;
   }
-  bicycle_vjp<FAST>(xa, cst, p.inv_wheelbase, cx, gL);  // k2 = f(xa), xa = x + dt/2 k1
+  bicycle_vjp<FAST>(xa, cst, p.inv_wheelbase, cx, gL, dv);  // k2 = f(xa), xa = x + dt/2 k1
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     mu0[i] += cx[i];
     cst[i] = p.sixth_dt * mu[i] + p.half_dt * cx[i];
     cx[i] = 0.0f;
   }
-  bicycle_vjp<FAST>(xt, cst, p.inv_wheelbase, cx, gL);  // k1 = f(x)
+  bicycle_vjp<FAST>(xt, cst, p.inv_wheelbase, cx, gL, dv);  // k1 = f(x)
 #pragma unroll
   for (int i = 0; i < N; ++i) mu0[i] += cx[i];
 }
@@ -234,11 +237,28 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// The tile's share of dL/du_t = sum_k a_k dJ_k/du_t for one step: dv holds
+// the a_k-weighted (dF/dv)^T mu of the lane's sample; the control term of the
+// running cost (2 R v) and, with the importance-sampling term, its
+// derivative in u through v = u + eps and directly (lambda Sigma^-1 v) are
+// added, then the 16 samples of the tile are summed (fixed xor tree) and
+// lane 0 writes out[0..1].  Every lane of the wave must call it.
+__device__ __forceinline__ void du_step(const DevParams& p, float a, const float* v, float* dv,
+                                        int lane, float* out) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    float d = dv[q] + a * (2.0f * p.w[8 + q] * v[q]);
+    if (p.importance) d += a * (p.is_coef[q] * v[q]);
+    const float sum = group_sum(d);
+    if (lane == 0) out[q] = sum;
+  }
+}
+
 template <int MT, bool FAST>
 __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
-    const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp,
+    const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp, int du_off,
     mlp::f4* __restrict__ pre) {
   using Model = Bicycle<FAST>;
   using L = SweepLds<MT>;
@@ -350,8 +370,8 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
       for (int i = 0; i < N; ++i) xt[i] = xs[j * N + i];
 #pragma unroll
       for (int q = 0; q < M; ++q) v[q] = vs[j * M + q];
-      float mu0[N];
-      rk4_vjp<FAST>(p, xt, v, mu, mu0, gL);
+      float mu0[N], dv[M] = {0.0f, 0.0f};
+      rk4_vjp<FAST>(p, xt, v, mu, mu0, gL, dv);
 
       if constexpr (MT > 0) {
         // residual dt g(z): c = dt mu_{t+1}
@@ -372,6 +392,8 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
         mlp::broadcast5(dz, n, dzs);
 #pragma unroll
         for (int i = 0; i < N; ++i) mu0[i] += dzs[i];
+        dv[0] += __shfl(dz[1], 16 + n, kWave);  // z rows 5, 6: the controls
+        dv[1] += __shfl(dz[2], 16 + n, kWave);
 #pragma unroll
         for (int t2 = 0; t2 < MT; ++t2) { db1[t2] += da1[t2]; db2[t2] += da2[t2]; }
 #pragma unroll
@@ -416,6 +438,7 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
         }
         __syncthreads();
       }
+      if (du_off >= 0) du_step(p, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
 #pragma unroll
       for (int i = 0; i < N; ++i) mu[i] = mu0[i];
     }
@@ -486,7 +509,7 @@ template <int MT, int SW, bool FAST>
 __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
-    const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp,
+    const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp, int du_off,
     mlp::f4* __restrict__ pre) {
   static_assert(MT % SW == 0, "tiles per wave");
   constexpr int TW = MT / SW;
@@ -647,8 +670,8 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
       for (int i = 0; i < N; ++i) xt[i] = xs[j * N + i];
 #pragma unroll
       for (int q = 0; q < M; ++q) v[q] = vs[j * M + q];
-      float mu0[N];
-      rk4_vjp<FAST>(p, xt, v, mu, mu0, gL);
+      float mu0[N], dv[M] = {0.0f, 0.0f};
+      rk4_vjp<FAST>(p, xt, v, mu, mu0, gL, dv);
       // the MLP residual dt g(z): c = dt mu_{t+1}
       f4 h1[TW], d1[TW], h2[TW], d2[TW];
       {
@@ -714,6 +737,8 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
       mlp::broadcast5(dz, n, dzs);
 #pragma unroll
       for (int i = 0; i < N; ++i) mu0[i] += dzs[i];
+      dv[0] += __shfl(dz[1], 16 + n, kWave);  // z rows 5, 6: the controls
+      dv[1] += __shfl(dz[2], 16 + n, kWave);
 #pragma unroll
       for (int q = 0; q < TW; ++q) {
         db1[q] += da1[q];
@@ -744,6 +769,8 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
         }
       }
       __syncthreads();  // the transposition buffer is rewritten by the next step
+      if (du_off >= 0 && w == 0)
+        du_step(p, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
 #pragma unroll
       for (int i = 0; i < N; ++i) mu[i] = mu0[i];
     }
@@ -783,19 +810,22 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
   }
 }
 
-// grad[j] = sum over the swept tiles of partial[tile][j]: 64 columns per
-// workgroup, the tiles split over 16 lanes per column (tile = p mod 16), the
-// 16 partial sums combined in a fixed order.
+// Column j of the sum over the swept tiles of partial[tile][j]: 64 columns
+// per workgroup, the tiles split over 16 lanes per column (tile = p mod 16),
+// the 16 partial sums combined in a fixed order.  Columns j < ngrad are the
+// gradient (grad[j] = sum, or += with accumulate); columns ngrad.. (ncols >
+// ngrad) are dL/du, added to G[j - ngrad].
 constexpr int kReduceCols = 64, kReduceParts = 16;
 __global__ __launch_bounds__(kReduceCols * kReduceParts) void adjoint_reduce_kernel(
-    const float* __restrict__ partial, int64_t ngp, int ngrad, const BwdMeta* __restrict__ meta,
-    float* __restrict__ grad) {
+    const float* __restrict__ partial, int64_t ngp, int ngrad, int ncols,
+    const BwdMeta* __restrict__ meta, float* __restrict__ grad, int accumulate,
+    float* __restrict__ G) {
   __shared__ float red[kReduceParts][kReduceCols];
   const int c = threadIdx.x % kReduceCols, part = threadIdx.x / kReduceCols;
   const int j = blockIdx.x * kReduceCols + c;
   const int tiles = (meta->count + kTileS - 1) / kTileS;
   float s = 0.0f;
-  if (j < ngrad) {
+  if (j < ncols) {
     int w = part;
     float s1 = 0.0f;
     for (; w + kReduceParts < tiles; w += 2 * kReduceParts) {
@@ -807,11 +837,15 @@ __global__ __launch_bounds__(kReduceCols * kReduceParts) void adjoint_reduce_ker
   }
   red[part][c] = s;
   __syncthreads();
-  if (part == 0 && j < ngrad) {
+  if (part == 0 && j < ncols) {
     float t = red[0][c];
 #pragma unroll
     for (int q = 1; q < kReduceParts; ++q) t += red[q][c];
-    grad[j] = t;
+    if (j < ngrad) {
+      grad[j] = accumulate ? grad[j] + t : t;
+    } else {
+      G[j - ngrad] += t;
+    }
   }
 }
 
@@ -821,11 +855,11 @@ int adjoint_grad_len(uint32_t dynamics, int hidden) {
   return (H ? 14 * H + H * H + 5 : 0) + 6;
 }
 
-AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_every) {
+AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_every, int TM) {
   AdjointScratch s{};
   const int nb = (K + kProjectSamples - 1) / kProjectSamples;
   const int tiles = (K + kTileS - 1) / kTileS;
-  s.ngp = (ngrad + 63) / 64 * 64;
+  s.ngp = (ngrad + TM + 63) / 64 * 64;  // the gradient, then dL/du
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off = (off + b + 255) / 256 * 256; return o; };
   s.gk = take(sizeof(float) * K);
@@ -853,7 +887,7 @@ size_t adjoint_lds_bytes(int hidden, int ckpt_every) {
 
 namespace {
 using SweepFn = void (*)(DevParams, const float*, const float*, int64_t, int, const float*, int,
-                         const BwdItem*, const BwdMeta*, float*, int64_t, mlp::f4*);
+                         const BwdItem*, const BwdMeta*, float*, int64_t, int, mlp::f4*);
 template <int MT>
 SweepFn pick_sweep(bool accurate) {
   return accurate ? adjoint_sweep_kernel<MT, false> : adjoint_sweep_kernel<MT, true>;
@@ -868,8 +902,9 @@ SweepFn pick_split_sweep(bool accurate) {
 hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, float step, const float* d_ckpt,
-                          int ckpt_every, char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
-                          hipStream_t stream, int waves) {
+                          int ckpt_every, char* d_scratch, const AdjointScratch& s, int ngrad,
+                          float* d_grad, hipStream_t stream, int waves, bool accumulate,
+                          float* d_G_acc) {
   SweepFn fn = nullptr;
   size_t lds = adjoint_lds_bytes(hidden, ckpt_every);
   if (waves > 1) {
@@ -918,11 +953,14 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
                      K, static_cast<float>(static_cast<double>(step) / static_cast<double>(lambda)),
                      offs, meta, list);
   const int tiles = (K + kTileS - 1) / kTileS;
+  const int du_off = d_G_acc ? ngrad : -1;
+  const int ncols = ngrad + (d_G_acc ? TM : 0);
+  if (ncols > s.ngp) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(tiles), dim3(kWave * waves), lds, stream, p, d_u, d_eps, ldk, T,
-                     d_ckpt, ckpt_every, list, meta, partial, s.ngp, pre);
-  hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((ngrad + kReduceCols - 1) / kReduceCols),
-                     dim3(kReduceCols * kReduceParts), 0, stream, partial, s.ngp, ngrad, meta,
-                     d_grad);
+                     d_ckpt, ckpt_every, list, meta, partial, s.ngp, du_off, pre);
+  hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((ncols + kReduceCols - 1) / kReduceCols),
+                     dim3(kReduceCols * kReduceParts), 0, stream, partial, s.ngp, ngrad, ncols,
+                     meta, d_grad, accumulate ? 1 : 0, d_G_acc);
   return hipGetLastError();
 }
 

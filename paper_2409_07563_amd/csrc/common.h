@@ -99,6 +99,7 @@ struct BatchPlan {
   int n_row_tiles;
   int n_inst;
   size_t rollout_lds;
+  size_t max_tm_bytes;  // largest T * m of an instance, in bytes (the shift's LDS)
 };
 
 // ---- host launchers (one translation unit each) ---------------------------
@@ -168,14 +169,29 @@ struct AdjointScratch {
   int64_t ngp;  // floats per partial-gradient row
 };
 int adjoint_grad_len(uint32_t dynamics, int hidden);
-AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_every);
+// TM = T * m: room for the dL/du columns of the partial rows
+AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_every, int TM);
 size_t adjoint_lds_bytes(int hidden, int ckpt_every);
+// accumulate: d_grad += the gradient (else d_grad = it); d_G_acc (optional):
+// d_G_acc += sum_k a_k dJ_k/du (may be d_G itself: the update happens after
+// every read of d_G, in stream order).
 hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, float step, const float* d_ckpt,
-                          int ckpt_every,
-                          char* d_scratch, const AdjointScratch& s, int ngrad, float* d_grad,
-                          hipStream_t stream, int waves = 1);
+                          int ckpt_every, char* d_scratch, const AdjointScratch& s, int ngrad,
+                          float* d_grad, hipStream_t stream, int waves = 1,
+                          bool accumulate = false, float* d_G_acc = nullptr);
+hipError_t launch_weights_only(const float* d_S, int K, float lambda, float* d_e,
+                               DevState* d_scratch_state, hipStream_t stream);
+// The differentiation tape (gradient mode): record u and the iteration word
+// of an update in slot *count (if below cap) and advance the count; reset it.
+hipError_t launch_tape_record(const float* d_u, int TM, const DevState* d_state, float* d_tape_u,
+                              uint32_t* d_tape_word, int32_t* d_count, int cap,
+                              hipStream_t stream);
+hipError_t launch_tape_reset(int32_t* d_count, hipStream_t stream);
+// u[t] <- u[min(t + steps, T - 1)] (fill 0) or 0 past the horizon (fill 1)
+hipError_t launch_shift(float* d_u, int T, int m, int steps, int fill, hipStream_t stream);
+hipError_t launch_batch_shift(const BatchPlan& b, int steps, int fill, hipStream_t stream);
 
 hipError_t launch_batch_noise(const BatchPlan& b, hipStream_t stream);
 hipError_t launch_batch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,

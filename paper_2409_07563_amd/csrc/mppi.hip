@@ -65,6 +65,9 @@ struct Layout {
   // the adjoint's scratch
   size_t ckpt, u_roll, adj;
   AdjointScratch adj_layout;
+  // the differentiation tape: u [tape_len][T*m], iteration words, the count,
+  // the reverse pass's dL/du and its scratch state
+  size_t tape_u, tape_word, tape_count, tape_G, tape_state;
   // split rollout form: the trajectory buffer [T][traj_words][ldk] and the
   // cost chunks' partial sums and counts
   size_t traj, split_part;
@@ -84,6 +87,8 @@ int pack_rows(int hidden, bool bwd) {
   }
 }
 bool wants_grad(const mppi_config* c) { return (c->flags & MPPI_F_REQUIRES_GRAD) != 0; }
+// Updates the reverse pass of mppi_backward_iters can reach back through.
+int tape_len_of(const mppi_params* p) { return p->tape_len > 0 ? p->tape_len : 16; }
 // The step size gamma of the update (1: Algorithm 1).
 float step_size(const mppi_config& c) {
   return (c.flags & MPPI_F_STEP_SIZE) ? c.step_size : 1.0f;
@@ -188,6 +193,8 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
                   "the MLP residual), RK4 and the TRACK cost");
     if (p->checkpoint_every < 0 || p->checkpoint_every > 64)
       return fail(MPPI_EINVAL, "checkpoint_every %d outside [0, 64]", p->checkpoint_every);
+    if (p->tape_len < 0 || p->tape_len > 1024)
+      return fail(MPPI_EINVAL, "tape_len %d outside [0, 1024]", p->tape_len);
   }
   if (p->cost_cosines < 0 || p->cost_cosines > 65536)
     return fail(MPPI_EINVAL, "cost_cosines %d outside [0, 65536]", p->cost_cosines);
@@ -264,8 +271,14 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
     const int nseg = (T + ce - 1) / ce;
     L.ckpt = take(sizeof(float) * 7 * static_cast<size_t>(nseg) * L.ldk);
     L.u_roll = take(sizeof(float) * TM);
-    L.adj_layout = adjoint_scratch_layout(K, adjoint_grad_len(c->dynamics, H), H, ce);
+    L.adj_layout = adjoint_scratch_layout(K, adjoint_grad_len(c->dynamics, H), H, ce, TM);
     L.adj = take(L.adj_layout.total);
+    const int tl = tape_len_of(p);
+    L.tape_u = take(sizeof(float) * static_cast<size_t>(tl) * TM);
+    L.tape_word = take(sizeof(uint32_t) * tl);
+    L.tape_count = take(sizeof(int32_t));
+    L.tape_G = take(sizeof(float) * TM);
+    L.tape_state = take(sizeof(DevState));
   }
   if (split_form_for(c, p, batch)) {
     L.traj_words = split_traj_words(c->dynamics, c->cost);
@@ -364,6 +377,7 @@ struct Instance {
   int lanes;   // lanes per sample of the single-instance rollout (1, 4, 8, 16)
   bool split;  // the split rollout form is available
   bool grad;   // MPPI_F_REQUIRES_GRAD
+  int tape_cap;  // gradient mode: tape slots
   int hidden, ckpt_every, n_theta;
   // views into the context's packed regions
   DevState* st;
@@ -441,6 +455,7 @@ struct mppi_ctx {
   bool have_costs = false;
   bool rollout_fresh = false;  // the costs are this iteration's rollout
   bool grad_ready = false;     // an update followed a fresh rollout
+  bool tape_external = false;  // an update since the tape's reset used mppi_set_costs
   std::map<int, hipGraphExec_t> graphs;  // mppi_iterate(I) launch sequences
   mppi_tuning tune{};                     // launch shapes (lanes: instance 0's choice)
   ~mppi_ctx() { drop_graphs(); }
@@ -450,6 +465,17 @@ struct mppi_ctx {
   }
   const Instance& one() const { return inst[0]; }
 };
+
+namespace {
+// The tape starts over: the next update's u no longer depends on the
+// parameters through earlier updates (new controls, state or parameters).
+hipError_t tape_reset(mppi_ctx* c) {
+  if (c->batch || !c->one().grad) return hipSuccess;
+  c->tape_external = false;
+  return launch_tape_reset(c->one().at<int32_t>(c->one().L.tape_count), c->stream);
+}
+
+}  // namespace
 
 namespace {
 
@@ -505,6 +531,7 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
     e = up(I->L.costmap, p->costmap, sizeof(float) * (size_t)p->map_w * p->map_h);
   I->hidden = mlp_hidden_of(cfg, p);
   I->grad = wants_grad(cfg);
+  I->tape_cap = I->grad ? tape_len_of(p) : 0;
   I->ckpt_every = ckpt_every_of(p);
   I->n_theta = adjoint_grad_len(cfg->dynamics, I->hidden);
   if (e == hipSuccess && I->hidden) {
@@ -689,6 +716,9 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
     P.n_row_tiles = static_cast<int>(row_tiles.size());
     P.n_inst = n_inst;
     P.rollout_lds = lds;
+    size_t tm = 0;
+    for (int i = 0; i < n_inst; ++i) tm = std::max(tm, sizeof(float) * c->inst[i].TM);
+    P.max_tm_bytes = tm;
   }
   const hipError_t e2 = hipStreamSynchronize(c->stream);  // host staging buffers die here
   if (e == hipSuccess) e = e2;
@@ -703,6 +733,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   c->tune.noise_calls = 1;
   c->tune.rollout_form = MPPI_ROLLOUT_FUSED;
   c->tune.cost_waves = 8;
+  if (e == hipSuccess) e = tape_reset(c);
   if (e == hipSuccess && batch) e = upload_sample_tiles(c, c->tune.batch_tile);
   if (e != hipSuccess) { delete c; return hip_fail(e, "context upload"); }
   *out = c;
@@ -750,6 +781,12 @@ hipError_t phase_rollout(mppi_ctx* c) {
 hipError_t phase_update(mppi_ctx* c) {
   if (c->batch) return launch_batch_update(c->plan, c->stream);
   const Instance& I = c->one();
+  if (I.grad) {
+    hipError_t e = launch_tape_record(I.u, I.TM, I.st, I.at<float>(I.L.tape_u),
+                                      I.at<uint32_t>(I.L.tape_word), I.at<int32_t>(I.L.tape_count),
+                                      I.tape_cap, c->stream);
+    if (e != hipSuccess) return e;
+  }
   return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, step_size(I.cfg),
                                I.e(), I.u, I.st,
                                c->stream);
@@ -1025,6 +1062,7 @@ mppi_status mppi_set_state(mppi_ctx* c, const float* d_x0) {
   if (!c || !d_x0) return fail(MPPI_EINVAL, "ctx and d_x0 must not be NULL");
   HIP_TRY(hipMemcpyAsync(c->ws + c->C.x0, d_x0, sizeof(float) * c->n_x0, hipMemcpyDeviceToDevice,
                          c->stream));
+  HIP_TRY(tape_reset(c));
   c->have_state = true;
   return MPPI_OK;
 }
@@ -1033,6 +1071,22 @@ mppi_status mppi_set_controls(mppi_ctx* c, const float* d_u) {
   if (!c || !d_u) return fail(MPPI_EINVAL, "ctx and d_u must not be NULL");
   HIP_TRY(hipMemcpyAsync(c->ws + c->C.u, d_u, sizeof(float) * c->n_u, hipMemcpyDeviceToDevice,
                          c->stream));
+  HIP_TRY(tape_reset(c));
+  return MPPI_OK;
+}
+
+mppi_status mppi_shift(mppi_ctx* c, int32_t steps, int32_t fill) {
+  if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
+  if (steps < 0) return fail(MPPI_EINVAL, "steps must be >= 0");
+  if (fill != MPPI_SHIFT_HOLD && fill != MPPI_SHIFT_ZERO)
+    return fail(MPPI_EINVAL, "fill must be MPPI_SHIFT_HOLD or MPPI_SHIFT_ZERO");
+  if (c->batch) {
+    HIP_TRY(launch_batch_shift(c->plan, steps, fill, c->stream));
+  } else {
+    const Instance& I = c->one();
+    HIP_TRY(launch_shift(I.u, I.T, I.m, steps, fill, c->stream));
+  }
+  HIP_TRY(tape_reset(c));
   return MPPI_OK;
 }
 
@@ -1081,6 +1135,7 @@ mppi_status mppi_update(mppi_ctx* c) {
   hipError_t e = phase_update(c);
   if (e != hipSuccess) return hip_fail(e, "update launch");
   c->grad_ready = c->rollout_fresh;
+  if (!c->rollout_fresh) c->tape_external = true;
   return MPPI_OK;
 }
 
@@ -1203,6 +1258,7 @@ mppi_status mppi_set_theta(mppi_ctx* c, const float* host_theta) {
   I.dp.inv_wheelbase = static_cast<float>(1.0 / wheelbase);
   // the kernels take the constants by value: recapture graphs on next use
   c->drop_graphs();
+  HIP_TRY(tape_reset(c));
   return MPPI_OK;
 }
 
@@ -1221,6 +1277,56 @@ mppi_status mppi_backward(mppi_ctx* c, const float* d_dL_dU, float* d_grad) {
                                 I.at<char>(I.L.adj), I.L.adj_layout, I.n_theta, d_grad, c->stream,
                                 c->tune.rollout_block / kWave);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  return MPPI_OK;
+}
+
+mppi_status mppi_backward_iters(mppi_ctx* c, const float* d_dL_dU, float* d_grad,
+                                float* d_dL_du0) {
+  if (!c || !d_dL_dU || !d_grad)
+    return fail(MPPI_EINVAL, "ctx, d_dL_dU and d_grad must not be NULL");
+  if (c->batch || !c->one().grad)
+    return fail(MPPI_ESTATE, "the context was created without MPPI_F_REQUIRES_GRAD");
+  if (c->tape_external)
+    return fail(MPPI_ESTATE, "an update since the tape's start used mppi_set_costs");
+  const Instance& I = c->one();
+  int32_t n = 0;
+  HIP_TRY(hipMemcpyAsync(&n, I.at<int32_t>(I.L.tape_count), sizeof n, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (n < 1) return fail(MPPI_ESTATE, "no update since the tape's start");
+  if (n > I.tape_cap)
+    return fail(MPPI_ESTATE, "more than tape_len = %d updates since the tape's start",
+                I.tape_cap);
+  const bool accurate = (I.cfg.flags & MPPI_F_ACCURATE_TRIG) != 0;
+  const int waves = c->tune.rollout_block / kWave;
+  float* G = I.at<float>(I.L.tape_G);
+  float* ckpt = I.at<float>(I.L.ckpt);
+  DevState* scratch_state = I.at<DevState>(I.L.tape_state);
+  HIP_TRY(hipMemcpyAsync(G, d_dL_dU, sizeof(float) * I.TM, hipMemcpyDeviceToDevice, c->stream));
+  for (int i = n - 1; i >= 0; --i) {
+    // rebuild iteration i from its tape entry: noise, checkpointing rollout, weights
+    const float* u_i = I.at<float>(I.L.tape_u) + static_cast<int64_t>(i) * I.TM;
+    hipError_t e = launch_noise(I.cfg.seed, I.at<uint32_t>(I.L.tape_word) + i, 0u,
+                                I.cfg.instance, I.K, I.T, I.m, I.cfg.sigma, I.eps(), I.L.ldk,
+                                c->stream, c->tune.noise_calls);
+    if (e == hipSuccess)
+      e = launch_rollout_tiles(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp, I.x0,
+                               u_i, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,
+                               c->stream, waves);
+    if (e == hipSuccess) e = launch_weights_only(I.S, I.K, I.cfg.lambda, I.e(), scratch_state,
+                                                 c->stream);
+    // then its reverse pass: grad (+)= sum_k a_k dJ_k/dtheta, G += sum_k a_k dJ_k/du_i
+    if (e == hipSuccess)
+      e = launch_adjoint(I.dp, accurate, I.hidden, G, u_i, I.eps(), I.L.ldk, I.K, I.T, I.e(),
+                         I.cfg.lambda, step_size(I.cfg), ckpt, I.ckpt_every, I.at<char>(I.L.adj),
+                         I.L.adj_layout, I.n_theta, d_grad, c->stream, waves, i != n - 1, G);
+    if (e != hipSuccess) return hip_fail(e, "reverse pass launch");
+  }
+  if (d_dL_du0)
+    HIP_TRY(hipMemcpyAsync(d_dL_du0, G, sizeof(float) * I.TM, hipMemcpyDeviceToDevice,
+                           c->stream));
+  // the noise, cost and weight buffers now hold the first taped iteration's
+  c->rollout_fresh = c->grad_ready = false;
   return MPPI_OK;
 }
 

@@ -31,6 +31,17 @@ hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t l
   return hipGetLastError();
 }
 
+// The weights step alone, its statistics going to a scratch state (the
+// reverse pass of several iterations rebuilds each iteration's weights
+// without touching the context's state).
+hipError_t launch_weights_only(const float* d_S, int K, float lambda, float* d_e,
+                               DevState* d_scratch_state, hipStream_t stream) {
+  const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
+  hipLaunchKernelGGL(weights_kernel_one, dim3(1), dim3(kWeightsBlock), 0, stream, d_S, K, lambda,
+                     inv_lambda, d_e, d_scratch_state);
+  return hipGetLastError();
+}
+
 // w_k = exp(-(J_k - rho)/lambda) / eta from the last update's rho and eta.
 __global__ __launch_bounds__(256) void weights_kernel(const float* __restrict__ S, int K,
                                                       float inv_lambda,
