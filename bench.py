@@ -313,12 +313,27 @@ def bench_grad(args, wl):
         t_fg = timed(grad.stream, lambda: M._abi.check(L.mppi_iterate(grad.ctx, 1)),
                      args.steps, args.warmup)
         swept = int((grad.weights() > 0).sum())
-        grad.close()
-        return t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept, tuning
+        # three warm-started iterations and the reverse pass through all of
+        # them (rebuilds each iteration from the tape, then its adjoint)
+        du0 = torch.empty(wl.T * wl.m, device=dev)
+        u0 = torch.as_tensor(w.u0, device=dev).contiguous()
 
-    t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept, tuning = measure(wl)
+        def fwd3():
+            M._abi.check(L.mppi_set_controls(grad.ctx, u0.data_ptr()))
+            M._abi.check(L.mppi_iterate(grad.ctx, 3))
+
+        def fwd3_bwd():
+            fwd3()
+            M._abi.check(L.mppi_backward_iters(grad.ctx, G.data_ptr(), out.data_ptr(),
+                                               du0.data_ptr()))
+        t_f3 = timed(grad.stream, fwd3, args.steps, args.warmup)
+        t_f3b = timed(grad.stream, fwd3_bwd, args.steps, args.warmup)
+        grad.close()
+        return t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept, tuning, t_f3, t_f3b
+
+    t_fwd, t_noise, t_roll, t_upd, t_fb, t_fg, swept, tuning, t_f3, t_f3b = measure(wl)
     dense = wl.replace(lam=500.0)
-    d_fwd, _, _, _, d_fb, d_fg, d_swept, _ = measure(dense)
+    d_fwd, _, _, _, d_fb, d_fg, d_swept, _, _, _ = measure(dense)
 
     steps = wl.K * wl.T
     flops = 2.0 * mlp_macs(wl.mlp_hidden) * steps
@@ -337,6 +352,8 @@ def bench_grad(args, wl):
         "grad": {"fwd_plain_ms": t_fwd * 1e3, "fwd_checkpointing_ms": t_fg * 1e3,
                  "fwd_plus_bwd_ms": t_fb * 1e3, "bwd_ms": (t_fb - t_fg) * 1e3,
                  "samples_swept": swept,
+                 "three_iterations": {"fwd_ms": t_f3 * 1e3, "fwd_plus_bwd_ms": t_f3b * 1e3,
+                                      "fwd_bwd_over_fwd": t_f3b / t_f3},
                  "lambda_500": {"fwd_bwd_over_fwd": d_fb / d_fwd, "fwd_plus_bwd_ms": d_fb * 1e3,
                                 "bwd_ms": (d_fb - d_fg) * 1e3, "samples_swept": d_swept}},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12,
