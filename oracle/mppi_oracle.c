@@ -243,7 +243,46 @@ typedef struct {
   /* cosines chained ahead of every running cost, scaled by zero (the cost
    * complexity experiment of the Results section); 0 = none */
   int32_t cost_cosines;
+  /* sampling options (section "Sampling Distributions"): a per-step standard
+   * deviation table sigma_t[T][m] (NULL: sigma for every step); sample 0 drawn
+   * without noise (the mean itself); a fraction of the samples drawn around
+   * zero instead of u (the last floor(zero_frac K) samples, at most K - 1 of
+   * them when sample 0 is the noiseless mean) */
+  const float* sigma_t;
+  int32_t mean_sample;
+  double zero_frac;
 } orc_problem;
+
+/* Samples k >= orc_plain_count(P) are drawn around zero. */
+static int32_t orc_plain_count(const orc_problem* P) {
+  int32_t nz = (int32_t)floor(P->zero_frac * (double)P->K);
+  if (nz > P->K) nz = P->K;
+  if (P->mean_sample && nz > P->K - 1) nz = P->K - 1;
+  if (nz < 0) nz = 0;
+  return P->K - nz;
+}
+
+/* The standard deviation of control j at step t. */
+static float orc_sigma(const orc_problem* P, int32_t t, int j) {
+  return P->sigma_t ? P->sigma_t[(int64_t)t * P->m + j] : P->sigma[j];
+}
+
+/* The perturbations of one iteration with the sampling options:
+ * eps[t][j][k] = sigma_{t,j} z (one binary32 product of the standard normal
+ * z of the noise definition), and eps[.][.][0] = 0 for the noiseless mean
+ * sample. */
+void orc_sample(const orc_problem* P, uint32_t iter, int64_t ldk, float* eps) {
+  const int32_t K = P->K, T = P->T, m = P->m;
+  for (int32_t t = 0; t < T; ++t)
+    for (int32_t j = 0; j < m; ++j) {
+      const float sg = orc_sigma(P, t, j);
+      for (int32_t k = 0; k < K; ++k) {
+        const uint32_t n = (uint32_t)(t * m + j);
+        const float z = std_normal(P->seed, (uint32_t)k, iter, P->instance, n);
+        eps[((int64_t)t * m + j) * ldk + k] = (P->mean_sample && k == 0) ? 0.0f : sg * z;
+      }
+    }
+}
 
 /* ------------------------------------------------------------------------ */
 /* 3. Models                                                                 */
@@ -576,36 +615,43 @@ static double terminal_cost(const orc_problem* P, const double* x) {
  * the sum over steps of the costmap's |dM/dx| + |dM/dy| at the visited
  * positions (how strongly the cost reacts to a position error). */
 /* The importance-sampling term of one step (section "MPPI-Generic's MPPI
- * Implementation" and Eq. information_theoretic_weighting): the sampling distribution N(u_t, Sigma)
- * against the base distribution N(0, Sigma) gives ln p/s = -(v - u/2)' Sigma^-1
- * u, and the weights use J - lambda beta ln p/s, i.e. J plus
- * lambda (v - u/2)' Sigma^-1 u (Sigma diagonal). */
-static double is_term(const orc_problem* P, const double* u_t, const double* v) {
+ * Implementation" and Eq. information_theoretic_weighting): the sampling
+ * distribution N(u_t, Sigma_t) against the base distribution N(0, Sigma_t)
+ * gives ln p/s = -(v - u/2)' Sigma_t^-1 u, and the weights use
+ * J - lambda beta ln p/s, i.e. J plus lambda (v - u/2)' Sigma_t^-1 u (Sigma_t
+ * diagonal).  u_t is the mean the sample was drawn around (zero for the
+ * zero-mean samples, whose term then vanishes: their density is the base
+ * one). */
+static double is_term(const orc_problem* P, int32_t t, const double* u_t, const double* v) {
   double s = 0.0;
   for (int j = 0; j < P->m; ++j) {
-    const double sg = (double)P->sigma[j];
+    const double sg = (double)orc_sigma(P, t, j);
     s += (v[j] - 0.5 * u_t[j]) * u_t[j] / (sg * sg);
   }
   return P->lambda * s;
 }
 
-/* S[k]: the cost J of sample k's rollout (Algorithm 1), plus the
+/* S[k]: the cost J of sample k's rollout (Algorithm 1) with
+ * v = u + eps_k (v = eps_k for the zero-mean samples), plus the
  * importance-sampling term when P->is_beta is set. */
 void orc_rollout_costs(const orc_problem* P, const double* x0, const double* u,
                        const float* eps, int64_t ldk, double* S, double* margin,
                        int32_t* crashes, double* slope) {
   const int n = P->n, m = P->m;
+  const int32_t n_plain = orc_plain_count(P);
   for (int32_t k = 0; k < P->K; ++k) {
-    double x[16], v[8];
+    double x[16], v[8], mean[8];
     for (int i = 0; i < n; ++i) x[i] = x0[i];
     double J = 0.0, mg = INFINITY, sl = 0.0;
     int cr = 0;
     for (int32_t t = 0; t < P->T; ++t) {
-      for (int j = 0; j < m; ++j)
-        v[j] = u[t * m + j] + (double)eps[((int64_t)t * m + j) * ldk + k];
+      for (int j = 0; j < m; ++j) {
+        mean[j] = k < n_plain ? u[t * m + j] : 0.0;
+        v[j] = mean[j] + (double)eps[((int64_t)t * m + j) * ldk + k];
+      }
       orc_step(P, x, v);
       J += running_cost(P, x, v, t, &mg, &cr, &sl);
-      if (P->is_beta) J += is_term(P, u + t * m, v);
+      if (P->is_beta) J += is_term(P, t, mean, v);
     }
     J += terminal_cost(P, x);
     if (!isfinite(J)) J = INFINITY;
@@ -646,12 +692,17 @@ int orc_softmin_update(const orc_problem* P, const double* S, const float* eps,
     w[k] = exp(-(S[k] - rho) / lam) / eta;
     sw2 += w[k] * w[k];
   }
+  /* U = u + gamma sum_k w_k (v_k - u): v_k - u = eps_k for the samples
+   * drawn around u, eps_k - u for those drawn around zero */
+  const int32_t n_plain = orc_plain_count(P);
   for (int32_t t = 0; t < T; ++t)
     for (int32_t j = 0; j < m; ++j) {
       double acc = 0.0;
       const float* row = eps + ((int64_t)t * m + j) * ldk;
-      for (int32_t k = 0; k < K; ++k) acc += w[k] * (double)row[k];
-      U[t * m + j] = u[t * m + j] + P->gamma * acc;
+      const double ut = u[t * m + j];
+      for (int32_t k = 0; k < K; ++k)
+        acc += w[k] * (k < n_plain ? (double)row[k] : (double)row[k] - ut);
+      U[t * m + j] = ut + P->gamma * acc;
     }
   if (stats) {
     stats[0] = rho;
@@ -675,7 +726,7 @@ int orc_mppi(const orc_problem* P, const double* x0, double* u, int32_t iters,
   double* U = (double*)malloc(sizeof(double) * (size_t)T * m);
   int rc = 0;
   for (int32_t i = 0; i < iters; ++i) {
-    orc_noise(P->seed, iter0 + (uint32_t)i, P->instance, K, T, m, P->sigma, K, eps);
+    orc_sample(P, iter0 + (uint32_t)i, K, eps);
     orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL, NULL);
     rc = orc_softmin_update(P, S, eps, K, u, w, U, stats_out);
     for (int32_t q = 0; q < T * m; ++q) u[q] = U[q];
@@ -920,7 +971,7 @@ static void step_vjp(const orc_problem* P, const double* x0, const double* v, co
 
 static int backward_supported(const orc_problem* P) {
   return (P->model == ORC_BICYCLE || P->model == ORC_BICYCLE_MLP) && P->cost == ORC_COST_TRACK &&
-         P->integrator == ORC_RK4;
+         P->integrator == ORC_RK4 && orc_plain_count(P) == P->K;
 }
 
 /* One iteration's reverse pass (accumulating): grad += dL/dtheta at fixed u,
@@ -1008,7 +1059,8 @@ static int backward_one(const orc_problem* P, const double* x0, const double* u,
          * v = u + eps: its derivative in u is lambda Sigma^-1 v */
         if (P->is_beta)
           for (int j = 0; j < m; ++j)
-            dv[j] += P->lambda * vs[t * m + j] / ((double)P->sigma[j] * (double)P->sigma[j]);
+            dv[j] += P->lambda * vs[t * m + j] /
+                     ((double)orc_sigma(P, t, j) * (double)orc_sigma(P, t, j));
         for (int i = 0; i < n; ++i) mu[i] = mu0[i];
       }
       for (int i = 0; i < ngrad; ++i) {
@@ -1090,7 +1142,7 @@ int orc_backward_iters(const orc_problem* P, const double* x0, const double* u0,
   for (int32_t it = 0; it < iters; ++it) {
     const double* u = tape + (size_t)it * TM;
     double* U = tape + (size_t)(it + 1) * TM;
-    orc_noise(P->seed, iter0 + (uint32_t)it, P->instance, K, T, m, P->sigma, K, eps);
+    orc_sample(P, iter0 + (uint32_t)it, K, eps);
     orc_rollout_costs(P, x0, u, eps, K, S, NULL, NULL, NULL);
     const int r = orc_softmin_update(P, S, eps, K, u, w, U, stats);
     if (r && !rc) rc = r;
@@ -1103,7 +1155,7 @@ int orc_backward_iters(const orc_problem* P, const double* x0, const double* u0,
   double* du = (double*)malloc(sizeof(double) * TM);
   for (int i = 0; i < TM; ++i) Gc[i] = G[i];
   for (int32_t it = iters - 1; it >= 0; --it) {
-    orc_noise(P->seed, iter0 + (uint32_t)it, P->instance, K, T, m, P->sigma, K, eps);
+    orc_sample(P, iter0 + (uint32_t)it, K, eps);
     for (int i = 0; i < TM; ++i) du[i] = 0.0;
     const int r = backward_one(P, x0, tape + (size_t)it * TM, eps, Gc, NULL, NULL, grad, grad_abs,
                                du, NULL, NULL, NULL, NULL);

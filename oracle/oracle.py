@@ -41,6 +41,7 @@ class OrcProblem(C.Structure):
         ("map_x0", C.c_double), ("map_y0", C.c_double), ("map_res", C.c_double),
         ("map", _dp),
         ("is_beta", C.c_int32), ("gamma", C.c_double), ("cost_cosines", C.c_int32),
+        ("sigma_t", C.POINTER(C.c_float)), ("mean_sample", C.c_int32), ("zero_frac", C.c_double),
     ]
 
 
@@ -89,6 +90,7 @@ def lib():
         L.orc_cost_condition.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p]
         L.orc_cost_condition.restype = C.c_int
         L.orc_shift.argtypes = [P, f64p, C.c_int32, C.c_int32]
+        L.orc_sample.argtypes = [P, C.c_uint32, C.c_int64, f32p]
         L.orc_trajectory.argtypes = [P, f64p, f64p, f64p]
         L.orc_sequence_cost.argtypes = [P, f64p, f64p]
         L.orc_sequence_cost.restype = C.c_double
@@ -134,6 +136,13 @@ class Problem:
         p.is_beta = int(getattr(wl, "is_beta", 0))
         p.gamma = float(np.float32(getattr(wl, "gamma", 1.0)))
         p.cost_cosines = int(getattr(wl, "cost_cosines", 0))
+        p.mean_sample = int(getattr(wl, "mean_sample", 0))
+        p.zero_frac = float(np.float32(getattr(wl, "zero_frac", 0.0)))
+        sig_t = getattr(wl, "sigma_t", None)
+        if sig_t is not None:
+            st = np.ascontiguousarray(np.asarray(sig_t, np.float32).ravel())
+            self._sigma_t = st
+            p.sigma_t = st.ctypes.data_as(C.POINTER(C.c_float))
         for i in range(32):
             p.w[i] = float(wl.w[i])
         self._keep = []
@@ -200,7 +209,12 @@ def noise(seed: int, iteration: int, instance: int, K: int, T: int, m: int,
 
 
 def workload_noise(wl, iteration: int = 0) -> np.ndarray:
-    return noise(wl.seed, iteration, wl.instance, wl.K, wl.T, wl.m, wl.sigma)
+    """eps[T][m][K] of an iteration of the workload, with its sampling options
+    (per-step sigma, noiseless mean sample)."""
+    P = Problem(wl)
+    eps = np.empty((wl.T, wl.m, wl.K), np.float32)
+    lib().orc_sample(P.ref, iteration, wl.K, eps)
+    return eps
 
 
 # --------------------------------------------------------------------------

@@ -194,3 +194,32 @@ def test_one_iteration_of_the_chain_is_the_single_backward():
     b = O.backward_iters(wl, G, 1)
     assert np.array_equal(a["grad"], b["grad"])
     assert np.array_equal(G + a["du"], b["du0"])
+
+
+def test_gradient_with_sampling_options_vs_fd():
+    """Per-step sigma (in the importance term's derivative) and the noiseless
+    mean sample through two iterations."""
+    wl = W.c5(K=40, T=10, hidden=8).replace(lam=20.0)
+    sig_t = np.random.default_rng(8).uniform(0.5, 1.2, (10, 2)).astype(np.float32)
+    u0 = np.random.default_rng(9).normal(0, 0.2, (10, 2)).astype(np.float32)
+    wl = wl.replace(u0=u0, sigma_t=sig_t, mean_sample=1, is_beta=1, gamma=0.9)
+    uref = W.c5_uref(T=10)
+    L0, U0 = O.loss_and_controls(wl, uref, iters=2)
+    r = O.backward_iters(wl, 2.0 * (U0 - uref), 2)
+    theta = O.theta_of(wl)
+    n = O.n_grad(wl)
+    scale = np.abs(r["grad"]).max()
+    for i in list(range(0, n - 6, 37)) + list(range(n - 6, n)):
+        h = 1e-3 * max(1.0, abs(theta[i]))
+        fd = _fd_theta(wl, uref, theta, i, h, 2)
+        assert abs(r["grad"][i] - fd) <= 2e-5 * max(abs(fd), 1e-3 * scale), (i, r["grad"][i], fd)
+    su = np.abs(r["du0"]).max()
+    for j in range(0, 20, 3):
+        fd = _fd_u(wl, uref, u0.astype(np.float64), j, 1e-3, 2)
+        assert abs(r["du0"].flat[j] - fd) <= 2e-5 * max(abs(fd), 1e-3 * su), (j, r["du0"].flat[j], fd)
+
+
+def test_backward_refuses_zero_mean_samples():
+    wl = W.c5(K=16, T=5, hidden=8).replace(zero_frac=0.5)
+    with pytest.raises(ValueError):
+        O.backward(wl, np.zeros((5, 2)))

@@ -170,3 +170,66 @@ def test_shift_composes(oracle_lib):
         for a, b in ((1, 1), (3, 5), (20, 20), (0, 9)):
             two = oracle_lib.shift(wl, oracle_lib.shift(wl, u, a, fill), b, fill)
             assert np.array_equal(two, oracle_lib.shift(wl, u, a + b, fill))
+
+
+# ---------------------------------------------------------------------------
+# sampling options (section "Sampling Distributions")
+# ---------------------------------------------------------------------------
+def test_noiseless_mean_sample(oracle_lib):
+    wl = _with_controls(W.c2("circles", K=200, T=30, iters=1), 12, 0.4)
+    plain = oracle_lib.workload_noise(wl)
+    wm = wl.replace(mean_sample=1)
+    eps = oracle_lib.workload_noise(wm)
+    assert np.all(eps[:, :, 0].view(np.uint32) == 0)           # +0.0 exactly
+    assert np.array_equal(eps[:, :, 1:], plain[:, :, 1:])
+    S, _, _ = oracle_lib.rollout_costs(wm, eps=eps)
+    assert S[0] == oracle_lib.sequence_cost(wl, wl.u0)
+
+
+def test_zero_mean_samples(oracle_lib):
+    wl = _with_controls(W.c2("circles", K=300, T=30, iters=1), 13, 0.4)
+    wz = wl.replace(zero_frac=0.25, gamma=0.6)
+    eps = oracle_lib.workload_noise(wz)
+    S, _, _ = oracle_lib.rollout_costs(wz, eps=eps)
+    S_u, _, _ = oracle_lib.rollout_costs(wl, eps=eps)
+    S_0, _, _ = oracle_lib.rollout_costs(wl, eps=eps, u=np.zeros((30, 2)))
+    n_plain = 300 - 75
+    assert np.array_equal(S[:n_plain], S_u[:n_plain])
+    assert np.array_equal(S[n_plain:], S_0[n_plain:])
+    w, U, _, rc = oracle_lib.softmin_update(wz, S, eps)
+    # the mirror-descent form over the samples' controls v_k
+    u = wl.u0.astype(np.float64)
+    v = eps.astype(np.float64).copy()
+    v[:, :, :n_plain] += u[:, :, None]
+    U_ref = (1 - np.float32(0.6)) * u + np.float32(0.6) * np.tensordot(v, w, axes=([2], [0]))
+    assert rc == 0 and np.allclose(U, U_ref, rtol=1e-13, atol=1e-13)
+
+
+def test_all_samples_around_zero_forget_u(oracle_lib):
+    """With every sample drawn around zero (and gamma = 1, no importance
+    term) the update is sum_k w_k eps_k, whatever u was."""
+    wl = W.c1(K=64, T=12).replace(zero_frac=1.0)
+    a = oracle_lib.mppi(_with_controls(wl, 1, 0.5), iters=1)
+    b = oracle_lib.mppi(_with_controls(wl, 2, 0.5), iters=1)
+    assert np.array_equal(a["S"], b["S"])
+    assert np.allclose(a["U"], b["U"], rtol=0, atol=1e-14)
+
+
+def test_time_varying_sigma(oracle_lib):
+    wl = _with_controls(W.c2("circles", K=100, T=25, iters=1), 14, 0.3)
+    z = oracle_lib.noise(wl.seed, 0, wl.instance, wl.K, wl.T, wl.m, np.ones(2, np.float32))
+    sig_t = np.random.default_rng(4).uniform(0.2, 1.5, (25, 2)).astype(np.float32)
+    ws = wl.replace(sigma_t=sig_t)
+    eps = oracle_lib.workload_noise(ws)
+    assert np.array_equal(eps, (sig_t[:, :, None] * z).astype(np.float32))
+    const = wl.replace(sigma_t=np.tile(wl.sigma, (25, 1)))
+    assert np.array_equal(oracle_lib.workload_noise(const), oracle_lib.workload_noise(wl))
+    # the importance term against per-step Gaussian log-densities
+    S0, _, _ = oracle_lib.rollout_costs(ws, eps=eps)
+    S1, _, _ = oracle_lib.rollout_costs(ws.replace(is_beta=1), eps=eps)
+    u = ws.u0.astype(np.float64)[:, :, None]
+    v = u + eps.astype(np.float64)
+    sg = sig_t.astype(np.float64)[:, :, None]
+    I = (norm.logpdf(v, 0.0, sg) - norm.logpdf(v, u, sg)).sum(axis=(0, 1))
+    scale = np.abs(S0) + np.abs(_lam32(ws) * I)
+    assert np.all(np.abs((S1 - S0) + _lam32(ws) * I) <= 1e-12 * scale)

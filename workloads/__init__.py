@@ -58,6 +58,9 @@ class Workload:
     is_beta: int = 0      # importance-sampling term in the weights (0 or 1)
     gamma: float = 1.0    # step size of the update (1: plain MPPI)
     cost_cosines: int = 0 # cosines chained ahead of each running cost, times 0
+    mean_sample: int = 0  # sample 0 drawn without noise (v = u)
+    zero_frac: float = 0.0  # fraction of the samples drawn around zero
+    sigma_t: Optional[np.ndarray] = None  # per-step noise std [T][m] (None: sigma)
     wheelbase: float = 0.0
     mass: float = 0.0
     inertia: tuple = (0.0, 0.0, 0.0)
