@@ -133,7 +133,10 @@ enum {
                                 cost, which is the cost the weights are formed from
                                 and mppi_get_debug(MPPI_DEBUG_COSTS) returns; needs
                                 every sigma > 0.  Without it beta = 0 (Algorithm 1) */
-  MPPI_F_STEP_SIZE = 64u     /* use config.step_size as the step size gamma >= 0 of
+  MPPI_F_MEAN_SAMPLE = 128u, /* sample 0 is drawn without noise (eps_0 = 0, v = u: the
+                                mean itself is one of the samples; section
+                                "Sampling Distributions") */
+  MPPI_F_STEP_SIZE = 64u,    /* use config.step_size as the step size gamma >= 0 of
                                 the dynamic mirror-descent update (section
                                 "Comparisons to sampling-efficient algorithms"):
                                 U = (1 - gamma) u + gamma sum_k w_k v_k, computed as
@@ -157,6 +160,13 @@ typedef struct mppi_config {
   uint32_t instance;     /* Philox counter word 3 (independent streams) */
   uint32_t flags;        /* MPPI_F_* */
   float step_size;       /* gamma, read only with MPPI_F_STEP_SIZE: finite, >= 0 */
+  float zero_mean_fraction; /* in [0, 1]: the last floor(fraction K) samples (at
+                               most K - 1 with MPPI_F_MEAN_SAMPLE) are drawn around
+                               zero instead of u: v_k = eps_k, the update is
+                               U = u + gamma sum_k w_k (v_k - u), their
+                               importance-sampling term is zero (section
+                               "Sampling Distributions").  Not with
+                               MPPI_F_REQUIRES_GRAD */
 } mppi_config;
 
 /* Model and cost constants.  Every array pointer is host memory, read during
@@ -186,6 +196,10 @@ typedef struct mppi_params {
                                checkpoints, 1..64 (0 = 10) */
   int32_t tape_len;       /* MPPI_F_REQUIRES_GRAD: updates mppi_backward_iters can
                              differentiate through, 1..1024 (0 = 16) */
+  const float* sigma_t;   /* optional [T][m]: a noise standard deviation per step and
+                             control (>= 0, > 0 with MPPI_F_IMPORTANCE_SAMPLING),
+                             replacing config.sigma; eps = sigma_t[t][j] z (one
+                             binary32 product; section "Sampling Distributions") */
   int32_t cost_cosines;   /* 0..65536 nested cosines evaluated ahead of every running
                              cost and scaled by zero: the synthetic cost-complexity
                              load of the paper's Results section.  It changes no

@@ -31,6 +31,7 @@ F_ROLLOUT_QUAD = 8
 F_REQUIRES_GRAD = 16
 F_IMPORTANCE_SAMPLING = 32
 F_STEP_SIZE = 64
+F_MEAN_SAMPLE = 128
 ROLLOUT_FUSED, ROLLOUT_SPLIT = 0, 1
 SHIFT_HOLD, SHIFT_ZERO = 0, 1
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
@@ -46,7 +47,7 @@ class Config(C.Structure):
                 ("state_dim", C.c_int32), ("control_dim", C.c_int32),
                 ("dt", C.c_float), ("lam", C.c_float), ("sigma", C.c_float * MAX_CONTROL),
                 ("seed", C.c_uint64), ("instance", C.c_uint32), ("flags", C.c_uint32),
-                ("step_size", C.c_float)]
+                ("step_size", C.c_float), ("zero_mean_fraction", C.c_float)]
 
 
 class Params(C.Structure):
@@ -58,7 +59,7 @@ class Params(C.Structure):
                 ("map_w", C.c_int32), ("map_h", C.c_int32), ("map_x0", C.c_float),
                 ("map_y0", C.c_float), ("map_res", C.c_float), ("costmap", _fp),
                 ("checkpoint_every", C.c_int32), ("tape_len", C.c_int32),
-                ("cost_cosines", C.c_int32)]
+                ("sigma_t", _fp), ("cost_cosines", C.c_int32)]
 
 
 class Tuning(C.Structure):

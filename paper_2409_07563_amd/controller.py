@@ -47,7 +47,9 @@ def _config(pb, debug: bool, accurate_trig: bool, rollout: str,
                  | {"auto": 0, "lane": _abi.F_ROLLOUT_LANE, "quad": _abi.F_ROLLOUT_QUAD}[rollout]
                  | (_abi.F_REQUIRES_GRAD if requires_grad else 0)
                  | (_abi.F_IMPORTANCE_SAMPLING if getattr(pb, "is_beta", 0) else 0)
+                 | (_abi.F_MEAN_SAMPLE if getattr(pb, "mean_sample", 0) else 0)
                  | _abi.F_STEP_SIZE)
+    cfg.zero_mean_fraction = float(np.float32(getattr(pb, "zero_frac", 0.0)))
     # always explicit (gamma = 1 is Algorithm 1): the instances of a batch
     # share their flags but not their step sizes
     cfg.step_size = float(np.float32(getattr(pb, "gamma", 1.0)))
@@ -59,6 +61,7 @@ def _params(pb, keep: list, checkpoint_every: int = 0, tape_len: int = 0) -> _ab
     p.checkpoint_every = int(checkpoint_every)
     p.tape_len = int(tape_len)
     p.cost_cosines = int(getattr(pb, "cost_cosines", 0))
+    sig_t = getattr(pb, "sigma_t", None)
 
     def arr(a):
         a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
@@ -91,6 +94,8 @@ def _params(pb, keep: list, checkpoint_every: int = 0, tape_len: int = 0) -> _ab
         p.map_x0, p.map_y0 = float(pb.map_x0), float(pb.map_y0)
         p.map_res = float(pb.map_res)
         p.costmap = arr(pb.costmap)
+    if sig_t is not None:
+        p.sigma_t = arr(sig_t)
     return p
 
 

@@ -243,12 +243,13 @@ __device__ __forceinline__ float group_sum(float v) {
 // derivative in u through v = u + eps and directly (lambda Sigma^-1 v) are
 // added, then the 16 samples of the tile are summed (fixed xor tree) and
 // lane 0 writes out[0..1].  Every lane of the wave must call it.
-__device__ __forceinline__ void du_step(const DevParams& p, float a, const float* v, float* dv,
-                                        int lane, float* out) {
+__device__ __forceinline__ void du_step(const DevParams& p, int t, float a, const float* v,
+                                        float* dv, int lane, float* out) {
+  const float* cf = p.is_coef_t ? p.is_coef_t + 2 * t : p.is_coef;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     float d = dv[q] + a * (2.0f * p.w[8 + q] * v[q]);
-    if (p.importance) d += a * (p.is_coef[q] * v[q]);
+    if (p.importance) d += a * (cf[q] * v[q]);
     const float sum = group_sum(d);
     if (lane == 0) out[q] = sum;
   }
@@ -438,7 +439,8 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
         }
         __syncthreads();
       }
-      if (du_off >= 0) du_step(p, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
+      if (du_off >= 0)
+        du_step(p, t, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
 #pragma unroll
       for (int i = 0; i < N; ++i) mu[i] = mu0[i];
     }
@@ -770,7 +772,7 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
       }
       __syncthreads();  // the transposition buffer is rewritten by the next step
       if (du_off >= 0 && w == 0)
-        du_step(p, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
+        du_step(p, t, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
 #pragma unroll
       for (int i = 0; i < N; ++i) mu[i] = mu0[i];
     }

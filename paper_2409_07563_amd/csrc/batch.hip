@@ -26,7 +26,8 @@ __global__ __launch_bounds__(kBatchMaxTile) void batch_noise_kernel(
   const int ncall = (b.TM + 3) / 4;
   const int m = b.TM / b.T;
   for (int c = 0; c < ncall; ++c)
-    noise::emit_call(b.key0, b.key1, it, b.instance, k, c, b.TM, m, b.sigma.v, b.eps, b.ldk);
+    noise::emit_call(b.key0, b.key1, it, b.instance, k, c, b.TM, m, b.sigma.v, b.eps, b.ldk,
+                     b.p.sigma_t, b.p.mean_sample && k == 0);
 }
 
 // (a2) one lane per sample over a tile of samples of one instance;
@@ -42,7 +43,8 @@ __global__ __launch_bounds__(kBatchMaxTile) void batch_rollout_kernel(
   const int k = tl.y * static_cast<int>(blockDim.x) + threadIdx.x;
   if (k >= b.K) return;  // no barrier follows
   const RolloutResult r =
-      rollout_lane<Model, INTEG, Cost, COUNT>(p, b.x0, lds_u, b.eps + k, b.ldk, b.T, lds);
+      rollout_lane<Model, INTEG, Cost, COUNT>(p, b.x0, lds_u, b.eps + k, b.ldk, b.T, lds,
+                                              k < p.n_plain);
   b.S[k] = r.cost;
   if constexpr (COUNT) b.crashes[k] = r.crashes;
 }
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(kBatchMaxTile) void batch_rollout_kernel(
 __global__ __launch_bounds__(kWeightsBlock) void batch_weights_kernel(
     const BatchInst* __restrict__ insts) {
   const BatchInst& b = insts[blockIdx.x];
-  weights_body(b.S, b.K, b.lambda, b.inv_lambda, b.e, b.st);
+  weights_body(b.S, b.K, b.lambda, b.inv_lambda, b.e, b.st, b.p.n_plain);
 }
 
 __global__ __launch_bounds__(kGemvBlock) void batch_gemv_kernel(const BatchInst* __restrict__ insts,

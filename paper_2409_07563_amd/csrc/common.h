@@ -51,6 +51,14 @@ struct DevParams {
   float is_coef[MPPI_MAX_CONTROL];
   // nested cosines ahead of each running cost (a pure compute load)
   int cosines;
+  // sampling options: samples k < n_plain are drawn around u, the others
+  // around zero; per-step importance coefficients lambda / sigma_{t,j}^2
+  // ([T][m], null: is_coef for every step) and noise deviations ([T][m],
+  // null: the configuration's sigma)
+  int n_plain;
+  const float* is_coef_t;
+  const float* sigma_t;
+  int mean_sample;  // sample 0 drawn without noise
 };
 
 // Largest circle grid the rollout kernel stages into LDS.
@@ -63,7 +71,8 @@ struct DevState {
   float stats[4];     // rho, eta, free energy, 1/sum w^2
   int32_t status;     // MPPI_OK or MPPI_ENUMERIC
   uint32_t iteration; // Philox iteration word of the next sampling
-  int32_t pad[2];
+  float wz;           // weight of the samples drawn around zero (0 when none)
+  int32_t pad;
 };
 
 // One instance of a batch, as the batched kernels read it (device memory).
@@ -106,9 +115,12 @@ struct BatchPlan {
 // The iteration word is *d_iteration + iteration when d_iteration is given
 // (read on the device at run time), else iteration.
 // calls: Philox calls per thread (1, 2 or 4; the values do not depend on it)
+// d_sigma_t (optional, device [T][m]): per-step deviations replacing sigma;
+// mean_sample: eps[.][.][0] = 0.
 hipError_t launch_noise(uint64_t seed, const uint32_t* d_iteration, uint32_t iteration,
                         uint32_t instance, int K, int T, int m, const float* sigma,
-                        float* d_eps, int64_t ldk, hipStream_t stream, int calls = 1);
+                        float* d_eps, int64_t ldk, hipStream_t stream, int calls = 1,
+                        const float* d_sigma_t = nullptr, bool mean_sample = false);
 hipError_t launch_noise_tables(float* d_r, float* d_c, float* d_s, hipStream_t stream);
 
 // Returns hipErrorInvalidValue when the (dynamics, integrator, cost)
@@ -145,10 +157,12 @@ size_t rollout_lds_bytes(uint32_t dynamics, uint32_t cost, int stage_words4, int
 constexpr size_t kMaxRolloutLds = 160 * 1024;
 
 int gemv_rows_per_block();
-// step: the step size gamma of u += gamma sum_k w_k eps_k (1 for Algorithm 1)
+// step: the step size gamma of u += gamma sum_k w_k (v_k - u) (1 for
+// Algorithm 1); samples k >= n_plain were drawn around zero (n_plain = K:
+// none)
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
                                  int TM, float lambda, float step, float* d_e, float* d_u,
-                                 DevState* d_state, hipStream_t stream);
+                                 DevState* d_state, hipStream_t stream, int n_plain);
 hipError_t launch_set_iteration(DevState* d_state, uint32_t iteration, hipStream_t stream);
 hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState* d_state,
                           float* d_w, hipStream_t stream);

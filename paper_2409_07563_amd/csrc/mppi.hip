@@ -61,6 +61,7 @@ struct Layout {
   int64_t ldk;  // noise row stride (K rounded up to a wave)
   size_t eps, e;
   size_t ref, stage, costmap, mlp, mlp_bwd;
+  size_t sigma_t, is_coef_t;  // per-step noise deviations and importance coefficients
   // MPPI_F_REQUIRES_GRAD: checkpoints [nseg][7][ldk], the rollout's controls,
   // the adjoint's scratch
   size_t ckpt, u_roll, adj;
@@ -89,6 +90,16 @@ int pack_rows(int hidden, bool bwd) {
 bool wants_grad(const mppi_config* c) { return (c->flags & MPPI_F_REQUIRES_GRAD) != 0; }
 // Updates the reverse pass of mppi_backward_iters can reach back through.
 int tape_len_of(const mppi_params* p) { return p->tape_len > 0 ? p->tape_len : 16; }
+// Samples k >= n_plain are drawn around zero: the last floor(fraction K), at
+// most K - 1 when sample 0 is the noiseless mean.
+int n_plain_of(const mppi_config* c) {
+  const int K = c->num_samples;
+  int64_t nz = static_cast<int64_t>(floor(static_cast<double>(c->zero_mean_fraction) * K));
+  if (nz > K) nz = K;
+  if ((c->flags & MPPI_F_MEAN_SAMPLE) && nz > K - 1) nz = K - 1;
+  if (nz < 0) nz = 0;
+  return K - static_cast<int>(nz);
+}
 // The step size gamma of the update (1: Algorithm 1).
 float step_size(const mppi_config& c) {
   return (c.flags & MPPI_F_STEP_SIZE) ? c.step_size : 1.0f;
@@ -173,6 +184,17 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
         return fail(MPPI_EINVAL, "MPPI_F_IMPORTANCE_SAMPLING needs sigma[%d] > 0", j);
   if ((c->flags & MPPI_F_STEP_SIZE) && (!(c->step_size >= 0.0f) || !isfinite(c->step_size)))
     return fail(MPPI_EINVAL, "step_size must be finite and >= 0");
+  if (!(c->zero_mean_fraction >= 0.0f && c->zero_mean_fraction <= 1.0f))
+    return fail(MPPI_EINVAL, "zero_mean_fraction must be in [0, 1]");
+  if (wants_grad(c) && c->zero_mean_fraction != 0.0f)
+    return fail(MPPI_EUNSUPPORTED, "MPPI_F_REQUIRES_GRAD needs zero_mean_fraction = 0");
+  if (p->sigma_t)
+    for (int64_t i = 0; i < (int64_t)c->horizon * m; ++i) {
+      const float sg = p->sigma_t[i];
+      if (!(sg >= 0.0f) || !isfinite(sg)) return fail(MPPI_EINVAL, "sigma_t[%lld] must be finite and >= 0", (long long)i);
+      if ((c->flags & MPPI_F_IMPORTANCE_SAMPLING) && !(sg > 0.0f))
+        return fail(MPPI_EINVAL, "MPPI_F_IMPORTANCE_SAMPLING needs sigma_t[%lld] > 0", (long long)i);
+    }
   if (c->dynamics == MPPI_DYN_BICYCLE_MLP) {
     if (!p->mlp) return fail(MPPI_EINVAL, "MLP dynamics need the weight blob");
     if (p->mlp_hidden != 16 && p->mlp_hidden != 32 && p->mlp_hidden != 64)
@@ -263,6 +285,10 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
   const size_t cells =
       c->cost == MPPI_COST_PATH_COSTMAP ? (size_t)p->map_w * (size_t)p->map_h : 1;
   L.costmap = take(sizeof(float) * cells);
+  if (p->sigma_t) {
+    L.sigma_t = take(sizeof(float) * TM);
+    L.is_coef_t = take(sizeof(float) * TM);
+  }
   const int H = mlp_hidden_of(c, p);
   L.mlp = take(sizeof(float) * kWave * (H ? pack_rows(H, false) : 1));
   L.mlp_bwd = take(sizeof(float) * kWave * (H ? pack_rows(H, true) : 1));
@@ -529,6 +555,22 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
   if (e == hipSuccess) e = up(I->L.stage, stage.data(), sizeof(float4) * stage.size());
   if (e == hipSuccess && cfg->cost == MPPI_COST_PATH_COSTMAP)
     e = up(I->L.costmap, p->costmap, sizeof(float) * (size_t)p->map_w * p->map_h);
+  if (e == hipSuccess && p->sigma_t) {
+    keep->emplace_back();
+    std::vector<float4>& tab = keep->back();  // sigma_t, then lambda / sigma_t^2
+    const int TM = I->TM;
+    tab.assign((2 * static_cast<size_t>(TM) + 3) / 4, float4{0, 0, 0, 0});
+    float* f = reinterpret_cast<float*>(tab.data());
+    for (int i = 0; i < TM; ++i) {
+      const double sg = p->sigma_t[i];
+      f[i] = p->sigma_t[i];
+      f[TM + i] = (cfg->flags & MPPI_F_IMPORTANCE_SAMPLING)
+                      ? static_cast<float>(static_cast<double>(cfg->lambda) / (sg * sg))
+                      : 0.0f;
+    }
+    e = up(I->L.sigma_t, f, sizeof(float) * TM);
+    if (e == hipSuccess) e = up(I->L.is_coef_t, f + TM, sizeof(float) * TM);
+  }
   I->hidden = mlp_hidden_of(cfg, p);
   I->grad = wants_grad(cfg);
   I->tape_cap = I->grad ? tape_len_of(p) : 0;
@@ -570,6 +612,11 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
   d.mlp = I->hidden ? I->at<float>(I->L.mlp) : nullptr;
   d.mlp_bwd = I->hidden ? I->at<float>(I->L.mlp_bwd) : nullptr;
   d.cosines = p->cost_cosines;
+  d.n_plain = n_plain_of(cfg);
+  d.mean_sample = (cfg->flags & MPPI_F_MEAN_SAMPLE) ? 1 : 0;
+  d.sigma_t = p->sigma_t ? I->at<float>(I->L.sigma_t) : nullptr;
+  d.is_coef_t =
+      p->sigma_t && (cfg->flags & MPPI_F_IMPORTANCE_SAMPLING) ? I->at<float>(I->L.is_coef_t) : nullptr;
   d.importance = (cfg->flags & MPPI_F_IMPORTANCE_SAMPLING) ? 1 : 0;
   for (int j = 0; j < m && d.importance; ++j) {
     const double sg = cfg->sigma[j];
@@ -746,7 +793,8 @@ hipError_t phase_sample(mppi_ctx* c) {
   if (c->batch) return launch_batch_noise(c->plan, c->stream);
   const Instance& I = c->one();
   return launch_noise(I.cfg.seed, &I.st->iteration, 0u, I.cfg.instance, I.K, I.T, I.m,
-                      I.cfg.sigma, I.eps(), I.L.ldk, c->stream, c->tune.noise_calls);
+                      I.cfg.sigma, I.eps(), I.L.ldk, c->stream, c->tune.noise_calls, I.dp.sigma_t,
+                      I.dp.mean_sample != 0);
 }
 
 hipError_t phase_rollout(mppi_ctx* c) {
@@ -788,8 +836,7 @@ hipError_t phase_update(mppi_ctx* c) {
     if (e != hipSuccess) return e;
   }
   return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, step_size(I.cfg),
-                               I.e(), I.u, I.st,
-                               c->stream);
+                               I.e(), I.u, I.st, c->stream, I.dp.n_plain);
 }
 
 }  // namespace
@@ -1308,7 +1355,8 @@ mppi_status mppi_backward_iters(mppi_ctx* c, const float* d_dL_dU, float* d_grad
     const float* u_i = I.at<float>(I.L.tape_u) + static_cast<int64_t>(i) * I.TM;
     hipError_t e = launch_noise(I.cfg.seed, I.at<uint32_t>(I.L.tape_word) + i, 0u,
                                 I.cfg.instance, I.K, I.T, I.m, I.cfg.sigma, I.eps(), I.L.ldk,
-                                c->stream, c->tune.noise_calls);
+                                c->stream, c->tune.noise_calls, I.dp.sigma_t,
+                                I.dp.mean_sample != 0);
     if (e == hipSuccess)
       e = launch_rollout_tiles(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp, I.x0,
                                u_i, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,

@@ -65,14 +65,18 @@ struct NoiseAhead {
   }
 };
 
-// The importance-sampling term of one step (section "MPPI-Generic's MPPI
+// The importance-sampling term of step t (section "MPPI-Generic's MPPI
 // Implementation", Eq. information_theoretic_weighting, beta = 1):
-// lambda (v - u/2)' Sigma^-1 u with p.is_coef[j] = lambda / sigma_j^2.
+// lambda (v - u/2)' Sigma_t^-1 u with the coefficients lambda / sigma^2 of the
+// step (per step with a sigma table).  Only for samples drawn around u: the
+// term of a zero-mean sample is zero.
 template <int M>
-__device__ __forceinline__ float is_term(const DevParams& p, const float* v, const float* u) {
+__device__ __forceinline__ float is_term(const DevParams& p, int t, const float* v,
+                                         const float* u) {
+  const float* cf = p.is_coef_t ? p.is_coef_t + t * M : p.is_coef;
   float s = 0.0f;
 #pragma unroll
-  for (int j = 0; j < M; ++j) s += (p.is_coef[j] * u[j]) * (v[j] - 0.5f * u[j]);
+  for (int j = 0; j < M; ++j) s += (cf[j] * u[j]) * (v[j] - 0.5f * u[j]);
   return s;
 }
 
@@ -90,13 +94,14 @@ struct RolloutResult {
   int crashes;
 };
 
-// One lane per sample: e points at eps[0][0][k] of this lane's sample.
+// One lane per sample: e points at eps[0][0][k] of this lane's sample;
+// plain: the sample is drawn around u (else around zero, v = eps).
 template <class Model, int INTEG, class Cost, bool COUNT>
 __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
                                                       const float* __restrict__ x0,
                                                       const float* lds_u,
                                                       const float* __restrict__ e, int64_t ldk,
-                                                      int T, const float4* lds) {
+                                                      int T, const float4* lds, bool plain) {
   constexpr int N = Model::N, M = Model::M;
   float x[N], comp[N];
 #pragma unroll
@@ -111,11 +116,11 @@ __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
     float v[M];
     ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + v[j];
+    for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + v[j];
     step<Model, INTEG>(x, v, comp, p);
     bool hit;
     float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
-    if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
+    if (p.importance && plain) l += is_term<M>(p, t, v, lds_u + t * M);
     if (p.cosines) l += inflation(p);
     if constexpr (COUNT) ncrash += hit ? 1 : 0;
     const float y = l - sum_c;

@@ -22,7 +22,8 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_kernel(
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * Model::M, lds);
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;  // no barrier follows
-  const RolloutResult r = rollout_lane<Model, INTEG, Cost, COUNT>(p, x0, lds_u, eps + k, ldk, T, lds);
+  const RolloutResult r =
+      rollout_lane<Model, INTEG, Cost, COUNT>(p, x0, lds_u, eps + k, ldk, T, lds, k < p.n_plain);
   S[k] = r.cost;
   if constexpr (COUNT) crashes[k] = r.crashes;
 }
@@ -74,6 +75,7 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
   const int slot = gl & (L - 1);  // latches the steps t = slot (mod L)
   const int k = gl / L;
   if (k >= K) return;  // whole groups leave together; no barrier follows
+  const float mean = k < p.n_plain ? 1.0f : 0.0f;  // drawn around u, or around zero
   // stage coefficient c_j dt (0, dt/2, dt/2, dt) and RK4 weight (1, 2, 2, 1)
   const float cdt = j == 0 ? 0.0f : (j == 3 ? p.dt : p.half_dt);
   const float wj = (j == 1 || j == 2) ? 2.0f : 1.0f;
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
       if (t < T) {
         float v[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) v[c] = un[c] + q[d][c];
+        for (int c = 0; c < M; ++c) v[c] = mean * un[c] + q[d][c];
         if (t + 4 < T) {
           const float* en = e + static_cast<int64_t>(t + 4) * M * ldk;
 #pragma unroll
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
           if (lt >= 0) {
             bool hit;
             float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
-            if (p.importance) l += is_term<M>(p, lv, lds_u + lt * M);
+            if (p.importance && mean != 0.0f) l += is_term<M>(p, lt, lv, lds_u + lt * M);
             if (p.cosines) l += inflation(p);
             if constexpr (COUNT) ncrash += hit ? 1 : 0;
             const float y = l - sum_c;

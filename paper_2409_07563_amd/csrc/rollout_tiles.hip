@@ -30,6 +30,7 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
   const int lane = threadIdx.x, n = lane % kTile, g = lane / kTile;
   const int k = blockIdx.x * kTile + n;
   const bool live = k < K;
+  const bool plain = k < p.n_plain;  // drawn around u (else around zero)
   // lanes past K recompute sample K-1 (they take part in the MFMAs) and store nothing
   NoiseAhead<M> ahead;
   ahead.init(eps + (live ? k : K - 1), ldk, T);
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
     float v[M];
     ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + v[j];
+    for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + v[j];
     if (ck && t == next_ckpt) {
       if (g == 0 && live) {
 #pragma unroll
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
     }
     bool hit;
     float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
-    if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
+    if (p.importance && plain) l += is_term<M>(p, t, v, lds_u + t * M);
     if (p.cosines) l += inflation(p);
     const float y = l - sum_c;
     const float s = sum + y;
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
   const int n = lane % kTile, g = lane / kTile;
   const int k = blockIdx.x * kTile + n;
   const bool live = k < K;
+  const bool plain = k < p.n_plain;  // drawn around u (else around zero)
   NoiseAhead<M> ahead;
   ahead.init(eps + (live ? k : K - 1), ldk, T);
   // this wave's operands (tiles q0 .. q0 + TW - 1)
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     float v[M];
     ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + v[j];
+    for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + v[j];
     if (ck && t == next_ckpt) {
       if (w == 0 && g == 0 && live) {
 #pragma unroll
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     step<Model, INTEG>(x, v, comp, p, res);
     bool hit;
     float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
-    if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
+    if (p.importance && plain) l += is_term<M>(p, t, v, lds_u + t * M);
     if (p.cosines) l += inflation(p);
     const float y = l - sum_c;
     const float s = sum + y;

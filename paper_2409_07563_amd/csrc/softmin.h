@@ -69,9 +69,11 @@ __device__ __forceinline__ void block_sum2(float& a, float& b, float2* lds) {
 // one per element; when K fits one chunk (K <= 32768) the costs stay in
 // registers between the min pass and the exponential pass.
 constexpr int kWeightsChunk = 32;
+// Samples k >= n_plain were drawn around zero: their weight mass
+// W_Z = sum_{k >= n_plain} w_k goes to st->wz for the update.
 __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K, float lambda,
                                              float inv_lambda, float* __restrict__ e,
-                                             DevState* __restrict__ st) {
+                                             DevState* __restrict__ st, int n_plain) {
   constexpr int NW = kWeightsBlock / kWave;
   constexpr int kSpan = kWeightsChunk * kWeightsBlock;  // costs per chunk
   __shared__ float lds[NW];
@@ -92,7 +94,7 @@ __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K,
   }
   const float rho = block_min<NW>(m, lds);
   const bool finite = rho < __builtin_inff();
-  float se = 0.0f, se2 = 0.0f;
+  float se = 0.0f, se2 = 0.0f, sz = 0.0f;
   for (int c0 = 0; c0 < K; c0 += kSpan) {
     if (K > kSpan) load_chunk(c0);  // one chunk: still in registers
 #pragma unroll
@@ -105,12 +107,16 @@ __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K,
         e[k] = ek;
         se += ek;
         se2 += ek * ek;
+        sz += k >= n_plain ? ek : 0.0f;
       }
     }
   }
   block_sum2<NW>(se, se2, lds2);
   const float eta = se, sum_e2 = se2;
+  float wz = 0.0f;
+  if (n_plain < K) wz = block_sum<NW>(sz, lds) / eta;  // uniform branch
   if (threadIdx.x == 0) {
+    st->wz = finite ? wz : 0.0f;
     st->stats[0] = rho;
     st->stats[1] = finite ? eta : 0.0f;
     st->stats[2] = finite ? rho - lambda * logf(eta / static_cast<float>(K)) : __builtin_inff();
@@ -121,7 +127,9 @@ __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K,
 }
 
 // Row r of the update, one workgroup of kGemvBlock threads:
-// u[r] += step * ((sum_k e_k eps[r][k]) / eta), step the step size gamma.  The row starts 16-byte aligned (ldk is
+// u[r] += step * ((sum_k e_k eps[r][k]) / eta - u[r] W_Z), step the step size
+// gamma and W_Z the weight of the samples drawn around zero (whose v - u is
+// eps - u).  The row starts 16-byte aligned (ldk is
 // a multiple of 64); the last K mod 4 entries go through a scalar tail so the
 // unwritten padding of a row is never read.  Eight 16-byte loads of the row
 // (and eight of e) are in flight per lane, so a row of up to 8192 samples is
@@ -167,7 +175,12 @@ __device__ __forceinline__ void gemv_row(const float* __restrict__ eps, int64_t 
 #pragma unroll
     for (int i = 1; i < NW; ++i) tot += part[i];
     const float eta = st->stats[1];
-    if (eta > 0.0f) u[r] = u[r] + step * (tot / eta);
+    const float wz = st->wz;
+    if (eta > 0.0f) {
+      float q = tot / eta;
+      if (wz != 0.0f) q -= u[r] * wz;
+      u[r] = u[r] + step * q;
+    }
   }
 }
 

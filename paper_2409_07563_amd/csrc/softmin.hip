@@ -8,8 +8,8 @@ int gemv_rows_per_block() { return 1; }
 
 __global__ __launch_bounds__(kWeightsBlock) void weights_kernel_one(
     const float* __restrict__ S, int K, float lambda, float inv_lambda, float* __restrict__ e,
-    DevState* __restrict__ st) {
-  weights_body(S, K, lambda, inv_lambda, e, st);
+    DevState* __restrict__ st, int n_plain) {
+  weights_body(S, K, lambda, inv_lambda, e, st, n_plain);
 }
 
 __global__ __launch_bounds__(kGemvBlock) void gemv_kernel_one(
@@ -20,10 +20,10 @@ __global__ __launch_bounds__(kGemvBlock) void gemv_kernel_one(
 
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
                                  int TM, float lambda, float step, float* d_e, float* d_u,
-                                 DevState* d_state, hipStream_t stream) {
+                                 DevState* d_state, hipStream_t stream, int n_plain) {
   const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
   hipLaunchKernelGGL(weights_kernel_one, dim3(1), dim3(kWeightsBlock), 0, stream, d_S, K, lambda,
-                     inv_lambda, d_e, d_state);
+                     inv_lambda, d_e, d_state, n_plain);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(gemv_kernel_one, dim3(TM), dim3(kGemvBlock), 0, stream, d_eps, ldk, K, d_e,
@@ -38,7 +38,7 @@ hipError_t launch_weights_only(const float* d_S, int K, float lambda, float* d_e
                                DevState* d_scratch_state, hipStream_t stream) {
   const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
   hipLaunchKernelGGL(weights_kernel_one, dim3(1), dim3(kWeightsBlock), 0, stream, d_S, K, lambda,
-                     inv_lambda, d_e, d_scratch_state);
+                     inv_lambda, d_e, d_scratch_state, K);
   return hipGetLastError();
 }
 

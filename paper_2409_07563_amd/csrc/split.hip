@@ -31,6 +31,7 @@ __global__ __launch_bounds__(kSplitMaxBlock) void split_dynamics_kernel(
   const float* lds_u = stage_rollout_lds<CostQuadratic>(p, u, T * M, lds);  // u only
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;  // no barrier follows
+  const bool plain = k < p.n_plain;  // drawn around u (else around zero)
   float x[N], comp[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(kSplitMaxBlock) void split_dynamics_kernel(
     float v[M];
     ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + v[j];
+    for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + v[j];
     step<Model, INTEG>(x, v, comp, p);
 #pragma unroll
     for (int i = 0; i < N; ++i) y[i * ldk] = x[i];
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(kSplitMaxBlock) void split_bicycle_quad_kernel(
   const int j = gl & 3;
   const int k = gl >> 2;
   if (k >= K) return;  // whole quads leave together; no barrier follows
+  const float mean = k < p.n_plain ? 1.0f : 0.0f;  // drawn around u, or around zero
   const float cdt = j == 0 ? 0.0f : (j == 3 ? p.dt : p.half_dt);
   const float wj = (j == 1 || j == 2) ? 2.0f : 1.0f;
   float x[N], comp[N];
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(kSplitMaxBlock) void split_bicycle_quad_kernel(
     float v[M];
     ahead.pop(t, v);
 #pragma unroll
-    for (int c = 0; c < M; ++c) v[c] = lds_u[t * M + c] + v[c];
+    for (int c = 0; c < M; ++c) v[c] = mean * lds_u[t * M + c] + v[c];
     bicycle_quad_step<FAST>(x, comp, v, j, cdt, wj, p);
     const float own = j == 0 ? x[0] : (j == 1 ? x[1] : (j == 2 ? x[2] : x[3]));
     y[j * ldk] = own;
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(kWave * kSplitMaxWaves) void split_cost_kernel(
   const int G = C * W, g = c * W + w;
   const int k = blockIdx.x * kWave + lane;
   const bool live = k < K;
+  const bool plain = k < p.n_plain;  // drawn around u (else around zero)
   typename Cost::State cs;
   {
     const float xz[N] = {};
@@ -144,11 +147,11 @@ __global__ __launch_bounds__(kWave * kSplitMaxWaves) void split_cost_kernel(
         comp[1] = yn[N + 1];
       }
 #pragma unroll
-      for (int j = 0; j < M; ++j) v[j] = lds_u[t * M + j] + en[j];
+      for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + en[j];
       if (t + G < T) fetch(t + G);
       bool hit;
       float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
-      if (p.importance) l += is_term<M>(p, v, lds_u + t * M);
+      if (p.importance && plain) l += is_term<M>(p, t, v, lds_u + t * M);
       if (p.cosines) l += inflation(p);
       if constexpr (COUNT) nh += hit ? 1 : 0;
       const float yk = l - sum_c;

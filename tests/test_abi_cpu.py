@@ -39,7 +39,7 @@ def test_every_declared_function_is_exported(abi):
 def test_struct_sizes_match_the_header(abi):
     # sizes of the C structs as laid out by the host compiler
     assert C.sizeof(abi.Config) == 96
-    assert C.sizeof(abi.Params) == 280
+    assert C.sizeof(abi.Params) == 288
     assert C.sizeof(abi.Tuning) == 24
 
 

@@ -1,0 +1,181 @@
+"""GPU parity of the sampling options (section "Sampling Distributions"): a
+noise deviation per step, the noiseless mean sample, and a fraction of the
+samples drawn around zero, through the C ABI against the oracle, in every
+rollout kernel and in the gradient.  Noise stays bit-exact; costs and controls
+follow tests/parity.py (for the zero-mean samples the update's sensitivity
+uses v_k - u = eps_k - u).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", file=sys.stderr, flush=True)
+    yield
+
+
+@pytest.fixture(scope="module")
+def mppi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2409_07563_amd as M
+    M.lib()
+    return M
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _options(wl, seed, zero_frac=0.2, mean_sample=1, is_beta=1, gamma=0.7):
+    rng = np.random.default_rng(seed)
+    sig_t = (np.asarray(wl.sigma, np.float64)[None, :]
+             * rng.uniform(0.5, 1.5, (wl.T, wl.m))).astype(np.float32)
+    u0 = rng.normal(0.0, 0.3, (wl.T, wl.m)).astype(np.float32)
+    return wl.replace(sigma_t=sig_t, u0=u0, zero_frac=zero_frac, mean_sample=mean_sample,
+                      is_beta=is_beta, gamma=gamma)
+
+
+def _n_plain(wl):
+    nz = int(np.floor(float(np.float32(wl.zero_frac)) * wl.K))
+    nz = min(nz, wl.K - (1 if wl.mean_sample else 0))
+    return wl.K - max(nz, 0)
+
+
+def _controls_tol(wl, S_or, w_or, eps, u, cond=None):
+    dev = eps.astype(np.float64).copy()           # v_k - u
+    dev[:, :, _n_plain(wl):] -= u[:, :, None]
+    return parity.controls_tol(wl, S_or, w_or, dev.astype(np.float64), cond=cond)
+
+
+CASES = {
+    "c1": (lambda: W.c1(K=1000, T=40), {}),
+    "c3": (lambda: W.c3(K=700, T=40), {}),
+    "c2_lanes1": (lambda: W.c2("circles", K=1500, T=80, iters=1), dict(lanes_per_sample=1)),
+    "c2_lanes4": (lambda: W.c2("circles", K=1500, T=80, iters=1), dict(lanes_per_sample=4)),
+    "c2_lanes16": (lambda: W.c2("circles", K=1500, T=77, iters=1), dict(lanes_per_sample=16)),
+    "c2_split": (lambda: W.c2("circles", K=1500, T=80, iters=1),
+                 dict(rollout_form=1, lanes_per_sample=4, cost_waves=32)),
+    "c2_costmap_split1": (lambda: W.c2("costmap", K=900, T=60, iters=1),
+                          dict(rollout_form=1, lanes_per_sample=1, cost_waves=8)),
+    "c5_mlp": (lambda: W.c5(K=600, T=40, hidden=64), dict(rollout_block=256)),
+    "c5_mlp16": (lambda: W.c5(K=333, T=30, hidden=16), dict(rollout_block=64)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sampling_options_parity(mppi, oracle_lib, name):
+    make, shape = CASES[name]
+    wl = _options(make(), sum(map(ord, name)))
+    ctl = mppi.Controller(wl)
+    if shape:
+        ctl.set_tuning(**shape)
+    ctl.sample()
+    ctl.rollout()
+    eps = _np(ctl.noise())
+    S = _np(ctl.costs()).astype(np.float64)
+    ctl.update()
+    U = _np(ctl.controls())
+    st = ctl.stats()
+    ctl.close()
+    e_or = oracle_lib.workload_noise(wl)
+    assert np.array_equal(eps.view(np.uint32), e_or.view(np.uint32))
+    assert np.all(eps[:, :, 0] == 0)
+    S_or, margin, _, slope = oracle_lib.rollout_costs(wl, eps=eps, slope=True)
+    cond = oracle_lib.cost_condition(wl, eps) if wl.model == "bicycle_mlp" else None
+    parity.assert_costs_close(S, S_or, margin, f"{name} costs", cond=cond,
+                              slope=slope if wl.cost == "path_costmap" else None)
+    w_or, U_or, _, rc = oracle_lib.softmin_update(wl, S_or, eps)
+    assert rc == 0 and st["status"] == 0
+    parity.assert_controls_close(U, U_or,
+                                 _controls_tol(wl, S_or, w_or, eps, wl.u0.astype(np.float64), cond),
+                                 f"{name} controls")
+
+
+def test_sampling_options_batch(mppi, oracle_lib):
+    insts = []
+    for i, wl in enumerate(W.c4(n_instances=4)):
+        insts.append(_options(wl.replace(K=min(wl.K, 500) - 7 * i), 50 + i,
+                              zero_frac=(0.0, 0.1, 0.5, 1.0)[i]))
+    ctl = mppi.Controller(insts)
+    ctl.sample()
+    ctl.rollout()
+    S = ctl.split(_np(ctl.costs()), 2)
+    eps = ctl.split(_np(ctl.noise()), 3)
+    ctl.update()
+    U = ctl.split(_np(ctl.controls()), 1)
+    ctl.close()
+    for i, wl in enumerate(insts):
+        e = eps[i].reshape(wl.T, wl.m, wl.K)
+        assert np.array_equal(e.view(np.uint32), oracle_lib.workload_noise(wl).view(np.uint32))
+        S_or, margin, _ = oracle_lib.rollout_costs(wl, eps=e)
+        parity.assert_costs_close(S[i], S_or, margin, f"instance {i}")
+        w_or, U_or, _, _ = oracle_lib.softmin_update(wl, S_or, e)
+        parity.assert_controls_close(U[i].reshape(wl.T, wl.m), U_or,
+                                     _controls_tol(wl, S_or, w_or, e, wl.u0.astype(np.float64)),
+                                     f"instance {i}")
+
+
+def test_warm_started_iterations_with_sampling_options(mppi, oracle_lib):
+    wl = _options(W.c2("circles", K=2000, T=100, iters=3), 77)
+    ctl = mppi.Controller(wl)
+    u = wl.u0.astype(np.float64)
+    for i in range(wl.iters):
+        o = oracle_lib.mppi(wl, iters=1, iter0=i, u=u)
+        ctl.set_controls(u.astype(np.float32))
+        ctl.set_iteration(i)
+        ctl.iterate(1)
+        U = _np(ctl.controls())
+        parity.assert_controls_close(U, o["U"], _controls_tol(wl, o["S"], o["w"], o["eps"], u),
+                                     f"iteration {i}")
+        u = o["U"]
+    ctl.close()
+
+
+@pytest.mark.parametrize("iters", [1, 2])
+def test_gradient_with_sampling_options(mppi, oracle_lib, iters):
+    wl = _options(W.c5(K=700, T=30, hidden=64).replace(lam=50.0), 90 + iters, zero_frac=0.0)
+    uref = W.c5_uref(T=30)
+    ctl = mppi.Controller(wl, requires_grad=True)
+    rec = []
+    for _ in range(iters):
+        u = _np(ctl.controls()).astype(np.float64)
+        ctl.sample()
+        ctl.rollout()
+        rec.append((u, _np(ctl.noise()), _np(ctl.costs()).astype(np.float64)))
+        ctl.update()
+    U = _np(ctl.controls()).astype(np.float64)
+    G = 2.0 * (U - uref)
+    g, du0 = ctl.backward_iters(G.astype(np.float32))
+    g, du0 = _np(g).astype(np.float64), _np(du0).astype(np.float64)
+    ctl.close()
+    grad = np.zeros_like(g)
+    gabs = np.zeros_like(g)
+    Gc, dabs = G.copy(), np.zeros_like(G)
+    for u, eps, S in reversed(rec):
+        r = oracle_lib.backward(wl, Gc, u=u, eps=eps, S=S)
+        grad += r["grad"]
+        gabs += r["grad_abs"]
+        dabs += r["du_abs"]
+        Gc = Gc + r["du"]
+    tol = 1e-4 * gabs + 1e-7 * gabs.max()
+    assert np.all(np.abs(g - grad) <= tol), np.max(np.abs(g - grad) / tol)
+    dtol = 1e-4 * (np.abs(G) + dabs) + 1e-7 * (np.abs(G) + dabs).max()
+    assert np.all(np.abs(du0 - Gc) <= dtol), np.max(np.abs(du0 - Gc) / dtol)
+
+
+def test_gradient_mode_refuses_zero_mean_samples(mppi):
+    from paper_2409_07563_amd import _abi
+    with pytest.raises(_abi.MPPIError):
+        mppi.Controller(W.c5(K=64, T=10, hidden=16).replace(zero_frac=0.5), requires_grad=True)
