@@ -171,6 +171,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing the candidates")
+    ap.add_argument("--tuning", default=None,
+                    help="launch shapes to apply instead of autotuning, as JSON "
+                         "(e.g. the 'tuning' object of an earlier bench line)")
     ap.add_argument("--cost-cosines", type=int, default=0,
                     help="nested cosines ahead of every running cost (the cost-complexity "
                          "load of the paper's Results section)")
@@ -207,7 +210,11 @@ def main():
     I = wl.iters
     ctl = M.Controller(wl, device=dev)
     stream = ctl.stream
-    tuned = ctl.autotune(reps=30) if not args.no_autotune else None
+    tuned = None
+    if args.tuning:
+        ctl.set_tuning(**json.loads(args.tuning))
+    elif not args.no_autotune:
+        tuned = ctl.autotune(reps=30)
 
     for _ in range(args.warmup):
         ctl.iterate(I)

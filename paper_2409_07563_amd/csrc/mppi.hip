@@ -286,7 +286,7 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
       c->cost == MPPI_COST_PATH_COSTMAP ? (size_t)p->map_w * (size_t)p->map_h : 1;
   L.costmap = take(sizeof(float) * cells);
   if (p->sigma_t) {
-    L.sigma_t = take(sizeof(float) * TM);
+    L.sigma_t = take(sizeof(float) * ((TM + 3) / 4 * 4));  // read four at a time
     L.is_coef_t = take(sizeof(float) * TM);
   }
   const int H = mlp_hidden_of(c, p);
@@ -557,19 +557,20 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
     e = up(I->L.costmap, p->costmap, sizeof(float) * (size_t)p->map_w * p->map_h);
   if (e == hipSuccess && p->sigma_t) {
     keep->emplace_back();
-    std::vector<float4>& tab = keep->back();  // sigma_t, then lambda / sigma_t^2
-    const int TM = I->TM;
-    tab.assign((2 * static_cast<size_t>(TM) + 3) / 4, float4{0, 0, 0, 0});
+    // sigma_t padded with zeros to a multiple of four, then lambda / sigma_t^2
+    std::vector<float4>& tab = keep->back();
+    const int TM = I->TM, TM4 = (TM + 3) / 4 * 4;
+    tab.assign((static_cast<size_t>(TM4) + TM + 3) / 4, float4{0, 0, 0, 0});
     float* f = reinterpret_cast<float*>(tab.data());
     for (int i = 0; i < TM; ++i) {
       const double sg = p->sigma_t[i];
       f[i] = p->sigma_t[i];
-      f[TM + i] = (cfg->flags & MPPI_F_IMPORTANCE_SAMPLING)
-                      ? static_cast<float>(static_cast<double>(cfg->lambda) / (sg * sg))
-                      : 0.0f;
+      f[TM4 + i] = (cfg->flags & MPPI_F_IMPORTANCE_SAMPLING)
+                       ? static_cast<float>(static_cast<double>(cfg->lambda) / (sg * sg))
+                       : 0.0f;
     }
-    e = up(I->L.sigma_t, f, sizeof(float) * TM);
-    if (e == hipSuccess) e = up(I->L.is_coef_t, f + TM, sizeof(float) * TM);
+    e = up(I->L.sigma_t, f, sizeof(float) * TM4);
+    if (e == hipSuccess) e = up(I->L.is_coef_t, f + TM4, sizeof(float) * TM);
   }
   I->hidden = mlp_hidden_of(cfg, p);
   I->grad = wants_grad(cfg);

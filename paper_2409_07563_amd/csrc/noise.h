@@ -123,15 +123,24 @@ __device__ __forceinline__ void emit_call(uint32_t key0, uint32_t key1, uint32_t
   box_muller(w.x0, w.x1, z[0], z[1]);
   box_muller(w.x2, w.x3, z[2], z[3]);
   const int n0 = 4 * c;
-  int j = n0 % m;
+  // the four deviations of this call (the per-step table is padded to a
+  // multiple of four entries, so one aligned 16-byte read covers them)
+  float sg[4];
+  if (sigma_t) {
+    const float4 s4 = *reinterpret_cast<const float4*>(sigma_t + n0);
+    sg[0] = s4.x; sg[1] = s4.y; sg[2] = s4.z; sg[3] = s4.w;
+  } else {
+    int j = n0 % m;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      sg[s] = sigma[j];
+      j = (j + 1 == m) ? 0 : j + 1;
+    }
+  }
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int n = n0 + s;
-    if (n < TM) {
-      const float sg = sigma_t ? sigma_t[n] : sigma[j];
-      eps[static_cast<int64_t>(n) * ldk + k] = zero ? 0.0f : sg * z[s];
-    }
-    j = (j + 1 == m) ? 0 : j + 1;
+    if (n < TM) eps[static_cast<int64_t>(n) * ldk + k] = zero ? 0.0f : sg[s] * z[s];
   }
 }
 

@@ -89,6 +89,43 @@ __device__ __forceinline__ float inflation(const DevParams& p) {
   return 0.0f * z;
 }
 
+// Runs body(t, n, d) for t = 0 .. T-1, n the noise of step t (M floats) and
+// d = t mod D.  The noise of step t + D is requested at step t into the
+// register slot step t has just used: the slots are fixed (the step loop is
+// unrolled by D) and rows past the horizon are clamped to row T - 1, so the
+// unrolled body has no branch of its own and the wait for a step's noise
+// comes D steps after its request (a rotating queue, by contrast, makes the
+// compiler wait for the newest request at every step).  e points at
+// eps[0][0][k].
+template <int M, int D, class Body>
+__device__ __forceinline__ void noise_steps(const float* __restrict__ e, int64_t ldk, int T,
+                                            Body&& body) {
+  float q[D][M];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int r = d < T ? d : T - 1;
+#pragma unroll
+    for (int c = 0; c < M; ++c) q[d][c] = e[static_cast<int64_t>(r * M + c) * ldk];
+  }
+  int t0 = 0;
+  for (; t0 + D <= T; t0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      float n[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) n[c] = q[d][c];
+      const int t = t0 + d;
+      const int r = t + D < T ? t + D : T - 1;
+#pragma unroll
+      for (int c = 0; c < M; ++c) q[d][c] = e[static_cast<int64_t>(r * M + c) * ldk];
+      body(t, n, d);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (t0 + d < T) body(t0 + d, q[d], d);
+}
+
 struct RolloutResult {
   float cost;
   int crashes;
@@ -106,17 +143,17 @@ __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
   float x[N], comp[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
-  NoiseAhead<M> ahead;
-  ahead.init(e, ldk, T);
   typename Cost::State cs;
   Cost::init(cs, x, p, lds);
   float sum = 0.0f, sum_c = 0.0f;
   int ncrash = 0;
-  for (int t = 0; t < T; ++t) {
+  // v = mean u + eps: an unconditional load of u and one FMA (exactly u + eps
+  // for mean = 1), so no branch guards the load
+  const float mean = plain ? 1.0f : 0.0f;
+  auto body = [&](int t, const float* n, int) {
     float v[M];
-    ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + v[j];
+    for (int j = 0; j < M; ++j) v[j] = mean * lds_u[t * M + j] + n[j];
     step<Model, INTEG>(x, v, comp, p);
     bool hit;
     float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
@@ -127,6 +164,19 @@ __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
     const float s = sum + y;
     sum_c = (s - sum) - y;
     sum = s;
+  };
+  if constexpr (M <= 2) {
+    noise_steps<M, 8>(e, ldk, T, body);  // noise requested 8 steps ahead
+  } else {
+    // the four-control quadrotor: its long step covers the latency of a
+    // request made one step ahead, and a rolled loop keeps its large body small
+    NoiseAhead<M> ahead;
+    ahead.init(e, ldk, T);
+    for (int t = 0; t < T; ++t) {
+      float n[M];
+      ahead.pop(t, n);
+      body(t, n, 0);
+    }
   }
   sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
   return RolloutResult{__builtin_isfinite(sum) ? sum : __builtin_inff(), ncrash};

@@ -40,9 +40,9 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_kernel(
 // as many waves.  Each lane keeps a compensated partial sum, summed over the
 // L lanes in a fixed butterfly order at the end.
 //
-// The step loop is unrolled by four: the noise of step t + 4 is requested
-// into the register slot that step t has just used, and u of step t + 1 is
-// read from LDS during step t, so neither load stalls the step that needs it.
+// The step loop runs through noise_steps (the noise of step t + 8 requested
+// into the register slot step t has just used), and the latch is a select, so
+// the steps between two cost evaluations are straight-line code.
 // ---------------------------------------------------------------------------
 // sum over the L lanes of a sample (every lane gets the same value)
 template <int L>
@@ -82,65 +82,48 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
   float x[N], comp[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
-  const float* e = eps + k;
-  float q[4][M];  // noise of the next four steps, slot t mod 4
-#pragma unroll
-  for (int d = 0; d < 4; ++d)
-#pragma unroll
-    for (int c = 0; c < M; ++c) q[d][c] = d < T ? e[static_cast<int64_t>(d * M + c) * ldk] : 0.0f;
-  float un[M];  // u of the coming step
-#pragma unroll
-  for (int c = 0; c < M; ++c) un[c] = lds_u[c];
   // the step this lane evaluates the running cost of
-  float lx[N], lc[N], lv[M];
+  float lx[N] = {}, lc[N] = {}, lv[M] = {};
   int lt = -1;
   typename Cost::State cs;
   Cost::init(cs, x, p, lds);
   float sum = 0.0f, sum_c = 0.0f;
   int ncrash = 0;
-  for (int t0 = 0; t0 < T; t0 += 4) {
+  auto evaluate = [&]() {
+    bool hit;
+    float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
+    if (p.importance && mean != 0.0f) l += is_term<M>(p, lt, lv, lds_u + lt * M);
+    if (p.cosines) l += inflation(p);
+    if constexpr (COUNT) ncrash += hit ? 1 : 0;
+    const float y = l - sum_c;
+    const float s = sum + y;
+    sum_c = (s - sum) - y;
+    sum = s;
+  };
+  noise_steps<M, 8>(eps + k, ldk, T, [&](int t, const float* nz, int d) {
+    float v[M];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const int t = t0 + d;
-      if (t < T) {
-        float v[M];
+    for (int c = 0; c < M; ++c) v[c] = mean * lds_u[t * M + c] + nz[c];
+    bicycle_quad_step<FAST>(x, comp, v, j, cdt, wj, p);
+    // latch this step for lane t mod L (selects, no branch) ...
+    const bool mine = (t & (L - 1)) == slot;
 #pragma unroll
-        for (int c = 0; c < M; ++c) v[c] = mean * un[c] + q[d][c];
-        if (t + 4 < T) {
-          const float* en = e + static_cast<int64_t>(t + 4) * M * ldk;
-#pragma unroll
-          for (int c = 0; c < M; ++c) q[d][c] = en[c * ldk];
-        }
-        if (t + 1 < T) {
-#pragma unroll
-          for (int c = 0; c < M; ++c) un[c] = lds_u[(t + 1) * M + c];
-        }
-        bicycle_quad_step<FAST>(x, comp, v, j, cdt, wj, p);
-        // latch this step for lane t mod L, evaluate a full group every L steps
-        if ((t & (L - 1)) == slot) {
-#pragma unroll
-          for (int i = 0; i < N; ++i) { lx[i] = x[i]; lc[i] = comp[i]; }
-#pragma unroll
-          for (int c = 0; c < M; ++c) lv[c] = v[c];
-          lt = t;
-        }
-        if ((t & (L - 1)) == L - 1 || t + 1 == T) {
-          if (lt >= 0) {
-            bool hit;
-            float l = Cost::template running<N, M>(lx, lc, lv, lt, p, lds, cs, hit);
-            if (p.importance && mean != 0.0f) l += is_term<M>(p, lt, lv, lds_u + lt * M);
-            if (p.cosines) l += inflation(p);
-            if constexpr (COUNT) ncrash += hit ? 1 : 0;
-            const float y = l - sum_c;
-            const float s = sum + y;
-            sum_c = (s - sum) - y;
-            sum = s;
-            lt = -1;
-          }
-        }
-      }
+    for (int i = 0; i < N; ++i) {
+      lx[i] = mine ? x[i] : lx[i];
+      lc[i] = mine ? comp[i] : lc[i];
     }
-  }
+#pragma unroll
+    for (int c = 0; c < M; ++c) lv[c] = mine ? v[c] : lv[c];
+    lt = mine ? t : lt;
+    // ... and evaluate a full group every L steps (the step blocks start at
+    // multiples of 8, so for L <= 8 the positions are fixed by d)
+    const bool full = L <= 8 ? (d & (L - 1)) == L - 1 : (t & (L - 1)) == L - 1;
+    if (full) {
+      evaluate();
+      lt = -1;
+    }
+  });
+  if (lt >= 0) evaluate();  // the last, incomplete group of steps
   // terminal cost once per sample (slot 0), then the group's partial sums
   const float phi = terminal_cost<Cost, N>(x, T, p, lds, cs);
   if (slot == 0) {

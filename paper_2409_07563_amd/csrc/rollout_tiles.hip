@@ -31,9 +31,11 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
   const int k = blockIdx.x * kTile + n;
   const bool live = k < K;
   const bool plain = k < p.n_plain;  // drawn around u (else around zero)
+  // v = mean u + eps: an unconditional load and one FMA (mean u + eps is
+  // exactly u + eps for mean = 1), no branch around the load of u
+  const float mean = plain ? 1.0f : 0.0f;
   // lanes past K recompute sample K-1 (they take part in the MFMAs) and store nothing
-  NoiseAhead<M> ahead;
-  ahead.init(eps + (live ? k : K - 1), ldk, T);
+  const float* e = eps + (live ? k : K - 1);
   mlp::Weights<MT ? MT : 1> W;
   if constexpr (MT > 0) W.load(p.mlp, lane);
   float x[N], comp[N];
@@ -44,11 +46,10 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
   float sum = 0.0f, sum_c = 0.0f;
   int next_ckpt = 0;
   float* ck = ckpt ? ckpt + k : nullptr;
-  for (int t = 0; t < T; ++t) {
+  noise_steps<M, 8>(e, ldk, T, [&](int t, const float* nz, int) {
     float v[M];
-    ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + v[j];
+    for (int j = 0; j < M; ++j) v[j] = mean * lds_u[t * M + j] + nz[j];
     if (ck && t == next_ckpt) {
       if (g == 0 && live) {
 #pragma unroll
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
     const float s = sum + y;
     sum_c = (s - sum) - y;
     sum = s;
-  }
+  });
   sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
   if (g == 0 && live) S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
 }
@@ -109,8 +110,10 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
   const int k = blockIdx.x * kTile + n;
   const bool live = k < K;
   const bool plain = k < p.n_plain;  // drawn around u (else around zero)
-  NoiseAhead<M> ahead;
-  ahead.init(eps + (live ? k : K - 1), ldk, T);
+  // v = mean u + eps: an unconditional load and one FMA (mean u + eps is
+  // exactly u + eps for mean = 1), no branch around the load of u
+  const float mean = plain ? 1.0f : 0.0f;
+  const float* e = eps + (live ? k : K - 1);
   // this wave's operands (tiles q0 .. q0 + TW - 1)
   const int q0 = w * TW;
   const float* pk = p.mlp + lane;
@@ -142,12 +145,11 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
   float sum = 0.0f, sum_c = 0.0f;
   int next_ckpt = 0;
   float* ck = ckpt ? ckpt + k : nullptr;
-  for (int t = 0; t < T; ++t) {
+  noise_steps<M, 8>(e, ldk, T, [&](int t, const float* nz, int) {
     const int par = t & 1;
     float v[M];
-    ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + v[j];
+    for (int j = 0; j < M; ++j) v[j] = mean * lds_u[t * M + j] + nz[j];
     if (ck && t == next_ckpt) {
       if (w == 0 && g == 0 && live) {
 #pragma unroll
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     const float s = sum + y;
     sum_c = (s - sum) - y;
     sum = s;
-  }
+  });
   sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
   if (w == 0 && g == 0 && live) S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
 }

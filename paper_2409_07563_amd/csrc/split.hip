@@ -31,32 +31,31 @@ __global__ __launch_bounds__(kSplitMaxBlock) void split_dynamics_kernel(
   const float* lds_u = stage_rollout_lds<CostQuadratic>(p, u, T * M, lds);  // u only
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;  // no barrier follows
-  const bool plain = k < p.n_plain;  // drawn around u (else around zero)
+  const float mean = k < p.n_plain ? 1.0f : 0.0f;  // drawn around u, or around zero
   float x[N], comp[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
-  NoiseAhead<M> ahead;
-  ahead.init(eps + k, ldk, T);
   float* y = traj + k;
-  for (int t = 0; t < T; ++t) {
+  noise_steps<M, 8>(eps + k, ldk, T, [&](int t, const float* n, int) {
     float v[M];
-    ahead.pop(t, v);
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + v[j];
+    for (int j = 0; j < M; ++j) v[j] = mean * lds_u[t * M + j] + n[j];
     step<Model, INTEG>(x, v, comp, p);
+    float* yt = y + static_cast<int64_t>(t) * NY * ldk;
 #pragma unroll
-    for (int i = 0; i < N; ++i) y[i * ldk] = x[i];
+    for (int i = 0; i < N; ++i) yt[i * ldk] = x[i];
     if constexpr (NY > N) {
-      y[N * ldk] = comp[0];
-      y[(N + 1) * ldk] = comp[1];
+      yt[N * ldk] = comp[0];
+      yt[(N + 1) * ldk] = comp[1];
     }
-    y += NY * ldk;
-  }
+  });
 }
 
 // ---- dynamics: the bicycle with RK4, four lanes per sample -------------------
 // The quad's lanes hold the same state after each step; lane j stores
-// component j (lane 0 also the steer, lanes 1 and 2 the compensation terms).
+// component j, and a second value: lane 0 the steer, lanes 1 and 2 the
+// compensation terms (costmap), the others their component again (the same
+// value to the same address), so both stores are unconditional.
 template <bool FAST, int NY>
 __global__ __launch_bounds__(kSplitMaxBlock) void split_bicycle_quad_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
@@ -74,24 +73,27 @@ __global__ __launch_bounds__(kSplitMaxBlock) void split_bicycle_quad_kernel(
   float x[N], comp[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
-  NoiseAhead<M> ahead;
-  ahead.init(eps + k, ldk, T);
+  const int row2 = j == 0 ? 4 : (NY > N && j == 1 ? 5 : (NY > N && j == 2 ? 6 : j));
   float* y = traj + k;
-  for (int t = 0; t < T; ++t) {
+  noise_steps<M, 8>(eps + k, ldk, T, [&](int t, const float* n, int) {
     float v[M];
-    ahead.pop(t, v);
 #pragma unroll
-    for (int c = 0; c < M; ++c) v[c] = mean * lds_u[t * M + c] + v[c];
+    for (int c = 0; c < M; ++c) v[c] = mean * lds_u[t * M + c] + n[c];
     bicycle_quad_step<FAST>(x, comp, v, j, cdt, wj, p);
-    const float own = j == 0 ? x[0] : (j == 1 ? x[1] : (j == 2 ? x[2] : x[3]));
-    y[j * ldk] = own;
-    if (j == 0) y[4 * ldk] = x[4];
+    // selects, not branches
+    float own = x[0];
+    own = j == 1 ? x[1] : own;
+    own = j == 2 ? x[2] : own;
+    own = j == 3 ? x[3] : own;
+    float second = j == 0 ? x[4] : own;
     if constexpr (NY > N) {
-      if (j == 1) y[5 * ldk] = comp[0];
-      if (j == 2) y[6 * ldk] = comp[1];
+      second = j == 1 ? comp[0] : second;
+      second = j == 2 ? comp[1] : second;
     }
-    y += NY * ldk;
-  }
+    float* yt = y + static_cast<int64_t>(t) * NY * ldk;
+    yt[j * ldk] = own;
+    yt[row2 * ldk] = second;
+  });
 }
 
 // ---- costs: parallel over time -----------------------------------------------
@@ -120,6 +122,7 @@ __global__ __launch_bounds__(kWave * kSplitMaxWaves) void split_cost_kernel(
   const int k = blockIdx.x * kWave + lane;
   const bool live = k < K;
   const bool plain = k < p.n_plain;  // drawn around u (else around zero)
+  const float mean = plain ? 1.0f : 0.0f;
   typename Cost::State cs;
   {
     const float xz[N] = {};
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kWave * kSplitMaxWaves) void split_cost_kernel(
         comp[1] = yn[N + 1];
       }
 #pragma unroll
-      for (int j = 0; j < M; ++j) v[j] = (plain ? lds_u[t * M + j] : 0.0f) + en[j];
+      for (int j = 0; j < M; ++j) v[j] = mean * lds_u[t * M + j] + en[j];
       if (t + G < T) fetch(t + G);
       bool hit;
       float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
