@@ -157,12 +157,25 @@ size_t rollout_lds_bytes(uint32_t dynamics, uint32_t cost, int stage_words4, int
 constexpr size_t kMaxRolloutLds = 160 * 1024;
 
 int gemv_rows_per_block();
+// The differentiation tape of gradient mode (device pointers; u null: none):
+// the weights step records u and the iteration word of the update in slot
+// *count (if below cap) and advances the count (cap + 1 marks an overflow).
+struct TapeRef {
+  const float* u = nullptr;
+  int TM = 0;
+  float* tape_u = nullptr;
+  uint32_t* tape_word = nullptr;
+  int32_t* count = nullptr;
+  int cap = 0;
+};
+
 // step: the step size gamma of u += gamma sum_k w_k (v_k - u) (1 for
 // Algorithm 1); samples k >= n_plain were drawn around zero (n_plain = K:
-// none)
+// none); tape: see TapeRef.
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
                                  int TM, float lambda, float step, float* d_e, float* d_u,
-                                 DevState* d_state, hipStream_t stream, int n_plain);
+                                 DevState* d_state, hipStream_t stream, int n_plain,
+                                 const TapeRef& tape = TapeRef{});
 hipError_t launch_set_iteration(DevState* d_state, uint32_t iteration, hipStream_t stream);
 hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState* d_state,
                           float* d_w, hipStream_t stream);
@@ -197,11 +210,7 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
                           bool accumulate = false, float* d_G_acc = nullptr);
 hipError_t launch_weights_only(const float* d_S, int K, float lambda, float* d_e,
                                DevState* d_scratch_state, hipStream_t stream);
-// The differentiation tape (gradient mode): record u and the iteration word
-// of an update in slot *count (if below cap) and advance the count; reset it.
-hipError_t launch_tape_record(const float* d_u, int TM, const DevState* d_state, float* d_tape_u,
-                              uint32_t* d_tape_word, int32_t* d_count, int cap,
-                              hipStream_t stream);
+// The differentiation tape: start over (count = 0).
 hipError_t launch_tape_reset(int32_t* d_count, hipStream_t stream);
 // u[t] <- u[min(t + steps, T - 1)] (fill 0) or 0 past the horizon (fill 1)
 hipError_t launch_shift(float* d_u, int T, int m, int steps, int fill, hipStream_t stream);

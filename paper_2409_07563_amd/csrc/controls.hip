@@ -1,10 +1,10 @@
 // Kernels on the nominal control sequence u between iterations: the MPC
 // warm-start shift (arXiv 2409.07563, section "Beginner": a new MPC
 // iteration samples around the previous sequence moved forward by the
-// optimisation stride) and the differentiation tape of gradient mode (the u
-// and the Philox iteration word of every update, so that the reverse pass can
-// rebuild each iteration).  All are kernels, so they stay in stream order and
-// may be captured in a graph.
+// optimisation stride) and the reset of gradient mode's differentiation tape
+// (the weights kernel records each update's u and Philox iteration word, so
+// that the reverse pass can rebuild every iteration).  Both are kernels, so
+// they stay in stream order and may be captured in a graph.
 #include "common.h"
 
 namespace mppi {
@@ -71,32 +71,7 @@ hipError_t launch_batch_shift(const BatchPlan& b, int steps, int fill, hipStream
   return hipGetLastError();
 }
 
-// Slot s = *count: tape_u[s] = u, tape_word[s] = the iteration word this
-// update's noise was drawn with (read before the weights step advances it);
-// then *count = s + 1, or cap + 1 when the tape is full (an overflow the
-// reverse pass refuses).
-__global__ __launch_bounds__(kControlsBlock) void tape_record_kernel(
-    const float* __restrict__ u, int TM, const DevState* __restrict__ st,
-    float* __restrict__ tape_u, uint32_t* __restrict__ tape_word, int32_t* count, int cap) {
-  const int s = *count;
-  if (s < cap) {
-    float* dst = tape_u + static_cast<int64_t>(s) * TM;
-    for (int i = threadIdx.x; i < TM; i += blockDim.x) dst[i] = u[i];
-    if (threadIdx.x == 0) tape_word[s] = st->iteration;
-  }
-  __syncthreads();  // every thread has read *count
-  if (threadIdx.x == 0) *count = s < cap ? s + 1 : cap + 1;
-}
-
 __global__ void tape_reset_kernel(int32_t* count) { *count = 0; }
-
-hipError_t launch_tape_record(const float* d_u, int TM, const DevState* d_state, float* d_tape_u,
-                              uint32_t* d_tape_word, int32_t* d_count, int cap,
-                              hipStream_t stream) {
-  hipLaunchKernelGGL(tape_record_kernel, dim3(1), dim3(kControlsBlock), 0, stream, d_u, TM,
-                     d_state, d_tape_u, d_tape_word, d_count, cap);
-  return hipGetLastError();
-}
 
 hipError_t launch_tape_reset(int32_t* d_count, hipStream_t stream) {
   hipLaunchKernelGGL(tape_reset_kernel, dim3(1), dim3(1), 0, stream, d_count);

@@ -830,14 +830,17 @@ hipError_t phase_rollout(mppi_ctx* c) {
 hipError_t phase_update(mppi_ctx* c) {
   if (c->batch) return launch_batch_update(c->plan, c->stream);
   const Instance& I = c->one();
+  TapeRef tape;
   if (I.grad) {
-    hipError_t e = launch_tape_record(I.u, I.TM, I.st, I.at<float>(I.L.tape_u),
-                                      I.at<uint32_t>(I.L.tape_word), I.at<int32_t>(I.L.tape_count),
-                                      I.tape_cap, c->stream);
-    if (e != hipSuccess) return e;
+    tape.u = I.u;
+    tape.TM = I.TM;
+    tape.tape_u = I.at<float>(I.L.tape_u);
+    tape.tape_word = I.at<uint32_t>(I.L.tape_word);
+    tape.count = I.at<int32_t>(I.L.tape_count);
+    tape.cap = I.tape_cap;
   }
   return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, step_size(I.cfg),
-                               I.e(), I.u, I.st, c->stream, I.dp.n_plain);
+                               I.e(), I.u, I.st, c->stream, I.dp.n_plain, tape);
 }
 
 }  // namespace

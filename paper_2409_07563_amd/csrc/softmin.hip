@@ -6,9 +6,23 @@ namespace mppi {
 
 int gemv_rows_per_block() { return 1; }
 
+// The weights step; with a tape, first the update's record: slot s = *count
+// takes u and the iteration word this update's noise was drawn with (read
+// before the weights step advances it), then *count = s + 1 (cap + 1 when
+// the tape is full).
 __global__ __launch_bounds__(kWeightsBlock) void weights_kernel_one(
     const float* __restrict__ S, int K, float lambda, float inv_lambda, float* __restrict__ e,
-    DevState* __restrict__ st, int n_plain) {
+    DevState* __restrict__ st, int n_plain, TapeRef tape) {
+  if (tape.u) {
+    const int s = *tape.count;
+    if (s < tape.cap) {
+      float* dst = tape.tape_u + static_cast<int64_t>(s) * tape.TM;
+      for (int i = threadIdx.x; i < tape.TM; i += blockDim.x) dst[i] = tape.u[i];
+      if (threadIdx.x == 0) tape.tape_word[s] = st->iteration;
+    }
+    __syncthreads();  // every thread has read *count and the iteration word
+    if (threadIdx.x == 0) *tape.count = s < tape.cap ? s + 1 : tape.cap + 1;
+  }
   weights_body(S, K, lambda, inv_lambda, e, st, n_plain);
 }
 
@@ -20,10 +34,11 @@ __global__ __launch_bounds__(kGemvBlock) void gemv_kernel_one(
 
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
                                  int TM, float lambda, float step, float* d_e, float* d_u,
-                                 DevState* d_state, hipStream_t stream, int n_plain) {
+                                 DevState* d_state, hipStream_t stream, int n_plain,
+                                 const TapeRef& tape) {
   const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
   hipLaunchKernelGGL(weights_kernel_one, dim3(1), dim3(kWeightsBlock), 0, stream, d_S, K, lambda,
-                     inv_lambda, d_e, d_state, n_plain);
+                     inv_lambda, d_e, d_state, n_plain, tape);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(gemv_kernel_one, dim3(TM), dim3(kGemvBlock), 0, stream, d_eps, ldk, K, d_e,
@@ -38,7 +53,7 @@ hipError_t launch_weights_only(const float* d_S, int K, float lambda, float* d_e
                                DevState* d_scratch_state, hipStream_t stream) {
   const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
   hipLaunchKernelGGL(weights_kernel_one, dim3(1), dim3(kWeightsBlock), 0, stream, d_S, K, lambda,
-                     inv_lambda, d_e, d_scratch_state, K);
+                     inv_lambda, d_e, d_scratch_state, K, TapeRef{});
   return hipGetLastError();
 }
 
