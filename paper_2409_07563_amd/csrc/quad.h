@@ -15,9 +15,11 @@ namespace mppi {
 
 // quad_perm selectors: [1,0,3,2], [2,3,0,1] and the shift [0,0,1,2]
 constexpr int kQuadSwap1 = 0xB1, kQuadSwap2 = 0x4E, kQuadShift = 0x90;
+// Every lane of a quad reads a valid source under these permutations, so the
+// move needs no initialised destination (no extra register move per use).
 template <int CTRL>
 __device__ __forceinline__ float quad_dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float quad_sum(float v) {
   const float a = v + quad_dpp<kQuadSwap1>(v);
@@ -53,9 +55,10 @@ __device__ __forceinline__ void bicycle_quad_step(float* x, float* comp, const f
   const float gy = quad_sum(wj * (sj * sn));
   const float gp = quad_sum(wj * kpsi);
   const float x0s[N] = {x[0], x[1], x[2], x[3], x[4]};
-  const float inc[N] = {p.sixth_dt * gx, p.sixth_dt * gy, p.sixth_dt * gp,
-                        p.sixth_dt * (((v[0] + 2.0f * v[0]) + 2.0f * v[0]) + v[0]),
-                        p.sixth_dt * (((v[1] + 2.0f * v[1]) + 2.0f * v[1]) + v[1])};
+  // speed and steer have the constant derivatives (a, steer rate) over the
+  // step: their RK4 increment is dt v
+  const float inc[N] = {p.sixth_dt * gx, p.sixth_dt * gy, p.sixth_dt * gp, p.dt * v[0],
+                        p.dt * v[1]};
   advance<Bicycle<FAST>>(x, x0s, inc, comp);
 }
 
