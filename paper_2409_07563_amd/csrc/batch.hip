@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kGemvBlock) void batch_gemv_kernel(const BatchInst*
                                                                 const int2* __restrict__ tiles) {
   const int2 tl = tiles[blockIdx.x];
   const BatchInst& b = insts[tl.x];
-  gemv_row(b.eps, b.ldk, b.K, b.e, b.st, b.u, b.step, tl.y);
+  gemv_row(b.eps, b.ldk, b.K, b.e, b.st, b.u, b.step, tl.y, false);
 }
 
 __global__ void batch_set_iteration_kernel(const BatchInst* __restrict__ insts, int n,

@@ -172,10 +172,23 @@ struct TapeRef {
 // step: the step size gamma of u += gamma sum_k w_k (v_k - u) (1 for
 // Algorithm 1); samples k >= n_plain were drawn around zero (n_plain = K:
 // none); tape: see TapeRef.
+// The next iteration's noise, drawn by the weights launch (iteration word + 1)
+// into another buffer; kblocks is filled in by the launcher.
+struct NoiseJob {
+  uint32_t key0, key1, instance;
+  int T, TM;
+  Sigma8 sigma;
+  float* eps;
+  int64_t ldk;
+  const float* sigma_t;
+  int mean_sample;
+  int calls;
+  int kblocks;
+};
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
                                  int TM, float lambda, float step, float* d_e, float* d_u,
                                  DevState* d_state, hipStream_t stream, int n_plain,
-                                 const TapeRef& tape = TapeRef{});
+                                 const TapeRef& tape = TapeRef{}, const NoiseJob* next = nullptr);
 hipError_t launch_set_iteration(DevState* d_state, uint32_t iteration, hipStream_t stream);
 hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState* d_state,
                           float* d_w, hipStream_t stream);

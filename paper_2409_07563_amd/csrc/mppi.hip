@@ -59,7 +59,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Per-instance workspace slice (byte offsets from the slice base, 256-aligned).
 struct Layout {
   int64_t ldk;  // noise row stride (K rounded up to a wave)
-  size_t eps, e;
+  // single contexts: two noise buffers, so that an update can draw the next
+  // iteration's noise while the weighted sum still reads this one's
+  size_t eps, eps2, e;
   size_t ref, stage, costmap, mlp, mlp_bwd;
   size_t sigma_t, is_coef_t;  // per-step noise deviations and importance coefficients
   // MPPI_F_REQUIRES_GRAD: checkpoints [nseg][7][ldk], the rollout's controls,
@@ -277,6 +279,7 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   L.eps = take(sizeof(float) * (size_t)TM * L.ldk);
+  L.eps2 = batch ? L.eps : take(sizeof(float) * (size_t)TM * L.ldk);
   L.e = take(sizeof(float) * L.ldk);
   L.ref = take(sizeof(float) * (size_t)(p->ref ? p->ref_len : 1));
   const int S = uses_spline(c->cost) ? p->num_segments : 0;
@@ -412,10 +415,12 @@ struct Instance {
   float* S;
   int32_t* crashes;
   int64_t off_x0, off_u, off_S;
+  int cur;  // the noise buffer of the current iteration (0: eps, 1: eps2)
 
   template <class X>
   X* at(size_t off) const { return reinterpret_cast<X*>(base + off); }
-  float* eps() const { return at<float>(L.eps); }
+  float* eps() const { return at<float>(cur ? L.eps2 : L.eps); }
+  float* eps_other() const { return at<float>(cur ? L.eps : L.eps2); }
   float* e() const { return at<float>(L.e); }
 };
 
@@ -714,6 +719,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
     I.S = reinterpret_cast<float*>(c->ws + C.S) + oS;
     I.crashes = reinterpret_cast<int32_t*>(c->ws + C.crashes) + oS;
     I.off_x0 = ox; I.off_u = ou; I.off_S = oS;
+    I.cur = 0;
     ox += I.n; ou += I.TM; oS += I.K;
     states[i] = DevState{};
     states[i].status = MPPI_OK;
@@ -827,7 +833,9 @@ hipError_t phase_rollout(mppi_ctx* c) {
                         c->stream, c->tune.rollout_block);
 }
 
-hipError_t phase_update(mppi_ctx* c) {
+// next: the weights launch also draws the next iteration's noise into the
+// other buffer (the caller then switches buffers).
+hipError_t phase_update(mppi_ctx* c, bool next = false) {
   if (c->batch) return launch_batch_update(c->plan, c->stream);
   const Instance& I = c->one();
   TapeRef tape;
@@ -839,8 +847,46 @@ hipError_t phase_update(mppi_ctx* c) {
     tape.count = I.at<int32_t>(I.L.tape_count);
     tape.cap = I.tape_cap;
   }
+  NoiseJob job{};
+  if (next) {
+    job.key0 = static_cast<uint32_t>(I.cfg.seed);
+    job.key1 = static_cast<uint32_t>(I.cfg.seed >> 32);
+    job.instance = I.cfg.instance;
+    job.T = I.T;
+    job.TM = I.TM;
+    for (int j = 0; j < I.m; ++j) job.sigma.v[j] = I.cfg.sigma[j];
+    job.eps = I.eps_other();
+    job.ldk = I.L.ldk;
+    job.sigma_t = I.dp.sigma_t;
+    job.mean_sample = I.dp.mean_sample != 0;
+    job.calls = c->tune.noise_calls;
+  }
   return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, step_size(I.cfg),
-                               I.e(), I.u, I.st, c->stream, I.dp.n_plain, tape);
+                               I.e(), I.u, I.st, c->stream, I.dp.n_plain, tape,
+                               next ? &job : nullptr);
+}
+
+// Iteration i of n in mppi_iterate.  A single context draws the noise of
+// the first iteration only; each update but the last draws the next one's
+// into the other buffer.  The sequence starts from buffer 0 so that a
+// captured graph and a direct launch use the same buffers.
+hipError_t phase_iteration(mppi_ctx* c, int i, int n) {
+  hipError_t e = hipSuccess;
+  if (c->batch) {
+    e = phase_sample(c);
+    if (e == hipSuccess) e = phase_rollout(c);
+    return e == hipSuccess ? phase_update(c) : e;
+  }
+  Instance& I = c->inst[0];
+  if (i == 0) {
+    I.cur = 0;
+    e = phase_sample(c);
+  }
+  if (e == hipSuccess) e = phase_rollout(c);
+  if (e != hipSuccess || i + 1 == n) return e == hipSuccess ? phase_update(c) : e;
+  e = phase_update(c, true);
+  I.cur ^= 1;
+  return e;
 }
 
 }  // namespace
@@ -1198,9 +1244,7 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
   // (the null stream cannot be captured: launch directly there)
   if (c->stream == nullptr) {
     for (int i = 0; i < num_iters; ++i) {
-      hipError_t e = phase_sample(c);
-      if (e == hipSuccess) e = phase_rollout(c);
-      if (e == hipSuccess) e = phase_update(c);
+      hipError_t e = phase_iteration(c, i, num_iters);
       if (e != hipSuccess) return hip_fail(e, "iteration launch");
     }
     c->have_noise = c->have_costs = c->rollout_fresh = c->grad_ready = true;
@@ -1211,11 +1255,7 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < num_iters && e == hipSuccess; ++i) {
-      e = phase_sample(c);
-      if (e == hipSuccess) e = phase_rollout(c);
-      if (e == hipSuccess) e = phase_update(c);
-    }
+    for (int i = 0; i < num_iters && e == hipSuccess; ++i) e = phase_iteration(c, i, num_iters);
     const hipError_t ec = hipStreamEndCapture(c->stream, &g);
     if (e != hipSuccess || ec != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
@@ -1228,6 +1268,7 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
     it = c->graphs.emplace(num_iters, exec).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, c->stream));
+  if (!c->batch) c->inst[0].cur = (num_iters - 1) & 1;
   c->have_noise = c->have_costs = c->rollout_fresh = c->grad_ready = true;
   return MPPI_OK;
 }

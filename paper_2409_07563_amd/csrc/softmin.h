@@ -71,9 +71,12 @@ __device__ __forceinline__ void block_sum2(float& a, float& b, float2* lds) {
 constexpr int kWeightsChunk = 32;
 // Samples k >= n_plain were drawn around zero: their weight mass
 // W_Z = sum_{k >= n_plain} w_k goes to st->wz for the update.
+// advance: also step the iteration word (otherwise the update's row kernel
+// does, after the noise of the next iteration has been drawn from it).
 __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K, float lambda,
                                              float inv_lambda, float* __restrict__ e,
-                                             DevState* __restrict__ st, int n_plain) {
+                                             DevState* __restrict__ st, int n_plain,
+                                             bool advance = true) {
   constexpr int NW = kWeightsBlock / kWave;
   constexpr int kSpan = kWeightsChunk * kWeightsBlock;  // costs per chunk
   __shared__ float lds[NW];
@@ -122,7 +125,7 @@ __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K,
     st->stats[2] = finite ? rho - lambda * logf(eta / static_cast<float>(K)) : __builtin_inff();
     st->stats[3] = finite ? (eta * eta) / sum_e2 : 0.0f;
     st->status = finite ? MPPI_OK : MPPI_ENUMERIC;
-    st->iteration = st->iteration + 1u;
+    if (advance) st->iteration = st->iteration + 1u;
   }
 }
 
@@ -135,9 +138,12 @@ __device__ __forceinline__ void weights_body(const float* __restrict__ S, int K,
 // (and eight of e) are in flight per lane, so a row of up to 8192 samples is
 // one memory round trip.  When every cost was non-finite (eta = 0) u is left
 // unchanged.
+// advance: row 0 steps the iteration word at the end (the single-instance
+// update; the weights step then leaves it).
 __device__ __forceinline__ void gemv_row(const float* __restrict__ eps, int64_t ldk, int K,
-                                         const float* __restrict__ e, const DevState* st,
-                                         float* __restrict__ u, float step, int r) {
+                                         const float* __restrict__ e, DevState* st,
+                                         float* __restrict__ u, float step, int r,
+                                         bool advance = false) {
   constexpr int NW = kGemvBlock / kWave;
   constexpr int kIn = 8;                     // loads in flight per lane and array
   constexpr int kStride = 4 * kGemvBlock;    // floats per sweep of the workgroup
@@ -181,6 +187,7 @@ __device__ __forceinline__ void gemv_row(const float* __restrict__ eps, int64_t 
       if (wz != 0.0f) q -= u[r] * wz;
       u[r] = u[r] + step * q;
     }
+    if (advance && r == 0) st->iteration = st->iteration + 1u;
   }
 }
 

@@ -62,6 +62,48 @@ def test_sequence_equals_single_iterations(mppi, oracle_lib, I):
     one.close()
 
 
+def _with_options(wl, seed):
+    rng = np.random.default_rng(seed)
+    sig_t = (np.asarray(wl.sigma, np.float64)[None, :]
+             * rng.uniform(0.5, 1.5, (wl.T, wl.m))).astype(np.float32)
+    return wl.replace(sigma_t=sig_t, mean_sample=1, zero_frac=0.1, is_beta=1, gamma=0.8)
+
+
+# the next iteration's noise is drawn by the update of the one before, into a
+# second buffer: every rollout kernel reads the right buffer, per-step
+# deviations and the mean sample included
+SEQ_CASES = {
+    "c3": (lambda: W.c3(K=700, T=40), {}),
+    "c2_lanes1": (lambda: W.c2("circles", K=1100, T=60), dict(lanes_per_sample=1)),
+    "c2_split": (lambda: W.c2("circles", K=1100, T=60),
+                 dict(rollout_form=1, lanes_per_sample=4, cost_waves=8)),
+    "c5_mlp": (lambda: W.c5(K=500, T=30, hidden=64), dict(rollout_block=128)),
+}
+
+
+@pytest.mark.parametrize("name", list(SEQ_CASES))
+def test_sequence_with_sampling_options(mppi, oracle_lib, name):
+    make, shape = SEQ_CASES[name]
+    wl = _with_options(make(), sum(map(ord, name)))
+    outs = []
+    for split_calls in (False, True):
+        c = mppi.Controller(wl)
+        if shape:
+            c.set_tuning(**shape)
+        if split_calls:
+            for _ in range(3):
+                c.iterate(1)
+        else:
+            c.iterate(3)
+        outs.append([_np(getattr(c, n)()) for n in ("controls", "costs", "noise")])
+        assert c.stats()["iteration"] == 3
+        c.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(_bits(a), _bits(b))
+    eps = oracle_lib.workload_noise(wl, iteration=2)
+    assert np.array_equal(_bits(outs[0][2]), _bits(eps))
+
+
 def test_staged_calls_after_a_sequence(mppi, oracle_lib):
     wl = W.c2("circles", K=1000, T=30)
     c = mppi.Controller(wl)
