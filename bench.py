@@ -232,6 +232,22 @@ def main():
     steps_per_iter = wl.K * wl.T
     value = I * steps_per_iter / (ms_per_step * 1e-3)
 
+    # the step with each form of the update (the single-pass one where it exists)
+    update_forms = None
+    if ctl.tuning()["update_form"] == 1:
+        update_forms = {}
+        for form, name in ((0, "two_pass"), (1, "one_pass")):
+            ctl.set_tuning(update_form=form)
+            for _ in range(max(1, args.warmup)):
+                ctl.iterate(I)
+            torch.cuda.synchronize()
+            start.record(stream)
+            for _ in range(args.steps):
+                ctl.iterate(I)
+            end.record(stream)
+            torch.cuda.synchronize()
+            update_forms[name] = start.elapsed_time(end) / args.steps
+
     t_noise, t_roll, t_upd = phase_times(ctl, args.kernel_reps)
 
     ops = rollout_ops_per_step(wl) * steps_per_iter
@@ -263,6 +279,7 @@ def main():
         "wall_s_timed": wall,
         "tuning": ctl.tuning(),
         "rollout_forms_us": rollout_forms(tuned),
+        "update_forms_ms_per_step": update_forms,
         "roofline": roofline,
         "kernels": kernels,
     }

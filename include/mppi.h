@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MPPI_ABI_VERSION 2u
+#define MPPI_ABI_VERSION 3u
 #define MPPI_MAX_STATE 16
 #define MPPI_MAX_CONTROL 8
 
@@ -251,7 +251,8 @@ mppi_status mppi_offsets(const mppi_ctx* ctx, int32_t what, int64_t* host_offset
 /* ---- launch shapes and the autotuner (spec extension) ------------------
  * How the kernels of a context are launched; none of it changes results
  * except lanes_per_sample and rollout_form, which select a different (equally
- * accurate) rollout kernel.  The paper picks between its kernels by timing
+ * accurate) rollout kernel, and update_form, which rounds the update's sums in
+ * another order.  The paper picks between its kernels by timing
  * them (section "Choosing between the Split and Combined Kernels");
  * mppi_autotune does the same over this table.
  *
@@ -264,6 +265,13 @@ mppi_status mppi_offsets(const mppi_ctx* ctx, int32_t what, int64_t* host_offset
  * for single contexts with DOUBLE_INTEGRATOR, BICYCLE or QUADROTOR dynamics
  * (not for MLP dynamics, gradient mode or batches). */
 enum { MPPI_ROLLOUT_FUSED = 0, MPPI_ROLLOUT_SPLIT = 1 };
+/* Steps (a3)-(a6) (Algorithm 1, Eq. mppi_update_rule): two launches (a
+ * weights step writing the weights, then one workgroup per row of the
+ * weighted noise sum), or one launch in which every row's workgroup computes
+ * the baseline, the weights and the normaliser itself from the costs (single
+ * contexts with at most 16384 samples, no gradient mode; the default there).
+ * Both are equally accurate; their sums are rounded in different orders. */
+enum { MPPI_UPDATE_TWO_PASS = 0, MPPI_UPDATE_ONE_PASS = 1 };
 typedef struct mppi_tuning {
   int32_t lanes_per_sample; /* rollout: 1, or 4, 8 or 16 (the bicycle with RK4, single
                                instance: RK4 stages across a quad, the running cost
@@ -285,6 +293,8 @@ typedef struct mppi_tuning {
                                the cost kernel, a power of two from 1 to 128 (up to
                                16 in one workgroup; beyond, chunks of 16 waves whose
                                partial sums a small kernel adds; default 8) */
+  int32_t update_form;      /* MPPI_UPDATE_TWO_PASS or MPPI_UPDATE_ONE_PASS (the
+                               default where it exists) */
 } mppi_tuning;
 
 /* The context's current launch shapes. */

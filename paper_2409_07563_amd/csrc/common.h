@@ -120,7 +120,8 @@ struct BatchPlan {
 hipError_t launch_noise(uint64_t seed, const uint32_t* d_iteration, uint32_t iteration,
                         uint32_t instance, int K, int T, int m, const float* sigma,
                         float* d_eps, int64_t ldk, hipStream_t stream, int calls = 1,
-                        const float* d_sigma_t = nullptr, bool mean_sample = false);
+                        const float* d_sigma_t = nullptr, bool mean_sample = false,
+                        uint32_t* d_word_out = nullptr);
 hipError_t launch_noise_tables(float* d_r, float* d_c, float* d_s, hipStream_t stream);
 
 // Returns hipErrorInvalidValue when the (dynamics, integrator, cost)
@@ -172,11 +173,17 @@ struct TapeRef {
 // step: the step size gamma of u += gamma sum_k w_k (v_k - u) (1 for
 // Algorithm 1); samples k >= n_plain were drawn around zero (n_plain = K:
 // none); tape: see TapeRef.
-// The next iteration's noise, drawn by the weights launch (iteration word + 1)
-// into another buffer; kblocks is filled in by the launcher.
+// Samples up to which the single-pass update exists.
+constexpr int kOnePassMaxK = 16384;
+
+// The next iteration's noise, drawn by the update's launch into the other
+// buffer with word *word_in + 1 (word_in: the word of the buffer the update
+// reads), which it records in *word_out; kblocks is filled in by the launcher.
 struct NoiseJob {
   uint32_t key0, key1, instance;
-  int T, TM;
+  const uint32_t* word_in;
+  uint32_t* word_out;
+  int K, T, TM;
   Sigma8 sigma;
   float* eps;
   int64_t ldk;
@@ -189,6 +196,13 @@ hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t l
                                  int TM, float lambda, float step, float* d_e, float* d_u,
                                  DevState* d_state, hipStream_t stream, int n_plain,
                                  const TapeRef& tape = TapeRef{}, const NoiseJob* next = nullptr);
+// Steps (a3)-(a6) in one launch for a single instance with K <= 16384 (one
+// workgroup per row computes the weights itself), optionally drawing the next
+// iteration's noise too.
+hipError_t launch_update_one_pass(const float* d_S, const float* d_eps, int64_t ldk, int K,
+                                  int TM, float lambda, float step, float* d_u,
+                                  DevState* d_state, hipStream_t stream, int n_plain,
+                                  const NoiseJob* next);
 hipError_t launch_set_iteration(DevState* d_state, uint32_t iteration, hipStream_t stream);
 hipError_t launch_weights(const float* d_S, int K, float lambda, const DevState* d_state,
                           float* d_w, hipStream_t stream);

@@ -62,6 +62,7 @@ struct Layout {
   // single contexts: two noise buffers, so that an update can draw the next
   // iteration's noise while the weighted sum still reads this one's
   size_t eps, eps2, e;
+  size_t words;  // single contexts: the iteration word each noise buffer was drawn with
   size_t ref, stage, costmap, mlp, mlp_bwd;
   size_t sigma_t, is_coef_t;  // per-step noise deviations and importance coefficients
   // MPPI_F_REQUIRES_GRAD: checkpoints [nseg][7][ldk], the rollout's controls,
@@ -280,6 +281,7 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   L.eps = take(sizeof(float) * (size_t)TM * L.ldk);
   L.eps2 = batch ? L.eps : take(sizeof(float) * (size_t)TM * L.ldk);
+  L.words = take(2 * sizeof(uint32_t));
   L.e = take(sizeof(float) * L.ldk);
   L.ref = take(sizeof(float) * (size_t)(p->ref ? p->ref_len : 1));
   const int S = uses_spline(c->cost) ? p->num_segments : 0;
@@ -421,6 +423,7 @@ struct Instance {
   X* at(size_t off) const { return reinterpret_cast<X*>(base + off); }
   float* eps() const { return at<float>(cur ? L.eps2 : L.eps); }
   float* eps_other() const { return at<float>(cur ? L.eps : L.eps2); }
+  uint32_t* word(int buf) const { return at<uint32_t>(L.words) + buf; }
   float* e() const { return at<float>(L.e); }
 };
 
@@ -504,6 +507,12 @@ hipError_t tape_reset(mppi_ctx* c) {
   if (c->batch || !c->one().grad) return hipSuccess;
   c->tape_external = false;
   return launch_tape_reset(c->one().at<int32_t>(c->one().L.tape_count), c->stream);
+}
+
+// The single-pass update exists for single, non-gradient contexts with up to
+// kOnePassMaxK samples (the gradient mode's adjoint reads the stored weights).
+bool one_pass_for(const mppi_ctx* c) {
+  return !c->batch && !c->one().grad && c->one().K <= kOnePassMaxK;
 }
 
 }  // namespace
@@ -787,6 +796,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   c->tune.noise_calls = 1;
   c->tune.rollout_form = MPPI_ROLLOUT_FUSED;
   c->tune.cost_waves = 8;
+  c->tune.update_form = one_pass_for(c) ? MPPI_UPDATE_ONE_PASS : MPPI_UPDATE_TWO_PASS;
   if (e == hipSuccess) e = tape_reset(c);
   if (e == hipSuccess && batch) e = upload_sample_tiles(c, c->tune.batch_tile);
   if (e != hipSuccess) { delete c; return hip_fail(e, "context upload"); }
@@ -801,7 +811,7 @@ hipError_t phase_sample(mppi_ctx* c) {
   const Instance& I = c->one();
   return launch_noise(I.cfg.seed, &I.st->iteration, 0u, I.cfg.instance, I.K, I.T, I.m,
                       I.cfg.sigma, I.eps(), I.L.ldk, c->stream, c->tune.noise_calls, I.dp.sigma_t,
-                      I.dp.mean_sample != 0);
+                      I.dp.mean_sample != 0, I.word(I.cur));
 }
 
 hipError_t phase_rollout(mppi_ctx* c) {
@@ -852,6 +862,9 @@ hipError_t phase_update(mppi_ctx* c, bool next = false) {
     job.key0 = static_cast<uint32_t>(I.cfg.seed);
     job.key1 = static_cast<uint32_t>(I.cfg.seed >> 32);
     job.instance = I.cfg.instance;
+    job.word_in = I.word(I.cur);
+    job.word_out = I.word(I.cur ^ 1);
+    job.K = I.K;
     job.T = I.T;
     job.TM = I.TM;
     for (int j = 0; j < I.m; ++j) job.sigma.v[j] = I.cfg.sigma[j];
@@ -861,6 +874,10 @@ hipError_t phase_update(mppi_ctx* c, bool next = false) {
     job.mean_sample = I.dp.mean_sample != 0;
     job.calls = c->tune.noise_calls;
   }
+  if (c->tune.update_form == MPPI_UPDATE_ONE_PASS)
+    return launch_update_one_pass(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda,
+                                  step_size(I.cfg), I.u, I.st, c->stream, I.dp.n_plain,
+                                  next ? &job : nullptr);
   return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, step_size(I.cfg),
                                I.e(), I.u, I.st, c->stream, I.dp.n_plain, tape,
                                next ? &job : nullptr);
@@ -965,6 +982,11 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
                 kSplitMaxWaves * kSplitMaxChunks);
   if (t->rollout_form != MPPI_ROLLOUT_FUSED && t->rollout_form != MPPI_ROLLOUT_SPLIT)
     return fail(MPPI_EINVAL, "rollout_form must be MPPI_ROLLOUT_FUSED or MPPI_ROLLOUT_SPLIT");
+  if (t->update_form != MPPI_UPDATE_TWO_PASS && t->update_form != MPPI_UPDATE_ONE_PASS)
+    return fail(MPPI_EINVAL, "update_form must be MPPI_UPDATE_TWO_PASS or MPPI_UPDATE_ONE_PASS");
+  if (t->update_form == MPPI_UPDATE_ONE_PASS && !one_pass_for(c))
+    return fail(MPPI_EUNSUPPORTED, "the single-pass update exists for single contexts with at "
+                "most %d samples (no gradient mode)", kOnePassMaxK);
   Instance& I = c->inst[0];
   if (t->rollout_form == MPPI_ROLLOUT_SPLIT) {
     if (c->batch || !I.split)
@@ -1029,10 +1051,11 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     return err;
   };
   auto line = [&](const char* phase, const mppi_tuning& t, double us) {
-    char buf[160];
-    snprintf(buf, sizeof buf, "%s lanes=%d block=%d tile=%d calls=%d form=%d waves=%d %.2f\n",
-             phase, t.lanes_per_sample, t.rollout_block, t.batch_tile, t.noise_calls,
-             t.rollout_form, t.cost_waves, us);
+    char buf[192];
+    snprintf(buf, sizeof buf,
+             "%s lanes=%d block=%d tile=%d calls=%d form=%d waves=%d update=%d %.2f\n", phase,
+             t.lanes_per_sample, t.rollout_block, t.batch_tile, t.noise_calls, t.rollout_form,
+             t.cost_waves, t.update_form, us);
     text += buf;
   };
   // Each group of candidates shapes one phase; the candidates of a group are

@@ -18,10 +18,11 @@ __global__ __launch_bounds__(256) void noise_kernel(uint32_t key0, uint32_t key1
                                                     int K, int TM, int m, Sigma8 sigma,
                                                     float* __restrict__ eps, int64_t ldk,
                                                     int calls, const float* __restrict__ sigma_t,
-                                                    int mean_sample) {
+                                                    int mean_sample, uint32_t* d_word_out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const uint32_t it = d_iteration ? *d_iteration + iteration : iteration;
+  if (d_word_out && k == 0 && blockIdx.y == 0) *d_word_out = it;
   const int ncall = (TM + 3) / 4;
   const int c0 = blockIdx.y * calls;
   for (int c = c0; c < c0 + calls && c < ncall; ++c)
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(256) void noise_kernel(uint32_t key0, uint32_t key1
 hipError_t launch_noise(uint64_t seed, const uint32_t* d_iteration, uint32_t iteration,
                         uint32_t instance, int K, int T, int m, const float* sigma,
                         float* d_eps, int64_t ldk, hipStream_t stream, int calls,
-                        const float* d_sigma_t, bool mean_sample) {
+                        const float* d_sigma_t, bool mean_sample, uint32_t* d_word_out) {
   if (calls < 1) return hipErrorInvalidValue;
   const int TM = T * m;
   const int ncall = (TM + 3) / 4;
@@ -41,7 +42,7 @@ hipError_t launch_noise(uint64_t seed, const uint32_t* d_iteration, uint32_t ite
   dim3 grid((K + 255) / 256, (ncall + calls - 1) / calls);
   hipLaunchKernelGGL(noise_kernel, grid, dim3(256), 0, stream, static_cast<uint32_t>(seed),
                      static_cast<uint32_t>(seed >> 32), d_iteration, iteration, instance, K,
-                     TM, m, s, d_eps, ldk, calls, d_sigma_t, mean_sample ? 1 : 0);
+                     TM, m, s, d_eps, ldk, calls, d_sigma_t, mean_sample ? 1 : 0, d_word_out);
   return hipGetLastError();
 }
 

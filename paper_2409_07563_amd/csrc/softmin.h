@@ -191,4 +191,103 @@ __device__ __forceinline__ void gemv_row(const float* __restrict__ eps, int64_t 
   }
 }
 
+// The single-pass update of row r (single contexts, K <= kOnePassMaxK): the
+// workgroup of row r computes rho, the weights and eta itself from the costs,
+// instead of reading them from a weights step, and takes the weighted sum of
+// its noise row in the same pass.  Every workgroup runs the same code on the
+// same costs, so each finds the same rho, weights and eta (bitwise).  Thread
+// t holds samples 4t + 1024q .. + 3 (q < NQ, NQ = ceil(K / 1024)); the noise
+// row and the costs are loaded first, all loads in flight together.  Row 0
+// records the statistics and the weight mass of the zero-mean samples and
+// steps the iteration word.  The weights themselves are not stored (only the
+// gradient mode's adjoint reads them, and it uses the two-pass update).
+
+template <int NQ>
+__device__ __forceinline__ void one_pass_row(const float* __restrict__ S, int K, float lambda,
+                                             float inv_lambda, const float* __restrict__ eps,
+                                             int64_t ldk, DevState* st, float* __restrict__ u,
+                                             float step, int r, int n_plain) {
+  constexpr int NW = kGemvBlock / kWave;
+  constexpr int kStride = 4 * kGemvBlock;
+  __shared__ float lds[NW];
+  __shared__ float4 lds4[NW];
+  const int tid = threadIdx.x;
+  const float* row = eps + static_cast<int64_t>(r) * ldk;
+  const int K4 = K & ~3;
+  const float inf = __builtin_inff();
+  float4 x[NQ];
+  float s[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int k = 4 * tid + q * kStride;
+    if (k < K4) {
+      x[q] = *reinterpret_cast<const float4*>(row + k);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s[q][j] = S[k + j];
+    } else {
+      x[q] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s[q][j] = inf;
+    }
+  }
+  const int kt = K4 + tid;  // the last K mod 4 samples, one per thread
+  const bool tail = kt < K;
+  const float xt = tail ? row[kt] : 0.0f;
+  const float st_ = tail ? S[kt] : inf;
+  float m = st_;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m = fminf(m, s[q][j]);
+  const float rho = block_min<NW>(m, lds);
+  const bool finite = rho < inf;
+  float dot = 0.0f, se = 0.0f, se2 = 0.0f, sz = 0.0f;
+  auto take = [&](int k, float sk, float xk) {
+    // non-finite J_k (NaN was turned into +inf by the rollout) gets weight 0
+    const float ek = (finite && sk < inf) ? expf((rho - sk) * inv_lambda) : 0.0f;
+    se += ek;
+    se2 += ek * ek;
+    sz += k >= n_plain ? ek : 0.0f;
+    dot += ek * xk;
+  };
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int k = 4 * tid + q * kStride;
+    if (k < K4) {
+      take(k, s[q][0], x[q].x);
+      take(k + 1, s[q][1], x[q].y);
+      take(k + 2, s[q][2], x[q].z);
+      take(k + 3, s[q][3], x[q].w);
+    }
+  }
+  if (tail) take(kt, st_, xt);
+  // one reduction of (dot, eta, sum e^2, zero-mean mass), fixed order
+  float4 v{wave_sum(dot), wave_sum(se), wave_sum(se2), wave_sum(sz)};
+  __syncthreads();
+  if (tid % kWave == 0) lds4[tid / kWave] = v;
+  __syncthreads();
+  if (tid != 0) return;
+  v = lds4[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) {
+    v.x += lds4[i].x; v.y += lds4[i].y; v.z += lds4[i].z; v.w += lds4[i].w;
+  }
+  const float eta = v.y;
+  const float wz = (finite && n_plain < K) ? v.w / eta : 0.0f;
+  if (eta > 0.0f) {
+    float qv = v.x / eta;
+    if (wz != 0.0f) qv -= u[r] * wz;
+    u[r] = u[r] + step * qv;
+  }
+  if (r == 0) {
+    st->wz = wz;
+    st->stats[0] = rho;
+    st->stats[1] = finite ? eta : 0.0f;
+    st->stats[2] = finite ? rho - lambda * logf(eta / static_cast<float>(K)) : inf;
+    st->stats[3] = finite ? (eta * eta) / v.z : 0.0f;
+    st->status = finite ? MPPI_OK : MPPI_ENUMERIC;
+    st->iteration = st->iteration + 1u;
+  }
+}
+
 }  // namespace mppi

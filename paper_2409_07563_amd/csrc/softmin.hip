@@ -30,12 +30,28 @@ __global__ __launch_bounds__(kWeightsBlock) void weights_kernel_one(
   weights_body(S, K, lambda, inv_lambda, e, st, n_plain, false);
 }
 
-// The weights step of iteration i in workgroup 0 and, in the others, the
-// noise of iteration i + 1 (iteration word + 1: the update's rows step the
-// word after this kernel) into the other noise buffer: two independent
+// Noise workgroup b of a launch that also draws the next iteration's noise:
+// word *job.word_in + 1 (the word of the noise the launch's update reads, plus
+// one) into job.eps, samples (b mod kblocks) * blockDim .. and the Philox
+// calls (b / kblocks) * calls ..; workgroup 0 records the word in
+// *job.word_out for the launch after.
+__device__ __forceinline__ void next_noise(const NoiseJob& job, int b) {
+  const uint32_t it = *job.word_in + 1u;
+  if (b == 0 && threadIdx.x == 0) *job.word_out = it;
+  const int k = (b % job.kblocks) * static_cast<int>(blockDim.x) + threadIdx.x;
+  if (k >= job.K) return;
+  const int ncall = (job.TM + 3) / 4;
+  const int c0 = (b / job.kblocks) * job.calls;
+  const int m = job.TM / job.T;
+  for (int c = c0; c < c0 + job.calls && c < ncall; ++c)
+    noise::emit_call(job.key0, job.key1, it, job.instance, k, c, job.TM, m, job.sigma.v, job.eps,
+                     job.ldk, job.sigma_t, job.mean_sample && k == 0);
+}
+
+// The weights step of an iteration in workgroup 0 and, in the others, the
+// noise of the next iteration into the other noise buffer: two independent
 // pieces of work in one launch, so the latency-bound weights step and the
-// VALU-bound noise overlap.  Noise workgroup b covers samples
-// (b mod kblocks) * 1024 .. and the Philox calls (b / kblocks) * calls ..
+// VALU-bound noise overlap.
 __global__ __launch_bounds__(kWeightsBlock) void weights_noise_kernel(
     const float* __restrict__ S, int K, float lambda, float inv_lambda, float* __restrict__ e,
     DevState* __restrict__ st, int n_plain, TapeRef tape, NoiseJob job) {
@@ -44,16 +60,53 @@ __global__ __launch_bounds__(kWeightsBlock) void weights_noise_kernel(
     weights_body(S, K, lambda, inv_lambda, e, st, n_plain, false);
     return;
   }
-  const int b = blockIdx.x - 1;
-  const int k = (b % job.kblocks) * kWeightsBlock + threadIdx.x;
-  if (k >= K) return;
-  const uint32_t it = st->iteration + 1u;
-  const int ncall = (job.TM + 3) / 4;
-  const int c0 = (b / job.kblocks) * job.calls;
-  const int m = job.TM / job.T;
-  for (int c = c0; c < c0 + job.calls && c < ncall; ++c)
-    noise::emit_call(job.key0, job.key1, it, job.instance, k, c, job.TM, m, job.sigma.v, job.eps,
-                     job.ldk, job.sigma_t, job.mean_sample && k == 0);
+  next_noise(job, blockIdx.x - 1);
+}
+
+// The single-pass update: workgroups 0 .. TM-1 take one row each; with a
+// next-noise job the workgroups after them draw the next iteration's noise.
+template <int NQ>
+__global__ __launch_bounds__(kGemvBlock) void one_pass_kernel(
+    const float* __restrict__ S, int K, float lambda, float inv_lambda,
+    const float* __restrict__ eps, int64_t ldk, DevState* __restrict__ st, float* __restrict__ u,
+    float step, int n_plain, int TM, NoiseJob job) {
+  if (static_cast<int>(blockIdx.x) < TM) {
+    one_pass_row<NQ>(S, K, lambda, inv_lambda, eps, ldk, st, u, step, blockIdx.x, n_plain);
+    return;
+  }
+  next_noise(job, blockIdx.x - TM);
+}
+
+// Blocks of the noise part for `threads` threads per workgroup.
+int noise_blocks(NoiseJob* job, int threads) {
+  job->kblocks = (job->K + threads - 1) / threads;
+  const int ncall = (job->TM + 3) / 4;
+  return job->kblocks * ((ncall + job->calls - 1) / job->calls);
+}
+
+hipError_t launch_update_one_pass(const float* d_S, const float* d_eps, int64_t ldk, int K,
+                                  int TM, float lambda, float step, float* d_u,
+                                  DevState* d_state, hipStream_t stream, int n_plain,
+                                  const NoiseJob* next) {
+  if (K < 1 || K > kOnePassMaxK) return hipErrorInvalidValue;
+  const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
+  NoiseJob job{};
+  int blocks = TM;
+  if (next) {
+    job = *next;
+    blocks += noise_blocks(&job, kGemvBlock);
+  }
+  const int nq = (K + 4 * kGemvBlock - 1) / (4 * kGemvBlock);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kGemvBlock), 0, stream, d_S, K, lambda,
+                       inv_lambda, d_eps, ldk, d_state, d_u, step, n_plain, TM, job);
+  };
+  if (nq <= 1) go(one_pass_kernel<1>);
+  else if (nq <= 2) go(one_pass_kernel<2>);
+  else if (nq <= 4) go(one_pass_kernel<4>);
+  else if (nq <= 8) go(one_pass_kernel<8>);
+  else go(one_pass_kernel<16>);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kGemvBlock) void gemv_kernel_one(
@@ -69,11 +122,9 @@ hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t l
   const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
   if (next) {
     NoiseJob job = *next;
-    job.kblocks = (K + kWeightsBlock - 1) / kWeightsBlock;
-    const int ncall = (job.TM + 3) / 4;
-    const int cblocks = (ncall + job.calls - 1) / job.calls;
-    hipLaunchKernelGGL(weights_noise_kernel, dim3(1 + job.kblocks * cblocks), dim3(kWeightsBlock),
-                       0, stream, d_S, K, lambda, inv_lambda, d_e, d_state, n_plain, tape, job);
+    const int blocks = 1 + noise_blocks(&job, kWeightsBlock);
+    hipLaunchKernelGGL(weights_noise_kernel, dim3(blocks), dim3(kWeightsBlock), 0, stream, d_S,
+                       K, lambda, inv_lambda, d_e, d_state, n_plain, tape, job);
   } else {
     hipLaunchKernelGGL(weights_kernel_one, dim3(1), dim3(kWeightsBlock), 0, stream, d_S, K,
                        lambda, inv_lambda, d_e, d_state, n_plain, tape);

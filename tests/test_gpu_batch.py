@@ -71,7 +71,8 @@ def test_batch_against_oracle(mppi, oracle_lib):
 
 def test_batch_equals_single_contexts_bitwise(mppi):
     """The batch runs the same lane body and the same reduction order as a
-    single-instance context with one lane per sample: results are identical."""
+    single-instance context with one lane per sample and the two-pass update:
+    results are identical."""
     insts = small_batch(n=6)
     ctl = mppi.Controller(insts)
     ctl.iterate(3)
@@ -80,6 +81,7 @@ def test_batch_equals_single_contexts_bitwise(mppi):
     ctl.close()
     for i, wl in enumerate(insts):
         one = mppi.Controller(wl, rollout="lane")
+        one.set_tuning(update_form=0)
         one.iterate(3)
         u1 = _np(one.controls()).ravel()
         s1 = _np(one.costs())

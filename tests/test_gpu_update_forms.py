@@ -1,0 +1,168 @@
+"""GPU parity of the two forms of steps (a3)-(a6) (Algorithm 1, Eq.
+mppi_update_rule) against the oracle, through the C ABI: the two-pass update
+(a weights step, then one workgroup per row of the weighted noise sum) and the
+single-pass update (every row's workgroup finds the baseline, the weights and
+the normaliser itself).  The update is isolated: both sides weight the same
+binary32 costs (the oracle's, set with mppi_set_costs) of the same noise.
+Sample counts span one to sixteen 1024-sample chunks with ragged tails, with
+and without zero-mean samples and importance sampling; non-finite costs, the
+statistics and the weights are checked too.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", file=sys.stderr, flush=True)
+    yield
+
+
+@pytest.fixture(scope="module")
+def mppi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2409_07563_amd as M
+    M.lib()
+    return M
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _n_plain(wl):
+    nz = int(np.floor(float(np.float32(wl.zero_frac)) * wl.K))
+    nz = min(nz, wl.K - (1 if wl.mean_sample else 0))
+    return wl.K - max(nz, 0)
+
+
+def _workload(K, T, seed, options):
+    wl = W.c2("circles", K=K, T=T, iters=1)
+    rng = np.random.default_rng(seed)
+    wl = wl.replace(u0=rng.normal(0.0, 0.4, (T, 2)).astype(np.float32))
+    if options:
+        wl = wl.replace(zero_frac=0.25, mean_sample=1, is_beta=1, gamma=0.6)
+    return wl
+
+
+def _update(mppi, wl, form, S32):
+    ctl = mppi.Controller(wl)
+    ctl.set_tuning(update_form=form)
+    ctl.sample()
+    ctl.set_costs(S32)
+    ctl.update()
+    out = dict(U=_np(ctl.controls()), st=ctl.stats(), w=_np(ctl.weights()), eps=_np(ctl.noise()))
+    ctl.close()
+    return out
+
+
+SIZES = [1, 3, 64, 1000, 1023, 1025, 4097, 8192, 12345, 16384]
+
+
+@pytest.mark.parametrize("options", [False, True], ids=["plain", "options"])
+@pytest.mark.parametrize("K", SIZES)
+@pytest.mark.parametrize("form", [0, 1], ids=["two_pass", "one_pass"])
+def test_update_forms_on_oracle_costs(mppi, oracle_lib, form, K, options):
+    wl = _workload(K, 12, K + 7 * options, options)
+    eps = oracle_lib.workload_noise(wl)
+    S_or, _, _ = oracle_lib.rollout_costs(wl, eps=eps)
+    S32 = S_or.astype(np.float32)
+    g = _update(mppi, wl, form, S32)
+    assert np.array_equal(g["eps"].view(np.uint32), eps.view(np.uint32))
+    S64 = S32.astype(np.float64)
+    w_or, U_or, stats_or, rc = oracle_lib.softmin_update(wl, S64, eps)
+    assert rc == 0 and g["st"]["status"] == 0 and g["st"]["iteration"] == 1
+    dev = eps.astype(np.float64).copy()            # v_k - u
+    dev[:, :, _n_plain(wl):] -= wl.u0.astype(np.float64)[:, :, None]
+    tol = parity.controls_tol(wl, S64, w_or, dev)
+    parity.assert_controls_close(g["U"], U_or, tol, f"form {form} K {K}")
+    st = g["st"]
+    assert st["rho"] == pytest.approx(stats_or[0], rel=1e-7)
+    assert st["eta"] == pytest.approx(stats_or[1], rel=1e-4)
+    assert st["ess"] == pytest.approx(stats_or[3], rel=1e-4)
+    assert st["free_energy"] == pytest.approx(stats_or[2], rel=1e-4, abs=1e-4)
+    assert abs(g["w"].astype(np.float64).sum() - 1.0) < 1e-5
+    assert np.allclose(g["w"], w_or, rtol=1e-4, atol=1e-7)
+
+
+@pytest.mark.parametrize("form", [0, 1], ids=["two_pass", "one_pass"])
+def test_update_forms_with_non_finite_costs(mppi, oracle_lib, form):
+    wl = _workload(3001, 10, 5, False)
+    eps = oracle_lib.workload_noise(wl)
+    S_or, _, _ = oracle_lib.rollout_costs(wl, eps=eps)
+    S32 = S_or.astype(np.float32)
+    S32[::7] = np.inf                              # crashed samples: weight 0
+    g = _update(mppi, wl, form, S32)
+    w_or, U_or, _, rc = oracle_lib.softmin_update(wl, S32.astype(np.float64), eps)
+    assert rc == 0 and g["st"]["status"] == 0
+    assert np.all(g["w"][::7] == 0)
+    fin = np.isfinite(S32)
+    tol = parity.controls_tol(wl, np.where(fin, S32, 0).astype(np.float64), w_or,
+                              eps.astype(np.float64))
+    parity.assert_controls_close(g["U"], U_or, tol, f"form {form}")
+    # every cost non-finite: status ENUMERIC, controls unchanged
+    g = _update(mppi, wl, form, np.full(wl.K, np.inf, np.float32))
+    assert g["st"]["status"] != 0 and g["st"]["iteration"] == 1
+    assert np.array_equal(g["U"].view(np.uint32), wl.u0.view(np.uint32))
+
+
+def test_update_forms_agree(mppi):
+    """Same costs, both forms: the controls differ only by rounding."""
+    wl = _workload(8192, 100, 11, True)
+    rng = np.random.default_rng(3)
+    S32 = rng.gamma(2.0, 50.0, wl.K).astype(np.float32)
+    a, b = (_update(mppi, wl, f, S32) for f in (0, 1))
+    scale = np.abs(a["U"]).max()
+    assert np.abs(a["U"] - b["U"]).max() <= 1e-5 * scale
+    assert a["st"]["rho"] == b["st"]["rho"]
+
+
+@pytest.mark.parametrize("form", [0, 1], ids=["two_pass", "one_pass"])
+def test_sequences_in_both_forms(mppi, oracle_lib, form):
+    """Five warm-started iterations through the captured graph, the next
+    iteration's noise drawn by each update's launch, equal bitwise to five
+    single iterations of the same form and at parity with the oracle."""
+    wl = _workload(4000, 40, 21, True).replace(iters=5)
+    outs = []
+    for seq in (True, False):
+        c = mppi.Controller(wl)
+        c.set_tuning(update_form=form)
+        if seq:
+            c.iterate(5)
+        else:
+            for _ in range(5):
+                c.iterate(1)
+        outs.append([_np(getattr(c, n)()) for n in ("controls", "costs", "noise")])
+        assert c.stats()["iteration"] == 5
+        c.close()
+    for x, y in zip(*outs):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert np.array_equal(outs[0][2].view(np.uint32),
+                          oracle_lib.workload_noise(wl, iteration=4).view(np.uint32))
+
+
+def test_one_pass_refused_where_it_does_not_exist(mppi):
+    from paper_2409_07563_amd import _abi
+    for ctl in (mppi.Controller(W.c2("circles", K=16385, T=10, iters=1)),
+                mppi.Controller([W.c2("circles", K=128, T=10), W.c2("circles", K=64, T=12)]),
+                mppi.Controller(W.c5(K=128, T=10, hidden=16), requires_grad=True)):
+        assert ctl.tuning()["update_form"] == 0
+        with pytest.raises(_abi.MPPIError):
+            ctl.set_tuning(update_form=1)
+        ctl.close()
+    ctl = mppi.Controller(W.c2("circles", K=16384, T=10, iters=1))
+    assert ctl.tuning()["update_form"] == 1
+    with pytest.raises(_abi.MPPIError):
+        ctl.set_tuning(update_form=2)
+    ctl.close()
