@@ -232,21 +232,24 @@ def main():
     steps_per_iter = wl.K * wl.T
     value = I * steps_per_iter / (ms_per_step * 1e-3)
 
-    # the step with each form of the update (the single-pass one where it exists)
-    update_forms = None
-    if ctl.tuning()["update_form"] == 1:
-        update_forms = {}
-        for form, name in ((0, "two_pass"), (1, "one_pass")):
+    # the step with each form of the update that the context has
+    update_forms = {}
+    chosen = ctl.tuning()["update_form"]
+    for form, name in ((0, "two_pass"), (1, "one_pass"), (2, "chunked")):
+        try:
             ctl.set_tuning(update_form=form)
-            for _ in range(max(1, args.warmup)):
-                ctl.iterate(I)
-            torch.cuda.synchronize()
-            start.record(stream)
-            for _ in range(args.steps):
-                ctl.iterate(I)
-            end.record(stream)
-            torch.cuda.synchronize()
-            update_forms[name] = start.elapsed_time(end) / args.steps
+        except M.MPPIError:
+            continue
+        for _ in range(max(1, args.warmup)):
+            ctl.iterate(I)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.steps):
+            ctl.iterate(I)
+        end.record(stream)
+        torch.cuda.synchronize()
+        update_forms[name] = start.elapsed_time(end) / args.steps
+    ctl.set_tuning(update_form=chosen)
 
     t_noise, t_roll, t_upd = phase_times(ctl, args.kernel_reps)
 

@@ -265,13 +265,20 @@ mppi_status mppi_offsets(const mppi_ctx* ctx, int32_t what, int64_t* host_offset
  * for single contexts with DOUBLE_INTEGRATOR, BICYCLE or QUADROTOR dynamics
  * (not for MLP dynamics, gradient mode or batches). */
 enum { MPPI_ROLLOUT_FUSED = 0, MPPI_ROLLOUT_SPLIT = 1 };
-/* Steps (a3)-(a6) (Algorithm 1, Eq. mppi_update_rule): two launches (a
- * weights step writing the weights, then one workgroup per row of the
- * weighted noise sum), or one launch in which every row's workgroup computes
- * the baseline, the weights and the normaliser itself from the costs (single
- * contexts with at most 16384 samples, no gradient mode; the default there).
- * Both are equally accurate; their sums are rounded in different orders. */
-enum { MPPI_UPDATE_TWO_PASS = 0, MPPI_UPDATE_ONE_PASS = 1 };
+/* Steps (a3)-(a6) (Algorithm 1, Eq. mppi_update_rule):
+ *  TWO_PASS: a weights step in one workgroup writes the weights, then one
+ *    workgroup per row forms the weighted noise sum (every context; the
+ *    default for batches and gradient mode, whose adjoint reads the weights);
+ *  ONE_PASS: one launch in which every row's workgroup computes the baseline,
+ *    the weights and the normaliser itself from the costs (single contexts
+ *    with at most 16384 samples, no gradient mode; the default there);
+ *  CHUNKED: the weights step spread over workgroups of 2048 samples, each
+ *    weighting its samples against its own minimum, and the rows rescale the
+ *    chunks to the global minimum (single contexts, no gradient mode; the
+ *    default above 16384 samples).
+ * All three are equally accurate; their sums are rounded in different orders
+ * (CHUNKED's weights are products of two exponentials). */
+enum { MPPI_UPDATE_TWO_PASS = 0, MPPI_UPDATE_ONE_PASS = 1, MPPI_UPDATE_CHUNKED = 2 };
 typedef struct mppi_tuning {
   int32_t lanes_per_sample; /* rollout: 1, or 4, 8 or 16 (the bicycle with RK4, single
                                instance: RK4 stages across a quad, the running cost
@@ -293,8 +300,8 @@ typedef struct mppi_tuning {
                                the cost kernel, a power of two from 1 to 128 (up to
                                16 in one workgroup; beyond, chunks of 16 waves whose
                                partial sums a small kernel adds; default 8) */
-  int32_t update_form;      /* MPPI_UPDATE_TWO_PASS or MPPI_UPDATE_ONE_PASS (the
-                               default where it exists) */
+  int32_t update_form;      /* MPPI_UPDATE_TWO_PASS, _ONE_PASS or _CHUNKED (defaults
+                               as listed above) */
 } mppi_tuning;
 
 /* The context's current launch shapes. */

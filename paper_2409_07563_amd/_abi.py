@@ -33,7 +33,7 @@ F_IMPORTANCE_SAMPLING = 32
 F_STEP_SIZE = 64
 F_MEAN_SAMPLE = 128
 ROLLOUT_FUSED, ROLLOUT_SPLIT = 0, 1
-UPDATE_TWO_PASS, UPDATE_ONE_PASS = 0, 1
+UPDATE_TWO_PASS, UPDATE_ONE_PASS, UPDATE_CHUNKED = 0, 1, 2
 SHIFT_HOLD, SHIFT_ZERO = 0, 1
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
 PACKED_STATE, PACKED_CONTROLS, PACKED_SAMPLES, PACKED_NOISE = 0, 1, 2, 3

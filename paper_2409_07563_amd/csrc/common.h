@@ -175,6 +175,8 @@ struct TapeRef {
 // none); tape: see TapeRef.
 // Samples up to which the single-pass update exists.
 constexpr int kOnePassMaxK = 16384;
+// Samples per workgroup of the chunked update's weights step.
+constexpr int kWChunk = 2048;
 
 // The next iteration's noise, drawn by the update's launch into the other
 // buffer with word *word_in + 1 (word_in: the word of the buffer the update
@@ -196,6 +198,14 @@ hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t l
                                  int TM, float lambda, float step, float* d_e, float* d_u,
                                  DevState* d_state, hipStream_t stream, int n_plain,
                                  const TapeRef& tape = TapeRef{}, const NoiseJob* next = nullptr);
+// Steps (a3)-(a6) for a single instance of any size (no gradient mode): the
+// weights step spread over ceil(K / kWChunk) workgroups (with a next-noise job
+// the same launch draws the next iteration's noise), then the rows;
+// d_part holds ceil(K / kWChunk) float4.
+hipError_t launch_update_chunked(const float* d_S, const float* d_eps, int64_t ldk, int K,
+                                 int TM, float lambda, float step, float* d_e, float4* d_part,
+                                 float* d_u, DevState* d_state, hipStream_t stream, int n_plain,
+                                 const NoiseJob* next);
 // Steps (a3)-(a6) in one launch for a single instance with K <= 16384 (one
 // workgroup per row computes the weights itself), optionally drawing the next
 // iteration's noise too.

@@ -63,6 +63,7 @@ struct Layout {
   // iteration's noise while the weighted sum still reads this one's
   size_t eps, eps2, e;
   size_t words;  // single contexts: the iteration word each noise buffer was drawn with
+  size_t wpart;  // single contexts: the chunked update's per-chunk sums
   size_t ref, stage, costmap, mlp, mlp_bwd;
   size_t sigma_t, is_coef_t;  // per-step noise deviations and importance coefficients
   // MPPI_F_REQUIRES_GRAD: checkpoints [nseg][7][ldk], the rollout's controls,
@@ -282,6 +283,7 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
   L.eps = take(sizeof(float) * (size_t)TM * L.ldk);
   L.eps2 = batch ? L.eps : take(sizeof(float) * (size_t)TM * L.ldk);
   L.words = take(2 * sizeof(uint32_t));
+  L.wpart = take(sizeof(float4) * ((K + kWChunk - 1) / kWChunk));
   L.e = take(sizeof(float) * L.ldk);
   L.ref = take(sizeof(float) * (size_t)(p->ref ? p->ref_len : 1));
   const int S = uses_spline(c->cost) ? p->num_segments : 0;
@@ -510,10 +512,10 @@ hipError_t tape_reset(mppi_ctx* c) {
 }
 
 // The single-pass update exists for single, non-gradient contexts with up to
-// kOnePassMaxK samples (the gradient mode's adjoint reads the stored weights).
-bool one_pass_for(const mppi_ctx* c) {
-  return !c->batch && !c->one().grad && c->one().K <= kOnePassMaxK;
-}
+// kOnePassMaxK samples, the chunked one for single, non-gradient contexts (the
+// gradient mode's adjoint reads the weights the two-pass update stores).
+bool chunked_for(const mppi_ctx* c) { return !c->batch && !c->one().grad; }
+bool one_pass_for(const mppi_ctx* c) { return chunked_for(c) && c->one().K <= kOnePassMaxK; }
 
 }  // namespace
 
@@ -796,7 +798,9 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   c->tune.noise_calls = 1;
   c->tune.rollout_form = MPPI_ROLLOUT_FUSED;
   c->tune.cost_waves = 8;
-  c->tune.update_form = one_pass_for(c) ? MPPI_UPDATE_ONE_PASS : MPPI_UPDATE_TWO_PASS;
+  c->tune.update_form = one_pass_for(c)  ? MPPI_UPDATE_ONE_PASS
+                        : chunked_for(c) ? MPPI_UPDATE_CHUNKED
+                                         : MPPI_UPDATE_TWO_PASS;
   if (e == hipSuccess) e = tape_reset(c);
   if (e == hipSuccess && batch) e = upload_sample_tiles(c, c->tune.batch_tile);
   if (e != hipSuccess) { delete c; return hip_fail(e, "context upload"); }
@@ -878,6 +882,10 @@ hipError_t phase_update(mppi_ctx* c, bool next = false) {
     return launch_update_one_pass(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda,
                                   step_size(I.cfg), I.u, I.st, c->stream, I.dp.n_plain,
                                   next ? &job : nullptr);
+  if (c->tune.update_form == MPPI_UPDATE_CHUNKED)
+    return launch_update_chunked(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda,
+                                 step_size(I.cfg), I.e(), I.at<float4>(I.L.wpart), I.u, I.st,
+                                 c->stream, I.dp.n_plain, next ? &job : nullptr);
   return launch_softmin_update(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda, step_size(I.cfg),
                                I.e(), I.u, I.st, c->stream, I.dp.n_plain, tape,
                                next ? &job : nullptr);
@@ -982,11 +990,16 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
                 kSplitMaxWaves * kSplitMaxChunks);
   if (t->rollout_form != MPPI_ROLLOUT_FUSED && t->rollout_form != MPPI_ROLLOUT_SPLIT)
     return fail(MPPI_EINVAL, "rollout_form must be MPPI_ROLLOUT_FUSED or MPPI_ROLLOUT_SPLIT");
-  if (t->update_form != MPPI_UPDATE_TWO_PASS && t->update_form != MPPI_UPDATE_ONE_PASS)
-    return fail(MPPI_EINVAL, "update_form must be MPPI_UPDATE_TWO_PASS or MPPI_UPDATE_ONE_PASS");
+  if (t->update_form != MPPI_UPDATE_TWO_PASS && t->update_form != MPPI_UPDATE_ONE_PASS &&
+      t->update_form != MPPI_UPDATE_CHUNKED)
+    return fail(MPPI_EINVAL, "update_form must be MPPI_UPDATE_TWO_PASS, MPPI_UPDATE_ONE_PASS "
+                "or MPPI_UPDATE_CHUNKED");
   if (t->update_form == MPPI_UPDATE_ONE_PASS && !one_pass_for(c))
     return fail(MPPI_EUNSUPPORTED, "the single-pass update exists for single contexts with at "
                 "most %d samples (no gradient mode)", kOnePassMaxK);
+  if (t->update_form == MPPI_UPDATE_CHUNKED && !chunked_for(c))
+    return fail(MPPI_EUNSUPPORTED, "the chunked update exists for single contexts (no gradient "
+                "mode)");
   Instance& I = c->inst[0];
   if (t->rollout_form == MPPI_ROLLOUT_SPLIT) {
     if (c->batch || !I.split)

@@ -290,4 +290,146 @@ __device__ __forceinline__ void one_pass_row(const float* __restrict__ S, int K,
   }
 }
 
+// The chunked update (single contexts of any size, no gradient mode): the
+// weights step is spread over workgroups of kWChunk samples.  Chunk c finds
+// its own minimum m_c and writes e'_k = exp(-(J_k - m_c)/lambda) with the
+// chunk's sums s_c = sum e'_k, sum e'_k^2 and the zero-mean samples' sum; the
+// row workgroups then take rho = min_c m_c, the factors
+// f_c = exp(-(m_c - rho)/lambda) (so f_c e'_k is the weight e_k up to
+// rounding), eta = sum_c f_c s_c, and the row's sum_c f_c sum_{k in c} e'_k
+// eps[r][k].
+constexpr int kWChunkBlock = 256;
+constexpr int kMaxWChunks = (1 << 20) / kWChunk;  // MPPI's sample limit
+
+__device__ __forceinline__ void chunk_weights(const float* __restrict__ S, int K,
+                                              float inv_lambda, float* __restrict__ e,
+                                              float4* __restrict__ part, int c, int n_plain) {
+  constexpr int NW = kWChunkBlock / kWave;
+  constexpr int kPer = kWChunk / kWChunkBlock;
+  __shared__ float lds[NW];
+  __shared__ float4 lds4[NW];
+  const float inf = __builtin_inff();
+  const int k0 = c * kWChunk + threadIdx.x;
+  float sv[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int k = k0 + j * kWChunkBlock;
+    sv[j] = k < K ? S[k] : inf;
+  }
+  float m = inf;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) m = fminf(m, sv[j]);
+  const float mc = block_min<NW>(m, lds);
+  float se = 0.0f, se2 = 0.0f, sz = 0.0f;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int k = k0 + j * kWChunkBlock;
+    if (k < K) {
+      const float ek = sv[j] < inf ? expf((mc - sv[j]) * inv_lambda) : 0.0f;
+      e[k] = ek;
+      se += ek;
+      se2 += ek * ek;
+      sz += k >= n_plain ? ek : 0.0f;
+    }
+  }
+  float4 v{wave_sum(se), wave_sum(se2), wave_sum(sz), 0.0f};
+  __syncthreads();
+  if (threadIdx.x % kWave == 0) lds4[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  v = lds4[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) { v.x += lds4[i].x; v.y += lds4[i].y; v.z += lds4[i].z; }
+  part[c] = float4{mc, v.x, v.y, v.z};
+}
+
+// Row r of the chunked update (kGemvBlock threads); row 0 records the
+// statistics and steps the iteration word.
+__device__ __forceinline__ void chunked_row(const float* __restrict__ eps, int64_t ldk, int K,
+                                           const float* __restrict__ e,
+                                           const float4* __restrict__ part, float lambda,
+                                           float inv_lambda, DevState* st,
+                                           float* __restrict__ u, float step, int r, int n_plain) {
+  constexpr int NW = kGemvBlock / kWave;
+  constexpr int kIn = 8;
+  constexpr int kStride = 4 * kGemvBlock;
+  __shared__ float fsc[kMaxWChunks];
+  __shared__ float lds[NW];
+  __shared__ float4 lds4[NW];
+  const int tid = threadIdx.x;
+  const float inf = __builtin_inff();
+  const int C = (K + kWChunk - 1) / kWChunk;
+  // rho, the chunk factors and the sums
+  float m = inf;
+  for (int c = tid; c < C; c += kGemvBlock) m = fminf(m, part[c].x);
+  const float rho = block_min<NW>(m, lds);
+  const bool finite = rho < inf;
+  float se = 0.0f, se2 = 0.0f, sz = 0.0f;
+  for (int c = tid; c < C; c += kGemvBlock) {
+    const float4 p = part[c];
+    const float f = (finite && p.x < inf) ? expf((rho - p.x) * inv_lambda) : 0.0f;
+    fsc[c] = f;
+    se += p.y * f;
+    se2 += p.z * (f * f);
+    sz += p.w * f;
+  }
+  float4 v{wave_sum(se), wave_sum(se2), wave_sum(sz), 0.0f};
+  __syncthreads();
+  if (tid % kWave == 0) lds4[tid / kWave] = v;
+  __syncthreads();  // also publishes fsc
+  v = lds4[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) { v.x += lds4[i].x; v.y += lds4[i].y; v.z += lds4[i].z; }
+  const float eta = v.x;
+  // the weighted row sum, eight 16-byte loads of the row and of e' in flight
+  const float* row = eps + static_cast<int64_t>(r) * ldk;
+  const int K4 = K & ~3;
+  float acc[kIn];
+#pragma unroll
+  for (int q = 0; q < kIn; ++q) acc[q] = 0.0f;
+  int k = 4 * tid;
+  for (; k + (kIn - 1) * kStride < K4; k += kIn * kStride) {
+    float4 x[kIn], w[kIn];
+#pragma unroll
+    for (int q = 0; q < kIn; ++q) {
+      x[q] = *reinterpret_cast<const float4*>(row + k + q * kStride);
+      w[q] = *reinterpret_cast<const float4*>(e + k + q * kStride);
+    }
+#pragma unroll
+    for (int q = 0; q < kIn; ++q)
+      acc[q] += fsc[(k + q * kStride) / kWChunk] *
+                (w[q].x * x[q].x + w[q].y * x[q].y + w[q].z * x[q].z + w[q].w * x[q].w);
+  }
+  for (; k < K4; k += kStride) {
+    const float4 x = *reinterpret_cast<const float4*>(row + k);
+    const float4 w = *reinterpret_cast<const float4*>(e + k);
+    acc[0] += fsc[k / kWChunk] * (w.x * x.x + w.y * x.y + w.z * x.z + w.w * x.w);
+  }
+  if (K4 + tid < K) acc[0] += fsc[(K4 + tid) / kWChunk] * (e[K4 + tid] * row[K4 + tid]);
+  const float a = wave_sum(((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                           ((acc[4] + acc[5]) + (acc[6] + acc[7])));
+  // (block_min's reads of lds are two barriers behind)
+  if (tid % kWave == 0) lds[tid / kWave] = a;
+  __syncthreads();
+  if (tid != 0) return;
+  float tot = lds[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) tot += lds[i];
+  const float wz = (finite && n_plain < K) ? v.z / eta : 0.0f;
+  if (eta > 0.0f) {
+    float qv = tot / eta;
+    if (wz != 0.0f) qv -= u[r] * wz;
+    u[r] = u[r] + step * qv;
+  }
+  if (r == 0) {
+    st->wz = wz;
+    st->stats[0] = rho;
+    st->stats[1] = finite ? eta : 0.0f;
+    st->stats[2] = finite ? rho - lambda * logf(eta / static_cast<float>(K)) : inf;
+    st->stats[3] = finite ? (eta * eta) / v.y : 0.0f;
+    st->status = finite ? MPPI_OK : MPPI_ENUMERIC;
+    st->iteration = st->iteration + 1u;
+  }
+}
+
 }  // namespace mppi

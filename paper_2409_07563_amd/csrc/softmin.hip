@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kGemvBlock) void one_pass_kernel(
 }
 
 // Blocks of the noise part for `threads` threads per workgroup.
-int noise_blocks(NoiseJob* job, int threads) {
+static int noise_blocks(NoiseJob* job, int threads) {
   job->kblocks = (job->K + threads - 1) / threads;
   const int ncall = (job->TM + 3) / 4;
   return job->kblocks * ((ncall + job->calls - 1) / job->calls);
@@ -106,6 +106,47 @@ hipError_t launch_update_one_pass(const float* d_S, const float* d_eps, int64_t 
   else if (nq <= 4) go(one_pass_kernel<4>);
   else if (nq <= 8) go(one_pass_kernel<8>);
   else go(one_pass_kernel<16>);
+  return hipGetLastError();
+}
+
+// The chunked update's weights step (workgroups 0 .. C-1) and, with a
+// next-noise job, the next iteration's noise (the workgroups after).
+__global__ __launch_bounds__(kWChunkBlock) void chunk_weights_kernel(
+    const float* __restrict__ S, int K, float inv_lambda, float* __restrict__ e,
+    float4* __restrict__ part, int n_plain, int C, NoiseJob job) {
+  if (static_cast<int>(blockIdx.x) < C) {
+    chunk_weights(S, K, inv_lambda, e, part, blockIdx.x, n_plain);
+    return;
+  }
+  next_noise(job, blockIdx.x - C);
+}
+
+__global__ __launch_bounds__(kGemvBlock) void chunked_rows_kernel(
+    const float* __restrict__ eps, int64_t ldk, int K, const float* __restrict__ e,
+    const float4* __restrict__ part, float lambda, float inv_lambda, DevState* __restrict__ st,
+    float* __restrict__ u, float step, int n_plain) {
+  chunked_row(eps, ldk, K, e, part, lambda, inv_lambda, st, u, step, blockIdx.x, n_plain);
+}
+
+hipError_t launch_update_chunked(const float* d_S, const float* d_eps, int64_t ldk, int K,
+                                 int TM, float lambda, float step, float* d_e, float4* d_part,
+                                 float* d_u, DevState* d_state, hipStream_t stream, int n_plain,
+                                 const NoiseJob* next) {
+  const int C = (K + kWChunk - 1) / kWChunk;
+  if (K < 1 || C > kMaxWChunks) return hipErrorInvalidValue;
+  const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
+  NoiseJob job{};
+  int blocks = C;
+  if (next) {
+    job = *next;
+    blocks += noise_blocks(&job, kWChunkBlock);
+  }
+  hipLaunchKernelGGL(chunk_weights_kernel, dim3(blocks), dim3(kWChunkBlock), 0, stream, d_S, K,
+                     inv_lambda, d_e, d_part, n_plain, C, job);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(chunked_rows_kernel, dim3(TM), dim3(kGemvBlock), 0, stream, d_eps, ldk, K,
+                     d_e, d_part, lambda, inv_lambda, d_state, d_u, step, n_plain);
   return hipGetLastError();
 }
 

@@ -1,10 +1,13 @@
-"""GPU parity of the two forms of steps (a3)-(a6) (Algorithm 1, Eq.
+"""GPU parity of the three forms of steps (a3)-(a6) (Algorithm 1, Eq.
 mppi_update_rule) against the oracle, through the C ABI: the two-pass update
-(a weights step, then one workgroup per row of the weighted noise sum) and the
+(a weights step, then one workgroup per row of the weighted noise sum), the
 single-pass update (every row's workgroup finds the baseline, the weights and
-the normaliser itself).  The update is isolated: both sides weight the same
-binary32 costs (the oracle's, set with mppi_set_costs) of the same noise.
-Sample counts span one to sixteen 1024-sample chunks with ragged tails, with
+the normaliser itself) and the chunked update (per-chunk weights against the
+chunk's own minimum, rescaled by the rows).  The update is isolated: both
+sides weight the same binary32 costs (the oracle's, set with mppi_set_costs)
+of the same noise.
+Sample counts span one to sixteen 1024-sample chunks with ragged tails (and,
+for the two-pass and chunked forms, up to 36 weights chunks of 2048), with
 and without zero-mean samples and importance sampling; non-finite costs, the
 statistics and the weights are checked too.
 """
@@ -67,14 +70,18 @@ def _update(mppi, wl, form, S32):
     return out
 
 
-SIZES = [1, 3, 64, 1000, 1023, 1025, 4097, 8192, 12345, 16384]
+SIZES = [1, 3, 64, 1000, 1023, 1025, 2049, 4097, 8192, 12345, 16384, 16385, 40000, 73001]
+FORMS = [0, 1, 2]
+FORM_IDS = ["two_pass", "one_pass", "chunked"]
 
 
 @pytest.mark.parametrize("options", [False, True], ids=["plain", "options"])
 @pytest.mark.parametrize("K", SIZES)
-@pytest.mark.parametrize("form", [0, 1], ids=["two_pass", "one_pass"])
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
 def test_update_forms_on_oracle_costs(mppi, oracle_lib, form, K, options):
-    wl = _workload(K, 12, K + 7 * options, options)
+    if form == 1 and K > 16384:
+        pytest.skip("the single-pass update stops at 16384 samples")
+    wl = _workload(K, 12 if K <= 16384 else 4, K + 7 * options, options)
     eps = oracle_lib.workload_noise(wl)
     S_or, _, _ = oracle_lib.rollout_costs(wl, eps=eps)
     S32 = S_or.astype(np.float32)
@@ -96,13 +103,14 @@ def test_update_forms_on_oracle_costs(mppi, oracle_lib, form, K, options):
     assert np.allclose(g["w"], w_or, rtol=1e-4, atol=1e-7)
 
 
-@pytest.mark.parametrize("form", [0, 1], ids=["two_pass", "one_pass"])
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
 def test_update_forms_with_non_finite_costs(mppi, oracle_lib, form):
-    wl = _workload(3001, 10, 5, False)
+    wl = _workload(5001, 10, 5, False)
     eps = oracle_lib.workload_noise(wl)
     S_or, _, _ = oracle_lib.rollout_costs(wl, eps=eps)
     S32 = S_or.astype(np.float32)
     S32[::7] = np.inf                              # crashed samples: weight 0
+    S32[2048:4096] = np.inf                        # a whole weights chunk
     g = _update(mppi, wl, form, S32)
     w_or, U_or, _, rc = oracle_lib.softmin_update(wl, S32.astype(np.float64), eps)
     assert rc == 0 and g["st"]["status"] == 0
@@ -118,18 +126,19 @@ def test_update_forms_with_non_finite_costs(mppi, oracle_lib, form):
 
 
 def test_update_forms_agree(mppi):
-    """Same costs, both forms: the controls differ only by rounding."""
+    """Same costs, every form: the controls differ only by rounding."""
     wl = _workload(8192, 100, 11, True)
     rng = np.random.default_rng(3)
     S32 = rng.gamma(2.0, 50.0, wl.K).astype(np.float32)
-    a, b = (_update(mppi, wl, f, S32) for f in (0, 1))
+    a, b, c = (_update(mppi, wl, f, S32) for f in FORMS)
     scale = np.abs(a["U"]).max()
-    assert np.abs(a["U"] - b["U"]).max() <= 1e-5 * scale
-    assert a["st"]["rho"] == b["st"]["rho"]
+    for o in (b, c):
+        assert np.abs(a["U"] - o["U"]).max() <= 1e-5 * scale
+        assert a["st"]["rho"] == o["st"]["rho"]
 
 
-@pytest.mark.parametrize("form", [0, 1], ids=["two_pass", "one_pass"])
-def test_sequences_in_both_forms(mppi, oracle_lib, form):
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+def test_sequences_in_every_form(mppi, oracle_lib, form):
     """Five warm-started iterations through the captured graph, the next
     iteration's noise drawn by each update's launch, equal bitwise to five
     single iterations of the same form and at parity with the oracle."""
@@ -152,17 +161,22 @@ def test_sequences_in_both_forms(mppi, oracle_lib, form):
                           oracle_lib.workload_noise(wl, iteration=4).view(np.uint32))
 
 
-def test_one_pass_refused_where_it_does_not_exist(mppi):
+def test_forms_refused_where_they_do_not_exist(mppi):
     from paper_2409_07563_amd import _abi
-    for ctl in (mppi.Controller(W.c2("circles", K=16385, T=10, iters=1)),
-                mppi.Controller([W.c2("circles", K=128, T=10), W.c2("circles", K=64, T=12)]),
+    for ctl in (mppi.Controller([W.c2("circles", K=128, T=10), W.c2("circles", K=64, T=12)]),
                 mppi.Controller(W.c5(K=128, T=10, hidden=16), requires_grad=True)):
         assert ctl.tuning()["update_form"] == 0
-        with pytest.raises(_abi.MPPIError):
-            ctl.set_tuning(update_form=1)
+        for form in (1, 2):
+            with pytest.raises(_abi.MPPIError):
+                ctl.set_tuning(update_form=form)
         ctl.close()
+    ctl = mppi.Controller(W.c2("circles", K=16385, T=10, iters=1))
+    assert ctl.tuning()["update_form"] == 2
+    with pytest.raises(_abi.MPPIError):
+        ctl.set_tuning(update_form=1)
+    ctl.close()
     ctl = mppi.Controller(W.c2("circles", K=16384, T=10, iters=1))
     assert ctl.tuning()["update_form"] == 1
     with pytest.raises(_abi.MPPIError):
-        ctl.set_tuning(update_form=2)
+        ctl.set_tuning(update_form=3)
     ctl.close()
