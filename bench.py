@@ -326,7 +326,9 @@ def bench_grad(args, wl):
         t_noise, t_roll, t_upd = phase_times(plain, args.kernel_reps)
         plain.close()
         grad = M.Controller(w, device=dev, requires_grad=True)
-        grad.set_tuning(**tuning)  # the same launch shapes as the plain forward
+        # the same launch shapes as the plain forward (the gradient mode has
+        # the two-pass update only: its adjoint reads the stored weights)
+        grad.set_tuning(**{k: v for k, v in tuning.items() if k != "update_form"})
         grad.iterate(1)
         G = (2.0 * (grad.controls() - uref)).contiguous()
         L = M.lib()

@@ -59,8 +59,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Per-instance workspace slice (byte offsets from the slice base, 256-aligned).
 struct Layout {
   int64_t ldk;  // noise row stride (K rounded up to a wave)
-  // single contexts: two noise buffers, so that an update can draw the next
-  // iteration's noise while the weighted sum still reads this one's
+  // single contexts whose two buffers fit the cache: two noise buffers, so
+  // that an update can draw the next iteration's noise while the weighted sum
+  // still reads this one's (eps2 == eps otherwise)
   size_t eps, eps2, e;
   size_t words;  // single contexts: the iteration word each noise buffer was drawn with
   size_t wpart;  // single contexts: the chunked update's per-chunk sums
@@ -273,6 +274,19 @@ bool split_form_for(const mppi_config* c, const mppi_params* p, bool batch) {
   return true;
 }
 
+// The next iteration's noise is drawn ahead by the update only while both
+// noise buffers fit in half of the 256 MiB last-level cache: beyond, the
+// second buffer's writes would evict the noise that the rollout has just read
+// and the weighted sum reads next (measured: the 210 MB buffers of a
+// K = 65536, T = 200, m = 4 problem lose more to HBM re-reads than the
+// overlap gains).
+constexpr size_t kDrawAheadMaxBytes = size_t(64) << 20;  // per buffer
+
+bool draw_ahead_for(int TM, int64_t ldk, bool batch) {
+  return !batch && sizeof(float) * static_cast<size_t>(TM) * static_cast<size_t>(ldk) <=
+                       kDrawAheadMaxBytes;
+}
+
 Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, bool batch) {
   (void)n;
   Layout L{};
@@ -281,7 +295,7 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   L.eps = take(sizeof(float) * (size_t)TM * L.ldk);
-  L.eps2 = batch ? L.eps : take(sizeof(float) * (size_t)TM * L.ldk);
+  L.eps2 = draw_ahead_for(TM, L.ldk, batch) ? take(sizeof(float) * (size_t)TM * L.ldk) : L.eps;
   L.words = take(2 * sizeof(uint32_t));
   L.wpart = take(sizeof(float4) * ((K + kWChunk - 1) / kWChunk));
   L.e = take(sizeof(float) * L.ldk);
@@ -409,6 +423,7 @@ struct Instance {
   DevParams dp;
   int lanes;   // lanes per sample of the single-instance rollout (1, 4, 8, 16)
   bool split;  // the split rollout form is available
+  bool ahead_ok;  // a second noise buffer: updates draw the next iteration's noise
   bool grad;   // MPPI_F_REQUIRES_GRAD
   int tape_cap;  // gradient mode: tape slots
   int hidden, ckpt_every, n_theta;
@@ -492,7 +507,13 @@ struct mppi_ctx {
   bool rollout_fresh = false;  // the costs are this iteration's rollout
   bool grad_ready = false;     // an update followed a fresh rollout
   bool tape_external = false;  // an update since the tape's reset used mppi_set_costs
-  std::map<int, hipGraphExec_t> graphs;  // mppi_iterate(I) launch sequences
+  // single contexts: the last mppi_iterate's final update drew the noise of
+  // the current iteration word into the other buffer, and nothing since has
+  // changed the word or the buffers (the next mppi_iterate starts from it)
+  bool ahead = false;
+  // mppi_iterate launch sequences, keyed by (iterations, first noise buffer,
+  // whether its noise was drawn ahead)
+  std::map<int64_t, hipGraphExec_t> graphs;
   mppi_tuning tune{};                     // launch shapes (lanes: instance 0's choice)
   ~mppi_ctx() { drop_graphs(); }
   void drop_graphs() {
@@ -558,6 +579,7 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
                 kMaxRolloutLds);
   // the split form's cost kernel also holds 16 x 64 partial sums and counts
   I->split = I->L.traj_words > 0 && lds_need + 2 * 16 * 64 * 4 <= kMaxRolloutLds;
+  I->ahead_ok = I->L.eps2 != I->L.eps;
   keep->emplace_back();
   std::vector<float4>& ref4 = keep->back();
   const int ref_len = p->ref ? p->ref_len : 1;
@@ -891,26 +913,22 @@ hipError_t phase_update(mppi_ctx* c, bool next = false) {
                                next ? &job : nullptr);
 }
 
-// Iteration i of n in mppi_iterate.  A single context draws the noise of
-// the first iteration only; each update but the last draws the next one's
-// into the other buffer.  The sequence starts from buffer 0 so that a
-// captured graph and a direct launch use the same buffers.
-hipError_t phase_iteration(mppi_ctx* c, int i, int n) {
+// Iteration i of mppi_iterate.  A single context with two noise buffers
+// draws the noise of the first iteration only, and not even that when it was
+// drawn ahead; every update draws the next iteration's noise into the other
+// buffer (after the last one, the noise of the next call's first iteration)
+// and switches buffers.  Other contexts sample in every iteration.
+hipError_t phase_iteration(mppi_ctx* c, int i, bool ahead) {
   hipError_t e = hipSuccess;
-  if (c->batch) {
+  if (c->batch || !c->one().ahead_ok) {
     e = phase_sample(c);
     if (e == hipSuccess) e = phase_rollout(c);
     return e == hipSuccess ? phase_update(c) : e;
   }
-  Instance& I = c->inst[0];
-  if (i == 0) {
-    I.cur = 0;
-    e = phase_sample(c);
-  }
+  if (i == 0 && !ahead) e = phase_sample(c);
   if (e == hipSuccess) e = phase_rollout(c);
-  if (e != hipSuccess || i + 1 == n) return e == hipSuccess ? phase_update(c) : e;
-  e = phase_update(c, true);
-  I.cur ^= 1;
+  if (e == hipSuccess) e = phase_update(c, true);
+  c->inst[0].cur ^= 1;
   return e;
 }
 
@@ -979,6 +997,7 @@ mppi_status mppi_get_tuning(const mppi_ctx* c, mppi_tuning* out) {
 
 mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
   if (!c || !t) return fail(MPPI_EINVAL, "ctx and t must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   auto shape = [](int v) { return v == 64 || v == 128 || v == 256; };
   if (!shape(t->rollout_block) || !shape(t->batch_tile))
     return fail(MPPI_EINVAL, "rollout_block and batch_tile must be 64, 128 or 256");
@@ -1036,6 +1055,7 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
 
 mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report_len) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   if (!c->have_state) return fail(MPPI_ESTATE, "mppi_set_state must come before mppi_autotune");
   if (reps < 1) reps = 1;
   std::string text;
@@ -1225,6 +1245,7 @@ mppi_status mppi_shift(mppi_ctx* c, int32_t steps, int32_t fill) {
 
 mppi_status mppi_set_iteration(mppi_ctx* c, uint32_t iteration) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   if (c->batch) {
     HIP_TRY(launch_batch_set_iteration(c->plan, iteration, c->stream));
   } else {
@@ -1235,6 +1256,7 @@ mppi_status mppi_set_iteration(mppi_ctx* c, uint32_t iteration) {
 
 mppi_status mppi_sample(mppi_ctx* c) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   HIP_TRY(phase_sample(c));
   c->have_noise = true;
   c->rollout_fresh = c->grad_ready = false;
@@ -1243,6 +1265,7 @@ mppi_status mppi_sample(mppi_ctx* c) {
 
 mppi_status mppi_rollout(mppi_ctx* c) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   if (!c->have_state) return fail(MPPI_ESTATE, "mppi_set_state must come before a rollout");
   if (!c->have_noise) return fail(MPPI_ESTATE, "mppi_sample must come before a rollout");
   hipError_t e = phase_rollout(c);
@@ -1254,6 +1277,7 @@ mppi_status mppi_rollout(mppi_ctx* c) {
 
 mppi_status mppi_set_costs(mppi_ctx* c, const float* d_costs) {
   if (!c || !d_costs) return fail(MPPI_EINVAL, "ctx and d_costs must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   HIP_TRY(hipMemcpyAsync(c->ws + c->C.S, d_costs, sizeof(float) * c->n_S, hipMemcpyDeviceToDevice,
                          c->stream));
   c->have_costs = true;
@@ -1263,6 +1287,7 @@ mppi_status mppi_set_costs(mppi_ctx* c, const float* d_costs) {
 
 mppi_status mppi_update(mppi_ctx* c) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   if (!c->have_noise || !c->have_costs)
     return fail(MPPI_ESTATE, "mppi_update needs noise and costs of the current iteration");
   hipError_t e = phase_update(c);
@@ -1276,23 +1301,42 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
   if (!c) return fail(MPPI_EINVAL, "ctx must not be NULL");
   if (num_iters < 1) return fail(MPPI_EINVAL, "num_iters must be >= 1");
   if (!c->have_state) return fail(MPPI_ESTATE, "mppi_set_state must come before mppi_iterate");
-  // the launch sequence of num_iters iterations, captured once and replayed
-  // (the null stream cannot be captured: launch directly there)
-  if (c->stream == nullptr) {
-    for (int i = 0; i < num_iters; ++i) {
-      hipError_t e = phase_iteration(c, i, num_iters);
-      if (e != hipSuccess) return hip_fail(e, "iteration launch");
-    }
+  // A single context's sequence starts in the buffer after the current one
+  // (holding noise drawn ahead, if any) and ends with the last iteration's
+  // noise current and the next call's drawn ahead in the other buffer.
+  const bool single = !c->batch && c->one().ahead_ok;
+  const bool ahead = single && c->ahead;
+  const int start = single ? c->inst[0].cur ^ 1 : 0;
+  const int last = start ^ ((num_iters - 1) & 1);
+  c->ahead = false;
+  auto finish = [&] {
+    if (single) c->inst[0].cur = last;
+    c->ahead = single;
     c->have_noise = c->have_costs = c->rollout_fresh = c->grad_ready = true;
     return MPPI_OK;
+  };
+  // the launch sequence of num_iters iterations, captured once and replayed
+  // (the null stream cannot be captured: launch directly there)
+  if (single) c->inst[0].cur = start;
+  if (c->stream == nullptr) {
+    for (int i = 0; i < num_iters; ++i) {
+      hipError_t e = phase_iteration(c, i, ahead);
+      if (e != hipSuccess) {
+        if (single) c->inst[0].cur = last;
+        return hip_fail(e, "iteration launch");
+      }
+    }
+    return finish();
   }
-  auto it = c->graphs.find(num_iters);
+  const int64_t key = static_cast<int64_t>(num_iters) * 4 + start * 2 + (ahead ? 1 : 0);
+  auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < num_iters && e == hipSuccess; ++i) e = phase_iteration(c, i, num_iters);
+    for (int i = 0; i < num_iters && e == hipSuccess; ++i) e = phase_iteration(c, i, ahead);
     const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+    if (single) c->inst[0].cur = last;
     if (e != hipSuccess || ec != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
       return hip_fail(e != hipSuccess ? e : ec, "iteration capture");
@@ -1301,12 +1345,10 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
     e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "graph instantiation");
-    it = c->graphs.emplace(num_iters, exec).first;
+    it = c->graphs.emplace(key, exec).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, c->stream));
-  if (!c->batch) c->inst[0].cur = (num_iters - 1) & 1;
-  c->have_noise = c->have_costs = c->rollout_fresh = c->grad_ready = true;
-  return MPPI_OK;
+  return finish();
 }
 
 mppi_status mppi_get_controls(mppi_ctx* c, float* d_U) {
@@ -1365,6 +1407,7 @@ int32_t mppi_theta_len(const mppi_ctx* c) {
 
 mppi_status mppi_set_theta(mppi_ctx* c, const float* host_theta) {
   if (!c || !host_theta) return fail(MPPI_EINVAL, "ctx and host_theta must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   if (c->batch || !c->one().grad)
     return fail(MPPI_ESTATE, "the context was created without MPPI_F_REQUIRES_GRAD");
   Instance& I = c->inst[0];
@@ -1412,6 +1455,7 @@ mppi_status mppi_backward_iters(mppi_ctx* c, const float* d_dL_dU, float* d_grad
                                 float* d_dL_du0) {
   if (!c || !d_dL_dU || !d_grad)
     return fail(MPPI_EINVAL, "ctx, d_dL_dU and d_grad must not be NULL");
+  c->ahead = false;  // the word or a noise buffer may change
   if (c->batch || !c->one().grad)
     return fail(MPPI_ESTATE, "the context was created without MPPI_F_REQUIRES_GRAD");
   if (c->tape_external)

@@ -63,6 +63,11 @@ def test_workspace_size_for_valid_configs(abi):
         # two noise buffers, the split form's trajectories (at most 16 words
         # per step and sample) and a few MiB of tables
         assert n < 2 * eps_bytes + 4 * wl.T * 16 * ldk + (8 << 20)
+    # above 64 MiB of noise a single context keeps one noise buffer: one more
+    # step of horizon past the threshold drops the second buffer
+    on, _ = _bytes(abi, W.c2("circles", K=8192, T=1024))   # 64 MiB per buffer
+    off, _ = _bytes(abi, W.c2("circles", K=8192, T=1025))
+    assert 0 < off < on - (60 << 20), (on, off)
 
 
 @pytest.mark.parametrize("override,needle", [

@@ -134,3 +134,63 @@ def test_backward_after_a_sequence(mppi):
     assert torch.equal(ga, gb)
     a.close()
     b.close()
+
+
+AHEAD_CASES = {
+    "c2": (lambda: W.c2("circles", K=1500, T=40), {}),
+    "c2_two_pass": (lambda: W.c2("circles", K=1500, T=40), dict(update_form=0)),
+    "c3_chunked": (lambda: W.c3(K=20000, T=20), {}),
+    "c5_grad": (lambda: W.c5(K=400, T=20, hidden=16).replace(lam=50.0), dict(grad=True)),
+}
+
+
+@pytest.mark.parametrize("name", list(AHEAD_CASES))
+def test_noise_drawn_ahead_across_calls(mppi, oracle_lib, name):
+    """An MPC loop (new state, one iteration, shift by one step) reads the noise
+    that the previous call's last update drew ahead; forcing a fresh draw in
+    every call (set_iteration to the same word) gives bitwise the same
+    controls, costs and noise, and the noise is the oracle's."""
+    make, shape = AHEAD_CASES[name]
+    wl = make()
+    shape = dict(shape)
+    grad = shape.pop("grad", False)
+    rng = np.random.default_rng(5)
+    states = [wl.x0 + rng.normal(0.0, 0.05, wl.x0.shape).astype(np.float32) for _ in range(4)]
+    runs = []
+    for fresh in (False, True):
+        c = mppi.Controller(wl, requires_grad=grad)
+        if shape:
+            c.set_tuning(**shape)
+        out = []
+        for i, x in enumerate(states):
+            c.set_state(x)
+            if fresh:
+                c.set_iteration(i)
+            c.iterate(1)
+            out.append([_np(getattr(c, n)()) for n in ("controls", "costs", "noise")])
+            c.shift(1)
+        assert c.stats()["iteration"] == len(states)
+        c.close()
+        runs.append(out)
+    for a, b in zip(*runs):
+        for x, y in zip(a, b):
+            assert np.array_equal(_bits(x), _bits(y))
+    for i, step in enumerate(runs[0]):
+        assert np.array_equal(_bits(step[2]), _bits(oracle_lib.workload_noise(wl, iteration=i)))
+
+
+def test_noise_drawn_ahead_is_dropped_by_a_new_word(mppi, oracle_lib):
+    wl = W.c2("circles", K=1000, T=30)
+    c = mppi.Controller(wl)
+    c.iterate(2)
+    c.set_iteration(7)
+    c.iterate(1)
+    assert np.array_equal(_bits(_np(c.noise())), _bits(oracle_lib.workload_noise(wl, iteration=7)))
+    # a staged update steps the word: the next sequence draws afresh
+    c.sample()
+    c.rollout()
+    c.update()
+    c.iterate(2)
+    assert c.stats()["iteration"] == 11
+    assert np.array_equal(_bits(_np(c.noise())), _bits(oracle_lib.workload_noise(wl, iteration=10)))
+    c.close()
