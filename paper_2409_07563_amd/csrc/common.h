@@ -66,6 +66,32 @@ constexpr int kMaxGridBytes = 64 * 1024;
 
 struct Sigma8 { float v[MPPI_MAX_CONTROL]; };
 
+// The next iteration's noise, drawn by extra workgroups of a rollout or update
+// launch into the other buffer with word *word_in + 1 (word_in: the word of
+// the buffer the launch reads), which they record in *word_out; kblocks is
+// filled in by the launcher.
+struct NoiseJob {
+  uint32_t key0, key1, instance;
+  const uint32_t* word_in;
+  uint32_t* word_out;
+  int K, T, TM;
+  Sigma8 sigma;
+  float* eps;
+  int64_t ldk;
+  const float* sigma_t;
+  int mean_sample;
+  int calls;
+  int kblocks;
+};
+
+// Workgroups of `threads` threads that draw a NoiseJob: kblocks sample blocks
+// times the Philox call groups (fills job->kblocks).
+inline int noise_job_blocks(NoiseJob* job, int threads) {
+  job->kblocks = (job->K + threads - 1) / threads;
+  const int ncall = (job->TM + 3) / 4;
+  return job->kblocks * ((ncall + job->calls - 1) / job->calls);
+}
+
 // Device-side scalars of a context.
 struct DevState {
   float stats[4];     // rho, eta, free energy, 1/sum w^2
@@ -133,7 +159,8 @@ bool rollout_quad_available(uint32_t dynamics, uint32_t integrator);
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                           bool accurate_trig, int lanes, const DevParams& p, const float* d_x0,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
-                          float* d_S, int32_t* d_crashes, hipStream_t stream, int block = 64);
+                          float* d_S, int32_t* d_crashes, hipStream_t stream, int block = 64,
+                          const NoiseJob* next = nullptr);
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
 
 // The split form of (a2) (split.hip): a dynamics kernel writes the states
@@ -178,22 +205,6 @@ constexpr int kOnePassMaxK = 16384;
 // Samples per workgroup of the chunked update's weights step.
 constexpr int kWChunk = 2048;
 
-// The next iteration's noise, drawn by the update's launch into the other
-// buffer with word *word_in + 1 (word_in: the word of the buffer the update
-// reads), which it records in *word_out; kblocks is filled in by the launcher.
-struct NoiseJob {
-  uint32_t key0, key1, instance;
-  const uint32_t* word_in;
-  uint32_t* word_out;
-  int K, T, TM;
-  Sigma8 sigma;
-  float* eps;
-  int64_t ldk;
-  const float* sigma_t;
-  int mean_sample;
-  int calls;
-  int kblocks;
-};
 hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t ldk, int K,
                                  int TM, float lambda, float step, float* d_e, float* d_u,
                                  DevState* d_state, hipStream_t stream, int n_plain,

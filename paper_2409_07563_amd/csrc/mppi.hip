@@ -840,7 +840,36 @@ hipError_t phase_sample(mppi_ctx* c) {
                       I.dp.mean_sample != 0, I.word(I.cur));
 }
 
-hipError_t phase_rollout(mppi_ctx* c) {
+// The next iteration's noise, into the buffer after the current one.
+NoiseJob next_noise_job(const mppi_ctx* c) {
+  const Instance& I = c->one();
+  NoiseJob job{};
+  job.key0 = static_cast<uint32_t>(I.cfg.seed);
+  job.key1 = static_cast<uint32_t>(I.cfg.seed >> 32);
+  job.instance = I.cfg.instance;
+  job.word_in = I.word(I.cur);
+  job.word_out = I.word(I.cur ^ 1);
+  job.K = I.K;
+  job.T = I.T;
+  job.TM = I.TM;
+  for (int j = 0; j < I.m; ++j) job.sigma.v[j] = I.cfg.sigma[j];
+  job.eps = I.eps_other();
+  job.ldk = I.L.ldk;
+  job.sigma_t = I.dp.sigma_t;
+  job.mean_sample = I.dp.mean_sample != 0;
+  job.calls = c->tune.noise_calls;
+  return job;
+}
+
+// The rollout launch that can also draw the next iteration's noise: the
+// fused kernels of a single context (not the MLP tiles or the split form).
+bool rollout_draws_noise(const mppi_ctx* c) {
+  const Instance& I = c->one();
+  return !c->batch && !(I.hidden || I.grad) && c->tune.rollout_form != MPPI_ROLLOUT_SPLIT;
+}
+
+// next: also draw the next iteration's noise (rollout_draws_noise only).
+hipError_t phase_rollout(mppi_ctx* c, bool next = false) {
   const Instance& I = c->one();
   const bool count = (I.cfg.flags & MPPI_F_DEBUG) && uses_circles(I.cfg.cost);
   const bool accurate = (I.cfg.flags & MPPI_F_ACCURATE_TRIG) != 0;
@@ -864,9 +893,11 @@ hipError_t phase_rollout(mppi_ctx* c) {
                                 I.at<float>(I.L.split_part), I.S, count ? I.crashes : nullptr,
                                 c->stream,
                                 c->tune.rollout_block, c->tune.cost_waves);
+  NoiseJob job{};
+  if (next) job = next_noise_job(c);
   return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.lanes, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
-                        c->stream, c->tune.rollout_block);
+                        c->stream, c->tune.rollout_block, next ? &job : nullptr);
 }
 
 // next: the weights launch also draws the next iteration's noise into the
@@ -884,22 +915,7 @@ hipError_t phase_update(mppi_ctx* c, bool next = false) {
     tape.cap = I.tape_cap;
   }
   NoiseJob job{};
-  if (next) {
-    job.key0 = static_cast<uint32_t>(I.cfg.seed);
-    job.key1 = static_cast<uint32_t>(I.cfg.seed >> 32);
-    job.instance = I.cfg.instance;
-    job.word_in = I.word(I.cur);
-    job.word_out = I.word(I.cur ^ 1);
-    job.K = I.K;
-    job.T = I.T;
-    job.TM = I.TM;
-    for (int j = 0; j < I.m; ++j) job.sigma.v[j] = I.cfg.sigma[j];
-    job.eps = I.eps_other();
-    job.ldk = I.L.ldk;
-    job.sigma_t = I.dp.sigma_t;
-    job.mean_sample = I.dp.mean_sample != 0;
-    job.calls = c->tune.noise_calls;
-  }
+  if (next) job = next_noise_job(c);
   if (c->tune.update_form == MPPI_UPDATE_ONE_PASS)
     return launch_update_one_pass(I.S, I.eps(), I.L.ldk, I.K, I.TM, I.cfg.lambda,
                                   step_size(I.cfg), I.u, I.st, c->stream, I.dp.n_plain,
@@ -926,8 +942,12 @@ hipError_t phase_iteration(mppi_ctx* c, int i, bool ahead) {
     return e == hipSuccess ? phase_update(c) : e;
   }
   if (i == 0 && !ahead) e = phase_sample(c);
-  if (e == hipSuccess) e = phase_rollout(c);
-  if (e == hipSuccess) e = phase_update(c, true);
+  // the next noise in the rollout's launch where it can go there (its
+  // workgroups fill the issue slots the latency-bound rollout leaves), else
+  // in the update's
+  const bool in_rollout = rollout_draws_noise(c);
+  if (e == hipSuccess) e = phase_rollout(c, in_rollout);
+  if (e == hipSuccess) e = phase_update(c, !in_rollout);
   c->inst[0].cur ^= 1;
   return e;
 }

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.h"
+
 namespace mppi {
 namespace noise {
 
@@ -145,4 +147,23 @@ __device__ __forceinline__ void emit_call(uint32_t key0, uint32_t key1, uint32_t
 }
 
 }  // namespace noise
+
+// Workgroup b of the noise part of a launch that also draws the next
+// iteration's noise: word *job.word_in + 1 (the word of the noise the launch
+// reads, plus one) into job.eps, samples (b mod kblocks) * blockDim .. and the
+// Philox calls (b / kblocks) * calls ..; workgroup 0 records the word in
+// *job.word_out for the launches after.
+__device__ __forceinline__ void next_noise(const NoiseJob& job, int b) {
+  const uint32_t it = *job.word_in + 1u;
+  if (b == 0 && threadIdx.x == 0) *job.word_out = it;
+  const int k = (b % job.kblocks) * static_cast<int>(blockDim.x) + threadIdx.x;
+  if (k >= job.K) return;
+  const int ncall = (job.TM + 3) / 4;
+  const int c0 = (b / job.kblocks) * job.calls;
+  const int m = job.TM / job.T;
+  for (int c = c0; c < c0 + job.calls && c < ncall; ++c)
+    noise::emit_call(job.key0, job.key1, it, job.instance, k, c, job.TM, m, job.sigma.v, job.eps,
+                     job.ldk, job.sigma_t, job.mean_sample && k == 0);
+}
+
 }  // namespace mppi

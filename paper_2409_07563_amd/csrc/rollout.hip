@@ -4,6 +4,7 @@
 // and the spline are staged once per workgroup into LDS, so no step waits on
 // a scalar or global load of them; the noise is requested a few steps ahead
 // of its use (NoiseAhead) so that its memory latency overlaps the arithmetic.
+#include "noise.h"
 #include "quad.h"
 #include "rollout.h"
 
@@ -17,7 +18,11 @@ template <class Model, int INTEG, class Cost, bool COUNT>
 __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
-    int32_t* __restrict__ crashes) {
+    int32_t* __restrict__ crashes, int rblocks, NoiseJob job) {
+  if (static_cast<int>(blockIdx.x) >= rblocks) {  // the next iteration's noise
+    next_noise(job, blockIdx.x - rblocks);
+    return;
+  }
   extern __shared__ float4 lds[];
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * Model::M, lds);
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,8 +70,12 @@ template <class Cost, bool FAST, bool COUNT, int L>
 __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
-    int32_t* __restrict__ crashes) {
+    int32_t* __restrict__ crashes, int rblocks, NoiseJob job) {
   static_assert(L == 4 || L == 8 || L == 16, "lanes per sample");
+  if (static_cast<int>(blockIdx.x) >= rblocks) {  // the next iteration's noise
+    next_noise(job, blockIdx.x - rblocks);
+    return;
+  }
   constexpr int N = 5, M = 2;
   extern __shared__ float4 lds[];
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
@@ -143,7 +152,7 @@ __global__ __launch_bounds__(kRolloutMaxBlock) void rollout_bicycle_group_kernel
 namespace {
 
 using RolloutFn = void (*)(DevParams, const float*, const float*, const float*, int64_t, int,
-                           int, float*, int32_t*);
+                           int, float*, int32_t*, int, NoiseJob);
 
 template <class Model, int INTEG, class Cost>
 RolloutFn pick(bool count) {
@@ -243,7 +252,8 @@ bool rollout_quad_available(uint32_t dynamics, uint32_t integrator) {
 hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                           bool accurate_trig, int lanes, const DevParams& p, const float* d_x0,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
-                          float* d_S, int32_t* d_crashes, hipStream_t stream, int block) {
+                          float* d_S, int32_t* d_crashes, hipStream_t stream, int block,
+                          const NoiseJob* next) {
   if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
   const bool count = d_crashes != nullptr;
   const bool group = lanes > 1;
@@ -262,9 +272,15 @@ hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
     if (e != hipSuccess) return e;
   }
   const int64_t threads = static_cast<int64_t>(K) * lanes_per_sample;
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>((threads + block - 1) / block)),
-                     dim3(block), lds, stream, p, d_x0, d_u, d_eps, ldk, K, T, d_S,
-                     d_crashes);
+  const int rblocks = static_cast<int>((threads + block - 1) / block);
+  NoiseJob job{};
+  int blocks = rblocks;
+  if (next) {
+    job = *next;
+    blocks += noise_job_blocks(&job, block);
+  }
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(block), lds, stream, p, d_x0,
+                     d_u, d_eps, ldk, K, T, d_S, d_crashes, rblocks, job);
   return hipGetLastError();
 }
 

@@ -30,24 +30,6 @@ __global__ __launch_bounds__(kWeightsBlock) void weights_kernel_one(
   weights_body(S, K, lambda, inv_lambda, e, st, n_plain, false);
 }
 
-// Noise workgroup b of a launch that also draws the next iteration's noise:
-// word *job.word_in + 1 (the word of the noise the launch's update reads, plus
-// one) into job.eps, samples (b mod kblocks) * blockDim .. and the Philox
-// calls (b / kblocks) * calls ..; workgroup 0 records the word in
-// *job.word_out for the launch after.
-__device__ __forceinline__ void next_noise(const NoiseJob& job, int b) {
-  const uint32_t it = *job.word_in + 1u;
-  if (b == 0 && threadIdx.x == 0) *job.word_out = it;
-  const int k = (b % job.kblocks) * static_cast<int>(blockDim.x) + threadIdx.x;
-  if (k >= job.K) return;
-  const int ncall = (job.TM + 3) / 4;
-  const int c0 = (b / job.kblocks) * job.calls;
-  const int m = job.TM / job.T;
-  for (int c = c0; c < c0 + job.calls && c < ncall; ++c)
-    noise::emit_call(job.key0, job.key1, it, job.instance, k, c, job.TM, m, job.sigma.v, job.eps,
-                     job.ldk, job.sigma_t, job.mean_sample && k == 0);
-}
-
 // The weights step of an iteration in workgroup 0 and, in the others, the
 // noise of the next iteration into the other noise buffer: two independent
 // pieces of work in one launch, so the latency-bound weights step and the
@@ -77,13 +59,6 @@ __global__ __launch_bounds__(kGemvBlock) void one_pass_kernel(
   next_noise(job, blockIdx.x - TM);
 }
 
-// Blocks of the noise part for `threads` threads per workgroup.
-static int noise_blocks(NoiseJob* job, int threads) {
-  job->kblocks = (job->K + threads - 1) / threads;
-  const int ncall = (job->TM + 3) / 4;
-  return job->kblocks * ((ncall + job->calls - 1) / job->calls);
-}
-
 hipError_t launch_update_one_pass(const float* d_S, const float* d_eps, int64_t ldk, int K,
                                   int TM, float lambda, float step, float* d_u,
                                   DevState* d_state, hipStream_t stream, int n_plain,
@@ -94,7 +69,7 @@ hipError_t launch_update_one_pass(const float* d_S, const float* d_eps, int64_t 
   int blocks = TM;
   if (next) {
     job = *next;
-    blocks += noise_blocks(&job, kGemvBlock);
+    blocks += noise_job_blocks(&job, kGemvBlock);
   }
   const int nq = (K + 4 * kGemvBlock - 1) / (4 * kGemvBlock);
   auto go = [&](auto kernel) {
@@ -139,7 +114,7 @@ hipError_t launch_update_chunked(const float* d_S, const float* d_eps, int64_t l
   int blocks = C;
   if (next) {
     job = *next;
-    blocks += noise_blocks(&job, kWChunkBlock);
+    blocks += noise_job_blocks(&job, kWChunkBlock);
   }
   hipLaunchKernelGGL(chunk_weights_kernel, dim3(blocks), dim3(kWChunkBlock), 0, stream, d_S, K,
                      inv_lambda, d_e, d_part, n_plain, C, job);
@@ -163,7 +138,7 @@ hipError_t launch_softmin_update(const float* d_S, const float* d_eps, int64_t l
   const float inv_lambda = static_cast<float>(1.0 / static_cast<double>(lambda));
   if (next) {
     NoiseJob job = *next;
-    const int blocks = 1 + noise_blocks(&job, kWeightsBlock);
+    const int blocks = 1 + noise_job_blocks(&job, kWeightsBlock);
     hipLaunchKernelGGL(weights_noise_kernel, dim3(blocks), dim3(kWeightsBlock), 0, stream, d_S,
                        K, lambda, inv_lambda, d_e, d_state, n_plain, tape, job);
   } else {
