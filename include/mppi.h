@@ -350,7 +350,17 @@ mppi_status mppi_update(mppi_ctx* ctx);
 /* (a7) num_iters >= 1 full iterations, warm-started (u <- U between them).
  * The launch sequence for a given num_iters is captured into a hipGraph on
  * first use and replayed afterwards (the context's stream must not be under
- * capture by the caller at that first call). */
+ * capture by the caller at that first call).
+ * Results are those of num_iters x (sample, rollout, update); the noise
+ * visible afterwards (MPPI_DEBUG_NOISE, mppi_backward) is the last
+ * iteration's.  A single context whose noise buffer is at most 64 MiB keeps a
+ * second one: each iteration's noise is drawn by a launch of the iteration
+ * before, and the last iteration draws the noise of the next call's first
+ * one, which that call then uses unless mppi_set_iteration, mppi_sample,
+ * mppi_rollout, mppi_set_costs, mppi_update, mppi_set_tuning, mppi_autotune,
+ * mppi_set_theta or mppi_backward_iters came in between (mppi_set_state,
+ * mppi_set_controls and mppi_shift keep it).  The noise is the same either
+ * way: it depends on the seed, the iteration word and the instance only. */
 mppi_status mppi_iterate(mppi_ctx* ctx, int32_t num_iters);
 
 /* d_U[T][m] <- current nominal controls (enqueued device copy). */

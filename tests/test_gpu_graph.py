@@ -75,6 +75,9 @@ def _with_options(wl, seed):
 SEQ_CASES = {
     "c3": (lambda: W.c3(K=700, T=40), {}),
     "c2_lanes1": (lambda: W.c2("circles", K=1100, T=60), dict(lanes_per_sample=1)),
+    "c2_lanes8": (lambda: W.c2("circles", K=1100, T=61), dict(lanes_per_sample=8)),
+    "c2_lanes16_costmap": (lambda: W.c2("costmap", K=1100, T=59), dict(lanes_per_sample=16)),
+    "c1_euler_lane": (lambda: W.c1(K=700, T=45).replace(integrator="euler"), {}),
     "c2_split": (lambda: W.c2("circles", K=1100, T=60),
                  dict(rollout_form=1, lanes_per_sample=4, cost_waves=8)),
     "c5_mlp": (lambda: W.c5(K=500, T=30, hidden=64), dict(rollout_block=128)),
