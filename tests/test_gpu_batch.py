@@ -109,3 +109,34 @@ def test_batch_full_size_sampled(mppi, oracle_lib):
         eps = oracle_lib.workload_noise(wl)[:, :, idx]
         S_or, margin, _ = oracle_lib.rollout_costs(wl.replace(K=len(idx)), eps=eps)
         parity.assert_costs_close(S[i][idx], S_or, margin, f"instance {i}")
+
+
+def test_batch_sequence_and_single_calls_agree(mppi, oracle_lib):
+    """A 3-iteration sequence, 3 single-iteration calls, and single iterations
+    each after a set_iteration to the same word: controls, costs and noise
+    are bitwise equal, and the visible noise is the oracle's for the last
+    word."""
+    insts = small_batch(n=7, kmax=600)
+    rng = np.random.default_rng(4)
+    insts = [w.replace(sigma_t=(np.asarray(w.sigma)[None, :] * rng.uniform(
+        0.5, 1.5, (w.T, w.m))).astype(np.float32), mean_sample=1) for w in insts]
+    outs = []
+    for mode in ("sequence", "calls", "fresh"):
+        ctl = mppi.Controller(insts)
+        if mode == "sequence":
+            ctl.iterate(3)
+        else:
+            for i in range(3):
+                if mode == "fresh":
+                    ctl.set_iteration(i)
+                ctl.iterate(1)
+        outs.append([_np(ctl.controls()), _np(ctl.costs()), _np(ctl.noise())])
+        assert all(s["iteration"] == 3 for s in ctl.stats())
+        ctl.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    eps = np.split(outs[0][2], np.cumsum([w.T * w.m * w.K for w in insts])[:-1])
+    for i, wl in enumerate(insts):
+        e_or = oracle_lib.workload_noise(wl, iteration=2)
+        assert np.array_equal(eps[i].view(np.uint32), e_or.ravel().view(np.uint32)), i
