@@ -101,14 +101,17 @@ def source_hash(*rel):
     return h.hexdigest()[:16]
 
 
-def traffic_record(kernel: str, workload: str):
+def traffic_record(kernel: str, workload: str, instance: str = ""):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
+    it was taken on the current kernel source and on the kernel instance
+    whose name contains `instance`; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("source_hash") != source_hash(*rec.get("sources", [])):
+        return None
+    if instance not in rec.get("kernel", ""):
         return None
     return rec.get("bytes_per_launch")
 
@@ -255,12 +258,17 @@ def main():
 
     ops = rollout_ops_per_step(wl) * steps_per_iter
     achieved = ops / t_roll
-    traffic = traffic_record("rollout", args.workload)
     split = ctl.tuning()["rollout_form"] == 1
+    lanes = ctl.tuning()["lanes_per_sample"]
+    # the counters were taken on one kernel instance: the grouped kernel's
+    # lane count is its last template argument
+    traffic = traffic_record("rollout", args.workload,
+                             f", {lanes}>" if lanes > 1 else "rollout_kernel<")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS,
                 "traffic": None if split else traffic,
-                "kernel": "split_dynamics + split_cost" if split else "rollout_kernel",
+                "kernel": ("split_dynamics + split_cost" if split else
+                           "rollout_bicycle_group_kernel" if lanes > 1 else "rollout_kernel"),
                 "ops_per_rollout_step": rollout_ops_per_step(wl), "launch_us": t_roll * 1e6}
     eps_bytes = 4 * wl.T * wl.m * wl.K
     kernels = {
