@@ -18,6 +18,15 @@ Tolerances (the target is 1e-4 relative in binary32):
     adjoint) is the first-order change of J_k when every state component is
     rounded once per step; a binary32 step rounds each component a few times
     (RK4 stages, the MLP's sums), COND_ULPS = 32 covers that with margin;
+  * chaotic samples: where nudging every noise input of the oracle by one
+    binary32 ulp (up, or down: a 6e-8 relative change) already moves a cost
+    by more than CHAOS_REL = 1e-2 relative, the amplification exceeds 1e5
+    and a first-order bound no longer describes what the GPU's own rounding
+    does (the MLP residual dynamics can diverge there): no single value is
+    the right one.  Such samples are exempt from the cost comparison (a GPU
+    cost must still not be NaN) and must be rare; where controls are
+    compared with the oracle's, they must also carry negligible weight
+    (below 1e-6 in all), so the controls' bound is unchanged (`chaotic`);
   * controls: |U_gpu - U_or| <= 1e-4 max(|U_or|_inf, |sigma|_inf) plus the
     change that the allowed cost deviation can cause through the softmin:
     sum_k |dU/dJ_k| 1e-4 max(|J_k|, 1), dU_t/dJ_k = -(gamma w_k/lambda)(eps_k,t -
@@ -30,6 +39,7 @@ REL = 1e-4
 AMBIGUOUS_MARGIN = 1e-3
 POS_EPS = 2.0 ** -24 * 100.0
 COND_ULPS = 32.0
+CHAOS_REL = 1e-2
 
 
 def cost_tol(S_or, cond=None):
@@ -50,12 +60,27 @@ def controls_tol(wl, S_or, w_or, eps, lam=None, cond=None):
     return REL * scale + prop
 
 
-def assert_costs_close(S_gpu, S_or, margin=None, name="", slope=None, cond=None):
+def chaotic(oracle_lib, wl, eps, S_or, u=None):
+    """Samples whose oracle cost moves by more than CHAOS_REL relative when
+    every noise input moves by one binary32 ulp (either direction)."""
+    tol = CHAOS_REL * np.maximum(np.abs(S_or), 1.0)
+    out = np.zeros(np.shape(S_or), bool)
+    for direction in (np.inf, -np.inf):
+        e = np.nextafter(np.asarray(eps, np.float32), np.float32(direction))
+        S = oracle_lib.rollout_costs(wl, e, u=u)[0]
+        out |= ~(np.abs(S - S_or) <= tol)
+    return out
+
+
+def assert_costs_close(S_gpu, S_or, margin=None, name="", slope=None, cond=None, skip=None):
     S_gpu = np.asarray(S_gpu, np.float64)
     tol = cost_tol(S_or, cond) if slope is None else cost_tol(S_or, cond) + POS_EPS * slope
     ok = np.abs(S_gpu - S_or) <= tol
     if margin is not None:
         ok |= margin < AMBIGUOUS_MARGIN
+    if skip is not None:
+        assert not np.isnan(S_gpu[skip]).any(), name
+        ok |= skip
     bad = np.flatnonzero(~ok)
     assert bad.size == 0, (
         f"{name}: {bad.size} costs off; first {bad[:5]}: gpu {S_gpu[bad[:5]]} "

@@ -90,8 +90,11 @@ def test_mlp_iterations_end_to_end(mppi, oracle_lib):
         U = _np(c.controls())
         S_or, _, _ = oracle_lib.rollout_costs(wl, eps, u=u)
         cond = oracle_lib.cost_condition(wl, eps, u=u)
-        parity.assert_costs_close(S, S_or, name=f"iteration {it}", cond=cond)
+        ch = parity.chaotic(oracle_lib, wl, eps, S_or, u=u)
+        assert ch.sum() <= wl.K // 20, ch.sum()
+        parity.assert_costs_close(S, S_or, name=f"iteration {it}", cond=cond, skip=ch)
         w_or, U_or, _, _ = oracle_lib.softmin_update(wl, S_or, eps, u=u)
+        assert w_or[ch].sum() < 1e-6  # their cost cannot move U by 1e-4
         tol = parity.controls_tol(wl, S_or, w_or, eps, cond=cond)
         parity.assert_controls_close(U, U_or, tol, name=f"iteration {it}")
         u = U.astype(np.float64)  # continue from the GPU's controls
@@ -181,7 +184,10 @@ def test_backward_full_size(mppi, oracle_lib, lam):
     S = _np(c.costs()).astype(np.float64)
     S_or = oracle_lib.rollout_costs(wl, eps)[0]
     cond = oracle_lib.cost_condition(wl, eps)
-    parity.assert_costs_close(S, S_or, name="c5 full size costs", cond=cond)
+    ch = parity.chaotic(oracle_lib, wl, eps, S_or)
+    assert ch.sum() <= wl.K // 20, ch.sum()
+    # (the gradient below is checked on the GPU's own costs)
+    parity.assert_costs_close(S, S_or, name="c5 full size costs", cond=cond, skip=ch)
     rel = np.maximum(1e-4, parity.COND_ULPS * 2.0 ** -24 * cond / np.maximum(np.abs(S_or), 1.0))
     ref = oracle_lib.backward(wl, G.astype(np.float64), eps=eps, S=S, rel=rel)
     _assert_grad_close(g, ref, name=f"c5 full size lambda={lam}", rel=rel)
