@@ -1,8 +1,8 @@
 // Device bodies of steps (a3)-(a6): baseline, normaliser, weights and control
 // update (arXiv 2409.07563, Algorithm 1 and Eq. mppi_update_rule), shared by
 // the single-instance kernels (softmin.hip) and the batched kernels
-// (batch.hip).  Two phases, both with a fixed reduction order (bitwise
-// reproducible):
+// (batch.hip).  Every reduction has a fixed order (bitwise reproducible).
+// The two-pass form:
 //  * weights: one workgroup per instance finds rho = min_k J_k, writes
 //    e_k = exp(-(J_k - rho)/lambda) (0 for a non-finite J_k), reduces
 //    eta = sum e_k and sum e_k^2, and records the statistics;
@@ -11,6 +11,9 @@
 //    its lanes stream the row with 16-byte loads along k (eight in flight per
 //    lane), accumulate privately, reduce once per wave and combine the four
 //    wave sums in a fixed order, so eps is read exactly once.
+// The single-pass form (one_pass_row) folds the weights into the row
+// workgroups; the chunked form (chunk_weights, chunked_row) spreads the
+// weights over workgroups of 2048 samples, each against its own minimum.
 #pragma once
 
 #include "common.h"

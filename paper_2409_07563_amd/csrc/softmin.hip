@@ -1,5 +1,6 @@
-// Steps (a3)-(a6) for one instance: the weights and weighted-noise kernels
-// (bodies in softmin.h), the weights for inspection and the iteration word.
+// Steps (a3)-(a6) for one instance in its three forms (two-pass, single-pass,
+// chunked; bodies in softmin.h), the launches that also draw the next
+// iteration's noise, the weights for inspection and the iteration word.
 #include "noise.h"
 #include "softmin.h"
 
