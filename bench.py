@@ -118,25 +118,26 @@ def traffic_record(kernel: str, workload: str, instance: str = ""):
 
 def phase_times(ctl, reps: int):
     """Average durations (s) of the sampling, rollout and update launches:
-    HIP events recorded on the library's stream around direct C-ABI calls."""
+    HIP events recorded on the library's stream around `reps` back-to-back
+    launches of each phase through the C ABI (so the dispatch latency of one
+    launch is not counted)."""
     import torch
     import paper_2409_07563_amd as M
     L, ctx, stream = M.lib(), ctl.ctx, ctl.stream
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    acc = [0.0, 0.0, 0.0]
-    torch.cuda.synchronize()
-    for _ in range(reps):
-        ev[0].record(stream)
-        M._abi.check(L.mppi_sample(ctx))
-        ev[1].record(stream)
-        M._abi.check(L.mppi_rollout(ctx))
-        ev[2].record(stream)
-        M._abi.check(L.mppi_update(ctx))
-        ev[3].record(stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = []
+    M._abi.check(L.mppi_sample(ctx))
+    M._abi.check(L.mppi_rollout(ctx))
+    for call in (L.mppi_sample, L.mppi_rollout, L.mppi_update):
+        M._abi.check(call(ctx))  # warm
         torch.cuda.synchronize()
-        for i in range(3):
-            acc[i] += ev[i].elapsed_time(ev[i + 1])
-    return tuple(a / reps * 1e-3 for a in acc)
+        ev[0].record(stream)
+        for _ in range(reps):
+            M._abi.check(call(ctx))
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        out.append(ev[0].elapsed_time(ev[1]) / reps * 1e-3)
+    return tuple(out)
 
 
 def rollout_forms(tuned):
