@@ -167,7 +167,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2_circles")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=None,
