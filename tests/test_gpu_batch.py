@@ -140,3 +140,27 @@ def test_batch_sequence_and_single_calls_agree(mppi, oracle_lib):
     for i, wl in enumerate(insts):
         e_or = oracle_lib.workload_noise(wl, iteration=2)
         assert np.array_equal(eps[i].view(np.uint32), e_or.ravel().view(np.uint32)), i
+
+
+@pytest.mark.parametrize("n", [2, 5, 9])
+def test_iteration_equals_staged_phases(mppi, n):
+    """mppi_iterate (the captured sequence), the staged calls and the
+    sequence with 64-sample tiles give bitwise the same controls and costs."""
+    insts = small_batch(n=n, kmax=900)
+    outs = []
+    for mode in ("iterate", "staged", "tile64"):
+        ctl = mppi.Controller(insts)
+        if mode == "tile64":
+            ctl.set_tuning(batch_tile=64)
+        for _ in range(2):
+            if mode == "staged":
+                ctl.sample()
+                ctl.rollout()
+                ctl.update()
+            else:
+                ctl.iterate(1)
+        outs.append([_np(ctl.controls()), _np(ctl.costs())])
+        ctl.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
