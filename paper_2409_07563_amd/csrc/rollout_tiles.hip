@@ -87,9 +87,13 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
 // through LDS (double-buffered by step parity, two barriers).  Every
 // per-element accumulation runs in the same order as in the one-wave kernel
 // (layer 2: K-steps (tt, i) in order; output: the K-tile partials summed 0,
-// 1, ..., MT-1), so the results are bitwise the same; the waves of a tile
-// repeat its bicycle step and cost.  More waves keep more SIMDs busy, and a
-// wave's matrix-core work overlaps another wave's VALU work.
+// 1, ..., MT-1), so the results are bitwise the same.  One leader wave per
+// tile (wave blockIdx mod SW, so that the leaders of the tiles spread over
+// the SIMDs) takes the bicycle step and the running cost and hands the new
+// state to the other waves through LDS at a third barrier: the step's VALU
+// work is done once per tile instead of SW times.  More waves keep more
+// SIMDs busy, and a wave's matrix-core work overlaps another wave's VALU
+// work.
 template <int MT, int SW, int INTEG, class Cost, bool FAST>
 __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
@@ -103,10 +107,12 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
   constexpr int N = Model::N, M = Model::M;
   __shared__ f4 xh[2][MT][kWave];  // h1 tiles
   __shared__ f4 xg[2][MT][kWave];  // output partials per K-tile
+  __shared__ float xs[kTile][8];   // the leader's new state of the tile's samples
   extern __shared__ float4 lds[];
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int n = lane % kTile, g = lane / kTile;
+  const bool leader = w == static_cast<int>(blockIdx.x % SW);
   const int k = blockIdx.x * kTile + n;
   const bool live = k < K;
   const bool plain = k < p.n_plain;  // drawn around u (else around zero)
@@ -151,7 +157,7 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
 #pragma unroll
     for (int j = 0; j < M; ++j) v[j] = mean * lds_u[t * M + j] + nz[j];
     if (ck && t == next_ckpt) {
-      if (w == 0 && g == 0 && live) {
+      if (leader && g == 0 && live) {  // the leader's compensation is current
 #pragma unroll
         for (int i = 0; i < N; ++i) ck[i * ldk] = x[i];
         ck[5 * ldk] = comp[0];
@@ -189,23 +195,38 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
       xg[par][q0 + q][lane] = part;
     }
     __syncthreads();
-    f4 out = xg[par][0][lane];
+    if (leader) {  // a wave-uniform branch
+      f4 out = xg[par][0][lane];
 #pragma unroll
-    for (int tt = 1; tt < MT; ++tt) out += xg[par][tt][lane];
-    float res[N];
-    mlp::broadcast5(out, n, res);
-    step<Model, INTEG>(x, v, comp, p, res);
-    bool hit;
-    float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
-    if (p.importance && plain) l += is_term<M>(p, t, v, lds_u + t * M);
-    if (p.cosines) l += inflation(p);
-    const float y = l - sum_c;
-    const float s = sum + y;
-    sum_c = (s - sum) - y;
-    sum = s;
+      for (int tt = 1; tt < MT; ++tt) out += xg[par][tt][lane];
+      float res[N];
+      mlp::broadcast5(out, n, res);
+      step<Model, INTEG>(x, v, comp, p, res);
+      bool hit;
+      float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
+      if (p.importance && plain) l += is_term<M>(p, t, v, lds_u + t * M);
+      if (p.cosines) l += inflation(p);
+      const float y = l - sum_c;
+      const float s = sum + y;
+      sum_c = (s - sum) - y;
+      sum = s;
+      if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) xs[n][i] = x[i];
+      }
+    }
+    // the others take the new state (xs is next written after the next
+    // step's second barrier, which every wave reaches after this read)
+    __syncthreads();
+    if (!leader) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[i] = xs[n][i];
+    }
   });
-  sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
-  if (w == 0 && g == 0 && live) S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
+  if (leader) {
+    sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
+    if (g == 0 && live) S[k] = __builtin_isfinite(sum) ? sum : __builtin_inff();
+  }
 }
 
 namespace {
