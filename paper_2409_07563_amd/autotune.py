@@ -2,8 +2,8 @@
 
 A choice is keyed by what decides it: the device architecture, the dynamics,
 integrator and cost, the number of samples rounded up to a power of two, the
-horizon, the MLP width, the number of batch instances and the cost's
-synthetic load (nested cosines).  The cache is a
+horizon, the MLP width, the number of batch instances, the cost's synthetic
+load (nested cosines) and gradient mode (which has its own launch shapes).  The cache is a
 JSON object {key: {"tuning": {...}, "timings": [...]}} written atomically.
 """
 from __future__ import annotations
@@ -34,7 +34,8 @@ def key(ctl, arch_name: str | None = None) -> str:
     return "|".join([arch_name or arch(ctl.device), pb.model, pb.integrator, pb.cost,
                      f"K{k_bucket(max(Ks))}", f"T{max(Ts)}", f"H{hidden}",
                      f"n{ctl.n_inst}", f"sumKT{k_bucket(sum(k * t for k, t in zip(Ks, Ts)))}",
-                     f"cos{int(getattr(pb, 'cost_cosines', 0))}"])
+                     f"cos{int(getattr(pb, 'cost_cosines', 0))}",
+                     f"grad{int(bool(getattr(ctl, 'requires_grad', False)))}"])
 
 
 def parse_report(text: str) -> list:

@@ -116,6 +116,7 @@ class Controller:
                  stream: torch.cuda.Stream | None = None, requires_grad: bool = False,
                  checkpoint_every: int = 10, tape_len: int = 16):
         self.device = torch.device(device)
+        self.requires_grad = bool(requires_grad)
         self.batch = isinstance(problem, (list, tuple))
         probs: Sequence = list(problem) if self.batch else [problem]
         self.problems = probs

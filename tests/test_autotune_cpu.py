@@ -12,15 +12,17 @@ def test_k_bucket():
 
 
 def test_key_separates_what_decides_the_choice():
-    def ctl(probs):
-        return types.SimpleNamespace(problems=probs, n_inst=len(probs), device="cuda:0")
+    def ctl(probs, grad=False):
+        return types.SimpleNamespace(problems=probs, n_inst=len(probs), device="cuda:0",
+                                     requires_grad=grad)
     a = A.key(ctl([W.c2("circles", K=8192)]), "gfx950")
     b = A.key(ctl([W.c2("circles", K=8000)]), "gfx950")   # same K bucket
     c = A.key(ctl([W.c2("circles", K=9000)]), "gfx950")
     d = A.key(ctl([W.c2("circles", K=8192, T=50)]), "gfx950")
     e = A.key(ctl([W.c2("circles", K=8192)]), "gfx942")
     f = A.key(ctl(W.c4(n_instances=3)), "gfx950")
-    assert a == b and len({a, c, d, e, f}) == 5
+    g = A.key(ctl([W.c2("circles", K=8192)], grad=True), "gfx950")
+    assert a == b and len({a, c, d, e, f, g}) == 6
     assert "H64" in A.key(ctl([W.c5()]), "gfx950")
 
 
