@@ -152,6 +152,25 @@ def rollout_forms(tuned):
     return best or None
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 10) -> float:
+    """Achievable HBM bandwidth (GB/s, read + write bytes) of a device-to-device
+    copy of `mib` MiB: the measured ceiling next to the 8 TB/s datasheet peak."""
+    import torch
+    a = torch.ones(mib << 18, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / reps * 1e-3
+    del a, b
+    return 2.0 * (mib << 20) / s / 1e9
+
+
 def cpu_baseline(wl, iters: int):
     import oracle
     t0 = time.perf_counter()
@@ -294,6 +313,7 @@ def main():
         "update_forms_ms_per_step": update_forms,
         "roofline": roofline,
         "kernels": kernels,
+        "achievable": {"hbm_copy_GBps": copy_bandwidth()},
     }
     ctl.close()
     if not args.no_cpu_baseline:
@@ -407,6 +427,7 @@ def bench_grad(args, wl):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, 1)
+    out["achievable"] = {"hbm_copy_GBps": copy_bandwidth()}
     print(json.dumps(out), flush=True)
 
 
@@ -475,6 +496,7 @@ def bench_batch(args, insts):
                     "rollout": {"us": tr * 1e6},
                     "softmin_update": {"us": tu * 1e6, "hbm_GBps": eps_bytes / tu / 1e9}},
     }
+    out["achievable"] = {"hbm_copy_GBps": copy_bandwidth()}
     print(json.dumps(out), flush=True)
 
 
