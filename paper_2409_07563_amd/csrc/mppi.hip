@@ -1495,19 +1495,25 @@ mppi_status mppi_backward_iters(mppi_ctx* c, const float* d_dL_dU, float* d_grad
   float* ckpt = I.at<float>(I.L.ckpt);
   DevState* scratch_state = I.at<DevState>(I.L.tape_state);
   HIP_TRY(hipMemcpyAsync(G, d_dL_dU, sizeof(float) * I.TM, hipMemcpyDeviceToDevice, c->stream));
+  // the last taped iteration is still in the buffers (noise, checkpoints,
+  // costs, weights) when its update came right after its rollout and nothing
+  // has run since
+  const bool last_in_place = c->grad_ready;
   for (int i = n - 1; i >= 0; --i) {
-    // rebuild iteration i from its tape entry: noise, checkpointing rollout, weights
     const float* u_i = I.at<float>(I.L.tape_u) + static_cast<int64_t>(i) * I.TM;
-    hipError_t e = launch_noise(I.cfg.seed, I.at<uint32_t>(I.L.tape_word) + i, 0u,
-                                I.cfg.instance, I.K, I.T, I.m, I.cfg.sigma, I.eps(), I.L.ldk,
-                                c->stream, c->tune.noise_calls, I.dp.sigma_t,
-                                I.dp.mean_sample != 0);
-    if (e == hipSuccess)
-      e = launch_rollout_tiles(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp, I.x0,
-                               u_i, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,
-                               c->stream, waves);
-    if (e == hipSuccess) e = launch_weights_only(I.S, I.K, I.cfg.lambda, I.e(), scratch_state,
-                                                 c->stream);
+    hipError_t e = hipSuccess;
+    if (!(i == n - 1 && last_in_place)) {
+      // rebuild iteration i from its tape entry: noise, checkpointing rollout, weights
+      e = launch_noise(I.cfg.seed, I.at<uint32_t>(I.L.tape_word) + i, 0u, I.cfg.instance, I.K,
+                       I.T, I.m, I.cfg.sigma, I.eps(), I.L.ldk, c->stream, c->tune.noise_calls,
+                       I.dp.sigma_t, I.dp.mean_sample != 0);
+      if (e == hipSuccess)
+        e = launch_rollout_tiles(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp,
+                                 I.x0, u_i, I.eps(), I.L.ldk, I.K, I.T, I.S, ckpt, I.ckpt_every,
+                                 c->stream, waves);
+      if (e == hipSuccess)
+        e = launch_weights_only(I.S, I.K, I.cfg.lambda, I.e(), scratch_state, c->stream);
+    }
     // then its reverse pass: grad (+)= sum_k a_k dJ_k/dtheta, G += sum_k a_k dJ_k/du_i
     if (e == hipSuccess)
       e = launch_adjoint(I.dp, accurate, I.hidden, G, u_i, I.eps(), I.L.ldk, I.K, I.T, I.e(),
