@@ -406,7 +406,7 @@ mppi_status mppi_set_theta(mppi_ctx* ctx, const float* host_theta);
  * skipped.  Binary32 throughout except the normaliser eta (binary64).
  * Enqueued on the context's stream; the result is bitwise reproducible.
  * Errors: EINVAL (NULL), ESTATE (no MPPI_F_REQUIRES_GRAD, or no update since
- * the last mppi_sample / mppi_set_costs), EDEVICE. */
+ * the last mppi_sample / mppi_rollout / mppi_set_costs), EDEVICE. */
 mppi_status mppi_backward(mppi_ctx* ctx, const float* d_dL_dU, float* d_grad);
 
 /* Gradient through every update since the tape started (the warm-started
@@ -418,7 +418,8 @@ mppi_status mppi_backward(mppi_ctx* ctx, const float* d_dL_dU, float* d_grad);
  * tape starts over at mppi_create, mppi_set_state, mppi_set_controls,
  * mppi_set_theta and mppi_shift.  The reverse pass runs the updates
  * backwards: it rebuilds update i (its noise from the recorded word, the
- * checkpointing rollout from the recorded u_i, the weights), adds the
+ * checkpointing rollout from the recorded u_i, the weights; the last update
+ * is taken from the buffers when mppi_backward could run), adds the
  * gradient of that iteration at fixed u_i, and carries dL/du_i = dL/du_{i+1} +
  * sum_k a_k dJ_k/du_i (the costs depend on u_i through v = u_i + eps and,
  * with MPPI_F_IMPORTANCE_SAMPLING, directly) to the next one.  With one

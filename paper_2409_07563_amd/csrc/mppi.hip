@@ -1292,6 +1292,7 @@ mppi_status mppi_rollout(mppi_ctx* c) {
   if (e != hipSuccess) return hip_fail(e, "rollout launch");
   c->have_costs = true;
   c->rollout_fresh = true;
+  c->grad_ready = false;  // the costs and checkpoints no longer match the last update
   return MPPI_OK;
 }
 
@@ -1459,7 +1460,7 @@ mppi_status mppi_backward(mppi_ctx* c, const float* d_dL_dU, float* d_grad) {
     return fail(MPPI_ESTATE, "the context was created without MPPI_F_REQUIRES_GRAD");
   if (!c->grad_ready)
     return fail(MPPI_ESTATE, "mppi_backward needs an update that followed this iteration's "
-                "rollout (none since the last mppi_sample or mppi_set_costs)");
+                "rollout (none since the last mppi_sample, mppi_rollout or mppi_set_costs)");
   const Instance& I = c->one();
   hipError_t e = launch_adjoint(I.dp, (I.cfg.flags & MPPI_F_ACCURATE_TRIG) != 0, I.hidden, d_dL_dU,
                                 I.at<float>(I.L.u_roll), I.eps(), I.L.ldk, I.K, I.T, I.e(),

@@ -308,6 +308,11 @@ def test_backward_state_errors(mppi):
     c.rollout()
     c.update()
     c.backward(G)
+    c.rollout()                      # the costs no longer those of the update
+    with pytest.raises(MPPIError, match="update"):
+        c.backward(G)
+    c.update()
+    c.backward(G)
     c.sample()
     with pytest.raises(MPPIError, match="update"):
         c.backward(G)

@@ -169,6 +169,32 @@ def test_one_taped_iteration_is_the_single_backward(mppi):
     ctl.close()
 
 
+def test_last_iteration_in_place_or_rebuilt(mppi):
+    """The reverse pass takes the last update from the buffers when they still
+    hold it and rebuilds it otherwise (a second reverse pass, or a rollout
+    after the update): the gradients agree bitwise."""
+    from paper_2409_07563_amd import _abi
+    wl = _c5(600, 24, 32).replace(lam=50.0)
+    uref = W.c5_uref(T=24)
+    ctl = mppi.Controller(wl, requires_grad=True)
+    ctl.iterate(3)
+    U = _np(ctl.controls())
+    G = (2.0 * (U - uref)).astype(np.float32)
+    first = [_np(x) for x in ctl.backward_iters(G)]      # last update in place
+    again = [_np(x) for x in ctl.backward_iters(G)]      # all three rebuilt
+    ctl.close()
+    other = mppi.Controller(wl, requires_grad=True)
+    other.iterate(3)
+    other.rollout()                                      # costs of the new controls
+    with pytest.raises(_abi.MPPIError):
+        other.backward(G)
+    rebuilt = [_np(x) for x in other.backward_iters(G)]
+    other.close()
+    for a, b, c in zip(first, again, rebuilt):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+
+
 def test_backward_iters_end_to_end(mppi, oracle_lib):
     wl = _c5(1024, 30, 64).replace(lam=50.0)
     uref = W.c5_uref(T=30)
