@@ -38,7 +38,7 @@
 namespace mppi {
 
 constexpr int kTileS = 16;           // samples per sweep tile (one wave)
-constexpr int kProjectBlock = 256;   // 64 samples x 4 row groups
+constexpr int kProjectBlock = 1024;  // 16 quads of 4 samples x 64 row groups
 constexpr int kProjectSamples = 64;
 
 struct BwdBlock {
@@ -57,19 +57,41 @@ struct BwdItem {
   float a;
 };
 
+// g_k = sum_r G_r eps_k[r] for the 64 samples of a workgroup: each thread
+// reads four adjacent samples (one 16-byte load; ldk is a multiple of 64) of
+// every 64th row, and the 64 row-group partials are added in a fixed order.
 __global__ __launch_bounds__(kProjectBlock) void adjoint_project_kernel(
     const float* __restrict__ G, const float* __restrict__ eps, int64_t ldk, int K, int TM,
     const float* __restrict__ e, float* __restrict__ gk, BwdBlock* __restrict__ part) {
-  __shared__ float red[kProjectBlock];
-  const int s = threadIdx.x % kProjectSamples, rg = threadIdx.x / kProjectSamples;
-  const int k = blockIdx.x * kProjectSamples + s;
-  float acc = 0.0f;
-  if (k < K)
-    for (int r = rg; r < TM; r += 4) acc += G[r] * eps[static_cast<int64_t>(r) * ldk + k];
-  red[threadIdx.x] = acc;
+  constexpr int kQuads = kProjectSamples / 4;
+  constexpr int kRowGroups = kProjectBlock / kQuads;
+  __shared__ float red[kProjectBlock * 4];  // [row group][sample]
+  const int q = threadIdx.x % kQuads, rg = threadIdx.x / kQuads;
+  const int k0 = blockIdx.x * kProjectSamples + 4 * q;
+  float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (k0 < K) {
+    const float4* col = reinterpret_cast<const float4*>(eps + k0);
+    const int64_t ld4 = ldk / 4;
+    for (int r = rg; r < TM; r += kRowGroups) {
+      const float gr = G[r];
+      const float4 v = col[r * ld4];
+      acc.x += gr * v.x;
+      acc.y += gr * v.y;
+      acc.z += gr * v.z;
+      acc.w += gr * v.w;
+    }
+  }
+  float* mine = red + rg * kProjectSamples + 4 * q;
+  mine[0] = acc.x;
+  mine[1] = acc.y;
+  mine[2] = acc.z;
+  mine[3] = acc.w;
   __syncthreads();
-  if (rg == 0) {
-    const float g = (red[s] + red[s + 64]) + (red[s + 128] + red[s + 192]);
+  if (threadIdx.x < kProjectSamples) {
+    const int s = threadIdx.x;
+    const int k = blockIdx.x * kProjectSamples + s;
+    float g = 0.0f;
+    for (int i = 0; i < kRowGroups; ++i) g += red[i * kProjectSamples + s];
     const float ek = k < K ? e[k] : 0.0f;
     if (k < K) gk[k] = g;
     // per-block sums over the 64 samples (one wave, fixed shuffle tree)
@@ -92,22 +114,40 @@ __global__ __launch_bounds__(kScanBlock) void adjoint_scan_kernel(
   __shared__ double s_eta;
   __shared__ float s_gref;
   __shared__ float red[kScanBlock / kWave];
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < kWave) {
+    // the first wave scans the block counts 64 at a time (exclusive offsets)
+    // and sums eta per lane, then over the lanes in a fixed tree
+    const int lane = threadIdx.x;
     double eta = 0.0;
     int count = 0, kmin = 0x7FFFFFFF;
-    for (int b = 0; b < nb; ++b) {
-      const BwdBlock q = part[b];
-      offs[b] = count;
-      count += q.count;
+    for (int b0 = 0; b0 < nb; b0 += kWave) {
+      const int b = b0 + lane;
+      BwdBlock q{0.0, 0, 0x7FFFFFFF};
+      if (b < nb) q = part[b];
+      int incl = q.count;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+      }
+      if (b < nb) offs[b] = count + incl - q.count;
+      count += __shfl(incl, kWave - 1, kWave);
       eta += q.sum_e;
       kmin = min(kmin, q.kmin);
     }
-    const bool ok = eta > 0.0 && kmin < K;
-    s_eta = ok ? eta : 0.0;
-    s_gref = ok ? gk[kmin] : 0.0f;
-    meta->eta = s_eta;
-    meta->gref = s_gref;
-    meta->count = ok ? count : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      eta += __shfl_xor(eta, o, kWave);
+      kmin = min(kmin, __shfl_xor(kmin, o, kWave));
+    }
+    if (lane == 0) {
+      const bool ok = eta > 0.0 && kmin < K;
+      s_eta = ok ? eta : 0.0;
+      s_gref = ok ? gk[kmin] : 0.0f;
+      meta->eta = s_eta;
+      meta->gref = s_gref;
+      meta->count = ok ? count : 0;
+    }
   }
   __syncthreads();
   // d = sum_i e_i (g_i - g_ref) / eta, fixed partition and tree
