@@ -149,7 +149,10 @@ def _assert_grad_close(g, ref, name="", rel=None):
 @pytest.mark.parametrize("H,K,T,ce,lam", [
     (64, 1024, 40, 10, 0.5), (64, 1024, 40, 10, 50.0), (16, 700, 33, 10, 50.0),
     (32, 256, 20, 7, 5.0), (64, 100, 23, 1, 50.0), (64, 333, 50, 64, 0.5),
-    (64, 333, 50, 64, 50.0), (0, 1000, 50, 10, 0.5), (0, 1000, 50, 10, 50.0)])
+    (64, 333, 50, 64, 50.0), (0, 1000, 50, 10, 0.5), (0, 1000, 50, 10, 50.0),
+    # more than 64 blocks of 64 samples, the last one ragged (the scan's second
+    # chunk and the projection's partial quad of samples)
+    (64, 5001, 20, 10, 0.5), (16, 4162, 24, 8, 50.0)])
 def test_backward_vs_oracle(mppi, oracle_lib, H, K, T, ce, lam):
     wl = _c5(K, T, H if H else 16).replace(lam=lam)
     if H == 0:
