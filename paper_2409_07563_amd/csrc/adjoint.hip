@@ -634,11 +634,24 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
     for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
     comp[0] = ck[5 * ldk];
     comp[1] = ck[6 * ldk];
+    // u and the noise of a step are requested one step ahead, so their
+    // latency hides behind the previous step's work (barriers wait for LDS
+    // only, not for these loads)
+    float un[M], en[M];
+    auto fetch_v = [&](int t) {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        un[q] = u[t * M + q];
+        en[q] = e[static_cast<int64_t>(t * M + q) * ldk];
+      }
+    };
+    fetch_v(t0);
     for (int j = 0; j < len; ++j) {
       const int t = t0 + j;
       float v[M];
 #pragma unroll
-      for (int q = 0; q < M; ++q) v[q] = u[t * M + q] + e[static_cast<int64_t>(t * M + q) * ldk];
+      for (int q = 0; q < M; ++q) v[q] = un[q] + en[q];
+      if (j + 1 < len) fetch_v(t + 1);
       if (w == 0 && g == 0) {
 #pragma unroll
         for (int i = 0; i < N; ++i) xs[j * N + i] = x[i];
@@ -698,9 +711,34 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
         gQ[i] += a * p.w[16] * d * d;
       }
     }
+    // the reference state after the step and the step's MLP pre-activations,
+    // requested one step ahead like the forward's noise
+    float rn[N];
+    f4 pn1[TW], pn2[TW];
+    auto fetch_r = [&](int j) {
+      const float* r = p.ref + static_cast<int64_t>(t0 + j + 1) * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) rn[i] = r[i];
+      const f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        pn1[q] = ps[(q0 + q) * kWave];
+        pn2[q] = ps[(MT + q0 + q) * kWave];
+      }
+    };
+    fetch_r(len - 1);
     for (int j = len - 1; j >= 0; --j) {
       const int t = t0 + j;
-      const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
+      float r[N];
+      f4 pa1[TW], pa2[TW];
+#pragma unroll
+      for (int i = 0; i < N; ++i) r[i] = rn[i];
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        pa1[q] = pn1[q];
+        pa2[q] = pn2[q];
+      }
+      if (j > 0) fetch_r(j - 1);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         const float d = xs[(j + 1) * N + i] - r[i];
@@ -716,13 +754,10 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
       rk4_vjp<FAST>(p, xt, v, mu, mu0, gL, dv);
       // the MLP residual dt g(z): c = dt mu_{t+1}
       f4 h1[TW], d1[TW], h2[TW], d2[TW];
-      {
-        const f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
 #pragma unroll
-        for (int q = 0; q < TW; ++q) {
-          mlp::tanh4_d(ps[(q0 + q) * kWave], h1[q], d1[q]);
-          mlp::tanh4_d(ps[(MT + q0 + q) * kWave], h2[q], d2[q]);
-        }
+      for (int q = 0; q < TW; ++q) {
+        mlp::tanh4_d(pa1[q], h1[q], d1[q]);
+        mlp::tanh4_d(pa2[q], h2[q], d2[q]);
       }
       float cg[N];
 #pragma unroll
