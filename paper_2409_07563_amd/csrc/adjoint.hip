@@ -356,11 +356,22 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
     for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
     comp[0] = ck[5 * ldk];
     comp[1] = ck[6 * ldk];
+    // u and the noise of a step are requested one step ahead
+    float un[M], en[M];
+    auto fetch_v = [&](int t) {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        un[q] = u[t * M + q];
+        en[q] = e[static_cast<int64_t>(t * M + q) * ldk];
+      }
+    };
+    fetch_v(t0);
     for (int j = 0; j < len; ++j) {
       const int t = t0 + j;
       float v[M];
 #pragma unroll
-      for (int q = 0; q < M; ++q) v[q] = u[t * M + q] + e[static_cast<int64_t>(t * M + q) * ldk];
+      for (int q = 0; q < M; ++q) v[q] = un[q] + en[q];
+      if (j + 1 < len) fetch_v(t + 1);
       if (g == 0) {
 #pragma unroll
         for (int i = 0; i < N; ++i) xs[j * N + i] = x[i];
@@ -396,10 +407,21 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
         gQ[i] += a * p.w[16] * d * d;
       }
     }
+    // the reference state after each step, requested one step ahead
+    float rn[N];
+    auto fetch_r = [&](int j) {
+      const float* r = p.ref + static_cast<int64_t>(t0 + j + 1) * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) rn[i] = r[i];
+    };
+    fetch_r(len - 1);
     for (int j = len - 1; j >= 0; --j) {
       const int t = t0 + j;
       // running cost at x_{t+1}
-      const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
+      float r[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) r[i] = rn[i];
+      if (j > 0) fetch_r(j - 1);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         const float d = xs[(j + 1) * N + i] - r[i];
