@@ -283,13 +283,19 @@ __device__ __forceinline__ float group_sum(float v) {
 // derivative in u through v = u + eps and directly (lambda Sigma^-1 v) are
 // added, then the 16 samples of the tile are summed (fixed xor tree) and
 // lane 0 writes out[0..1].  Every lane of the wave must call it.
-__device__ __forceinline__ void du_step(const DevParams& p, int t, float a, const float* v,
-                                        float* dv, int lane, float* out) {
-  const float* cf = p.is_coef_t ? p.is_coef_t + 2 * t : p.is_coef;
+// ic: the constant importance coefficients, read once per kernel by the caller.
+__device__ __forceinline__ void du_step(const DevParams& p, const float* ic, int t, float a,
+                                        const float* v, float* dv, int lane, float* out) {
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     float d = dv[q] + a * (2.0f * p.w[8 + q] * v[q]);
-    if (p.importance) d += a * (cf[q] * v[q]);
+    if (p.importance) {
+      // a branch, not a pointer select: a pointer that may name the
+      // by-value array becomes a generic (flat) load, whose wait also drains
+      // the loads the sweep requests ahead
+      const float cq = p.is_coef_t ? p.is_coef_t[2 * t + q] : ic[q];
+      d += a * (cq * v[q]);
+    }
     const float sum = group_sum(d);
     if (lane == 0) out[q] = sum;
   }
@@ -345,6 +351,7 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) { db3[i] = 0.0f; gQ[i] = 0.0f; mu[i] = 0.0f; }
+  const float ic[2] = {p.is_coef[0], p.is_coef[1]};
 
   const int nseg = (T + c - 1) / c;
   for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -502,7 +509,7 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
         __syncthreads();
       }
       if (du_off >= 0)
-        du_step(p, t, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
+        du_step(p, ic, t, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
 #pragma unroll
       for (int i = 0; i < N; ++i) mu[i] = mu0[i];
     }
@@ -645,6 +652,7 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
   float db3[N], gQ[N], gL = 0.0f, mu[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { db3[i] = 0.0f; gQ[i] = 0.0f; mu[i] = 0.0f; }
+  const float ic[2] = {p.is_coef[0], p.is_coef[1]};
   int par = 0;
 
   const int nseg = (T + c - 1) / c;
@@ -869,7 +877,7 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
       }
       __syncthreads();  // the transposition buffer is rewritten by the next step
       if (du_off >= 0 && w == 0)
-        du_step(p, t, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
+        du_step(p, ic, t, a, v, dv, lane, partial + blockIdx.x * ngp + du_off + t * M);
 #pragma unroll
       for (int i = 0; i < N; ++i) mu[i] = mu0[i];
     }
