@@ -784,6 +784,28 @@ double orc_sequence_cost(const orc_problem* P, const double* x0,
   return J + terminal_cost(P, x);
 }
 
+/* Test support for orc_cost_condition: the cost of one control sequence with
+ * delta added to component i of x_s (the state after step s, 1 <= s <= T)
+ * right after the step that produces it, before its running cost (and, for
+ * s = T, the terminal cost) is charged; the perturbation then propagates
+ * through every later step.  Central differences of this function in delta
+ * give dJ/dx_{s,i}, the sensitivities that orc_cost_condition forms with its
+ * adjoint. */
+double orc_sequence_cost_injected(const orc_problem* P, const double* x0, const double* v_seq,
+                                  int32_t s, int32_t i, double delta) {
+  const int n = P->n, m = P->m;
+  double x[16], mg = INFINITY, sl = 0.0;
+  int cr = 0;
+  for (int q = 0; q < n; ++q) x[q] = x0[q];
+  double J = 0.0;
+  for (int32_t t = 0; t < P->T; ++t) {
+    orc_step(P, x, v_seq + t * m);
+    if (t + 1 == s) x[i] += delta;
+    J += running_cost(P, x, v_seq + t * m, t, &mg, &cr, &sl);
+  }
+  return J + terminal_cost(P, x);
+}
+
 /* Single-point evaluations used by unit tests of the model and cost pieces. */
 double orc_eval_running_cost(const orc_problem* P, const double* x,
                              const double* v, int32_t t) {

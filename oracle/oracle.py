@@ -94,6 +94,8 @@ def lib():
         L.orc_trajectory.argtypes = [P, f64p, f64p, f64p]
         L.orc_sequence_cost.argtypes = [P, f64p, f64p]
         L.orc_sequence_cost.restype = C.c_double
+        L.orc_sequence_cost_injected.argtypes = [P, f64p, f64p, C.c_int32, C.c_int32, C.c_double]
+        L.orc_sequence_cost_injected.restype = C.c_double
         L.orc_eval_running_cost.argtypes = [P, f64p, f64p, C.c_int32]
         L.orc_eval_running_cost.restype = C.c_double
         L.orc_eval_terminal_cost.argtypes = [P, f64p]
@@ -410,6 +412,14 @@ def sequence_cost(wl, v_seq, x0=None, **override):
                                    _d(v_seq).ravel())
 
 
+def sequence_cost_injected(wl, v_seq, s: int, i: int, delta: float, x0=None):
+    """Cost of one control sequence with delta added to component i of the
+    state after step s (1 <= s <= T) before that state's cost is charged."""
+    P = Problem(wl)
+    return lib().orc_sequence_cost_injected(P.ref, _d(wl.x0 if x0 is None else x0),
+                                            _d(v_seq).ravel(), int(s), int(i), float(delta))
+
+
 def running_cost(wl, x, v, t=0):
     P = Problem(wl)
     return lib().orc_eval_running_cost(P.ref, _d(x), _d(v), t)
@@ -436,4 +446,4 @@ __all__ = ["philox", "bm_tables", "noise", "workload_noise", "rollout_costs",
            "softmin_update", "mppi", "step", "deriv", "trajectory", "sequence_cost",
            "running_cost", "terminal_cost", "spline", "costmap", "Problem", "n_grad",
            "backward", "with_theta", "theta_of", "loss_and_controls",
-           "cost_condition", "shift", "backward_iters"]
+           "cost_condition", "shift", "backward_iters", "sequence_cost_injected"]
