@@ -11,8 +11,12 @@
 #include "noise.h"
 #include "rollout.h"
 #include "softmin.h"
+#include "worklist.h"
 
 namespace mppi {
+
+static_assert(sizeof(WorkItem) == sizeof(int2) && alignof(WorkItem) <= alignof(int2),
+              "work lists are uploaded as int2 tables");
 
 // (a1) every normal of a tile's samples; one thread per sample loops
 // over the Philox calls of its sample, each call storing four coalesced rows.
@@ -60,6 +64,9 @@ __global__ __launch_bounds__(kGemvBlock) void batch_gemv_kernel(const BatchInst*
                                                                 const int2* __restrict__ tiles) {
   const int2 tl = tiles[blockIdx.x];
   const BatchInst& b = insts[tl.x];
+  // the host checks every row tile against T*m before the upload; a row past
+  // the instance's would read and write another instance's buffers
+  if (tl.y >= b.TM) return;  // uniform over the workgroup: no barrier is skipped by part of it
   gemv_row(b.eps, b.ldk, b.K, b.e, b.st, b.u, b.step, tl.y, false);
 }
 

@@ -15,6 +15,7 @@
 
 #include "common.h"
 #include "mlp.h"
+#include "worklist.h"
 
 using namespace mppi;
 
@@ -686,23 +687,26 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
 }
 
 // The sample tiles of a batch, `tile` samples each, longest horizon first
-// (stable: instance order within a horizon).  Uploads and waits.
-hipError_t upload_sample_tiles(mppi_ctx* c, int tile) {
+// (stable: instance order within a horizon).  Checked against the instances'
+// sample counts and the table's capacity before the upload (the launch grid
+// is the checked length); uploads and waits.
+mppi_status upload_sample_tiles(mppi_ctx* c, int tile) {
   const int n_inst = static_cast<int>(c->inst.size());
-  std::vector<int> order(n_inst);
-  for (int i = 0; i < n_inst; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return c->inst[a].T > c->inst[b].T; });
-  std::vector<int2> tiles;
-  for (int i : order)
-    for (int t = 0; t * tile < c->inst[i].K; ++t) tiles.push_back(int2{i, t});
-  hipError_t e = hipMemcpyAsync(c->ws + c->C.sample_tiles, tiles.data(), sizeof(int2) * tiles.size(),
-                                hipMemcpyHostToDevice, c->stream);
+  if (tile < kBatchMinTile || tile > kBatchMaxTile || tile % kBatchMinTile)
+    return fail(MPPI_EINVAL, "batch tile %d outside %d..%d", tile, kBatchMinTile, kBatchMaxTile);
+  std::vector<int32_t> K(n_inst), T(n_inst);
+  for (int i = 0; i < n_inst; ++i) { K[i] = c->inst[i].K; T[i] = c->inst[i].T; }
+  const std::vector<WorkItem> tiles = build_sample_tiles(K.data(), T.data(), n_inst, tile);
+  const std::string bad = check_work_list(tiles.data(), static_cast<int64_t>(tiles.size()),
+                                          c->C.n_sample_tiles, tile, K.data(), n_inst);
+  if (!bad.empty()) return fail(MPPI_EINVAL, "sample work list: %s", bad.c_str());
+  hipError_t e = hipMemcpyAsync(c->ws + c->C.sample_tiles, tiles.data(),
+                                sizeof(WorkItem) * tiles.size(), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess) return hip_fail(e, "sample work list upload");
   c->plan.n_sample_tiles = static_cast<int>(tiles.size());
   c->plan.tile = tile;
-  return hipSuccess;
+  return MPPI_OK;
 }
 
 mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n_inst, bool batch,
@@ -766,7 +770,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
 
   // batch tables
   std::vector<BatchInst> bi;
-  std::vector<int2> row_tiles;
+  std::vector<WorkItem> row_tiles;
   if (batch && e == hipSuccess) {
     size_t lds = 0;
     for (int i = 0; i < n_inst; ++i) {
@@ -789,13 +793,22 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
       lds = std::max(lds, rollout_lds_bytes(cfgs[i].dynamics, cfgs[i].cost, I.dp.stage_words4, I.T));
     }
     const int rpb = gemv_rows_per_block();
-    for (int i = 0; i < n_inst; ++i)
-      for (int rb = 0; rb * rpb < c->inst[i].TM; ++rb) row_tiles.push_back(int2{i, rb});
+    std::vector<int32_t> TM(n_inst);
+    for (int i = 0; i < n_inst; ++i) TM[i] = c->inst[i].TM;
+    row_tiles = build_row_tiles(TM.data(), n_inst, rpb);
+    const std::string bad = check_work_list(row_tiles.data(),
+                                            static_cast<int64_t>(row_tiles.size()),
+                                            C.n_row_tiles, rpb, TM.data(), n_inst);
+    if (!bad.empty()) {
+      (void)hipStreamSynchronize(c->stream);
+      delete c;
+      return fail(MPPI_EINVAL, "row work list: %s", bad.c_str());
+    }
     e = hipMemcpyAsync(c->ws + C.insts, bi.data(), sizeof(BatchInst) * n_inst,
                        hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(c->ws + C.row_tiles, row_tiles.data(), sizeof(int2) * row_tiles.size(),
-                         hipMemcpyHostToDevice, c->stream);
+      e = hipMemcpyAsync(c->ws + C.row_tiles, row_tiles.data(),
+                         sizeof(WorkItem) * row_tiles.size(), hipMemcpyHostToDevice, c->stream);
     BatchPlan& P = c->plan;
     P.insts = reinterpret_cast<const BatchInst*>(c->ws + C.insts);
     P.sample_tiles = reinterpret_cast<const int2*>(c->ws + C.sample_tiles);
@@ -824,8 +837,11 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
                         : chunked_for(c) ? MPPI_UPDATE_CHUNKED
                                          : MPPI_UPDATE_TWO_PASS;
   if (e == hipSuccess) e = tape_reset(c);
-  if (e == hipSuccess && batch) e = upload_sample_tiles(c, c->tune.batch_tile);
   if (e != hipSuccess) { delete c; return hip_fail(e, "context upload"); }
+  if (batch) {
+    const mppi_status st = upload_sample_tiles(c, c->tune.batch_tile);
+    if (st != MPPI_OK) { delete c; return st; }
+  }
   *out = c;
   g_last_error.clear();
   return MPPI_OK;
@@ -1066,7 +1082,10 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
   } else if (t->lanes_per_sample != 1) {
     return fail(MPPI_EINVAL, "lanes_per_sample must be 1, 4, 8 or 16");
   }
-  if (c->batch && t->batch_tile != c->plan.tile) HIP_TRY(upload_sample_tiles(c, t->batch_tile));
+  if (c->batch && t->batch_tile != c->plan.tile) {
+    const mppi_status st = upload_sample_tiles(c, t->batch_tile);
+    if (st != MPPI_OK) return st;
+  }
   if (!(I.hidden || I.grad)) I.lanes = t->lanes_per_sample;
   c->tune = *t;
   c->drop_graphs();
