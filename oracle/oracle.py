@@ -77,6 +77,11 @@ def lib():
         L.orc_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
                                 C.c_int32, f32p, C.c_int64, f32p]
         L.orc_rollout_costs.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p, f64p, i32p, f64p]
+        # the same entry with raw pointers, for sample ranges of a larger noise array
+        Lr = C.CDLL(_LIB_PATH)
+        Lr.orc_rollout_costs.argtypes = [P, f64p, f64p, C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]
+        L._ranged = Lr
         L.orc_softmin_update.argtypes = [P, f64p, f32p, C.c_int64, f64p, f64p, f64p, f64p]
         L.orc_softmin_update.restype = C.c_int
         L.orc_mppi.argtypes = [P, f64p, f64p, C.c_int32, C.c_uint32, f32p, f64p, f64p, f64p]
@@ -240,6 +245,52 @@ def rollout_costs(wl, eps=None, x0=None, u=None, iteration: int = 0, slope=False
     if slope:
         return S, margin, crashes, sl
     return S, margin, crashes
+
+
+def host_threads() -> int:
+    """Worker threads for the sample-parallel oracle: the CPUs this process
+    may run on, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def rollout_costs_parallel(wl, eps, x0=None, u=None, threads=None, **override):
+    """S[K] of the rollout stage, the samples split into contiguous ranges
+    that run concurrently on `threads` host threads (default host_threads()).
+    Each range is the same oracle call on its own samples (the samples are
+    independent), so S is bitwise the single-threaded result."""
+    import threading
+    threads = threads or host_threads()
+    eps = np.ascontiguousarray(eps, np.float32)
+    K = eps.shape[-1]
+    x0 = _d(wl.x0 if x0 is None else x0)
+    u = _d(wl.u0 if u is None else u).ravel()
+    S = np.empty(K)
+    bounds = np.linspace(0, K, min(threads, K) + 1).astype(np.int64)
+    L = lib()._ranged
+    probs = []
+    errors = []
+
+    def work(a, b):
+        try:
+            P = Problem(wl.replace(K=int(b - a)), **override)
+            probs.append(P)
+            L.orc_rollout_costs(P.ref, x0, u, eps.ctypes.data + 4 * int(a), K,
+                                S.ctypes.data + 8 * int(a), None, None, None)
+        except Exception as e:  # noqa: BLE001
+            errors.append(e)
+    ts = [threading.Thread(target=work, args=(bounds[i], bounds[i + 1]))
+          for i in range(len(bounds) - 1) if bounds[i + 1] > bounds[i]]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    if errors:
+        raise errors[0]
+    return S
 
 
 def softmin_update(wl, S, eps, u=None, **override):
@@ -446,4 +497,5 @@ __all__ = ["philox", "bm_tables", "noise", "workload_noise", "rollout_costs",
            "softmin_update", "mppi", "step", "deriv", "trajectory", "sequence_cost",
            "running_cost", "terminal_cost", "spline", "costmap", "Problem", "n_grad",
            "backward", "with_theta", "theta_of", "loss_and_controls",
-           "cost_condition", "shift", "backward_iters", "sequence_cost_injected"]
+           "cost_condition", "shift", "backward_iters", "sequence_cost_injected",
+           "rollout_costs_parallel", "host_threads"]

@@ -62,10 +62,8 @@ def test_batch_against_oracle(mppi, oracle_lib):
         parity.assert_costs_close(S[i], S_or, margin, f"instance {i}")
         sure = margin >= parity.AMBIGUOUS_MARGIN
         assert np.array_equal(crashes[i][sure], cr_or[sure])
-        o = oracle_lib.mppi(wl, iters=1)
-        parity.assert_controls_close(U[i].reshape(wl.T, 2), o["U"],
-                                     parity.controls_tol(wl, o["S"], o["w"], o["eps"]),
-                                     f"instance {i}")
+        parity.assert_end_to_end(oracle_lib, wl, U[i].reshape(wl.T, 2), S[i], e_or, S_or,
+                                 f"instance {i}")
         assert stats[i]["status"] == 0 and stats[i]["iteration"] == 1
 
 
@@ -91,17 +89,30 @@ def test_batch_equals_single_contexts_bitwise(mppi):
 
 
 def test_batch_full_size_sampled(mppi, oracle_lib):
-    """All 256 instances of the c4 recipe in one context: every status OK, and
-    a sample of instances / samples recomputed by the oracle."""
+    """All 256 instances of the c4 recipe in one context, in the benchmark's
+    launch configuration: every status OK; the instance with the most
+    rollout steps checked in full (every cost, and its controls end to end);
+    a sample of other instances / samples recomputed by the oracle."""
     insts = W.c4()
     ctl = mppi.Controller(insts)
     ctl.sample()
     ctl.rollout()
     S = ctl.split(_np(ctl.costs()), 2)
+    big = int(np.argmax([w.K * w.T for w in insts]))
+    eps_big = ctl.split(_np(ctl.noise()), 3)[big]
     ctl.update()
     stats = ctl.stats()
+    U = ctl.split(_np(ctl.controls()), 1)
     ctl.close()
     assert all(s["status"] == 0 for s in stats)
+    wl = insts[big]
+    e_or = oracle_lib.workload_noise(wl)
+    assert np.array_equal(eps_big.view(np.uint32), e_or.ravel().view(np.uint32))
+    S_or = oracle_lib.rollout_costs_parallel(wl, e_or)
+    margin = oracle_lib.rollout_costs(wl, eps=e_or)[1]
+    parity.assert_costs_close(S[big], S_or, margin, f"instance {big} (K {wl.K}, T {wl.T})")
+    parity.assert_end_to_end(oracle_lib, wl, U[big].reshape(wl.T, 2), S[big], e_or, S_or,
+                             f"full-size instance {big}")
     rng = np.random.default_rng(4)
     for i in rng.choice(len(insts), 6, replace=False):
         wl = insts[i]

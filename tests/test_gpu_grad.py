@@ -95,8 +95,7 @@ def test_mlp_iterations_end_to_end(mppi, oracle_lib):
         parity.assert_costs_close(S, S_or, name=f"iteration {it}", cond=cond, skip=ch)
         w_or, U_or, _, _ = oracle_lib.softmin_update(wl, S_or, eps, u=u)
         assert w_or[ch].sum() < 1e-6  # their cost cannot move U by 1e-4
-        tol = parity.controls_tol(wl, S_or, w_or, eps, cond=cond)
-        parity.assert_controls_close(U, U_or, tol, name=f"iteration {it}")
+        parity.assert_end_to_end(oracle_lib, wl, U, S, eps, S_or, f"iteration {it}", u=u)
         u = U.astype(np.float64)  # continue from the GPU's controls
     c.close()
 

@@ -99,8 +99,7 @@ def test_importance_sampling_and_step_size(mppi, oracle_lib, name, gamma):
     assert np.abs(S_or - S_plain).max() > parity.REL * np.abs(S_or).max()
     w_or, U_or, stats_or, rc = oracle_lib.softmin_update(wl, S_or, eps)
     assert rc == 0 and st["status"] == 0
-    tol = parity.controls_tol(wl, S_or, w_or, eps, cond=cond)
-    parity.assert_controls_close(U, U_or, tol, f"{name} controls")
+    parity.assert_end_to_end(oracle_lib, wl, U, S, eps, S_or, f"{name} controls")
 
 
 def test_zero_step_size_keeps_the_controls(mppi):
@@ -129,11 +128,10 @@ def test_warm_started_iterations_with_options(mppi, oracle_lib):
         ctl.set_iteration(i)
         ctl.iterate(1)
         U = _np(ctl.controls())
-        parity.assert_controls_close(U, o["U"], parity.controls_tol(wl, o["S"], o["w"], o["eps"]),
-                                     f"iteration {i}")
         S = _np(ctl.costs())
         margin = oracle_lib.rollout_costs(wl, eps=o["eps"], u=u)[1]
         parity.assert_costs_close(S, o["S"], margin, f"iteration {i} costs")
+        parity.assert_end_to_end(oracle_lib, wl, U, S, o["eps"], o["S"], f"iteration {i}", u=u)
         u = o["U"]
     ctl.close()
 
@@ -156,9 +154,8 @@ def test_batch_with_options(mppi, oracle_lib):
         e = eps[i].reshape(wl.T, wl.m, -1)[:, :, :wl.K]
         S_or, margin, _ = oracle_lib.rollout_costs(wl, eps=e)
         parity.assert_costs_close(S[i], S_or, margin, f"instance {i}")
-        w_or, U_or, _, _ = oracle_lib.softmin_update(wl, S_or, e)
-        parity.assert_controls_close(U[i].reshape(wl.T, wl.m), U_or,
-                                     parity.controls_tol(wl, S_or, w_or, e), f"instance {i}")
+        parity.assert_end_to_end(oracle_lib, wl, U[i].reshape(wl.T, wl.m), S[i],
+                                 np.ascontiguousarray(e), S_or, f"instance {i}")
 
 
 @pytest.mark.parametrize("H,lam,gamma", [(64, 50.0, 0.5), (16, 5.0, 1.0), (0, 50.0, 0.3)])

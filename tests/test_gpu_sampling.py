@@ -47,18 +47,6 @@ def _options(wl, seed, zero_frac=0.2, mean_sample=1, is_beta=1, gamma=0.7):
                       is_beta=is_beta, gamma=gamma)
 
 
-def _n_plain(wl):
-    nz = int(np.floor(float(np.float32(wl.zero_frac)) * wl.K))
-    nz = min(nz, wl.K - (1 if wl.mean_sample else 0))
-    return wl.K - max(nz, 0)
-
-
-def _controls_tol(wl, S_or, w_or, eps, u, cond=None):
-    dev = eps.astype(np.float64).copy()           # v_k - u
-    dev[:, :, _n_plain(wl):] -= u[:, :, None]
-    return parity.controls_tol(wl, S_or, w_or, dev.astype(np.float64), cond=cond)
-
-
 CASES = {
     "c1": (lambda: W.c1(K=1000, T=40), {}),
     "c3": (lambda: W.c3(K=700, T=40), {}),
@@ -98,9 +86,7 @@ def test_sampling_options_parity(mppi, oracle_lib, name):
                               slope=slope if wl.cost == "path_costmap" else None)
     w_or, U_or, _, rc = oracle_lib.softmin_update(wl, S_or, eps)
     assert rc == 0 and st["status"] == 0
-    parity.assert_controls_close(U, U_or,
-                                 _controls_tol(wl, S_or, w_or, eps, wl.u0.astype(np.float64), cond),
-                                 f"{name} controls")
+    parity.assert_end_to_end(oracle_lib, wl, U, S, eps, S_or, f"{name} controls")
 
 
 def test_sampling_options_batch(mppi, oracle_lib):
@@ -121,10 +107,8 @@ def test_sampling_options_batch(mppi, oracle_lib):
         assert np.array_equal(e.view(np.uint32), oracle_lib.workload_noise(wl).view(np.uint32))
         S_or, margin, _ = oracle_lib.rollout_costs(wl, eps=e)
         parity.assert_costs_close(S[i], S_or, margin, f"instance {i}")
-        w_or, U_or, _, _ = oracle_lib.softmin_update(wl, S_or, e)
-        parity.assert_controls_close(U[i].reshape(wl.T, wl.m), U_or,
-                                     _controls_tol(wl, S_or, w_or, e, wl.u0.astype(np.float64)),
-                                     f"instance {i}")
+        parity.assert_end_to_end(oracle_lib, wl, U[i].reshape(wl.T, wl.m), S[i], e, S_or,
+                                 f"instance {i}")
 
 
 def test_warm_started_iterations_with_sampling_options(mppi, oracle_lib):
@@ -137,8 +121,8 @@ def test_warm_started_iterations_with_sampling_options(mppi, oracle_lib):
         ctl.set_iteration(i)
         ctl.iterate(1)
         U = _np(ctl.controls())
-        parity.assert_controls_close(U, o["U"], _controls_tol(wl, o["S"], o["w"], o["eps"], u),
-                                     f"iteration {i}")
+        parity.assert_end_to_end(oracle_lib, wl, U, _np(ctl.costs()), o["eps"], o["S"],
+                                 f"iteration {i}", u=u)
         u = o["U"]
     ctl.close()
 

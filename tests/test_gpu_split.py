@@ -92,9 +92,7 @@ def test_split_form_parity(mppi, oracle_lib, name, lanes, waves):
     if debug:
         sure = margin >= parity.AMBIGUOUS_MARGIN
         assert np.array_equal(crashes[sure], cr_or[sure])
-    o = oracle_lib.mppi(wl, iters=1)
-    parity.assert_controls_close(U, o["U"], parity.controls_tol(wl, o["S"], o["w"], o["eps"]),
-                                 f"{name} split")
+    parity.assert_end_to_end(oracle_lib, wl, U, S, eps, S_or, f"{name} split")
     assert st["status"] == 0
 
 
@@ -111,8 +109,8 @@ def test_split_form_ten_iterations_in_graph(mppi, oracle_lib):
         ctl.set_iteration(i)
         ctl.iterate(1)
         U = _np(ctl.controls())
-        parity.assert_controls_close(U, o["U"], parity.controls_tol(wl, o["S"], o["w"], o["eps"]),
-                                     f"iteration {i}")
+        parity.assert_end_to_end(oracle_lib, wl, U, _np(ctl.costs()), o["eps"], o["S"],
+                                 f"iteration {i}", u=u)
         u = o["U"]
     ctl.close()
 
@@ -124,8 +122,7 @@ def test_split_form_with_importance_sampling(mppi, oracle_lib):
     S, eps, _, U, st = _run(mppi, wl, dict(rollout_form=1, lanes_per_sample=1, cost_waves=8))
     S_or, margin, _ = oracle_lib.rollout_costs(wl, eps=eps)
     parity.assert_costs_close(S, S_or, margin, "split + IS")
-    w_or, U_or, _, _ = oracle_lib.softmin_update(wl, S_or, eps)
-    parity.assert_controls_close(U, U_or, parity.controls_tol(wl, S_or, w_or, eps), "split + IS")
+    parity.assert_end_to_end(oracle_lib, wl, U, S, eps, S_or, "split + IS")
 
 
 # every rollout kernel: lane, grouped (4, 8, 16), split (1 and 4 lanes), the
