@@ -36,6 +36,25 @@ def test_every_declared_function_is_exported(abi):
     assert sorted(abi.EXPORTS) == names  # and the binding declares nothing else
 
 
+def test_ceilings_library_exports_its_header():
+    """The measurement library (include/mppi_ceilings.h) loads without a GPU
+    and exports exactly what its header declares."""
+    from paper_2409_07563_amd import ceilings
+    text = open(os.path.join(ROOT, "include", "mppi_ceilings.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(mppi_[a-z_]+)\s*\(", text)))
+    L = ceilings.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(ceilings.EXPORTS) == names
+    # invalid arguments are refused before any device call
+    us, ops = C.c_double(), C.c_double()
+    assert L.mppi_ceiling_valu(7, 1, 1, 1, None, None, C.byref(us), C.byref(ops)) == -1
+    assert L.mppi_ceiling_chain(0, 1, None, None, None, C.byref(us)) == -1
+    assert L.mppi_ceiling_chain(257, 1, None, None, None, C.byref(us)) == -1
+    assert L.mppi_ceiling_graph(0, 1, 1, None, C.byref(us)) == -1
+
+
 def test_struct_sizes_match_the_header(abi):
     # sizes of the C structs as laid out by the host compiler
     assert C.sizeof(abi.Config) == 96
