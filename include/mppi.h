@@ -212,8 +212,11 @@ typedef struct mppi_ctx mppi_ctx;
  * (0 if the configuration is invalid; see mppi_last_error). */
 size_t mppi_workspace_bytes(const mppi_config* cfg, const mppi_params* params);
 
-/* Create a context.  d_workspace: device memory of at least
- * mppi_workspace_bytes, 256-byte aligned, owned by the caller and used
+/* Create a context: the fixed inputs of Algorithm 1 (the dynamics F, the
+ * running and terminal costs, the horizon T, the sample count K, the
+ * temperature lambda and the noise covariance Sigma; the number of
+ * iterations is mppi_iterate's argument).  d_workspace: device memory of at
+ * least mppi_workspace_bytes, 256-byte aligned, owned by the caller and used
  * exclusively by this context until mppi_destroy.  hip_stream: a hipStream_t
  * (NULL = the null stream).  Copies the parameter arrays to the device and
  * waits for the copies.  The nominal controls start at zero and the iteration
@@ -320,7 +323,8 @@ mppi_status mppi_set_tuning(mppi_ctx* ctx, const mppi_tuning* t);
  * Synchronises the context's stream. */
 mppi_status mppi_autotune(mppi_ctx* ctx, int32_t reps, char* host_report, size_t report_len);
 
-/* x0 <- d_x0[0..n) (enqueued device copy; packed for a batch). */
+/* x0 <- d_x0[0..n): the initial state every rollout of Algorithm 1 starts
+ * from (enqueued device copy; packed for a batch).  Errors: EINVAL (NULL). */
 mppi_status mppi_set_state(mppi_ctx* ctx, const float* d_x0);
 /* u <- d_u[T][m] (enqueued device copy; warm start or restore; packed). */
 mppi_status mppi_set_controls(mppi_ctx* ctx, const float* d_u);
@@ -363,7 +367,9 @@ mppi_status mppi_update(mppi_ctx* ctx);
  * way: it depends on the seed, the iteration word and the instance only. */
 mppi_status mppi_iterate(mppi_ctx* ctx, int32_t num_iters);
 
-/* d_U[T][m] <- current nominal controls (enqueued device copy). */
+/* d_U[T][m] <- the current nominal control sequence, Algorithm 1's output
+ * after its last update (enqueued device copy; packed for a batch).  Errors:
+ * EINVAL (NULL). */
 mppi_status mppi_get_controls(mppi_ctx* ctx, float* d_U);
 
 enum {

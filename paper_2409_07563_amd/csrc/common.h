@@ -45,6 +45,12 @@ struct DevParams {
   int map_w, map_h;
   float map_x0, map_y0, map_res, map_inv_res;
   const float* costmap;   // [map_h][map_w]
+  // A costmap holding at most two distinct values (an occupancy map: free /
+  // obstacle) is also staged losslessly as a bitmap: bit iy*map_w + ix of the
+  // uint32 words at float4 offset map_bits4 of the stage selects map_v1 (set)
+  // or map_v0; map_bits4 < 0 when the map is read from memory instead.
+  int map_bits4;
+  float map_v0, map_v1;
   // importance-sampling term of a step: sum_j is_coef[j] (v_j - u_j/2) u_j with
   // is_coef[j] = lambda / sigma_j^2 (added to the running cost when importance)
   int importance;
@@ -125,6 +131,22 @@ struct BatchInst {
 // The tile size is a launch parameter (64, 128 or 256 samples, one thread
 // each; the autotuner picks it); kBatchMinTile sizes the tile table.
 constexpr int kBatchMaxTile = 256, kBatchMinTile = 64;
+
+// The fused batch launch (one persistent launch per iteration: rollout tiles,
+// the weights of an instance by the workgroup that finishes its last tile, the
+// rows of its update) takes work items from one list through an atomic
+// counter.  Item (i, t) with t >= 0 is sample tile t of instance i; (i, -1 - r)
+// is row r of instance i's update.  Every row item of an instance comes after
+// all of its sample tiles in the list (checked on the host), so a workgroup
+// that waits for an instance's weights waits only for workgroups that are
+// already running its tiles.
+struct BatchSync {
+  uint32_t next;    // next item to hand out (reset by the last workgroup to leave)
+  uint32_t exited;  // workgroups that have left this launch
+  uint32_t epoch;   // launches completed; ready[i] == epoch + 1 once instance i's weights are out
+  uint32_t error;   // a wait for an instance's weights gave up (never expected)
+};
+constexpr uint32_t kFusedSpinLimit = 1u << 24;  // polls (~1 us apart) before a wait gives up
 struct BatchPlan {
   const BatchInst* insts;
   const int2* sample_tiles;
@@ -135,6 +157,12 @@ struct BatchPlan {
   int n_inst;
   size_t rollout_lds;
   size_t max_tm_bytes;  // largest T * m of an instance, in bytes (the shift's LDS)
+  // the fused launch (form 1): its item list, counters (BatchSync, then
+  // done[n_inst] tile counters, then ready[n_inst] words) and grid
+  const int2* fused_items;
+  int n_fused_items;
+  BatchSync* sync;
+  int fused_grid;
 };
 
 // ---- host launchers (one translation unit each) ---------------------------
@@ -269,6 +297,14 @@ hipError_t launch_batch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t
                                 bool accurate_trig, bool count, const BatchPlan& b,
                                 hipStream_t stream);
 hipError_t launch_batch_update(const BatchPlan& b, hipStream_t stream);
+// One persistent launch: every rollout tile (tile = kGemvBlock samples), the
+// weights and every row of the update (the noise is drawn before it).
+hipError_t launch_batch_fused(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                              bool accurate_trig, bool count, const BatchPlan& b,
+                              hipStream_t stream);
+// Workgroups of the fused launch that fit the device at once (0 on error).
+int batch_fused_capacity(uint32_t dynamics, uint32_t integrator, uint32_t cost, bool accurate_trig,
+                         bool count, size_t lds);
 hipError_t launch_batch_set_iteration(const BatchPlan& b, uint32_t iteration, hipStream_t stream);
 
 // ---- wave / block reductions ------------------------------------------------

@@ -114,13 +114,21 @@ __device__ __forceinline__ bool in_any_circle(float px, float py, const DevParam
   return hit;
 }
 
+// One cell of a two-valued costmap from the LDS bitmap (see DevParams).
+__device__ __forceinline__ float map_cell_bit(const uint32_t* bits, int idx, const DevParams& p) {
+  return (bits[idx >> 5] >> (idx & 31)) & 1u ? p.map_v1 : p.map_v0;
+}
+
 // Bilinear costmap between cell centres, clamped to the edge cells.  The
 // cell comes from the rounded cell coordinate; the interpolation fractions are
 // measured from that cell's centre (exact in binary32 for the usual
 // power-of-two-friendly resolutions) and include the position's compensation
 // term, so they do not inherit the rounding of a coordinate near 256 cells.
+// The four corner values come from the LDS bitmap when the map is staged as
+// one (the same binary32 values as the map's, so the result is identical),
+// else from the map in memory (L2).
 __device__ __forceinline__ float costmap_value(float px, float py, float cpx, float cpy,
-                                               const DevParams& p) {
+                                               const DevParams& p, const float4* lds) {
   const float gx = fminf(fmaxf((px - p.map_x0) * p.map_inv_res - 0.5f, 0.0f),
                          static_cast<float>(p.map_w - 1));
   const float gy = fminf(fmaxf((py - p.map_y0) * p.map_inv_res - 0.5f, 0.0f),
@@ -132,9 +140,21 @@ __device__ __forceinline__ float costmap_value(float px, float py, float cpx, fl
   const float cy = p.map_y0 + (static_cast<float>(iy) + 0.5f) * res;
   const float fx = fminf(fmaxf(((px - cx) - cpx) * p.map_inv_res, 0.0f), 1.0f);
   const float fy = fminf(fmaxf(((py - cy) - cpy) * p.map_inv_res, 0.0f), 1.0f);
-  const float* row = p.costmap + static_cast<int64_t>(iy) * p.map_w + ix;
-  const float m00 = row[0], m01 = row[1];
-  const float m10 = row[p.map_w], m11 = row[p.map_w + 1];
+  float m00, m01, m10, m11;
+  if (p.map_bits4 >= 0) {
+    const uint32_t* bits = reinterpret_cast<const uint32_t*>(lds + p.map_bits4);
+    const int idx = iy * p.map_w + ix;
+    m00 = map_cell_bit(bits, idx, p);
+    m01 = map_cell_bit(bits, idx + 1, p);
+    m10 = map_cell_bit(bits, idx + p.map_w, p);
+    m11 = map_cell_bit(bits, idx + p.map_w + 1, p);
+  } else {
+    const float* row = p.costmap + static_cast<int64_t>(iy) * p.map_w + ix;
+    m00 = row[0];
+    m01 = row[1];
+    m10 = row[p.map_w];
+    m11 = row[p.map_w + 1];
+  }
   return (1.0f - fx) * (1.0f - fy) * m00 + fx * (1.0f - fy) * m01 + (1.0f - fx) * fy * m10 +
          fx * fy * m11;
 }
@@ -157,7 +177,7 @@ struct CostPath {
       c += hit ? p.w[6] : 0.0f;
     } else {
       hit = false;
-      c += costmap_value(x[0], x[1], comp[0], comp[1], p);
+      c += costmap_value(x[0], x[1], comp[0], comp[1], p, lds);
     }
     return c;
   }

@@ -302,10 +302,15 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
   L.e = take(sizeof(float) * L.ldk);
   L.ref = take(sizeof(float) * (size_t)(p->ref ? p->ref_len : 1));
   const int S = uses_spline(c->cost) ? p->num_segments : 0;
-  L.stage = take((uses_circles(c->cost) ? kMaxGridBytes : sizeof(float4)) +
-                 sizeof(float4) * (S + (S + 1 + 3) / 4));
   const size_t cells =
       c->cost == MPPI_COST_PATH_COSTMAP ? (size_t)p->map_w * (size_t)p->map_h : 1;
+  // room for the costmap's bitmap (staged when the map is two-valued and the
+  // bitmap fits the LDS)
+  const size_t map_bits = c->cost == MPPI_COST_PATH_COSTMAP && (cells + 7) / 8 <= kMaxRolloutLds
+                              ? sizeof(float4) * ((cells + 127) / 128)
+                              : 0;
+  L.stage = take((uses_circles(c->cost) ? kMaxGridBytes : sizeof(float4)) +
+                 sizeof(float4) * (S + (S + 1 + 3) / 4) + map_bits);
   L.costmap = take(sizeof(float) * cells);
   if (p->sigma_t) {
     L.sigma_t = take(sizeof(float) * ((TM + 3) / 4 * 4));  // read four at a time
@@ -573,6 +578,42 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
     for (size_t q = 0; q < kn.size(); q += 4)
       stage.push_back(float4{kn[q], kn[q + 1], kn[q + 2], kn[q + 3]});
   }
+  // a costmap of at most two distinct values (compared bit for bit) is also
+  // staged as a bitmap, when it fits beside the rest of the stage
+  int map_bits4 = -1;
+  float map_v[2] = {0.0f, 0.0f};
+  if (cfg->cost == MPPI_COST_PATH_COSTMAP) {
+    const int64_t cells = static_cast<int64_t>(p->map_w) * p->map_h;
+    uint32_t vals[2];
+    int nval = 0;
+    for (int64_t q = 0; q < cells && nval <= 2; ++q) {
+      uint32_t b;
+      memcpy(&b, p->costmap + q, 4);
+      if (nval > 0 && b == vals[0]) continue;
+      if (nval > 1 && b == vals[1]) continue;
+      if (nval < 2) vals[nval] = b;
+      ++nval;
+    }
+    const size_t words4 = static_cast<size_t>((cells + 127) / 128);
+    const size_t need = rollout_lds_bytes(cfg->dynamics, cfg->cost,
+                                          static_cast<int>(stage.size() + words4), I->T);
+    if (nval <= 2 && need <= kMaxRolloutLds) {
+      memcpy(&map_v[0], &vals[0], 4);
+      memcpy(&map_v[1], nval == 2 ? &vals[1] : &vals[0], 4);
+      map_bits4 = static_cast<int>(stage.size());
+      std::vector<uint32_t> bits(4 * words4, 0u);
+      for (int64_t q = 0; q < cells; ++q) {
+        uint32_t b;
+        memcpy(&b, p->costmap + q, 4);
+        if (nval == 2 && b == vals[1]) bits[q >> 5] |= 1u << (q & 31);
+      }
+      for (size_t w = 0; w < words4; ++w) {
+        float4 f;
+        memcpy(&f, bits.data() + 4 * w, 16);
+        stage.push_back(f);
+      }
+    }
+  }
   const size_t lds_need =
       rollout_lds_bytes(cfg->dynamics, cfg->cost, static_cast<int>(stage.size()), I->T);
   if (lds_need > kMaxRolloutLds)
@@ -683,6 +724,9 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
     d.map_inv_res = static_cast<float>(1.0 / static_cast<double>(p->map_res));
     d.costmap = I->at<float>(I->L.costmap);
   }
+  d.map_bits4 = map_bits4;
+  d.map_v0 = map_v[0];
+  d.map_v1 = map_v[1];
   return MPPI_OK;
 }
 
