@@ -214,8 +214,8 @@ def measure_ceilings() -> dict:
     from paper_2409_07563_amd import ceilings as CE
     s = torch.cuda.Stream()
     valu = {}
-    for mode in ("fma", "fma+exp", "exp", "mad_u64"):
-        rate, _ = CE.valu(mode, blocks=8192, iters=2048, reps=5, stream=s)
+    for mode in ("fma", "fma+exp", "exp", "mad_u64", "int_xor_add"):
+        rate, _ = CE.valu(mode, blocks=16384, iters=1024, reps=5, stream=s)
         valu[mode] = rate
     return {
         "valu_lane_ops_per_s": valu,

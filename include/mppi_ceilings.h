@@ -31,7 +31,8 @@ extern "C" {
  *           beside FMAs, or in the same slots?);
  *   mode 2: v_exp_f32 only (8 per trip);
  *   mode 3: v_mad_u64_u32 (32 x 32 -> 64-bit multiply-add, Philox's product;
- *           8 per trip).
+ *           8 per trip);
+ *   mode 4: 32-bit integer v_xor_b32 and v_add_u32 (16 per trip).
  * d_sink: blocks * 256 floats, written so that nothing is optimised away.
  * *lane_ops_out: VALU lane-instructions the loop body issues per launch
  * (blocks * 256 * iters * instructions per trip). */

@@ -19,7 +19,7 @@ EXPORTS = {
                                      C.POINTER(C.c_double)]),
     "mppi_ceiling_last_error": (C.c_char_p, []),
 }
-VALU_MODES = {"fma": 0, "fma+exp": 1, "exp": 2, "mad_u64": 3}
+VALU_MODES = {"fma": 0, "fma+exp": 1, "exp": 2, "mad_u64": 3, "int_xor_add": 4}
 
 _lib = None
 

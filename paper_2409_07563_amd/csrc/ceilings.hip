@@ -32,7 +32,24 @@ template <int MODE>
 __global__ __launch_bounds__(kThreads) void valu_loop_kernel(int iters, float a, float b,
                                                               float* __restrict__ sink) {
   const int gid = blockIdx.x * kThreads + threadIdx.x;
-  if constexpr (MODE == 3) {
+  if constexpr (MODE == 4) {
+    uint32_t x[8];
+    const uint32_t k = __float_as_uint(a) | 1u;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = static_cast<uint32_t>(gid * 8 + i);
+#pragma unroll 4
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[i] = (i & 1) ? (x[i] + k) : (x[i] ^ k);
+      // rotate the roles so that no chain folds into a constant
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[i] = (i & 1) ? (x[i] ^ (k << 1)) : (x[i] + (k << 1));
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s ^= x[i];
+    sink[gid] = static_cast<float>(s);
+  } else if constexpr (MODE == 3) {
     uint64_t x[8];
     const uint32_t mul = __float_as_uint(a) | 1u;
 #pragma unroll
@@ -129,7 +146,7 @@ const char* mppi_ceiling_last_error(void) { return g_err.c_str(); }
 
 int mppi_ceiling_valu(int32_t mode, int32_t blocks, int32_t iters, int32_t reps, float* d_sink,
                       void* hip_stream, double* us_out, double* lane_ops_out) {
-  if (mode < 0 || mode > 3 || blocks < 1 || iters < 1 || reps < 1 || !d_sink || !us_out ||
+  if (mode < 0 || mode > 4 || blocks < 1 || iters < 1 || reps < 1 || !d_sink || !us_out ||
       !lane_ops_out) {
     g_err = "mppi_ceiling_valu: invalid argument";
     return -1;
@@ -137,7 +154,7 @@ int mppi_ceiling_valu(int32_t mode, int32_t blocks, int32_t iters, int32_t reps,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   void (*fn)(int, float, float, float*) =
       mode == 0 ? valu_loop_kernel<0> : mode == 1 ? valu_loop_kernel<1>
-      : mode == 2 ? valu_loop_kernel<2> : valu_loop_kernel<3>;
+      : mode == 2 ? valu_loop_kernel<2> : mode == 3 ? valu_loop_kernel<3> : valu_loop_kernel<4>;
   const float a = 0.999999f, b = 1e-7f;
   Events ev;
   CEIL_TRY(hipEventCreate(&ev.a), "event");
@@ -152,7 +169,7 @@ int mppi_ceiling_valu(int32_t mode, int32_t blocks, int32_t iters, int32_t reps,
   float ms = 0.0f;
   CEIL_TRY(hipEventElapsedTime(&ms, ev.a, ev.b), "elapsed");
   *us_out = 1e3 * static_cast<double>(ms) / reps;
-  const double per_trip = mode == 1 ? 10.0 : 8.0;
+  const double per_trip = mode == 1 ? 10.0 : mode == 4 ? 16.0 : 8.0;
   *lane_ops_out = static_cast<double>(blocks) * kThreads * iters * per_trip;
   return 0;
 }

@@ -40,8 +40,9 @@ Tolerances (the target is 1e-4 relative in binary32):
         is small), dU_t/dJ_k = -(gamma w_k / lambda)(d_k,t - sum_i w_i d_i,t)
         with d_k = v_k - u;
       - flat: |U_gpu - U_or| <= 1e-4 max(|U_or|_inf, |sigma|_inf) outright,
-        asserted for the workloads where the measured cost deviations are
-        too small to move the weights by that much.
+        asserted for every workload except the MLP residual dynamics (whose
+        long-horizon trajectories are ill-conditioned: there the first two
+        checks carry the claim).
   * update alone (both sides weight the same binary32 costs): the flat bound.
 """
 import numpy as np
@@ -93,12 +94,16 @@ def _finite(S):
 E2E_LOG = []  # (name, flat ratio, first-order residual ratio, remainder ratio, max |dJ|/lambda)
 
 
-def assert_end_to_end(oracle_lib, wl, U_gpu, S_gpu, eps, S_or, name="", u=None, flat=False,
+def assert_end_to_end(oracle_lib, wl, U_gpu, S_gpu, eps, S_or, name="", u=None, flat=None,
                       lam=None):
     """Controls of one iteration against the oracle's, the softmin carrying
     the GPU's measured cost deviations (see the module docstring).  eps: the
     iteration's noise [T][m][K]; S_or: the oracle's costs on it; u: the
-    nominal controls the iteration started from (default wl.u0)."""
+    nominal controls the iteration started from (default wl.u0).  flat
+    (default: every workload without the MLP residual dynamics, whose long
+    horizons are ill-conditioned) also asserts the flat bound outright."""
+    if flat is None:
+        flat = wl.model != "bicycle_mlp"
     over = {} if lam is None else {"lam": lam}
     u = np.asarray(wl.u0 if u is None else u, np.float64).reshape(wl.T, wl.m)
     S_or = _finite(S_or)
