@@ -178,13 +178,13 @@ def phase_times(ctl, reps: int):
 
 
 def rollout_forms(tuned):
-    """Fastest autotuned rollout launch (us) of the fused and of the split form."""
+    """Fastest autotuned rollout launch (us) of the fused, split and scan forms."""
     if not tuned or "timings" not in tuned:
         return None
     best = {}
     for r in tuned["timings"]:
         if r["phase"] == "rollout":
-            name = "split" if r.get("form") == 1 else "fused"
+            name = {1: "split", 2: "scan"}.get(r.get("form"), "fused")
             best[name] = min(best.get(name, float("inf")), r["us"])
     return best or None
 
@@ -359,17 +359,21 @@ def run_single(args, wl, update_forms: bool = False, autotune_reps: int = 30) ->
     achieved = ops_step * steps_per_iter / t_roll
     tune = ctl.tuning()
     split = tune["rollout_form"] == 1
+    scan = tune["rollout_form"] == 2
     lanes = tune["lanes_per_sample"]
+    kernel = ("split_dynamics + split_cost" if split else
+              "rollout_bicycle_scan_kernel" if scan else
+              "rollout_bicycle_group_kernel" if lanes > 1 else "rollout_kernel")
     traffic = traffic_record("rollout", args.workload if args.workload != "all" else
                              {"c3_quadrotor": "c3", "c2_bicycle_circles": "c2_circles"}.get(
                                  wl.name, wl.name),
+                             "scan_kernel<" if scan else
                              f", {lanes}>" if lanes > 1 else "rollout_kernel<")
     out["roofline"] = {
         "bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
         "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS,
         "traffic": None if split else traffic,
-        "kernel": ("split_dynamics + split_cost" if split else
-                   "rollout_bicycle_group_kernel" if lanes > 1 else "rollout_kernel"),
+        "kernel": kernel,
         "ops_per_rollout_step": ops_step, "launch_us": t_roll * 1e6}
     eps_bytes = 4 * wl.T * wl.m * wl.K
     out["kernels"] = {
@@ -486,9 +490,23 @@ def run_batch(args, insts, loop_baseline: bool = True) -> dict:
     total = sum(w.K * w.T for w in insts)
     ctl = M.Controller(insts, device="cuda:0")
     stream = ctl.stream
-    if not args.no_autotune:
+    if args.tuning:
+        ctl.set_tuning(**json.loads(args.tuning))
+    elif not args.no_autotune:
         ctl.autotune(reps=3)
     tuning = ctl.tuning()
+    # both batch forms timed on their own (one warm-started iteration per
+    # step): four launches per iteration, and the one-launch form
+    forms = {}
+    for form, name, extra in ((0, "phases", {}),
+                              (1, "one_launch", {"batch_tile": 256, "update_form": 0})):
+        try:
+            ctl.set_tuning(batch_form=form, **extra)
+        except M.MPPIError:
+            continue
+        forms[name] = timed(stream, lambda: ctl.iterate(1), max(1, args.steps // 2),
+                            max(1, args.warmup // 2)) * 1e3
+    ctl.set_tuning(**tuning)
     s = timed(stream, lambda: ctl.iterate(1), args.steps, args.warmup)
     tn, tr, tu = phase_times(ctl, max(1, args.kernel_reps // 5))
     ctl.close()
@@ -497,7 +515,8 @@ def run_batch(args, insts, loop_baseline: bool = True) -> dict:
            "T_range": [min(w.T for w in insts), max(w.T for w in insts)],
            "obstacles_range": [min(len(w.cx) for w in insts), max(len(w.cx) for w in insts)],
            "iterations_per_step": 1, "dynamics": insts[0].model, "cost": insts[0].cost,
-           "value": total / s, "ms_per_step": s * 1e3, "tuning": tuning}
+           "value": total / s, "ms_per_step": s * 1e3, "tuning": tuning,
+           "batch_forms_ms_per_step": forms}
     if loop_baseline:
         # the same instances as single contexts, one after another on one
         # stream (each with the default launch shapes of its size)

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MPPI_ABI_VERSION 3u
+#define MPPI_ABI_VERSION 4u
 #define MPPI_MAX_STATE 16
 #define MPPI_MAX_CONTROL 8
 
@@ -267,7 +267,17 @@ mppi_status mppi_offsets(const mppi_ctx* ctx, int32_t what, int64_t* host_offset
  * g + cost_waves, ...) and sums them per sample in a fixed order.  It exists
  * for single contexts with DOUBLE_INTEGRATOR, BICYCLE or QUADROTOR dynamics
  * (not for MLP dynamics, gradient mode or batches). */
-enum { MPPI_ROLLOUT_FUSED = 0, MPPI_ROLLOUT_SPLIT = 1 };
+/* The scan form runs step (a2) for the bicycle with RK4 time-parallel: with
+ * the control held over a step, speed and steer advance by dt times the
+ * controls, the stage yaw rates depend only on speed and steer, and the
+ * position increments only on the yaw and those, so a rollout is three
+ * prefix sums over time (a sample's horizon spread over 16 lanes, chunks of
+ * ceil(T / 16) steps per lane) followed by the running costs of all steps in
+ * parallel.  It exists for single contexts with BICYCLE dynamics, RK4 and
+ * T <= 256 (not for gradient mode), with lanes_per_sample 16 and
+ * rollout_block threads per workgroup.  Equally accurate: the positions are
+ * summed with compensation; only the rounding order differs. */
+enum { MPPI_ROLLOUT_FUSED = 0, MPPI_ROLLOUT_SPLIT = 1, MPPI_ROLLOUT_SCAN = 2 };
 /* Steps (a3)-(a6) (Algorithm 1, Eq. mppi_update_rule):
  *  TWO_PASS: a weights step in one workgroup writes the weights, then one
  *    workgroup per row forms the weighted noise sum (every context; the
@@ -282,10 +292,30 @@ enum { MPPI_ROLLOUT_FUSED = 0, MPPI_ROLLOUT_SPLIT = 1 };
  * All three are equally accurate; their sums are rounded in different orders
  * (CHUNKED's weights are products of two exponentials). */
 enum { MPPI_UPDATE_TWO_PASS = 0, MPPI_UPDATE_ONE_PASS = 1, MPPI_UPDATE_CHUNKED = 2 };
+/* How mppi_iterate runs an iteration of a batch context:
+ *  PHASES: four launches (noise, rollout, weights, update rows), each over
+ *    all instances;
+ *  ONE_LAUNCH: one launch per iteration with a workgroup per tile of 256
+ *    samples (tiles ordered longest horizon first).  A tile draws its own
+ *    noise (stored to the noise buffer), rolls out, weights its samples
+ *    against its own minimum cost and forms its weighted noise rows; the
+ *    workgroup that completes an instance's last tile (a per-instance
+ *    completion counter) rescales the tiles to the instance's minimum and
+ *    updates u, the statistics and the iteration word.  No workgroup waits
+ *    for another and there is no grid-wide barrier.  Needs batch_tile 256, the
+ *    two-pass update setting, at most 65536 samples per instance and a kernel
+ *    for the combination (the models and costs of the per-phase kernels with
+ *    two or four controls).  Noise and costs are bitwise those of PHASES; the
+ *    update equals it up to the rounding order of its sums (the chunked
+ *    update's arithmetic with tiles for chunks).
+ * The staged calls (mppi_sample, mppi_rollout, mppi_update) always run the
+ * per-phase launches. */
+enum { MPPI_BATCH_PHASES = 0, MPPI_BATCH_ONE_LAUNCH = 1 };
 typedef struct mppi_tuning {
   int32_t lanes_per_sample; /* rollout: 1, or 4, 8 or 16 (the bicycle with RK4, single
                                instance: RK4 stages across a quad, the running cost
-                               shared by the lanes); 16 for MLP dynamics and
+                               shared by the lanes; 16 also in the scan form: the
+                               horizon across the lanes); 16 for MLP dynamics and
                                gradient mode (fixed) */
   int32_t rollout_block;    /* threads per rollout workgroup: 64, 128 or 256; for MLP
                                dynamics and gradient mode 64 (one wave per 16-sample
@@ -295,16 +325,19 @@ typedef struct mppi_tuning {
   int32_t batch_tile;       /* samples per work tile of a batch context: 64, 128 or 256 */
   int32_t noise_calls;      /* Philox calls per thread of the single-instance noise
                                kernel: 1, 2 or 4 */
-  int32_t rollout_form;     /* MPPI_ROLLOUT_FUSED (default) or MPPI_ROLLOUT_SPLIT; in
-                               the split form lanes_per_sample (1, or 4 for the
-                               bicycle with RK4) and rollout_block shape the
-                               dynamics kernel */
+  int32_t rollout_form;     /* MPPI_ROLLOUT_FUSED (default), MPPI_ROLLOUT_SPLIT or
+                               MPPI_ROLLOUT_SCAN; in the split form
+                               lanes_per_sample (1, or 4 for the bicycle with RK4)
+                               and rollout_block shape the dynamics kernel, in the
+                               scan form lanes_per_sample is 16 */
   int32_t cost_waves;       /* split form: waves that share the steps of 64 samples in
                                the cost kernel, a power of two from 1 to 128 (up to
                                16 in one workgroup; beyond, chunks of 16 waves whose
                                partial sums a small kernel adds; default 8) */
   int32_t update_form;      /* MPPI_UPDATE_TWO_PASS, _ONE_PASS or _CHUNKED (defaults
                                as listed above) */
+  int32_t batch_form;       /* batch contexts: MPPI_BATCH_PHASES or
+                               MPPI_BATCH_ONE_LAUNCH (single contexts: PHASES) */
 } mppi_tuning;
 
 /* The context's current launch shapes. */

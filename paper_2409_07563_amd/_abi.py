@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmppi.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_CONTROL = 8
 
 MPPI_OK, MPPI_EINVAL, MPPI_ENOMEM, MPPI_EDEVICE, MPPI_ESTATE, MPPI_EUNSUPPORTED, \
@@ -32,8 +32,9 @@ F_REQUIRES_GRAD = 16
 F_IMPORTANCE_SAMPLING = 32
 F_STEP_SIZE = 64
 F_MEAN_SAMPLE = 128
-ROLLOUT_FUSED, ROLLOUT_SPLIT = 0, 1
+ROLLOUT_FUSED, ROLLOUT_SPLIT, ROLLOUT_SCAN = 0, 1, 2
 UPDATE_TWO_PASS, UPDATE_ONE_PASS, UPDATE_CHUNKED = 0, 1, 2
+BATCH_PHASES, BATCH_ONE_LAUNCH = 0, 1
 SHIFT_HOLD, SHIFT_ZERO = 0, 1
 DEBUG_NOISE, DEBUG_COSTS, DEBUG_WEIGHTS, DEBUG_STATS, DEBUG_CRASHES = 0, 1, 2, 3, 4
 PACKED_STATE, PACKED_CONTROLS, PACKED_SAMPLES, PACKED_NOISE = 0, 1, 2, 3
@@ -67,7 +68,7 @@ class Tuning(C.Structure):
     _fields_ = [("lanes_per_sample", C.c_int32), ("rollout_block", C.c_int32),
                 ("batch_tile", C.c_int32), ("noise_calls", C.c_int32),
                 ("rollout_form", C.c_int32), ("cost_waves", C.c_int32),
-                ("update_form", C.c_int32)]
+                ("update_form", C.c_int32), ("batch_form", C.c_int32)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}

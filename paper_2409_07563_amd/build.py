@@ -10,8 +10,8 @@ LIB = os.path.join(HERE, "libmppi.so")
 # measured ceilings for the benchmark (not part of the MPPI path)
 CEIL_LIB = os.path.join(HERE, "libmppi_ceilings.so")
 CEIL_SOURCES = ["ceilings.hip"]
-SOURCES = ["mppi.hip", "noise.hip", "rollout.hip", "rollout_tiles.hip", "softmin.hip", "batch.hip",
-           "adjoint.hip", "split.hip", "controls.hip"]
+SOURCES = ["mppi.hip", "noise.hip", "rollout.hip", "rollout_scan.hip", "rollout_tiles.hip",
+           "softmin.hip", "batch.hip", "adjoint.hip", "split.hip", "controls.hip"]
 ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU

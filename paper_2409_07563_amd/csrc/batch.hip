@@ -76,9 +76,233 @@ __global__ void batch_set_iteration_kernel(const BatchInst* __restrict__ insts, 
   if (i < n) insts[i].st->iteration = iteration;
 }
 
+// ---------------------------------------------------------------------------
+// The one-launch form: a whole iteration of every instance in one launch, no
+// workgroup ever waiting for another.  Workgroup q takes sample tile (i, t)
+// = fused_items[q] of kBatchMaxTile samples (the list is ordered longest
+// horizon first, so the dispatcher starts the long rollouts early) and
+//   1. draws the tile's noise in its lanes (the Philox calls of
+//      batch_noise_kernel, stored to the noise buffer) and rolls out from it;
+//   2. weights the tile's samples against the tile's own minimum m_t
+//      (e_k = exp(-(J_k - m_t)/lambda)) and sums them (as the chunked update's
+//      chunk weights);
+//   3. forms the tile's weighted noise rows N_t[r] = sum_k e_k eps[r][k] from
+//      the noise it has just stored (one thread per row);
+//   4. counts the tile in the instance's completion counter done[i]; the
+//      workgroup that completes the instance's last tile rescales the tiles to
+//      the instance's minimum rho (factor exp(-(m_t - rho)/lambda)) and
+//      updates u[r] += gamma (sum_t f_t N_t[r] / eta - u[r] W_Z), the
+//      statistics and the iteration word, and resets the counter.
+// There is no loop over work items in the kernel (a loop whose exit the
+// compiler cannot prove uniform, with barriers in its body, can be split so
+// that not every path back to a barrier takes the next item).  The costs and
+// the noise are bitwise those of the per-phase launches; the update equals
+// theirs up to the rounding order of its sums (the arithmetic of the chunked
+// update form, with tiles for chunks).
+// ---------------------------------------------------------------------------
+template <class Model, int INTEG, class Cost, bool COUNT>
+__device__ __forceinline__ float tile_rollout_drawn(const BatchInst& b, int tile, float4* lds) {
+  constexpr int M = Model::M;
+  static_assert(4 % M == 0, "whole steps per Philox call");
+  constexpr int SPC = 4 / M;  // steps per Philox call
+  const DevParams& p = b.p;
+  const float* lds_u = stage_rollout_lds<Cost>(p, b.u, b.TM, lds);
+  const int k = tile * kBatchMaxTile + static_cast<int>(threadIdx.x);
+  if (k >= b.K) return __builtin_inff();  // no barrier follows in the tile
+  const uint32_t it = b.st->iteration;
+  const bool zero = p.mean_sample && k == 0;
+  LaneRollout<Model, INTEG, Cost, COUNT> lane(p, b.x0, lds, k < p.n_plain);
+  const int ncall = (b.TM + 3) / 4;
+  for (int c = 0; c < ncall; ++c) {
+    float z[4];
+    noise::emit_call(b.key0, b.key1, it, b.instance, k, c, b.TM, M, b.sigma.v, b.eps, b.ldk,
+                     p.sigma_t, zero, z);
+#pragma unroll
+    for (int q = 0; q < SPC; ++q) {
+      const int t = c * SPC + q;
+      if (t < b.T) lane.step(p, lds_u, lds, t, z + q * M);
+    }
+  }
+  const RolloutResult r = lane.finish(p, b.T, lds);
+  b.S[k] = r.cost;
+  if constexpr (COUNT) b.crashes[k] = r.crashes;
+  return r.cost;
+}
+
+// Steps 2 and 3 for one tile: its minimum and weight sums to tile_stat[t],
+// its weighted noise rows to tile_part[t][.].  S_k: this lane's cost (+inf
+// past the instance's samples).
+__device__ __forceinline__ void tile_softmin_partials(const BatchInst& b, int tile, float S_k) {
+  constexpr int NW = kBatchMaxTile / kWave;
+  __shared__ float lds_m[NW];
+  __shared__ float4 lds4[NW];
+  __shared__ float lds_e[kBatchMaxTile];
+  const float inf = __builtin_inff();
+  const int tid = threadIdx.x;
+  const int k0 = tile * kBatchMaxTile;
+  const int k = k0 + tid;
+  const float mt = block_min<NW>(S_k, lds_m);
+  const float ek = (k < b.K && S_k < inf) ? expf((mt - S_k) * b.inv_lambda) : 0.0f;
+  lds_e[tid] = ek;
+  float4 v{wave_sum(ek), wave_sum(ek * ek), wave_sum(k >= b.p.n_plain ? ek : 0.0f), 0.0f};
+  if (tid % kWave == 0) lds4[tid / kWave] = v;
+  __syncthreads();  // also orders this tile's noise stores before the row reads
+  if (tid == 0) {
+    v = lds4[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) { v.x += lds4[i].x; v.y += lds4[i].y; v.z += lds4[i].z; }
+    b.tile_stat[tile] = float4{mt, v.x, v.y, v.z};
+  }
+  // one thread per row: sum_k e_k eps[r][k] over the tile's samples, 16-byte
+  // loads of the noise row (aligned: ldk is a multiple of 64 and k0 of 256)
+  // and of the weights; the row's padding past K is never read
+  const int nk = min(kBatchMaxTile, b.K - k0);
+  const int nk4 = nk & ~3;
+  const float4* e4 = reinterpret_cast<const float4*>(lds_e);
+  for (int r = tid; r < b.TM; r += kBatchMaxTile) {
+    const float* row = b.eps + static_cast<int64_t>(r) * b.ldk + k0;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    for (int kk = 0; kk < nk4; kk += 4) {
+      const float4 x = *reinterpret_cast<const float4*>(row + kk);
+      const float4 w = e4[kk / 4];
+      a0 += w.x * x.x;
+      a1 += w.y * x.y;
+      a2 += w.z * x.z;
+      a3 += w.w * x.w;
+    }
+    for (int kk = nk4; kk < nk; ++kk) a0 += lds_e[kk] * row[kk];
+    b.tile_part[static_cast<int64_t>(tile) * b.TM + r] = (a0 + a1) + (a2 + a3);
+  }
+}
+
+// Step 4 for the instance's last tile: rho, the tile factors, eta and the
+// statistics, and every row of the update (the chunked update's arithmetic).
+__device__ __forceinline__ void instance_combine(const BatchInst& b, int ntile) {
+  constexpr int NW = kBatchMaxTile / kWave;
+  __shared__ float lds_m[NW];
+  __shared__ float4 lds4[NW];
+  __shared__ float fsc[kOneLaunchMaxTiles];
+  const float inf = __builtin_inff();
+  const int tid = threadIdx.x;
+  float m = inf;
+  for (int c = tid; c < ntile; c += kBatchMaxTile) m = fminf(m, b.tile_stat[c].x);
+  const float rho = block_min<NW>(m, lds_m);
+  const bool finite = rho < inf;
+  float se = 0.0f, se2 = 0.0f, sz = 0.0f;
+  for (int c = tid; c < ntile; c += kBatchMaxTile) {
+    const float4 q = b.tile_stat[c];
+    const float f = (finite && q.x < inf) ? expf((rho - q.x) * b.inv_lambda) : 0.0f;
+    fsc[c] = f;
+    se += q.y * f;
+    se2 += q.z * (f * f);
+    sz += q.w * f;
+  }
+  float4 v{wave_sum(se), wave_sum(se2), wave_sum(sz), 0.0f};
+  __syncthreads();
+  if (tid % kWave == 0) lds4[tid / kWave] = v;
+  __syncthreads();  // also publishes fsc
+  v = lds4[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) { v.x += lds4[i].x; v.y += lds4[i].y; v.z += lds4[i].z; }
+  const float eta = v.x;
+  const float wz = (finite && b.p.n_plain < b.K) ? v.z / eta : 0.0f;
+  for (int r = tid; r < b.TM; r += kBatchMaxTile) {
+    float tot = 0.0f;
+    for (int c = 0; c < ntile; ++c) tot += fsc[c] * b.tile_part[static_cast<int64_t>(c) * b.TM + r];
+    if (eta > 0.0f) {
+      float qv = tot / eta;
+      if (wz != 0.0f) qv -= b.u[r] * wz;
+      b.u[r] = b.u[r] + b.step * qv;
+    }
+  }
+  if (tid == 0) {
+    DevState* st = b.st;
+    st->wz = wz;
+    st->stats[0] = rho;
+    st->stats[1] = finite ? eta : 0.0f;
+    st->stats[2] = finite ? rho - b.lambda * logf(eta / static_cast<float>(b.K)) : inf;
+    st->stats[3] = finite ? (eta * eta) / v.y : 0.0f;
+    st->status = finite ? MPPI_OK : MPPI_ENUMERIC;
+    st->iteration = st->iteration + 1u;
+  }
+}
+
+template <class Model, int INTEG, class Cost, bool COUNT>
+__global__ __launch_bounds__(kBatchMaxTile) void batch_one_launch_kernel(BatchPlan b) {
+  extern __shared__ float4 lds[];
+  __shared__ int s_last;
+  uint32_t* done = b.done;
+  const int2 w = b.fused_items[blockIdx.x];
+  const BatchInst& inst = b.insts[w.x];
+  const float S_k = tile_rollout_drawn<Model, INTEG, Cost, COUNT>(inst, w.y, lds);
+  tile_softmin_partials(inst, w.y, S_k);
+  // the tile's partials are visible before it is counted
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  const int ntile = (inst.K + kBatchMaxTile - 1) / kBatchMaxTile;
+  if (threadIdx.x == 0) {
+    const uint32_t old =
+        __hip_atomic_fetch_add(&done[w.x], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = old + 1u == static_cast<uint32_t>(ntile);
+  }
+  __syncthreads();
+  if (!__builtin_amdgcn_readfirstlane(s_last)) return;  // the whole workgroup
+  // this workgroup completed the instance's last tile
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  instance_combine(inst, ntile);
+  if (threadIdx.x == 0) __hip_atomic_store(&done[w.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 namespace {
 
 using BatchFn = void (*)(const BatchInst*, const int2*);
+using OneLaunchFn = void (*)(BatchPlan);
+
+template <class Model, int INTEG, class Cost>
+OneLaunchFn pick_one_launch(bool count) {
+  if (count) return batch_one_launch_kernel<Model, INTEG, Cost, true>;
+  return batch_one_launch_kernel<Model, INTEG, Cost, false>;
+}
+
+template <class Model, int INTEG>
+OneLaunchFn pick_one_launch_wheeled(uint32_t cost, bool count) {
+  switch (cost) {
+    case MPPI_COST_PATH_CIRCLES: return pick_one_launch<Model, INTEG, CostPath<true>>(count);
+    case MPPI_COST_PATH_COSTMAP: return pick_one_launch<Model, INTEG, CostPath<false>>(count);
+    case MPPI_COST_GOAL_CIRCLES: return pick_one_launch<Model, INTEG, CostGoalCircles>(count);
+    case MPPI_COST_QUADRATIC: return pick_one_launch<Model, INTEG, CostQuadratic>(count);
+    case MPPI_COST_TRACK: return pick_one_launch<Model, INTEG, CostTrack>(count);
+    default: return nullptr;
+  }
+}
+
+template <int INTEG>
+OneLaunchFn pick_one_launch_model(uint32_t dynamics, uint32_t cost, bool accurate, bool count) {
+  switch (dynamics) {
+    case MPPI_DYN_DOUBLE_INTEGRATOR:
+      if (cost == MPPI_COST_QUADRATIC)
+        return pick_one_launch<DoubleIntegrator, INTEG, CostQuadratic>(count);
+      if (cost == MPPI_COST_TRACK) return pick_one_launch<DoubleIntegrator, INTEG, CostTrack>(count);
+      return nullptr;
+    case MPPI_DYN_BICYCLE:
+      return accurate ? pick_one_launch_wheeled<Bicycle<false>, INTEG>(cost, count)
+                      : pick_one_launch_wheeled<Bicycle<true>, INTEG>(cost, count);
+    case MPPI_DYN_QUADROTOR:
+      if (cost == MPPI_COST_HOVER) return pick_one_launch<Quadrotor, INTEG, CostHover>(count);
+      if (cost == MPPI_COST_QUADRATIC)
+        return pick_one_launch<Quadrotor, INTEG, CostQuadratic>(count);
+      if (cost == MPPI_COST_TRACK) return pick_one_launch<Quadrotor, INTEG, CostTrack>(count);
+      return nullptr;
+    default: return nullptr;
+  }
+}
+
+OneLaunchFn pick_one_launch_fn(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                                bool accurate, bool count) {
+  return integrator == MPPI_INT_EULER
+             ? pick_one_launch_model<kEuler>(dynamics, cost, accurate, count)
+             : pick_one_launch_model<kRK4>(dynamics, cost, accurate, count);
+}
 
 template <class Model, int INTEG, class Cost>
 BatchFn pick(bool count) {
@@ -148,6 +372,26 @@ hipError_t launch_batch_update(const BatchPlan& b, hipStream_t stream) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batch_gemv_kernel, dim3(b.n_row_tiles), dim3(kGemvBlock), 0, stream, b.insts,
                      b.row_tiles);
+  return hipGetLastError();
+}
+
+bool batch_one_launch_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost) {
+  return pick_one_launch_fn(dynamics, integrator, cost, false, false) != nullptr;
+}
+
+hipError_t launch_batch_one_launch(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                                   bool accurate_trig, bool count, const BatchPlan& b,
+                                   hipStream_t stream) {
+  OneLaunchFn fn = pick_one_launch_fn(dynamics, integrator, cost, accurate_trig, count);
+  if (!fn || b.n_fused_items < 1) return hipErrorInvalidValue;
+  if (b.rollout_lds > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(b.rollout_lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(b.n_fused_items)), dim3(kBatchMaxTile),
+                     b.rollout_lds, stream, b);
   return hipGetLastError();
 }
 

@@ -123,6 +123,10 @@ struct BatchInst {
   Sigma8 sigma;
   float* e;  // unnormalised weights exp(-(J_k - rho)/lambda) [ldk]
   DevState* st;
+  // the one-launch form's tile partials: weighted noise rows [ntile][TM]
+  // and (minimum, sum e, sum e^2, sum e over the zero-mean samples) [ntile]
+  float* tile_part;
+  float4* tile_stat;
 };
 
 // Work lists of the batched kernels (host-built, device-resident):
@@ -132,21 +136,8 @@ struct BatchInst {
 // each; the autotuner picks it); kBatchMinTile sizes the tile table.
 constexpr int kBatchMaxTile = 256, kBatchMinTile = 64;
 
-// The fused batch launch (one persistent launch per iteration: rollout tiles,
-// the weights of an instance by the workgroup that finishes its last tile, the
-// rows of its update) takes work items from one list through an atomic
-// counter.  Item (i, t) with t >= 0 is sample tile t of instance i; (i, -1 - r)
-// is row r of instance i's update.  Every row item of an instance comes after
-// all of its sample tiles in the list (checked on the host), so a workgroup
-// that waits for an instance's weights waits only for workgroups that are
-// already running its tiles.
-struct BatchSync {
-  uint32_t next;    // next item to hand out (reset by the last workgroup to leave)
-  uint32_t exited;  // workgroups that have left this launch
-  uint32_t epoch;   // launches completed; ready[i] == epoch + 1 once instance i's weights are out
-  uint32_t error;   // a wait for an instance's weights gave up (never expected)
-};
-constexpr uint32_t kFusedSpinLimit = 1u << 24;  // polls (~1 us apart) before a wait gives up
+// Most tiles of one instance in the one-launch batch form (K <= 65536).
+constexpr int kOneLaunchMaxTiles = 256;
 struct BatchPlan {
   const BatchInst* insts;
   const int2* sample_tiles;
@@ -157,12 +148,11 @@ struct BatchPlan {
   int n_inst;
   size_t rollout_lds;
   size_t max_tm_bytes;  // largest T * m of an instance, in bytes (the shift's LDS)
-  // the fused launch (form 1): its item list, counters (BatchSync, then
-  // done[n_inst] tile counters, then ready[n_inst] words) and grid
+  // the one-launch form: its sample tiles of kBatchMaxTile (longest horizon
+  // first; one workgroup each) and the per-instance tile counters
   const int2* fused_items;
   int n_fused_items;
-  BatchSync* sync;
-  int fused_grid;
+  uint32_t* done;
 };
 
 // ---- host launchers (one translation unit each) ---------------------------
@@ -190,6 +180,16 @@ hipError_t launch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                           float* d_S, int32_t* d_crashes, hipStream_t stream, int block = 64,
                           const NoiseJob* next = nullptr);
 bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
+
+// The time-parallel form of (a2) (rollout_scan.hip): the bicycle with RK4, a
+// sample's horizon spread over the 16 lanes of a DPP row (T <= 256); block:
+// threads per workgroup (64, 128, 256).
+bool rollout_scan_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int T);
+hipError_t launch_rollout_scan(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                               bool accurate_trig, const DevParams& p, const float* d_x0,
+                               const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
+                               float* d_S, int32_t* d_crashes, hipStream_t stream, int block,
+                               const NoiseJob* next = nullptr);
 
 // The split form of (a2) (split.hip): a dynamics kernel writes the states
 // x_1..x_T of every sample to d_traj ([T][traj_words][ldk], the state then,
@@ -297,14 +297,13 @@ hipError_t launch_batch_rollout(uint32_t dynamics, uint32_t integrator, uint32_t
                                 bool accurate_trig, bool count, const BatchPlan& b,
                                 hipStream_t stream);
 hipError_t launch_batch_update(const BatchPlan& b, hipStream_t stream);
-// One persistent launch: every rollout tile (tile = kGemvBlock samples), the
-// weights and every row of the update (the noise is drawn before it).
-hipError_t launch_batch_fused(uint32_t dynamics, uint32_t integrator, uint32_t cost,
-                              bool accurate_trig, bool count, const BatchPlan& b,
-                              hipStream_t stream);
-// Workgroups of the fused launch that fit the device at once (0 on error).
-int batch_fused_capacity(uint32_t dynamics, uint32_t integrator, uint32_t cost, bool accurate_trig,
-                         bool count, size_t lds);
+// One launch per iteration for a whole batch: every sample tile
+// (kBatchMaxTile samples) draws its noise, rolls out and leaves its softmin
+// partials; the workgroup that completes an instance's last tile updates it.
+hipError_t launch_batch_one_launch(uint32_t dynamics, uint32_t integrator, uint32_t cost,
+                                   bool accurate_trig, bool count, const BatchPlan& b,
+                                   hipStream_t stream);
+bool batch_one_launch_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
 hipError_t launch_batch_set_iteration(const BatchPlan& b, uint32_t iteration, hipStream_t stream);
 
 // ---- wave / block reductions ------------------------------------------------

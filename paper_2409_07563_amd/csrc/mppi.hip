@@ -454,10 +454,13 @@ struct Instance {
 // views of set_state / set_controls / get_controls / costs are single copies),
 // then the batch tables, then the instance slices.
 struct CtxLayout {
-  size_t states, x0, u, S, crashes, insts, sample_tiles, row_tiles;
+  size_t states, x0, u, S, crashes, insts, sample_tiles, row_tiles, one_items, done;
+  size_t tile_part, tile_stat;  // the one-launch form's tile partials (packed)
   std::vector<size_t> slice;
   size_t total;
   int n_sample_tiles, n_row_tiles;
+  int64_t n_one_items;  // tiles of kBatchMaxTile samples
+  int64_t n_tile_part;  // floats of tile partial rows: sum_i ntile_i T_i m_i
 };
 
 CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, int n_inst,
@@ -467,6 +470,8 @@ CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, in
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   int64_t nx = 0, nu = 0, nS = 0;
   C.n_sample_tiles = C.n_row_tiles = 0;
+  C.n_one_items = 0;
+  C.n_tile_part = 0;
   for (int i = 0; i < n_inst; ++i) {
     int n, m;
     model_dims(cfgs[i].dynamics, &n, &m);
@@ -476,6 +481,9 @@ CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, in
     const int TM = cfgs[i].horizon * m;
     C.n_sample_tiles += (cfgs[i].num_samples + kBatchMinTile - 1) / kBatchMinTile;
     C.n_row_tiles += (TM + gemv_rows_per_block() - 1) / gemv_rows_per_block();
+    const int64_t ntile = (cfgs[i].num_samples + kBatchMaxTile - 1) / kBatchMaxTile;
+    C.n_one_items += ntile;
+    C.n_tile_part += ntile * TM;
   }
   C.states = take(sizeof(DevState) * n_inst);
   C.x0 = take(sizeof(float) * (nx + MPPI_MAX_STATE));
@@ -486,6 +494,10 @@ CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, in
     C.insts = take(sizeof(BatchInst) * n_inst);
     C.sample_tiles = take(sizeof(int2) * C.n_sample_tiles);
     C.row_tiles = take(sizeof(int2) * C.n_row_tiles);
+    C.one_items = take(sizeof(int2) * C.n_one_items);
+    C.done = take(sizeof(uint32_t) * n_inst);
+    C.tile_part = take(sizeof(float) * C.n_tile_part);
+    C.tile_stat = take(sizeof(float4) * C.n_one_items);
   }
   C.slice.resize(n_inst);
   for (int i = 0; i < n_inst; ++i) {
@@ -814,9 +826,11 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
 
   // batch tables
   std::vector<BatchInst> bi;
-  std::vector<WorkItem> row_tiles;
+  std::vector<WorkItem> row_tiles, one_items;
   if (batch && e == hipSuccess) {
     size_t lds = 0;
+    int64_t part_off = 0, stat_off = 0;
+    bool one_ok = true;  // every instance within the one-launch form's tile limit
     for (int i = 0; i < n_inst; ++i) {
       const Instance& I = c->inst[i];
       BatchInst b{};
@@ -833,6 +847,12 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
       for (int j = 0; j < I.m; ++j) b.sigma.v[j] = cfgs[i].sigma[j];
       b.e = I.e();
       b.st = I.st;
+      b.tile_part = reinterpret_cast<float*>(c->ws + C.tile_part) + part_off;
+      b.tile_stat = reinterpret_cast<float4*>(c->ws + C.tile_stat) + stat_off;
+      const int64_t ntile_i = (I.K + kBatchMaxTile - 1) / kBatchMaxTile;
+      part_off += ntile_i * I.TM;
+      stat_off += ntile_i;
+      one_ok = one_ok && ntile_i <= kOneLaunchMaxTiles;
       bi.push_back(b);
       lds = std::max(lds, rollout_lds_bytes(cfgs[i].dynamics, cfgs[i].cost, I.dp.stage_words4, I.T));
     }
@@ -863,6 +883,30 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
     size_t tm = 0;
     for (int i = 0; i < n_inst; ++i) tm = std::max(tm, sizeof(float) * c->inst[i].TM);
     P.max_tm_bytes = tm;
+    // the one-launch form: its tiles (longest horizon first, checked) and
+    // zeroed per-instance tile counters, where the combination has a kernel
+    // and every instance at most kOneLaunchMaxTiles tiles
+    P.fused_items = reinterpret_cast<const int2*>(c->ws + C.one_items);
+    P.n_fused_items = 0;
+    P.done = reinterpret_cast<uint32_t*>(c->ws + C.done);
+    if (e == hipSuccess) e = hipMemsetAsync(P.done, 0, sizeof(uint32_t) * n_inst, c->stream);
+    if (one_ok && batch_one_launch_supported(cfgs[0].dynamics, cfgs[0].integrator, cfgs[0].cost) &&
+        e == hipSuccess) {
+      std::vector<int32_t> Kv(n_inst), Tv(n_inst);
+      for (int i = 0; i < n_inst; ++i) { Kv[i] = c->inst[i].K; Tv[i] = c->inst[i].T; }
+      one_items = build_sample_tiles(Kv.data(), Tv.data(), n_inst, kBatchMaxTile);
+      const std::string bad2 = check_work_list(one_items.data(),
+                                               static_cast<int64_t>(one_items.size()),
+                                               C.n_one_items, kBatchMaxTile, Kv.data(), n_inst);
+      if (!bad2.empty()) {
+        (void)hipStreamSynchronize(c->stream);
+        delete c;
+        return fail(MPPI_EINVAL, "one-launch work list: %s", bad2.c_str());
+      }
+      e = hipMemcpyAsync(c->ws + C.one_items, one_items.data(),
+                         sizeof(WorkItem) * one_items.size(), hipMemcpyHostToDevice, c->stream);
+      P.n_fused_items = static_cast<int>(one_items.size());
+    }
   }
   const hipError_t e2 = hipStreamSynchronize(c->stream);  // host staging buffers die here
   if (e == hipSuccess) e = e2;
@@ -877,6 +921,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   c->tune.noise_calls = 1;
   c->tune.rollout_form = MPPI_ROLLOUT_FUSED;
   c->tune.cost_waves = 8;
+  c->tune.batch_form = MPPI_BATCH_PHASES;
   c->tune.update_form = one_pass_for(c)  ? MPPI_UPDATE_ONE_PASS
                         : chunked_for(c) ? MPPI_UPDATE_CHUNKED
                                          : MPPI_UPDATE_TWO_PASS;
@@ -955,6 +1000,10 @@ hipError_t phase_rollout(mppi_ctx* c, bool next = false) {
                                 c->tune.rollout_block, c->tune.cost_waves);
   NoiseJob job{};
   if (next) job = next_noise_job(c);
+  if (c->tune.rollout_form == MPPI_ROLLOUT_SCAN)
+    return launch_rollout_scan(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp, I.x0,
+                               I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
+                               c->stream, c->tune.rollout_block, next ? &job : nullptr);
   return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.lanes, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
                         c->stream, c->tune.rollout_block, next ? &job : nullptr);
@@ -996,6 +1045,13 @@ hipError_t phase_update(mppi_ctx* c, bool next = false) {
 // and switches buffers.  Other contexts sample in every iteration.
 hipError_t phase_iteration(mppi_ctx* c, int i, bool ahead) {
   hipError_t e = hipSuccess;
+  if (c->batch && c->tune.batch_form == MPPI_BATCH_ONE_LAUNCH) {
+    const Instance& I = c->one();
+    const bool count = (I.cfg.flags & MPPI_F_DEBUG) && uses_circles(I.cfg.cost);
+    const bool accurate = (I.cfg.flags & MPPI_F_ACCURATE_TRIG) != 0;
+    return launch_batch_one_launch(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, count,
+                                   c->plan, c->stream);
+  }
   if (c->batch || !c->one().ahead_ok) {
     e = phase_sample(c);
     if (e == hipSuccess) e = phase_rollout(c);
@@ -1087,12 +1143,26 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
   if (cw < 1 || cw > kSplitMaxWaves * kSplitMaxChunks || (cw & (cw - 1)))
     return fail(MPPI_EINVAL, "cost_waves must be a power of two from 1 to %d",
                 kSplitMaxWaves * kSplitMaxChunks);
-  if (t->rollout_form != MPPI_ROLLOUT_FUSED && t->rollout_form != MPPI_ROLLOUT_SPLIT)
-    return fail(MPPI_EINVAL, "rollout_form must be MPPI_ROLLOUT_FUSED or MPPI_ROLLOUT_SPLIT");
+  if (t->rollout_form != MPPI_ROLLOUT_FUSED && t->rollout_form != MPPI_ROLLOUT_SPLIT &&
+      t->rollout_form != MPPI_ROLLOUT_SCAN)
+    return fail(MPPI_EINVAL, "rollout_form must be MPPI_ROLLOUT_FUSED, MPPI_ROLLOUT_SPLIT or "
+                "MPPI_ROLLOUT_SCAN");
   if (t->update_form != MPPI_UPDATE_TWO_PASS && t->update_form != MPPI_UPDATE_ONE_PASS &&
       t->update_form != MPPI_UPDATE_CHUNKED)
     return fail(MPPI_EINVAL, "update_form must be MPPI_UPDATE_TWO_PASS, MPPI_UPDATE_ONE_PASS "
                 "or MPPI_UPDATE_CHUNKED");
+  if (t->batch_form != MPPI_BATCH_PHASES && t->batch_form != MPPI_BATCH_ONE_LAUNCH)
+    return fail(MPPI_EINVAL, "batch_form must be MPPI_BATCH_PHASES or MPPI_BATCH_ONE_LAUNCH");
+  if (t->batch_form == MPPI_BATCH_ONE_LAUNCH) {
+    if (!c->batch)
+      return fail(MPPI_EUNSUPPORTED, "the one-launch form is a form of batch contexts");
+    if (c->plan.n_fused_items < 1)
+      return fail(MPPI_EUNSUPPORTED, "no one-launch kernel for this batch's dynamics and cost, "
+                  "or an instance with more than %d samples", kOneLaunchMaxTiles * kBatchMaxTile);
+    if (t->batch_tile != kBatchMaxTile || t->update_form != MPPI_UPDATE_TWO_PASS)
+      return fail(MPPI_EUNSUPPORTED, "the one-launch form needs batch_tile %d and the "
+                  "two-pass update setting", kBatchMaxTile);
+  }
   if (t->update_form == MPPI_UPDATE_ONE_PASS && !one_pass_for(c))
     return fail(MPPI_EUNSUPPORTED, "the single-pass update exists for single contexts with at "
                 "most %d samples (no gradient mode)", kOnePassMaxK);
@@ -1108,6 +1178,14 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
         !(t->lanes_per_sample == 4 && rollout_quad_available(I.cfg.dynamics, I.cfg.integrator)))
       return fail(MPPI_EUNSUPPORTED, "split form: lanes_per_sample 1, or 4 for the bicycle "
                   "with RK4");
+  }
+  if (t->rollout_form == MPPI_ROLLOUT_SCAN) {
+    if (c->batch || I.hidden || I.grad ||
+        !rollout_scan_supported(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, I.T))
+      return fail(MPPI_EUNSUPPORTED, "the scan rollout form exists for single contexts with "
+                  "bicycle dynamics, RK4 and at most 256 steps (no gradient mode)");
+    if (t->lanes_per_sample != 16)
+      return fail(MPPI_EINVAL, "scan form: lanes_per_sample must be 16");
   }
   if (I.hidden || I.grad) {
     // waves per 16-sample tile: 1, or the MLP split over 2 (H = 32, 64) or 4 (H = 64)
@@ -1167,11 +1245,11 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     return err;
   };
   auto line = [&](const char* phase, const mppi_tuning& t, double us) {
-    char buf[192];
+    char buf[208];
     snprintf(buf, sizeof buf,
-             "%s lanes=%d block=%d tile=%d calls=%d form=%d waves=%d update=%d %.2f\n", phase,
-             t.lanes_per_sample, t.rollout_block, t.batch_tile, t.noise_calls, t.rollout_form,
-             t.cost_waves, t.update_form, us);
+             "%s lanes=%d block=%d tile=%d calls=%d form=%d waves=%d update=%d batch=%d %.2f\n",
+             phase, t.lanes_per_sample, t.rollout_block, t.batch_tile, t.noise_calls,
+             t.rollout_form, t.cost_waves, t.update_form, t.batch_form, us);
     text += buf;
   };
   // Each group of candidates shapes one phase; the candidates of a group are
@@ -1221,6 +1299,37 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     }
     st = search("sample+rollout", cands, sample_rollout, &best);
     if (st != MPPI_OK) return done(st);
+    if (c->plan.n_fused_items > 0) {
+      // a whole iteration in each batch form; u and the instances' scalars
+      // (iteration words) are put back afterwards
+      std::vector<float> u_save(static_cast<size_t>(c->n_u));
+      std::vector<DevState> st_save(c->inst.size());
+      e = hipMemcpyAsync(u_save.data(), c->ws + c->C.u, sizeof(float) * u_save.size(),
+                         hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(st_save.data(), c->ws + c->C.states, sizeof(DevState) * st_save.size(),
+                           hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return done(hip_fail(e, "autotune save"));
+      std::vector<mppi_tuning> forms;
+      mppi_tuning a = best;
+      a.batch_form = MPPI_BATCH_PHASES;
+      forms.push_back(a);
+      mppi_tuning b2 = best;
+      b2.batch_tile = kBatchMaxTile;
+      b2.update_form = MPPI_UPDATE_TWO_PASS;
+      b2.batch_form = MPPI_BATCH_ONE_LAUNCH;
+      forms.push_back(b2);
+      st = search("iteration", forms, [&] { return phase_iteration(c, 0, false); }, &best);
+      e = hipMemcpyAsync(c->ws + c->C.u, u_save.data(), sizeof(float) * u_save.size(),
+                         hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + c->C.states, st_save.data(), sizeof(DevState) * st_save.size(),
+                           hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (st != MPPI_OK) return done(st);
+      if (e != hipSuccess) return done(hip_fail(e, "autotune restore"));
+    }
   } else {
     std::vector<mppi_tuning> cands;
     for (int calls : {1, 2, 4}) {
@@ -1254,6 +1363,15 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
           cands.push_back(t);
         }
       }
+      // the time-parallel scan form
+      if (rollout_scan_supported(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, I.T))
+        for (int block : {64, 128, 256}) {
+          mppi_tuning t = best;
+          t.rollout_form = MPPI_ROLLOUT_SCAN;
+          t.lanes_per_sample = 16;
+          t.rollout_block = block;
+          cands.push_back(t);
+        }
       // the split form (section "Choosing between the Split and Combined
       // Kernels": both are timed, the faster is kept)
       if (I.split)

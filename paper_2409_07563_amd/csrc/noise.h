@@ -113,12 +113,13 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
 // Philox call c of sample k: the four normals n = 4c .. 4c+3 (n = t*m + j),
 // scaled by sigma_j (or sigma_t[n] when a per-step table is given) and stored
 // at eps[n * ldk + k] (n < TM); zero for every n when `zero` (the noiseless
-// mean sample).
+// mean sample).  out (optional): the four values as stored (entries n >= TM
+// are computed but not stored).
 __device__ __forceinline__ void emit_call(uint32_t key0, uint32_t key1, uint32_t iteration,
                                           uint32_t instance, int k, int c, int TM, int m,
                                           const float* sigma, float* __restrict__ eps,
                                           int64_t ldk, const float* __restrict__ sigma_t = nullptr,
-                                          bool zero = false) {
+                                          bool zero = false, float* out = nullptr) {
   const Words w = philox4x32_10(static_cast<uint32_t>(c), static_cast<uint32_t>(k), iteration,
                                 instance, key0, key1);
   float z[4];
@@ -142,7 +143,9 @@ __device__ __forceinline__ void emit_call(uint32_t key0, uint32_t key1, uint32_t
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int n = n0 + s;
-    if (n < TM) eps[static_cast<int64_t>(n) * ldk + k] = zero ? 0.0f : sg[s] * z[s];
+    const float v = zero ? 0.0f : sg[s] * z[s];
+    if (n < TM) eps[static_cast<int64_t>(n) * ldk + k] = v;
+    if (out) out[s] = v;
   }
 }
 

@@ -131,30 +131,39 @@ struct RolloutResult {
   int crashes;
 };
 
-// One lane per sample: e points at eps[0][0][k] of this lane's sample;
-// plain: the sample is drawn around u (else around zero, v = eps).
+// The state of one sample's rollout in one lane: the model state and its
+// compensation, the cost's state and the compensated running-cost sum.
+// step(t, n) takes the noise n of step t (M floats): v = mean u_t + n (an
+// unconditional load of u and one FMA, exactly u + n for mean = 1, so no
+// branch guards the load), one dynamics step, the running cost on the new
+// state; finish(T) adds the terminal cost.
 template <class Model, int INTEG, class Cost, bool COUNT>
-__device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
-                                                      const float* __restrict__ x0,
-                                                      const float* lds_u,
-                                                      const float* __restrict__ e, int64_t ldk,
-                                                      int T, const float4* lds, bool plain) {
-  constexpr int N = Model::N, M = Model::M;
+struct LaneRollout {
+  static constexpr int N = Model::N, M = Model::M;
   float x[N], comp[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
   typename Cost::State cs;
-  Cost::init(cs, x, p, lds);
-  float sum = 0.0f, sum_c = 0.0f;
-  int ncrash = 0;
-  // v = mean u + eps: an unconditional load of u and one FMA (exactly u + eps
-  // for mean = 1), so no branch guards the load
-  const float mean = plain ? 1.0f : 0.0f;
-  auto body = [&](int t, const float* n, int) {
+  float sum, sum_c;
+  int ncrash;
+  float mean;
+  bool plain;
+
+  __device__ __forceinline__ LaneRollout(const DevParams& p, const float* __restrict__ x0,
+                                         const float4* lds, bool plain_) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
+    Cost::init(cs, x, p, lds);
+    sum = 0.0f;
+    sum_c = 0.0f;
+    ncrash = 0;
+    plain = plain_;
+    mean = plain ? 1.0f : 0.0f;
+  }
+  __device__ __forceinline__ void step(const DevParams& p, const float* lds_u, const float4* lds,
+                                       int t, const float* n) {
     float v[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) v[j] = mean * lds_u[t * M + j] + n[j];
-    step<Model, INTEG>(x, v, comp, p);
+    mppi::step<Model, INTEG>(x, v, comp, p);
     bool hit;
     float l = Cost::template running<N, M>(x, comp, v, t, p, lds, cs, hit);
     if (p.importance && plain) l += is_term<M>(p, t, v, lds_u + t * M);
@@ -164,7 +173,24 @@ __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
     const float s = sum + y;
     sum_c = (s - sum) - y;
     sum = s;
-  };
+  }
+  __device__ __forceinline__ RolloutResult finish(const DevParams& p, int T, const float4* lds) {
+    const float tot = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
+    return RolloutResult{__builtin_isfinite(tot) ? tot : __builtin_inff(), ncrash};
+  }
+};
+
+// One lane per sample: e points at eps[0][0][k] of this lane's sample;
+// plain: the sample is drawn around u (else around zero, v = eps).
+template <class Model, int INTEG, class Cost, bool COUNT>
+__device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
+                                                      const float* __restrict__ x0,
+                                                      const float* lds_u,
+                                                      const float* __restrict__ e, int64_t ldk,
+                                                      int T, const float4* lds, bool plain) {
+  constexpr int M = Model::M;
+  LaneRollout<Model, INTEG, Cost, COUNT> lane(p, x0, lds, plain);
+  auto body = [&](int t, const float* n, int) { lane.step(p, lds_u, lds, t, n); };
   if constexpr (M <= 2) {
     noise_steps<M, 8>(e, ldk, T, body);  // noise requested 8 steps ahead
   } else {
@@ -178,8 +204,7 @@ __device__ __forceinline__ RolloutResult rollout_lane(const DevParams& p,
       body(t, n, 0);
     }
   }
-  sum = sum + (terminal_cost<Cost, N>(x, T, p, lds, cs) - sum_c);
-  return RolloutResult{__builtin_isfinite(sum) ? sum : __builtin_inff(), ncrash};
+  return lane.finish(p, T, lds);
 }
 
 }  // namespace mppi

@@ -183,12 +183,13 @@ def test_split_form_refused_where_it_does_not_exist(mppi):
 
 def test_autotuner_considers_both_forms(mppi, oracle_lib):
     """With a heavy cost (200 nested cosines per step) the tuner times the
-    fused and the split forms; whichever it keeps, the costs stay at parity."""
+    fused, split and (the bicycle with RK4) scan forms; whichever it keeps,
+    the costs stay at parity."""
     wl = W.c2("circles", K=2048, T=100, iters=1).replace(cost_cosines=200)
     ctl = mppi.Controller(wl)
     res = ctl.autotune(reps=3)
     forms = {r.get("form") for r in res["timings"] if r["phase"] == "rollout"}
-    assert forms == {0, 1}
+    assert forms == {0, 1, 2}
     ctl.sample()
     ctl.rollout()
     S = _np(ctl.costs()).astype(np.float64)
