@@ -225,6 +225,28 @@ mppi_status mppi_create(const mppi_config* cfg, const mppi_params* params,
                         void* d_workspace, size_t workspace_bytes, void* hip_stream,
                         mppi_ctx** out);
 
+/* ---- a context that allocates nothing --------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  As
+ * mppi_create for one instance, but the workspace is a fixed array of
+ * MPPI_STATIC_WORKSPACE_BYTES that libmppi.so holds on every GPU it runs on
+ * (each GPU its own copy) until the process ends; the call and the context's
+ * later calls allocate no device memory (no hipMalloc, hipFree or allocating
+ * library routine).  The context uses the current device; hip_stream, if not
+ * NULL, must belong to it.  The array keeps the previous context's contents:
+ * creation initialises everything an iteration reads before writing it, as
+ * mppi_create does for a fresh workspace.  Every context created here on one
+ * GPU shares that GPU's array, so work of two such contexts overlapping in
+ * time would race: one lives per GPU at a time (a second call on the device
+ * returns MPPI_ESTATE until the first is destroyed), and mppi_destroy of such
+ * a context waits for its stream before it frees the array for the next one.
+ * Errors: as mppi_create; MPPI_ENOMEM when mppi_workspace_bytes exceeds
+ * MPPI_STATIC_WORKSPACE_BYTES (the message gives both sizes); MPPI_ESTATE as
+ * above; MPPI_EINVAL for a stream of another device. */
+#define MPPI_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+mppi_status mppi_create_static(const mppi_config* cfg, const mppi_params* params,
+                               void* hip_stream, mppi_ctx** out);
+
 /* ---- batches (spec extension: many independent instances) ----------
  * A batch context holds n independent MPPI instances that share dynamics,
  * integrator, cost kind and flags but each have their own K, T, dt, lambda,

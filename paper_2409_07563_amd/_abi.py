@@ -78,6 +78,8 @@ EXPORTS = {
     "mppi_workspace_bytes": (C.c_size_t, [C.POINTER(Config), C.POINTER(Params)]),
     "mppi_create": (C.c_int, [C.POINTER(Config), C.POINTER(Params), C.c_void_p, C.c_size_t,
                               C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mppi_create_static": (C.c_int, [C.POINTER(Config), C.POINTER(Params), C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
     "mppi_set_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mppi_set_controls": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mppi_set_iteration": (C.c_int, [C.c_void_p, C.c_uint32]),

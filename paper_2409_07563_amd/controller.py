@@ -109,12 +109,17 @@ class Controller:
     requires_grad: keep what `backward` needs (state checkpoints every
     `checkpoint_every` steps and the controls of the rollout) and a tape of
     `tape_len` updates for `backward_iters`.
+
+    static_workspace: run on the library's own per-GPU workspace
+    (mppi_create_static: no device allocation for the context; one such
+    controller per GPU at a time; single instances only).
     """
 
     def __init__(self, problem, device: str | torch.device = "cuda", debug: bool = False,
                  accurate_trig: bool = False, rollout: str = "auto",
                  stream: torch.cuda.Stream | None = None, requires_grad: bool = False,
-                 checkpoint_every: int = 10, tape_len: int = 16):
+                 checkpoint_every: int = 10, tape_len: int = 16,
+                 static_workspace: bool = False):
         self.device = torch.device(device)
         self.requires_grad = bool(requires_grad)
         self.batch = isinstance(problem, (list, tuple))
@@ -140,15 +145,24 @@ class Controller:
             raise _abi.MPPIError(_abi.MPPI_EINVAL, L.mppi_last_error().decode())
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self._enter()
-        with torch.cuda.stream(self.stream):
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         ctx = C.c_void_p()
-        if self.batch:
-            check(L.mppi_create_batch(cfgs, params, self.n_inst, self.workspace.data_ptr(), nbytes,
-                                      self.stream.cuda_stream, C.byref(ctx)))
+        if static_workspace:
+            if self.batch:
+                raise ValueError("static_workspace is for single instances")
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                check(L.mppi_create_static(C.byref(cfgs[0]), C.byref(params[0]),
+                                           self.stream.cuda_stream, C.byref(ctx)))
         else:
-            check(L.mppi_create(C.byref(cfgs[0]), C.byref(params[0]), self.workspace.data_ptr(),
-                                nbytes, self.stream.cuda_stream, C.byref(ctx)))
+            with torch.cuda.stream(self.stream):
+                self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self.batch:
+                check(L.mppi_create_batch(cfgs, params, self.n_inst, self.workspace.data_ptr(),
+                                          nbytes, self.stream.cuda_stream, C.byref(ctx)))
+            else:
+                check(L.mppi_create(C.byref(cfgs[0]), C.byref(params[0]),
+                                    self.workspace.data_ptr(), nbytes, self.stream.cuda_stream,
+                                    C.byref(ctx)))
         self.ctx = ctx
         self._off = {k: self._offsets(k) for k in (_abi.PACKED_STATE, _abi.PACKED_CONTROLS,
                                                    _abi.PACKED_SAMPLES, _abi.PACKED_NOISE)}

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,20 @@ using namespace mppi;
 namespace {
 
 thread_local std::string g_last_error = "";
+
+// The workspace of mppi_create_static: a fixed array every GPU this library
+// runs on holds (its own copy at its own address) until the process ends.  In
+// host code the name only stands for the array; its device address comes from
+// hipGetSymbolAddress on that device, kept per device below.
+constexpr size_t kStaticWorkspaceBytes = MPPI_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) char scratch[kStaticWorkspaceBytes];
+constexpr int kMaxStaticDevices = 64;
+struct StaticWorkspace {
+  char* ptr = nullptr;  // device address on that device (set on first use)
+  bool busy = false;    // a live context holds it
+};
+std::mutex g_static_mu;
+StaticWorkspace g_static[kMaxStaticDevices];
 
 mppi_status fail(mppi_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 mppi_status fail(mppi_status s, const char* fmt, ...) {
@@ -529,6 +544,9 @@ struct mppi_ctx {
   // the current iteration word into the other buffer, and nothing since has
   // changed the word or the buffers (the next mppi_iterate starts from it)
   bool ahead = false;
+  // device whose static workspace this context holds (mppi_create_static),
+  // else -1
+  int static_device = -1;
   // mppi_iterate launch sequences, keyed by (iterations, first noise buffer,
   // whether its noise was drawn ahead)
   std::map<int64_t, hipGraphExec_t> graphs;
@@ -1103,7 +1121,73 @@ mppi_status mppi_create_batch(const mppi_config* cfgs, const mppi_params* params
   return create_ctx(cfgs, params, n, true, d_workspace, workspace_bytes, hip_stream, out);
 }
 
-void mppi_destroy(mppi_ctx* ctx) { delete ctx; }
+mppi_status mppi_create_static(const mppi_config* cfg, const mppi_params* p, void* hip_stream,
+                               mppi_ctx** out) {
+  if (!out) return fail(MPPI_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  const size_t need = mppi_workspace_bytes(cfg, p);
+  if (need == 0) return MPPI_EINVAL;  // message set by the size query
+  if (need > kStaticWorkspaceBytes)
+    return fail(MPPI_ENOMEM, "this configuration needs a workspace of %zu bytes; the static "
+                "workspace holds %zu (use mppi_create with a workspace of your own)",
+                need, kStaticWorkspaceBytes);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  if (dev < 0 || dev >= kMaxStaticDevices)
+    return fail(MPPI_EUNSUPPORTED, "device %d: static workspaces exist for devices 0..%d", dev,
+                kMaxStaticDevices - 1);
+  if (hip_stream) {
+    int sdev = -1;
+    e = hipStreamGetDevice(static_cast<hipStream_t>(hip_stream), &sdev);
+    if (e != hipSuccess) return hip_fail(e, "stream device");
+    if (sdev != dev)
+      return fail(MPPI_EINVAL, "the stream belongs to device %d but device %d is current", sdev,
+                  dev);
+  }
+  char* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticWorkspace& W = g_static[dev];
+    if (W.busy)
+      return fail(MPPI_ESTATE, "device %d's static workspace belongs to a live context; "
+                  "destroy that context first", dev);
+    if (!W.ptr) {
+      // the array's device address on the current device (each GPU holds its
+      // own copy); taken once per device and kept
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return hip_fail(e, "static workspace address");
+      if (!ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign)
+        return fail(MPPI_EDEVICE, "static workspace at %p is not %zu-byte aligned", ptr, kAlign);
+      W.ptr = static_cast<char*>(ptr);
+    }
+    W.busy = true;
+    ws = W.ptr;
+  }
+  const mppi_status st = create_ctx(cfg, p, 1, false, ws, kStaticWorkspaceBytes, hip_stream, out);
+  if (st != MPPI_OK) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[dev].busy = false;
+    return st;
+  }
+  (*out)->static_device = dev;
+  return MPPI_OK;
+}
+
+void mppi_destroy(mppi_ctx* ctx) {
+  if (!ctx) return;
+  const int dev = ctx->static_device;
+  if (dev >= 0) {
+    // the next static context reuses the array: the work enqueued on it ends first
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[dev].busy = false;
+    return;
+  }
+  delete ctx;
+}
 
 int32_t mppi_num_instances(const mppi_ctx* c) { return c ? static_cast<int32_t>(c->inst.size()) : 0; }
 
