@@ -607,7 +607,8 @@ def main():
         line = headline_line(args, r, config={k: r[k] for k in (
             "workload", "instances", "sum_K_T", "K_range", "T_range", "obstacles_range",
             "iterations_per_step", "cost")}, **{k: v for k, v in r.items() if k in (
-                "tuning", "looped_single_contexts", "roofline", "kernels")})
+                "tuning", "looped_single_contexts", "roofline", "kernels",
+                "batch_forms_ms_per_step")})
         if not args.no_cpu_baseline:
             line["cpu_baseline"] = cpu_baseline_batch(wl, 8, 128)
     elif wl.model == "bicycle_mlp":
@@ -659,6 +660,7 @@ def main_all(args):
                          roofline=lead["roofline"], kernels=lead["kernels"],
                          tuning=lead["tuning"],
                          looped_single_contexts=lead.get("looped_single_contexts"),
+                         batch_forms_ms_per_step=lead.get("batch_forms_ms_per_step"),
                          legs={"c3": c3, "c2": c2, "c5": c5, "c1": c1},
                          ceilings=ceil)
     if not args.no_cpu_baseline:
