@@ -112,16 +112,24 @@ __device__ __forceinline__ float tile_rollout_drawn(const BatchInst& b, int tile
   const uint32_t it = b.st->iteration;
   const bool zero = p.mean_sample && k == 0;
   LaneRollout<Model, INTEG, Cost, COUNT> lane(p, b.x0, lds, k < p.n_plain);
+  // kCalls Philox calls are drawn together (independent chains the
+  // scheduler interleaves), then their steps run
+  constexpr int kCalls = 4;
   const int ncall = (b.TM + 3) / 4;
-  for (int c = 0; c < ncall; ++c) {
-    float z[4];
-    noise::emit_call(b.key0, b.key1, it, b.instance, k, c, b.TM, M, b.sigma.v, b.eps, b.ldk,
-                     p.sigma_t, zero, z);
+  for (int c0 = 0; c0 < ncall; c0 += kCalls) {
+    float z[kCalls][4];
 #pragma unroll
-    for (int q = 0; q < SPC; ++q) {
-      const int t = c * SPC + q;
-      if (t < b.T) lane.step(p, lds_u, lds, t, z + q * M);
-    }
+    for (int g = 0; g < kCalls; ++g)
+      if (c0 + g < ncall)
+        noise::emit_call(b.key0, b.key1, it, b.instance, k, c0 + g, b.TM, M, b.sigma.v, b.eps,
+                         b.ldk, p.sigma_t, zero, z[g]);
+#pragma unroll
+    for (int g = 0; g < kCalls; ++g)
+#pragma unroll
+      for (int q = 0; q < SPC; ++q) {
+        const int t = (c0 + g) * SPC + q;
+        if (t < b.T) lane.step(p, lds_u, lds, t, z[g] + q * M);
+      }
   }
   const RolloutResult r = lane.finish(p, b.T, lds);
   b.S[k] = r.cost;
@@ -129,23 +137,43 @@ __device__ __forceinline__ float tile_rollout_drawn(const BatchInst& b, int tile
   return r.cost;
 }
 
+// The sum of v over the wave, returned to every lane: a prefix sum over each
+// 16-lane row (DPP row_shr 1, 2, 4, 8), then the row totals carried across
+// rows (row_bcast 15 into rows 1 and 3, row_bcast 31 into rows 2 and 3), so
+// lane 63 holds the total in a fixed order.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ float wave_dpp(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, BOUND));
+}
+__device__ __forceinline__ float wave_total(float v) {
+  v += wave_dpp<0x111, 0xF, true>(v);   // row_shr:1
+  v += wave_dpp<0x112, 0xF, true>(v);   // row_shr:2
+  v += wave_dpp<0x114, 0xF, true>(v);   // row_shr:4
+  v += wave_dpp<0x118, 0xF, true>(v);   // row_shr:8
+  v += wave_dpp<0x142, 0xA, false>(v);  // row_bcast:15 into rows 1 and 3
+  v += wave_dpp<0x143, 0xC, false>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1));
+}
+
 // Steps 2 and 3 for one tile: its minimum and weight sums to tile_stat[t],
 // its weighted noise rows to tile_part[t][.].  S_k: this lane's cost (+inf
 // past the instance's samples).
 __device__ __forceinline__ void tile_softmin_partials(const BatchInst& b, int tile, float S_k) {
   constexpr int NW = kBatchMaxTile / kWave;
+  constexpr int kRows = kWave;  // rows per round (one per lane of the combine)
+  constexpr int kIn = 8;        // rows whose loads are in flight at once
   __shared__ float lds_m[NW];
   __shared__ float4 lds4[NW];
-  __shared__ float lds_e[kBatchMaxTile];
+  __shared__ float part[NW][kRows];
   const float inf = __builtin_inff();
-  const int tid = threadIdx.x;
-  const int k0 = tile * kBatchMaxTile;
-  const int k = k0 + tid;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  const int k = tile * kBatchMaxTile + tid;
+  const bool valid = k < b.K;
   const float mt = block_min<NW>(S_k, lds_m);
-  const float ek = (k < b.K && S_k < inf) ? expf((mt - S_k) * b.inv_lambda) : 0.0f;
-  lds_e[tid] = ek;
+  const float ek = (valid && S_k < inf) ? expf((mt - S_k) * b.inv_lambda) : 0.0f;
   float4 v{wave_sum(ek), wave_sum(ek * ek), wave_sum(k >= b.p.n_plain ? ek : 0.0f), 0.0f};
-  if (tid % kWave == 0) lds4[tid / kWave] = v;
+  if (lane == 0) lds4[wv] = v;
   __syncthreads();  // also orders this tile's noise stores before the row reads
   if (tid == 0) {
     v = lds4[0];
@@ -153,25 +181,33 @@ __device__ __forceinline__ void tile_softmin_partials(const BatchInst& b, int ti
     for (int i = 1; i < NW; ++i) { v.x += lds4[i].x; v.y += lds4[i].y; v.z += lds4[i].z; }
     b.tile_stat[tile] = float4{mt, v.x, v.y, v.z};
   }
-  // one thread per row: sum_k e_k eps[r][k] over the tile's samples, 16-byte
-  // loads of the noise row (aligned: ldk is a multiple of 64 and k0 of 256)
-  // and of the weights; the row's padding past K is never read
-  const int nk = min(kBatchMaxTile, b.K - k0);
-  const int nk4 = nk & ~3;
-  const float4* e4 = reinterpret_cast<const float4*>(lds_e);
-  for (int r = tid; r < b.TM; r += kBatchMaxTile) {
-    const float* row = b.eps + static_cast<int64_t>(r) * b.ldk + k0;
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    for (int kk = 0; kk < nk4; kk += 4) {
-      const float4 x = *reinterpret_cast<const float4*>(row + kk);
-      const float4 w = e4[kk / 4];
-      a0 += w.x * x.x;
-      a1 += w.y * x.y;
-      a2 += w.z * x.z;
-      a3 += w.w * x.w;
+  // N_t[r] = sum_k e_k eps[r][k]: each wave reduces its 64 samples of a row
+  // (coalesced 256-byte reads, kIn rows in flight; padding past K is never
+  // read), the four wave sums are added in a fixed order
+  static_assert(NW == 4, "the wave sums below are added as a fixed tree of four");
+  const float* col = b.eps + (valid ? k : 0);
+  // uniform bounds (a scalar register) for the loop that holds barriers
+  const int TM = __builtin_amdgcn_readfirstlane(b.TM);
+  for (int r0 = 0; r0 < TM; r0 += kRows) {
+    const int nr = min(kRows, TM - r0);
+    for (int rr = 0; rr < nr; rr += kIn) {
+      float x[kIn];
+#pragma unroll
+      for (int q = 0; q < kIn; ++q) {
+        const int r = r0 + rr + q;
+        x[q] = (valid && rr + q < nr) ? col[static_cast<int64_t>(r) * b.ldk] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < kIn; ++q) {
+        const float t = wave_total(ek * x[q]);
+        if (lane == 0 && rr + q < nr) part[wv][rr + q] = t;
+      }
     }
-    for (int kk = nk4; kk < nk; ++kk) a0 += lds_e[kk] * row[kk];
-    b.tile_part[static_cast<int64_t>(tile) * b.TM + r] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (tid < nr)
+      b.tile_part[static_cast<int64_t>(tile) * TM + r0 + tid] =
+          (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+    __syncthreads();  // part is rewritten by the next round
   }
 }
 
