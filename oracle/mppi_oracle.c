@@ -26,7 +26,7 @@
  *      control update U_t = u_t + sum_m w^m eps^m_t.
  *   6. Free-energy statistics (Section II-B, Eq. free_energy).
  *
- * Readings of the paper used here (each also listed in the design doc):
+ * Readings of the paper used here:
  *   - The running cost is charged on the post-step state and the sampled
  *     control, l(x_{t+1}, v_t), for t = 0..T-1, and phi on x_T (Algorithm 1;
  *     the combined-kernel description in Section III-C agrees).
@@ -251,6 +251,13 @@ typedef struct {
   const float* sigma_t;
   int32_t mean_sample;
   double zero_frac;
+  /* bicycle with an MLP residual: the three matrix products take bfloat16
+   * operands (0: binary64 operands).  The weights and each product's input
+   * (z, h1, h2) are rounded to binary32 and then to the nearest bfloat16,
+   * ties to even (bf16_of); biases, sums and tanh stay binary64.  The
+   * backward pass takes the roundings as the identity: it differentiates
+   * with the rounded weights and inputs. */
+  int32_t mlp_bf16;
 } orc_problem;
 
 /* Samples k >= orc_plain_count(P) are drawn around zero. */
@@ -348,8 +355,33 @@ static void deriv(const orc_problem* P, const double* x, const double* v,
   }
 }
 
+/* The bfloat16 value nearest to x: x rounded to binary32 (nearest, ties to
+ * even), then to 8 significand bits with binary32's exponent range, the
+ * discarded low 16 bits of the binary32 encoding compared with half of the
+ * kept unit, ties to the even kept value.  A carry out of the significand
+ * moves up one binade (to infinity past the largest finite value); NaN and
+ * infinities pass through. */
+double orc_bf16(double x) {
+  const float f = (float)x;
+  uint32_t b;
+  memcpy(&b, &f, sizeof b);
+  if ((b & 0x7f800000u) == 0x7f800000u) return (double)f;
+  const uint32_t low = b & 0xffffu;
+  uint32_t r = b & 0xffff0000u;
+  if (low > 0x8000u || (low == 0x8000u && (r & 0x10000u) != 0u)) r += 0x10000u;
+  float y;
+  memcpy(&y, &r, sizeof y);
+  return (double)y;
+}
+
+/* An operand of one of the MLP's products: rounded in the bfloat16 option. */
+static double mlp_op(const orc_problem* P, double x) {
+  return P->mlp_bf16 ? orc_bf16(x) : x;
+}
+
 /* The MLP residual g([x; v]) = W3 tanh(W2 tanh(W1 z + b1) + b2) + b3,
- * z = (x[0..5), v[0..2)). */
+ * z = (x[0..5), v[0..2)); in the bfloat16 option every product operand goes
+ * through mlp_op. */
 static void mlp_residual(const orc_problem* P, const double* x, const double* v,
                          double* g) {
   const int H = P->mlp_hidden;
@@ -363,17 +395,17 @@ static void mlp_residual(const orc_problem* P, const double* x, const double* v,
   double h1[256], h2[256];
   for (int i = 0; i < H; ++i) {
     double a = b1[i];
-    for (int j = 0; j < 7; ++j) a += W1[i * 7 + j] * z[j];
+    for (int j = 0; j < 7; ++j) a += mlp_op(P, W1[i * 7 + j]) * mlp_op(P, z[j]);
     h1[i] = tanh(a);
   }
   for (int i = 0; i < H; ++i) {
     double a = b2[i];
-    for (int j = 0; j < H; ++j) a += W2[i * H + j] * h1[j];
+    for (int j = 0; j < H; ++j) a += mlp_op(P, W2[i * H + j]) * mlp_op(P, h1[j]);
     h2[i] = tanh(a);
   }
   for (int i = 0; i < 5; ++i) {
     double a = b3[i];
-    for (int j = 0; j < H; ++j) a += W3[i * H + j] * h2[j];
+    for (int j = 0; j < H; ++j) a += mlp_op(P, W3[i * H + j]) * mlp_op(P, h2[j]);
     g[i] = a;
   }
 }
@@ -871,7 +903,8 @@ static void bicycle_deriv_vjp(const orc_problem* P, const double* x, const doubl
   if (dv) { dv[0] += c[3]; dv[1] += c[4]; }
 }
 
-/* MLP residual forward with the activations kept for its backward. */
+/* MLP residual forward with the activations kept for its backward (tanh
+ * outputs before any bfloat16 rounding). */
 static void mlp_forward_keep(const orc_problem* P, const double* z, double* h1, double* h2,
                              double* g) {
   const int H = P->mlp_hidden;
@@ -883,24 +916,30 @@ static void mlp_forward_keep(const orc_problem* P, const double* z, double* h1, 
   const double* b3 = W3 + 5 * H;
   for (int i = 0; i < H; ++i) {
     double a = b1[i];
-    for (int j = 0; j < 7; ++j) a += W1[i * 7 + j] * z[j];
+    for (int j = 0; j < 7; ++j) a += mlp_op(P, W1[i * 7 + j]) * mlp_op(P, z[j]);
     h1[i] = tanh(a);
   }
   for (int i = 0; i < H; ++i) {
     double a = b2[i];
-    for (int j = 0; j < H; ++j) a += W2[i * H + j] * h1[j];
+    for (int j = 0; j < H; ++j) a += mlp_op(P, W2[i * H + j]) * mlp_op(P, h1[j]);
     h2[i] = tanh(a);
   }
   for (int i = 0; i < 5; ++i) {
     double a = b3[i];
-    for (int j = 0; j < H; ++j) a += W3[i * H + j] * h2[j];
+    for (int j = 0; j < H; ++j) a += mlp_op(P, W3[i * H + j]) * mlp_op(P, h2[j]);
     g[i] = a;
   }
 }
 
-/* Backward of g(z): dz += (dg/dz)^T cg, dmlp += (dg/dtheta)^T cg. */
+/* Backward of g(z): dz += (dg/dz)^T cg, dmlp += (dg/dtheta)^T cg.  In the
+ * bfloat16 option the roundings count as the identity: the products'
+ * derivatives take the rounded weights and inputs, tanh' the unrounded
+ * outputs.  sens (optional) += sum over the product inputs o of
+ * |dJ/do| |o| (o = z, h1, h2 as the products consume them, dJ/do with cg =
+ * dJ/dg): the first-order change of J when every such input moves by its own
+ * size. */
 static void mlp_vjp(const orc_problem* P, const double* z, const double* cg, double* dz,
-                    double* dmlp) {
+                    double* dmlp, double* sens) {
   const int H = P->mlp_hidden;
   double h1[256], h2[256], g[5], da2[256], da1[256];
   mlp_forward_keep(P, z, h1, h2, g);
@@ -915,38 +954,48 @@ static void mlp_vjp(const orc_problem* P, const double* z, const double* cg, dou
   double* db3 = dW3 + 5 * H;
   for (int i = 0; i < 5; ++i) {
     db3[i] += cg[i];
-    for (int j = 0; j < H; ++j) dW3[i * H + j] += cg[i] * h2[j];
+    for (int j = 0; j < H; ++j) dW3[i * H + j] += cg[i] * mlp_op(P, h2[j]);
   }
   for (int j = 0; j < H; ++j) {
     double s = 0.0;
-    for (int i = 0; i < 5; ++i) s += W3[i * H + j] * cg[i];
+    for (int i = 0; i < 5; ++i) s += mlp_op(P, W3[i * H + j]) * cg[i];
+    if (sens) *sens += fabs(s) * fabs(mlp_op(P, h2[j]));
     da2[j] = s * (1.0 - h2[j] * h2[j]);
   }
   for (int i = 0; i < H; ++i) {
     db2[i] += da2[i];
-    for (int j = 0; j < H; ++j) dW2[i * H + j] += da2[i] * h1[j];
+    for (int j = 0; j < H; ++j) dW2[i * H + j] += da2[i] * mlp_op(P, h1[j]);
   }
   for (int j = 0; j < H; ++j) {
     double s = 0.0;
-    for (int i = 0; i < H; ++i) s += W2[i * H + j] * da2[i];
+    for (int i = 0; i < H; ++i) s += mlp_op(P, W2[i * H + j]) * da2[i];
+    if (sens) *sens += fabs(s) * fabs(mlp_op(P, h1[j]));
     da1[j] = s * (1.0 - h1[j] * h1[j]);
   }
   for (int i = 0; i < H; ++i) {
     db1[i] += da1[i];
-    for (int j = 0; j < 7; ++j) dW1[i * 7 + j] += da1[i] * z[j];
+    for (int j = 0; j < 7; ++j) dW1[i * 7 + j] += da1[i] * mlp_op(P, z[j]);
   }
   for (int j = 0; j < 7; ++j) {
     double s = 0.0;
-    for (int i = 0; i < H; ++i) s += W1[i * 7 + j] * da1[i];
+    for (int i = 0; i < H; ++i) s += mlp_op(P, W1[i * 7 + j]) * da1[i];
+    if (sens) *sens += fabs(s) * fabs(mlp_op(P, z[j]));
     dz[j] += s;
   }
+}
+
+/* Test support: mlp_vjp alone, dz[7] and dmlp (the weight blob's layout)
+ * accumulated from z[7] and cg[5] = dJ/dg. */
+void orc_mlp_vjp(const orc_problem* P, const double* z, const double* cg, double* dz,
+                 double* dmlp) {
+  mlp_vjp(P, z, cg, dz, dmlp, NULL);
 }
 
 /* Backward of one step x1 = F(x0, v): given mu1 = dJ/dx1, returns
  * mu0 = (dF/dx0)^T mu1 and accumulates (dF/dtheta)^T mu1 into grad and, when
  * dv is given, (dF/dv)^T mu1 into dv. */
 static void step_vjp(const orc_problem* P, const double* x0, const double* v, const double* mu1,
-                     double* mu0, double* grad_mlp, double* grad_L, double* dv) {
+                     double* mu0, double* grad_mlp, double* grad_L, double* dv, double* sens) {
   const int n = 5;
   const double h = P->dt;
   double k1[5], k2[5], k3[5], x2[5], x3[5], x4[5];
@@ -985,7 +1034,7 @@ static void step_vjp(const orc_problem* P, const double* x0, const double* v, co
     double z[7] = {x0[0], x0[1], x0[2], x0[3], x0[4], v[0], v[1]};
     double cg[5], dz[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int i = 0; i < 5; ++i) cg[i] = h * mu1[i];
-    mlp_vjp(P, z, cg, dz, grad_mlp);
+    mlp_vjp(P, z, cg, dz, grad_mlp, sens);
     for (int i = 0; i < 5; ++i) mu0[i] += dz[i];
     if (dv) { dv[0] += dz[5]; dv[1] += dz[6]; }
   }
@@ -1076,7 +1125,7 @@ static int backward_one(const orc_problem* P, const double* x0, const double* u,
         /* dJ/dv_t: the control term of l_t, then the step */
         double* dv = dku + t * m;
         for (int j = 0; j < m; ++j) dv[j] = 2.0 * P->w[8 + j] * vs[t * m + j];
-        step_vjp(P, xs + t * n, vs + t * m, mu, mu0, gmlp, gL, dv);
+        step_vjp(P, xs + t * n, vs + t * m, mu, mu0, gmlp, gL, dv, NULL);
         /* the importance-sampling term lambda (v - u/2)' Sigma^-1 u with
          * v = u + eps: its derivative in u is lambda Sigma^-1 v */
         if (P->is_beta)
@@ -1201,9 +1250,15 @@ int orc_backward_iters(const orc_problem* P, const double* x0, const double* u0,
  * unit in the last place relative to its size.  A binary32 rollout commits a
  * few such roundings per component and step, so its cost can differ from the
  * binary64 one by a small multiple of 2^-24 cond[k] whatever the kernel does.
- * Same models, integrator and cost as orc_backward; returns -1 otherwise. */
+ * cond_bf (optional, the bfloat16 option of the MLP): cond_bf[k] = sum over
+ * steps and over the inputs o of the MLP's products (z, h1, h2 after their
+ * rounding) of |dJ_k/do| |o|, the first-order change of J_k when every such
+ * operand moves by its own size.  An operand whose rounding decision goes the
+ * other way moves by one bfloat16 unit in the last place, at most 2^-7 of its
+ * size.  Same models, integrator and cost as orc_backward; returns -1
+ * otherwise. */
 int orc_cost_condition(const orc_problem* P, const double* x0, const double* u, const float* eps,
-                       int64_t ldk, double* cond) {
+                       int64_t ldk, double* cond, double* cond_bf) {
   if ((P->model != ORC_BICYCLE && P->model != ORC_BICYCLE_MLP) || P->cost != ORC_COST_TRACK ||
       P->integrator != ORC_RK4)
     return -1;
@@ -1220,7 +1275,7 @@ int orc_cost_condition(const orc_problem* P, const double* x0, const double* u, 
       for (int i = 0; i < n; ++i) xs[(t + 1) * n + i] = xs[t * n + i];
       orc_step(P, xs + (t + 1) * n, vs + t * m);
     }
-    double mu[5], mu0[5], c = 0.0;
+    double mu[5], mu0[5], c = 0.0, cb = 0.0;
     const double* xT = xs + T * n;
     const double* rT = P->ref + (int64_t)T * n;
     for (int i = 0; i < n; ++i) mu[i] = 2.0 * P->w[16] * P->w[i] * (xT[i] - rT[i]);
@@ -1229,10 +1284,12 @@ int orc_cost_condition(const orc_problem* P, const double* x0, const double* u, 
       const double* r1 = P->ref + (int64_t)(t + 1) * n;
       for (int i = 0; i < n; ++i) mu[i] += 2.0 * P->w[i] * (x1[i] - r1[i]);
       for (int i = 0; i < n; ++i) c += fabs(mu[i]) * fabs(x1[i]);
-      step_vjp(P, xs + t * n, vs + t * m, mu, mu0, scratch, scratch + nmlp, NULL);
+      step_vjp(P, xs + t * n, vs + t * m, mu, mu0, scratch, scratch + nmlp, NULL,
+               cond_bf ? &cb : NULL);
       for (int i = 0; i < n; ++i) mu[i] = mu0[i];
     }
     cond[k] = c;
+    if (cond_bf) cond_bf[k] = cb;
   }
   free(scratch);
   free(xs);

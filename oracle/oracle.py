@@ -42,6 +42,7 @@ class OrcProblem(C.Structure):
         ("map", _dp),
         ("is_beta", C.c_int32), ("gamma", C.c_double), ("cost_cosines", C.c_int32),
         ("sigma_t", C.POINTER(C.c_float)), ("mean_sample", C.c_int32), ("zero_frac", C.c_double),
+        ("mlp_bf16", C.c_int32),
     ]
 
 
@@ -92,7 +93,10 @@ def lib():
         L.orc_backward_iters.argtypes = [P, f64p, f64p, C.c_int32, C.c_uint32, f64p, f64p,
                                          _opt_f64p, _opt_f64p, _opt_f64p]
         L.orc_backward_iters.restype = C.c_int
-        L.orc_cost_condition.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p]
+        L.orc_cost_condition.argtypes = [P, f64p, f64p, f32p, C.c_int64, f64p, _dp]
+        L.orc_mlp_vjp.argtypes = [P, f64p, f64p, f64p, f64p]
+        L.orc_bf16.argtypes = [C.c_double]
+        L.orc_bf16.restype = C.c_double
         L.orc_cost_condition.restype = C.c_int
         L.orc_shift.argtypes = [P, f64p, C.c_int32, C.c_int32]
         L.orc_sample.argtypes = [P, C.c_uint32, C.c_int64, f32p]
@@ -144,6 +148,7 @@ class Problem:
         p.gamma = float(np.float32(getattr(wl, "gamma", 1.0)))
         p.cost_cosines = int(getattr(wl, "cost_cosines", 0))
         p.mean_sample = int(getattr(wl, "mean_sample", 0))
+        p.mlp_bf16 = int(getattr(wl, "mlp_bf16", 0))
         p.zero_frac = float(np.float32(getattr(wl, "zero_frac", 0.0)))
         sig_t = getattr(wl, "sigma_t", None)
         if sig_t is not None:
@@ -385,19 +390,31 @@ def backward_iters(wl, dL_dU, iters: int, u=None, x0=None, iter0: int = 0):
             "U": U.reshape(wl.T, wl.m), "status": rc}
 
 
-def cost_condition(wl, eps=None, x0=None, u=None, iteration: int = 0):
+def cost_condition(wl, eps=None, x0=None, u=None, iteration: int = 0, bf: bool = False):
     """cond[K]: first-order sensitivity of each J_k to a relative perturbation
-    of every state component at every step (sum_t,i |dJ_k/dx_t,i| |x_t,i|)."""
+    of every state component at every step (sum_t,i |dJ_k/dx_t,i| |x_t,i|).
+    bf: also cond_bf[K], the same sum over the inputs of the MLP's products
+    (z, h1, h2 as consumed; returns (cond, cond_bf))."""
     P = Problem(wl)
     if eps is None:
         eps = workload_noise(wl, iteration)
     eps = np.ascontiguousarray(eps, np.float32)
     cond = np.empty(wl.K)
+    cond_bf = np.zeros(wl.K) if bf else None
     rc = lib().orc_cost_condition(P.ref, _d(wl.x0 if x0 is None else x0),
-                                  _d(wl.u0 if u is None else u).ravel(), eps, eps.shape[-1], cond)
+                                  _d(wl.u0 if u is None else u).ravel(), eps, eps.shape[-1], cond,
+                                  None if cond_bf is None else cond_bf.ctypes.data_as(_dp))
     if rc == -1:
         raise ValueError("cost_condition needs a bicycle model with RK4 and the track cost")
-    return cond
+    return (cond, cond_bf) if bf else cond
+
+
+def bf16(x):
+    """The oracle's bfloat16 rounding (binary32 first, then 8 significand
+    bits, ties to even) of each element, as binary64."""
+    f = lib().orc_bf16
+    a = np.asarray(x, np.float64)
+    return np.array([f(float(v)) for v in a.ravel()]).reshape(a.shape)
 
 
 def with_theta(wl, theta):
@@ -441,6 +458,16 @@ def step(wl, x, v):
     x = _d(x).copy()
     lib().orc_step(P.ref, x, _d(v))
     return x
+
+
+def mlp_vjp(wl, z, cg):
+    """(dz[7], dtheta_mlp) of the MLP residual g at input z for dJ/dg = cg."""
+    P = Problem(wl)
+    H = wl.mlp_hidden
+    dz = np.zeros(7)
+    dm = np.zeros(14 * H + H * H + 5)
+    lib().orc_mlp_vjp(P.ref, _d(z), _d(cg), dz, dm)
+    return dz, dm
 
 
 def deriv(wl, x, v):
@@ -498,4 +525,4 @@ __all__ = ["philox", "bm_tables", "noise", "workload_noise", "rollout_costs",
            "running_cost", "terminal_cost", "spline", "costmap", "Problem", "n_grad",
            "backward", "with_theta", "theta_of", "loss_and_controls",
            "cost_condition", "shift", "backward_iters", "sequence_cost_injected",
-           "rollout_costs_parallel", "host_threads"]
+           "rollout_costs_parallel", "host_threads", "bf16", "mlp_vjp"]

@@ -44,6 +44,22 @@ Tolerances (the target is 1e-4 relative in binary32):
         long-horizon trajectories are ill-conditioned: there the first two
         checks carry the claim).
   * update alone (both sides weight the same binary32 costs): the flat bound.
+  * the MLP's bfloat16 mode (products on bfloat16 operands, binary32
+    accumulation) against the oracle's bfloat16 option, which rounds the same
+    operands at the same points (binary64 -> binary32 -> bfloat16, nearest
+    even).  The binary32 arithmetic between the roundings differs, so a
+    rounding decision can go the other way where an operand lies within
+    binary32 reach of a tie; the operand then moves by one bfloat16 unit in
+    the last place, at most 2^-7 of its size.  Bounds (assert_costs_close_bf16):
+      - every sample: |J_gpu - J_bf| <= cost_tol(J_bf, cond) + 2^-7 cond_bf,
+        cond_bf = sum over the rounded operands o of |dJ/do| |o| (from the
+        oracle's adjoint): the first-order change if every decision flipped;
+      - at most BF_FLIP_FRAC of the samples may need the second term (the
+        rest meet the binary32 bound outright);
+      - the GPU takes the oracle's decisions, not merely some rounding: the
+        median |J_gpu - J_bf| is at most BF_SAME_ROUNDING of the median
+        |J_bf - J_fp64| (the whole effect of the roundings; a kernel that
+        truncated, or skipped a rounding, would sit near 1).
 """
 import numpy as np
 
@@ -171,6 +187,36 @@ def assert_costs_close(S_gpu, S_or, margin=None, name="", slope=None, cond=None,
     assert bad.size == 0, (
         f"{name}: {bad.size} costs off; first {bad[:5]}: gpu {S_gpu[bad[:5]]} "
         f"oracle {S_or[bad[:5]]} rel {(np.abs(S_gpu - S_or) / np.maximum(np.abs(S_or), 1))[bad[:5]]}")
+
+
+BF_ULP = 2.0 ** -7
+BF_FLIP_FRAC = 0.01
+BF_SAME_ROUNDING = 0.1
+
+
+def assert_costs_close_bf16(S_gpu, S_bf, S_fp, cond, cond_bf, name=""):
+    """The bfloat16 mode's costs against the oracle's bfloat16 option (S_bf)
+    and its binary64 model (S_fp); cond, cond_bf from cost_condition(bf=True).
+    Returns (fraction of samples beyond the binary32 bound, median ratio)."""
+    S_gpu = np.asarray(S_gpu, np.float64)
+    d = np.abs(S_gpu - S_bf)
+    tol = cost_tol(S_bf, cond)
+    outer = tol + BF_ULP * cond_bf
+    bad = np.flatnonzero(~(d <= outer))
+    assert bad.size == 0, (
+        f"{name}: {bad.size} costs beyond the bfloat16 bound; first {bad[:5]}: gpu "
+        f"{S_gpu[bad[:5]]} oracle {S_bf[bad[:5]]} bound {outer[bad[:5]]}")
+    flipped = float(np.mean(d > tol))
+    assert flipped <= BF_FLIP_FRAC, f"{name}: {flipped:.4f} of the samples beyond the binary32 bound"
+    effect = float(np.median(np.abs(S_bf - S_fp)))
+    ratio = float(np.median(d)) / effect if effect > 0 else 0.0
+    assert ratio <= BF_SAME_ROUNDING, (
+        f"{name}: median |J_gpu - J_bf| is {ratio:.3g} of the roundings' median effect")
+    import sys
+    print(f"[bf16] {name}: beyond binary32 bound {flipped:.4f}, worst |d|/bound "
+          f"{float(np.max(d / outer)):.3g}, median |d| / median rounding effect {ratio:.3g}",
+          file=sys.stderr, flush=True)
+    return flipped, ratio
 
 
 def assert_controls_close(U_gpu, U_or, tol, name=""):

@@ -60,3 +60,28 @@ def test_end_to_end_check_accepts_exact_propagation_and_rejects_offsets():
     bad[3, 1] += 2.0 * parity.flat_tol(wl, U_or)
     with pytest.raises(AssertionError):
         parity.assert_end_to_end(O, wl, bad, S_gpu, eps, S_or, "offset")
+
+
+def test_bf16_cost_check_accepts_the_oracle_and_rejects_other_roundings(oracle_lib):
+    """The bfloat16 cost check on results of the oracle itself: its own
+    bfloat16 option (plus a binary32-sized jitter) passes; the binary64 model,
+    the weights rounded but not the activations, and a costs shifted past the
+    outer bound fail."""
+    wl = W.c5(K=200, T=20, hidden=16).replace(mlp_bf16=1)
+    eps = oracle_lib.workload_noise(wl)
+    S_bf = oracle_lib.rollout_costs(wl, eps)[0]
+    S_fp = oracle_lib.rollout_costs(wl.replace(mlp_bf16=0), eps)[0]
+    cond, cond_bf = oracle_lib.cost_condition(wl, eps, bf=True)
+    assert (cond_bf > 0).all()
+    jitter = 1.0 + 2.0 ** -22 * np.random.default_rng(1).standard_normal(wl.K)
+    parity.assert_costs_close_bf16(S_bf * jitter, S_bf, S_fp, cond, cond_bf, "oracle")
+    with pytest.raises(AssertionError):
+        parity.assert_costs_close_bf16(S_fp, S_bf, S_fp, cond, cond_bf, "binary64 model")
+    wr = wl.replace(mlp=oracle_lib.bf16(wl.mlp).astype(np.float32), mlp_bf16=0)
+    S_wr = oracle_lib.rollout_costs(wr, eps)[0]
+    with pytest.raises(AssertionError):
+        parity.assert_costs_close_bf16(S_wr, S_bf, S_fp, cond, cond_bf, "weights only")
+    S_off = S_bf.copy()
+    S_off[7] += 2.0 * (parity.cost_tol(S_bf, cond) + parity.BF_ULP * cond_bf)[7]
+    with pytest.raises(AssertionError):
+        parity.assert_costs_close_bf16(S_off, S_bf, S_fp, cond, cond_bf, "one sample off")

@@ -67,6 +67,7 @@ class Workload:
     gravity: float = 0.0
     mlp: Optional[np.ndarray] = None
     mlp_hidden: int = 0
+    mlp_bf16: int = 0     # MLP products on bfloat16 operands (binary32 accumulation)
     ref: Optional[np.ndarray] = None
     knots: Optional[np.ndarray] = None
     coef: Optional[np.ndarray] = None
