@@ -50,6 +50,8 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12
 # Dense FP32 matrix-core peak of MI355X (v_mfma_f32_16x16x4_f32), FLOP/s.
 MFMA_FP32_PEAK = 157.3e12
+# Dense BF16 matrix-core peak of MI355X, FLOP/s.
+MFMA_BF16_PEAK = 2.5e15
 
 
 def mlp_macs(hidden: int) -> int:
@@ -479,6 +481,16 @@ def run_grad(args, wl, full: bool = True) -> dict:
                                      "fwd_plus_bwd_ms": d["t_fb"] * 1e3,
                                      "bwd_ms": (d["t_fb"] - d["t_fg"]) * 1e3,
                                      "samples_swept": d["swept"]}
+    # the bfloat16 mode of the MLP (bfloat16 operands, binary32 accumulation)
+    b = measure(wl.replace(mlp_bf16=1), False)
+    out["bf16"] = {"ms_per_step": b["t_fwd"] * 1e3, "value": steps / b["t_fwd"],
+                   "fwd_bwd_over_fwd": b["t_fb"] / b["t_fwd"],
+                   "fwd_plus_bwd_ms": b["t_fb"] * 1e3, "bwd_ms": (b["t_fb"] - b["t_fg"]) * 1e3,
+                   "rollout_us": b["t_roll"] * 1e6,
+                   "rollout_speedup_over_fp32": r["t_roll"] / b["t_roll"],
+                   "mfma_TFLOPs": flops / b["t_roll"] / 1e12,
+                   "frac_of_bf16_peak": flops / b["t_roll"] / MFMA_BF16_PEAK,
+                   "tuning": b["tuning"]}
     return out
 
 
@@ -616,7 +628,7 @@ def main():
         line = headline_line(args, r, config={k: r[k] for k in (
             "workload", "K", "T", "iterations_per_step", "dynamics", "hidden", "integrator",
             "cost", "lambda", "checkpoint_every")}, **{k: r[k] for k in (
-                "fwd_bwd_over_fwd", "grad", "roofline", "kernels", "tuning")})
+                "fwd_bwd_over_fwd", "grad", "roofline", "kernels", "tuning", "bf16")})
         if not args.no_cpu_baseline:
             line["cpu_baseline"] = cpu_baseline_single(wl, 1)
     else:

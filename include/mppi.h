@@ -133,6 +133,17 @@ enum {
                                 cost, which is the cost the weights are formed from
                                 and mppi_get_debug(MPPI_DEBUG_COSTS) returns; needs
                                 every sigma > 0.  Without it beta = 0 (Algorithm 1) */
+  MPPI_F_BF16_MLP = 256u,    /* BICYCLE_MLP: the MLP's three matrix products take
+                                bfloat16 operands (the weights and the layer inputs
+                                z, h1, h2 rounded to nearest-even from binary32)
+                                with binary32 accumulation on the matrix cores
+                                (v_mfma_f32_16x16x32_bf16); biases and tanh stay
+                                binary32.  Single-wave tiles only (rollout_block
+                                64).  With MPPI_F_REQUIRES_GRAD the adjoint
+                                differentiates this forward with the roundings
+                                taken as the identity (the products' derivatives
+                                use the rounded weights and inputs).  Without it
+                                the products are binary32 */
   MPPI_F_MEAN_SAMPLE = 128u, /* sample 0 is drawn without noise (eps_0 = 0, v = u: the
                                 mean itself is one of the samples; section
                                 "Sampling Distributions") */

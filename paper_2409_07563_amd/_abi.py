@@ -32,6 +32,7 @@ F_REQUIRES_GRAD = 16
 F_IMPORTANCE_SAMPLING = 32
 F_STEP_SIZE = 64
 F_MEAN_SAMPLE = 128
+F_BF16_MLP = 256
 ROLLOUT_FUSED, ROLLOUT_SPLIT, ROLLOUT_SCAN = 0, 1, 2
 UPDATE_TWO_PASS, UPDATE_ONE_PASS, UPDATE_CHUNKED = 0, 1, 2
 BATCH_PHASES, BATCH_ONE_LAUNCH = 0, 1

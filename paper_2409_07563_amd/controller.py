@@ -48,6 +48,7 @@ def _config(pb, debug: bool, accurate_trig: bool, rollout: str,
                  | (_abi.F_REQUIRES_GRAD if requires_grad else 0)
                  | (_abi.F_IMPORTANCE_SAMPLING if getattr(pb, "is_beta", 0) else 0)
                  | (_abi.F_MEAN_SAMPLE if getattr(pb, "mean_sample", 0) else 0)
+                 | (_abi.F_BF16_MLP if getattr(pb, "mlp_bf16", 0) else 0)
                  | _abi.F_STEP_SIZE)
     cfg.zero_mean_fraction = float(np.float32(getattr(pb, "zero_frac", 0.0)))
     # always explicit (gamma = 1 is Algorithm 1): the instances of a batch

@@ -257,14 +257,16 @@ __device__ __forceinline__ void rk4_vjp(const DevParams& p, const float* xt, con
   for (int i = 0; i < N; ++i) mu0[i] += cx[i];
 }
 
-template <int MT>
+template <int MT, bool BF = false>
 struct SweepLds {
   static constexpr int P = 64 * MT + 16;  // transposition row stride (16 mod 32: no bank conflicts)
   static constexpr int kFwd = MT ? mlp::Pack<MT>::kFwdRows * kWave : 0;
   static constexpr int kBwd = MT ? mlp::Pack<MT>::kBwdRows * kWave : 0;
+  // BF16 mode: the bfloat16 weight pack (16 bytes per lane and row)
+  static constexpr int kBf = (MT && BF) ? mlp::PackBf<MT ? MT : 1>::kRows * kWave * 4 : 0;
   static constexpr int kTb = MT ? kTileS * P : 0;
   static size_t bytes(int c) {
-    return sizeof(float) * (kFwd + kBwd + kTb + kTileS * ((c + 1) * 5 + c * 2));
+    return sizeof(float) * (kFwd + kBwd + kBf + kTb + kTileS * ((c + 1) * 5 + c * 2));
   }
 };
 
@@ -301,14 +303,17 @@ __device__ __forceinline__ void du_step(const DevParams& p, const float* ic, int
   }
 }
 
-template <int MT, bool FAST>
+// BF: the forward rebuild takes the BF16 products (mlp::hidden_bf), and the
+// weight gradients take the rounded layer inputs (the roundings count as the
+// identity; the adjoint's transposed pack holds the rounded weights).
+template <int MT, bool FAST, bool BF = false>
 __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
     const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp, int du_off,
     mlp::f4* __restrict__ pre) {
   using Model = Bicycle<FAST>;
-  using L = SweepLds<MT>;
+  using L = SweepLds<MT, BF>;
   using f4 = mlp::f4;
   constexpr int N = 5, M = 2, H = 16 * MT;
   const int base = blockIdx.x * kTileS;
@@ -321,10 +326,16 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
     const float4* src_b = reinterpret_cast<const float4*>(p.mlp_bwd);
     for (int i = lane; i < L::kFwd / 4; i += kWave) lds4[i] = src_f[i];
     for (int i = lane; i < L::kBwd / 4; i += kWave) lds4[L::kFwd / 4 + i] = src_b[i];
+    if constexpr (BF) {
+      const float4* src_h = reinterpret_cast<const float4*>(p.mlp_bf);
+      for (int i = lane; i < L::kBf / 4; i += kWave) lds4[(L::kFwd + L::kBwd) / 4 + i] = src_h[i];
+    }
   }
   const mlp::PackView<MT ? MT : 1> WF{lds + lane};
   const mlp::PackView<MT ? MT : 1> WB{lds + L::kFwd + lane};
-  float* tb = lds + L::kFwd + L::kBwd;
+  const mlp::PackViewBf<MT ? MT : 1> WFB{
+      reinterpret_cast<const uint4*>(lds + L::kFwd + L::kBwd) + lane, WF};
+  float* tb = lds + L::kFwd + L::kBwd + L::kBf;
   float* xs = tb + L::kTb + n * ((c + 1) * N);                     // [c+1][5] of sample n
   float* vs = tb + L::kTb + kTileS * (c + 1) * N + n * (c * M);    // [c][2] of sample n
   __syncthreads();
@@ -388,7 +399,8 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
       if constexpr (MT > 0) {
         float res[N];
         f4 a1[MT], a2[MT];
-        mlp::residual_keep<MT>(WF, x, v, g, n, res, a1, a2);
+        if constexpr (BF) mlp::residual_keep<MT>(WFB, x, v, g, n, res, a1, a2);
+        else mlp::residual_keep<MT>(WF, x, v, g, n, res, a1, a2);
         f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
 #pragma unroll
         for (int t2 = 0; t2 < MT; ++t2) {
@@ -473,16 +485,17 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
         float* row = tb + n * L::P;
 #pragma unroll
         for (int t2 = 0; t2 < MT; ++t2) {
-          *reinterpret_cast<f4*>(row + 16 * t2 + 4 * g) = h1[t2];
-          *reinterpret_cast<f4*>(row + H + 16 * t2 + 4 * g) = h2[t2];
+          *reinterpret_cast<f4*>(row + 16 * t2 + 4 * g) = BF ? mlp::round_bf4(h1[t2]) : h1[t2];
+          *reinterpret_cast<f4*>(row + H + 16 * t2 + 4 * g) = BF ? mlp::round_bf4(h2[t2]) : h2[t2];
           *reinterpret_cast<f4*>(row + 2 * H + 16 * t2 + 4 * g) = da1[t2];
           *reinterpret_cast<f4*>(row + 3 * H + 16 * t2 + 4 * g) = da2[t2];
         }
         // rows 4H .. 4H+7: z = (x, v, 0); rows 4H+8 .. 4H+15: c (5) and zeros
-        const f4 zc = g == 0 ? f4{xt[0], xt[1], xt[2], xt[3]}
-                    : g == 1 ? f4{xt[4], v[0], v[1], 0.0f}
-                    : g == 2 ? f4{cg[0], cg[1], cg[2], cg[3]}
-                             : f4{cg[4], 0.0f, 0.0f, 0.0f};
+        f4 zc = g == 0 ? f4{xt[0], xt[1], xt[2], xt[3]}
+              : g == 1 ? f4{xt[4], v[0], v[1], 0.0f}
+              : g == 2 ? f4{cg[0], cg[1], cg[2], cg[3]}
+                       : f4{cg[4], 0.0f, 0.0f, 0.0f};
+        if (BF && g < 2) zc = mlp::round_bf4(zc);
         *reinterpret_cast<f4*>(row + 4 * H + 4 * g) = zc;
         __syncthreads();
 #pragma unroll
@@ -982,12 +995,12 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_eve
   return s;
 }
 
-size_t adjoint_lds_bytes(int hidden, int ckpt_every) {
+size_t adjoint_lds_bytes(int hidden, int ckpt_every, bool bf) {
   switch (hidden) {
     case 0: return SweepLds<0>::bytes(ckpt_every);
-    case 16: return SweepLds<1>::bytes(ckpt_every);
-    case 32: return SweepLds<2>::bytes(ckpt_every);
-    case 64: return SweepLds<4>::bytes(ckpt_every);
+    case 16: return bf ? SweepLds<1, true>::bytes(ckpt_every) : SweepLds<1>::bytes(ckpt_every);
+    case 32: return bf ? SweepLds<2, true>::bytes(ckpt_every) : SweepLds<2>::bytes(ckpt_every);
+    case 64: return bf ? SweepLds<4, true>::bytes(ckpt_every) : SweepLds<4>::bytes(ckpt_every);
     default: return 0;
   }
 }
@@ -995,9 +1008,9 @@ size_t adjoint_lds_bytes(int hidden, int ckpt_every) {
 namespace {
 using SweepFn = void (*)(DevParams, const float*, const float*, int64_t, int, const float*, int,
                          const BwdItem*, const BwdMeta*, float*, int64_t, int, mlp::f4*);
-template <int MT>
+template <int MT, bool BF = false>
 SweepFn pick_sweep(bool accurate) {
-  return accurate ? adjoint_sweep_kernel<MT, false> : adjoint_sweep_kernel<MT, true>;
+  return accurate ? adjoint_sweep_kernel<MT, false, BF> : adjoint_sweep_kernel<MT, true, BF>;
 }
 template <int MT, int SW>
 SweepFn pick_split_sweep(bool accurate) {
@@ -1013,7 +1026,9 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
                           float* d_grad, hipStream_t stream, int waves, bool accumulate,
                           float* d_G_acc) {
   SweepFn fn = nullptr;
-  size_t lds = adjoint_lds_bytes(hidden, ckpt_every);
+  const bool bf = hidden > 0 && p.mlp_bf != nullptr;  // BF16 mode: single-wave sweep only
+  size_t lds = adjoint_lds_bytes(hidden, ckpt_every, bf);
+  if (waves > 1 && bf) return hipErrorInvalidValue;
   if (waves > 1) {
     if (hidden == 64 && waves == 4) {
       fn = pick_split_sweep<4, 4>(accurate_trig);
@@ -1030,9 +1045,9 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   } else {
     switch (hidden) {
       case 0: fn = pick_sweep<0>(accurate_trig); break;
-      case 16: fn = pick_sweep<1>(accurate_trig); break;
-      case 32: fn = pick_sweep<2>(accurate_trig); break;
-      case 64: fn = pick_sweep<4>(accurate_trig); break;
+      case 16: fn = bf ? pick_sweep<1, true>(accurate_trig) : pick_sweep<1>(accurate_trig); break;
+      case 32: fn = bf ? pick_sweep<2, true>(accurate_trig) : pick_sweep<2>(accurate_trig); break;
+      case 64: fn = bf ? pick_sweep<4, true>(accurate_trig) : pick_sweep<4>(accurate_trig); break;
       default: return hipErrorInvalidValue;
     }
   }

@@ -65,6 +65,8 @@ struct DevParams {
   const float* is_coef_t;
   const float* sigma_t;
   int mean_sample;  // sample 0 drawn without noise
+  // MLP residual in BF16 mode: the bfloat16 weight pack (mlp.h), else null
+  const uint4* mlp_bf;
 };
 
 // Largest circle grid the rollout kernel stages into LDS.
@@ -274,7 +276,7 @@ struct AdjointScratch {
 int adjoint_grad_len(uint32_t dynamics, int hidden);
 // TM = T * m: room for the dL/du columns of the partial rows
 AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_every, int TM);
-size_t adjoint_lds_bytes(int hidden, int ckpt_every);
+size_t adjoint_lds_bytes(int hidden, int ckpt_every, bool bf16 = false);
 // accumulate: d_grad += the gradient (else d_grad = it); d_G_acc (optional):
 // d_G_acc += sum_k a_k dJ_k/du (may be d_G itself: the update happens after
 // every read of d_G, in stream order).

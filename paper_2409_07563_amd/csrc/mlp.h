@@ -283,5 +283,179 @@ __device__ __forceinline__ void backward(const PackView<MT>& B, const float* c, 
   for (int tt = 1; tt < MT; ++tt) dz += zacc[tt];
 }
 
+// ---------------------------------------------------------------------------
+// BF16 mode: the three products take bfloat16 operands (weights and the layer
+// inputs z, h1, h2, rounded to nearest-even from binary32) with binary32
+// accumulation, on v_mfma_f32_16x16x32_bf16; the biases are the accumulators'
+// binary32 start values and tanh stays binary32.  A lane holds 8 bfloat16 of
+// an operand: lane (g, n) supplies the K-block's contraction slots
+// (g, j), j = 0..7, of A row n and of B column n, and the matrix core pairs
+// equal slots of A and B, so any fixed map from slots to the contraction
+// index that the weight pack and the activations share gives the product.
+// K-block kb of a hidden layer covers the previous layer's M-tiles 2kb and
+// 2kb+1: slot (g, j) is hidden unit 16(2kb) + 4g + j for j < 4 and
+// 16(2kb+1) + 4g + (j - 4) for j >= 4, which are exactly the D registers
+// (t, i) lane (g, n) holds for its sample, so the activations feed the next
+// layer without data movement (MT odd: the missing tile's slots are zero).
+// The input layer has one K-block: slot (0, j) is z_j (j < 7), every other
+// slot zero.
+//
+// Pack (host-built, per lane 16 bytes = 8 bfloat16 per operand row), rows:
+//   W1: MT (M-tile t), W2: MT * KB (t, kb), W3: KB (kb, output rows 0..4 of 16)
+// with KB = ceil(MT / 2); the biases come from the binary32 pack.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float fl8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int MT>
+struct PackBf {
+  static constexpr int KB = (MT + 1) / 2;
+  static constexpr int kW1 = 0;
+  static constexpr int kW2 = kW1 + MT;
+  static constexpr int kW3 = kW2 + MT * KB;
+  static constexpr int kRows = kW3 + KB;
+};
+
+// the bfloat16 operand rows of one lane, register resident, and the biases
+template <int MT>
+struct WeightsBf {
+  static constexpr int KB = PackBf<MT>::KB;
+  bf8 w1_[MT], w2_[MT][KB], w3_[KB];
+  f4 b1_[MT], b2_[MT], b3_;
+  __device__ __forceinline__ void load(const uint4* __restrict__ bpack,
+                                       const float* __restrict__ fpack, int lane) {
+    using P = PackBf<MT>;
+    auto at = [&](int row) { return __builtin_bit_cast(bf8, bpack[row * kWave + lane]); };
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      w1_[t] = at(P::kW1 + t);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) w2_[t][kb] = at(P::kW2 + t * KB + kb);
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) w3_[kb] = at(P::kW3 + kb);
+    using F = Pack<MT>;
+    auto fat = [&](int row) { return fpack[row * kWave + lane]; };
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        b1_[t][i] = fat(F::kB1 + 4 * t + i);
+        b2_[t][i] = fat(F::kB2 + 4 * t + i);
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b3_[i] = fat(F::kB3 + i);
+  }
+  __device__ __forceinline__ bf8 w1(int t) const { return w1_[t]; }
+  __device__ __forceinline__ bf8 w2(int t, int kb) const { return w2_[t][kb]; }
+  __device__ __forceinline__ bf8 w3(int kb) const { return w3_[kb]; }
+  __device__ __forceinline__ f4 b1(int t) const { return b1_[t]; }
+  __device__ __forceinline__ f4 b2(int t) const { return b2_[t]; }
+  __device__ __forceinline__ f4 b3() const { return b3_; }
+};
+
+// The same operands read at each use from packs in LDS: the bfloat16 weight
+// pack (bp points at row 0 of this lane) and the binary32 pack's biases.
+template <int MT>
+struct PackViewBf {
+  static constexpr int KB = PackBf<MT>::KB;
+  const uint4* bp;
+  PackView<MT> fv;
+  __device__ __forceinline__ bf8 at(int row) const {
+    return __builtin_bit_cast(bf8, bp[row * kWave]);
+  }
+  __device__ __forceinline__ bf8 w1(int t) const { return at(PackBf<MT>::kW1 + t); }
+  __device__ __forceinline__ bf8 w2(int t, int kb) const { return at(PackBf<MT>::kW2 + t * KB + kb); }
+  __device__ __forceinline__ bf8 w3(int kb) const { return at(PackBf<MT>::kW3 + kb); }
+  __device__ __forceinline__ f4 b1(int t) const { return fv.b1(t); }
+  __device__ __forceinline__ f4 b2(int t) const { return fv.b2(t); }
+  __device__ __forceinline__ f4 b3() const { return fv.b3(); }
+};
+
+// The B operand of K-block kb over the activations h (D layout), rounded to
+// bfloat16.
+template <int MT>
+__device__ __forceinline__ bf8 kblock_operand(const f4 (&h)[MT], int kb) {
+  fl8 v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = h[2 * kb][i];
+    v[4 + i] = 2 * kb + 1 < MT ? h[2 * kb + 1 < MT ? 2 * kb + 1 : 0][i] : 0.0f;
+  }
+  return __builtin_convertvector(v, bf8);
+}
+
+// The input-layer B operand: z = (x0..x4, v0, v1) in lane group 0, rounded.
+__device__ __forceinline__ bf8 input_operand_bf(const float* x, const float* v, int g) {
+  const fl8 zf = g == 0 ? fl8{x[0], x[1], x[2], x[3], x[4], v[0], v[1], 0.0f}
+                        : fl8{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  return __builtin_convertvector(zf, bf8);
+}
+
+// x rounded to bfloat16 and back (the value a product consumed)
+__device__ __forceinline__ float round_bf(float x) {
+  return static_cast<float>(static_cast<__bf16>(x));
+}
+__device__ __forceinline__ f4 round_bf4(f4 x) {
+  return f4{round_bf(x[0]), round_bf(x[1]), round_bf(x[2]), round_bf(x[3])};
+}
+
+// Hidden activations (and pre-activations) of the tile in BF16 mode
+// (WB: WeightsBf or PackViewBf).
+template <int MT, class WB>
+__device__ __forceinline__ void hidden_bf(const WB& W, const float* x, const float* v, int g,
+                                          f4 (&h1)[MT], f4 (&h2)[MT], f4* pre1 = nullptr,
+                                          f4* pre2 = nullptr) {
+  constexpr int KB = PackBf<MT>::KB;
+  const bf8 z = input_operand_bf(x, v, g);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const f4 a = mfma_bf(W.w1(t), z, W.b1(t));
+    if (pre1) pre1[t] = a;
+    h1[t] = tanh4(a);
+  }
+  bf8 hb[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) hb[kb] = kblock_operand<MT>(h1, kb);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    f4 acc = W.b2(t);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) acc = mfma_bf(W.w2(t, kb), hb[kb], acc);
+    if (pre2) pre2[t] = acc;
+    h2[t] = tanh4(acc);
+  }
+}
+
+// Output rows 4g + i of W3 h2 + b3 in BF16 mode.
+template <int MT, class WB>
+__device__ __forceinline__ f4 output_bf(const WB& W, const f4 (&h2)[MT]) {
+  constexpr int KB = PackBf<MT>::KB;
+  f4 acc = W.b3();
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) acc = mfma_bf(W.w3(kb), kblock_operand<MT>(h2, kb), acc);
+  return acc;
+}
+
+template <int MT>
+__device__ __forceinline__ void residual(const WeightsBf<MT>& W, const float* x, const float* v,
+                                         int g, int n, float* res) {
+  f4 h1[MT], h2[MT];
+  hidden_bf<MT>(W, x, v, g, h1, h2);
+  broadcast5(output_bf<MT>(W, h2), n, res);
+}
+
+template <int MT>
+__device__ __forceinline__ void residual_keep(const PackViewBf<MT>& W, const float* x,
+                                              const float* v, int g, int n, float* res,
+                                              f4 (&pre1)[MT], f4 (&pre2)[MT]) {
+  f4 h1[MT], h2[MT];
+  hidden_bf<MT>(W, x, v, g, h1, h2, pre1, pre2);
+  broadcast5(output_bf<MT>(W, h2), n, res);
+}
+
 }  // namespace mlp
 }  // namespace mppi

@@ -81,7 +81,7 @@ struct Layout {
   size_t eps, eps2, e;
   size_t words;  // single contexts: the iteration word each noise buffer was drawn with
   size_t wpart;  // single contexts: the chunked update's per-chunk sums
-  size_t ref, stage, costmap, mlp, mlp_bwd;
+  size_t ref, stage, costmap, mlp, mlp_bwd, mlp_bf;
   size_t sigma_t, is_coef_t;  // per-step noise deviations and importance coefficients
   // MPPI_F_REQUIRES_GRAD: checkpoints [nseg][7][ldk], the rollout's controls,
   // the adjoint's scratch
@@ -127,16 +127,97 @@ float step_size(const mppi_config& c) {
 }
 int ckpt_every_of(const mppi_params* p) { return p->checkpoint_every ? p->checkpoint_every : 10; }
 
+bool bf16_of(const mppi_config* c) { return (c->flags & MPPI_F_BF16_MLP) != 0; }
+// rows of the bfloat16 weight pack (mlp::PackBf)
+int bf_pack_rows(int hidden) {
+  const int MT = hidden / 16, KB = (MT + 1) / 2;
+  return MT + MT * KB + KB;
+}
+
+// binary32 -> bfloat16 bits, round to nearest, ties to even (a NaN stays a
+// quiet NaN)
+uint16_t bf16_bits(float x) {
+  uint32_t b;
+  memcpy(&b, &x, 4);
+  if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x7FFFFFu)) return static_cast<uint16_t>((b >> 16) | 0x40u);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return static_cast<uint16_t>(b >> 16);
+}
+float bf16_round(float x) {
+  const uint32_t b = static_cast<uint32_t>(bf16_bits(x)) << 16;
+  float r;
+  memcpy(&r, &b, 4);
+  return r;
+}
+
 // The MFMA operand packs of the MLP (lane layout in mlp.h) from the weight
-// blob W1[H][7] b1[H] W2[H][H] b2[H] W3[5][H] b3[5].
-void build_mlp_packs(const float* blob, int H, std::vector<float4>* fwd, std::vector<float4>* bwd) {
+// blob W1[H][7] b1[H] W2[H][H] b2[H] W3[5][H] b3[5].  bf (BF16 mode, optional):
+// also the bfloat16 weight pack, and the adjoint's pack takes the rounded
+// weights (the products' derivatives use the weights the forward used).
+void build_mlp_packs(const float* blob_in, int H, std::vector<float4>* fwd,
+                     std::vector<float4>* bwd, std::vector<uint4>* bf = nullptr) {
   const int MT = H / 16;
+  std::vector<float> rounded;
+  const float* blob = blob_in;
+  if (bf) {
+    const int nw = 14 * H + H * H + 5;
+    rounded.assign(blob_in, blob_in + nw);
+    const int oW2 = 8 * H, oW3 = 9 * H + H * H;
+    for (int i = 0; i < 7 * H; ++i) rounded[i] = bf16_round(rounded[i]);
+    for (int i = 0; i < H * H; ++i) rounded[oW2 + i] = bf16_round(rounded[oW2 + i]);
+    for (int i = 0; i < 5 * H; ++i) rounded[oW3 + i] = bf16_round(rounded[oW3 + i]);
+    blob = rounded.data();
+  }
   const float* W1 = blob;
   const float* b1 = W1 + 7 * H;
   const float* W2 = b1 + H;
   const float* b2 = W2 + H * H;
   const float* W3 = b2 + H;
   const float* b3 = W3 + 5 * H;
+  if (bf) {
+    // slot (g, j) of K-block kb: hidden unit 16(2kb) + 4g + j (j < 4) or
+    // 16(2kb+1) + 4g + j - 4; -1 where the tile does not exist
+    auto unit = [&](int kb, int g, int j) {
+      const int tile = 2 * kb + (j >> 2);
+      return tile < MT ? 16 * tile + 4 * g + (j & 3) : -1;
+    };
+    const int KB = (MT + 1) / 2;
+    bf->assign(static_cast<size_t>(bf_pack_rows(H)) * kWave, uint4{0, 0, 0, 0});
+    for (int l = 0; l < kWave; ++l) {
+      const int n = l % 16, g = l / 16;
+      int r = 0;
+      auto put = [&](const float* v8) {
+        uint32_t w[4];
+        for (int q = 0; q < 4; ++q)
+          w[q] = static_cast<uint32_t>(bf16_bits(v8[2 * q])) |
+                 (static_cast<uint32_t>(bf16_bits(v8[2 * q + 1])) << 16);
+        (*bf)[static_cast<size_t>(r++) * kWave + l] = uint4{w[0], w[1], w[2], w[3]};
+      };
+      float v8[8];
+      for (int t = 0; t < MT; ++t) {  // W1: z slot (0, j) = z_j
+        for (int j = 0; j < 8; ++j) {
+          const int k = 8 * g + j;
+          v8[j] = k < 7 ? W1[(16 * t + n) * 7 + k] : 0.0f;
+        }
+        put(v8);
+      }
+      for (int t = 0; t < MT; ++t)
+        for (int kb = 0; kb < KB; ++kb) {
+          for (int j = 0; j < 8; ++j) {
+            const int u = unit(kb, g, j);
+            v8[j] = u >= 0 ? W2[(16 * t + n) * H + u] : 0.0f;
+          }
+          put(v8);
+        }
+      for (int kb = 0; kb < KB; ++kb) {
+        for (int j = 0; j < 8; ++j) {
+          const int u = unit(kb, g, j);
+          v8[j] = (u >= 0 && n < 5) ? W3[n * H + u] : 0.0f;
+        }
+        put(v8);
+      }
+    }
+  }
   const int fr = pack_rows(H, false), br = pack_rows(H, true);
   std::vector<float> f(static_cast<size_t>(fr) * kWave, 0.0f), b(static_cast<size_t>(br) * kWave, 0.0f);
   for (int l = 0; l < kWave; ++l) {
@@ -216,6 +297,8 @@ mppi_status validate(const mppi_config* c, const mppi_params* p, int* n_out, int
       if ((c->flags & MPPI_F_IMPORTANCE_SAMPLING) && !(sg > 0.0f))
         return fail(MPPI_EINVAL, "MPPI_F_IMPORTANCE_SAMPLING needs sigma_t[%lld] > 0", (long long)i);
     }
+  if (bf16_of(c) && c->dynamics != MPPI_DYN_BICYCLE_MLP)
+    return fail(MPPI_EINVAL, "MPPI_F_BF16_MLP is for BICYCLE_MLP dynamics");
   if (c->dynamics == MPPI_DYN_BICYCLE_MLP) {
     if (!p->mlp) return fail(MPPI_EINVAL, "MLP dynamics need the weight blob");
     if (p->mlp_hidden != 16 && p->mlp_hidden != 32 && p->mlp_hidden != 64)
@@ -334,6 +417,7 @@ Layout make_layout(const mppi_config* c, const mppi_params* p, int n, int m, boo
   const int H = mlp_hidden_of(c, p);
   L.mlp = take(sizeof(float) * kWave * (H ? pack_rows(H, false) : 1));
   L.mlp_bwd = take(sizeof(float) * kWave * (H ? pack_rows(H, true) : 1));
+  L.mlp_bf = take(sizeof(uint4) * kWave * (H && bf16_of(c) ? bf_pack_rows(H) : 1));
   if (wants_grad(c)) {
     const int ce = ckpt_every_of(p);
     const int nseg = (T + ce - 1) / ce;
@@ -692,9 +776,16 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
     std::vector<float4>& fwd = keep->back();
     keep->emplace_back();
     std::vector<float4>& bwd = keep->back();
-    build_mlp_packs(p->mlp, I->hidden, &fwd, &bwd);
+    std::vector<uint4> bfp;
+    build_mlp_packs(p->mlp, I->hidden, &fwd, &bwd, bf16_of(cfg) ? &bfp : nullptr);
     e = up(I->L.mlp, fwd.data(), sizeof(float4) * fwd.size());
     if (e == hipSuccess) e = up(I->L.mlp_bwd, bwd.data(), sizeof(float4) * bwd.size());
+    if (e == hipSuccess && !bfp.empty()) {
+      // staged through the kept buffers so the asynchronous copy's source lives on
+      keep->emplace_back(bfp.size());
+      memcpy(keep->back().data(), bfp.data(), sizeof(uint4) * bfp.size());
+      e = up(I->L.mlp_bf, keep->back().data(), sizeof(uint4) * bfp.size());
+    }
   }
   if (e != hipSuccess) return hip_fail(e, "parameter upload");
 
@@ -722,6 +813,7 @@ mppi_status setup_instance(const mppi_config* cfg, const mppi_params* p, bool ba
   d.mlp_hidden = I->hidden;
   d.mlp = I->hidden ? I->at<float>(I->L.mlp) : nullptr;
   d.mlp_bwd = I->hidden ? I->at<float>(I->L.mlp_bwd) : nullptr;
+  d.mlp_bf = I->hidden && bf16_of(cfg) ? I->at<uint4>(I->L.mlp_bf) : nullptr;
   d.cosines = p->cost_cosines;
   d.n_plain = n_plain_of(cfg);
   d.mean_sample = (cfg->flags & MPPI_F_MEAN_SAMPLE) ? 1 : 0;
@@ -816,7 +908,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   c->C = C;
   c->inst.resize(n_inst);
   std::vector<std::vector<float4>> keep;
-  keep.reserve(4 * n_inst);
+  keep.reserve(8 * n_inst);
   std::vector<DevState> states(n_inst);
   int64_t ox = 0, ou = 0, oS = 0;
   for (int i = 0; i < n_inst; ++i) {
@@ -934,7 +1026,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   const bool tiles = I0.hidden || I0.grad;
   c->tune.lanes_per_sample = tiles ? 16 : (batch ? 1 : I0.lanes);
   // MLP dynamics: the tile's MLP split over H/16 waves where that form exists
-  c->tune.rollout_block = I0.hidden >= 32 ? 4 * I0.hidden : 64;
+  c->tune.rollout_block = I0.hidden >= 32 && !I0.dp.mlp_bf ? 4 * I0.hidden : 64;
   c->tune.batch_tile = kBatchMaxTile;
   c->tune.noise_calls = 1;
   c->tune.rollout_form = MPPI_ROLLOUT_FUSED;
@@ -1274,8 +1366,8 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
   if (I.hidden || I.grad) {
     // waves per 16-sample tile: 1, or the MLP split over 2 (H = 32, 64) or 4 (H = 64)
     const int waves = t->rollout_block / kWave;
-    const bool split_ok = (I.hidden == 64 && (waves == 2 || waves == 4)) ||
-                          (I.hidden == 32 && waves == 2);
+    const bool split_ok = !I.dp.mlp_bf && ((I.hidden == 64 && (waves == 2 || waves == 4)) ||
+                                           (I.hidden == 32 && waves == 2));
     if (t->lanes_per_sample != 16 || !(t->rollout_block == 64 || split_ok))
       return fail(MPPI_EUNSUPPORTED, "MLP dynamics and gradient mode use 16 lanes per sample "
                   "and 64-thread workgroups, or 128 / 256 threads with the MLP split over "
@@ -1428,7 +1520,7 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     st = mppi_set_tuning(c, &best);
     if (st != MPPI_OK) return done(st);
     cands.clear();
-    if (tiles && I.hidden >= 32) {
+    if (tiles && I.hidden >= 32 && !I.dp.mlp_bf) {  // BF16 mode: single-wave tiles only
       for (int block : {64, 128, 256}) {
         if (block == 256 && I.hidden != 64) continue;
         mppi_tuning t = best;
@@ -1704,11 +1796,15 @@ mppi_status mppi_set_theta(mppi_ctx* c, const float* host_theta) {
   if (!(wheelbase > 0.0f)) return fail(MPPI_EINVAL, "wheelbase must be > 0");
   if (I.hidden) {
     std::vector<float4> fwd, bwd;
-    build_mlp_packs(host_theta, I.hidden, &fwd, &bwd);
+    std::vector<uint4> bfp;
+    build_mlp_packs(host_theta, I.hidden, &fwd, &bwd, bf16_of(&I.cfg) ? &bfp : nullptr);
     HIP_TRY(hipMemcpyAsync(I.at<char>(I.L.mlp), fwd.data(), sizeof(float4) * fwd.size(),
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(I.at<char>(I.L.mlp_bwd), bwd.data(), sizeof(float4) * bwd.size(),
                            hipMemcpyHostToDevice, c->stream));
+    if (!bfp.empty())
+      HIP_TRY(hipMemcpyAsync(I.at<char>(I.L.mlp_bf), bfp.data(), sizeof(uint4) * bfp.size(),
+                             hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
   for (int i = 0; i < I.n; ++i) I.dp.w[i] = host_theta[nmlp + i];

@@ -10,6 +10,8 @@
 // Checkpoints (optional): the state and the compensation terms of the
 // positions at t = 0, c, 2c, ... are stored as ckpt[s][7][ldk], so the
 // adjoint can rebuild each segment bit for bit.
+#include <type_traits>
+
 #include "mlp.h"
 #include "rollout.h"
 
@@ -18,7 +20,8 @@ namespace mppi {
 constexpr int kTile = 16;
 constexpr int kCkptWords = 7;
 
-template <int MT, int INTEG, class Cost, bool FAST>
+// BF: the MLP's products on bfloat16 operands (mlp::WeightsBf)
+template <int MT, int INTEG, class Cost, bool FAST, bool BF>
 __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
@@ -36,8 +39,11 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
   const float mean = plain ? 1.0f : 0.0f;
   // lanes past K recompute sample K-1 (they take part in the MFMAs) and store nothing
   const float* e = eps + (live ? k : K - 1);
-  mlp::Weights<MT ? MT : 1> W;
-  if constexpr (MT > 0) W.load(p.mlp, lane);
+  std::conditional_t<BF, mlp::WeightsBf<MT ? MT : 1>, mlp::Weights<MT ? MT : 1>> W;
+  if constexpr (MT > 0) {
+    if constexpr (BF) W.load(p.mlp_bf, p.mlp, lane);
+    else W.load(p.mlp, lane);
+  }
   float x[N], comp[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) { x[i] = x0[i]; comp[i] = 0.0f; }
@@ -234,19 +240,20 @@ namespace {
 using TileFn = void (*)(DevParams, const float*, const float*, const float*, int64_t, int, int,
                         float*, float*, int);
 
-template <int MT, int INTEG, bool FAST>
+template <int MT, int INTEG, bool FAST, bool BF>
 TileFn pick_cost(uint32_t cost) {
-  if (cost == MPPI_COST_TRACK) return rollout_tile_kernel<MT, INTEG, CostTrack, FAST>;
-  if (cost == MPPI_COST_QUADRATIC) return rollout_tile_kernel<MT, INTEG, CostQuadratic, FAST>;
+  if (cost == MPPI_COST_TRACK) return rollout_tile_kernel<MT, INTEG, CostTrack, FAST, BF>;
+  if (cost == MPPI_COST_QUADRATIC) return rollout_tile_kernel<MT, INTEG, CostQuadratic, FAST, BF>;
   return nullptr;
 }
 
-template <int MT>
+template <int MT, bool BF = false>
 TileFn pick_tile(uint32_t integrator, uint32_t cost, bool accurate) {
   if (integrator == MPPI_INT_RK4)
-    return accurate ? pick_cost<MT, kRK4, false>(cost) : pick_cost<MT, kRK4, true>(cost);
+    return accurate ? pick_cost<MT, kRK4, false, BF>(cost) : pick_cost<MT, kRK4, true, BF>(cost);
   if (integrator == MPPI_INT_EULER)
-    return accurate ? pick_cost<MT, kEuler, false>(cost) : pick_cost<MT, kEuler, true>(cost);
+    return accurate ? pick_cost<MT, kEuler, false, BF>(cost)
+                    : pick_cost<MT, kEuler, true, BF>(cost);
   return nullptr;
 }
 
@@ -270,13 +277,16 @@ TileFn pick_split(uint32_t integrator, uint32_t cost, bool accurate) {
 }
 
 TileFn select_tile(uint32_t dynamics, uint32_t integrator, uint32_t cost, bool accurate,
-                   int hidden) {
+                   int hidden, bool bf = false) {
   if (dynamics == MPPI_DYN_BICYCLE) return pick_tile<0>(integrator, cost, accurate);
   if (dynamics != MPPI_DYN_BICYCLE_MLP) return nullptr;
   switch (hidden) {
-    case 16: return pick_tile<1>(integrator, cost, accurate);
-    case 32: return pick_tile<2>(integrator, cost, accurate);
-    case 64: return pick_tile<4>(integrator, cost, accurate);
+    case 16: return bf ? pick_tile<1, true>(integrator, cost, accurate)
+                       : pick_tile<1>(integrator, cost, accurate);
+    case 32: return bf ? pick_tile<2, true>(integrator, cost, accurate)
+                       : pick_tile<2>(integrator, cost, accurate);
+    case 64: return bf ? pick_tile<4, true>(integrator, cost, accurate)
+                       : pick_tile<4>(integrator, cost, accurate);
     default: return nullptr;
   }
 }
@@ -294,8 +304,10 @@ hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t
                                 int waves) {
   // the split forms: H = 32 over 2 waves; H = 64 over 2 or 4 waves
   const bool mlp = dynamics == MPPI_DYN_BICYCLE_MLP;
+  const bool bf = mlp && p.mlp_bf != nullptr;  // BF16 mode: single-wave tiles only
   TileFn fn = nullptr;
-  if (waves == 1) fn = select_tile(dynamics, integrator, cost, accurate_trig, p.mlp_hidden);
+  if (waves == 1) fn = select_tile(dynamics, integrator, cost, accurate_trig, p.mlp_hidden, bf);
+  else if (bf) fn = nullptr;
   else if (mlp && p.mlp_hidden == 64 && waves == 4) fn = pick_split<4, 4>(integrator, cost, accurate_trig);
   else if (mlp && p.mlp_hidden == 64 && waves == 2) fn = pick_split<4, 2>(integrator, cost, accurate_trig);
   else if (mlp && p.mlp_hidden == 32 && waves == 2) fn = pick_split<2, 2>(integrator, cost, accurate_trig);
