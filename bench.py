@@ -66,7 +66,7 @@ def rollout_ops_per_step(wl) -> int:
     operation, a transcendental function one, sign and absolute-value source
     modifiers and exact power-of-two scalings are free, and terms that do not
     change over the four RK4 stages (the control held over the step) are
-    formed once per step.  The derivation is in the design doc, section 7."""
+    formed once per step."""
     v_form = wl.m                     # v = u + eps
     kahan = 4
     if wl.model == "bicycle":
