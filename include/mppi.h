@@ -138,8 +138,9 @@ enum {
                                 z, h1, h2 rounded to nearest-even from binary32)
                                 with binary32 accumulation on the matrix cores
                                 (v_mfma_f32_16x16x32_bf16); biases and tanh stay
-                                binary32.  Single-wave tiles only (rollout_block
-                                64).  With MPPI_F_REQUIRES_GRAD the adjoint
+                                binary32.  Every tile form (rollout_block 64, or
+                                the MLP split over 2 or 4 waves).  With
+                                MPPI_F_REQUIRES_GRAD the adjoint
                                 differentiates this forward with the roundings
                                 taken as the identity (the products' derivatives
                                 use the rounded weights and inputs).  Without it

@@ -589,7 +589,10 @@ struct SplitLds {
   }
 };
 
-template <int MT, int SW, bool FAST>
+// BF: the forward rebuild on the bfloat16 products as the split forward
+// kernel takes them (h2 tiles exchanged, the output over every K-block in
+// order), and the weight gradients over the rounded layer inputs.
+template <int MT, int SW, bool FAST, bool BF = false>
 __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
@@ -618,31 +621,49 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
   // this wave's operand slices
   const float* pf = p.mlp + lane;
   const float* pb = p.mlp_bwd + lane;
-  float fw1[TW][2], fw2[TW][MT][4], fw3[TW][4], bw3t[TW][2], bw2t[TW][MT][4], bw1t[TW][4];
+  constexpr int KB = mlp::PackBf<MT>::KB;
+  constexpr int TWF = BF ? 1 : TW, MTF = BF ? 1 : MT;
+  constexpr int TWB = BF ? TW : 1, KBB = BF ? KB : 1;
+  float fw1[TWF][2], fw2[TWF][MTF][4], fw3[TWF][4], bw3t[TW][2], bw2t[TW][MT][4], bw1t[TW][4];
+  mlp::bf8 v1[TWB], v2[TWB][KBB], v3[KBB];
   f4 fb1[TW], fb2[TW], fb3[TW];
 #pragma unroll
   for (int q = 0; q < TW; ++q) {
     const int t = q0 + q;
+    if constexpr (BF) {
+      using PB = mlp::PackBf<MT>;
+      const uint4* bp = p.mlp_bf + lane;
+      v1[q] = __builtin_bit_cast(mlp::bf8, bp[(PB::kW1 + t) * kWave]);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        v2[q][kb] = __builtin_bit_cast(mlp::bf8, bp[(PB::kW2 + t * KB + kb) * kWave]);
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      fw1[q][j] = pf[(PK::kW1 + 2 * t + j) * kWave];
+      if constexpr (!BF) fw1[q][j] = pf[(PK::kW1 + 2 * t + j) * kWave];
       bw3t[q][j] = pb[(PK::kW3t + 2 * t + j) * kWave];
     }
 #pragma unroll
     for (int tt = 0; tt < MT; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        fw2[q][tt][i] = pf[(PK::kW2 + (t * MT + tt) * 4 + i) * kWave];
+        if constexpr (!BF) fw2[q][tt][i] = pf[(PK::kW2 + (t * MT + tt) * 4 + i) * kWave];
         bw2t[q][tt][i] = pb[(PK::kW2t + (t * MT + tt) * 4 + i) * kWave];
       }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      fw3[q][i] = pf[(PK::kW3 + 4 * t + i) * kWave];
+      if constexpr (!BF) fw3[q][i] = pf[(PK::kW3 + 4 * t + i) * kWave];
       bw1t[q][i] = pb[(PK::kW1t + 4 * t + i) * kWave];
       fb1[q][i] = pf[(PK::kB1 + 4 * t + i) * kWave];
       fb2[q][i] = pf[(PK::kB2 + 4 * t + i) * kWave];
-      fb3[q][i] = t == 0 ? pf[(PK::kB3 + i) * kWave] : 0.0f;
+      fb3[q][i] = (BF || t == 0) ? pf[(PK::kB3 + i) * kWave] : 0.0f;
     }
+  }
+  if constexpr (BF) {
+    using PB = mlp::PackBf<MT>;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      v3[kb] = __builtin_bit_cast(mlp::bf8, p.mlp_bf[(PB::kW3 + kb) * kWave + lane]);
   }
 
   // this tile's pre-activation scratch: [c steps][2 layers][MT][64 lanes] f4
@@ -703,38 +724,73 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
       }
       // MLP forward, split (as the split forward kernel)
       f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
-      const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
+      if constexpr (BF) {
+        const mlp::bf8 zb = mlp::input_operand_bf(x, v, g);
 #pragma unroll
-      for (int q = 0; q < TW; ++q) {
-        const f4 a1 = mlp::mfma(fw1[q][1], z1, mlp::mfma(fw1[q][0], z0, fb1[q]));
-        ps[(q0 + q) * kWave] = a1;
-        xch(xa, par, q0 + q) = mlp::tanh4(a1);
+        for (int q = 0; q < TW; ++q) {
+          const f4 a1 = mlp::mfma_bf(v1[q], zb, fb1[q]);
+          ps[(q0 + q) * kWave] = a1;
+          xch(xa, par, q0 + q) = mlp::tanh4(a1);
+        }
+      } else {
+        const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
+#pragma unroll
+        for (int q = 0; q < TW; ++q) {
+          const f4 a1 = mlp::mfma(fw1[q][1], z1, mlp::mfma(fw1[q][0], z0, fb1[q]));
+          ps[(q0 + q) * kWave] = a1;
+          xch(xa, par, q0 + q) = mlp::tanh4(a1);
+        }
       }
       __syncthreads();
       f4 acc[TW];
 #pragma unroll
       for (int q = 0; q < TW; ++q) acc[q] = fb2[q];
+      f4 out;
+      if constexpr (BF) {
+        f4 h1a[MT];
 #pragma unroll
-      for (int tt = 0; tt < MT; ++tt) {
-        const f4 h = xch(xa, par, tt);
+        for (int tt = 0; tt < MT; ++tt) h1a[tt] = xch(xa, par, tt);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int kb = 0; kb < KB; ++kb) {
+          const mlp::bf8 hb = mlp::kblock_operand<MT>(h1a, kb);
 #pragma unroll
-          for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(fw2[q][tt][i], h[i], acc[q]);
+          for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma_bf(v2[q][kb], hb, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < TW; ++q) {
+          ps[(MT + q0 + q) * kWave] = acc[q];
+          xch(xb, par, q0 + q) = mlp::tanh4(acc[q]);
+        }
+        __syncthreads();
+        f4 h2a[MT];
+#pragma unroll
+        for (int tt = 0; tt < MT; ++tt) h2a[tt] = xch(xb, par, tt);
+        out = fb3[0];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) out = mlp::mfma_bf(v3[kb], mlp::kblock_operand<MT>(h2a, kb), out);
+      } else {
+#pragma unroll
+        for (int tt = 0; tt < MT; ++tt) {
+          const f4 h = xch(xa, par, tt);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(fw2[q][tt][i], h[i], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < TW; ++q) {
+          ps[(MT + q0 + q) * kWave] = acc[q];
+          const f4 h2 = mlp::tanh4(acc[q]);
+          f4 part = fb3[q];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[q][i], h2[i], part);
+          xch(xb, par, q0 + q) = part;
+        }
+        __syncthreads();
+        out = xch(xb, par, 0);
+#pragma unroll
+        for (int tt = 1; tt < MT; ++tt) out += xch(xb, par, tt);
       }
-#pragma unroll
-      for (int q = 0; q < TW; ++q) {
-        ps[(MT + q0 + q) * kWave] = acc[q];
-        const f4 h2 = mlp::tanh4(acc[q]);
-        f4 part = fb3[q];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[q][i], h2[i], part);
-        xch(xb, par, q0 + q) = part;
-      }
-      __syncthreads();
-      f4 out = xch(xb, par, 0);
-#pragma unroll
-      for (int tt = 1; tt < MT; ++tt) out += xch(xb, par, tt);
       par ^= 1;
       float res[N];
       mlp::broadcast5(out, n, res);
@@ -836,16 +892,17 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
         xch(xb, par, q0 + q) = zp;
         // the transposition buffer: the own rows
         const int qt = q0 + q;
-        *reinterpret_cast<f4*>(row + 16 * qt + 4 * g) = h1[q];
-        *reinterpret_cast<f4*>(row + H + 16 * qt + 4 * g) = h2[q];
+        *reinterpret_cast<f4*>(row + 16 * qt + 4 * g) = BF ? mlp::round_bf4(h1[q]) : h1[q];
+        *reinterpret_cast<f4*>(row + H + 16 * qt + 4 * g) = BF ? mlp::round_bf4(h2[q]) : h2[q];
         *reinterpret_cast<f4*>(row + 2 * H + 16 * qt + 4 * g) = da1[q];
         *reinterpret_cast<f4*>(row + 3 * H + 16 * qt + 4 * g) = da2[q];
       }
       if (w == 0) {  // z and c
-        const f4 zc = g == 0 ? f4{xt[0], xt[1], xt[2], xt[3]}
-                    : g == 1 ? f4{xt[4], v[0], v[1], 0.0f}
-                    : g == 2 ? f4{cg[0], cg[1], cg[2], cg[3]}
-                             : f4{cg[4], 0.0f, 0.0f, 0.0f};
+        f4 zc = g == 0 ? f4{xt[0], xt[1], xt[2], xt[3]}
+              : g == 1 ? f4{xt[4], v[0], v[1], 0.0f}
+              : g == 2 ? f4{cg[0], cg[1], cg[2], cg[3]}
+                       : f4{cg[4], 0.0f, 0.0f, 0.0f};
+        if (BF && g < 2) zc = mlp::round_bf4(zc);
         *reinterpret_cast<f4*>(row + 4 * H + 4 * g) = zc;
       }
       __syncthreads();
@@ -1013,7 +1070,10 @@ SweepFn pick_sweep(bool accurate) {
   return accurate ? adjoint_sweep_kernel<MT, false, BF> : adjoint_sweep_kernel<MT, true, BF>;
 }
 template <int MT, int SW>
-SweepFn pick_split_sweep(bool accurate) {
+SweepFn pick_split_sweep(bool accurate, bool bf) {
+  if (bf)
+    return accurate ? adjoint_sweep_split_kernel<MT, SW, false, true>
+                    : adjoint_sweep_split_kernel<MT, SW, true, true>;
   return accurate ? adjoint_sweep_split_kernel<MT, SW, false>
                   : adjoint_sweep_split_kernel<MT, SW, true>;
 }
@@ -1026,18 +1086,17 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
                           float* d_grad, hipStream_t stream, int waves, bool accumulate,
                           float* d_G_acc) {
   SweepFn fn = nullptr;
-  const bool bf = hidden > 0 && p.mlp_bf != nullptr;  // BF16 mode: single-wave sweep only
+  const bool bf = hidden > 0 && p.mlp_bf != nullptr;  // BF16 products
   size_t lds = adjoint_lds_bytes(hidden, ckpt_every, bf);
-  if (waves > 1 && bf) return hipErrorInvalidValue;
   if (waves > 1) {
     if (hidden == 64 && waves == 4) {
-      fn = pick_split_sweep<4, 4>(accurate_trig);
+      fn = pick_split_sweep<4, 4>(accurate_trig, bf);
       lds = SplitLds<4, 4>::bytes(ckpt_every);
     } else if (hidden == 64 && waves == 2) {
-      fn = pick_split_sweep<4, 2>(accurate_trig);
+      fn = pick_split_sweep<4, 2>(accurate_trig, bf);
       lds = SplitLds<4, 2>::bytes(ckpt_every);
     } else if (hidden == 32 && waves == 2) {
-      fn = pick_split_sweep<2, 2>(accurate_trig);
+      fn = pick_split_sweep<2, 2>(accurate_trig, bf);
       lds = SplitLds<2, 2>::bytes(ckpt_every);
     } else {
       return hipErrorInvalidValue;

@@ -1026,7 +1026,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   const bool tiles = I0.hidden || I0.grad;
   c->tune.lanes_per_sample = tiles ? 16 : (batch ? 1 : I0.lanes);
   // MLP dynamics: the tile's MLP split over H/16 waves where that form exists
-  c->tune.rollout_block = I0.hidden >= 32 && !I0.dp.mlp_bf ? 4 * I0.hidden : 64;
+  c->tune.rollout_block = I0.hidden >= 32 ? 4 * I0.hidden : 64;
   c->tune.batch_tile = kBatchMaxTile;
   c->tune.noise_calls = 1;
   c->tune.rollout_form = MPPI_ROLLOUT_FUSED;
@@ -1366,8 +1366,8 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
   if (I.hidden || I.grad) {
     // waves per 16-sample tile: 1, or the MLP split over 2 (H = 32, 64) or 4 (H = 64)
     const int waves = t->rollout_block / kWave;
-    const bool split_ok = !I.dp.mlp_bf && ((I.hidden == 64 && (waves == 2 || waves == 4)) ||
-                                           (I.hidden == 32 && waves == 2));
+    const bool split_ok = (I.hidden == 64 && (waves == 2 || waves == 4)) ||
+                          (I.hidden == 32 && waves == 2);
     if (t->lanes_per_sample != 16 || !(t->rollout_block == 64 || split_ok))
       return fail(MPPI_EUNSUPPORTED, "MLP dynamics and gradient mode use 16 lanes per sample "
                   "and 64-thread workgroups, or 128 / 256 threads with the MLP split over "
@@ -1520,7 +1520,7 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     st = mppi_set_tuning(c, &best);
     if (st != MPPI_OK) return done(st);
     cands.clear();
-    if (tiles && I.hidden >= 32 && !I.dp.mlp_bf) {  // BF16 mode: single-wave tiles only
+    if (tiles && I.hidden >= 32) {
       for (int block : {64, 128, 256}) {
         if (block == 256 && I.hidden != 64) continue;
         mppi_tuning t = best;

@@ -100,7 +100,11 @@ __global__ __launch_bounds__(kWave) void rollout_tile_kernel(
 // work is done once per tile instead of SW times.  More waves keep more
 // SIMDs busy, and a wave's matrix-core work overlaps another wave's VALU
 // work.
-template <int MT, int SW, int INTEG, class Cost, bool FAST>
+// BF (the bfloat16 products of mlp::hidden_bf / output_bf): the waves
+// exchange their h2 tiles instead of output partials, and the leader forms
+// the output over every K-block in order, so each product is the one-wave
+// kernel's and the results are bitwise the same as there too.
+template <int MT, int SW, int INTEG, class Cost, bool FAST, bool BF = false>
 __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, float* __restrict__ S,
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
   using P = mlp::Pack<MT>;
   constexpr int N = Model::N, M = Model::M;
   __shared__ f4 xh[2][MT][kWave];  // h1 tiles
-  __shared__ f4 xg[2][MT][kWave];  // output partials per K-tile
+  __shared__ f4 xg[2][MT][kWave];  // output partials per K-tile (BF: h2 tiles)
   __shared__ float xs[kTile][8];   // the leader's new state of the tile's samples
   extern __shared__ float4 lds[];
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
@@ -130,24 +134,45 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
   const int q0 = w * TW;
   const float* pk = p.mlp + lane;
   auto at = [&](int row) { return pk[row * kWave]; };
-  float w1[TW][2], w2[TW][MT][4], w3[TW][4];
+  // binary32 operands (unused in BF), and the bfloat16 ones (unused otherwise)
+  constexpr int KB = mlp::PackBf<MT>::KB;
+  constexpr int TWF = BF ? 1 : TW, MTF = BF ? 1 : MT;
+  constexpr int TWB = BF ? TW : 1, KBB = BF ? KB : 1;
+  float w1[TWF][2], w2[TWF][MTF][4], w3[TWF][4];
+  mlp::bf8 v1[TWB], v2[TWB][KBB], v3[KBB];
   f4 b1[TW], b2[TW], b3[TW];
 #pragma unroll
   for (int q = 0; q < TW; ++q) {
     const int t = q0 + q;
-    w1[q][0] = at(P::kW1 + 2 * t);
-    w1[q][1] = at(P::kW1 + 2 * t + 1);
+    if constexpr (BF) {
+      using PB = mlp::PackBf<MT>;
+      const uint4* bp = p.mlp_bf + lane;
+      v1[q] = __builtin_bit_cast(mlp::bf8, bp[(PB::kW1 + t) * kWave]);
 #pragma unroll
-    for (int tt = 0; tt < MT; ++tt)
+      for (int kb = 0; kb < KB; ++kb)
+        v2[q][kb] = __builtin_bit_cast(mlp::bf8, bp[(PB::kW2 + t * KB + kb) * kWave]);
+    } else {
+      w1[q][0] = at(P::kW1 + 2 * t);
+      w1[q][1] = at(P::kW1 + 2 * t + 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) w2[q][tt][i] = at(P::kW2 + (t * MT + tt) * 4 + i);
+      for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w2[q][tt][i] = at(P::kW2 + (t * MT + tt) * 4 + i);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w3[q][i] = at(P::kW3 + 4 * t + i);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      w3[q][i] = at(P::kW3 + 4 * t + i);
       b1[q][i] = at(P::kB1 + 4 * t + i);
       b2[q][i] = at(P::kB2 + 4 * t + i);
-      b3[q][i] = t == 0 ? at(P::kB3 + i) : 0.0f;
+      b3[q][i] = (BF || t == 0) ? at(P::kB3 + i) : 0.0f;
     }
+  }
+  if constexpr (BF) {
+    using PB = mlp::PackBf<MT>;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      v3[kb] = __builtin_bit_cast(mlp::bf8, p.mlp_bf[(PB::kW3 + kb) * kWave + lane]);
   }
   float x[N], comp[N];
 #pragma unroll
@@ -173,10 +198,17 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
       next_ckpt += ckpt_every;
     }
     // layer 1, own tiles
-    const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
+    if constexpr (BF) {
+      const mlp::bf8 zb = mlp::input_operand_bf(x, v, g);
 #pragma unroll
-    for (int q = 0; q < TW; ++q)
-      xh[par][q0 + q][lane] = mlp::tanh4(mlp::mfma(w1[q][1], z1, mlp::mfma(w1[q][0], z0, b1[q])));
+      for (int q = 0; q < TW; ++q) xh[par][q0 + q][lane] = mlp::tanh4(mlp::mfma_bf(v1[q], zb, b1[q]));
+    } else {
+      const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
+#pragma unroll
+      for (int q = 0; q < TW; ++q)
+        xh[par][q0 + q][lane] =
+            mlp::tanh4(mlp::mfma(w1[q][1], z1, mlp::mfma(w1[q][0], z0, b1[q])));
+    }
     __syncthreads();
     f4 h1[MT];  // every tile, the own ones included, read back from LDS
 #pragma unroll
@@ -185,26 +217,48 @@ __global__ __launch_bounds__(kWave * SW) void rollout_tile_split_kernel(
     f4 acc[TW];
 #pragma unroll
     for (int q = 0; q < TW; ++q) acc[q] = b2[q];
+    if constexpr (BF) {
 #pragma unroll
-    for (int tt = 0; tt < MT; ++tt)
+      for (int kb = 0; kb < KB; ++kb) {
+        const mlp::bf8 hb = mlp::kblock_operand<MT>(h1, kb);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma_bf(v2[q][kb], hb, acc[q]);
+      }
+      // the own h2 tiles to the leader
 #pragma unroll
-        for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(w2[q][tt][i], h1[tt][i], acc[q]);
-    // output partials of the own K-tiles
+      for (int q = 0; q < TW; ++q) xg[par][q0 + q][lane] = mlp::tanh4(acc[q]);
+    } else {
 #pragma unroll
-    for (int q = 0; q < TW; ++q) {
-      const f4 h2 = mlp::tanh4(acc[q]);
-      f4 part = b3[q];
+      for (int tt = 0; tt < MT; ++tt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) part = mlp::mfma(w3[q][i], h2[i], part);
-      xg[par][q0 + q][lane] = part;
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(w2[q][tt][i], h1[tt][i], acc[q]);
+      // output partials of the own K-tiles
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        const f4 h2 = mlp::tanh4(acc[q]);
+        f4 part = b3[q];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part = mlp::mfma(w3[q][i], h2[i], part);
+        xg[par][q0 + q][lane] = part;
+      }
     }
     __syncthreads();
     if (leader) {  // a wave-uniform branch
-      f4 out = xg[par][0][lane];
+      f4 out;
+      if constexpr (BF) {
+        f4 h2[MT];
 #pragma unroll
-      for (int tt = 1; tt < MT; ++tt) out += xg[par][tt][lane];
+        for (int tt = 0; tt < MT; ++tt) h2[tt] = xg[par][tt][lane];
+        out = b3[0];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) out = mlp::mfma_bf(v3[kb], mlp::kblock_operand<MT>(h2, kb), out);
+      } else {
+        out = xg[par][0][lane];
+#pragma unroll
+        for (int tt = 1; tt < MT; ++tt) out += xg[par][tt][lane];
+      }
       float res[N];
       mlp::broadcast5(out, n, res);
       step<Model, INTEG>(x, v, comp, p, res);
@@ -257,23 +311,29 @@ TileFn pick_tile(uint32_t integrator, uint32_t cost, bool accurate) {
   return nullptr;
 }
 
-template <int MT, int SW, int INTEG, bool FAST>
+template <int MT, int SW, int INTEG, bool FAST, bool BF>
 TileFn pick_split_cost(uint32_t cost) {
-  if (cost == MPPI_COST_TRACK) return rollout_tile_split_kernel<MT, SW, INTEG, CostTrack, FAST>;
+  if (cost == MPPI_COST_TRACK) return rollout_tile_split_kernel<MT, SW, INTEG, CostTrack, FAST, BF>;
   if (cost == MPPI_COST_QUADRATIC)
-    return rollout_tile_split_kernel<MT, SW, INTEG, CostQuadratic, FAST>;
+    return rollout_tile_split_kernel<MT, SW, INTEG, CostQuadratic, FAST, BF>;
+  return nullptr;
+}
+
+template <int MT, int SW, bool BF>
+TileFn pick_split_bf(uint32_t integrator, uint32_t cost, bool accurate) {
+  if (integrator == MPPI_INT_RK4)
+    return accurate ? pick_split_cost<MT, SW, kRK4, false, BF>(cost)
+                    : pick_split_cost<MT, SW, kRK4, true, BF>(cost);
+  if (integrator == MPPI_INT_EULER)
+    return accurate ? pick_split_cost<MT, SW, kEuler, false, BF>(cost)
+                    : pick_split_cost<MT, SW, kEuler, true, BF>(cost);
   return nullptr;
 }
 
 template <int MT, int SW>
-TileFn pick_split(uint32_t integrator, uint32_t cost, bool accurate) {
-  if (integrator == MPPI_INT_RK4)
-    return accurate ? pick_split_cost<MT, SW, kRK4, false>(cost)
-                    : pick_split_cost<MT, SW, kRK4, true>(cost);
-  if (integrator == MPPI_INT_EULER)
-    return accurate ? pick_split_cost<MT, SW, kEuler, false>(cost)
-                    : pick_split_cost<MT, SW, kEuler, true>(cost);
-  return nullptr;
+TileFn pick_split(uint32_t integrator, uint32_t cost, bool accurate, bool bf) {
+  return bf ? pick_split_bf<MT, SW, true>(integrator, cost, accurate)
+            : pick_split_bf<MT, SW, false>(integrator, cost, accurate);
 }
 
 TileFn select_tile(uint32_t dynamics, uint32_t integrator, uint32_t cost, bool accurate,
@@ -304,13 +364,12 @@ hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t
                                 int waves) {
   // the split forms: H = 32 over 2 waves; H = 64 over 2 or 4 waves
   const bool mlp = dynamics == MPPI_DYN_BICYCLE_MLP;
-  const bool bf = mlp && p.mlp_bf != nullptr;  // BF16 mode: single-wave tiles only
+  const bool bf = mlp && p.mlp_bf != nullptr;  // BF16 products
   TileFn fn = nullptr;
   if (waves == 1) fn = select_tile(dynamics, integrator, cost, accurate_trig, p.mlp_hidden, bf);
-  else if (bf) fn = nullptr;
-  else if (mlp && p.mlp_hidden == 64 && waves == 4) fn = pick_split<4, 4>(integrator, cost, accurate_trig);
-  else if (mlp && p.mlp_hidden == 64 && waves == 2) fn = pick_split<4, 2>(integrator, cost, accurate_trig);
-  else if (mlp && p.mlp_hidden == 32 && waves == 2) fn = pick_split<2, 2>(integrator, cost, accurate_trig);
+  else if (mlp && p.mlp_hidden == 64 && waves == 4) fn = pick_split<4, 4>(integrator, cost, accurate_trig, bf);
+  else if (mlp && p.mlp_hidden == 64 && waves == 2) fn = pick_split<4, 2>(integrator, cost, accurate_trig, bf);
+  else if (mlp && p.mlp_hidden == 32 && waves == 2) fn = pick_split<2, 2>(integrator, cost, accurate_trig, bf);
   if (!fn || (d_ckpt && ckpt_every < 1)) return hipErrorInvalidValue;
   const size_t lds = sizeof(float) * static_cast<size_t>(T) * 2;
   if (lds > 48 * 1024) {
