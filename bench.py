@@ -344,26 +344,46 @@ def run_single(args, wl, update_forms: bool = False, autotune_reps: int = 30) ->
            "us_per_iteration": s * 1e6 / I}
     if wl.cx is not None:
         out["obstacles"] = len(wl.cx)
+    chosen = ctl.tuning()
     if update_forms:
+        # the per-phase form with each update form, and the iteration forms
         forms = {}
-        chosen = ctl.tuning()["update_form"]
         for form, name in ((0, "two_pass"), (1, "one_pass"), (2, "chunked")):
             try:
-                ctl.set_tuning(update_form=form)
+                ctl.set_tuning(update_form=form, batch_form=0)
             except M.MPPIError:
                 continue
             forms[name] = timed(stream, lambda: ctl.iterate(I), args.steps,
                                 max(1, args.warmup)) * 1e3
-        ctl.set_tuning(update_form=chosen)
+        ctl.set_tuning(**chosen)
         out["update_forms_ms_per_step"] = forms
+        iforms = {}
+        for bf, name in ((0, "phases"), (1, "one_launch")):
+            try:
+                ctl.set_tuning(batch_form=bf)
+            except M.MPPIError:
+                continue
+            iforms[name] = timed(stream, lambda: ctl.iterate(I), args.steps,
+                                 max(1, args.warmup)) * 1e3
+        ctl.set_tuning(**chosen)
+        if len(iforms) > 1:
+            out["iteration_forms_ms_per_step"] = iforms
     t_noise, t_roll, t_upd = phase_times(ctl, args.kernel_reps)
     ops_step = rollout_ops_per_step(wl)
-    achieved = ops_step * steps_per_iter / t_roll
     tune = ctl.tuning()
+    fused = tune["batch_form"] == 1
+    if fused:
+        # the whole iteration is one launch: its duration from ten iterations
+        # replayed from one graph (an upper bound: the gaps between launches
+        # are counted)
+        t_roll = timed(stream, lambda: ctl.iterate(10), max(1, args.steps // 5),
+                       max(1, args.warmup // 5)) / 10
+    achieved = ops_step * steps_per_iter / t_roll
     split = tune["rollout_form"] == 1
     scan = tune["rollout_form"] == 2
     lanes = tune["lanes_per_sample"]
-    kernel = ("split_dynamics + split_cost" if split else
+    kernel = ("di_iteration_kernel (the whole iteration)" if fused else
+              "split_dynamics + split_cost" if split else
               "rollout_bicycle_scan_kernel" if scan else
               "rollout_bicycle_group_kernel" if lanes > 1 else "rollout_kernel")
     traffic = traffic_record("rollout", args.workload if args.workload != "all" else
@@ -374,7 +394,7 @@ def run_single(args, wl, update_forms: bool = False, autotune_reps: int = 30) ->
     out["roofline"] = {
         "bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
         "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS,
-        "traffic": None if split else traffic,
+        "traffic": None if (split or fused) else traffic,
         "kernel": kernel,
         "ops_per_rollout_step": ops_step, "launch_us": t_roll * 1e6}
     eps_bytes = 4 * wl.T * wl.m * wl.K
@@ -636,7 +656,8 @@ def main():
         line = headline_line(args, r, config={k: r[k] for k in (
             "workload", "K", "T", "iterations_per_step", "dynamics", "integrator", "cost")
             if k in r}, **{k: v for k, v in r.items() if k in (
-                "roofline", "kernels", "tuning", "rollout_forms_us", "update_forms_ms_per_step")})
+                "roofline", "kernels", "tuning", "rollout_forms_us", "update_forms_ms_per_step",
+                "iteration_forms_ms_per_step")})
         line["config"]["cost_cosines"] = int(getattr(wl, "cost_cosines", 0))
         if not args.no_cpu_baseline:
             line["cpu_baseline"] = cpu_baseline_single(wl, args.cpu_iters or wl.iters)

@@ -10,6 +10,7 @@
 // sequence of a batch is captured once in a hipGraph by the host code.
 #include "noise.h"
 #include "rollout.h"
+#include "rowscan.h"
 #include "softmin.h"
 #include "worklist.h"
 
@@ -243,8 +244,18 @@ __device__ __forceinline__ void instance_combine(const BatchInst& b, int ntile) 
   const float eta = v.x;
   const float wz = (finite && b.p.n_plain < b.K) ? v.z / eta : 0.0f;
   for (int r = tid; r < b.TM; r += kBatchMaxTile) {
+    // the tiles' partials of row r, kIn loads in flight, added in tile order
+    constexpr int kIn = 16;
     float tot = 0.0f;
-    for (int c = 0; c < ntile; ++c) tot += fsc[c] * b.tile_part[static_cast<int64_t>(c) * b.TM + r];
+    int c = 0;
+    for (; c + kIn <= ntile; c += kIn) {
+      float x[kIn];
+#pragma unroll
+      for (int q = 0; q < kIn; ++q) x[q] = b.tile_part[static_cast<int64_t>(c + q) * b.TM + r];
+#pragma unroll
+      for (int q = 0; q < kIn; ++q) tot += fsc[c + q] * x[q];
+    }
+    for (; c < ntile; ++c) tot += fsc[c] * b.tile_part[static_cast<int64_t>(c) * b.TM + r];
     if (eta > 0.0f) {
       float qv = tot / eta;
       if (wz != 0.0f) qv -= b.u[r] * wz;
@@ -287,6 +298,182 @@ __global__ __launch_bounds__(kBatchMaxTile) void batch_one_launch_kernel(BatchPl
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   instance_combine(inst, ntile);
   if (threadIdx.x == 0) __hip_atomic_store(&done[w.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// One iteration of a single instance of the double integrator with forward
+// Euler and the quadratic cost, in one launch and time-parallel.  With Euler
+// the model is linear: the velocity after step t is v_0 + sum_{s<=t} dt a_s
+// and the position after step t is p_0 + sum_{s<=t} dt vel_s, two prefix
+// sums over time, after which every running cost is evaluated in parallel.
+// A sample's horizon is spread over the 16 lanes of a DPP row: lane c owns
+// the steps [cC, cC + C), C even, so the Philox calls of its steps (two
+// steps of the two controls each) are its own.  A workgroup holds 16
+// samples (one tile) and
+//   1. each lane draws its steps' noise (exactly as the noise kernel draws
+//      it; staged through LDS so that the workgroup stores it in rows of 16
+//      consecutive samples) and forms v = mean u + eps;
+//   2. the velocities and positions come from two row scans; each lane sums
+//      its steps' running costs (Kahan), the row adds the lanes' sums in a
+//      fixed order and the terminal cost of the lane that holds x_T;
+//   3. the tile's samples are weighted against the tile's minimum, and its
+//      weighted noise rows sum_k e_k eps[r][k] formed from the lanes' own
+//      steps (xor shuffles over a wave's four samples, then the four waves
+//      in a fixed order through LDS);
+//   4. the completion counter and the last workgroup's combination are those
+//      of the batch's one-launch form (instance_combine).
+// ---------------------------------------------------------------------------
+constexpr int kDiLanes = 16;                          // lanes per sample
+constexpr int kDiSamples = kBatchMaxTile / kDiLanes;  // samples per workgroup
+
+template <int C>
+__global__ __launch_bounds__(kBatchMaxTile) void di_iteration_kernel(BatchInst b, uint32_t* done) {
+  constexpr int N = 4, M = 2, NW = kBatchMaxTile / kWave;
+  static_assert(C % 2 == 0, "whole Philox calls per lane");
+  using Cost = CostQuadratic;
+  __shared__ float part[NW][kDiLanes * M * C];
+  __shared__ float nz[kDiLanes * M * C][kDiSamples + 1];  // [row][sample], padded
+  __shared__ float lds_m[NW];
+  __shared__ float4 lds4[NW];
+  __shared__ int s_last;
+  const DevParams& p = b.p;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  const int c = tid % kDiLanes;
+  const int k = blockIdx.x * kDiSamples + tid / kDiLanes;
+  const bool valid = k < b.K;
+  const int kk = valid ? k : b.K - 1;  // lanes past K recompute sample K-1, store nothing
+  const int T = b.T;
+  const uint32_t it = b.st->iteration;  // read before this workgroup is counted
+  const bool plain = kk < p.n_plain;
+  const float mean = plain ? 1.0f : 0.0f;
+  const bool zero = p.mean_sample && kk == 0;
+  const int t0 = c * C;
+
+  // 1. the noise of the own steps (rows 2t, 2t + 1), and v
+  float eps[C][M], v[C][M];
+#pragma unroll
+  for (int q = 0; q < C / 2; ++q) {
+    const int call = t0 / 2 + q;
+    float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (2 * call < T)
+      noise::emit_call(b.key0, b.key1, it, b.instance, kk, call, 0, M, b.sigma.v, b.eps, b.ldk,
+                       p.sigma_t, zero, z);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = 2 * q + h, t = t0 + i;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        eps[i][j] = z[M * h + j];
+        v[i][j] = t < T ? mean * b.u[t * M + j] + eps[i][j] : 0.0f;
+        nz[t * M + j][tid / kDiLanes] = eps[i][j];
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < b.TM * kDiSamples; idx += kBatchMaxTile) {
+    const int r = idx / kDiSamples, sm = idx % kDiSamples;
+    const int ks = blockIdx.x * kDiSamples + sm;
+    if (ks < b.K) b.eps[static_cast<int64_t>(r) * b.ldk + ks] = nz[r][sm];
+  }
+
+  // 2. velocities (increments dt a_t), then positions (increments dt vel_t)
+  float vel[M], pos[M];
+  {
+    float tot[M] = {0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+#pragma unroll
+      for (int j = 0; j < M; ++j) tot[j] += p.dt * v[i][j];
+#pragma unroll
+    for (int j = 0; j < M; ++j) vel[j] = b.x0[2 + j] + row_exclusive(tot[j]);
+    float pv[M] = {0.0f, 0.0f}, w[M] = {vel[0], vel[1]};
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        pv[j] += p.dt * w[j];
+        w[j] += p.dt * v[i][j];
+      }
+#pragma unroll
+    for (int j = 0; j < M; ++j) pos[j] = b.x0[j] + row_exclusive(pv[j]);
+  }
+  typename Cost::State cs;
+  float sum = 0.0f, sum_c = 0.0f, term = 0.0f;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int t = t0 + i;
+    if (t < T) {
+      // x_{t+1}: the Euler step of the double integrator
+      float x[N], comp[N] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        x[j] = pos[j] + p.dt * vel[j];
+        x[2 + j] = vel[j] + p.dt * v[i][j];
+      }
+      bool hit;
+      float l = Cost::template running<N, M>(x, comp, v[i], t, p, nullptr, cs, hit);
+      if (p.importance && plain) l += is_term<M>(p, t, v[i], b.u + t * M);
+      if (p.cosines) l += inflation(p);
+      const float y = l - sum_c;
+      const float s2 = sum + y;
+      sum_c = (s2 - sum) - y;
+      sum = s2;
+      if (t == T - 1) term = terminal_cost<Cost, N>(x, T, p, nullptr, cs);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        pos[j] = x[j];
+        vel[j] = x[2 + j];
+      }
+    }
+  }
+  const int row0 = lane & ~(kDiLanes - 1);
+  const float run = __shfl(row_scan(sum - sum_c), row0 + kDiLanes - 1, kWave);
+  const float J0 = run + __shfl(term, row0 + (T - 1) / C, kWave);
+  const float J = __builtin_isfinite(J0) ? J0 : __builtin_inff();
+  if (valid && c == 0) b.S[k] = J;
+
+  // 3. the tile's weights and weighted noise rows
+  const int tile = blockIdx.x;
+  const float inf = __builtin_inff();
+  const float mt = block_min<NW>(valid ? J : inf, lds_m);
+  const float ek = (valid && J < inf) ? expf((mt - J) * b.inv_lambda) : 0.0f;
+  const float e1 = c == 0 ? ek : 0.0f;  // each sample once
+  float4 st4{wave_sum(e1), wave_sum(e1 * e1), wave_sum(kk >= p.n_plain ? e1 : 0.0f), 0.0f};
+  if (lane == 0) lds4[wv] = st4;
+#pragma unroll
+  for (int i = 0; i < C; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      float y = ek * eps[i][j];
+      y += __shfl_xor(y, 16, kWave);
+      y += __shfl_xor(y, 32, kWave);
+      if (lane < kDiLanes) part[wv][(t0 + i) * M + j] = y;
+    }
+  __syncthreads();
+  if (tid == 0) {
+    float4 a = lds4[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) { a.x += lds4[i].x; a.y += lds4[i].y; a.z += lds4[i].z; }
+    b.tile_stat[tile] = float4{mt, a.x, a.y, a.z};
+  }
+  static_assert(NW == 4, "the wave sums are added as a fixed tree of four");
+  for (int r = tid; r < b.TM; r += kBatchMaxTile)
+    b.tile_part[static_cast<int64_t>(tile) * b.TM + r] =
+        (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+
+  // 4. count the tile; the last one combines the tiles
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  const int ntile = static_cast<int>(gridDim.x);
+  if (tid == 0) {
+    const uint32_t old = __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = old + 1u == static_cast<uint32_t>(ntile);
+  }
+  __syncthreads();
+  if (!__builtin_amdgcn_readfirstlane(s_last)) return;  // the whole workgroup
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  instance_combine(b, ntile);
+  if (tid == 0) __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 namespace {
@@ -428,6 +615,39 @@ hipError_t launch_batch_one_launch(uint32_t dynamics, uint32_t integrator, uint3
   }
   hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(b.n_fused_items)), dim3(kBatchMaxTile),
                      b.rollout_lds, stream, b);
+  return hipGetLastError();
+}
+
+bool di_iteration_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int K, int T) {
+  return dynamics == MPPI_DYN_DOUBLE_INTEGRATOR && integrator == MPPI_INT_EULER &&
+         cost == MPPI_COST_QUADRATIC && K >= 1 && T >= 1 && T <= 256 &&
+         (K + kDiSamples - 1) / kDiSamples <= kOneLaunchMaxTiles;
+}
+
+int di_iteration_tiles(int K) { return (K + kDiSamples - 1) / kDiSamples; }
+
+hipError_t launch_di_iteration(const BatchInst& b, uint32_t* d_done, hipStream_t stream) {
+  if (!di_iteration_supported(MPPI_DYN_DOUBLE_INTEGRATOR, MPPI_INT_EULER, MPPI_COST_QUADRATIC, b.K,
+                              b.T) ||
+      b.TM != 2 * b.T)
+    return hipErrorInvalidValue;
+  // C = 2 ceil(T / 32): 16 lanes cover the horizon in whole Philox calls
+  const int C = 2 * ((b.T + 31) / 32);
+  using Fn = void (*)(BatchInst, uint32_t*);
+  Fn fn = nullptr;
+  switch (C) {
+    case 2: fn = di_iteration_kernel<2>; break;
+    case 4: fn = di_iteration_kernel<4>; break;
+    case 6: fn = di_iteration_kernel<6>; break;
+    case 8: fn = di_iteration_kernel<8>; break;
+    case 10: fn = di_iteration_kernel<10>; break;
+    case 12: fn = di_iteration_kernel<12>; break;
+    case 14: fn = di_iteration_kernel<14>; break;
+    case 16: fn = di_iteration_kernel<16>; break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(di_iteration_tiles(b.K))), dim3(kBatchMaxTile),
+                     0, stream, b, d_done);
   return hipGetLastError();
 }
 

@@ -306,6 +306,13 @@ hipError_t launch_batch_one_launch(uint32_t dynamics, uint32_t integrator, uint3
                                    bool accurate_trig, bool count, const BatchPlan& b,
                                    hipStream_t stream);
 bool batch_one_launch_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
+// One iteration of a single double-integrator instance (forward Euler, the
+// quadratic cost) in one time-parallel launch; K <= 4096, T <= 256.  b: the
+// instance's descriptor with tile partials for ceil(K / 16) tiles of 16
+// samples; d_done: its zeroed completion counter.
+bool di_iteration_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int K, int T);
+int di_iteration_tiles(int K);
+hipError_t launch_di_iteration(const BatchInst& b, uint32_t* d_done, hipStream_t stream);
 hipError_t launch_batch_set_iteration(const BatchPlan& b, uint32_t iteration, hipStream_t stream);
 
 // ---- wave / block reductions ------------------------------------------------

@@ -555,12 +555,20 @@ struct Instance {
 struct CtxLayout {
   size_t states, x0, u, S, crashes, insts, sample_tiles, row_tiles, one_items, done;
   size_t tile_part, tile_stat;  // the one-launch form's tile partials (packed)
+  bool one_single;  // a single context with the one-launch form (its tiles of 16 samples)
   std::vector<size_t> slice;
   size_t total;
   int n_sample_tiles, n_row_tiles;
   int64_t n_one_items;  // tiles of kBatchMaxTile samples
   int64_t n_tile_part;  // floats of tile partial rows: sum_i ntile_i T_i m_i
 };
+
+// A single context whose iteration also runs as one time-parallel launch
+// (launch_di_iteration).
+bool one_single_for(const mppi_config* c) {
+  return !wants_grad(c) && di_iteration_supported(c->dynamics, c->integrator, c->cost,
+                                                  c->num_samples, c->horizon);
+}
 
 CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, int n_inst,
                           bool batch) {
@@ -589,6 +597,13 @@ CtxLayout make_ctx_layout(const mppi_config* cfgs, const mppi_params* params, in
   C.u = take(sizeof(float) * nu);
   C.S = take(sizeof(float) * (nS + kWave));
   C.crashes = take(sizeof(int32_t) * (nS + kWave));
+  C.one_single = !batch && one_single_for(&cfgs[0]);
+  if (C.one_single) {
+    const int64_t nt = di_iteration_tiles(cfgs[0].num_samples);
+    C.done = take(sizeof(uint32_t));
+    C.tile_part = take(sizeof(float) * nt * cfgs[0].horizon * 2);
+    C.tile_stat = take(sizeof(float4) * nt);
+  }
   if (batch) {
     C.insts = take(sizeof(BatchInst) * n_inst);
     C.sample_tiles = take(sizeof(int2) * C.n_sample_tiles);
@@ -1018,6 +1033,9 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
       P.n_fused_items = static_cast<int>(one_items.size());
     }
   }
+  // a single context's one-launch form: its zeroed tile counter
+  if (C.one_single && e == hipSuccess)
+    e = hipMemsetAsync(c->ws + C.done, 0, sizeof(uint32_t), c->stream);
   const hipError_t e2 = hipStreamSynchronize(c->stream);  // host staging buffers die here
   if (e == hipSuccess) e = e2;
   // default launch shapes: four lanes per sample where one lane per sample
@@ -1148,6 +1166,33 @@ hipError_t phase_update(mppi_ctx* c, bool next = false) {
                                next ? &job : nullptr);
 }
 
+// The one-launch form of a single context: its descriptor (the batch's
+// instance descriptor, with tiles of 16 samples).
+BatchInst single_inst(const mppi_ctx* c) {
+  const Instance& I = c->one();
+  BatchInst b{};
+  b.p = I.dp;
+  b.x0 = I.x0; b.u = I.u; b.eps = I.eps(); b.S = I.S;
+  b.crashes = nullptr;
+  b.ldk = I.L.ldk; b.K = I.K; b.T = I.T; b.TM = I.TM;
+  b.lambda = I.cfg.lambda;
+  b.inv_lambda = static_cast<float>(1.0 / static_cast<double>(I.cfg.lambda));
+  b.step = step_size(I.cfg);
+  b.key0 = static_cast<uint32_t>(I.cfg.seed);
+  b.key1 = static_cast<uint32_t>(I.cfg.seed >> 32);
+  b.instance = I.cfg.instance;
+  for (int j = 0; j < I.m; ++j) b.sigma.v[j] = I.cfg.sigma[j];
+  b.e = I.e();
+  b.st = I.st;
+  b.tile_part = reinterpret_cast<float*>(c->ws + c->C.tile_part);
+  b.tile_stat = reinterpret_cast<float4*>(c->ws + c->C.tile_stat);
+  return b;
+}
+
+bool one_launch_single(const mppi_ctx* c) {
+  return !c->batch && c->tune.batch_form == MPPI_BATCH_ONE_LAUNCH;
+}
+
 // Iteration i of mppi_iterate.  A single context with two noise buffers
 // draws the noise of the first iteration only, and not even that when it was
 // drawn ahead; every update draws the next iteration's noise into the other
@@ -1155,6 +1200,9 @@ hipError_t phase_update(mppi_ctx* c, bool next = false) {
 // and switches buffers.  Other contexts sample in every iteration.
 hipError_t phase_iteration(mppi_ctx* c, int i, bool ahead) {
   hipError_t e = hipSuccess;
+  if (one_launch_single(c))
+    return launch_di_iteration(single_inst(c), reinterpret_cast<uint32_t*>(c->ws + c->C.done),
+                               c->stream);
   if (c->batch && c->tune.batch_form == MPPI_BATCH_ONE_LAUNCH) {
     const Instance& I = c->one();
     const bool count = (I.cfg.flags & MPPI_F_DEBUG) && uses_circles(I.cfg.cost);
@@ -1329,9 +1377,12 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
                 "or MPPI_UPDATE_CHUNKED");
   if (t->batch_form != MPPI_BATCH_PHASES && t->batch_form != MPPI_BATCH_ONE_LAUNCH)
     return fail(MPPI_EINVAL, "batch_form must be MPPI_BATCH_PHASES or MPPI_BATCH_ONE_LAUNCH");
-  if (t->batch_form == MPPI_BATCH_ONE_LAUNCH) {
-    if (!c->batch)
-      return fail(MPPI_EUNSUPPORTED, "the one-launch form is a form of batch contexts");
+  if (t->batch_form == MPPI_BATCH_ONE_LAUNCH && !c->batch) {
+    if (!c->C.one_single)
+      return fail(MPPI_EUNSUPPORTED, "the one-launch form of a single context exists for the "
+                  "double integrator with forward Euler and the quadratic cost, at most %d "
+                  "samples and 256 steps (no gradient mode)", kOneLaunchMaxTiles * 16);
+  } else if (t->batch_form == MPPI_BATCH_ONE_LAUNCH) {
     if (c->plan.n_fused_items < 1)
       return fail(MPPI_EUNSUPPORTED, "no one-launch kernel for this batch's dynamics and cost, "
                   "or an instance with more than %d samples", kOneLaunchMaxTiles * kBatchMaxTile);
@@ -1496,7 +1547,10 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
       b2.update_form = MPPI_UPDATE_TWO_PASS;
       b2.batch_form = MPPI_BATCH_ONE_LAUNCH;
       forms.push_back(b2);
-      st = search("iteration", forms, [&] { return phase_iteration(c, 0, false); }, &best);
+      // timed as mppi_iterate runs them: one iteration replayed from its graph
+      st = search("iteration", forms, [&] {
+        return mppi_iterate(c, 1) == MPPI_OK ? hipSuccess : hipErrorLaunchFailure;
+      }, &best);
       e = hipMemcpyAsync(c->ws + c->C.u, u_save.data(), sizeof(float) * u_save.size(),
                          hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess)
@@ -1573,6 +1627,42 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
       best.rollout_block = pick.rollout_block;
       best.rollout_form = pick.rollout_form;
       best.cost_waves = pick.cost_waves;
+    }
+    if (c->C.one_single) {
+      // a whole iteration in each form (the per-phase launches in the shapes
+      // chosen above, and the one-launch form); u, the iteration word and
+      // the current noise buffer are put back afterwards
+      std::vector<float> u_save(static_cast<size_t>(c->n_u));
+      DevState st_save{};
+      const int cur_save = c->inst[0].cur;
+      e = hipMemcpyAsync(u_save.data(), c->ws + c->C.u, sizeof(float) * u_save.size(),
+                         hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&st_save, c->ws + c->C.states, sizeof(DevState), hipMemcpyDeviceToHost,
+                           c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return done(hip_fail(e, "autotune save"));
+      std::vector<mppi_tuning> forms;
+      mppi_tuning a = best;
+      a.batch_form = MPPI_BATCH_PHASES;
+      forms.push_back(a);
+      mppi_tuning b2 = best;
+      b2.batch_form = MPPI_BATCH_ONE_LAUNCH;
+      forms.push_back(b2);
+      // timed as mppi_iterate runs them: one iteration replayed from its graph
+      st = search("iteration", forms, [&] {
+        return mppi_iterate(c, 1) == MPPI_OK ? hipSuccess : hipErrorLaunchFailure;
+      }, &best);
+      c->inst[0].cur = cur_save;
+      c->ahead = false;
+      e = hipMemcpyAsync(c->ws + c->C.u, u_save.data(), sizeof(float) * u_save.size(),
+                         hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + c->C.states, &st_save, sizeof(DevState), hipMemcpyHostToDevice,
+                           c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (st != MPPI_OK) return done(st);
+      if (e != hipSuccess) return done(hip_fail(e, "autotune restore"));
     }
   }
   st = mppi_set_tuning(c, &best);
@@ -1682,7 +1772,7 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
   // A single context's sequence starts in the buffer after the current one
   // (holding noise drawn ahead, if any) and ends with the last iteration's
   // noise current and the next call's drawn ahead in the other buffer.
-  const bool single = !c->batch && c->one().ahead_ok;
+  const bool single = !c->batch && c->one().ahead_ok && !one_launch_single(c);
   const bool ahead = single && c->ahead;
   const int start = single ? c->inst[0].cur ^ 1 : 0;
   const int last = start ^ ((num_iters - 1) & 1);
