@@ -421,29 +421,39 @@ def run_grad(args, wl, full: bool = True) -> dict:
     uref = torch.as_tensor(W.c5_uref(T=wl.T), device=dev)
     L = M.lib()
 
+    u_start = torch.as_tensor(wl.u0, device=dev).contiguous()
+
+    def configured(c):
+        # every timed step is the configured iteration: iteration word 0
+        # from the nominal controls u0 (so the samples of nonzero weight,
+        # which the backward sweeps, are the same in every step)
+        M._abi.check(L.mppi_set_controls(c.ctx, u_start.data_ptr()))
+        M._abi.check(L.mppi_set_iteration(c.ctx, 0))
+        M._abi.check(L.mppi_iterate(c.ctx, 1))
+
     def measure(w, three: bool):
         plain = M.Controller(w, device=dev)
         if not args.no_autotune:
             plain.autotune(reps=10)
         tuning = plain.tuning()
-        t_fwd = timed(plain.stream, lambda: plain.iterate(1), args.steps, args.warmup)
+        plain._enter()
+        t_fwd = timed(plain.stream, lambda: configured(plain), args.steps, args.warmup)
         t_noise, t_roll, t_upd = phase_times(plain, args.kernel_reps)
         plain.close()
         grad = M.Controller(w, device=dev, requires_grad=True)
         # the same launch shapes as the plain forward (the gradient mode has
         # the two-pass update only: its adjoint reads the stored weights)
         grad.set_tuning(**{k: v for k, v in tuning.items() if k != "update_form"})
-        grad.iterate(1)
+        grad._enter()
+        configured(grad)
         G = (2.0 * (grad.controls() - uref)).contiguous()
         out = torch.empty(grad.theta_len(), device=dev)
 
         def fwd_bwd():
-            M._abi.check(L.mppi_iterate(grad.ctx, 1))
+            configured(grad)
             M._abi.check(L.mppi_backward(grad.ctx, G.data_ptr(), out.data_ptr()))
-        grad._enter()
         t_fb = timed(grad.stream, fwd_bwd, args.steps, args.warmup)
-        t_fg = timed(grad.stream, lambda: M._abi.check(L.mppi_iterate(grad.ctx, 1)),
-                     args.steps, args.warmup)
+        t_fg = timed(grad.stream, lambda: configured(grad), args.steps, args.warmup)
         swept = int((grad.weights() > 0).sum())
         res = dict(t_fwd=t_fwd, t_noise=t_noise, t_roll=t_roll, t_upd=t_upd, t_fb=t_fb,
                    t_fg=t_fg, swept=swept, tuning=tuning)
