@@ -186,12 +186,14 @@ bool rollout_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost);
 // The time-parallel form of (a2) (rollout_scan.hip): the bicycle with RK4, a
 // sample's horizon spread over the 16 lanes of a DPP row (T <= 256); block:
 // threads per workgroup (64, 128, 256).
-bool rollout_scan_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int T);
+// lanes: per sample, 16 (one DPP row) or 32 (two)
+bool rollout_scan_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int T,
+                            int lanes = 16);
 hipError_t launch_rollout_scan(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                                bool accurate_trig, const DevParams& p, const float* d_x0,
                                const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                                float* d_S, int32_t* d_crashes, hipStream_t stream, int block,
-                               const NoiseJob* next = nullptr);
+                               const NoiseJob* next = nullptr, int lanes = 16);
 
 // The split form of (a2) (split.hip): a dynamics kernel writes the states
 // x_1..x_T of every sample to d_traj ([T][traj_words][ldk], the state then,

@@ -1131,7 +1131,8 @@ hipError_t phase_rollout(mppi_ctx* c, bool next = false) {
   if (c->tune.rollout_form == MPPI_ROLLOUT_SCAN)
     return launch_rollout_scan(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.dp, I.x0,
                                I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
-                               c->stream, c->tune.rollout_block, next ? &job : nullptr);
+                               c->stream, c->tune.rollout_block, next ? &job : nullptr,
+                               c->tune.lanes_per_sample);
   return launch_rollout(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, accurate, I.lanes, I.dp, I.x0,
                         I.u, I.eps(), I.L.ldk, I.K, I.T, I.S, count ? I.crashes : nullptr,
                         c->stream, c->tune.rollout_block, next ? &job : nullptr);
@@ -1408,11 +1409,12 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
   }
   if (t->rollout_form == MPPI_ROLLOUT_SCAN) {
     if (c->batch || I.hidden || I.grad ||
-        !rollout_scan_supported(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, I.T))
+        !rollout_scan_supported(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, I.T,
+                                t->lanes_per_sample == 32 ? 32 : 16))
       return fail(MPPI_EUNSUPPORTED, "the scan rollout form exists for single contexts with "
                   "bicycle dynamics, RK4 and at most 256 steps (no gradient mode)");
-    if (t->lanes_per_sample != 16)
-      return fail(MPPI_EINVAL, "scan form: lanes_per_sample must be 16");
+    if (t->lanes_per_sample != 16 && t->lanes_per_sample != 32)
+      return fail(MPPI_EINVAL, "scan form: lanes_per_sample must be 16 or 32");
   }
   if (I.hidden || I.grad) {
     // waves per 16-sample tile: 1, or the MLP split over 2 (H = 32, 64) or 4 (H = 64)
@@ -1428,8 +1430,9 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
     if (c->batch || !rollout_quad_available(I.cfg.dynamics, I.cfg.integrator))
       return fail(MPPI_EUNSUPPORTED, "4, 8 or 16 lanes per sample exist for a single bicycle "
                   "instance with RK4 only");
-  } else if (t->lanes_per_sample != 1) {
-    return fail(MPPI_EINVAL, "lanes_per_sample must be 1, 4, 8 or 16");
+  } else if (t->lanes_per_sample != 1 &&
+             !(t->lanes_per_sample == 32 && t->rollout_form == MPPI_ROLLOUT_SCAN)) {
+    return fail(MPPI_EINVAL, "lanes_per_sample must be 1, 4, 8 or 16 (or 32 in the scan form)");
   }
   if (c->batch && t->batch_tile != c->plan.tile) {
     const mppi_status st = upload_sample_tiles(c, t->batch_tile);
@@ -1594,14 +1597,17 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
         }
       }
       // the time-parallel scan form
-      if (rollout_scan_supported(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, I.T))
+      for (int lanes : {16, 32}) {
+        if (!rollout_scan_supported(I.cfg.dynamics, I.cfg.integrator, I.cfg.cost, I.T, lanes))
+          continue;
         for (int block : {64, 128, 256}) {
           mppi_tuning t = best;
           t.rollout_form = MPPI_ROLLOUT_SCAN;
-          t.lanes_per_sample = 16;
+          t.lanes_per_sample = lanes;
           t.rollout_block = block;
           cands.push_back(t);
         }
+      }
       // the split form (section "Choosing between the Split and Combined
       // Kernels": both are timed, the faster is kept)
       if (I.split)

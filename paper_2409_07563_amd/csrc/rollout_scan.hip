@@ -33,8 +33,47 @@ namespace mppi {
 
 namespace {
 
-constexpr int kScanLanes = 16;  // one DPP row per sample
 constexpr int kScanMaxBlock = 256;
+
+// Sums over a sample's group of L lanes: one DPP row (L = 16) or two
+// adjacent rows (L = 32: rows 0-1 and 2-3 of a wave).  Lane 15 of rows 0
+// and 2 is broadcast into rows 1 and 3 (0 in rows 0 and 2).
+__device__ __forceinline__ float row_bcast15(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+}
+__device__ __forceinline__ int row_bcast15_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+}
+// inclusive prefix sum over the group
+template <int L>
+__device__ __forceinline__ float group_scan(float v) {
+  v = row_scan(v);
+  if constexpr (L == 32) v += row_bcast15(v);
+  return v;
+}
+template <int L>
+__device__ __forceinline__ int group_scan_int(int v) {
+  v = row_scan_int(v);
+  if constexpr (L == 32) v += row_bcast15_int(v);
+  return v;
+}
+// the value of the group's previous lane (0 in its first lane)
+template <int L>
+__device__ __forceinline__ float group_shift(float v) {
+  if constexpr (L == 16) {
+    return row_dpp<kRowShr1>(v);
+  } else {
+    const int lw = static_cast<int>(threadIdx.x) & (kWave - 1);
+    const float prev = __shfl(v, (lw + kWave - 1) & (kWave - 1), kWave);
+    return (lw & (L - 1)) == 0 ? 0.0f : prev;
+  }
+}
+// exclusive prefix sum over the group
+template <int L>
+__device__ __forceinline__ float group_exclusive(float v) {
+  if constexpr (L == 16) return row_exclusive(v);
+  return group_shift<L>(group_scan<L>(v));
+}
 
 // (h, l) += (bh, bl) in double-binary32 arithmetic (Knuth's TwoSum of the
 // high parts, the low parts added to its error, renormalised).
@@ -52,14 +91,19 @@ __device__ __forceinline__ void dd_scan_step(float& h, float& l) {
   const float oh = row_dpp<CTRL>(h), ol = row_dpp<CTRL>(l);
   dd_add(h, l, oh, ol);
 }
-// exclusive double-binary32 prefix sum over the row
-__device__ __forceinline__ void dd_row_exclusive(float& h, float& l) {
+// exclusive double-binary32 prefix sum over the group
+template <int L>
+__device__ __forceinline__ void dd_group_exclusive(float& h, float& l) {
   dd_scan_step<kRowShr1>(h, l);
   dd_scan_step<kRowShr2>(h, l);
   dd_scan_step<kRowShr4>(h, l);
   dd_scan_step<kRowShr8>(h, l);
-  h = row_dpp<kRowShr1>(h);
-  l = row_dpp<kRowShr1>(l);
+  if constexpr (L == 32) {
+    const float oh = row_bcast15(h), ol = row_bcast15(l);
+    if ((threadIdx.x >> 4) & 1) dd_add(h, l, oh, ol);  // rows 1 and 3
+  }
+  h = group_shift<L>(h);
+  l = group_shift<L>(l);
 }
 
 template <bool FAST>
@@ -82,9 +126,10 @@ __device__ __forceinline__ void sincos_of(float x, float* s, float* c) {
 
 }  // namespace
 
-// CMAX: the chunk length the kernel is compiled for (C <= CMAX, T <= 16 CMAX);
-// steps j >= C of a chunk are zero.
-template <class Cost, bool FAST, bool COUNT, int CMAX>
+// L: lanes per sample (16: one DPP row, or 32: two); CMAX: the chunk length
+// the kernel is compiled for (C <= CMAX, T <= L CMAX); steps j >= C of a
+// chunk are zero.
+template <class Cost, bool FAST, bool COUNT, int CMAX, int L>
 __global__ __launch_bounds__(kScanMaxBlock) void rollout_bicycle_scan_kernel(
     DevParams p, const float* __restrict__ x0, const float* __restrict__ u,
     const float* __restrict__ eps, int64_t ldk, int K, int T, int C, float* __restrict__ S,
@@ -97,9 +142,9 @@ __global__ __launch_bounds__(kScanMaxBlock) void rollout_bicycle_scan_kernel(
   extern __shared__ float4 lds[];
   const float* lds_u = stage_rollout_lds<Cost>(p, u, T * M, lds);
   const int gl = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = gl & (kScanLanes - 1);  // chunk of the horizon
-  const int k = gl / kScanLanes;
-  if (k >= K) return;  // whole rows leave together; no barrier follows
+  const int lane = gl & (L - 1);  // chunk of the horizon
+  const int k = gl / L;
+  if (k >= K) return;  // whole groups leave together; no barrier follows
   const int t0 = lane * C;
   const int nloc = max(0, min(C, T - t0));  // steps of this lane
   const float mean = k < p.n_plain ? 1.0f : 0.0f;  // drawn around u, or around zero
@@ -125,8 +170,8 @@ __global__ __launch_bounds__(kScanMaxBlock) void rollout_bicycle_scan_kernel(
     tot_r = fmaf(p.dt, vr[j], tot_r);
   }
   // round 1: speed and steer at the chunk's first step
-  const float s_c = x0[3] + row_exclusive(tot_a);
-  const float d_c = x0[4] + row_exclusive(tot_r);
+  const float s_c = x0[3] + group_exclusive<L>(tot_a);
+  const float d_c = x0[4] + group_exclusive<L>(tot_r);
 
   // round 2: stage yaw rates and yaw increments
   float k1[CMAX], k2[CMAX], dpsi[CMAX];
@@ -157,7 +202,7 @@ __global__ __launch_bounds__(kScanMaxBlock) void rollout_bicycle_scan_kernel(
       tn = tf;
     }
   }
-  const float psi_c = x0[2] + row_exclusive(tot_psi);
+  const float psi_c = x0[2] + group_exclusive<L>(tot_psi);
 
   // round 3: position increments (four sin / cos pairs per step)
   float dpx[CMAX], dpy[CMAX];
@@ -198,8 +243,8 @@ __global__ __launch_bounds__(kScanMaxBlock) void rollout_bicycle_scan_kernel(
       s = sf;
     }
   }
-  dd_row_exclusive(hx, lx);
-  dd_row_exclusive(hy, ly);
+  dd_group_exclusive<L>(hx, lx);
+  dd_group_exclusive<L>(hy, ly);
 
   // round 4: every step's post-step state and its running cost
   typename Cost::State cs;
@@ -256,12 +301,12 @@ __global__ __launch_bounds__(kScanMaxBlock) void rollout_bicycle_scan_kernel(
   }
   // the lane holding step T - 1 adds the terminal cost on x_T
   if (nloc > 0 && t0 + nloc == T) add(terminal_cost<Cost, N>(x, T, p, lds, cs));
-  // the row's sum in a fixed order; lane 15 holds it
-  const float total = row_scan(sum - sum_c);
-  if (lane == kScanLanes - 1) S[k] = __builtin_isfinite(total) ? total : __builtin_inff();
+  // the group's sum in a fixed order; its last lane holds it
+  const float total = group_scan<L>(sum - sum_c);
+  if (lane == L - 1) S[k] = __builtin_isfinite(total) ? total : __builtin_inff();
   if constexpr (COUNT) {
-    const int n = row_scan_int(ncrash);
-    if (lane == kScanLanes - 1) crashes[k] = n;
+    const int n = group_scan_int<L>(ncrash);
+    if (lane == L - 1) crashes[k] = n;
   }
 }
 
@@ -270,55 +315,65 @@ namespace {
 using ScanFn = void (*)(DevParams, const float*, const float*, const float*, int64_t, int, int,
                         int, float*, int32_t*, int, NoiseJob);
 
-template <class Cost, bool FAST, int CMAX>
+template <class Cost, bool FAST, int CMAX, int L>
 ScanFn pick_scan(bool count) {
-  if (count) return rollout_bicycle_scan_kernel<Cost, FAST, true, CMAX>;
-  return rollout_bicycle_scan_kernel<Cost, FAST, false, CMAX>;
+  if (count) return rollout_bicycle_scan_kernel<Cost, FAST, true, CMAX, L>;
+  return rollout_bicycle_scan_kernel<Cost, FAST, false, CMAX, L>;
 }
 
 template <class Cost, bool FAST>
-ScanFn pick_scan_chunk(int C, bool count) {
-  // the chunk loops run CMAX steps: compiled for the chunks of T = 64, 112,
-  // 160, 208 and 256 (C = 4, 7, 10, 13, 16; T = 100 and 200 take C = 7, 13)
-  if (C <= 4) return pick_scan<Cost, FAST, 4>(count);
-  if (C <= 7) return pick_scan<Cost, FAST, 7>(count);
-  if (C <= 10) return pick_scan<Cost, FAST, 10>(count);
-  if (C <= 13) return pick_scan<Cost, FAST, 13>(count);
-  if (C <= 16) return pick_scan<Cost, FAST, 16>(count);
+ScanFn pick_scan_chunk(int C, int L, bool count) {
+  // the chunk loops run CMAX steps.  16 lanes: compiled for the chunks of
+  // T = 64, 112, 160, 208 and 256 (C = 4, 7, 10, 13, 16; T = 100 and 200
+  // take C = 7, 13); 32 lanes: T = 128 and 256 (C = 4, 8)
+  if (L == 32) {
+    if (C <= 4) return pick_scan<Cost, FAST, 4, 32>(count);
+    if (C <= 8) return pick_scan<Cost, FAST, 8, 32>(count);
+    return nullptr;
+  }
+  if (L != 16) return nullptr;
+  if (C <= 4) return pick_scan<Cost, FAST, 4, 16>(count);
+  if (C <= 7) return pick_scan<Cost, FAST, 7, 16>(count);
+  if (C <= 10) return pick_scan<Cost, FAST, 10, 16>(count);
+  if (C <= 13) return pick_scan<Cost, FAST, 13, 16>(count);
+  if (C <= 16) return pick_scan<Cost, FAST, 16, 16>(count);
   return nullptr;
 }
 
 template <bool FAST>
-ScanFn pick_scan_cost(uint32_t cost, int C, bool count) {
+ScanFn pick_scan_cost(uint32_t cost, int C, int L, bool count) {
   switch (cost) {
-    case MPPI_COST_PATH_CIRCLES: return pick_scan_chunk<CostPath<true>, FAST>(C, count);
-    case MPPI_COST_PATH_COSTMAP: return pick_scan_chunk<CostPath<false>, FAST>(C, count);
-    case MPPI_COST_GOAL_CIRCLES: return pick_scan_chunk<CostGoalCircles, FAST>(C, count);
-    case MPPI_COST_QUADRATIC: return pick_scan_chunk<CostQuadratic, FAST>(C, count);
-    case MPPI_COST_TRACK: return pick_scan_chunk<CostTrack, FAST>(C, count);
+    case MPPI_COST_PATH_CIRCLES: return pick_scan_chunk<CostPath<true>, FAST>(C, L, count);
+    case MPPI_COST_PATH_COSTMAP: return pick_scan_chunk<CostPath<false>, FAST>(C, L, count);
+    case MPPI_COST_GOAL_CIRCLES: return pick_scan_chunk<CostGoalCircles, FAST>(C, L, count);
+    case MPPI_COST_QUADRATIC: return pick_scan_chunk<CostQuadratic, FAST>(C, L, count);
+    case MPPI_COST_TRACK: return pick_scan_chunk<CostTrack, FAST>(C, L, count);
     default: return nullptr;
   }
 }
 
 }  // namespace
 
-bool rollout_scan_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int T) {
-  const int C = (T + kScanLanes - 1) / kScanLanes;
+bool rollout_scan_supported(uint32_t dynamics, uint32_t integrator, uint32_t cost, int T,
+                            int lanes) {
+  if (lanes != 16 && lanes != 32) return false;
+  const int C = (T + lanes - 1) / lanes;
   return dynamics == MPPI_DYN_BICYCLE && integrator == MPPI_INT_RK4 && T >= 1 &&
-         pick_scan_cost<true>(cost, C, false) != nullptr;
+         pick_scan_cost<true>(cost, C, lanes, false) != nullptr;
 }
 
 hipError_t launch_rollout_scan(uint32_t dynamics, uint32_t integrator, uint32_t cost,
                                bool accurate_trig, const DevParams& p, const float* d_x0,
                                const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                                float* d_S, int32_t* d_crashes, hipStream_t stream, int block,
-                               const NoiseJob* next) {
+                               const NoiseJob* next, int lanes) {
   if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
-  if (!rollout_scan_supported(dynamics, integrator, cost, T) || K < 1) return hipErrorInvalidValue;
-  const int C = (T + kScanLanes - 1) / kScanLanes;
+  if (!rollout_scan_supported(dynamics, integrator, cost, T, lanes) || K < 1)
+    return hipErrorInvalidValue;
+  const int C = (T + lanes - 1) / lanes;
   const bool count = d_crashes != nullptr;
-  ScanFn fn = accurate_trig ? pick_scan_cost<false>(cost, C, count)
-                            : pick_scan_cost<true>(cost, C, count);
+  ScanFn fn = accurate_trig ? pick_scan_cost<false>(cost, C, lanes, count)
+                            : pick_scan_cost<true>(cost, C, lanes, count);
   if (!fn) return hipErrorInvalidValue;
   const size_t lds = rollout_lds_bytes(dynamics, cost, p.stage_words4, T);
   if (lds > 48 * 1024) {
@@ -327,7 +382,7 @@ hipError_t launch_rollout_scan(uint32_t dynamics, uint32_t integrator, uint32_t 
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  const int64_t threads = static_cast<int64_t>(K) * kScanLanes;
+  const int64_t threads = static_cast<int64_t>(K) * lanes;
   const int rblocks = static_cast<int>((threads + block - 1) / block);
   NoiseJob job{};
   int blocks = rblocks;

@@ -1,7 +1,7 @@
 """The time-parallel (scan) rollout form of the bicycle with RK4, against the
 binary64 oracle through the C ABI: each sample's horizon is spread over the 16
-lanes of a DPP row, the speed, steer, yaw and position as prefix sums over
-time, then every step's running cost in parallel.  Checked as every other
+lanes of a DPP row (or the 32 of two rows), the speed, steer, yaw and position
+as prefix sums over time, then every step's running cost in parallel.  Checked as every other
 rollout kernel is (tests/parity.py): costs, crash counts, the controls end to
 end, horizons that fill every compiled chunk length, the sampling and update
 options, and the benchmark workload over ten warm-started iterations from a
@@ -70,10 +70,10 @@ def _cases():
 CASES = _cases()
 
 
-def _one(mppi, wl, block=256, accurate=False, debug=True):
+def _one(mppi, wl, block=256, accurate=False, debug=True, lanes=16):
     ctl = mppi.Controller(wl, debug=debug and wl.cost in ("path_circles", "goal_circles"),
                           accurate_trig=accurate)
-    ctl.set_tuning(rollout_block=block, **SCAN)
+    ctl.set_tuning(rollout_block=block, **dict(SCAN, lanes_per_sample=lanes))
     ctl.sample()
     ctl.rollout()
     S = _np(ctl.costs())
@@ -86,11 +86,12 @@ def _one(mppi, wl, block=256, accurate=False, debug=True):
     return dict(S=S, eps=eps, U=U, crashes=crashes, stats=st)
 
 
+@pytest.mark.parametrize("lanes", [16, 32])
 @pytest.mark.parametrize("accurate", [False, True], ids=["hw_trig", "lib_trig"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_scan_rollout_parity(mppi, oracle_lib, name, accurate):
+def test_scan_rollout_parity(mppi, oracle_lib, name, accurate, lanes):
     wl = CASES[name]
-    g = _one(mppi, wl, accurate=accurate)
+    g = _one(mppi, wl, accurate=accurate, lanes=lanes)
     eps_or = oracle_lib.workload_noise(wl)
     assert np.array_equal(g["eps"].view(np.uint32), eps_or.view(np.uint32))
     S_or, margin, crashes, slope = oracle_lib.rollout_costs(wl, eps=eps_or, slope=True)
@@ -104,23 +105,26 @@ def test_scan_rollout_parity(mppi, oracle_lib, name, accurate):
         assert g["stats"]["ess"] > 50
 
 
-# every compiled chunk length (C = 4, 7, 10, 13, 16) with full, partial and
-# empty lanes, single samples and partial rows of the last wave
+# every compiled chunk length (16 lanes: C = 4, 7, 10, 13, 16; 32 lanes:
+# C = 4, 8) with full, partial and empty lanes, single samples and partial
+# rows and groups of the last wave
+@pytest.mark.parametrize("lanes", [16, 32])
 @pytest.mark.parametrize("K,T", [(1, 1), (3, 5), (17, 6), (64, 7), (65, 4), (33, 23), (5, 64),
                                  (7, 65), (9, 112), (3, 113), (2, 160), (4, 161), (6, 208),
-                                 (11, 209), (5, 256), (1, 250)])
+                                 (11, 209), (5, 256), (1, 250), (2, 128), (3, 129)])
 @pytest.mark.parametrize("block", [64, 256])
-def test_scan_ragged_shapes(mppi, oracle_lib, K, T, block):
+def test_scan_ragged_shapes(mppi, oracle_lib, K, T, block, lanes):
     wl = W.c2("circles", K=K, T=T, iters=1)
-    g = _one(mppi, wl, block=block)
+    g = _one(mppi, wl, block=block, lanes=lanes)
     S_or, margin, crashes = oracle_lib.rollout_costs(wl, eps=oracle_lib.workload_noise(wl))
-    parity.assert_costs_close(g["S"], S_or, margin, f"scan K{K} T{T} block {block}")
+    parity.assert_costs_close(g["S"], S_or, margin, f"scan K{K} T{T} block {block} lanes {lanes}")
     sure = margin >= parity.AMBIGUOUS_MARGIN
     assert np.array_equal(g["crashes"][sure], crashes[sure])
 
 
+@pytest.mark.parametrize("lanes", [16, 32])
 @pytest.mark.parametrize("opt", ["is_gamma", "zero_mean", "mean_sample", "sigma_t"])
-def test_scan_sampling_and_update_options(mppi, oracle_lib, opt):
+def test_scan_sampling_and_update_options(mppi, oracle_lib, opt, lanes):
     wl = W.c2("circles", K=1500, T=93, iters=1)
     u0 = np.random.default_rng(3).normal(0.0, 0.5, (wl.T, wl.m)).astype(np.float32)
     wl = wl.replace(u0=u0)
@@ -133,7 +137,7 @@ def test_scan_sampling_and_update_options(mppi, oracle_lib, opt):
     else:
         sig = np.linspace(0.5, 1.5, wl.T)[:, None] * wl.sigma[None, :]
         wl = wl.replace(sigma_t=sig.astype(np.float32))
-    g = _one(mppi, wl)
+    g = _one(mppi, wl, lanes=lanes)
     eps_or = oracle_lib.workload_noise(wl)
     assert np.array_equal(g["eps"].view(np.uint32), eps_or.view(np.uint32))
     S_or, margin, _ = oracle_lib.rollout_costs(wl, eps=eps_or)
@@ -141,18 +145,20 @@ def test_scan_sampling_and_update_options(mppi, oracle_lib, opt):
     parity.assert_end_to_end(oracle_lib, wl, g["U"], g["S"], eps_or, S_or, f"scan {opt}")
 
 
-def test_scan_full_size_ten_iterations(mppi, oracle_lib):
+@pytest.mark.parametrize("lanes", [16, 32])
+def test_scan_full_size_ten_iterations(mppi, oracle_lib, lanes):
     """The benchmark workload (K 8192, T 100) in the scan form: ten iterations
     replayed from the captured graph equal ten single iterations bitwise, and
     every iteration matches the oracle from the oracle's own warm start."""
     wl = W.c2("circles")
+    tune = dict(SCAN, lanes_per_sample=lanes)
     seq = mppi.Controller(wl)
-    seq.set_tuning(**SCAN)
+    seq.set_tuning(**tune)
     seq.iterate(wl.iters)
     U_seq, S_seq = _np(seq.controls()), _np(seq.costs())
     seq.close()
     ctl = mppi.Controller(wl)
-    ctl.set_tuning(**SCAN)
+    ctl.set_tuning(**tune)
     u = wl.u0.astype(np.float64)
     U_one = S_one = None
     for i in range(wl.iters):
@@ -170,7 +176,7 @@ def test_scan_full_size_ten_iterations(mppi, oracle_lib):
     ctl.close()
     # the graph sequence against single iterations on the GPU's own warm start
     one = mppi.Controller(wl)
-    one.set_tuning(**SCAN)
+    one.set_tuning(**tune)
     for _ in range(wl.iters):
         one.iterate(1)
     U_one, S_one = _np(one.controls()), _np(one.costs())
