@@ -1493,8 +1493,10 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     mppi_tuning t;
     double us;
   };
+  // margin: a later candidate replaces the one kept so far only if it is
+  // faster by more than this fraction (the first candidate is the default)
   auto search = [&](const char* phase, std::vector<mppi_tuning> cands, auto fn,
-                    mppi_tuning* chosen) -> mppi_status {
+                    mppi_tuning* chosen, double margin = 0.0) -> mppi_status {
     std::vector<Cand> cs;
     for (const mppi_tuning& t : cands) cs.push_back(Cand{t, 1e300});
     for (int r = 0; r < kRounds; ++r)
@@ -1509,7 +1511,7 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
     const Cand* b = &cs[0];
     for (const Cand& cd : cs) {
       line(phase, cd.t, cd.us);
-      if (cd.us < b->us) b = &cd;
+      if (cd.us < b->us * (1.0 - margin)) b = &cd;
     }
     *chosen = b->t;
     return MPPI_OK;
@@ -1551,9 +1553,10 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
       b2.batch_form = MPPI_BATCH_ONE_LAUNCH;
       forms.push_back(b2);
       // timed as mppi_iterate runs them: one iteration replayed from its graph
+      // (the one-launch form is kept only when clearly faster: 5 %)
       st = search("iteration", forms, [&] {
         return mppi_iterate(c, 1) == MPPI_OK ? hipSuccess : hipErrorLaunchFailure;
-      }, &best);
+      }, &best, 0.05);
       e = hipMemcpyAsync(c->ws + c->C.u, u_save.data(), sizeof(float) * u_save.size(),
                          hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess)
@@ -1656,9 +1659,10 @@ mppi_status mppi_autotune(mppi_ctx* c, int32_t reps, char* report, size_t report
       b2.batch_form = MPPI_BATCH_ONE_LAUNCH;
       forms.push_back(b2);
       // timed as mppi_iterate runs them: one iteration replayed from its graph
+      // (the one-launch form is kept only when clearly faster: 5 %)
       st = search("iteration", forms, [&] {
         return mppi_iterate(c, 1) == MPPI_OK ? hipSuccess : hipErrorLaunchFailure;
-      }, &best);
+      }, &best, 0.05);
       c->inst[0].cur = cur_save;
       c->ahead = false;
       e = hipMemcpyAsync(c->ws + c->C.u, u_save.data(), sizeof(float) * u_save.size(),
