@@ -419,9 +419,10 @@ mppi_status mppi_set_costs(mppi_ctx* ctx, const float* d_costs);
 mppi_status mppi_update(mppi_ctx* ctx);
 
 /* (a7) num_iters >= 1 full iterations, warm-started (u <- U between them).
- * The launch sequence for a given num_iters is captured into a hipGraph on
+ * For num_iters >= 2 the launch sequence is captured into a hipGraph on
  * first use and replayed afterwards (the context's stream must not be under
- * capture by the caller at that first call).
+ * capture by the caller at that first call); a single iteration (one to four
+ * kernel launches) is launched directly, which reaches the GPU sooner.
  * Results are those of num_iters x (sample, rollout, update); the noise
  * visible afterwards (MPPI_DEBUG_NOISE, mppi_backward) is the last
  * iteration's.  A single context whose noise buffer is at most 64 MiB keeps a

@@ -1794,9 +1794,11 @@ mppi_status mppi_iterate(mppi_ctx* c, int32_t num_iters) {
     return MPPI_OK;
   };
   // the launch sequence of num_iters iterations, captured once and replayed
-  // (the null stream cannot be captured: launch directly there)
+  // as a graph; one iteration (one to four launches) is launched directly,
+  // which reaches the GPU sooner than a graph launch, and the null stream
+  // cannot be captured
   if (single) c->inst[0].cur = start;
-  if (c->stream == nullptr) {
+  if (c->stream == nullptr || num_iters == 1) {
     for (int i = 0; i < num_iters; ++i) {
       hipError_t e = phase_iteration(c, i, ahead);
       if (e != hipSuccess) {
