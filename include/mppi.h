@@ -363,7 +363,7 @@ typedef struct mppi_tuning {
                                MPPI_ROLLOUT_SCAN; in the split form
                                lanes_per_sample (1, or 4 for the bicycle with RK4)
                                and rollout_block shape the dynamics kernel, in the
-                               scan form lanes_per_sample is 16 */
+                               scan form lanes_per_sample is 16 or 32 */
   int32_t cost_waves;       /* split form: waves that share the steps of 64 samples in
                                the cost kernel, a power of two from 1 to 128 (up to
                                16 in one workgroup; beyond, chunks of 16 waves whose
@@ -372,6 +372,13 @@ typedef struct mppi_tuning {
                                as listed above) */
   int32_t batch_form;       /* batch contexts: MPPI_BATCH_PHASES or
                                MPPI_BATCH_ONE_LAUNCH (single contexts: PHASES) */
+  int32_t adjoint_tiles;    /* gradient mode: mppi_backward sweeps the checkpoint
+                               segments in parallel (the costate chained through each
+                               segment's linear map) when the samples of nonzero
+                               weight fill at most this many 16-sample tiles, else
+                               one sweep per tile over the whole horizon; 0 to 64
+                               (0: always the per-tile sweep; default 16); the
+                               BF16 mode always takes the per-tile sweep */
 } mppi_tuning;
 
 /* The context's current launch shapes. */
@@ -477,8 +484,14 @@ mppi_status mppi_set_theta(mppi_ctx* ctx, const float* host_theta);
  * out) and through every rollout: the costate is swept backwards over the
  * discrete step (the four RK4 stages and the MLP residual) from state
  * checkpoints.  Samples of weight exactly zero contribute nothing and are
- * skipped.  Binary32 throughout except the normaliser eta (binary64).
- * Enqueued on the context's stream; the result is bitwise reproducible.
+ * skipped.  With few samples of nonzero weight (tuning adjoint_tiles) the
+ * checkpoint segments are swept in parallel: each segment's costate map
+ * (the product of its step Jacobians, formed in forward mode, and its running
+ * costs' share) chains the costate across segments, so the latency is that
+ * of one segment instead of the whole horizon; the result agrees with the
+ * per-tile sweep up to rounding.  Binary32 throughout except the normaliser
+ * eta (binary64).  Enqueued on the context's stream; the result is bitwise
+ * reproducible for a given tuning.
  * Errors: EINVAL (NULL), ESTATE (no MPPI_F_REQUIRES_GRAD, or no update since
  * the last mppi_sample / mppi_rollout / mppi_set_costs), EDEVICE. */
 mppi_status mppi_backward(mppi_ctx* ctx, const float* d_dL_dU, float* d_grad);

@@ -69,7 +69,8 @@ class Tuning(C.Structure):
     _fields_ = [("lanes_per_sample", C.c_int32), ("rollout_block", C.c_int32),
                 ("batch_tile", C.c_int32), ("noise_calls", C.c_int32),
                 ("rollout_form", C.c_int32), ("cost_waves", C.c_int32),
-                ("update_form", C.c_int32), ("batch_form", C.c_int32)]
+                ("update_form", C.c_int32), ("batch_form", C.c_int32),
+                ("adjoint_tiles", C.c_int32)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}

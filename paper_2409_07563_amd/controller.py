@@ -266,8 +266,8 @@ class Controller:
 
     def set_tuning(self, **shape) -> None:
         """Change launch shapes (lanes_per_sample, rollout_block, batch_tile,
-        noise_calls, rollout_form, cost_waves, update_form); the others keep
-        their values."""
+        noise_calls, rollout_form, cost_waves, update_form, batch_form,
+        adjoint_tiles); the others keep their values."""
         t = _abi.Tuning()
         check(lib().mppi_get_tuning(self.ctx, C.byref(t)))
         for k, v in shape.items():

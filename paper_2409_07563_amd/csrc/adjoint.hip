@@ -32,6 +32,8 @@
 //   reduce:   the partial gradients of the tiles, summed in tile order.
 // Every sum has a fixed order, so the gradient is bitwise reproducible.
 // Samples of zero weight contribute exactly zero and are skipped.
+#include <algorithm>
+
 #include "dynamics.h"
 #include "mlp.h"
 
@@ -257,6 +259,231 @@ __device__ __forceinline__ void rk4_vjp(const DevParams& p, const float* xt, con
   for (int i = 0; i < N; ++i) mu0[i] += cx[i];
 }
 
+// d = (df/dx) xd: the bicycle derivative's tangent along xd at x (control
+// held), the forward-mode counterpart of bicycle_vjp.
+template <bool FAST>
+__device__ __forceinline__ void bicycle_jvp(const float* x, const float* xd, float inv_l,
+                                            float* d) {
+  float sn, cs, sd, cd;
+  if constexpr (FAST) {
+    sn = __sinf(x[2]);
+    cs = __cosf(x[2]);
+    sd = __sinf(x[4]);
+    cd = __cosf(x[4]);
+  } else {
+    sincosf(x[2], &sn, &cs);
+    sincosf(x[4], &sd, &cd);
+  }
+  const float rc = FAST ? __builtin_amdgcn_rcpf(cd) : 1.0f / cd;
+  const float tn = FAST ? sd * rc : tanf(x[4]);
+  const float s = x[3];
+  d[0] = cs * xd[3] - s * sn * xd[2];
+  d[1] = sn * xd[3] + s * cs * xd[2];
+  d[2] = (tn * xd[3] + s * (1.0f + tn * tn) * xd[4]) * inv_l;
+  d[3] = 0.0f;
+  d[4] = 0.0f;
+}
+
+// xn = (dF/dx) xd for the RK4 bicycle step from x (control v held): the
+// stages' tangents in the order of the stages.
+template <bool FAST>
+__device__ __forceinline__ void rk4_jvp(const DevParams& p, const float* xt, const float* v,
+                                        const float* xd, float* xn) {
+  using Model = Bicycle<FAST>;
+  constexpr int N = 5;
+  float k[N], xs[N], kd[N], xsd[N], acc[N];
+  bicycle_jvp<FAST>(xt, xd, p.inv_wheelbase, kd);  // k1' at x
+  Model::deriv(xt, v, k, p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    acc[i] = kd[i];
+    xs[i] = xt[i] + p.half_dt * k[i];
+    xsd[i] = xd[i] + p.half_dt * kd[i];
+  }
+  bicycle_jvp<FAST>(xs, xsd, p.inv_wheelbase, kd);  // k2'
+  Model::deriv(xs, v, k, p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    acc[i] += 2.0f * kd[i];
+    xs[i] = xt[i] + p.half_dt * k[i];
+    xsd[i] = xd[i] + p.half_dt * kd[i];
+  }
+  bicycle_jvp<FAST>(xs, xsd, p.inv_wheelbase, kd);  // k3'
+  Model::deriv(xs, v, k, p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    acc[i] += 2.0f * kd[i];
+    xs[i] = xt[i] + p.dt * k[i];
+    xsd[i] = xd[i] + p.dt * kd[i];
+  }
+  bicycle_jvp<FAST>(xs, xsd, p.inv_wheelbase, kd);  // k4'
+#pragma unroll
+  for (int i = 0; i < N; ++i) xn[i] = xd[i] + p.sixth_dt * (acc[i] + kd[i]);
+}
+
+// Segment-parallel reverse pass.  The costate carried out of a checkpoint
+// segment s (steps t0 .. t1 - 1) is affine in the one carried in at its end:
+//   mu_out = P_s^T mu_in + q_s,  P_s = dx_{t1} / dx_{t0},
+//   q_s = sum_{t = t0+1 .. t1} (dx_t / dx_{t0})^T c_t,
+// c_t the running cost's gradient at x_t.  With few listed samples the
+// sequential sweep is latency-bound (one tile walks all T steps twice), so
+// for at most tp_tiles tiles:
+//   tp kernel:    per (tile, segment, column i) one wave rebuilds the segment
+//                 from its checkpoint and carries the tangent of x_{t0} + h e_i
+//                 (forward mode through the RK4 stages and the MLP), giving
+//                 column i of P_s and component i of q_s; column 0 of the last
+//                 segment also keeps x_T;
+//   sweep:        per (tile, segment) the usual rebuild and reverse pass over
+//                 that segment alone, from the costate the chain of the later
+//                 segments' maps gives (every workgroup forms the chain
+//                 itself, from x_T's terminal gradient, in the same order);
+//                 its partial gradient goes to its own row;
+//   reduce:       sums tiles x segments rows.
+// The mode is chosen on the device from the listed count, so no host
+// synchronisation is needed.  Record per (tile, segment, sample): for each
+// column i, P_s[0..4][i] then q_s[i] (6 floats), then x_T (5): 35 floats, padded
+// to 36.
+constexpr int kTpMaxTiles = kAdjointTilesMax;
+constexpr int kTpRec = 36;
+constexpr int kTpXT = 30;  // offset of x_T in a record
+static_assert(5 * 6 + 5 <= kTpRec, "record size");
+
+struct SegSel {
+  int tile, lo, hi;
+  bool par;
+};
+
+__device__ __forceinline__ SegSel seg_select(int nseg, int tp_tiles, int count) {
+  SegSel s;
+  s.par = tp_tiles > 0 && count <= tp_tiles * kTileS;
+  if (s.par) {
+    s.tile = blockIdx.x / nseg;
+    s.lo = s.hi = blockIdx.x % nseg;
+  } else {
+    s.tile = blockIdx.x;
+    s.lo = 0;
+    s.hi = nseg - 1;
+  }
+  return s;
+}
+
+// The costate carried into segment seg (< nseg - 1) for the lane's sample n of
+// tile `tile`: the terminal gradient at x_T, then the maps of segments
+// nseg - 1 .. seg + 1 in that order.
+__device__ __forceinline__ void tp_chain(const DevParams& p, const float* __restrict__ tp,
+                                         int tile, int nseg, int seg, int n, int T, float a,
+                                         float* mu) {
+  constexpr int N = 5;
+  const float* last = tp + (static_cast<int64_t>(tile * nseg + nseg - 1) * kTileS + n) * kTpRec;
+  const float* r = p.ref + static_cast<int64_t>(T) * N;
+#pragma unroll
+  for (int i = 0; i < N; ++i) mu[i] = a * 2.0f * p.w[16] * p.w[i] * (last[kTpXT + i] - r[i]);
+  for (int s = nseg - 1; s > seg; --s) {
+    const float* rec = tp + (static_cast<int64_t>(tile * nseg + s) * kTileS + n) * kTpRec;
+    float m[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      float acc = rec[i * 6 + 5];
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fmaf(rec[i * 6 + j], mu[j], acc);
+      m[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) mu[i] = m[i];
+  }
+}
+
+// Row `row` of the partial gradients holds dL/du only for the steps of its
+// segment: zero the other steps' columns (segment-parallel mode).
+__device__ __forceinline__ void tp_zero_du(float* __restrict__ row, int du_off, int T, int t0,
+                                           int len, int tid, int nthreads) {
+  constexpr int M = 2;
+  for (int i = tid; i < T * M; i += nthreads) {
+    const int t = i / M;
+    if (t < t0 || t >= t0 + len) row[du_off + i] = 0.0f;
+  }
+}
+
+template <int MT, bool FAST>
+__global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
+    DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
+    const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
+    const BwdMeta* __restrict__ meta, int tp_tiles, float* __restrict__ tp) {
+  using Model = Bicycle<FAST>;
+  using f4 = mlp::f4;
+  constexpr int N = 5, M = 2;
+  const int count = meta->count;
+  if (count > tp_tiles * kTileS) return;  // the sequential sweep runs instead
+  const int nseg = (T + c - 1) / c;
+  const int col = blockIdx.x % N, ts = blockIdx.x / N;
+  const int seg = ts % nseg, tile = ts / nseg;
+  const int base = tile * kTileS;
+  if (base >= count) return;  // wave-uniform
+  extern __shared__ float4 lds4[];
+  const float* lds = reinterpret_cast<const float*>(lds4);
+  const int lane = threadIdx.x, n = lane % kTileS, g = lane / kTileS;
+  if constexpr (MT > 0) {
+    const float4* src = reinterpret_cast<const float4*>(p.mlp);
+    for (int i = lane; i < mlp::Pack<MT>::kFwdRows * kWave / 4; i += kWave) lds4[i] = src[i];
+    __syncthreads();
+  }
+  const mlp::PackView<MT ? MT : 1> WF{lds + lane};
+  const int idx = base + n;
+  const bool valid = idx < count;
+  const BwdItem item = list[valid ? idx : base];
+  const float a = valid ? item.a : 0.0f;
+  const float* e = eps + item.k;
+  const int t0 = seg * c, len = min(c, T - t0);
+  float x[N], comp[N], xd[N];
+  const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + item.k;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    x[i] = ck[i * ldk];
+    comp[i] = 0.0f;
+    xd[i] = i == col ? 1.0f : 0.0f;
+  }
+  comp[0] = ck[5 * ldk];
+  comp[1] = ck[6 * ldk];
+  float q = 0.0f;
+  for (int j = 0; j < len; ++j) {
+    const int t = t0 + j;
+    float v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = u[t * M + k] + e[static_cast<int64_t>(t * M + k) * ldk];
+    float xn[N];
+    rk4_jvp<FAST>(p, x, v, xd, xn);
+    if constexpr (MT > 0) {
+      f4 h1[MT], h2[MT], d1[MT], d2[MT];
+      mlp::hidden_d<MT>(WF, x, v, g, h1, h2, d1, d2);
+      float res[N], gd[N];
+      mlp::broadcast5(mlp::output<MT>(WF, h2), n, res);
+      mlp::jvp<MT>(WF, xd, g, n, d1, d2, gd);
+#pragma unroll
+      for (int i = 0; i < N; ++i) xn[i] += p.dt * gd[i];
+      step<Model, kRK4>(x, v, comp, p, res);
+    } else {
+      step<Model, kRK4>(x, v, comp, p);
+    }
+    // the running cost's gradient at x_{t+1} along the tangent
+    const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      xd[i] = xn[i];
+      q = fmaf(a * 2.0f * p.w[i] * (x[i] - r[i]), xd[i], q);
+    }
+  }
+  if (g == 0) {
+    float* rec = tp + (static_cast<int64_t>(tile * nseg + seg) * kTileS + n) * kTpRec;
+#pragma unroll
+    for (int i = 0; i < N; ++i) rec[col * 6 + i] = xd[i];
+    rec[col * 6 + 5] = q;
+    if (seg == nseg - 1 && col == 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) rec[kTpXT + i] = x[i];
+    }
+  }
+}
+
 template <int MT, bool BF = false>
 struct SweepLds {
   static constexpr int P = 64 * MT + 16;  // transposition row stride (16 mod 32: no bank conflicts)
@@ -311,12 +538,14 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
     const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp, int du_off,
-    mlp::f4* __restrict__ pre) {
+    mlp::f4* __restrict__ pre, const float* __restrict__ tp, int tp_tiles) {
   using Model = Bicycle<FAST>;
   using L = SweepLds<MT, BF>;
   using f4 = mlp::f4;
   constexpr int N = 5, M = 2, H = 16 * MT;
-  const int base = blockIdx.x * kTileS;
+  const int nseg = (T + c - 1) / c;
+  const SegSel sel = seg_select(nseg, tp_tiles, meta->count);
+  const int base = sel.tile * kTileS;
   if (base >= meta->count) return;  // wave-uniform
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
@@ -364,8 +593,13 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   for (int i = 0; i < N; ++i) { db3[i] = 0.0f; gQ[i] = 0.0f; mu[i] = 0.0f; }
   const float ic[2] = {p.is_coef[0], p.is_coef[1]};
 
-  const int nseg = (T + c - 1) / c;
-  for (int seg = nseg - 1; seg >= 0; --seg) {
+  if (sel.par) {
+    if (sel.hi < nseg - 1) tp_chain(p, tp, sel.tile, nseg, sel.hi, n, T, a, mu);
+    if (du_off >= 0)
+      tp_zero_du(partial + static_cast<int64_t>(blockIdx.x) * ngp, du_off, T, sel.lo * c,
+                 min(c, T - sel.lo * c), threadIdx.x, blockDim.x);
+  }
+  for (int seg = sel.hi; seg >= sel.lo; --seg) {
     const int t0 = seg * c, len = min(c, T - t0);
     // rebuild x_{t0} .. x_{t0+len} from the checkpoint
     float x[N], comp[N];
@@ -597,14 +831,16 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
     const BwdMeta* __restrict__ meta, float* __restrict__ partial, int64_t ngp, int du_off,
-    mlp::f4* __restrict__ pre) {
+    mlp::f4* __restrict__ pre, const float* __restrict__ tp, int tp_tiles) {
   static_assert(MT % SW == 0, "tiles per wave");
   constexpr int TW = MT / SW;
   using Model = Bicycle<FAST>;
   using f4 = mlp::f4;
   using PK = mlp::Pack<MT>;
   constexpr int N = 5, M = 2, H = 16 * MT, PS = SplitLds<MT, SW>::P;
-  const int base = blockIdx.x * kTileS;
+  const int nseg = (T + c - 1) / c;
+  const SegSel sel = seg_select(nseg, tp_tiles, meta->count);
+  const int base = sel.tile * kTileS;
   if (base >= meta->count) return;  // workgroup-uniform
   extern __shared__ float4 lds4[];
   float* tb = reinterpret_cast<float*>(lds4);                             // [16][PS]
@@ -689,8 +925,13 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
   const float ic[2] = {p.is_coef[0], p.is_coef[1]};
   int par = 0;
 
-  const int nseg = (T + c - 1) / c;
-  for (int seg = nseg - 1; seg >= 0; --seg) {
+  if (sel.par) {
+    if (sel.hi < nseg - 1) tp_chain(p, tp, sel.tile, nseg, sel.hi, n, T, a, mu);
+    if (du_off >= 0)
+      tp_zero_du(partial + static_cast<int64_t>(blockIdx.x) * ngp, du_off, T, sel.lo * c,
+                 min(c, T - sel.lo * c), threadIdx.x, blockDim.x);
+  }
+  for (int seg = sel.hi; seg >= sel.lo; --seg) {
     const int t0 = seg * c, len = min(c, T - t0);
     float x[N], comp[N];
     const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + k;
@@ -991,16 +1232,19 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
 // per workgroup, the tiles split over 16 lanes per column (tile = p mod 16),
 // the 16 partial sums combined in a fixed order.  Columns j < ngrad are the
 // gradient (grad[j] = sum, or += with accumulate); columns ngrad.. (ncols >
-// ngrad) are dL/du, added to G[j - ngrad].
+// ngrad) are dL/du, added to G[j - ngrad].  In the segment-parallel mode the
+// rows are the (tile, segment) pairs.
 constexpr int kReduceCols = 64, kReduceParts = 16;
 __global__ __launch_bounds__(kReduceCols * kReduceParts) void adjoint_reduce_kernel(
     const float* __restrict__ partial, int64_t ngp, int ngrad, int ncols,
     const BwdMeta* __restrict__ meta, float* __restrict__ grad, int accumulate,
-    float* __restrict__ G) {
+    float* __restrict__ G, int tp_tiles, int nseg) {
   __shared__ float red[kReduceParts][kReduceCols];
   const int c = threadIdx.x % kReduceCols, part = threadIdx.x / kReduceCols;
   const int j = blockIdx.x * kReduceCols + c;
-  const int tiles = (meta->count + kTileS - 1) / kTileS;
+  const int count = meta->count;
+  const int tiles = (count + kTileS - 1) / kTileS *
+                    (tp_tiles > 0 && count <= tp_tiles * kTileS ? nseg : 1);
   float s = 0.0f;
   if (j < ncols) {
     int w = part;
@@ -1044,10 +1288,15 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_eve
   s.offs = take(sizeof(int) * nb);
   s.meta = take(sizeof(BwdMeta));
   s.list = take(sizeof(BwdItem) * K);
-  s.partial = take(sizeof(float) * static_cast<size_t>(tiles) * s.ngp);
-  // pre-activations of one segment per tile: c steps x 2 layers x H/16 x 64 lanes x 4
-  s.pre = take(sizeof(float) * 4 * static_cast<size_t>(tiles) * ckpt_every * 2 *
-               (hidden > 0 ? hidden / 16 : 0) * kWave);
+  // rows: one per tile, or per (tile, segment) in the segment-parallel mode
+  const int nseg = (TM / 2 + ckpt_every - 1) / ckpt_every;
+  const int tp_max = tiles < kTpMaxTiles ? tiles : kTpMaxTiles;
+  const size_t rows = std::max(static_cast<size_t>(tiles), static_cast<size_t>(tp_max) * nseg);
+  s.partial = take(sizeof(float) * rows * s.ngp);
+  // pre-activations of one segment per row: c steps x 2 layers x H/16 x 64 lanes x 4
+  s.pre = take(sizeof(float) * 4 * rows * ckpt_every * 2 * (hidden > 0 ? hidden / 16 : 0) *
+               kWave);
+  s.tp = take(sizeof(float) * static_cast<size_t>(tp_max) * nseg * kTileS * kTpRec);
   s.total = off;
   return s;
 }
@@ -1064,7 +1313,14 @@ size_t adjoint_lds_bytes(int hidden, int ckpt_every, bool bf) {
 
 namespace {
 using SweepFn = void (*)(DevParams, const float*, const float*, int64_t, int, const float*, int,
-                         const BwdItem*, const BwdMeta*, float*, int64_t, int, mlp::f4*);
+                         const BwdItem*, const BwdMeta*, float*, int64_t, int, mlp::f4*,
+                         const float*, int);
+using TpFn = void (*)(DevParams, const float*, const float*, int64_t, int, const float*, int,
+                      const BwdItem*, const BwdMeta*, int, float*);
+template <int MT>
+TpFn pick_tp(bool accurate) {
+  return accurate ? adjoint_tp_kernel<MT, false> : adjoint_tp_kernel<MT, true>;
+}
 template <int MT, bool BF = false>
 SweepFn pick_sweep(bool accurate) {
   return accurate ? adjoint_sweep_kernel<MT, false, BF> : adjoint_sweep_kernel<MT, true, BF>;
@@ -1084,9 +1340,23 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
                           const float* d_e, float lambda, float step, const float* d_ckpt,
                           int ckpt_every, char* d_scratch, const AdjointScratch& s, int ngrad,
                           float* d_grad, hipStream_t stream, int waves, bool accumulate,
-                          float* d_G_acc) {
+                          float* d_G_acc, int tp_tiles) {
   SweepFn fn = nullptr;
   const bool bf = hidden > 0 && p.mlp_bf != nullptr;  // BF16 products
+  const int tiles = (K + kTileS - 1) / kTileS;
+  const int nseg = (T + ckpt_every - 1) / ckpt_every;
+  // segment-parallel mode (binary32 products): up to tp tiles
+  const int tp = bf ? 0 : std::min(std::max(tp_tiles, 0), std::min(kTpMaxTiles, tiles));
+  TpFn tfn = nullptr;
+  size_t tlds = 0;
+  switch (hidden) {
+    case 0: tfn = pick_tp<0>(accurate_trig); break;
+    case 16: tfn = pick_tp<1>(accurate_trig); tlds = mlp::Pack<1>::kFwdRows; break;
+    case 32: tfn = pick_tp<2>(accurate_trig); tlds = mlp::Pack<2>::kFwdRows; break;
+    case 64: tfn = pick_tp<4>(accurate_trig); tlds = mlp::Pack<4>::kFwdRows; break;
+    default: break;
+  }
+  tlds *= sizeof(float) * kWave;
   size_t lds = adjoint_lds_bytes(hidden, ckpt_every, bf);
   if (waves > 1) {
     if (hidden == 64 && waves == 4) {
@@ -1133,15 +1403,21 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   hipLaunchKernelGGL(adjoint_compact_kernel, dim3(nb), dim3(kProjectSamples), 0, stream, d_e, gk,
                      K, static_cast<float>(static_cast<double>(step) / static_cast<double>(lambda)),
                      offs, meta, list);
-  const int tiles = (K + kTileS - 1) / kTileS;
   const int du_off = d_G_acc ? ngrad : -1;
   const int ncols = ngrad + (d_G_acc ? TM : 0);
   if (ncols > s.ngp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(tiles), dim3(kWave * waves), lds, stream, p, d_u, d_eps, ldk, T,
-                     d_ckpt, ckpt_every, list, meta, partial, s.ngp, du_off, pre);
+  float* tpbuf = reinterpret_cast<float*>(d_scratch + s.tp);
+  if (tp > 0) {
+    if (!tfn) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tfn, dim3(tp * nseg * 5), dim3(kWave), tlds, stream, p, d_u, d_eps, ldk,
+                       T, d_ckpt, ckpt_every, list, meta, tp, tpbuf);
+  }
+  const int rows = std::max(tiles, tp * nseg);
+  hipLaunchKernelGGL(fn, dim3(rows), dim3(kWave * waves), lds, stream, p, d_u, d_eps, ldk, T,
+                     d_ckpt, ckpt_every, list, meta, partial, s.ngp, du_off, pre, tpbuf, tp);
   hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((ncols + kReduceCols - 1) / kReduceCols),
                      dim3(kReduceCols * kReduceParts), 0, stream, partial, s.ngp, ngrad, ncols,
-                     meta, d_grad, accumulate ? 1 : 0, d_G_acc);
+                     meta, d_grad, accumulate ? 1 : 0, d_G_acc, tp, nseg);
   return hipGetLastError();
 }
 

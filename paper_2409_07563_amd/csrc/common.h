@@ -140,6 +140,10 @@ constexpr int kBatchMaxTile = 256, kBatchMinTile = 64;
 
 // Most tiles of one instance in the one-launch batch form (K <= 65536).
 constexpr int kOneLaunchMaxTiles = 256;
+
+// Segment-parallel reverse pass: the most 16-sample tiles of nonzero weight it
+// takes (its scratch is sized for that many), and the default bound.
+constexpr int kAdjointTilesMax = 64, kAdjointTilesDefault = 16;
 struct BatchPlan {
   const BatchInst* insts;
   const int2* sample_tiles;
@@ -272,7 +276,7 @@ hipError_t launch_rollout_tiles(uint32_t dynamics, uint32_t integrator, uint32_t
 
 // The adjoint (adjoint.hip).  Scratch: byte offsets inside one device region.
 struct AdjointScratch {
-  size_t gk, part, offs, meta, list, partial, pre, total;
+  size_t gk, part, offs, meta, list, partial, pre, tp, total;
   int64_t ngp;  // floats per partial-gradient row
 };
 int adjoint_grad_len(uint32_t dynamics, int hidden);
@@ -281,13 +285,16 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_eve
 size_t adjoint_lds_bytes(int hidden, int ckpt_every, bool bf16 = false);
 // accumulate: d_grad += the gradient (else d_grad = it); d_G_acc (optional):
 // d_G_acc += sum_k a_k dJ_k/du (may be d_G itself: the update happens after
-// every read of d_G, in stream order).
+// every read of d_G, in stream order).  tp_tiles: the segment-parallel
+// reverse pass when at most that many tiles hold listed samples (0: never;
+// binary32 products only; capped at 64 and at the context's tile count).
 hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, float step, const float* d_ckpt,
                           int ckpt_every, char* d_scratch, const AdjointScratch& s, int ngrad,
                           float* d_grad, hipStream_t stream, int waves = 1,
-                          bool accumulate = false, float* d_G_acc = nullptr);
+                          bool accumulate = false, float* d_G_acc = nullptr,
+                          int tp_tiles = 0);
 hipError_t launch_weights_only(const float* d_S, int K, float lambda, float* d_e,
                                DevState* d_scratch_state, hipStream_t stream);
 // The differentiation tape: start over (count = 0).

@@ -243,6 +243,45 @@ __device__ __forceinline__ void residual_keep(const WS& W, const float* x, const
   broadcast5(output<MT>(W, h2), n, res);
 }
 
+// Forward mode through g for the tile: the tangent
+//   g' = W3 ((W2 ((W1 z') * d1)) * d2)
+// of a tangent z' = (xd, 0) of the input (the state moves, the controls are
+// held), given the activation derivatives d1, d2 of the forward; gd receives
+// the five components of the lane's sample.  The products run in the
+// forward's order with zero start values in place of the biases.
+template <int MT, class WS>
+__device__ __forceinline__ void jvp(const WS& W, const float* xd, int g, int n,
+                                    const f4 (&d1)[MT], const f4 (&d2)[MT], float* gd) {
+  const f4 zero4{0.0f, 0.0f, 0.0f, 0.0f};
+  const float v0[2] = {0.0f, 0.0f};
+  const float z0 = input_operand(xd, v0, g, 0), z1 = input_operand(xd, v0, g, 1);
+  f4 h1[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+    h1[t] = mfma(W.w1(t, 1), z1, mfma(W.w1(t, 0), z0, zero4)) * d1[t];
+  f4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = zero4;
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int t = 0; t < MT; ++t) acc[t] = mfma(W.w2(t, tt, i), h1[tt][i], acc[t]);
+  f4 out[MT];
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt) {
+    const f4 h2 = acc[tt] * d2[tt];
+    out[tt] = zero4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[tt] = mfma(W.w3(tt, i), h2[i], out[tt]);
+  }
+  f4 r = out[0];
+#pragma unroll
+  for (int tt = 1; tt < MT; ++tt) r += out[tt];
+  broadcast5(r, n, gd);
+}
+
 // Reverse mode through g for the tile: given c = dL/dg (five components per
 // lane, for the lane's sample) and the activation derivatives of the forward
 // (d1, d2 = tanh' of the two hidden layers),

@@ -1050,6 +1050,7 @@ mppi_status create_ctx(const mppi_config* cfgs, const mppi_params* params, int n
   c->tune.rollout_form = MPPI_ROLLOUT_FUSED;
   c->tune.cost_waves = 8;
   c->tune.batch_form = MPPI_BATCH_PHASES;
+  c->tune.adjoint_tiles = kAdjointTilesDefault;
   c->tune.update_form = one_pass_for(c)  ? MPPI_UPDATE_ONE_PASS
                         : chunked_for(c) ? MPPI_UPDATE_CHUNKED
                                          : MPPI_UPDATE_TWO_PASS;
@@ -1378,6 +1379,8 @@ mppi_status mppi_set_tuning(mppi_ctx* c, const mppi_tuning* t) {
                 "or MPPI_UPDATE_CHUNKED");
   if (t->batch_form != MPPI_BATCH_PHASES && t->batch_form != MPPI_BATCH_ONE_LAUNCH)
     return fail(MPPI_EINVAL, "batch_form must be MPPI_BATCH_PHASES or MPPI_BATCH_ONE_LAUNCH");
+  if (t->adjoint_tiles < 0 || t->adjoint_tiles > kAdjointTilesMax)
+    return fail(MPPI_EINVAL, "adjoint_tiles must be 0 .. %d", kAdjointTilesMax);
   if (t->batch_form == MPPI_BATCH_ONE_LAUNCH && !c->batch) {
     if (!c->C.one_single)
       return fail(MPPI_EUNSUPPORTED, "the one-launch form of a single context exists for the "
@@ -1930,7 +1933,8 @@ mppi_status mppi_backward(mppi_ctx* c, const float* d_dL_dU, float* d_grad) {
                                 I.cfg.lambda, step_size(I.cfg), I.at<float>(I.L.ckpt),
                                 I.ckpt_every,
                                 I.at<char>(I.L.adj), I.L.adj_layout, I.n_theta, d_grad, c->stream,
-                                c->tune.rollout_block / kWave);
+                                c->tune.rollout_block / kWave, false, nullptr,
+                                c->tune.adjoint_tiles);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return MPPI_OK;
 }
@@ -1982,7 +1986,8 @@ mppi_status mppi_backward_iters(mppi_ctx* c, const float* d_dL_dU, float* d_grad
     if (e == hipSuccess)
       e = launch_adjoint(I.dp, accurate, I.hidden, G, u_i, I.eps(), I.L.ldk, I.K, I.T, I.e(),
                          I.cfg.lambda, step_size(I.cfg), ckpt, I.ckpt_every, I.at<char>(I.L.adj),
-                         I.L.adj_layout, I.n_theta, d_grad, c->stream, waves, i != n - 1, G);
+                         I.L.adj_layout, I.n_theta, d_grad, c->stream, waves, i != n - 1, G,
+                         c->tune.adjoint_tiles);
     if (e != hipSuccess) return hip_fail(e, "reverse pass launch");
   }
   if (d_dL_du0)

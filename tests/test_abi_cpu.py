@@ -59,7 +59,7 @@ def test_struct_sizes_match_the_header(abi):
     # sizes of the C structs as laid out by the host compiler
     assert C.sizeof(abi.Config) == 96
     assert C.sizeof(abi.Params) == 288
-    assert C.sizeof(abi.Tuning) == 32
+    assert C.sizeof(abi.Tuning) == 36
 
 
 def _bytes(abi, wl, grad=False, ckpt=0, **cfg_override):
