@@ -458,6 +458,14 @@ def run_grad(args, wl, full: bool = True) -> dict:
         res = dict(t_fwd=t_fwd, t_noise=t_noise, t_roll=t_roll, t_upd=t_upd, t_fb=t_fb,
                    t_fg=t_fg, swept=swept, tuning=tuning)
         if three:
+            # the same backward with the per-tile sweep over the whole horizon
+            # (the segment-parallel mode switched off), for comparison
+            grad.set_tuning(adjoint_tiles=0)
+            grad._enter()
+            res["t_fb_tile"] = timed(grad.stream, fwd_bwd, args.steps, args.warmup)
+            grad.set_tuning(adjoint_tiles=tuning["adjoint_tiles"])
+            grad._enter()
+        if three:
             # three warm-started iterations and the reverse pass through all
             # of them (rebuilds each iteration from the tape, then its adjoint)
             du0 = torch.empty(w.T * w.m, device=dev)
@@ -503,6 +511,9 @@ def run_grad(args, wl, full: bool = True) -> dict:
                                           "hbm_GBps": (eps_bytes + 8 * wl.K) / r["t_upd"] / 1e9}},
            "tuning": r["tuning"]}
     if full:
+        out["grad"]["bwd_forms_ms"] = {"segment_parallel": (r["t_fb"] - r["t_fg"]) * 1e3,
+                                       "per_tile": (r["t_fb_tile"] - r["t_fg"]) * 1e3}
+        out["grad"]["fwd_bwd_over_fwd_per_tile"] = r["t_fb_tile"] / r["t_fwd"]
         out["grad"]["three_iterations"] = {"fwd_ms": r["t_f3"] * 1e3,
                                            "fwd_plus_bwd_ms": r["t_f3b"] * 1e3,
                                            "fwd_bwd_over_fwd": r["t_f3b"] / r["t_f3"]}

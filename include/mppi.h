@@ -376,9 +376,10 @@ typedef struct mppi_tuning {
                                segments in parallel (the costate chained through each
                                segment's linear map) when the samples of nonzero
                                weight fill at most this many 16-sample tiles, else
-                               one sweep per tile over the whole horizon; 0 to 64
-                               (0: always the per-tile sweep; default 16); the
-                               BF16 mode always takes the per-tile sweep */
+                               one sweep per tile over the whole horizon; 0 to 128
+                               (0: always the per-tile sweep; default 64; also at
+                               most 1280 / checkpoint segments); the BF16 mode
+                               always takes the per-tile sweep */
 } mppi_tuning;
 
 /* The context's current launch shapes. */

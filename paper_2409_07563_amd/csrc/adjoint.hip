@@ -344,6 +344,15 @@ __device__ __forceinline__ void rk4_jvp(const DevParams& p, const float* xt, con
 // column i, P_s[0..4][i] then q_s[i] (6 floats), then x_T (5): 35 floats, padded
 // to 36.
 constexpr int kTpMaxTiles = kAdjointTilesMax;
+// at most this many (tile, segment) rows: the partial gradients and the
+// pre-activation scratch grow with them
+constexpr int kTpRowBudget = 1280;
+
+// The most tiles the segment-parallel mode takes for a context of `tiles`
+// tiles and nseg segments (the scratch is sized for it).
+inline int tp_cap(int tiles, int nseg) {
+  return std::min(std::min(tiles, kTpMaxTiles), kTpRowBudget / nseg);
+}
 constexpr int kTpRec = 36;
 constexpr int kTpXT = 30;  // offset of x_T in a record
 static_assert(5 * 6 + 5 <= kTpRec, "record size");
@@ -1290,7 +1299,7 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_eve
   s.list = take(sizeof(BwdItem) * K);
   // rows: one per tile, or per (tile, segment) in the segment-parallel mode
   const int nseg = (TM / 2 + ckpt_every - 1) / ckpt_every;
-  const int tp_max = tiles < kTpMaxTiles ? tiles : kTpMaxTiles;
+  const int tp_max = tp_cap(tiles, nseg);
   const size_t rows = std::max(static_cast<size_t>(tiles), static_cast<size_t>(tp_max) * nseg);
   s.partial = take(sizeof(float) * rows * s.ngp);
   // pre-activations of one segment per row: c steps x 2 layers x H/16 x 64 lanes x 4
@@ -1346,7 +1355,7 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   const int tiles = (K + kTileS - 1) / kTileS;
   const int nseg = (T + ckpt_every - 1) / ckpt_every;
   // segment-parallel mode (binary32 products): up to tp tiles
-  const int tp = bf ? 0 : std::min(std::max(tp_tiles, 0), std::min(kTpMaxTiles, tiles));
+  const int tp = bf ? 0 : std::min(std::max(tp_tiles, 0), tp_cap(tiles, nseg));
   TpFn tfn = nullptr;
   size_t tlds = 0;
   switch (hidden) {

@@ -10,7 +10,8 @@ chained costate rounds differently, so both are held to the oracle at the
 gradient bound of tests/test_gpu_grad.py (1e-4 of sum_k |a_k dJ_k/dtheta|
 per parameter), and to each other at the same bound.  Cases: every hidden
 width (and the plain bicycle), one-wave and split sweeps, ragged last
-segments, one-step segments, a single segment, many tiles (up to 64), the
+segments, one-step segments, a single segment, many tiles (up to 128, and
+beyond the row budget of 1280 / segments, where the per-tile sweep runs), the
 accurate trigonometry, the reverse pass through several iterations (dL/du
 columns written per segment), the mode's threshold (above it the per-tile
 sweep runs, bitwise), and the BF16 mode (always per tile)."""
@@ -63,7 +64,7 @@ def _close(g, ref, gabs, name):
                            f"worst ratio {(err / tol).max():.3g}")
 
 
-def _both(mppi, wl, ce, block=None, accurate=False, tiles=64):
+def _both(mppi, wl, ce, block=None, accurate=False, tiles=128):
     """One iteration in gradient mode; the gradient by the segment-parallel
     pass (adjoint_tiles = tiles) and by the per-tile sweep (0) on the same
     buffers."""
@@ -91,7 +92,8 @@ def _both(mppi, wl, ce, block=None, accurate=False, tiles=64):
     (64, 1024, 40, 10, 50.0, 256), (64, 1024, 40, 10, 0.5, 64), (64, 1000, 40, 10, 50.0, 128),
     (16, 700, 33, 10, 50.0, None), (32, 256, 20, 7, 5.0, 128), (32, 256, 20, 7, 5.0, 64),
     (64, 100, 23, 1, 50.0, 256), (64, 333, 50, 64, 0.5, 256), (64, 333, 50, 13, 50.0, 64),
-    (0, 1000, 50, 10, 0.5, None), (0, 1000, 50, 10, 50.0, None), (0, 37, 9, 4, 50.0, None)])
+    (0, 1000, 50, 10, 0.5, None), (0, 1000, 50, 10, 50.0, None), (0, 37, 9, 4, 50.0, None),
+    (64, 2048, 20, 10, 50.0, 256), (16, 1024, 40, 1, 50.0, None)])
 def test_segment_parallel_vs_oracle_and_sweep(mppi, oracle_lib, H, K, T, ce, lam, block):
     wl = _wl(H, K, T, lam)
     g_par, g_seq, G, S, eps = _both(mppi, wl, ce, block)
@@ -146,7 +148,7 @@ def test_segment_parallel_through_iterations(mppi, oracle_lib):
     ctl.iterate(3)
     U = _np(ctl.controls()).astype(np.float64)
     G = 2.0 * (U - W.c5_uref(T=30))
-    ctl.set_tuning(adjoint_tiles=64)
+    ctl.set_tuning(adjoint_tiles=128)
     g, du0 = (_np(x).astype(np.float64) for x in ctl.backward_iters(G.astype(np.float32)))
     ctl.set_tuning(adjoint_tiles=0)
     gs, du0s = (_np(x).astype(np.float64) for x in ctl.backward_iters(G.astype(np.float32)))
@@ -162,11 +164,11 @@ def test_segment_parallel_through_iterations(mppi, oracle_lib):
 def test_adjoint_tiles_bounds(mppi):
     from paper_2409_07563_amd import MPPIError
     c = mppi.Controller(_wl(16, 64, 10, 50.0), requires_grad=True)
-    assert c.tuning()["adjoint_tiles"] == 16
-    for bad in (-1, 65):
+    assert c.tuning()["adjoint_tiles"] == 64
+    for bad in (-1, 129):
         with pytest.raises(MPPIError) as e:
             c.set_tuning(adjoint_tiles=bad)
         assert e.value.status == -1  # MPPI_EINVAL
-    c.set_tuning(adjoint_tiles=64)
+    c.set_tuning(adjoint_tiles=128)
     c.set_tuning(adjoint_tiles=0)
     c.close()
