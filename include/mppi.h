@@ -378,8 +378,7 @@ typedef struct mppi_tuning {
                                weight fill at most this many 16-sample tiles, else
                                one sweep per tile over the whole horizon; 0 to 128
                                (0: always the per-tile sweep; default 64; also at
-                               most 1280 / checkpoint segments); the BF16 mode
-                               always takes the per-tile sweep */
+                               most 1280 / checkpoint segments) */
 } mppi_tuning;
 
 /* The context's current launch shapes. */

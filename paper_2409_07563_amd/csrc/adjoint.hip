@@ -413,7 +413,10 @@ __device__ __forceinline__ void tp_zero_du(float* __restrict__ row, int du_off, 
   }
 }
 
-template <int MT, bool FAST>
+// BF: the rebuild on the bfloat16 products (as the sweep's), the tangents
+// through the rounded weights with the roundings of the layer inputs taken as
+// the identity.
+template <int MT, bool FAST, bool BF = false>
 __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
@@ -431,12 +434,19 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
   extern __shared__ float4 lds4[];
   const float* lds = reinterpret_cast<const float*>(lds4);
   const int lane = threadIdx.x, n = lane % kTileS, g = lane / kTileS;
+  constexpr int kFwd = MT ? mlp::Pack<MT>::kFwdRows * kWave : 0;  // floats
   if constexpr (MT > 0) {
     const float4* src = reinterpret_cast<const float4*>(p.mlp);
-    for (int i = lane; i < mlp::Pack<MT>::kFwdRows * kWave / 4; i += kWave) lds4[i] = src[i];
+    for (int i = lane; i < kFwd / 4; i += kWave) lds4[i] = src[i];
+    if constexpr (BF) {
+      const float4* src_h = reinterpret_cast<const float4*>(p.mlp_bf);
+      for (int i = lane; i < mlp::PackBf<MT>::kRows * kWave; i += kWave)
+        lds4[kFwd / 4 + i] = src_h[i];
+    }
     __syncthreads();
   }
   const mlp::PackView<MT ? MT : 1> WF{lds + lane};
+  const mlp::PackViewBf<MT ? MT : 1> WFB{reinterpret_cast<const uint4*>(lds + kFwd) + lane, WF};
   const int idx = base + n;
   const bool valid = idx < count;
   const BwdItem item = list[valid ? idx : base];
@@ -462,11 +472,23 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
     float xn[N];
     rk4_jvp<FAST>(p, x, v, xd, xn);
     if constexpr (MT > 0) {
-      f4 h1[MT], h2[MT], d1[MT], d2[MT];
-      mlp::hidden_d<MT>(WF, x, v, g, h1, h2, d1, d2);
+      f4 d1[MT], d2[MT];
       float res[N], gd[N];
-      mlp::broadcast5(mlp::output<MT>(WF, h2), n, res);
-      mlp::jvp<MT>(WF, xd, g, n, d1, d2, gd);
+      if constexpr (BF) {
+        f4 a1[MT], a2[MT], h;
+        mlp::residual_keep<MT>(WFB, x, v, g, n, res, a1, a2);
+#pragma unroll
+        for (int t2 = 0; t2 < MT; ++t2) {
+          mlp::tanh4_d(a1[t2], h, d1[t2]);
+          mlp::tanh4_d(a2[t2], h, d2[t2]);
+        }
+        mlp::jvp<MT>(mlp::RoundedView<MT>{WF}, xd, g, n, d1, d2, gd);
+      } else {
+        f4 h1[MT], h2[MT];
+        mlp::hidden_d<MT>(WF, x, v, g, h1, h2, d1, d2);
+        mlp::broadcast5(mlp::output<MT>(WF, h2), n, res);
+        mlp::jvp<MT>(WF, xd, g, n, d1, d2, gd);
+      }
 #pragma unroll
       for (int i = 0; i < N; ++i) xn[i] += p.dt * gd[i];
       step<Model, kRK4>(x, v, comp, p, res);
@@ -1326,9 +1348,9 @@ using SweepFn = void (*)(DevParams, const float*, const float*, int64_t, int, co
                          const float*, int);
 using TpFn = void (*)(DevParams, const float*, const float*, int64_t, int, const float*, int,
                       const BwdItem*, const BwdMeta*, int, float*);
-template <int MT>
+template <int MT, bool BF = false>
 TpFn pick_tp(bool accurate) {
-  return accurate ? adjoint_tp_kernel<MT, false> : adjoint_tp_kernel<MT, true>;
+  return accurate ? adjoint_tp_kernel<MT, false, BF> : adjoint_tp_kernel<MT, true, BF>;
 }
 template <int MT, bool BF = false>
 SweepFn pick_sweep(bool accurate) {
@@ -1354,18 +1376,33 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   const bool bf = hidden > 0 && p.mlp_bf != nullptr;  // BF16 products
   const int tiles = (K + kTileS - 1) / kTileS;
   const int nseg = (T + ckpt_every - 1) / ckpt_every;
-  // segment-parallel mode (binary32 products): up to tp tiles
-  const int tp = bf ? 0 : std::min(std::max(tp_tiles, 0), tp_cap(tiles, nseg));
+  // segment-parallel mode: up to tp tiles
+  const int tp = std::min(std::max(tp_tiles, 0), tp_cap(tiles, nseg));
   TpFn tfn = nullptr;
-  size_t tlds = 0;
+  size_t tlds = 0;  // the forward pack (binary32), then the bfloat16 pack
   switch (hidden) {
     case 0: tfn = pick_tp<0>(accurate_trig); break;
-    case 16: tfn = pick_tp<1>(accurate_trig); tlds = mlp::Pack<1>::kFwdRows; break;
-    case 32: tfn = pick_tp<2>(accurate_trig); tlds = mlp::Pack<2>::kFwdRows; break;
-    case 64: tfn = pick_tp<4>(accurate_trig); tlds = mlp::Pack<4>::kFwdRows; break;
+    case 16:
+      tfn = bf ? pick_tp<1, true>(accurate_trig) : pick_tp<1>(accurate_trig);
+      tlds = mlp::Pack<1>::kFwdRows + (bf ? 4 * mlp::PackBf<1>::kRows : 0);
+      break;
+    case 32:
+      tfn = bf ? pick_tp<2, true>(accurate_trig) : pick_tp<2>(accurate_trig);
+      tlds = mlp::Pack<2>::kFwdRows + (bf ? 4 * mlp::PackBf<2>::kRows : 0);
+      break;
+    case 64:
+      tfn = bf ? pick_tp<4, true>(accurate_trig) : pick_tp<4>(accurate_trig);
+      tlds = mlp::Pack<4>::kFwdRows + (bf ? 4 * mlp::PackBf<4>::kRows : 0);
+      break;
     default: break;
   }
   tlds *= sizeof(float) * kWave;
+  if (tp > 0 && tfn && tlds > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(tfn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(tlds));
+    if (e != hipSuccess) return e;
+  }
   size_t lds = adjoint_lds_bytes(hidden, ckpt_every, bf);
   if (waves > 1) {
     if (hidden == 64 && waves == 4) {

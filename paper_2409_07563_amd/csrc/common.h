@@ -288,8 +288,7 @@ size_t adjoint_lds_bytes(int hidden, int ckpt_every, bool bf16 = false);
 // d_G_acc += sum_k a_k dJ_k/du (may be d_G itself: the update happens after
 // every read of d_G, in stream order).  tp_tiles: the segment-parallel
 // reverse pass when at most that many tiles hold listed samples (0: never;
-// binary32 products only; capped at 128, at 1280 / segments and at the
-// context's tile count).
+// capped at 128, at 1280 / segments and at the context's tile count).
 hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, float step, const float* d_ckpt,

@@ -496,5 +496,18 @@ __device__ __forceinline__ void residual_keep(const PackViewBf<MT>& W, const flo
   broadcast5(output_bf<MT>(W, h2), n, res);
 }
 
+// The binary32 forward pack read with its weights rounded to bfloat16 at each
+// use: the BF16 mode's tangents (jvp) take the rounded weights and count the
+// roundings of the layer inputs as the identity, as its adjoint does.
+template <int MT>
+struct RoundedView {
+  PackView<MT> fv;
+  __device__ __forceinline__ float w1(int t, int j) const { return round_bf(fv.w1(t, j)); }
+  __device__ __forceinline__ float w2(int t, int tt, int i) const {
+    return round_bf(fv.w2(t, tt, i));
+  }
+  __device__ __forceinline__ float w3(int tt, int i) const { return round_bf(fv.w3(tt, i)); }
+};
+
 }  // namespace mlp
 }  // namespace mppi

@@ -14,7 +14,7 @@ segments, one-step segments, a single segment, many tiles (up to 128, and
 beyond the row budget of 1280 / segments, where the per-tile sweep runs), the
 accurate trigonometry, the reverse pass through several iterations (dL/du
 columns written per segment), the mode's threshold (above it the per-tile
-sweep runs, bitwise), and the BF16 mode (always per tile)."""
+sweep runs, bitwise), and the BF16 mode."""
 import sys
 
 import numpy as np
@@ -129,10 +129,22 @@ def test_split_sweep_bitwise_in_segment_mode(mppi):
         assert np.array_equal(grads[0], g)
 
 
-def test_bf16_mode_keeps_the_per_tile_sweep(mppi):
-    wl = _wl(64, 512, 25, 50.0).replace(mlp_bf16=1)
-    g_par, g_seq, *_ = _both(mppi, wl, 10)
-    assert np.array_equal(g_par, g_seq)
+@pytest.mark.parametrize("H,K,T,ce,lam", [(64, 512, 25, 10, 50.0), (64, 1024, 40, 10, 0.5),
+                                         (16, 300, 30, 7, 50.0), (32, 256, 20, 6, 5.0)])
+def test_bf16_segment_parallel_vs_oracle_and_sweep(mppi, oracle_lib, H, K, T, ce, lam):
+    """The BF16 mode: the rebuild on the bfloat16 products, the tangents
+    through the rounded weights (the roundings of the layer inputs taken as
+    the identity, as the oracle's bfloat16 option differentiates); split and
+    one-wave sweeps bitwise equal."""
+    wl = _wl(H, K, T, lam).replace(mlp_bf16=1)
+    runs = [_both(mppi, wl, ce, block) for block in ((64, 4 * H) if H >= 32 else (64,))]
+    g_par, g_seq, G, S, eps = runs[0]
+    ref = oracle_lib.backward(wl, G.astype(np.float64), eps=eps, S=S)
+    name = f"bf16 H={H} K={K} T={T} c={ce} lambda={lam}"
+    _close(g_par, ref["grad"], ref["grad_abs"], "segment-parallel " + name)
+    _close(g_par, g_seq, ref["grad_abs"], "segment-parallel against per-tile " + name)
+    for r in runs[1:]:
+        assert np.array_equal(r[0], g_par) and np.array_equal(r[1], g_seq)
 
 
 def test_segment_parallel_through_iterations(mppi, oracle_lib):
