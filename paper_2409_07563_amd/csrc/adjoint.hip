@@ -340,35 +340,55 @@ __device__ __forceinline__ void rk4_jvp(const DevParams& p, const float* xt, con
 //                 its partial gradient goes to its own row;
 //   reduce:       sums tiles x segments rows.
 // The mode is chosen on the device from the listed count, so no host
-// synchronisation is needed.  Record per (tile, segment, sample): for each
-// column i, P_s[0..4][i] then q_s[i] (6 floats), then x_T (5): 35 floats, padded
-// to 36.
+// synchronisation is needed.
+//
+// The parallel units are finer than the checkpoint segments: each segment of
+// c steps splits into sub = ceil(c / 5) units of cs = ceil(c / sub) steps (the
+// last ones of a ragged final segment may be empty: identity maps).  A unit
+// past its segment's start has no checkpoint; its map's waves rebuild the
+// segment's earlier steps first (without tangents) and the column-0 wave
+// stores the unit's start state for its sweep.  Record per (tile, unit,
+// sample): for each column i, P[0..4][i] then q[i] (6 floats); x_T (5, the
+// last unit); the unit's start state x (5) and its compensation (2): 42
+// floats, padded to 44.
 constexpr int kTpMaxTiles = kAdjointTilesMax;
-// at most this many (tile, segment) rows: the partial gradients and the
+// at most this many (tile, unit) rows: the partial gradients and the
 // pre-activation scratch grow with them
 constexpr int kTpRowBudget = 1280;
+constexpr int kTpUnitSteps = 5;
+
+// units per checkpoint segment of c steps, and the steps of a unit
+__host__ __device__ inline int tp_sub(int c) { return (c + kTpUnitSteps - 1) / kTpUnitSteps; }
+__host__ __device__ inline int tp_unit_steps(int c) { return (c + tp_sub(c) - 1) / tp_sub(c); }
 
 // The most tiles the segment-parallel mode takes for a context of `tiles`
-// tiles and nseg segments (the scratch is sized for it).
-inline int tp_cap(int tiles, int nseg) {
-  return std::min(std::min(tiles, kTpMaxTiles), kTpRowBudget / nseg);
+// tiles and nunit units (the scratch is sized for it).
+inline int tp_cap(int tiles, int nunit) {
+  return std::min(std::min(tiles, kTpMaxTiles), kTpRowBudget / nunit);
 }
-constexpr int kTpRec = 36;
+constexpr int kTpRec = 44;
 constexpr int kTpXT = 30;  // offset of x_T in a record
-static_assert(5 * 6 + 5 <= kTpRec, "record size");
+constexpr int kTpX0 = 35;  // offset of the unit's start state (x, then comp[0..1])
+static_assert(kTpX0 + 7 <= kTpRec, "record size");
 
+// Which units a workgroup of the sweep handles: in the segment-parallel mode
+// one (tile, unit) pair, units of `sub` per segment; otherwise one tile and
+// every segment (units = segments).
 struct SegSel {
-  int tile, lo, hi;
+  int tile, lo, hi, sub;
   bool par;
 };
 
-__device__ __forceinline__ SegSel seg_select(int nseg, int tp_tiles, int count) {
+__device__ __forceinline__ SegSel seg_select(int nseg, int c, int tp_tiles, int count) {
   SegSel s;
   s.par = tp_tiles > 0 && count <= tp_tiles * kTileS;
   if (s.par) {
-    s.tile = blockIdx.x / nseg;
-    s.lo = s.hi = blockIdx.x % nseg;
+    s.sub = tp_sub(c);
+    const int nunit = nseg * s.sub;
+    s.tile = blockIdx.x / nunit;
+    s.lo = s.hi = blockIdx.x % nunit;
   } else {
+    s.sub = 1;
     s.tile = blockIdx.x;
     s.lo = 0;
     s.hi = nseg - 1;
@@ -376,19 +396,30 @@ __device__ __forceinline__ SegSel seg_select(int nseg, int tp_tiles, int count) 
   return s;
 }
 
-// The costate carried into segment seg (< nseg - 1) for the lane's sample n of
-// tile `tile`: the terminal gradient at x_T, then the maps of segments
-// nseg - 1 .. seg + 1 in that order.
+// Steps [t0, t0 + len) of unit u (sub units per segment of c steps).
+__device__ __forceinline__ void unit_steps(int u, int sub, int c, int T, int& seg, int& h,
+                                           int& t0, int& len) {
+  seg = u / sub;
+  h = u % sub;
+  const int cs = (c + sub - 1) / sub;
+  const int seg_len = min(c, T - seg * c);
+  t0 = seg * c + min(h * cs, seg_len);
+  len = max(0, min(cs, seg_len - h * cs));
+}
+
+// The costate carried into unit `unit` (< nunit - 1) for the lane's sample n of
+// tile `tile`: the terminal gradient at x_T, then the maps of units
+// nunit - 1 .. unit + 1 in that order.
 __device__ __forceinline__ void tp_chain(const DevParams& p, const float* __restrict__ tp,
-                                         int tile, int nseg, int seg, int n, int T, float a,
+                                         int tile, int nunit, int unit, int n, int T, float a,
                                          float* mu) {
   constexpr int N = 5;
-  const float* last = tp + (static_cast<int64_t>(tile * nseg + nseg - 1) * kTileS + n) * kTpRec;
+  const float* last = tp + (static_cast<int64_t>(tile * nunit + nunit - 1) * kTileS + n) * kTpRec;
   const float* r = p.ref + static_cast<int64_t>(T) * N;
 #pragma unroll
   for (int i = 0; i < N; ++i) mu[i] = a * 2.0f * p.w[16] * p.w[i] * (last[kTpXT + i] - r[i]);
-  for (int s = nseg - 1; s > seg; --s) {
-    const float* rec = tp + (static_cast<int64_t>(tile * nseg + s) * kTileS + n) * kTpRec;
+  for (int s = nunit - 1; s > unit; --s) {
+    const float* rec = tp + (static_cast<int64_t>(tile * nunit + s) * kTileS + n) * kTpRec;
     float m[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -399,6 +430,28 @@ __device__ __forceinline__ void tp_chain(const DevParams& p, const float* __rest
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) mu[i] = m[i];
+  }
+}
+
+// The start state of a unit: its segment's checkpoint (h = 0), or the state
+// the map kernel stored for it (record `row`, sample n).
+__device__ __forceinline__ void load_unit_start(const float* __restrict__ ckpt, int64_t ldk,
+                                                int k, int seg, int h,
+                                                const float* __restrict__ tp, int row, int n,
+                                                float* x, float* comp) {
+  constexpr int N = 5;
+  if (h == 0) {
+    const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + k;
+#pragma unroll
+    for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
+    comp[0] = ck[5 * ldk];
+    comp[1] = ck[6 * ldk];
+  } else {
+    const float* rec = tp + (static_cast<int64_t>(row) * kTileS + n) * kTpRec;
+#pragma unroll
+    for (int i = 0; i < N; ++i) { x[i] = rec[kTpX0 + i]; comp[i] = 0.0f; }
+    comp[0] = rec[kTpX0 + 5];
+    comp[1] = rec[kTpX0 + 6];
   }
 }
 
@@ -426,9 +479,9 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
   constexpr int N = 5, M = 2;
   const int count = meta->count;
   if (count > tp_tiles * kTileS) return;  // the sequential sweep runs instead
-  const int nseg = (T + c - 1) / c;
-  const int col = blockIdx.x % N, ts = blockIdx.x / N;
-  const int seg = ts % nseg, tile = ts / nseg;
+  const int nseg = (T + c - 1) / c, sub = tp_sub(c), nunit = nseg * sub;
+  const int col = blockIdx.x % N, tu = blockIdx.x / N;
+  const int unit = tu % nunit, tile = tu / nunit;
   const int base = tile * kTileS;
   if (base >= count) return;  // wave-uniform
   extern __shared__ float4 lds4[];
@@ -452,7 +505,8 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
   const BwdItem item = list[valid ? idx : base];
   const float a = valid ? item.a : 0.0f;
   const float* e = eps + item.k;
-  const int t0 = seg * c, len = min(c, T - t0);
+  int seg, h, t0, len;
+  unit_steps(unit, sub, c, T, seg, h, t0, len);
   float x[N], comp[N], xd[N];
   const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + item.k;
 #pragma unroll
@@ -463,6 +517,28 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
   }
   comp[0] = ck[5 * ldk];
   comp[1] = ck[6 * ldk];
+  // the segment's steps before the unit: the sweep's rebuild, no tangent
+  for (int t = seg * c; t < t0; ++t) {
+    float v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = u[t * M + k] + e[static_cast<int64_t>(t * M + k) * ldk];
+    if constexpr (MT > 0) {
+      f4 a1[MT], a2[MT];
+      float res[N];
+      if constexpr (BF) mlp::residual_keep<MT>(WFB, x, v, g, n, res, a1, a2);
+      else mlp::residual_keep<MT>(WF, x, v, g, n, res, a1, a2);
+      step<Model, kRK4>(x, v, comp, p, res);
+    } else {
+      step<Model, kRK4>(x, v, comp, p);
+    }
+  }
+  float* rec = tp + (static_cast<int64_t>(tile * nunit + unit) * kTileS + n) * kTpRec;
+  if (h > 0 && col == 0 && g == 0) {  // the unit's start state for its sweep
+#pragma unroll
+    for (int i = 0; i < N; ++i) rec[kTpX0 + i] = x[i];
+    rec[kTpX0 + 5] = comp[0];
+    rec[kTpX0 + 6] = comp[1];
+  }
   float q = 0.0f;
   for (int j = 0; j < len; ++j) {
     const int t = t0 + j;
@@ -475,12 +551,12 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
       f4 d1[MT], d2[MT];
       float res[N], gd[N];
       if constexpr (BF) {
-        f4 a1[MT], a2[MT], h;
+        f4 a1[MT], a2[MT], hh;
         mlp::residual_keep<MT>(WFB, x, v, g, n, res, a1, a2);
 #pragma unroll
         for (int t2 = 0; t2 < MT; ++t2) {
-          mlp::tanh4_d(a1[t2], h, d1[t2]);
-          mlp::tanh4_d(a2[t2], h, d2[t2]);
+          mlp::tanh4_d(a1[t2], hh, d1[t2]);
+          mlp::tanh4_d(a2[t2], hh, d2[t2]);
         }
         mlp::jvp<MT>(mlp::RoundedView<MT>{WF}, xd, g, n, d1, d2, gd);
       } else {
@@ -504,11 +580,10 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
     }
   }
   if (g == 0) {
-    float* rec = tp + (static_cast<int64_t>(tile * nseg + seg) * kTileS + n) * kTpRec;
 #pragma unroll
     for (int i = 0; i < N; ++i) rec[col * 6 + i] = xd[i];
     rec[col * 6 + 5] = q;
-    if (seg == nseg - 1 && col == 0) {
+    if (unit == nunit - 1 && col == 0) {  // after the last step: x_T
 #pragma unroll
       for (int i = 0; i < N; ++i) rec[kTpXT + i] = x[i];
     }
@@ -575,7 +650,8 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   using f4 = mlp::f4;
   constexpr int N = 5, M = 2, H = 16 * MT;
   const int nseg = (T + c - 1) / c;
-  const SegSel sel = seg_select(nseg, tp_tiles, meta->count);
+  const SegSel sel = seg_select(nseg, c, tp_tiles, meta->count);
+  const int nunit = nseg * sel.sub;
   const int base = sel.tile * kTileS;
   if (base >= meta->count) return;  // wave-uniform
   extern __shared__ float4 lds4[];
@@ -625,20 +701,21 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   const float ic[2] = {p.is_coef[0], p.is_coef[1]};
 
   if (sel.par) {
-    if (sel.hi < nseg - 1) tp_chain(p, tp, sel.tile, nseg, sel.hi, n, T, a, mu);
-    if (du_off >= 0)
-      tp_zero_du(partial + static_cast<int64_t>(blockIdx.x) * ngp, du_off, T, sel.lo * c,
-                 min(c, T - sel.lo * c), threadIdx.x, blockDim.x);
+    if (sel.hi < nunit - 1) tp_chain(p, tp, sel.tile, nunit, sel.hi, n, T, a, mu);
+    if (du_off >= 0) {
+      int sg, hp, ut0, ulen;
+      unit_steps(sel.hi, sel.sub, c, T, sg, hp, ut0, ulen);
+      tp_zero_du(partial + static_cast<int64_t>(blockIdx.x) * ngp, du_off, T, ut0, ulen,
+                 threadIdx.x, blockDim.x);
+    }
   }
-  for (int seg = sel.hi; seg >= sel.lo; --seg) {
-    const int t0 = seg * c, len = min(c, T - t0);
-    // rebuild x_{t0} .. x_{t0+len} from the checkpoint
+  for (int ui = sel.hi; ui >= sel.lo; --ui) {
+    int seg, hp, t0, len;
+    unit_steps(ui, sel.sub, c, T, seg, hp, t0, len);
+    // rebuild x_{t0} .. x_{t0+len} from the checkpoint (or the unit's stored
+    // start state)
     float x[N], comp[N];
-    const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + k;
-#pragma unroll
-    for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
-    comp[0] = ck[5 * ldk];
-    comp[1] = ck[6 * ldk];
+    load_unit_start(ckpt, ldk, k, seg, hp, tp, sel.tile * nunit + ui, n, x, comp);
     // u and the noise of a step are requested one step ahead
     float un[M], en[M];
     auto fetch_v = [&](int t) {
@@ -648,7 +725,7 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
         en[q] = e[static_cast<int64_t>(t * M + q) * ldk];
       }
     };
-    fetch_v(t0);
+    if (len > 0) fetch_v(t0);
     for (int j = 0; j < len; ++j) {
       const int t = t0 + j;
       float v[M];
@@ -682,7 +759,7 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
       for (int i = 0; i < N; ++i) xs[len * N + i] = x[i];
     }
     __syncthreads();
-    if (seg == nseg - 1) {  // terminal cost w16 sum_i Q_i (x_T - r_T)^2
+    if (ui == nunit - 1) {  // terminal cost w16 sum_i Q_i (x_T - r_T)^2
       const float* r = p.ref + static_cast<int64_t>(T) * N;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -698,7 +775,7 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
 #pragma unroll
       for (int i = 0; i < N; ++i) rn[i] = r[i];
     };
-    fetch_r(len - 1);
+    if (len > 0) fetch_r(len - 1);
     for (int j = len - 1; j >= 0; --j) {
       const int t = t0 + j;
       // running cost at x_{t+1}
@@ -870,7 +947,8 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
   using PK = mlp::Pack<MT>;
   constexpr int N = 5, M = 2, H = 16 * MT, PS = SplitLds<MT, SW>::P;
   const int nseg = (T + c - 1) / c;
-  const SegSel sel = seg_select(nseg, tp_tiles, meta->count);
+  const SegSel sel = seg_select(nseg, c, tp_tiles, meta->count);
+  const int nunit = nseg * sel.sub;
   const int base = sel.tile * kTileS;
   if (base >= meta->count) return;  // workgroup-uniform
   extern __shared__ float4 lds4[];
@@ -957,19 +1035,19 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
   int par = 0;
 
   if (sel.par) {
-    if (sel.hi < nseg - 1) tp_chain(p, tp, sel.tile, nseg, sel.hi, n, T, a, mu);
-    if (du_off >= 0)
-      tp_zero_du(partial + static_cast<int64_t>(blockIdx.x) * ngp, du_off, T, sel.lo * c,
-                 min(c, T - sel.lo * c), threadIdx.x, blockDim.x);
+    if (sel.hi < nunit - 1) tp_chain(p, tp, sel.tile, nunit, sel.hi, n, T, a, mu);
+    if (du_off >= 0) {
+      int sg, hp, ut0, ulen;
+      unit_steps(sel.hi, sel.sub, c, T, sg, hp, ut0, ulen);
+      tp_zero_du(partial + static_cast<int64_t>(blockIdx.x) * ngp, du_off, T, ut0, ulen,
+                 threadIdx.x, blockDim.x);
+    }
   }
-  for (int seg = sel.hi; seg >= sel.lo; --seg) {
-    const int t0 = seg * c, len = min(c, T - t0);
+  for (int ui = sel.hi; ui >= sel.lo; --ui) {
+    int seg, hp, t0, len;
+    unit_steps(ui, sel.sub, c, T, seg, hp, t0, len);
     float x[N], comp[N];
-    const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + k;
-#pragma unroll
-    for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
-    comp[0] = ck[5 * ldk];
-    comp[1] = ck[6 * ldk];
+    load_unit_start(ckpt, ldk, k, seg, hp, tp, sel.tile * nunit + ui, n, x, comp);
     // u and the noise of a step are requested one step ahead, so their
     // latency hides behind the previous step's work (barriers wait for LDS
     // only, not for these loads)
@@ -981,7 +1059,7 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
         en[q] = e[static_cast<int64_t>(t * M + q) * ldk];
       }
     };
-    fetch_v(t0);
+    if (len > 0) fetch_v(t0);
     for (int j = 0; j < len; ++j) {
       const int t = t0 + j;
       float v[M];
@@ -1073,7 +1151,7 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
       for (int i = 0; i < N; ++i) xs[len * N + i] = x[i];
     }
     __syncthreads();
-    if (seg == nseg - 1) {
+    if (ui == nunit - 1) {
       const float* r = p.ref + static_cast<int64_t>(T) * N;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -1097,7 +1175,7 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
         pn2[q] = ps[(MT + q0 + q) * kWave];
       }
     };
-    fetch_r(len - 1);
+    if (len > 0) fetch_r(len - 1);
     for (int j = len - 1; j >= 0; --j) {
       const int t = t0 + j;
       float r[N];
@@ -1264,18 +1342,18 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
 // the 16 partial sums combined in a fixed order.  Columns j < ngrad are the
 // gradient (grad[j] = sum, or += with accumulate); columns ngrad.. (ncols >
 // ngrad) are dL/du, added to G[j - ngrad].  In the segment-parallel mode the
-// rows are the (tile, segment) pairs.
+// rows are the (tile, unit) pairs.
 constexpr int kReduceCols = 64, kReduceParts = 16;
 __global__ __launch_bounds__(kReduceCols * kReduceParts) void adjoint_reduce_kernel(
     const float* __restrict__ partial, int64_t ngp, int ngrad, int ncols,
     const BwdMeta* __restrict__ meta, float* __restrict__ grad, int accumulate,
-    float* __restrict__ G, int tp_tiles, int nseg) {
+    float* __restrict__ G, int tp_tiles, int nunit) {
   __shared__ float red[kReduceParts][kReduceCols];
   const int c = threadIdx.x % kReduceCols, part = threadIdx.x / kReduceCols;
   const int j = blockIdx.x * kReduceCols + c;
   const int count = meta->count;
   const int tiles = (count + kTileS - 1) / kTileS *
-                    (tp_tiles > 0 && count <= tp_tiles * kTileS ? nseg : 1);
+                    (tp_tiles > 0 && count <= tp_tiles * kTileS ? nunit : 1);
   float s = 0.0f;
   if (j < ncols) {
     int w = part;
@@ -1319,15 +1397,15 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_eve
   s.offs = take(sizeof(int) * nb);
   s.meta = take(sizeof(BwdMeta));
   s.list = take(sizeof(BwdItem) * K);
-  // rows: one per tile, or per (tile, segment) in the segment-parallel mode
-  const int nseg = (TM / 2 + ckpt_every - 1) / ckpt_every;
-  const int tp_max = tp_cap(tiles, nseg);
-  const size_t rows = std::max(static_cast<size_t>(tiles), static_cast<size_t>(tp_max) * nseg);
+  // rows: one per tile, or per (tile, unit) in the segment-parallel mode
+  const int nunit = (TM / 2 + ckpt_every - 1) / ckpt_every * tp_sub(ckpt_every);
+  const int tp_max = tp_cap(tiles, nunit);
+  const size_t rows = std::max(static_cast<size_t>(tiles), static_cast<size_t>(tp_max) * nunit);
   s.partial = take(sizeof(float) * rows * s.ngp);
   // pre-activations of one segment per row: c steps x 2 layers x H/16 x 64 lanes x 4
   s.pre = take(sizeof(float) * 4 * rows * ckpt_every * 2 * (hidden > 0 ? hidden / 16 : 0) *
                kWave);
-  s.tp = take(sizeof(float) * static_cast<size_t>(tp_max) * nseg * kTileS * kTpRec);
+  s.tp = take(sizeof(float) * static_cast<size_t>(tp_max) * nunit * kTileS * kTpRec);
   s.total = off;
   return s;
 }
@@ -1375,9 +1453,9 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   SweepFn fn = nullptr;
   const bool bf = hidden > 0 && p.mlp_bf != nullptr;  // BF16 products
   const int tiles = (K + kTileS - 1) / kTileS;
-  const int nseg = (T + ckpt_every - 1) / ckpt_every;
+  const int nunit = (T + ckpt_every - 1) / ckpt_every * tp_sub(ckpt_every);
   // segment-parallel mode: up to tp tiles
-  const int tp = std::min(std::max(tp_tiles, 0), tp_cap(tiles, nseg));
+  const int tp = std::min(std::max(tp_tiles, 0), tp_cap(tiles, nunit));
   TpFn tfn = nullptr;
   size_t tlds = 0;  // the forward pack (binary32), then the bfloat16 pack
   switch (hidden) {
@@ -1455,15 +1533,15 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   float* tpbuf = reinterpret_cast<float*>(d_scratch + s.tp);
   if (tp > 0) {
     if (!tfn) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(tfn, dim3(tp * nseg * 5), dim3(kWave), tlds, stream, p, d_u, d_eps, ldk,
+    hipLaunchKernelGGL(tfn, dim3(tp * nunit * 5), dim3(kWave), tlds, stream, p, d_u, d_eps, ldk,
                        T, d_ckpt, ckpt_every, list, meta, tp, tpbuf);
   }
-  const int rows = std::max(tiles, tp * nseg);
+  const int rows = std::max(tiles, tp * nunit);
   hipLaunchKernelGGL(fn, dim3(rows), dim3(kWave * waves), lds, stream, p, d_u, d_eps, ldk, T,
                      d_ckpt, ckpt_every, list, meta, partial, s.ngp, du_off, pre, tpbuf, tp);
   hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((ncols + kReduceCols - 1) / kReduceCols),
                      dim3(kReduceCols * kReduceParts), 0, stream, partial, s.ngp, ngrad, ncols,
-                     meta, d_grad, accumulate ? 1 : 0, d_G_acc, tp, nseg);
+                     meta, d_grad, accumulate ? 1 : 0, d_G_acc, tp, nunit);
   return hipGetLastError();
 }
 

@@ -2,10 +2,12 @@
 against the binary64 oracle and against the per-tile sweep, through the C ABI.
 
 With few samples of nonzero weight the checkpoint segments are swept in
-parallel: each segment's costate map (the product of its step Jacobians,
-formed in forward mode through the RK4 stages and the MLP, plus its running
-costs' share) chains the costate from the terminal cost to every segment's
-end.  Mathematically the gradient is the per-tile sweep's; in binary32 the
+parallel, in units of at most 5 steps (a segment of c steps splits into
+ceil(c / 5) units; units past a segment's start begin from a state the map
+kernel stores; units of a ragged last segment may be empty): each unit's
+costate map (the product of its step Jacobians, formed in forward mode
+through the RK4 stages and the MLP, plus its running costs' share) chains the
+costate from the terminal cost to every unit's end.  Mathematically the gradient is the per-tile sweep's; in binary32 the
 chained costate rounds differently, so both are held to the oracle at the
 gradient bound of tests/test_gpu_grad.py (1e-4 of sum_k |a_k dJ_k/dtheta|
 per parameter), and to each other at the same bound.  Cases: every hidden
