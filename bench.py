@@ -336,7 +336,14 @@ def run_single(args, wl, update_forms: bool = False, autotune_reps: int = 30) ->
         ctl.set_tuning(**json.loads(args.tuning))
     elif not args.no_autotune:
         tuned = ctl.autotune(reps=autotune_reps)
-    s = timed(stream, lambda: ctl.iterate(I), args.steps, args.warmup)
+    # each step calls the C ABI directly on the library's stream (ordered once
+    # after torch's stream here, not re-synchronised with it in every step)
+    L = M.lib()
+    ctl._enter()
+
+    def step():
+        M._abi.check(L.mppi_iterate(ctl.ctx, I))
+    s = timed(stream, step, args.steps, args.warmup)
     steps_per_iter = wl.K * wl.T
     out = {"workload": wl.name, "K": wl.K, "T": wl.T, "iterations_per_step": I,
            "dynamics": wl.model, "integrator": wl.integrator, "cost": wl.cost,
@@ -353,8 +360,7 @@ def run_single(args, wl, update_forms: bool = False, autotune_reps: int = 30) ->
                 ctl.set_tuning(update_form=form, batch_form=0)
             except M.MPPIError:
                 continue
-            forms[name] = timed(stream, lambda: ctl.iterate(I), args.steps,
-                                max(1, args.warmup)) * 1e3
+            forms[name] = timed(stream, step, args.steps, max(1, args.warmup)) * 1e3
         ctl.set_tuning(**chosen)
         out["update_forms_ms_per_step"] = forms
         iforms = {}
@@ -363,8 +369,7 @@ def run_single(args, wl, update_forms: bool = False, autotune_reps: int = 30) ->
                 ctl.set_tuning(batch_form=bf)
             except M.MPPIError:
                 continue
-            iforms[name] = timed(stream, lambda: ctl.iterate(I), args.steps,
-                                 max(1, args.warmup)) * 1e3
+            iforms[name] = timed(stream, step, args.steps, max(1, args.warmup)) * 1e3
         ctl.set_tuning(**chosen)
         if len(iforms) > 1:
             out["iteration_forms_ms_per_step"] = iforms
@@ -548,6 +553,11 @@ def run_batch(args, insts, loop_baseline: bool = True) -> dict:
     elif not args.no_autotune:
         ctl.autotune(reps=3)
     tuning = ctl.tuning()
+    L = M.lib()
+    ctl._enter()
+
+    def step():  # the C ABI directly on the library's stream
+        M._abi.check(L.mppi_iterate(ctl.ctx, 1))
     # both batch forms timed on their own (one warm-started iteration per
     # step): four launches per iteration, and the one-launch form
     forms = {}
@@ -557,10 +567,10 @@ def run_batch(args, insts, loop_baseline: bool = True) -> dict:
             ctl.set_tuning(batch_form=form, **extra)
         except M.MPPIError:
             continue
-        forms[name] = timed(stream, lambda: ctl.iterate(1), max(1, args.steps // 2),
+        forms[name] = timed(stream, step, max(1, args.steps // 2),
                             max(1, args.warmup // 2)) * 1e3
     ctl.set_tuning(**tuning)
-    s = timed(stream, lambda: ctl.iterate(1), args.steps, args.warmup)
+    s = timed(stream, step, args.steps, args.warmup)
     tn, tr, tu = phase_times(ctl, max(1, args.kernel_reps // 5))
     ctl.close()
     out = {"workload": "c4_batched_bicycle", "instances": len(insts), "sum_K_T": total,
@@ -574,10 +584,11 @@ def run_batch(args, insts, loop_baseline: bool = True) -> dict:
         # the same instances as single contexts, one after another on one
         # stream (each with the default launch shapes of its size)
         singles = [M.Controller(w, device="cuda:0", stream=stream) for w in insts]
+        singles[0]._enter()
 
         def loop():
             for c in singles:
-                c.iterate(1)
+                M._abi.check(L.mppi_iterate(c.ctx, 1))
         s_loop = timed(stream, loop, max(1, args.steps // 4), 1)
         for c in singles:
             c.close()
@@ -702,9 +713,13 @@ def main_all(args):
     c5 = run_grad(args, W.c5(), full=False)
     print(f"[bench] c5: fwd+bwd/fwd {c5['fwd_bwd_over_fwd']:.3f}", file=sys.stderr, flush=True)
     c1 = run_single(args, W.c1(), autotune_reps=30)
-    floor_us = ceil["graph_launch_us"]["3_kernels"] + ceil["chain_us"]["T100"]
-    c1["latency_floor_us"] = floor_us
-    c1["us_per_iteration_over_floor"] = c1["us_per_iteration"] / floor_us
+    # latency references: one iteration's steps as a dependent chain on one
+    # wave, and an empty three-kernel graph launch (steps here are direct
+    # launches, pipelined on the stream, so a launch's own latency overlaps
+    # the previous iteration)
+    c1["floors_us"] = {"chain_T100": ceil["chain_us"]["T100"],
+                       "empty_3_kernel_graph": ceil["graph_launch_us"]["3_kernels"]}
+    c1["us_per_iteration_over_chain"] = c1["us_per_iteration"] / ceil["chain_us"]["T100"]
     print(f"[bench] c1: {c1['value']:.4g}", file=sys.stderr, flush=True)
     cfg = {k: lead[k] for k in ("workload", "instances", "sum_K_T", "K_range", "T_range",
                                 "obstacles_range", "iterations_per_step", "dynamics", "cost")}
