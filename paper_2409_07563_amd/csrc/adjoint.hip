@@ -590,6 +590,189 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
   }
 }
 
+// The map kernel with the MLP of the tile split over SW waves (binary32
+// products): wave w owns the hidden M-tiles w TW .. w TW + TW - 1 of every
+// product, forward and tangent, with its operand slices in registers; the
+// h1 and h1' tiles and the output partials meet in LDS (double-buffered by
+// step parity, two barriers per step).  The products accumulate in the order
+// of the one-wave kernel's; the bicycle step and its tangent are repeated by
+// every wave.  Used for H = 64 with binary32 products whatever the sweep's
+// split, so the sweeps of every split read the same records.
+template <int MT, int SW, bool FAST>
+__global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
+    DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
+    const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
+    const BwdMeta* __restrict__ meta, int tp_tiles, float* __restrict__ tp) {
+  static_assert(MT % SW == 0, "tiles per wave");
+  constexpr int TW = MT / SW;
+  using Model = Bicycle<FAST>;
+  using f4 = mlp::f4;
+  using PK = mlp::Pack<MT>;
+  constexpr int N = 5, M = 2;
+  const int count = meta->count;
+  if (count > tp_tiles * kTileS) return;  // the sequential sweep runs instead
+  const int nseg = (T + c - 1) / c, sub = tp_sub(c), nunit = nseg * sub;
+  const int col = blockIdx.x % N, tu = blockIdx.x / N;
+  const int unit = tu % nunit, tile = tu / nunit;
+  const int base = tile * kTileS;
+  if (base >= count) return;  // workgroup-uniform
+  extern __shared__ float4 lds4[];
+  f4* xa = reinterpret_cast<f4*>(lds4);  // [2][MT][64] each: h1, h1', output, tangent output
+  f4* xt1 = xa + 2 * MT * kWave;
+  f4* xb = xt1 + 2 * MT * kWave;
+  f4* xt3 = xb + 2 * MT * kWave;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int n = lane % kTileS, g = lane / kTileS;
+  const int q0 = w * TW;
+  auto xch = [&](f4* buf, int par, int q) -> f4& { return buf[(par * MT + q) * kWave + lane]; };
+
+  // this wave's forward operand slices
+  const float* pf = p.mlp + lane;
+  float fw1[TW][2], fw2[TW][MT][4], fw3[TW][4];
+  f4 fb1[TW], fb2[TW], fb3[TW];
+#pragma unroll
+  for (int q = 0; q < TW; ++q) {
+    const int t = q0 + q;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) fw1[q][j] = pf[(PK::kW1 + 2 * t + j) * kWave];
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fw2[q][tt][i] = pf[(PK::kW2 + (t * MT + tt) * 4 + i) * kWave];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fw3[q][i] = pf[(PK::kW3 + 4 * t + i) * kWave];
+      fb1[q][i] = pf[(PK::kB1 + 4 * t + i) * kWave];
+      fb2[q][i] = pf[(PK::kB2 + 4 * t + i) * kWave];
+      fb3[q][i] = t == 0 ? pf[(PK::kB3 + i) * kWave] : 0.0f;
+    }
+  }
+
+  const int idx = base + n;
+  const bool valid = idx < count;
+  const BwdItem item = list[valid ? idx : base];
+  const float a = valid ? item.a : 0.0f;
+  const float* e = eps + item.k;
+  int seg, h, t0, len;
+  unit_steps(unit, sub, c, T, seg, h, t0, len);
+  float x[N], comp[N], xd[N];
+  const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + item.k;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    x[i] = ck[i * ldk];
+    comp[i] = 0.0f;
+    xd[i] = i == col ? 1.0f : 0.0f;
+  }
+  comp[0] = ck[5 * ldk];
+  comp[1] = ck[6 * ldk];
+  const f4 zero4{0.0f, 0.0f, 0.0f, 0.0f};
+  const float v0[2] = {0.0f, 0.0f};
+  int par = 0;
+  float q = 0.0f;
+  // one step: the MLP forward (and with TAN its tangent along xd), then the
+  // RK4 step (and the tangent's); every wave runs it (barriers inside)
+  auto one_step = [&](int t, bool tan) {
+    float v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = u[t * M + k] + e[static_cast<int64_t>(t * M + k) * ldk];
+    float xn[N];
+    if (tan) rk4_jvp<FAST>(p, x, v, xd, xn);
+    const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
+    const float y0 = mlp::input_operand(xd, v0, g, 0), y1 = mlp::input_operand(xd, v0, g, 1);
+#pragma unroll
+    for (int qq = 0; qq < TW; ++qq) {
+      const f4 a1 = mlp::mfma(fw1[qq][1], z1, mlp::mfma(fw1[qq][0], z0, fb1[qq]));
+      f4 h1, d1;
+      mlp::tanh4_d(a1, h1, d1);
+      xch(xa, par, q0 + qq) = h1;
+      if (tan)
+        xch(xt1, par, q0 + qq) = mlp::mfma(fw1[qq][1], y1, mlp::mfma(fw1[qq][0], y0, zero4)) * d1;
+    }
+    __syncthreads();
+    f4 acc[TW], acct[TW];
+#pragma unroll
+    for (int qq = 0; qq < TW; ++qq) { acc[qq] = fb2[qq]; acct[qq] = zero4; }
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt) {
+      const f4 hh = xch(xa, par, tt);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int qq = 0; qq < TW; ++qq) acc[qq] = mlp::mfma(fw2[qq][tt][i], hh[i], acc[qq]);
+    }
+    if (tan) {
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt) {
+        const f4 ht = xch(xt1, par, tt);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int qq = 0; qq < TW; ++qq) acct[qq] = mlp::mfma(fw2[qq][tt][i], ht[i], acct[qq]);
+      }
+    }
+#pragma unroll
+    for (int qq = 0; qq < TW; ++qq) {
+      f4 h2, d2;
+      mlp::tanh4_d(acc[qq], h2, d2);
+      f4 part = fb3[qq];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[qq][i], h2[i], part);
+      xch(xb, par, q0 + qq) = part;
+      if (tan) {
+        const f4 h2t = acct[qq] * d2;
+        f4 pt = zero4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pt = mlp::mfma(fw3[qq][i], h2t[i], pt);
+        xch(xt3, par, q0 + qq) = pt;
+      }
+    }
+    __syncthreads();
+    f4 out = xch(xb, par, 0);
+#pragma unroll
+    for (int tt = 1; tt < MT; ++tt) out += xch(xb, par, tt);
+    float res[N];
+    mlp::broadcast5(out, n, res);
+    if (tan) {
+      f4 ot = xch(xt3, par, 0);
+#pragma unroll
+      for (int tt = 1; tt < MT; ++tt) ot += xch(xt3, par, tt);
+      float gd[N];
+      mlp::broadcast5(ot, n, gd);
+#pragma unroll
+      for (int i = 0; i < N; ++i) xn[i] += p.dt * gd[i];
+    }
+    par ^= 1;
+    step<Model, kRK4>(x, v, comp, p, res);
+    if (tan) {
+      const float* r = p.ref + static_cast<int64_t>(t + 1) * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        xd[i] = xn[i];
+        q = fmaf(a * 2.0f * p.w[i] * (x[i] - r[i]), xd[i], q);
+      }
+    }
+  };
+  // the segment's steps before the unit: the sweep's rebuild, no tangent
+  for (int t = seg * c; t < t0; ++t) one_step(t, false);
+  float* rec = tp + (static_cast<int64_t>(tile * nunit + unit) * kTileS + n) * kTpRec;
+  if (h > 0 && col == 0 && w == 0 && g == 0) {  // the unit's start state for its sweep
+#pragma unroll
+    for (int i = 0; i < N; ++i) rec[kTpX0 + i] = x[i];
+    rec[kTpX0 + 5] = comp[0];
+    rec[kTpX0 + 6] = comp[1];
+  }
+  for (int t = t0; t < t0 + len; ++t) one_step(t, true);
+  if (w == 0 && g == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) rec[col * 6 + i] = xd[i];
+    rec[col * 6 + 5] = q;
+    if (unit == nunit - 1 && col == 0) {  // after the last step: x_T
+#pragma unroll
+      for (int i = 0; i < N; ++i) rec[kTpXT + i] = x[i];
+    }
+  }
+}
+
 template <int MT, bool BF = false>
 struct SweepLds {
   static constexpr int P = 64 * MT + 16;  // transposition row stride (16 mod 32: no bank conflicts)
@@ -1457,6 +1640,7 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   // segment-parallel mode: up to tp tiles
   const int tp = std::min(std::max(tp_tiles, 0), tp_cap(tiles, nunit));
   TpFn tfn = nullptr;
+  int twaves = 1;
   size_t tlds = 0;  // the forward pack (binary32), then the bfloat16 pack
   switch (hidden) {
     case 0: tfn = pick_tp<0>(accurate_trig); break;
@@ -1475,6 +1659,11 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
     default: break;
   }
   tlds *= sizeof(float) * kWave;
+  if (hidden == 64 && !bf) {  // the MLP split over 4 waves
+    tfn = accurate_trig ? adjoint_tp_split_kernel<4, 4, false> : adjoint_tp_split_kernel<4, 4, true>;
+    twaves = 4;
+    tlds = sizeof(mlp::f4) * 4 * 2 * 4 * kWave;
+  }
   if (tp > 0 && tfn && tlds > 48 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(tfn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1533,8 +1722,8 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   float* tpbuf = reinterpret_cast<float*>(d_scratch + s.tp);
   if (tp > 0) {
     if (!tfn) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(tfn, dim3(tp * nunit * 5), dim3(kWave), tlds, stream, p, d_u, d_eps, ldk,
-                       T, d_ckpt, ckpt_every, list, meta, tp, tpbuf);
+    hipLaunchKernelGGL(tfn, dim3(tp * nunit * 5), dim3(kWave * twaves), tlds, stream, p, d_u,
+                       d_eps, ldk, T, d_ckpt, ckpt_every, list, meta, tp, tpbuf);
   }
   const int rows = std::max(tiles, tp * nunit);
   hipLaunchKernelGGL(fn, dim3(rows), dim3(kWave * waves), lds, stream, p, d_u, d_eps, ldk, T,
