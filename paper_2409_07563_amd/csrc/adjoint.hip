@@ -596,9 +596,12 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
 // h1 and h1' tiles and the output partials meet in LDS (double-buffered by
 // step parity, two barriers per step).  The products accumulate in the order
 // of the one-wave kernel's; the bicycle step and its tangent are repeated by
-// every wave.  Used for H = 64 with binary32 products whatever the sweep's
-// split, so the sweeps of every split read the same records.
-template <int MT, int SW, bool FAST>
+// every wave.  Used for H = 64 whatever the sweep's split, so the sweeps of
+// every split read the same records.  BF: the forward on the bfloat16
+// products as the split sweep's rebuild takes them (h2 tiles exchanged, every
+// wave forms the output over all K-blocks), the tangents through the rounded
+// weights.
+template <int MT, int SW, bool FAST, bool BF = false>
 __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
@@ -626,26 +629,48 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
   const int q0 = w * TW;
   auto xch = [&](f4* buf, int par, int q) -> f4& { return buf[(par * MT + q) * kWave + lane]; };
 
-  // this wave's forward operand slices
+  // this wave's forward operand slices (BF: the binary32 weights rounded to
+  // bfloat16 for the tangents, the bfloat16 rows for the forward)
   const float* pf = p.mlp + lane;
+  auto wt = [&](int row) {
+    const float w8 = pf[row * kWave];
+    return BF ? mlp::round_bf(w8) : w8;
+  };
   float fw1[TW][2], fw2[TW][MT][4], fw3[TW][4];
   f4 fb1[TW], fb2[TW], fb3[TW];
+  constexpr int KB = mlp::PackBf<MT>::KB;
+  constexpr int TWB = BF ? TW : 1, KBB = BF ? KB : 1;
+  mlp::bf8 v1[TWB], v2[TWB][KBB], v3[KBB];
 #pragma unroll
   for (int q = 0; q < TW; ++q) {
     const int t = q0 + q;
+    if constexpr (BF) {
+      using PB = mlp::PackBf<MT>;
+      const uint4* bp = p.mlp_bf + lane;
+      v1[q] = __builtin_bit_cast(mlp::bf8, bp[(PB::kW1 + t) * kWave]);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) fw1[q][j] = pf[(PK::kW1 + 2 * t + j) * kWave];
+      for (int kb = 0; kb < KB; ++kb)
+        v2[q][kb] = __builtin_bit_cast(mlp::bf8, bp[(PB::kW2 + t * KB + kb) * kWave]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) fw1[q][j] = wt(PK::kW1 + 2 * t + j);
 #pragma unroll
     for (int tt = 0; tt < MT; ++tt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) fw2[q][tt][i] = pf[(PK::kW2 + (t * MT + tt) * 4 + i) * kWave];
+      for (int i = 0; i < 4; ++i) fw2[q][tt][i] = wt(PK::kW2 + (t * MT + tt) * 4 + i);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      fw3[q][i] = pf[(PK::kW3 + 4 * t + i) * kWave];
+      fw3[q][i] = wt(PK::kW3 + 4 * t + i);
       fb1[q][i] = pf[(PK::kB1 + 4 * t + i) * kWave];
       fb2[q][i] = pf[(PK::kB2 + 4 * t + i) * kWave];
-      fb3[q][i] = t == 0 ? pf[(PK::kB3 + i) * kWave] : 0.0f;
+      fb3[q][i] = (BF || t == 0) ? pf[(PK::kB3 + i) * kWave] : 0.0f;
     }
+  }
+  if constexpr (BF) {
+    using PB = mlp::PackBf<MT>;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      v3[kb] = __builtin_bit_cast(mlp::bf8, p.mlp_bf[(PB::kW3 + kb) * kWave + lane]);
   }
 
   const int idx = base + n;
@@ -679,9 +704,13 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
     if (tan) rk4_jvp<FAST>(p, x, v, xd, xn);
     const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
     const float y0 = mlp::input_operand(xd, v0, g, 0), y1 = mlp::input_operand(xd, v0, g, 1);
+    mlp::bf8 zb;
+    if constexpr (BF) zb = mlp::input_operand_bf(x, v, g);
 #pragma unroll
     for (int qq = 0; qq < TW; ++qq) {
-      const f4 a1 = mlp::mfma(fw1[qq][1], z1, mlp::mfma(fw1[qq][0], z0, fb1[qq]));
+      f4 a1;
+      if constexpr (BF) a1 = mlp::mfma_bf(v1[qq], zb, fb1[qq]);
+      else a1 = mlp::mfma(fw1[qq][1], z1, mlp::mfma(fw1[qq][0], z0, fb1[qq]));
       f4 h1, d1;
       mlp::tanh4_d(a1, h1, d1);
       xch(xa, par, q0 + qq) = h1;
@@ -692,13 +721,25 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
     f4 acc[TW], acct[TW];
 #pragma unroll
     for (int qq = 0; qq < TW; ++qq) { acc[qq] = fb2[qq]; acct[qq] = zero4; }
+    if constexpr (BF) {
+      f4 h1a[MT];
 #pragma unroll
-    for (int tt = 0; tt < MT; ++tt) {
-      const f4 hh = xch(xa, par, tt);
+      for (int tt = 0; tt < MT; ++tt) h1a[tt] = xch(xa, par, tt);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int kb = 0; kb < KB; ++kb) {
+        const mlp::bf8 hb = mlp::kblock_operand<MT>(h1a, kb);
 #pragma unroll
-        for (int qq = 0; qq < TW; ++qq) acc[qq] = mlp::mfma(fw2[qq][tt][i], hh[i], acc[qq]);
+        for (int qq = 0; qq < TW; ++qq) acc[qq] = mlp::mfma_bf(v2[qq][kb], hb, acc[qq]);
+      }
+    } else {
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt) {
+        const f4 hh = xch(xa, par, tt);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int qq = 0; qq < TW; ++qq) acc[qq] = mlp::mfma(fw2[qq][tt][i], hh[i], acc[qq]);
+      }
     }
     if (tan) {
 #pragma unroll
@@ -714,10 +755,14 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
     for (int qq = 0; qq < TW; ++qq) {
       f4 h2, d2;
       mlp::tanh4_d(acc[qq], h2, d2);
-      f4 part = fb3[qq];
+      if constexpr (BF) {
+        xch(xb, par, q0 + qq) = h2;  // the h2 tiles: every wave forms the output
+      } else {
+        f4 part = fb3[qq];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[qq][i], h2[i], part);
-      xch(xb, par, q0 + qq) = part;
+        for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[qq][i], h2[i], part);
+        xch(xb, par, q0 + qq) = part;
+      }
       if (tan) {
         const f4 h2t = acct[qq] * d2;
         f4 pt = zero4;
@@ -727,9 +772,20 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
       }
     }
     __syncthreads();
-    f4 out = xch(xb, par, 0);
+    f4 out;
+    if constexpr (BF) {
+      f4 h2a[MT];
 #pragma unroll
-    for (int tt = 1; tt < MT; ++tt) out += xch(xb, par, tt);
+      for (int tt = 0; tt < MT; ++tt) h2a[tt] = xch(xb, par, tt);
+      out = fb3[0];
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        out = mlp::mfma_bf(v3[kb], mlp::kblock_operand<MT>(h2a, kb), out);
+    } else {
+      out = xch(xb, par, 0);
+#pragma unroll
+      for (int tt = 1; tt < MT; ++tt) out += xch(xb, par, tt);
+    }
     float res[N];
     mlp::broadcast5(out, n, res);
     if (tan) {
@@ -1659,8 +1715,13 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
     default: break;
   }
   tlds *= sizeof(float) * kWave;
-  if (hidden == 64 && !bf) {  // the MLP split over 4 waves
-    tfn = accurate_trig ? adjoint_tp_split_kernel<4, 4, false> : adjoint_tp_split_kernel<4, 4, true>;
+  if (hidden == 64) {  // the MLP split over 4 waves
+    if (bf)
+      tfn = accurate_trig ? adjoint_tp_split_kernel<4, 4, false, true>
+                          : adjoint_tp_split_kernel<4, 4, true, true>;
+    else
+      tfn = accurate_trig ? adjoint_tp_split_kernel<4, 4, false>
+                          : adjoint_tp_split_kernel<4, 4, true>;
     twaves = 4;
     tlds = sizeof(mlp::f4) * 4 * 2 * 4 * kWave;
   }
