@@ -378,7 +378,8 @@ typedef struct mppi_tuning {
                                weight fill at most this many 16-sample tiles, else
                                one sweep per tile over the whole horizon; 0 to 128
                                (0: always the per-tile sweep; default 64; also at
-                               most 1280 / checkpoint segments) */
+                               most 1280 / units, a unit being up to 5 steps of
+                               a checkpoint segment) */
 } mppi_tuning;
 
 /* The context's current launch shapes. */

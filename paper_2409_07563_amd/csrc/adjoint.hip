@@ -916,7 +916,10 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   __syncthreads();
 
   // this tile's pre-activation scratch: [c steps][2 layers][MT][64 lanes] f4
-  mlp::f4* my_pre = pre + static_cast<int64_t>(blockIdx.x) * c * 2 * (MT ? MT : 1) * kWave + lane;
+  // (a row holds c steps, or a unit's steps in the segment-parallel mode)
+  const int pre_steps = sel.par ? tp_unit_steps(c) : c;
+  mlp::f4* my_pre =
+      pre + static_cast<int64_t>(blockIdx.x) * pre_steps * 2 * (MT ? MT : 1) * kWave + lane;
   const int idx = base + n;
   const bool valid = idx < meta->count;
   const BwdItem item = list[valid ? idx : base];
@@ -1251,7 +1254,8 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
   }
 
   // this tile's pre-activation scratch: [c steps][2 layers][MT][64 lanes] f4
-  f4* my_pre = pre + static_cast<int64_t>(blockIdx.x) * c * 2 * MT * kWave + lane;
+  const int pre_steps = sel.par ? tp_unit_steps(c) : c;
+  f4* my_pre = pre + static_cast<int64_t>(blockIdx.x) * pre_steps * 2 * MT * kWave + lane;
   const int idx = base + n;
   const bool valid = idx < meta->count;
   const BwdItem item = list[valid ? idx : base];
@@ -1641,9 +1645,11 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_eve
   const int tp_max = tp_cap(tiles, nunit);
   const size_t rows = std::max(static_cast<size_t>(tiles), static_cast<size_t>(tp_max) * nunit);
   s.partial = take(sizeof(float) * rows * s.ngp);
-  // pre-activations of one segment per row: c steps x 2 layers x H/16 x 64 lanes x 4
-  s.pre = take(sizeof(float) * 4 * rows * ckpt_every * 2 * (hidden > 0 ? hidden / 16 : 0) *
-               kWave);
+  // pre-activations of one segment per tile row (c steps), or of one unit per
+  // (tile, unit) row: steps x 2 layers x H/16 x 64 lanes x 4
+  const size_t pre_steps = std::max(static_cast<size_t>(tiles) * ckpt_every,
+                                    static_cast<size_t>(tp_max) * nunit * tp_unit_steps(ckpt_every));
+  s.pre = take(sizeof(float) * 4 * pre_steps * 2 * (hidden > 0 ? hidden / 16 : 0) * kWave);
   s.tp = take(sizeof(float) * static_cast<size_t>(tp_max) * nunit * kTileS * kTpRec);
   s.total = off;
   return s;

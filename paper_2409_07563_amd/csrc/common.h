@@ -142,7 +142,7 @@ constexpr int kBatchMaxTile = 256, kBatchMinTile = 64;
 constexpr int kOneLaunchMaxTiles = 256;
 
 // Segment-parallel reverse pass: the most 16-sample tiles of nonzero weight it
-// takes (also at most 1280 / segments; its scratch is sized for that many),
+// takes (also at most 1280 / units; its scratch is sized for that many),
 // and the default bound.
 constexpr int kAdjointTilesMax = 128, kAdjointTilesDefault = 64;
 struct BatchPlan {
@@ -288,7 +288,7 @@ size_t adjoint_lds_bytes(int hidden, int ckpt_every, bool bf16 = false);
 // d_G_acc += sum_k a_k dJ_k/du (may be d_G itself: the update happens after
 // every read of d_G, in stream order).  tp_tiles: the segment-parallel
 // reverse pass when at most that many tiles hold listed samples (0: never;
-// capped at 128, at 1280 / segments and at the context's tile count).
+// capped at 128, at 1280 / units and at the context's tile count).
 hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, const float* d_G,
                           const float* d_u, const float* d_eps, int64_t ldk, int K, int T,
                           const float* d_e, float lambda, float step, const float* d_ckpt,

@@ -23,6 +23,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tests import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -95,7 +96,7 @@ def _both(mppi, wl, ce, block=None, accurate=False, tiles=128):
     (16, 700, 33, 10, 50.0, None), (32, 256, 20, 7, 5.0, 128), (32, 256, 20, 7, 5.0, 64),
     (64, 100, 23, 1, 50.0, 256), (64, 333, 50, 64, 0.5, 256), (64, 333, 50, 13, 50.0, 64),
     (0, 1000, 50, 10, 0.5, None), (0, 1000, 50, 10, 50.0, None), (0, 37, 9, 4, 50.0, None),
-    (64, 2048, 20, 10, 50.0, 256), (16, 1024, 40, 1, 50.0, None)])
+    (64, 2048, 20, 10, 50.0, 256), (16, 1024, 40, 1, 50.0, None), (32, 500, 31, 5, 0.5, 128)])
 def test_segment_parallel_vs_oracle_and_sweep(mppi, oracle_lib, H, K, T, ce, lam, block):
     wl = _wl(H, K, T, lam)
     g_par, g_seq, G, S, eps = _both(mppi, wl, ce, block)
@@ -104,6 +105,26 @@ def test_segment_parallel_vs_oracle_and_sweep(mppi, oracle_lib, H, K, T, ce, lam
     _close(g_par, ref["grad"], ref["grad_abs"], "segment-parallel " + name)
     _close(g_seq, ref["grad"], ref["grad_abs"], "per-tile " + name)
     _close(g_par, g_seq, ref["grad_abs"], "segment-parallel against per-tile " + name)
+
+
+@pytest.mark.parametrize("ce,lam", [(64, 50.0), (10, 50.0), (10, 5.0)])
+def test_segment_parallel_full_horizon(mppi, oracle_lib, ce, lam):
+    """T = 100 (the differentiable workload's horizon): part of the samples
+    follow chaotic trajectories there, so each sample's share of the bound
+    is widened by its own conditioning, as in the full-size gradient test of
+    tests/test_gpu_grad.py; c = 64 gives 26 units (the second segment's last
+    five empty) and prefixes of up to 60 rebuilt steps."""
+    wl = _wl(64, 700, 100, lam)
+    g_par, g_seq, G, S, eps = _both(mppi, wl, ce, 256)
+    S_or = oracle_lib.rollout_costs(wl, eps)[0]
+    cond = oracle_lib.cost_condition(wl, eps)
+    rel = np.maximum(1e-4, parity.COND_ULPS * 2.0 ** -24 * cond / np.maximum(np.abs(S_or), 1.0))
+    ref = oracle_lib.backward(wl, G.astype(np.float64), eps=eps, S=S, rel=rel)
+    name = f"T=100 c={ce} lambda={lam}"
+    # grad_abs already carries each sample's relative bound
+    _close(g_seq, ref["grad"], 1e4 * ref["grad_abs"], "per-tile " + name)
+    _close(g_par, ref["grad"], 1e4 * ref["grad_abs"], "segment-parallel " + name)
+    _close(g_par, g_seq, 1e4 * ref["grad_abs"], "segment-parallel against per-tile " + name)
 
 
 def test_segment_parallel_accurate_trig(mppi, oracle_lib):
