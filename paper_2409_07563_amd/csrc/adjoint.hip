@@ -333,11 +333,13 @@ __device__ __forceinline__ void rk4_jvp(const DevParams& p, const float* xt, con
 //                 (forward mode through the RK4 stages and the MLP), giving
 //                 column i of P_s and component i of q_s; column 0 of the last
 //                 segment also keeps x_T;
-//   sweep:        per (tile, segment) the usual rebuild and reverse pass over
-//                 that segment alone, from the costate the chain of the later
+//   sweep:        per (tile, segment) the usual reverse pass over that
+//                 segment alone, from the costate the chain of the later
 //                 segments' maps gives (every workgroup forms the chain
-//                 itself, from x_T's terminal gradient, in the same order);
-//                 its partial gradient goes to its own row;
+//                 itself, from x_T's terminal gradient, in the same order),
+//                 on the states and MLP pre-activations the map kernel's
+//                 column 0 kept (no rebuild); its partial gradient goes to
+//                 its own row;
 //   reduce:       sums tiles x segments rows.
 // The mode is chosen on the device from the listed count, so no host
 // synchronisation is needed.
@@ -346,11 +348,9 @@ __device__ __forceinline__ void rk4_jvp(const DevParams& p, const float* xt, con
 // c steps splits into sub = ceil(c / 5) units of cs = ceil(c / sub) steps (the
 // last ones of a ragged final segment may be empty: identity maps).  A unit
 // past its segment's start has no checkpoint; its map's waves rebuild the
-// segment's earlier steps first (without tangents) and the column-0 wave
-// stores the unit's start state for its sweep.  Record per (tile, unit,
+// segment's earlier steps first (without tangents).  Record per (tile, unit,
 // sample): for each column i, P[0..4][i] then q[i] (6 floats); x_T (5, the
-// last unit); the unit's start state x (5) and its compensation (2): 42
-// floats, padded to 44.
+// last unit): 35 floats, padded to 36.
 constexpr int kTpMaxTiles = kAdjointTilesMax;
 // at most this many (tile, unit) rows: the partial gradients and the
 // pre-activation scratch grow with them
@@ -366,10 +366,22 @@ __host__ __device__ inline int tp_unit_steps(int c) { return (c + tp_sub(c) - 1)
 inline int tp_cap(int tiles, int nunit) {
   return std::min(std::min(tiles, kTpMaxTiles), kTpRowBudget / nunit);
 }
-constexpr int kTpRec = 44;
+constexpr int kTpRec = 36;
 constexpr int kTpXT = 30;  // offset of x_T in a record
-constexpr int kTpX0 = 35;  // offset of the unit's start state (x, then comp[0..1])
-static_assert(kTpX0 + 7 <= kTpRec, "record size");
+static_assert(kTpXT + 5 <= kTpRec, "record size");
+
+// The unit's forward, kept by the map kernel's column-0 workgroup for the
+// unit's sweep (which then skips its rebuild): per (tile, unit, sample) the
+// states before each step and after the last ((cs + 1) x 5) and the controls
+// (cs x 2), after the records of the same launch; the MLP pre-activations go
+// to the unit's row of the pre-activation scratch.
+__host__ __device__ inline int tp_state_floats(int c) {
+  return (tp_unit_steps(c) + 1) * 5 + tp_unit_steps(c) * 2;
+}
+__device__ __forceinline__ int64_t tp_states_off(int tp_tiles, int nunit, int c, int row, int n) {
+  return static_cast<int64_t>(tp_tiles) * nunit * kTileS * kTpRec +
+         (static_cast<int64_t>(row) * kTileS + n) * tp_state_floats(c);
+}
 
 // Which units a workgroup of the sweep handles: in the segment-parallel mode
 // one (tile, unit) pair, units of `sub` per segment; otherwise one tile and
@@ -433,26 +445,28 @@ __device__ __forceinline__ void tp_chain(const DevParams& p, const float* __rest
   }
 }
 
-// The start state of a unit: its segment's checkpoint (h = 0), or the state
-// the map kernel stored for it (record `row`, sample n).
-__device__ __forceinline__ void load_unit_start(const float* __restrict__ ckpt, int64_t ldk,
-                                                int k, int seg, int h,
-                                                const float* __restrict__ tp, int row, int n,
-                                                float* x, float* comp) {
+// The state at a segment's start: its checkpoint.
+__device__ __forceinline__ void load_checkpoint(const float* __restrict__ ckpt, int64_t ldk, int k,
+                                                int seg, float* x, float* comp) {
   constexpr int N = 5;
-  if (h == 0) {
-    const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + k;
+  const float* ck = ckpt + static_cast<int64_t>(seg) * 7 * ldk + k;
 #pragma unroll
-    for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
-    comp[0] = ck[5 * ldk];
-    comp[1] = ck[6 * ldk];
-  } else {
-    const float* rec = tp + (static_cast<int64_t>(row) * kTileS + n) * kTpRec;
+  for (int i = 0; i < N; ++i) { x[i] = ck[i * ldk]; comp[i] = 0.0f; }
+  comp[0] = ck[5 * ldk];
+  comp[1] = ck[6 * ldk];
+}
+
+// The unit's states (len + 1) and controls (len) of one sample as the map
+// kernel kept them, into the sweep's per-sample arrays.
+__device__ __forceinline__ void copy_unit_forward(const float* __restrict__ st, int c, int len,
+                                                  float* xs, float* vs) {
+  const int cs = tp_unit_steps(c);
+  for (int j = 0; j <= len; ++j)
 #pragma unroll
-    for (int i = 0; i < N; ++i) { x[i] = rec[kTpX0 + i]; comp[i] = 0.0f; }
-    comp[0] = rec[kTpX0 + 5];
-    comp[1] = rec[kTpX0 + 6];
-  }
+    for (int i = 0; i < 5; ++i) xs[j * 5 + i] = st[j * 5 + i];
+  for (int j = 0; j < len; ++j)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) vs[j * 2 + q] = st[(cs + 1) * 5 + j * 2 + q];
 }
 
 // Row `row` of the partial gradients holds dL/du only for the steps of its
@@ -473,7 +487,8 @@ template <int MT, bool FAST, bool BF = false>
 __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
-    const BwdMeta* __restrict__ meta, int tp_tiles, float* __restrict__ tp) {
+    const BwdMeta* __restrict__ meta, int tp_tiles, float* __restrict__ tp,
+    mlp::f4* __restrict__ pre) {
   using Model = Bicycle<FAST>;
   using f4 = mlp::f4;
   constexpr int N = 5, M = 2;
@@ -533,25 +548,29 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
     }
   }
   float* rec = tp + (static_cast<int64_t>(tile * nunit + unit) * kTileS + n) * kTpRec;
-  if (h > 0 && col == 0 && g == 0) {  // the unit's start state for its sweep
-#pragma unroll
-    for (int i = 0; i < N; ++i) rec[kTpX0 + i] = x[i];
-    rec[kTpX0 + 5] = comp[0];
-    rec[kTpX0 + 6] = comp[1];
-  }
   float q = 0.0f;
+  // column 0 keeps the unit's forward for its sweep
+  const int row = tile * nunit + unit, cs = tp_unit_steps(c);
+  float* st = tp + tp_states_off(tp_tiles, nunit, c, row, n);
+  mlp::f4* my_pre = pre + static_cast<int64_t>(row) * cs * 2 * (MT ? MT : 1) * kWave + lane;
   for (int j = 0; j < len; ++j) {
     const int t = t0 + j;
     float v[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = u[t * M + k] + e[static_cast<int64_t>(t * M + k) * ldk];
+    if (col == 0 && g == 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) st[j * N + i] = x[i];
+#pragma unroll
+      for (int k = 0; k < M; ++k) st[(cs + 1) * N + j * M + k] = v[k];
+    }
     float xn[N];
     rk4_jvp<FAST>(p, x, v, xd, xn);
     if constexpr (MT > 0) {
-      f4 d1[MT], d2[MT];
+      f4 d1[MT], d2[MT], a1[MT], a2[MT];
       float res[N], gd[N];
       if constexpr (BF) {
-        f4 a1[MT], a2[MT], hh;
+        f4 hh;
         mlp::residual_keep<MT>(WFB, x, v, g, n, res, a1, a2);
 #pragma unroll
         for (int t2 = 0; t2 < MT; ++t2) {
@@ -561,9 +580,17 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
         mlp::jvp<MT>(mlp::RoundedView<MT>{WF}, xd, g, n, d1, d2, gd);
       } else {
         f4 h1[MT], h2[MT];
-        mlp::hidden_d<MT>(WF, x, v, g, h1, h2, d1, d2);
+        mlp::hidden_impl<MT, true>(WF, x, v, g, h1, h2, d1, d2, a1, a2);
         mlp::broadcast5(mlp::output<MT>(WF, h2), n, res);
         mlp::jvp<MT>(WF, xd, g, n, d1, d2, gd);
+      }
+      if (col == 0) {
+        f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
+#pragma unroll
+        for (int t2 = 0; t2 < MT; ++t2) {
+          ps[t2 * kWave] = a1[t2];
+          ps[(MT + t2) * kWave] = a2[t2];
+        }
       }
 #pragma unroll
       for (int i = 0; i < N; ++i) xn[i] += p.dt * gd[i];
@@ -583,6 +610,10 @@ __global__ __launch_bounds__(kWave) void adjoint_tp_kernel(
 #pragma unroll
     for (int i = 0; i < N; ++i) rec[col * 6 + i] = xd[i];
     rec[col * 6 + 5] = q;
+    if (col == 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) st[len * N + i] = x[i];
+    }
     if (unit == nunit - 1 && col == 0) {  // after the last step: x_T
 #pragma unroll
       for (int i = 0; i < N; ++i) rec[kTpXT + i] = x[i];
@@ -605,7 +636,8 @@ template <int MT, int SW, bool FAST, bool BF = false>
 __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
     DevParams p, const float* __restrict__ u, const float* __restrict__ eps, int64_t ldk, int T,
     const float* __restrict__ ckpt, int c, const BwdItem* __restrict__ list,
-    const BwdMeta* __restrict__ meta, int tp_tiles, float* __restrict__ tp) {
+    const BwdMeta* __restrict__ meta, int tp_tiles, float* __restrict__ tp,
+    mlp::f4* __restrict__ pre) {
   static_assert(MT % SW == 0, "tiles per wave");
   constexpr int TW = MT / SW;
   using Model = Bicycle<FAST>;
@@ -694,12 +726,24 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
   const float v0[2] = {0.0f, 0.0f};
   int par = 0;
   float q = 0.0f;
+  // column 0 keeps the unit's forward for its sweep
+  const int row = tile * nunit + unit, cs = tp_unit_steps(c);
+  float* st = tp + tp_states_off(tp_tiles, nunit, c, row, n);
+  f4* my_pre = pre + static_cast<int64_t>(row) * cs * 2 * MT * kWave + lane;
+  const bool keep = col == 0;
   // one step: the MLP forward (and with TAN its tangent along xd), then the
   // RK4 step (and the tangent's); every wave runs it (barriers inside)
   auto one_step = [&](int t, bool tan) {
     float v[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = u[t * M + k] + e[static_cast<int64_t>(t * M + k) * ldk];
+    f4* ps = my_pre + static_cast<int64_t>(t - t0) * 2 * MT * kWave;
+    if (tan && keep && w == 0 && g == 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) st[(t - t0) * N + i] = x[i];
+#pragma unroll
+      for (int k = 0; k < M; ++k) st[(cs + 1) * N + (t - t0) * M + k] = v[k];
+    }
     float xn[N];
     if (tan) rk4_jvp<FAST>(p, x, v, xd, xn);
     const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
@@ -711,6 +755,7 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
       f4 a1;
       if constexpr (BF) a1 = mlp::mfma_bf(v1[qq], zb, fb1[qq]);
       else a1 = mlp::mfma(fw1[qq][1], z1, mlp::mfma(fw1[qq][0], z0, fb1[qq]));
+      if (tan && keep) ps[(q0 + qq) * kWave] = a1;
       f4 h1, d1;
       mlp::tanh4_d(a1, h1, d1);
       xch(xa, par, q0 + qq) = h1;
@@ -753,6 +798,7 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
     }
 #pragma unroll
     for (int qq = 0; qq < TW; ++qq) {
+      if (tan && keep) ps[(MT + q0 + qq) * kWave] = acc[qq];
       f4 h2, d2;
       mlp::tanh4_d(acc[qq], h2, d2);
       if constexpr (BF) {
@@ -811,17 +857,15 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_tp_split_kernel(
   // the segment's steps before the unit: the sweep's rebuild, no tangent
   for (int t = seg * c; t < t0; ++t) one_step(t, false);
   float* rec = tp + (static_cast<int64_t>(tile * nunit + unit) * kTileS + n) * kTpRec;
-  if (h > 0 && col == 0 && w == 0 && g == 0) {  // the unit's start state for its sweep
-#pragma unroll
-    for (int i = 0; i < N; ++i) rec[kTpX0 + i] = x[i];
-    rec[kTpX0 + 5] = comp[0];
-    rec[kTpX0 + 6] = comp[1];
-  }
   for (int t = t0; t < t0 + len; ++t) one_step(t, true);
   if (w == 0 && g == 0) {
 #pragma unroll
     for (int i = 0; i < N; ++i) rec[col * 6 + i] = xd[i];
     rec[col * 6 + 5] = q;
+    if (keep) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) st[len * N + i] = x[i];
+    }
     if (unit == nunit - 1 && col == 0) {  // after the last step: x_T
 #pragma unroll
       for (int i = 0; i < N; ++i) rec[kTpXT + i] = x[i];
@@ -954,51 +998,56 @@ __global__ __launch_bounds__(kWave) void adjoint_sweep_kernel(
   for (int ui = sel.hi; ui >= sel.lo; --ui) {
     int seg, hp, t0, len;
     unit_steps(ui, sel.sub, c, T, seg, hp, t0, len);
-    // rebuild x_{t0} .. x_{t0+len} from the checkpoint (or the unit's stored
-    // start state)
-    float x[N], comp[N];
-    load_unit_start(ckpt, ldk, k, seg, hp, tp, sel.tile * nunit + ui, n, x, comp);
-    // u and the noise of a step are requested one step ahead
-    float un[M], en[M];
-    auto fetch_v = [&](int t) {
-#pragma unroll
-      for (int q = 0; q < M; ++q) {
-        un[q] = u[t * M + q];
-        en[q] = e[static_cast<int64_t>(t * M + q) * ldk];
-      }
-    };
-    if (len > 0) fetch_v(t0);
-    for (int j = 0; j < len; ++j) {
-      const int t = t0 + j;
-      float v[M];
-#pragma unroll
-      for (int q = 0; q < M; ++q) v[q] = un[q] + en[q];
-      if (j + 1 < len) fetch_v(t + 1);
-      if (g == 0) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) xs[j * N + i] = x[i];
-#pragma unroll
-        for (int q = 0; q < M; ++q) vs[j * M + q] = v[q];
-      }
-      if constexpr (MT > 0) {
-        float res[N];
-        f4 a1[MT], a2[MT];
-        if constexpr (BF) mlp::residual_keep<MT>(WFB, x, v, g, n, res, a1, a2);
-        else mlp::residual_keep<MT>(WF, x, v, g, n, res, a1, a2);
-        f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
-#pragma unroll
-        for (int t2 = 0; t2 < MT; ++t2) {
-          ps[t2 * kWave] = a1[t2];
-          ps[(MT + t2) * kWave] = a2[t2];
+    if (sel.par) {
+      // the unit's states, controls and pre-activations as the map kernel kept them
+      if (g == 0) copy_unit_forward(tp + tp_states_off(tp_tiles, nunit, c, sel.tile * nunit + ui, n),
+                                    c, len, xs, vs);
+    } else {
+      // rebuild x_{t0} .. x_{t0+len} from the checkpoint
+      float x[N], comp[N];
+      load_checkpoint(ckpt, ldk, k, seg, x, comp);
+      // u and the noise of a step are requested one step ahead
+      float un[M], en[M];
+      auto fetch_v = [&](int t) {
+  #pragma unroll
+        for (int q = 0; q < M; ++q) {
+          un[q] = u[t * M + q];
+          en[q] = e[static_cast<int64_t>(t * M + q) * ldk];
         }
-        step<Model, kRK4>(x, v, comp, p, res);
-      } else {
-        step<Model, kRK4>(x, v, comp, p);
+      };
+      if (len > 0) fetch_v(t0);
+      for (int j = 0; j < len; ++j) {
+        const int t = t0 + j;
+        float v[M];
+  #pragma unroll
+        for (int q = 0; q < M; ++q) v[q] = un[q] + en[q];
+        if (j + 1 < len) fetch_v(t + 1);
+        if (g == 0) {
+  #pragma unroll
+          for (int i = 0; i < N; ++i) xs[j * N + i] = x[i];
+  #pragma unroll
+          for (int q = 0; q < M; ++q) vs[j * M + q] = v[q];
+        }
+        if constexpr (MT > 0) {
+          float res[N];
+          f4 a1[MT], a2[MT];
+          if constexpr (BF) mlp::residual_keep<MT>(WFB, x, v, g, n, res, a1, a2);
+          else mlp::residual_keep<MT>(WF, x, v, g, n, res, a1, a2);
+          f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
+  #pragma unroll
+          for (int t2 = 0; t2 < MT; ++t2) {
+            ps[t2 * kWave] = a1[t2];
+            ps[(MT + t2) * kWave] = a2[t2];
+          }
+          step<Model, kRK4>(x, v, comp, p, res);
+        } else {
+          step<Model, kRK4>(x, v, comp, p);
+        }
       }
-    }
-    if (g == 0) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) xs[len * N + i] = x[i];
+      if (g == 0) {
+  #pragma unroll
+        for (int i = 0; i < N; ++i) xs[len * N + i] = x[i];
+      }
     }
     __syncthreads();
     if (ui == nunit - 1) {  // terminal cost w16 sum_i Q_i (x_T - r_T)^2
@@ -1289,109 +1338,116 @@ __global__ __launch_bounds__(kWave * SW) void adjoint_sweep_split_kernel(
   for (int ui = sel.hi; ui >= sel.lo; --ui) {
     int seg, hp, t0, len;
     unit_steps(ui, sel.sub, c, T, seg, hp, t0, len);
-    float x[N], comp[N];
-    load_unit_start(ckpt, ldk, k, seg, hp, tp, sel.tile * nunit + ui, n, x, comp);
-    // u and the noise of a step are requested one step ahead, so their
-    // latency hides behind the previous step's work (barriers wait for LDS
-    // only, not for these loads)
-    float un[M], en[M];
-    auto fetch_v = [&](int t) {
-#pragma unroll
-      for (int q = 0; q < M; ++q) {
-        un[q] = u[t * M + q];
-        en[q] = e[static_cast<int64_t>(t * M + q) * ldk];
+    if (sel.par) {
+      // the unit's states, controls and pre-activations as the map kernel kept them
+      if (w == 0 && g == 0)
+        copy_unit_forward(tp + tp_states_off(tp_tiles, nunit, c, sel.tile * nunit + ui, n), c,
+                          len, xs, vs);
+    } else {
+      float x[N], comp[N];
+      load_checkpoint(ckpt, ldk, k, seg, x, comp);
+      // u and the noise of a step are requested one step ahead, so their
+      // latency hides behind the previous step's work (barriers wait for LDS
+      // only, not for these loads)
+      float un[M], en[M];
+      auto fetch_v = [&](int t) {
+  #pragma unroll
+        for (int q = 0; q < M; ++q) {
+          un[q] = u[t * M + q];
+          en[q] = e[static_cast<int64_t>(t * M + q) * ldk];
+        }
+      };
+      if (len > 0) fetch_v(t0);
+      for (int j = 0; j < len; ++j) {
+        const int t = t0 + j;
+        float v[M];
+  #pragma unroll
+        for (int q = 0; q < M; ++q) v[q] = un[q] + en[q];
+        if (j + 1 < len) fetch_v(t + 1);
+        if (w == 0 && g == 0) {
+  #pragma unroll
+          for (int i = 0; i < N; ++i) xs[j * N + i] = x[i];
+  #pragma unroll
+          for (int q = 0; q < M; ++q) vs[j * M + q] = v[q];
+        }
+        // MLP forward, split (as the split forward kernel)
+        f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
+        if constexpr (BF) {
+          const mlp::bf8 zb = mlp::input_operand_bf(x, v, g);
+  #pragma unroll
+          for (int q = 0; q < TW; ++q) {
+            const f4 a1 = mlp::mfma_bf(v1[q], zb, fb1[q]);
+            ps[(q0 + q) * kWave] = a1;
+            xch(xa, par, q0 + q) = mlp::tanh4(a1);
+          }
+        } else {
+          const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
+  #pragma unroll
+          for (int q = 0; q < TW; ++q) {
+            const f4 a1 = mlp::mfma(fw1[q][1], z1, mlp::mfma(fw1[q][0], z0, fb1[q]));
+            ps[(q0 + q) * kWave] = a1;
+            xch(xa, par, q0 + q) = mlp::tanh4(a1);
+          }
+        }
+        __syncthreads();
+        f4 acc[TW];
+  #pragma unroll
+        for (int q = 0; q < TW; ++q) acc[q] = fb2[q];
+        f4 out;
+        if constexpr (BF) {
+          f4 h1a[MT];
+  #pragma unroll
+          for (int tt = 0; tt < MT; ++tt) h1a[tt] = xch(xa, par, tt);
+  #pragma unroll
+          for (int kb = 0; kb < KB; ++kb) {
+            const mlp::bf8 hb = mlp::kblock_operand<MT>(h1a, kb);
+  #pragma unroll
+            for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma_bf(v2[q][kb], hb, acc[q]);
+          }
+  #pragma unroll
+          for (int q = 0; q < TW; ++q) {
+            ps[(MT + q0 + q) * kWave] = acc[q];
+            xch(xb, par, q0 + q) = mlp::tanh4(acc[q]);
+          }
+          __syncthreads();
+          f4 h2a[MT];
+  #pragma unroll
+          for (int tt = 0; tt < MT; ++tt) h2a[tt] = xch(xb, par, tt);
+          out = fb3[0];
+  #pragma unroll
+          for (int kb = 0; kb < KB; ++kb) out = mlp::mfma_bf(v3[kb], mlp::kblock_operand<MT>(h2a, kb), out);
+        } else {
+  #pragma unroll
+          for (int tt = 0; tt < MT; ++tt) {
+            const f4 h = xch(xa, par, tt);
+  #pragma unroll
+            for (int i = 0; i < 4; ++i)
+  #pragma unroll
+              for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(fw2[q][tt][i], h[i], acc[q]);
+          }
+  #pragma unroll
+          for (int q = 0; q < TW; ++q) {
+            ps[(MT + q0 + q) * kWave] = acc[q];
+            const f4 h2 = mlp::tanh4(acc[q]);
+            f4 part = fb3[q];
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[q][i], h2[i], part);
+            xch(xb, par, q0 + q) = part;
+          }
+          __syncthreads();
+          out = xch(xb, par, 0);
+  #pragma unroll
+          for (int tt = 1; tt < MT; ++tt) out += xch(xb, par, tt);
+        }
+        par ^= 1;
+        float res[N];
+        mlp::broadcast5(out, n, res);
+        step<Model, kRK4>(x, v, comp, p, res);
       }
-    };
-    if (len > 0) fetch_v(t0);
-    for (int j = 0; j < len; ++j) {
-      const int t = t0 + j;
-      float v[M];
-#pragma unroll
-      for (int q = 0; q < M; ++q) v[q] = un[q] + en[q];
-      if (j + 1 < len) fetch_v(t + 1);
       if (w == 0 && g == 0) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) xs[j * N + i] = x[i];
-#pragma unroll
-        for (int q = 0; q < M; ++q) vs[j * M + q] = v[q];
+  #pragma unroll
+        for (int i = 0; i < N; ++i) xs[len * N + i] = x[i];
       }
-      // MLP forward, split (as the split forward kernel)
-      f4* ps = my_pre + static_cast<int64_t>(j) * 2 * MT * kWave;
-      if constexpr (BF) {
-        const mlp::bf8 zb = mlp::input_operand_bf(x, v, g);
-#pragma unroll
-        for (int q = 0; q < TW; ++q) {
-          const f4 a1 = mlp::mfma_bf(v1[q], zb, fb1[q]);
-          ps[(q0 + q) * kWave] = a1;
-          xch(xa, par, q0 + q) = mlp::tanh4(a1);
-        }
-      } else {
-        const float z0 = mlp::input_operand(x, v, g, 0), z1 = mlp::input_operand(x, v, g, 1);
-#pragma unroll
-        for (int q = 0; q < TW; ++q) {
-          const f4 a1 = mlp::mfma(fw1[q][1], z1, mlp::mfma(fw1[q][0], z0, fb1[q]));
-          ps[(q0 + q) * kWave] = a1;
-          xch(xa, par, q0 + q) = mlp::tanh4(a1);
-        }
-      }
-      __syncthreads();
-      f4 acc[TW];
-#pragma unroll
-      for (int q = 0; q < TW; ++q) acc[q] = fb2[q];
-      f4 out;
-      if constexpr (BF) {
-        f4 h1a[MT];
-#pragma unroll
-        for (int tt = 0; tt < MT; ++tt) h1a[tt] = xch(xa, par, tt);
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-          const mlp::bf8 hb = mlp::kblock_operand<MT>(h1a, kb);
-#pragma unroll
-          for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma_bf(v2[q][kb], hb, acc[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < TW; ++q) {
-          ps[(MT + q0 + q) * kWave] = acc[q];
-          xch(xb, par, q0 + q) = mlp::tanh4(acc[q]);
-        }
-        __syncthreads();
-        f4 h2a[MT];
-#pragma unroll
-        for (int tt = 0; tt < MT; ++tt) h2a[tt] = xch(xb, par, tt);
-        out = fb3[0];
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) out = mlp::mfma_bf(v3[kb], mlp::kblock_operand<MT>(h2a, kb), out);
-      } else {
-#pragma unroll
-        for (int tt = 0; tt < MT; ++tt) {
-          const f4 h = xch(xa, par, tt);
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < TW; ++q) acc[q] = mlp::mfma(fw2[q][tt][i], h[i], acc[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < TW; ++q) {
-          ps[(MT + q0 + q) * kWave] = acc[q];
-          const f4 h2 = mlp::tanh4(acc[q]);
-          f4 part = fb3[q];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) part = mlp::mfma(fw3[q][i], h2[i], part);
-          xch(xb, par, q0 + q) = part;
-        }
-        __syncthreads();
-        out = xch(xb, par, 0);
-#pragma unroll
-        for (int tt = 1; tt < MT; ++tt) out += xch(xb, par, tt);
-      }
-      par ^= 1;
-      float res[N];
-      mlp::broadcast5(out, n, res);
-      step<Model, kRK4>(x, v, comp, p, res);
-    }
-    if (w == 0 && g == 0) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) xs[len * N + i] = x[i];
     }
     __syncthreads();
     if (ui == nunit - 1) {
@@ -1650,7 +1706,9 @@ AdjointScratch adjoint_scratch_layout(int K, int ngrad, int hidden, int ckpt_eve
   const size_t pre_steps = std::max(static_cast<size_t>(tiles) * ckpt_every,
                                     static_cast<size_t>(tp_max) * nunit * tp_unit_steps(ckpt_every));
   s.pre = take(sizeof(float) * 4 * pre_steps * 2 * (hidden > 0 ? hidden / 16 : 0) * kWave);
-  s.tp = take(sizeof(float) * static_cast<size_t>(tp_max) * nunit * kTileS * kTpRec);
+  // the unit records, then the units' kept forward (states and controls)
+  s.tp = take(sizeof(float) * static_cast<size_t>(tp_max) * nunit * kTileS *
+              (kTpRec + tp_state_floats(ckpt_every)));
   s.total = off;
   return s;
 }
@@ -1670,7 +1728,7 @@ using SweepFn = void (*)(DevParams, const float*, const float*, int64_t, int, co
                          const BwdItem*, const BwdMeta*, float*, int64_t, int, mlp::f4*,
                          const float*, int);
 using TpFn = void (*)(DevParams, const float*, const float*, int64_t, int, const float*, int,
-                      const BwdItem*, const BwdMeta*, int, float*);
+                      const BwdItem*, const BwdMeta*, int, float*, mlp::f4*);
 template <int MT, bool BF = false>
 TpFn pick_tp(bool accurate) {
   return accurate ? adjoint_tp_kernel<MT, false, BF> : adjoint_tp_kernel<MT, true, BF>;
@@ -1790,7 +1848,7 @@ hipError_t launch_adjoint(const DevParams& p, bool accurate_trig, int hidden, co
   if (tp > 0) {
     if (!tfn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(tfn, dim3(tp * nunit * 5), dim3(kWave * twaves), tlds, stream, p, d_u,
-                       d_eps, ldk, T, d_ckpt, ckpt_every, list, meta, tp, tpbuf);
+                       d_eps, ldk, T, d_ckpt, ckpt_every, list, meta, tp, tpbuf, pre);
   }
   const int rows = std::max(tiles, tp * nunit);
   hipLaunchKernelGGL(fn, dim3(rows), dim3(kWave * waves), lds, stream, p, d_u, d_eps, ldk, T,
