@@ -3,20 +3,21 @@ against the binary64 oracle and against the per-tile sweep, through the C ABI.
 
 With few samples of nonzero weight the checkpoint segments are swept in
 parallel, in units of at most 5 steps (a segment of c steps splits into
-ceil(c / 5) units; units past a segment's start begin from a state the map
-kernel stores; units of a ragged last segment may be empty): each unit's
+ceil(c / 5) units; units of a ragged last segment may be empty): each unit's
 costate map (the product of its step Jacobians, formed in forward mode
 through the RK4 stages and the MLP, plus its running costs' share) chains the
-costate from the terminal cost to every unit's end.  Mathematically the gradient is the per-tile sweep's; in binary32 the
-chained costate rounds differently, so both are held to the oracle at the
-gradient bound of tests/test_gpu_grad.py (1e-4 of sum_k |a_k dJ_k/dtheta|
-per parameter), and to each other at the same bound.  Cases: every hidden
-width (and the plain bicycle), one-wave and split sweeps, ragged last
-segments, one-step segments, a single segment, many tiles (up to 128, and
-beyond the row budget of 1280 / segments, where the per-tile sweep runs), the
-accurate trigonometry, the reverse pass through several iterations (dL/du
-columns written per segment), the mode's threshold (above it the per-tile
-sweep runs, bitwise), and the BF16 mode."""
+costate from the terminal cost to every unit's end, and each unit's sweep
+runs on the forward the map kernel kept for it.  Mathematically the gradient
+is the per-tile sweep's; in binary32 the chained costate rounds differently,
+so both are held to the oracle at the gradient bound of tests/test_gpu_grad.py
+(1e-4 of sum_k |a_k dJ_k/dtheta| per parameter; at T = 100 widened per
+sample by its conditioning), and to each other at the same bound.  Cases:
+every hidden width (and the plain bicycle), one-wave and split sweeps, ragged
+last segments, one-step segments, a single segment, many tiles (up to 128,
+and beyond the row budget of 1280 / units, where the per-tile sweep runs),
+the accurate trigonometry, the full horizon, the reverse pass through several
+iterations (dL/du columns written per unit), the mode's threshold (above it
+the per-tile sweep runs, bitwise), and the BF16 mode."""
 import sys
 
 import numpy as np
